@@ -1,0 +1,17 @@
+"""Plain FP64 CPU oracle for the recursively preconditioned hierarchical interpolative
+factorization (test infrastructure only; see rhif_oracle for the rules on its use)."""
+from .rhif_oracle import (  # noqa: F401
+    NotSPDError,
+    assemble_fd,
+    fd_energy,
+    dof_coords,
+    num_levels,
+    classify,
+    closure_keys,
+    chol,
+    cpqr_id,
+    factor,
+    apply_inverse,
+    pcg,
+    dense_solve,
+)
