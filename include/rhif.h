@@ -1,0 +1,173 @@
+/*
+ * rhif.h -- C ABI of the MI355X (gfx950) recursively preconditioned hierarchical
+ * interpolative factorization (RHIF; "PHIF" in Feliu-Faba, Ho, Ying, "Recursively
+ * Preconditioned Hierarchical Interpolative Factorization for Elliptic Partial
+ * Differential Equations", arXiv 1808.01364).
+ *
+ * The library factors the SPD finite-difference matrix A of
+ *     -div(a grad u) + b u = f   on (0,1)^d, d = 2 or 3, zero Dirichlet data
+ * (the problem of Sec. 1, eqs. (1.1)-(1.2), discretized as in Sec. 3.1 / 3.2) into the
+ * generalized Cholesky form F = G G^T of eq. (eqF), and applies F^-1 (eq. (eqAinv)) as
+ * the preconditioner of a CG solve (Sec. 4).
+ *
+ * Conventions shared by every entry point
+ *  - Grid: n interior points per axis, N = n^d unknowns at x in {1..n}^d, h = 1/(n+1).
+ *    Unknown (x_1..x_d) has linear index sum_k (x_k-1) n^(k-1)  (x_1 fastest).
+ *  - Coefficient a: one value per grid cell, (n+1)^d values, cell (c_1..c_d) with
+ *    0 <= c_k <= n at linear index sum_k c_k (n+1)^(k-1). The coefficient of a grid edge
+ *    is the mean of the 2^(d-1) cells containing it.
+ *  - Pointers marked [device] are device (HBM) pointers owned by the caller; [host] are
+ *    host pointers. Device work is enqueued on the given stream (0 = the null stream).
+ *  - Every call returns an rhif_status; nothing throws across the ABI. On failure,
+ *    rhif_last_error() returns a thread-local message naming the failing step.
+ *  - One call in flight per factor handle at a time.
+ */
+#ifndef RHIF_H
+#define RHIF_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RHIF_OK = 0,
+    RHIF_EINVAL = 1,    /* invalid argument or matrix structure                          */
+    RHIF_ENOTSPD = 2,   /* a Cholesky pivot was <= 0 or not finite (loss of SPD-ness)      */
+    RHIF_ENOMEM = 3,    /* device or host allocation failed                              */
+    RHIF_EDEVICE = 4,   /* a HIP runtime call failed                                     */
+    RHIF_ENOCONV = 5    /* PCG reached maxit before the residual test passed            */
+} rhif_status;
+
+/* Regular grid: dim in {2,3}; n[0] = n[1] (= n[2] in 3D) interior points per axis. */
+typedef struct {
+    int32_t dim;
+    int32_t n[3];
+} rhif_grid;
+
+/* Factorization options.
+ *  leaf      m >= 2: level-l cells span 2^l m grid steps; levels run while 2^l m <= n
+ *            (Sec. 3.1: n = 2^L m); what remains after the last level is the root.
+ *  eps       relative precision of the interpolative decomposition (Sec. 2.2): the rank
+ *            is the number of leading column-pivoted QR steps with |R_jj| > eps |R_11|.
+ *            eps = 0 keeps every column (exact nested dissection).
+ *  precond   1 = block-Jacobi preconditioning of every separator group before each
+ *            skeletonization (the paper's PHIF, Sec. 3.1 step 2); 0 = plain HIF.
+ *  precision 0 = FP64 throughout (the only value accepted by this version).
+ *  flags     bit 0: record per-phase device times (adds one sync per phase). */
+typedef struct {
+    int32_t leaf;
+    double  eps;
+    int32_t precond;
+    int32_t precision;
+    int32_t flags;
+} rhif_opts;
+
+#define RHIF_FLAG_PHASE_TIMES 1
+#define RHIF_MAX_LEVELS 32
+
+/* Host-side summary of a factorization. Level l in [0, levels) is a skeletonization
+ * level; entry [levels] describes the root. */
+typedef struct {
+    int32_t levels;                          /* L                                        */
+    int32_t root_size;                       /* |S_L|                                    */
+    int64_t factor_bytes;                    /* device bytes held by the factor          */
+    int64_t n_active[RHIF_MAX_LEVELS + 1];   /* |S_l| at the start of level l            */
+    int32_t n_cells[RHIF_MAX_LEVELS + 1];    /* cell frontal matrices at level l         */
+    int32_t max_front[RHIF_MAX_LEVELS + 1];  /* largest frontal order at level l         */
+    int32_t n_groups[RHIF_MAX_LEVELS];       /* separator groups preconditioned          */
+    int32_t n_skel[RHIF_MAX_LEVELS];         /* edges (2D) / faces (3D) skeletonized     */
+    int64_t sum_skel_n[RHIF_MAX_LEVELS];     /* total DOFs in those groups               */
+    int64_t sum_rank[RHIF_MAX_LEVELS];       /* total skeleton DOFs kept                 */
+    int32_t max_rank[RHIF_MAX_LEVELS];
+    double  flops[RHIF_MAX_LEVELS + 1];      /* algorithmic flops of the level's kernels */
+    double  t_total_ms;                      /* host wall time of rhif_factor            */
+    double  t_phase_ms[8];                   /* with RHIF_FLAG_PHASE_TIMES: assemble,
+                                                eliminate, precondition, ID, skeleton
+                                                elimination, plan+upload, root, other    */
+} rhif_stats_t;
+
+typedef struct rhif_factor_s *rhif_factor_t;
+
+/* Number of nonzeros of the 5-/7-point matrix on grid g: N + 2 d n^(d-1) (n-1).
+ * [host] nnz. No device work. Errors: EINVAL for a malformed grid. */
+rhif_status rhif_fd_nnz(const rhif_grid *g, int64_t *nnz);
+
+/* Assemble A = h^-2 K(a) + diag(b) in CSR form (eq. (1.1)-(1.2); Sec. 3.1 five-point and
+ * Sec. 3.2 seven-point stencils). Columns of every row are ascending.
+ *  a_cells [device] (n+1)^d cell coefficients (must be > 0 for an SPD matrix)
+ *  b       [device] N reaction values, or NULL for b = 0
+ *  row_ptr [device] N+1 int32 (output), col [device] nnz int32 (output),
+ *  val     [device] nnz doubles (output); nnz from rhif_fd_nnz.
+ * Errors: EINVAL (grid), EDEVICE (launch). */
+rhif_status rhif_assemble_fd(const rhif_grid *g, const double *a_cells, const double *b,
+                             int32_t *row_ptr, int32_t *col, double *val, hipStream_t s);
+
+/* Factor A ~= F = G G^T level by level (Sec. 3.1 / 3.2): at each level l = 0..L-1 every
+ * cell interior is eliminated (Sec. 2.1), every separator group is block-Jacobi
+ * preconditioned (Sec. 2.3, when precond = 1), and every edge (2D) / face (3D) is
+ * skeletonized with a column-pivoted-QR interpolative decomposition at precision eps
+ * (Sec. 2.2, all IDs of a level taken from the same matrix); the rest is factored
+ * densely (root, eq. (eqF)).
+ *  row_ptr, col, val [device] the CSR of A as produced by rhif_assemble_fd (entries may
+ *            only couple grid neighbours); the handle keeps its own copy, so the caller
+ *            may free these after the call returns.
+ *  out       [host] receives the new handle; NULL on any error (nothing leaks).
+ * The call synchronizes the stream once per level (to read the ID ranks back).
+ * Errors: EINVAL (grid/options/structure), ENOTSPD (a pivot <= 0 or not finite; the
+ * message names level, step E/C/K/root and block), ENOMEM, EDEVICE. */
+rhif_status rhif_factor(const rhif_grid *g, const rhif_opts *o, const int32_t *row_ptr,
+                        const int32_t *col, const double *val, hipStream_t s,
+                        rhif_factor_t *out);
+
+/* z = F^-1 r for nrhs right-hand sides stored one after another (column-major N x nrhs):
+ * the up-sweep R_l^T = K_l^T C_l^T E_l^T for l = 0..L-1, the root solve, and the
+ * down-sweep R_l = E_l C_l K_l for l = L-1..0 (eq. (eqAinv)).
+ *  r [device] input (not modified), z [device] output; r == z is allowed.
+ * Stream-ordered, never synchronizes. Errors: EINVAL, EDEVICE. */
+rhif_status rhif_apply(rhif_factor_t f, const double *r, double *z, int32_t nrhs,
+                       hipStream_t s);
+
+/* Solve A u = rhs by CG preconditioned with F^-1 from u_0 = 0 (Sec. 4), stopping when the
+ * recursively updated residual satisfies ||r_k|| <= rtol ||rhs||.
+ *  rhs [device] N doubles, u [device] N doubles (output)
+ *  iters  [host] number of products A p taken; relres [host] final ||r_k||/||rhs||.
+ * Reads one scalar back per iteration. Errors: EINVAL, EDEVICE, ENOCONV (u then holds
+ * the last iterate and iters/relres are set). */
+rhif_status rhif_pcg_solve(rhif_factor_t f, const double *rhs, double *u, double rtol,
+                           int32_t maxit, int32_t *iters, double *relres, hipStream_t s);
+
+/* y = A x with the handle's copy of A (x, y [device] N doubles). */
+rhif_status rhif_matvec(rhif_factor_t f, const double *x, double *y, hipStream_t s);
+
+/* Fill [host] *out with the structure, sizes and timings of the factorization. */
+rhif_status rhif_stats(rhif_factor_t f, rhif_stats_t *out);
+
+/* Discrete choices of the interpolative decompositions at skeletonization level l, so
+ * that a reference implementation can replay them (several pivot orders are valid when
+ * column norms tie). With the host arrays NULL, only *ngroups and *total are written.
+ *  ngroups [host] number of edges/faces skeletonized at level l
+ *  total   [host] sum of their sizes
+ *  first_dof [host, ngroups] smallest unknown (linear index) of each group
+ *  size, rank [host, ngroups] group size n and kept rank k
+ *  perm    [host, total] pivot order of each group, as positions 0..n-1 into the group's
+ *          unknowns in ascending linear index, groups one after another. */
+rhif_status rhif_skeletons(rhif_factor_t f, int32_t level, int32_t *ngroups, int64_t *total,
+                           int32_t *first_dof, int32_t *size, int32_t *rank, int32_t *perm);
+
+/* Release every resource of the handle (synchronizes its device work). NULL is a no-op. */
+void rhif_destroy(rhif_factor_t f);
+
+/* Thread-local description of the last error of this thread ("" if none). */
+const char *rhif_last_error(void);
+
+/* Library version string. */
+const char *rhif_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RHIF_H */

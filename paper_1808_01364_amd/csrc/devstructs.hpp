@@ -1,0 +1,109 @@
+// Plain-old-data tables shared by the host planner and the device kernels.
+//
+// All dense blocks are FP64, column-major. A "frontal" is the dense matrix of one cell of
+// the current level over the active unknowns of its closed cell: its interior unknowns
+// first, then its boundary groups (edges/corners in 2D, faces/edges/corners in 3D) one
+// after another, every group in ascending linear index. A frontal holds the cell's own
+// additive share of the current matrix A_l; the shares of all cells sum to A_l.
+#pragma once
+#include <cstdint>
+
+namespace rhif {
+
+constexpr int kMaxSlots = 8;   // cells whose closure contains one group (2^d, d <= 3)
+
+// One dense matrix of a batch (frontal, group diagonal block, skeleton block).
+struct FrontDesc {
+    int64_t off;     // element offset into the pool
+    int32_t ld;      // leading dimension
+    int32_t n;       // order
+    int32_t p;       // number of leading pivots to eliminate (p <= n)
+    int32_t id;      // block id reported on loss of positive definiteness
+};
+
+// Reference to a cell frontal of some level (for gathers from children / neighbours).
+struct CellRef {
+    int64_t off;
+    int32_t ld;
+    int32_t nI;
+    int32_t nf;
+    int32_t dptr;    // offset of the frontal's unknowns in the level's cell-dof array
+};
+
+// A tile of a frontal to be assembled (64 x 64 elements starting at (r0, c0)).
+struct Tile {
+    int32_t cell;
+    int32_t r0;
+    int32_t c0;
+    int32_t pad;
+};
+
+// A separator group for the block-Jacobi step: where its diagonal block sits in every
+// cell frontal that contains it, and where its Cholesky factor goes.
+struct SepDesc {
+    int32_t n;
+    int32_t nslot;
+    int32_t slot_cell[kMaxSlots];
+    int32_t slot_off[kMaxSlots];   // frontal position of the group's first unknown
+    int64_t loff;                  // offset of L_g (n x n, ld n) in the group pool
+    int32_t dofs;                  // offset of its unknowns in the level's group-dof array
+    int32_t pad;
+};
+
+// One boundary group of one cell, for the two-sided block-Jacobi scaling of the cell.
+struct CellGroup {
+    int32_t off;     // frontal position of the group's first unknown
+    int32_t n;
+    int64_t loff;    // L_g offset in the group pool
+    int32_t owner;   // 1 if this cell holds the group's diagonal block after scaling
+    int32_t pad;
+};
+
+struct CellScaleDesc {
+    int64_t off;     // frontal offset
+    int32_t ld;
+    int32_t nI;
+    int32_t nB;
+    int32_t g_begin; // first CellGroup of this cell
+    int32_t g_count;
+    int32_t pad;
+};
+
+// One edge (2D) / face (3D) to be skeletonized.
+struct SkelDesc {
+    int32_t n;           // group size
+    int32_t r;           // rows of M = A[R_g, g]
+    int32_t nslot;       // cells containing the group (1 or 2)
+    int32_t rows;        // offset of the (pos1, pos2) row table
+    int32_t cell[2];
+    int32_t off[2];      // frontal position of the group's first unknown in each cell
+    int64_t moff;        // scratch for M (r x n) and later A_hat,hat T
+    int64_t toff;        // T (k x (n-k), ld k), room for floor(n^2/4)+1
+    int64_t goff;        // skeleton block G (n x n): [A~_tt, .; A~_ht, A_hh]
+    int32_t gid;         // index into the rank / pivot outputs
+    int32_t poff;        // offset of this group's pivot order in the pivot output
+};
+
+// One block of the factor apply: L in [0,nI)^2 and W^T in rows [nI, nI+nB) of columns
+// [0, nI) of the matrix at `off`; optionally an interpolation matrix T (nB x nI, ld nB).
+struct ApplyDesc {
+    int64_t off;
+    int64_t toff;        // -1: no T
+    int64_t yoff;        // >= 0: write y = W^T z_I to the scratch; -1: z_B -= y in place
+    int64_t wsoff;       // >= 0: stage z_I, z_B in this global workspace instead of LDS
+    int32_t ld;
+    int32_t nI;
+    int32_t nB;
+    int32_t dofs;        // offset of nI interior then nB boundary unknowns (global indices)
+};
+
+// Gather of the up-sweep boundary contributions of the cells for one separator group.
+struct GatherDesc {
+    int32_t n;
+    int32_t dofs;
+    int32_t nslot;
+    int32_t pad;
+    int64_t yoff[kMaxSlots];  // scratch position of the group's first unknown in each cell
+};
+
+}  // namespace rhif

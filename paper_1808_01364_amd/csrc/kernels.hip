@@ -1,0 +1,875 @@
+// HIP kernels for gfx950 (CDNA4, 64-wide wavefronts) of the recursively preconditioned
+// hierarchical interpolative factorization and its PCG solve.
+//
+// Every batched kernel runs one 256-thread workgroup (4 waves) per block of the batch and
+// works on dense FP64 column-major matrices in HBM; small operands are staged in LDS.
+// The dense Schur-complement updates use the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64). Nothing uses floating-point atomics: every sum that several
+// blocks contribute to is formed by one thread in a fixed order, so results are bitwise
+// repeatable run to run.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "devstructs.hpp"
+#include "kernels.hpp"
+
+namespace rhif {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kWG = 256;
+constexpr int kWaves = kWG / 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ void report(unsigned long long* err, unsigned long long code) {
+    atomicMin(err, code);
+}
+
+__device__ __forceinline__ unsigned long long err_code(int level, int step, int block) {
+    return (static_cast<unsigned long long>(level) << 40) |
+           (static_cast<unsigned long long>(step) << 32) |
+           static_cast<unsigned long long>(static_cast<uint32_t>(block));
+}
+
+// ---------------------------------------------------------------------------------------
+// Workgroup-collective partial Cholesky (right-looking, 16-column panels).
+//
+// On entry the lower triangle of the n x n matrix A (column-major, ld) holds the
+// symmetric matrix [[D, X^T], [X, S]] with D of order p. On exit
+//   A[0:p, 0:p]  = L  with D = L L^T                       (Sec. 2.1: L_I = chol(A_II))
+//   A[p:n, 0:p]  = X L^-T = W^T                             (W = L^-1 A_BI^T)
+//   A[p:n, p:n]  = S - W^T W, stored in full (both triangles)  (the Schur complement)
+// Trailing updates of every panel go through the FP64 matrix cores, one 16 x 16 tile per
+// wave at a time. A pivot <= 0 or NaN reports `code` (the smallest code wins) and the
+// factorization continues with pivot 1 so that every wave still finishes.
+// smem: 16*17 doubles for the diagonal block, then panel_cap*17 doubles for the panel.
+// ---------------------------------------------------------------------------------------
+__device__ void wg_potrf_partial(double* __restrict__ A, int ld, int n, int p, double* smem,
+                                 int panel_cap, unsigned long long* err, unsigned long long code) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* Ld = smem;
+    double* Pl = smem + 16 * 17;
+    for (int j0 = 0; j0 < p; j0 += 16) {
+        const int jb = min(16, p - j0);
+        const int j1 = j0 + jb;
+        const int m = n - j1;
+        // (1) unblocked Cholesky of the diagonal block in the registers of wave 0:
+        //     lane i holds row i.
+        if (wave == 0) {
+            double r[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                r[c] = (lane < jb && c <= lane) ? A[(j0 + lane) + static_cast<size_t>(j0 + c) * ld] : 0.0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                if (c < jb) {
+                    double dcc = __shfl(r[c], c, 64);
+                    if (!(dcc > 0.0) || !(dcc < INFINITY)) {
+                        if (lane == 0) report(err, code);
+                        dcc = 1.0;
+                    }
+                    const double lcc = sqrt(dcc);
+                    if (lane == c) r[c] = lcc;
+                    else if (lane > c) r[c] = r[c] / lcc;
+#pragma unroll
+                    for (int q = c + 1; q < 16; ++q) {
+                        const double lqc = __shfl(r[c], q, 64);
+                        if (q < jb && lane >= q) r[q] -= r[c] * lqc;
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                if (lane < jb && c <= lane) A[(j0 + lane) + static_cast<size_t>(j0 + c) * ld] = r[c];
+                if (lane < 16) Ld[lane * 17 + c] = (lane < jb && c <= lane) ? r[c] : 0.0;
+            }
+        }
+        __syncthreads();
+        // (2) panel: rows below the block solve  x L_blk^T = a  (forward substitution).
+        const bool lds_panel = (m <= panel_cap);
+        for (int i = j1 + tid; i < n; i += kWG) {
+            double a[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) a[c] = (c < jb) ? A[i + static_cast<size_t>(j0 + c) * ld] : 0.0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                if (c < jb) {
+                    double v = a[c];
+#pragma unroll
+                    for (int q = 0; q < c; ++q) v -= a[q] * Ld[c * 17 + q];
+                    a[c] = v / Ld[c * 17 + c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                if (c < jb) A[i + static_cast<size_t>(j0 + c) * ld] = a[c];
+                if (lds_panel) Pl[(i - j1) * 17 + c] = (c < jb) ? a[c] : 0.0;
+            }
+        }
+        __syncthreads();
+        // (3) trailing update of the lower triangle: A22 -= P P^T on the matrix cores.
+        const int nt = (m + 15) >> 4;
+        const int ntiles = nt * (nt + 1) / 2;
+        for (int t = wave; t < ntiles; t += kWaves) {
+            int ti = static_cast<int>((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+            while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+            while (ti * (ti + 1) / 2 > t) --ti;
+            const int tj = t - ti * (ti + 1) / 2;
+            const int ra = ti * 16 + (lane & 15);
+            const int rb = tj * 16 + (lane & 15);
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 16; kk += 4) {
+                const int k = kk + (lane >> 4);
+                double a = 0.0, b = 0.0;
+                if (k < jb) {
+                    if (lds_panel) {
+                        if (ra < m) a = Pl[ra * 17 + k];
+                        if (rb < m) b = Pl[rb * 17 + k];
+                    } else {
+                        if (ra < m) a = A[(j1 + ra) + static_cast<size_t>(j0 + k) * ld];
+                        if (rb < m) b = A[(j1 + rb) + static_cast<size_t>(j0 + k) * ld];
+                    }
+                }
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
+            // lane holds D[lane/16 + 4 q][lane % 16], q = 0..3
+            const int col = tj * 16 + (lane & 15);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = ti * 16 + (lane >> 4) + 4 * q;
+                if (row < m && col < m && row >= col)
+                    A[(j1 + row) + static_cast<size_t>(j1 + col) * ld] -= acc[q];
+            }
+        }
+        __syncthreads();
+    }
+    // the Schur complement in full
+    const int ms = n - p;
+    for (int e = tid; e < ms * ms; e += kWG) {
+        const int i = e % ms, j = e / ms;
+        if (i < j) A[(p + i) + static_cast<size_t>(p + j) * ld] = A[(p + j) + static_cast<size_t>(p + i) * ld];
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------------
+// Workgroup-collective interpolative decomposition by Householder QR with column pivoting
+// (Sec. 2.2). At step j the pivot is the trailing column with the largest 2-norm over rows
+// j.. (recomputed, not downdated; ties to the lowest column); steps continue while
+// |R_jj| > eps |R_11|. Returns k; perm[] (LDS) holds the column order; M holds R in its
+// first k rows (columns in pivot order).
+// ---------------------------------------------------------------------------------------
+__device__ int wg_cpqr(double* __restrict__ M, int ld, int r, int n, double eps, int* perm,
+                       double* nrm2, double* red) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < n; e += kWG) perm[e] = e;
+    __syncthreads();
+    const int kmax = min(r, n);
+    double r11 = 0.0;
+    int k = 0;
+    for (int j = 0; j < kmax; ++j) {
+        for (int c = j + wave; c < n; c += kWaves) {
+            double s = 0.0;
+            for (int i = j + lane; i < r; i += 64) {
+                const double v = M[i + static_cast<size_t>(c) * ld];
+                s += v * v;
+            }
+            s = wave_sum(s);
+            if (lane == 0) nrm2[c] = s;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            double best = -1.0;
+            int bi = n;
+            for (int c = j + lane; c < n; c += 64) {
+                const double v = nrm2[c];
+                if (v > best) {
+                    best = v;
+                    bi = c;
+                }
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_xor(best, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
+                if (ob > best || (ob == best && oi < bi)) {
+                    best = ob;
+                    bi = oi;
+                }
+            }
+            if (lane == 0) {
+                red[0] = best;
+                red[1] = static_cast<double>(bi);
+            }
+        }
+        __syncthreads();
+        const double bn2 = red[0];
+        const int piv = static_cast<int>(red[1]);
+        const double nrm = sqrt(bn2);
+        if (j == 0) r11 = nrm;
+        if (!(nrm > eps * r11)) break;
+        if (piv != j) {
+            for (int i = tid; i < r; i += kWG) {
+                const double t0 = M[i + static_cast<size_t>(j) * ld];
+                M[i + static_cast<size_t>(j) * ld] = M[i + static_cast<size_t>(piv) * ld];
+                M[i + static_cast<size_t>(piv) * ld] = t0;
+            }
+            if (tid == 0) {
+                const int t1 = perm[j];
+                perm[j] = perm[piv];
+                perm[piv] = t1;
+            }
+        }
+        __syncthreads();
+        const double x0 = M[j + static_cast<size_t>(j) * ld];
+        const double alpha = -copysign(nrm, x0);
+        const double v0 = x0 - alpha;
+        const double beta = 2.0 / (2.0 * nrm * (nrm + fabs(x0)));   // 2 / (v^T v)
+        for (int c = j + 1 + wave; c < n; c += kWaves) {
+            double dot = 0.0;
+            for (int i = j + 1 + lane; i < r; i += 64)
+                dot += M[i + static_cast<size_t>(j) * ld] * M[i + static_cast<size_t>(c) * ld];
+            dot = wave_sum(dot) + v0 * M[j + static_cast<size_t>(c) * ld];
+            const double f = beta * dot;
+            if (lane == 0) M[j + static_cast<size_t>(c) * ld] -= f * v0;
+            for (int i = j + 1 + lane; i < r; i += 64)
+                M[i + static_cast<size_t>(c) * ld] -= f * M[i + static_cast<size_t>(j) * ld];
+        }
+        __syncthreads();
+        if (tid == 0) M[j + static_cast<size_t>(j) * ld] = alpha;
+        __syncthreads();
+        k = j + 1;
+    }
+    return k;
+}
+
+// ---------------------------------------------------------------------------------------
+// Assembly of A = h^-2 K(a) + diag(b) (5-point / 7-point, Sec. 3.1 / 3.2): one thread per
+// row; the row pointer was filled on the host.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double edge_coef(const double* a, int d, int s, int k, const int* x, int xk) {
+#pragma clang fp contract(off)
+    // mean of the 2^(d-1) cells containing the grid edge from (.., xk, ..) to (.., xk+1, ..)
+    // along axis k: cell c_k = xk, c_j in {x_j - 1, x_j} for j != k (last other axis fastest)
+    const int s1 = s + 1;
+    double acc = 0.0;
+    int oth[2];
+    int no = 0;
+    for (int j = 0; j < d; ++j)
+        if (j != k) oth[no++] = j;
+    const int combos = 1 << no;
+    for (int t = 0; t < combos; ++t) {
+        int64_t lin = 0, mul = 1;
+        for (int j = 0; j < d; ++j) {
+            int cj;
+            if (j == k) {
+                cj = xk;
+            } else {
+                const int which = (j == oth[0]) ? (no == 2 ? ((t >> 1) & 1) : (t & 1)) : (t & 1);
+                cj = x[j] - 1 + which;
+            }
+            lin += cj * mul;
+            mul *= s1;
+        }
+        acc += a[lin];
+    }
+    return acc / static_cast<double>(combos);
+}
+
+__global__ __launch_bounds__(256) void k_assemble_fd(int d, int s, double inv_h2, const double* __restrict__ a,
+                                                     const double* __restrict__ b, const int32_t* __restrict__ row_ptr,
+                                                     int32_t* __restrict__ col, double* __restrict__ val) {
+#pragma clang fp contract(off)
+    const int64_t N = (d == 2) ? static_cast<int64_t>(s) * s : static_cast<int64_t>(s) * s * s;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < N;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        int x[3];
+        int64_t r = i;
+        for (int k = 0; k < d; ++k) {
+            x[k] = static_cast<int>(r % s) + 1;
+            r /= s;
+        }
+        double diag = 0.0;
+        double off_lo[3], off_hi[3];
+        for (int k = 0; k < d; ++k) {
+            const double lo = edge_coef(a, d, s, k, x, x[k] - 1) * inv_h2;
+            const double hi = edge_coef(a, d, s, k, x, x[k]) * inv_h2;
+            diag = diag + (lo + hi);
+            off_lo[k] = -lo;
+            off_hi[k] = -hi;
+        }
+        if (b != nullptr) diag = diag + b[i];
+        int64_t stride[3] = {1, s, static_cast<int64_t>(s) * s};
+        int e = row_ptr[i];
+        for (int k = d - 1; k >= 0; --k)
+            if (x[k] > 1) {
+                col[e] = static_cast<int32_t>(i - stride[k]);
+                val[e] = off_lo[k];
+                ++e;
+            }
+        col[e] = static_cast<int32_t>(i);
+        val[e] = diag;
+        ++e;
+        for (int k = 0; k < d; ++k)
+            if (x[k] < s) {
+                col[e] = static_cast<int32_t>(i + stride[k]);
+                val[e] = off_hi[k];
+                ++e;
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Level-0 frontal assembly: frontal element (p, q) of cell c is A[i, j] (i, j its unknowns)
+// when c is the first cell (lowest index) whose closure contains both i and j, else 0.
+// Every entry of A lands in exactly one frontal, so the frontals add up to A.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_front_csr(const Tile* __restrict__ tiles, const CellRef* __restrict__ cells,
+                                                   const int32_t* __restrict__ cdofs, int d, int s, int w, int nc1,
+                                                   const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                                   const double* __restrict__ val, double* __restrict__ F) {
+    const Tile t = tiles[blockIdx.x];
+    const CellRef cr = cells[t.cell];
+    const int nf = cr.nf;
+    const int p = t.r0 + (threadIdx.x & 63);
+    const bool prow = p < nf;
+    int xi[3] = {0, 0, 0};
+    int i = 0;
+    if (prow) {
+        i = cdofs[cr.dptr + p];
+        int rr = i;
+        for (int k = 0; k < d; ++k) {
+            xi[k] = rr % s + 1;
+            rr /= s;
+        }
+    }
+    for (int cq = threadIdx.x >> 6; cq < 64; cq += 4) {
+        const int q = t.c0 + cq;
+        if (q >= nf || !prow) continue;
+        const int j = cdofs[cr.dptr + q];
+        int xj[3];
+        int rr = j;
+        int dist = 0;
+        for (int k = 0; k < d; ++k) {
+            xj[k] = rr % s + 1;
+            rr /= s;
+            dist += abs(xj[k] - xi[k]);
+        }
+        double v = 0.0;
+        if (dist <= 1) {
+            // first common cell, axis by axis
+            int64_t own = 0, mul = 1;
+            bool ok = true;
+            for (int k = 0; k < d; ++k) {
+                const int a = xi[k], bb = xj[k];
+                const int alo = (a % w) ? a / w : max(a / w - 1, 0);
+                const int ahi = (a % w) ? a / w : min(a / w, nc1 - 1);
+                const int blo = (bb % w) ? bb / w : max(bb / w - 1, 0);
+                const int bhi = (bb % w) ? bb / w : min(bb / w, nc1 - 1);
+                const int lo = max(alo, blo), hi = min(ahi, bhi);
+                if (lo > hi) ok = false;
+                own += lo * mul;
+                mul *= nc1;
+            }
+            if (ok && own == t.cell) {
+                for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+                    if (col[e] == j) {
+                        v = val[e];
+                        break;
+                    }
+            }
+        }
+        F[cr.off + p + static_cast<size_t>(q) * cr.ld] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Level >= 1 frontal assembly ("extend-add"): frontal element (p, q) of cell c is the sum,
+// over the children of c whose closures contain both unknowns (ascending child index),
+// of the children's Schur-complement shares.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_front_extend(const Tile* __restrict__ tiles, const CellRef* __restrict__ cells,
+                                                      const int32_t* __restrict__ src, int W,
+                                                      const CellRef* __restrict__ child, const double* __restrict__ Fc,
+                                                      double* __restrict__ F) {
+    const Tile t = tiles[blockIdx.x];
+    const CellRef cr = cells[t.cell];
+    const int nf = cr.nf;
+    const int p = t.r0 + (threadIdx.x & 63);
+    if (p >= nf) return;
+    int pc[8], pp[8];
+    int np = 0;
+    const int32_t* sp = src + static_cast<size_t>(cr.dptr + p) * 2 * W;
+    for (int a = 0; a < W; ++a) {
+        const int c = sp[2 * a];
+        if (c < 0) break;
+        pc[np] = c;
+        pp[np] = sp[2 * a + 1];
+        ++np;
+    }
+    for (int cq = threadIdx.x >> 6; cq < 64; cq += 4) {
+        const int q = t.c0 + cq;
+        if (q >= nf) break;
+        const int32_t* sq = src + static_cast<size_t>(cr.dptr + q) * 2 * W;
+        double v = 0.0;
+        int b = 0;
+        for (int a = 0; a < np; ++a) {
+            // both source lists are sorted by child index
+            while (b < W) {
+                const int cb = sq[2 * b];
+                if (cb < 0 || cb >= pc[a]) break;
+                ++b;
+            }
+            if (b < W && sq[2 * b] == pc[a]) {
+                const CellRef ch = child[pc[a]];
+                v += Fc[ch.off + pp[a] + static_cast<size_t>(sq[2 * b + 1]) * ch.ld];
+            }
+        }
+        F[cr.off + p + static_cast<size_t>(q) * cr.ld] = v;
+    }
+}
+
+// Batched partial Cholesky of cell frontals (cell elimination, Sec. 2.1) or of the root.
+__global__ __launch_bounds__(256) void k_potrf_batch(const FrontDesc* __restrict__ desc, double* __restrict__ pool,
+                                                     int panel_cap, int level, int step, unsigned long long* err) {
+    extern __shared__ double smem[];
+    const FrontDesc fd = desc[blockIdx.x];
+    wg_potrf_partial(pool + fd.off, fd.ld, fd.n, fd.p, smem, panel_cap, err, err_code(level, step, fd.id));
+}
+
+// ---------------------------------------------------------------------------------------
+// Block-Jacobi step (Sec. 2.3), part 1: for every separator group g, gather its diagonal
+// block from every cell that holds a share of it and factor it, A_gg = L_g L_g^T.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_precond_groups(const SepDesc* __restrict__ sd, const CellRef* __restrict__ cells,
+                                                        const double* __restrict__ F, double* __restrict__ Lg,
+                                                        int panel_cap, int level, unsigned long long* err) {
+    extern __shared__ double smem[];
+    const SepDesc g = sd[blockIdx.x];
+    const int n = g.n;
+    double* L = Lg + g.loff;
+    for (int e = threadIdx.x; e < n * n; e += kWG) {
+        const int a = e % n, b = e / n;
+        double v = 0.0;
+        for (int sl = 0; sl < g.nslot; ++sl) {
+            const CellRef c = cells[g.slot_cell[sl]];
+            v += F[c.off + (g.slot_off[sl] + a) + static_cast<size_t>(g.slot_off[sl] + b) * c.ld];
+        }
+        L[e] = v;
+    }
+    __syncthreads();
+    wg_potrf_partial(L, n, n, n, smem, panel_cap, err, err_code(level, 1, blockIdx.x));
+}
+
+// Block-Jacobi step, part 2: every cell's share S of the separator matrix becomes
+// Lambda^-1 S Lambda^-T with Lambda = blockdiag(L_g) over the cell's boundary groups; the
+// diagonal blocks become I in the group's first cell and 0 in the others, so that the
+// assembled matrix has unit block diagonal.
+__global__ __launch_bounds__(256) void k_precond_scale(const CellScaleDesc* __restrict__ cd,
+                                                       const CellGroup* __restrict__ cg, const double* __restrict__ Lg,
+                                                       double* __restrict__ F) {
+    const CellScaleDesc c = cd[blockIdx.x];
+    double* A = F + c.off;
+    const int ld = c.ld;
+    // rows: U = S Lambda^-T
+    for (int i = threadIdx.x; i < c.nB; i += kWG) {
+        const int row = c.nI + i;
+        for (int e = 0; e < c.g_count; ++e) {
+            const CellGroup h = cg[c.g_begin + e];
+            const double* L = Lg + h.loff;
+            for (int q = 0; q < h.n; ++q) {
+                double v = A[row + static_cast<size_t>(h.off + q) * ld];
+                for (int t = 0; t < q; ++t) v -= L[q + t * h.n] * A[row + static_cast<size_t>(h.off + t) * ld];
+                A[row + static_cast<size_t>(h.off + q) * ld] = v / L[q + q * h.n];
+            }
+        }
+    }
+    __syncthreads();
+    // columns: Y = Lambda^-1 U
+    for (int j = threadIdx.x; j < c.nB; j += kWG) {
+        double* colp = A + static_cast<size_t>(c.nI + j) * ld;
+        for (int e = 0; e < c.g_count; ++e) {
+            const CellGroup g = cg[c.g_begin + e];
+            const double* L = Lg + g.loff;
+            for (int q = 0; q < g.n; ++q) {
+                double v = colp[g.off + q];
+                for (int t = 0; t < q; ++t) v -= L[q + t * g.n] * colp[g.off + t];
+                colp[g.off + q] = v / L[q + q * g.n];
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = 0; e < c.g_count; ++e) {
+        const CellGroup g = cg[c.g_begin + e];
+        for (int x = threadIdx.x; x < g.n * g.n; x += kWG) {
+            const int a = x % g.n, b = x / g.n;
+            A[(g.off + a) + static_cast<size_t>(g.off + b) * ld] = (g.owner && a == b) ? 1.0 : 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Skeletonization of one edge (2D) / face (3D) (Sec. 2.2), all groups of a level from the
+// same matrix:
+//   1. M = A[R_g, g]: the group's columns over the other boundary unknowns of its one or
+//      two cells, the shares of both cells added;
+//   2. ID by column-pivoted QR -> rank k, pivot order, T = R11^-1 R12;
+//   3. the zeroed blocks of eq. (eq_T) in the order (redundant, skeleton):
+//        G = [[A~_tt, A~_ht^T], [A~_ht, A_hh]] with
+//        A~_tt = A_tt - T^T A_ht - A_ht^T T + T^T A_hh T,  A~_ht = A_ht - A_hh T;
+//   4. partial Cholesky of G over the n-k redundant unknowns: L~, W~^T and the new
+//      skeleton block A_hh - W~^T W~;
+//   5. the new skeleton block goes to the group's first cell, the other cell's share of
+//      the group's diagonal block is cleared. Couplings of the redundant unknowns to R are
+//      dropped simply by not carrying them to the next level.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict__ sd, const int32_t* __restrict__ rows,
+                                                     const CellRef* __restrict__ cells, double* __restrict__ F,
+                                                     double* __restrict__ Mpool, double* __restrict__ Tpool,
+                                                     double* __restrict__ Gpool, double eps, int32_t* __restrict__ kout,
+                                                     int32_t* __restrict__ pout, int panel_cap, int level,
+                                                     unsigned long long* err) {
+    extern __shared__ double smem[];
+    const SkelDesc g = sd[blockIdx.x];
+    const int n = g.n, r = g.r;
+    double* M = Mpool + g.moff;
+    const int32_t* rw = rows + static_cast<size_t>(g.rows) * 2;
+    const CellRef c0 = cells[g.cell[0]];
+    CellRef c1 = c0;
+    if (g.nslot > 1) c1 = cells[g.cell[1]];
+    // 1. gather M
+    for (int e = threadIdx.x; e < r * n; e += kWG) {
+        const int i = e % r, j = e / r;
+        const int p1 = rw[2 * i], p2 = rw[2 * i + 1];
+        double v = 0.0;
+        if (p1 >= 0) v += F[c0.off + p1 + static_cast<size_t>(g.off[0] + j) * c0.ld];
+        if (p2 >= 0) v += F[c1.off + p2 + static_cast<size_t>(g.off[1] + j) * c1.ld];
+        M[e] = v;
+    }
+    __syncthreads();
+    // 2. ID
+    int* perm = reinterpret_cast<int*>(smem);              // n ints
+    double* nrm2 = smem + ((n + 1) / 2 + 1);               // n doubles
+    double* red = nrm2 + n;                                // 2 doubles
+    const int k = wg_cpqr(M, r, r, n, eps, perm, nrm2, red);
+    const int nr = n - k;
+    double* T = Tpool + g.toff;
+    for (int c = k + threadIdx.x; c < n; c += kWG) {
+        double* Tc = T + static_cast<size_t>(c - k) * k;
+        for (int i = k - 1; i >= 0; --i) {
+            double v = M[i + static_cast<size_t>(c) * r];
+            for (int e = i + 1; e < k; ++e) v -= M[i + static_cast<size_t>(e) * r] * Tc[e];
+            Tc[i] = v / M[i + static_cast<size_t>(i) * r];
+        }
+    }
+    if (threadIdx.x == 0) kout[g.gid] = k;
+    for (int e = threadIdx.x; e < n; e += kWG) pout[g.poff + e] = perm[e];
+    __syncthreads();
+    // 3. zeroed blocks; U = A_hh T goes to the (now free) M scratch
+    auto Agg = [&](int a, int b) -> double {
+        double v = F[c0.off + (g.off[0] + a) + static_cast<size_t>(g.off[0] + b) * c0.ld];
+        if (g.nslot > 1) v += F[c1.off + (g.off[1] + a) + static_cast<size_t>(g.off[1] + b) * c1.ld];
+        return v;
+    };
+    double* U = M;
+    for (int e = threadIdx.x; e < k * nr; e += kWG) {
+        const int c = e % k, a = e / k;
+        double v = 0.0;
+        for (int q = 0; q < k; ++q) v += Agg(perm[c], perm[q]) * T[q + static_cast<size_t>(a) * k];
+        U[e] = v;
+    }
+    __syncthreads();
+    double* G = Gpool + g.goff;
+    for (int e = threadIdx.x; e < n * n; e += kWG) {
+        const int a = e % n, b = e / n;
+        if (a < b) continue;
+        double v;
+        if (b < nr && a < nr) {
+            const int ta = perm[k + a], tb = perm[k + b];
+            v = Agg(ta, tb);
+            for (int c = 0; c < k; ++c) {
+                const int hc = perm[c];
+                v -= T[c + static_cast<size_t>(a) * k] * Agg(hc, tb);
+                v -= Agg(hc, ta) * T[c + static_cast<size_t>(b) * k];
+                v += T[c + static_cast<size_t>(a) * k] * U[c + static_cast<size_t>(b) * k];
+            }
+        } else if (b < nr) {
+            const int c = a - nr;
+            v = Agg(perm[c], perm[k + b]) - U[c + static_cast<size_t>(b) * k];
+        } else {
+            v = Agg(perm[a - nr], perm[b - nr]);
+        }
+        G[e] = v;
+    }
+    __syncthreads();
+    // 4. eliminate the redundant unknowns (smem: the perm ints must survive)
+    double* psmem = smem + ((n + 1) / 2 + 1);
+    wg_potrf_partial(G, n, n, nr, psmem, panel_cap, err, err_code(level, 2, blockIdx.x));
+    // 5. write back the skeleton block
+    for (int e = threadIdx.x; e < n * n; e += kWG) {
+        const int a = e % n, b = e / n;
+        if (a < k && b < k) {
+            // skeleton a, b sit at positions perm[a], perm[b] of the group's ascending order
+            F[c0.off + (g.off[0] + perm[a]) + static_cast<size_t>(g.off[0] + perm[b]) * c0.ld] =
+                G[(nr + a) + static_cast<size_t>(nr + b) * n];
+        }
+        if (g.nslot > 1) F[c1.off + (g.off[1] + a) + static_cast<size_t>(g.off[1] + b) * c1.ld] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Factor apply (eq. (eqAinv)). One workgroup per block; z_I and z_B are staged in LDS (or
+// in a global workspace for oversized blocks). Triangular solves go by 32-row blocks: the
+// diagonal block is solved by one wave from LDS, the rest is a GEMV by all threads.
+// ---------------------------------------------------------------------------------------
+constexpr int kTB = 32;
+
+__device__ void wg_trsv_lower(const double* __restrict__ L, int ld, int n, double* z, double* Dg) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int j0 = 0; j0 < n; j0 += kTB) {
+        const int jb = min(kTB, n - j0);
+        for (int e = tid; e < jb * jb; e += kWG) {
+            const int a = e % jb, b = e / jb;
+            Dg[a * (kTB + 1) + b] = L[(j0 + a) + static_cast<size_t>(j0 + b) * ld];
+        }
+        __syncthreads();
+        if (wave == 0) {
+            double x = (lane < jb) ? z[j0 + lane] : 0.0;
+            for (int c = 0; c < jb; ++c) {
+                const double xc = __shfl(x, c, 64) / Dg[c * (kTB + 1) + c];
+                if (lane == c) x = xc;
+                else if (lane > c && lane < jb) x -= Dg[lane * (kTB + 1) + c] * xc;
+            }
+            if (lane < jb) z[j0 + lane] = x;
+        }
+        __syncthreads();
+        for (int i = j0 + jb + tid; i < n; i += kWG) {
+            double acc = 0.0;
+            for (int c = 0; c < jb; ++c) acc += L[i + static_cast<size_t>(j0 + c) * ld] * z[j0 + c];
+            z[i] -= acc;
+        }
+        __syncthreads();
+    }
+}
+
+__device__ void wg_trsv_lower_t(const double* __restrict__ L, int ld, int n, double* z, double* Dg) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nblk = (n + kTB - 1) / kTB;
+    for (int bi = nblk - 1; bi >= 0; --bi) {
+        const int j0 = bi * kTB;
+        const int jb = min(kTB, n - j0);
+        for (int e = tid; e < jb * jb; e += kWG) {
+            const int a = e % jb, b = e / jb;
+            Dg[a * (kTB + 1) + b] = L[(j0 + a) + static_cast<size_t>(j0 + b) * ld];
+        }
+        __syncthreads();
+        if (wave == 0) {
+            double x = (lane < jb) ? z[j0 + lane] : 0.0;
+            for (int c = jb - 1; c >= 0; --c) {
+                const double xc = __shfl(x, c, 64) / Dg[c * (kTB + 1) + c];
+                if (lane == c) x = xc;
+                else if (lane < c) x -= Dg[c * (kTB + 1) + lane] * xc;
+            }
+            if (lane < jb) z[j0 + lane] = x;
+        }
+        __syncthreads();
+        for (int i = tid; i < j0; i += kWG) {
+            double acc = 0.0;
+            const double* Li = L + static_cast<size_t>(i) * ld + j0;
+            for (int c = 0; c < jb; ++c) acc += Li[c] * z[j0 + c];
+            z[i] -= acc;
+        }
+        __syncthreads();
+    }
+}
+
+// Up-sweep block: [z_I -= T^T z_B]; z_I <- L^-1 z_I; y = W^T z_I -> scratch or z_B -= y.
+__global__ __launch_bounds__(256) void k_apply_up(const ApplyDesc* __restrict__ ad, const double* __restrict__ pool,
+                                                  const double* __restrict__ Tp, const int32_t* __restrict__ dofs,
+                                                  double* __restrict__ z, double* __restrict__ ybuf,
+                                                  double* __restrict__ ws) {
+    extern __shared__ double smem[];
+    const ApplyDesc d = ad[blockIdx.x];
+    double* Dg = smem;
+    double* zI = (d.wsoff >= 0) ? ws + d.wsoff : smem + kTB * (kTB + 1);
+    double* zB = zI + d.nI;
+    const int32_t* di = dofs + d.dofs;
+    const int32_t* db = di + d.nI;
+    const bool needB = (d.toff >= 0) || (d.yoff < 0);
+    for (int i = threadIdx.x; i < d.nI; i += kWG) zI[i] = z[di[i]];
+    if (needB)
+        for (int i = threadIdx.x; i < d.nB; i += kWG) zB[i] = z[db[i]];
+    __syncthreads();
+    if (d.toff >= 0) {
+        const double* T = Tp + d.toff;
+        for (int a = threadIdx.x; a < d.nI; a += kWG) {
+            double acc = 0.0;
+            for (int c = 0; c < d.nB; ++c) acc += T[c + static_cast<size_t>(a) * d.nB] * zB[c];
+            zI[a] -= acc;
+        }
+        __syncthreads();
+    }
+    const double* A = pool + d.off;
+    wg_trsv_lower(A, d.ld, d.nI, zI, Dg);
+    for (int i = threadIdx.x; i < d.nI; i += kWG) z[di[i]] = zI[i];
+    for (int b = threadIdx.x; b < d.nB; b += kWG) {
+        double acc = 0.0;
+        for (int i = 0; i < d.nI; ++i) acc += A[(d.nI + b) + static_cast<size_t>(i) * d.ld] * zI[i];
+        if (d.yoff >= 0) ybuf[d.yoff + b] = acc;
+        else z[db[b]] = zB[b] - acc;
+    }
+}
+
+// Down-sweep block: z_I <- L^-T (z_I - W z_B); [z_B -= T z_I].
+__global__ __launch_bounds__(256) void k_apply_down(const ApplyDesc* __restrict__ ad, const double* __restrict__ pool,
+                                                    const double* __restrict__ Tp, const int32_t* __restrict__ dofs,
+                                                    double* __restrict__ z, double* __restrict__ ws) {
+    extern __shared__ double smem[];
+    const ApplyDesc d = ad[blockIdx.x];
+    double* Dg = smem;
+    double* zI = (d.wsoff >= 0) ? ws + d.wsoff : smem + kTB * (kTB + 1);
+    double* zB = zI + d.nI;
+    const int32_t* di = dofs + d.dofs;
+    const int32_t* db = di + d.nI;
+    for (int i = threadIdx.x; i < d.nI; i += kWG) zI[i] = z[di[i]];
+    for (int i = threadIdx.x; i < d.nB; i += kWG) zB[i] = z[db[i]];
+    __syncthreads();
+    const double* A = pool + d.off;
+    for (int i = threadIdx.x; i < d.nI; i += kWG) {
+        double acc = 0.0;
+        const double* Wi = A + static_cast<size_t>(i) * d.ld + d.nI;
+        for (int b = 0; b < d.nB; ++b) acc += Wi[b] * zB[b];
+        zI[i] -= acc;
+    }
+    __syncthreads();
+    wg_trsv_lower_t(A, d.ld, d.nI, zI, Dg);
+    for (int i = threadIdx.x; i < d.nI; i += kWG) z[di[i]] = zI[i];
+    if (d.toff >= 0) {
+        const double* T = Tp + d.toff;
+        for (int c = threadIdx.x; c < d.nB; c += kWG) {
+            double acc = 0.0;
+            for (int a = 0; a < d.nI; ++a) acc += T[c + static_cast<size_t>(a) * d.nB] * zI[a];
+            z[db[c]] = zB[c] - acc;
+        }
+    }
+}
+
+// Up-sweep gather: z_g -= sum over the cells containing g (ascending) of their y share.
+__global__ __launch_bounds__(256) void k_sep_gather(const GatherDesc* __restrict__ gd, const int32_t* __restrict__ dofs,
+                                                    const double* __restrict__ ybuf, double* __restrict__ z) {
+    const GatherDesc g = gd[blockIdx.x];
+    for (int t = threadIdx.x; t < g.n; t += kWG) {
+        const int i = dofs[g.dofs + t];
+        double v = z[i];
+        for (int sl = 0; sl < g.nslot; ++sl) v -= ybuf[g.yoff[sl] + t];
+        z[i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// CG building blocks. Reductions are two-stage with a fixed grid: kRedBlocks partial sums
+// in a fixed layout, then one block adds them in a fixed order.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kWaves; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// q = A p and partial sums of p . q
+__global__ __launch_bounds__(256) void k_spmv_dot(int64_t N, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                  const double* __restrict__ v, const double* __restrict__ p,
+                                                  double* __restrict__ q, double* __restrict__ part) {
+    __shared__ double red[kWaves];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; i < N; i += static_cast<int64_t>(gridDim.x) * kWG) {
+        double s = 0.0;
+        for (int e = rp[i]; e < rp[i + 1]; ++e) s += v[e] * p[ci[e]];
+        q[i] = s;
+        acc += s * p[i];
+    }
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_dot(int64_t N, const double* __restrict__ x, const double* __restrict__ y,
+                                             double* __restrict__ part) {
+    __shared__ double red[kWaves];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; i < N; i += static_cast<int64_t>(gridDim.x) * kWG)
+        acc += x[i] * y[i];
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// scalar slots: 0 rho, 1 pq, 2 alpha, 3 rr, 4 rho_new, 5 beta, 6 ff
+// mode 0: sc[6] = sum;   mode 1: sc[1] = sum, alpha = rho / pq;   mode 2: sc[3] = sum;
+// mode 3: rho = sum (initial);   mode 4: beta = sum / rho, rho = sum.
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ part, int nparts, int mode,
+                                                  double* __restrict__ sc, double* __restrict__ host_out) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nparts; ++b) s += part[b];
+    switch (mode) {
+        case 0: sc[6] = s; if (host_out) host_out[0] = s; break;
+        case 1: sc[1] = s; sc[2] = sc[0] / s; break;
+        case 2: sc[3] = s; if (host_out) host_out[0] = s; break;
+        case 3: sc[0] = s; break;
+        case 4: sc[4] = s; sc[5] = s / sc[0]; sc[0] = s; break;
+        default: break;
+    }
+}
+
+// u += alpha p ; r -= alpha q ; partial sums of r . r
+__global__ __launch_bounds__(256) void k_axpy2(int64_t N, const double* __restrict__ sc, const double* __restrict__ p,
+                                               const double* __restrict__ q, double* __restrict__ u, double* __restrict__ r,
+                                               double* __restrict__ part) {
+    __shared__ double red[kWaves];
+    const double alpha = sc[2];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; i < N; i += static_cast<int64_t>(gridDim.x) * kWG) {
+        u[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        acc += ri * ri;
+    }
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(256) void k_update_p(int64_t N, const double* __restrict__ sc, const double* __restrict__ z,
+                                                  double* __restrict__ p) {
+    const double beta = sc[5];
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; i < N; i += static_cast<int64_t>(gridDim.x) * kWG)
+        p[i] = z[i] + beta * p[i];
+}
+
+__global__ __launch_bounds__(256) void k_copy(int64_t N, const double* __restrict__ x, double* __restrict__ y) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; i < N; i += static_cast<int64_t>(gridDim.x) * kWG)
+        y[i] = x[i];
+}
+
+__global__ __launch_bounds__(256) void k_fill(int64_t N, double v, double* __restrict__ y) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; i < N; i += static_cast<int64_t>(gridDim.x) * kWG)
+        y[i] = v;
+}
+
+__global__ void k_set_u64(unsigned long long* p, unsigned long long v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+}  // namespace rhif

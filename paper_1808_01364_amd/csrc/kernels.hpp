@@ -1,0 +1,43 @@
+// Declarations of the device kernels (defined in kernels.hip) for the host driver.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "devstructs.hpp"
+
+namespace rhif {
+
+__global__ void k_assemble_fd(int d, int s, double inv_h2, const double* a, const double* b,
+                              const int32_t* row_ptr, int32_t* col, double* val);
+__global__ void k_front_csr(const Tile* tiles, const CellRef* cells, const int32_t* cdofs, int d, int s, int w,
+                            int nc1, const int32_t* row_ptr, const int32_t* col, const double* val, double* F);
+__global__ void k_front_extend(const Tile* tiles, const CellRef* cells, const int32_t* src, int W,
+                               const CellRef* child, const double* Fc, double* F);
+__global__ void k_potrf_batch(const FrontDesc* desc, double* pool, int panel_cap, int level, int step,
+                              unsigned long long* err);
+__global__ void k_precond_groups(const SepDesc* sd, const CellRef* cells, const double* F, double* Lg,
+                                 int panel_cap, int level, unsigned long long* err);
+__global__ void k_precond_scale(const CellScaleDesc* cd, const CellGroup* cg, const double* Lg, double* F);
+__global__ void k_skeletonize(const SkelDesc* sd, const int32_t* rows, const CellRef* cells, double* F,
+                              double* Mpool, double* Tpool, double* Gpool, double eps, int32_t* kout,
+                              int32_t* pout, int panel_cap, int level, unsigned long long* err);
+__global__ void k_apply_up(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
+                           double* z, double* ybuf, double* ws);
+__global__ void k_apply_down(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
+                             double* z, double* ws);
+__global__ void k_sep_gather(const GatherDesc* gd, const int32_t* dofs, const double* ybuf, double* z);
+__global__ void k_spmv_dot(int64_t N, const int32_t* rp, const int32_t* ci, const double* v, const double* p,
+                           double* q, double* part);
+__global__ void k_dot(int64_t N, const double* x, const double* y, double* part);
+__global__ void k_finalize(const double* part, int nparts, int mode, double* sc, double* host_out);
+__global__ void k_axpy2(int64_t N, const double* sc, const double* p, const double* q, double* u, double* r,
+                        double* part);
+__global__ void k_update_p(int64_t N, const double* sc, const double* z, double* p);
+__global__ void k_copy(int64_t N, const double* x, double* y);
+__global__ void k_fill(int64_t N, double v, double* y);
+__global__ void k_set_u64(unsigned long long* p, unsigned long long v);
+
+constexpr int kApplyDiagDoubles = 32 * 33;   // LDS diagonal block of the apply kernels
+
+}  // namespace rhif

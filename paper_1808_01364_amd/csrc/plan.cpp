@@ -1,0 +1,561 @@
+// Host planner (integers only). See plan.hpp for the grouping rule.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+
+namespace rhif {
+
+namespace {
+
+inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Coordinates x_k in 1..s of linear unknown i (x_1 fastest).
+inline void coords(int64_t i, int d, int s, int* x) {
+    for (int k = 0; k < d; ++k) {
+        x[k] = static_cast<int>(i % s) + 1;
+        i /= s;
+    }
+}
+
+}  // namespace
+
+void PlanScratch::init(int64_t N) {
+    for (int t = 0; t < 2; ++t) {
+        dof_group[t].assign(N, -1);
+        dof_tpos[t].assign(N, -1);
+    }
+    mark_stamp.assign(N, 0);
+    mark_row.assign(N, 0);
+    stamp = 0;
+    cur = 0;
+}
+
+int num_levels(int s, int leaf) {
+    int L = 0;
+    while ((static_cast<int64_t>(leaf) << L) <= s) ++L;
+    return L;
+}
+
+void build_level(const GridInfo& gi, int level, int leaf, bool root,
+                 const std::vector<int32_t>& active, const LevelPlan* prev,
+                 PlanScratch& scr, int lds_apply_cap, LevelPlan& P) {
+    const int d = gi.d, s = gi.s;
+    P = LevelPlan();
+    P.level = level;
+    P.root = root;
+    const int64_t w = static_cast<int64_t>(leaf) << level;
+    P.w = static_cast<int>(w);
+    const int nc1 = static_cast<int>((s + w - 1) / w);
+    P.nc1 = nc1;
+    if (root && nc1 != 1) throw std::logic_error("root level must have a single cell");
+    const int KB = 2 * nc1 + 2;
+    int64_t nkeys = 1;
+    for (int k = 0; k < d; ++k) nkeys *= KB;
+
+    // ---- classify the active unknowns and bucket them by key (stable) ----
+    const size_t na = active.size();
+    std::vector<int32_t> akey(na);
+    scr.count.assign(nkeys + 1, 0);
+    int x[3];
+    for (size_t a = 0; a < na; ++a) {
+        coords(active[a], d, s, x);
+        int64_t K = 0, mul = 1;
+        for (int k = 0; k < d; ++k) {
+            const int key = 2 * static_cast<int>(x[k] / w) + ((x[k] % w) != 0 ? 1 : 0);
+            K += key * mul;
+            mul *= KB;
+        }
+        akey[a] = static_cast<int32_t>(K);
+        scr.count[K + 1]++;
+    }
+    scr.key2g.assign(nkeys, -1);
+    int ngroups = 0;
+    for (int64_t K = 0; K < nkeys; ++K)
+        if (scr.count[K + 1] > 0) scr.key2g[K] = ngroups++;
+    for (int64_t K = 0; K < nkeys; ++K) scr.count[K + 1] += scr.count[K];
+    P.gptr.assign(ngroups + 1, 0);
+    P.gcls.assign(ngroups, 0);
+    for (int64_t K = 0; K < nkeys; ++K) {
+        const int g = scr.key2g[K];
+        if (g < 0) continue;
+        P.gptr[g] = scr.count[K];
+        int64_t r = K;
+        int even = 0;
+        for (int k = 0; k < d; ++k) {
+            if (((r % KB) & 1) == 0) ++even;
+            r /= KB;
+        }
+        P.gcls[g] = static_cast<int8_t>(even);
+    }
+    P.gptr[ngroups] = static_cast<int32_t>(na);
+    P.gdofs.assign(na, 0);
+    {
+        std::vector<int32_t> pos(scr.count.begin(), scr.count.end() - 1);
+        for (size_t a = 0; a < na; ++a) P.gdofs[pos[akey[a]]++] = active[a];
+    }
+    const int cur = scr.cur;
+    for (int g = 0; g < ngroups; ++g)
+        for (int t = P.gptr[g]; t < P.gptr[g + 1]; ++t) {
+            scr.dof_group[cur][P.gdofs[t]] = g;
+            scr.dof_tpos[cur][P.gdofs[t]] = t - P.gptr[g];
+        }
+
+    // ---- cells: every geometric cell; frontal = interior, then boundary groups ----
+    int64_t ncells = 1;
+    for (int k = 0; k < d; ++k) ncells *= nc1;
+    P.ncells = static_cast<int>(ncells);
+    P.c_nI.assign(ncells, 0);
+    P.c_nB.assign(ncells, 0);
+    P.c_nf.assign(ncells, 0);
+    P.c_ld.assign(ncells, 0);
+    P.c_foff.assign(ncells, 0);
+    P.c_dptr.assign(ncells + 1, 0);
+    P.c_gptr.assign(ncells + 1, 0);
+    P.gslot_cnt.assign(ngroups, 0);
+    P.gslot_cell.assign(static_cast<size_t>(ngroups) * kMaxSlots, -1);
+    P.gslot_off.assign(static_cast<size_t>(ngroups) * kMaxSlots, -1);
+    P.c_dofs.reserve(na + na / 2);
+    int n3 = 1;
+    for (int k = 0; k < d; ++k) n3 *= 3;
+    int64_t foff = 0;
+    for (int64_t ci = 0; ci < ncells; ++ci) {
+        int c[3];
+        int64_t r = ci;
+        for (int k = 0; k < d; ++k) {
+            c[k] = static_cast<int>(r % nc1);
+            r /= nc1;
+        }
+        P.c_dptr[ci] = static_cast<int32_t>(P.c_dofs.size());
+        // interior group
+        int64_t KI = 0, mul = 1;
+        for (int k = 0; k < d; ++k) {
+            KI += (2 * c[k] + 1) * mul;
+            mul *= KB;
+        }
+        const int gI = scr.key2g[KI];
+        int nI = 0;
+        if (gI >= 0) {
+            nI = P.gptr[gI + 1] - P.gptr[gI];
+            P.c_dofs.insert(P.c_dofs.end(), P.gdofs.begin() + P.gptr[gI], P.gdofs.begin() + P.gptr[gI + 1]);
+        }
+        int nf = nI;
+        for (int t = 0; t < n3; ++t) {
+            int tt = t;
+            int64_t K = 0, m2 = 1;
+            bool all_one = true;
+            for (int k = 0; k < d; ++k) {
+                const int dk = tt % 3;
+                tt /= 3;
+                if (dk != 1) all_one = false;
+                K += (2 * c[k] + dk) * m2;
+                m2 *= KB;
+            }
+            if (all_one) continue;
+            const int g = scr.key2g[K];
+            if (g < 0) continue;
+            const int ng = P.gptr[g + 1] - P.gptr[g];
+            P.c_g.push_back(g);
+            P.c_goff.push_back(nf);
+            const int sl = P.gslot_cnt[g]++;
+            if (sl >= kMaxSlots) throw std::logic_error("group in too many cells");
+            P.gslot_cell[static_cast<size_t>(g) * kMaxSlots + sl] = static_cast<int32_t>(ci);
+            P.gslot_off[static_cast<size_t>(g) * kMaxSlots + sl] = nf;
+            P.c_dofs.insert(P.c_dofs.end(), P.gdofs.begin() + P.gptr[g], P.gdofs.begin() + P.gptr[g + 1]);
+            nf += ng;
+        }
+        P.c_gptr[ci + 1] = static_cast<int32_t>(P.c_g.size());
+        P.c_nI[ci] = nI;
+        P.c_nB[ci] = nf - nI;
+        P.c_nf[ci] = nf;
+        P.c_ld[ci] = std::max(nf, 1);
+        P.c_foff[ci] = foff;
+        foff += align_up(static_cast<int64_t>(P.c_ld[ci]) * nf, 32);
+        P.max_nf = std::max(P.max_nf, nf);
+    }
+    P.c_dptr[ncells] = static_cast<int32_t>(P.c_dofs.size());
+    P.front_elems = std::max<int64_t>(foff, 32);
+
+    // ---- batched descriptors of the cells ----
+    for (int64_t ci = 0; ci < ncells; ++ci) {
+        P.cell_ref.push_back(CellRef{P.c_foff[ci], P.c_ld[ci], P.c_nI[ci], P.c_nf[ci], P.c_dptr[ci]});
+        const int nf = P.c_nf[ci];
+        for (int c0 = 0; c0 < nf; c0 += 64)
+            for (int r0 = 0; r0 < nf; r0 += 64)
+                P.tiles.push_back(Tile{static_cast<int32_t>(ci), r0, c0, 0});
+        const int nI = P.c_nI[ci], nB = P.c_nB[ci];
+        if (nI > 0) {
+            P.cell_potrf.push_back(FrontDesc{P.c_foff[ci], P.c_ld[ci], nf, nI, static_cast<int32_t>(ci)});
+            const double a = nI, b = nB;
+            P.flops += a * a * a / 3.0 + a * a * b + a * b * b;
+        }
+    }
+
+    // ---- extend-add sources from the children (level >= 1) ----
+    const int W = 1 << d;
+    if (prev != nullptr) {
+        const int pc = 1 - cur;
+        const int pnc1 = prev->nc1;
+        P.src.assign(static_cast<size_t>(P.c_dofs.size()) * 2 * W, -1);
+        for (int64_t ci = 0; ci < ncells; ++ci) {
+            for (int p = P.c_dptr[ci]; p < P.c_dptr[ci + 1]; ++p) {
+                const int32_t i = P.c_dofs[p];
+                const int g2 = scr.dof_group[pc][i];
+                const int t2 = scr.dof_tpos[pc][i];
+                if (g2 < 0) throw std::logic_error("active unknown missing from the level below");
+                int q = 0;
+                for (int sl = 0; sl < prev->gslot_cnt[g2]; ++sl) {
+                    const int cc = prev->gslot_cell[static_cast<size_t>(g2) * kMaxSlots + sl];
+                    int64_t rr = cc, par = 0, mul = 1;
+                    for (int k = 0; k < d; ++k) {
+                        par += ((rr % pnc1) / 2) * mul;
+                        rr /= pnc1;
+                        mul *= nc1;
+                    }
+                    if (par != ci) continue;
+                    P.src[(static_cast<size_t>(p) * W + q) * 2 + 0] = cc;
+                    P.src[(static_cast<size_t>(p) * W + q) * 2 + 1] =
+                        prev->gslot_off[static_cast<size_t>(g2) * kMaxSlots + sl] + t2;
+                    ++q;
+                }
+                if (q == 0) throw std::logic_error("frontal unknown without a child source");
+            }
+        }
+    }
+
+    // ---- cell apply descriptors and the y scratch ----
+    int64_t yoff = 0, ws = 0;
+    std::vector<int64_t> cell_y(ncells, -1);
+    for (int64_t ci = 0; ci < ncells; ++ci) {
+        const int nI = P.c_nI[ci], nB = P.c_nB[ci];
+        if (nI == 0) continue;
+        ApplyDesc ad{};
+        ad.off = P.c_foff[ci];
+        ad.toff = -1;
+        ad.yoff = nB > 0 ? yoff : -1;
+        cell_y[ci] = yoff;
+        ad.wsoff = -1;
+        if (nI + nB > lds_apply_cap) {
+            ad.wsoff = ws;
+            ws += align_up(nI + nB, 32);
+        }
+        ad.ld = P.c_ld[ci];
+        ad.nI = nI;
+        ad.nB = nB;
+        ad.dofs = P.c_dptr[ci];
+        P.cell_apply.push_back(ad);
+        yoff += nB;
+    }
+    P.y_elems = std::max<int64_t>(yoff, 1);
+
+    if (root) {
+        P.ws_elems = ws;
+        return;
+    }
+
+    // ---- separator groups: block Jacobi and the up-sweep gather ----
+    int64_t loff = 0;
+    std::vector<int64_t> g_loff(ngroups, -1);
+    for (int g = 0; g < ngroups; ++g) {
+        if (P.gcls[g] == 0) continue;
+        const int n = P.gptr[g + 1] - P.gptr[g];
+        P.seps.push_back(g);
+        SepDesc sd{};
+        sd.n = n;
+        sd.nslot = P.gslot_cnt[g];
+        for (int sl = 0; sl < kMaxSlots; ++sl) {
+            sd.slot_cell[sl] = P.gslot_cell[static_cast<size_t>(g) * kMaxSlots + sl];
+            sd.slot_off[sl] = P.gslot_off[static_cast<size_t>(g) * kMaxSlots + sl];
+        }
+        sd.loff = loff;
+        g_loff[g] = loff;
+        sd.dofs = static_cast<int32_t>(P.sep_dofs.size());
+        P.sep_dofs.insert(P.sep_dofs.end(), P.gdofs.begin() + P.gptr[g], P.gdofs.begin() + P.gptr[g + 1]);
+        P.sep_desc.push_back(sd);
+        loff += align_up(static_cast<int64_t>(n) * n, 32);
+        P.max_sep_n = std::max(P.max_sep_n, n);
+        P.flops += static_cast<double>(n) * n * n / 3.0;
+
+        GatherDesc gd{};
+        gd.n = n;
+        gd.dofs = sd.dofs;
+        gd.nslot = 0;
+        for (int sl = 0; sl < sd.nslot; ++sl) {
+            const int cc = sd.slot_cell[sl];
+            if (cell_y[cc] < 0) continue;
+            gd.yoff[gd.nslot++] = cell_y[cc] + (sd.slot_off[sl] - P.c_nI[cc]);
+        }
+        P.gather.push_back(gd);
+
+        ApplyDesc ad{};
+        ad.off = sd.loff;
+        ad.toff = -1;
+        ad.yoff = -1;
+        ad.wsoff = -1;
+        if (n > lds_apply_cap) {
+            ad.wsoff = ws;
+            ws += align_up(n, 32);
+        }
+        ad.ld = n;
+        ad.nI = n;
+        ad.nB = 0;
+        ad.dofs = sd.dofs;
+        P.sep_apply.push_back(ad);
+    }
+    P.lg_elems = std::max<int64_t>(loff, 32);
+    for (int64_t ci = 0; ci < ncells; ++ci) {
+        CellScaleDesc cs{};
+        cs.off = P.c_foff[ci];
+        cs.ld = P.c_ld[ci];
+        cs.nI = P.c_nI[ci];
+        cs.nB = P.c_nB[ci];
+        cs.g_begin = static_cast<int32_t>(P.cell_groups.size());
+        for (int e = P.c_gptr[ci]; e < P.c_gptr[ci + 1]; ++e) {
+            const int g = P.c_g[e];
+            CellGroup cg{};
+            cg.off = P.c_goff[e];
+            cg.n = P.gptr[g + 1] - P.gptr[g];
+            cg.loff = g_loff[g];
+            cg.owner = (P.gslot_cell[static_cast<size_t>(g) * kMaxSlots] == ci) ? 1 : 0;
+            P.cell_groups.push_back(cg);
+            const double nb = cs.nB, ng = cg.n;
+            P.flops += 2.0 * nb * ng * ng;
+        }
+        cs.g_count = static_cast<int32_t>(P.cell_groups.size()) - cs.g_begin;
+        if (cs.nB > 0) P.cell_scale.push_back(cs);
+    }
+
+    // ---- skeletonized groups: rows of M = A[R_g, g] from the one or two cells ----
+    int64_t moff = 0, toff = 0, goff = 0;
+    int32_t poff = 0;
+    for (int g = 0; g < ngroups; ++g) {
+        if (P.gcls[g] != 1) continue;
+        const int n = P.gptr[g + 1] - P.gptr[g];
+        const int ns = P.gslot_cnt[g];
+        if (ns < 1 || ns > 2) throw std::logic_error("an edge/face must touch one or two cells");
+        SkelDesc sk{};
+        sk.n = n;
+        sk.nslot = ns;
+        sk.rows = static_cast<int32_t>(P.skel_rows.size() / 2);
+        for (int sl = 0; sl < 2; ++sl) {
+            sk.cell[sl] = sl < ns ? P.gslot_cell[static_cast<size_t>(g) * kMaxSlots + sl] : -1;
+            sk.off[sl] = sl < ns ? P.gslot_off[static_cast<size_t>(g) * kMaxSlots + sl] : -1;
+        }
+        const int32_t st = ++scr.stamp;
+        int r = 0;
+        {
+            const int c1 = sk.cell[0], o1 = sk.off[0];
+            for (int p = P.c_nI[c1]; p < P.c_nf[c1]; ++p) {
+                if (p >= o1 && p < o1 + n) continue;
+                const int32_t i = P.c_dofs[P.c_dptr[c1] + p];
+                scr.mark_stamp[i] = st;
+                scr.mark_row[i] = r++;
+                P.skel_rows.push_back(p);
+                P.skel_rows.push_back(-1);
+            }
+        }
+        if (ns == 2) {
+            const int c2 = sk.cell[1], o2 = sk.off[1];
+            for (int p = P.c_nI[c2]; p < P.c_nf[c2]; ++p) {
+                if (p >= o2 && p < o2 + n) continue;
+                const int32_t i = P.c_dofs[P.c_dptr[c2] + p];
+                if (scr.mark_stamp[i] == st) {
+                    P.skel_rows[(static_cast<size_t>(sk.rows) + scr.mark_row[i]) * 2 + 1] = p;
+                } else {
+                    P.skel_rows.push_back(-1);
+                    P.skel_rows.push_back(p);
+                    ++r;
+                }
+            }
+        }
+        sk.r = r;
+        sk.moff = moff;
+        moff += align_up(static_cast<int64_t>(std::max(r, 1)) * n, 32);
+        sk.toff = toff;
+        toff += align_up(static_cast<int64_t>(n) * n / 4 + 1, 32);
+        sk.goff = goff;
+        goff += align_up(static_cast<int64_t>(n) * n, 32);
+        sk.gid = static_cast<int32_t>(P.skels.size());
+        sk.poff = poff;
+        poff += n;
+        P.skels.push_back(g);
+        P.skel_desc.push_back(sk);
+        P.max_skel_n = std::max(P.max_skel_n, n);
+        const double rr = r, nn = n;
+        P.flops += 4.0 * rr * nn * nn;   // CPQR bound (k <= n), refined after the ID
+    }
+    P.skel_ntotal = poff;
+    P.m_elems = std::max<int64_t>(moff, 32);
+    P.t_elems = std::max<int64_t>(toff, 32);
+    P.g_elems = std::max<int64_t>(goff, 32);
+    P.ws_elems = ws;
+}
+
+void finish_level(const LevelPlan& P, const int32_t* k, const int32_t* perm, int lds_apply_cap,
+                  std::vector<ApplyDesc>& skel_apply, std::vector<int32_t>& skel_dofs,
+                  int64_t& ws_elems, const std::vector<int32_t>& active,
+                  std::vector<int32_t>& next_active, PlanScratch& scr, double& flops) {
+    skel_apply.clear();
+    skel_dofs.clear();
+    const int32_t st = ++scr.stamp;
+    // interiors are eliminated
+    for (int g = 0; g + 1 < static_cast<int>(P.gptr.size()); ++g)
+        if (P.gcls[g] == 0)
+            for (int t = P.gptr[g]; t < P.gptr[g + 1]; ++t) scr.mark_stamp[P.gdofs[t]] = st;
+    for (size_t e = 0; e < P.skel_desc.size(); ++e) {
+        const SkelDesc& sk = P.skel_desc[e];
+        const int g = P.skels[e];
+        const int n = sk.n;
+        const int kk = k[sk.gid];
+        const int32_t* pv = perm + sk.poff;
+        const int32_t* gd = P.gdofs.data() + P.gptr[g];
+        for (int q = kk; q < n; ++q) scr.mark_stamp[gd[pv[q]]] = st;   // redundant unknowns
+        const double nr = n - kk, kd = kk;
+        flops += nr * nr * nr / 3.0 + nr * nr * kd + nr * kd * kd + nr * kd * kd;
+        if (kk == n) continue;
+        ApplyDesc ad{};
+        ad.off = sk.goff;
+        ad.toff = (kk > 0) ? sk.toff : -1;
+        ad.yoff = -1;
+        ad.wsoff = -1;
+        if (n > lds_apply_cap) {
+            ad.wsoff = ws_elems;
+            ws_elems += align_up(n, 32);
+        }
+        ad.ld = n;
+        ad.nI = n - kk;
+        ad.nB = kk;
+        ad.dofs = static_cast<int32_t>(skel_dofs.size());
+        for (int q = kk; q < n; ++q) skel_dofs.push_back(gd[pv[q]]);
+        for (int q = 0; q < kk; ++q) skel_dofs.push_back(gd[pv[q]]);
+        skel_apply.push_back(ad);
+    }
+    next_active.clear();
+    next_active.reserve(active.size());
+    for (int32_t i : active)
+        if (scr.mark_stamp[i] != st) next_active.push_back(i);
+    scr.cur = 1 - scr.cur;
+}
+
+}  // namespace rhif
+
+namespace rhif {
+
+namespace {
+[[noreturn]] void bad(const char* what, int64_t a, int64_t b) {
+    throw std::logic_error(std::string("plan check failed: ") + what + " (" + std::to_string(a) + " vs " +
+                           std::to_string(b) + ")");
+}
+inline void need(bool ok, const char* what, int64_t a = 0, int64_t b = 0) {
+    if (!ok) bad(what, a, b);
+}
+}  // namespace
+
+void validate_level(const LevelPlan& P, const LevelPlan* prev, int d) {
+    const int64_t ncd = static_cast<int64_t>(P.c_dofs.size());
+    for (int c = 0; c < P.ncells; ++c) {
+        const CellRef& r = P.cell_ref[c];
+        need(r.nf == P.c_nI[c] + P.c_nB[c], "cell nf");
+        need(r.ld >= r.nf && r.ld >= 1, "cell ld", r.ld, r.nf);
+        need(r.off >= 0 && r.off + static_cast<int64_t>(r.ld) * r.nf <= P.front_elems, "frontal bounds",
+             r.off + static_cast<int64_t>(r.ld) * r.nf, P.front_elems);
+        need(r.dptr >= 0 && r.dptr + r.nf <= ncd, "cell dofs bounds", r.dptr + r.nf, ncd);
+    }
+    for (const Tile& t : P.tiles) {
+        need(t.cell >= 0 && t.cell < P.ncells, "tile cell", t.cell, P.ncells);
+        need(t.r0 >= 0 && t.r0 < P.cell_ref[t.cell].nf && t.c0 >= 0 && t.c0 < P.cell_ref[t.cell].nf, "tile origin");
+    }
+    for (const FrontDesc& f : P.cell_potrf) {
+        need(f.id >= 0 && f.id < P.ncells, "potrf id");
+        const CellRef& r = P.cell_ref[f.id];
+        need(f.off == r.off && f.ld == r.ld && f.n == r.nf && f.p >= 1 && f.p <= f.n, "potrf desc");
+    }
+    const int W = 1 << d;
+    if (prev != nullptr) {
+        need(static_cast<int64_t>(P.src.size()) == ncd * 2 * W, "src size", P.src.size(), ncd * 2 * W);
+        for (int64_t e = 0; e < ncd * W; ++e) {
+            const int c = P.src[2 * e], pos = P.src[2 * e + 1];
+            if (c < 0) continue;
+            need(c < prev->ncells, "src child", c, prev->ncells);
+            need(pos >= prev->c_nI[c] && pos < prev->c_nf[c], "src child position", pos, prev->c_nf[c]);
+        }
+    }
+    for (const SepDesc& s : P.sep_desc) {
+        need(s.nslot >= 1 && s.nslot <= kMaxSlots, "sep slots", s.nslot, kMaxSlots);
+        need(s.n >= 1 && s.loff >= 0 && s.loff + static_cast<int64_t>(s.n) * s.n <= P.lg_elems, "sep L bounds");
+        need(s.dofs >= 0 && s.dofs + s.n <= static_cast<int64_t>(P.sep_dofs.size()), "sep dofs");
+        for (int q = 0; q < s.nslot; ++q) {
+            const int c = s.slot_cell[q];
+            need(c >= 0 && c < P.ncells, "sep slot cell", c, P.ncells);
+            need(s.slot_off[q] >= P.c_nI[c] && s.slot_off[q] + s.n <= P.c_nf[c], "sep slot offset");
+        }
+    }
+    for (const CellScaleDesc& cs : P.cell_scale) {
+        need(cs.g_begin >= 0 && cs.g_begin + cs.g_count <= static_cast<int64_t>(P.cell_groups.size()), "scale groups");
+        int64_t tot = 0;
+        for (int e = cs.g_begin; e < cs.g_begin + cs.g_count; ++e) {
+            const CellGroup& g = P.cell_groups[e];
+            need(g.off >= cs.nI && g.off + g.n <= cs.nI + cs.nB, "scale group offset");
+            need(g.loff >= 0 && g.loff + static_cast<int64_t>(g.n) * g.n <= P.lg_elems, "scale group L");
+            tot += g.n;
+        }
+        need(tot == cs.nB, "scale groups cover the boundary", tot, cs.nB);
+    }
+    for (const SkelDesc& k : P.skel_desc) {
+        need(k.nslot >= 1 && k.nslot <= 2, "skel slots");
+        need(k.rows >= 0 && 2 * (static_cast<int64_t>(k.rows) + k.r) <= static_cast<int64_t>(P.skel_rows.size()),
+             "skel rows");
+        for (int q = 0; q < k.nslot; ++q) {
+            const int c = k.cell[q];
+            need(c >= 0 && c < P.ncells, "skel cell");
+            need(k.off[q] >= P.c_nI[c] && k.off[q] + k.n <= P.c_nf[c], "skel group offset");
+        }
+        for (int i = 0; i < k.r; ++i) {
+            const int p1 = P.skel_rows[2 * (static_cast<int64_t>(k.rows) + i)];
+            const int p2 = P.skel_rows[2 * (static_cast<int64_t>(k.rows) + i) + 1];
+            need(p1 >= 0 || p2 >= 0, "skel row without source");
+            if (p1 >= 0) need(p1 < P.c_nf[k.cell[0]], "skel row pos1");
+            if (p2 >= 0) need(k.nslot == 2 && p2 < P.c_nf[k.cell[1]], "skel row pos2");
+        }
+        need(k.moff >= 0 && k.moff + static_cast<int64_t>(std::max(k.r, 1)) * k.n <= P.m_elems, "skel M bounds");
+        need(k.toff >= 0 && k.toff + static_cast<int64_t>(k.n) * k.n / 4 + 1 <= P.t_elems, "skel T bounds");
+        need(k.goff >= 0 && k.goff + static_cast<int64_t>(k.n) * k.n <= P.g_elems, "skel G bounds");
+        need(k.poff >= 0 && k.poff + k.n <= P.skel_ntotal, "skel perm bounds");
+        need(k.gid >= 0 && k.gid < static_cast<int>(P.skel_desc.size()), "skel gid");
+    }
+    int64_t ysum = 0;
+    for (const ApplyDesc& a : P.cell_apply) {
+        need(a.nI >= 1 && a.dofs >= 0 && a.dofs + a.nI + a.nB <= ncd, "cell apply dofs");
+        need(a.off >= 0 && a.off + static_cast<int64_t>(a.ld) * (a.nI + a.nB) <= P.front_elems, "cell apply bounds");
+        need(a.ld >= a.nI + a.nB, "cell apply ld");
+        if (a.yoff >= 0) need(a.yoff + a.nB <= P.y_elems, "cell apply y bounds");
+        if (a.wsoff >= 0) need(a.wsoff + a.nI + a.nB <= P.ws_elems, "cell apply ws bounds");
+        ysum += a.nB;
+    }
+    need(ysum <= P.y_elems, "y scratch", ysum, P.y_elems);
+    for (const GatherDesc& g : P.gather) {
+        need(g.dofs >= 0 && g.dofs + g.n <= static_cast<int64_t>(P.sep_dofs.size()), "gather dofs");
+        for (int q = 0; q < g.nslot; ++q) need(g.yoff[q] >= 0 && g.yoff[q] + g.n <= P.y_elems, "gather y bounds");
+    }
+    for (const ApplyDesc& a : P.sep_apply) {
+        need(a.nB == 0 && a.nI >= 1 && a.ld == a.nI, "sep apply shape");
+        need(a.off >= 0 && a.off + static_cast<int64_t>(a.nI) * a.nI <= P.lg_elems, "sep apply bounds");
+        need(a.dofs >= 0 && a.dofs + a.nI <= static_cast<int64_t>(P.sep_dofs.size()), "sep apply dofs");
+        if (a.wsoff >= 0) need(a.wsoff + a.nI <= P.ws_elems, "sep apply ws bounds");
+    }
+}
+
+void validate_skel_apply(const LevelPlan& P, const std::vector<ApplyDesc>& ad, const std::vector<int32_t>& dofs,
+                         int64_t N) {
+    for (const ApplyDesc& a : ad) {
+        need(a.nI >= 1 && a.nB >= 0 && a.ld == a.nI + a.nB, "skel apply shape");
+        need(a.off >= 0 && a.off + static_cast<int64_t>(a.ld) * a.ld <= P.g_elems, "skel apply bounds");
+        if (a.toff >= 0) need(a.toff + static_cast<int64_t>(a.nB) * a.nI <= P.t_elems, "skel apply T bounds");
+        need(a.dofs >= 0 && a.dofs + a.nI + a.nB <= static_cast<int64_t>(dofs.size()), "skel apply dofs");
+    }
+    for (int32_t i : dofs) need(i >= 0 && i < N, "skel dof range", i, N);
+}
+
+}  // namespace rhif

@@ -1,0 +1,114 @@
+// Host planner: the integer bookkeeping of one level of the factorization.
+//
+// Level l works at cell width w = 2^l m. An active unknown x is classified by
+// key_k = 2 (x_k / w) + (x_k mod w != 0): odd components are the open slab of a cell,
+// even ones the separator plane x_k = (key_k / 2) w. Unknowns with equal keys form one
+// group; the number of even components is its class (0 cell interior, 1 edge in 2D or
+// face in 3D, 2 corner in 2D or edge in 3D, 3 corner in 3D) -- the grouping of Sec. 3.1
+// and 3.2 of the paper, extended to any side n by letting the last cell of an axis be
+// ragged and the plane x_k = n be a separator with a cell on one side only.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "devstructs.hpp"
+
+namespace rhif {
+
+struct GridInfo {
+    int d = 0;
+    int s = 0;          // interior points per axis
+    int64_t N = 0;
+};
+
+struct LevelPlan {
+    int level = 0;
+    int w = 0;
+    int nc1 = 0;        // cells per axis
+    bool root = false;  // the last level: one cell, everything interior
+
+    // groups (ascending key), their unknowns ascending
+    std::vector<int32_t> gptr;      // ngroups + 1
+    std::vector<int32_t> gdofs;
+    std::vector<int8_t> gcls;
+    std::vector<int32_t> gslot_cnt; // per group, cells containing it
+    std::vector<int32_t> gslot_cell;  // ngroups * kMaxSlots
+    std::vector<int32_t> gslot_off;
+
+    // cells (every geometric cell of the level)
+    int ncells = 0;
+    std::vector<int32_t> c_nI, c_nB, c_nf, c_ld, c_dptr;
+    std::vector<int64_t> c_foff;
+    int64_t front_elems = 0;
+    std::vector<int32_t> c_dofs;    // frontal unknowns of every cell
+    std::vector<int32_t> c_gptr;    // boundary groups of every cell
+    std::vector<int32_t> c_g;
+    std::vector<int32_t> c_goff;
+
+    // separator groups (class >= 1) and the skeletonized ones (class 1)
+    std::vector<int32_t> seps;
+    std::vector<int32_t> skels;
+
+    // device-ready tables
+    std::vector<FrontDesc> cell_potrf;     // cells with interior unknowns
+    std::vector<CellRef> cell_ref;         // every cell
+    std::vector<Tile> tiles;               // assembly tiles
+    std::vector<int32_t> src;              // extend-add sources: per frontal position
+                                           // (2^d pairs of child cell, child position)
+    std::vector<SepDesc> sep_desc;
+    std::vector<CellGroup> cell_groups;
+    std::vector<CellScaleDesc> cell_scale;
+    std::vector<SkelDesc> skel_desc;
+    std::vector<int32_t> skel_rows;        // (pos1, pos2) pairs
+    std::vector<ApplyDesc> cell_apply;
+    std::vector<ApplyDesc> sep_apply;
+    std::vector<GatherDesc> gather;
+    std::vector<int32_t> sep_dofs;         // unknowns of every separator group
+    int64_t lg_elems = 0, m_elems = 0, t_elems = 0, g_elems = 0, y_elems = 0;
+    int64_t ws_elems = 0;                  // global workspace for oversized applies
+    int32_t skel_ntotal = 0;               // sum of skeletonized group sizes
+    int32_t max_nf = 0, max_sep_n = 0, max_skel_n = 0;
+    double flops = 0.0;                    // algorithmic flops (cells + groups + skeletons)
+};
+
+// Reusable per-factorization scratch sized by N.
+struct PlanScratch {
+    std::vector<int32_t> count;            // key buckets
+    std::vector<int32_t> key2g;
+    std::vector<int32_t> dof_group[2], dof_tpos[2];
+    std::vector<int32_t> mark_stamp, mark_row;
+    int32_t stamp = 0;
+    int cur = 0;
+    void init(int64_t N);
+};
+
+// Number of skeletonization levels L: all l >= 0 with 2^l m <= s.
+int num_levels(int s, int leaf);
+
+// Build the plan of `level` from its sorted active unknowns. `prev` is the plan of the
+// level below (nullptr at level 0) and is used for the extend-add source tables.
+// lds_apply_cap: largest nI + nB staged in LDS by the apply kernels.
+void build_level(const GridInfo& g, int level, int leaf, bool root,
+                 const std::vector<int32_t>& active, const LevelPlan* prev,
+                 PlanScratch& scr, int lds_apply_cap, LevelPlan& out);
+
+// Check that every offset and size in the device tables of a level stays inside the
+// buffers the driver allocates for them (throws std::logic_error otherwise), so that a
+// planning mistake becomes an error return instead of an out-of-bounds access on the GPU.
+// prev: the plan of the level below (its frontals are read by the extend-add).
+void validate_level(const LevelPlan& lp, const LevelPlan* prev, int d);
+
+// Same for the skeleton apply tables built by finish_level.
+void validate_skel_apply(const LevelPlan& lp, const std::vector<ApplyDesc>& ad,
+                         const std::vector<int32_t>& dofs, int64_t N);
+
+// After the IDs of a level: given ranks k and pivot orders (positions into each group's
+// ascending unknowns), build the apply descriptors of the skeleton blocks and the active
+// unknowns of the next level.
+void finish_level(const LevelPlan& lp, const int32_t* k, const int32_t* perm,
+                  int lds_apply_cap, std::vector<ApplyDesc>& skel_apply,
+                  std::vector<int32_t>& skel_dofs, int64_t& ws_elems,
+                  const std::vector<int32_t>& active, std::vector<int32_t>& next_active,
+                  PlanScratch& scr, double& flops);
+
+}  // namespace rhif

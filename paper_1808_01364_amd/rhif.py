@@ -1,0 +1,314 @@
+"""Python binding of librhif.so (the C ABI in include/rhif.h).
+
+Argument marshalling only: torch tensors supply device memory and the current HIP
+stream; every step of the factorization, the apply and the solve runs in the library's
+HIP kernels. There is no fallback: without the built library, or without a GPU, the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librhif.so")
+
+RHIF_OK, RHIF_EINVAL, RHIF_ENOTSPD, RHIF_ENOMEM, RHIF_EDEVICE, RHIF_ENOCONV = range(6)
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOTSPD", 3: "ENOMEM", 4: "EDEVICE", 5: "ENOCONV"}
+MAX_LEVELS = 32
+FLAG_PHASE_TIMES = 1
+
+# every function declared in include/rhif.h
+EXPORTED = ["rhif_fd_nnz", "rhif_assemble_fd", "rhif_factor", "rhif_apply", "rhif_pcg_solve",
+            "rhif_matvec", "rhif_stats", "rhif_skeletons", "rhif_destroy", "rhif_last_error",
+            "rhif_version"]
+
+
+class RhifError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class NotSPD(RhifError):
+    pass
+
+
+class NoConvergence(RhifError):
+    def __init__(self, status, msg, iters, relres):
+        super().__init__(status, msg)
+        self.iters, self.relres = iters, relres
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("leaf", ctypes.c_int32), ("eps", ctypes.c_double), ("precond", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("root_size", ctypes.c_int32),
+                ("factor_bytes", ctypes.c_int64),
+                ("n_active", ctypes.c_int64 * (MAX_LEVELS + 1)),
+                ("n_cells", ctypes.c_int32 * (MAX_LEVELS + 1)),
+                ("max_front", ctypes.c_int32 * (MAX_LEVELS + 1)),
+                ("n_groups", ctypes.c_int32 * MAX_LEVELS),
+                ("n_skel", ctypes.c_int32 * MAX_LEVELS),
+                ("sum_skel_n", ctypes.c_int64 * MAX_LEVELS),
+                ("sum_rank", ctypes.c_int64 * MAX_LEVELS),
+                ("max_rank", ctypes.c_int32 * MAX_LEVELS),
+                ("flops", ctypes.c_double * (MAX_LEVELS + 1)),
+                ("t_total_ms", ctypes.c_double),
+                ("t_phase_ms", ctypes.c_double * 8)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load librhif.so; raises if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1808_01364_amd.build`")
+    lib = ctypes.CDLL(path)
+    c_i32p = ctypes.POINTER(ctypes.c_int32)
+    vp = ctypes.c_void_p
+    lib.rhif_fd_nnz.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_int64)]
+    lib.rhif_assemble_fd.argtypes = [ctypes.POINTER(Grid), vp, vp, vp, vp, vp, vp]
+    lib.rhif_factor.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), vp, vp, vp, vp, ctypes.POINTER(vp)]
+    lib.rhif_apply.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
+    lib.rhif_pcg_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int32, c_i32p,
+                                   ctypes.POINTER(ctypes.c_double), vp]
+    lib.rhif_matvec.argtypes = [vp, vp, vp, vp]
+    lib.rhif_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.rhif_skeletons.argtypes = [vp, ctypes.c_int32, c_i32p, ctypes.POINTER(ctypes.c_int64), c_i32p, c_i32p,
+                                   c_i32p, c_i32p]
+    lib.rhif_destroy.argtypes = [vp]
+    lib.rhif_destroy.restype = None
+    lib.rhif_last_error.restype = ctypes.c_char_p
+    lib.rhif_version.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("rhif_destroy", "rhif_last_error", "rhif_version"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != RHIF_OK:
+        msg = load_library().rhif_last_error().decode()
+        if st == RHIF_ENOTSPD:
+            raise NotSPD(st, msg)
+        raise RhifError(st, msg)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("librhif needs a GPU; torch.cuda is not available")
+    return torch
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr()) if t is not None else 0
+
+
+def make_grid(dim: int, n: int) -> Grid:
+    g = Grid()
+    g.dim = dim
+    g.n[0] = n
+    g.n[1] = n
+    g.n[2] = n if dim == 3 else 0
+    return g
+
+
+def fd_nnz(dim: int, n: int) -> int:
+    out = ctypes.c_int64()
+    _check(load_library().rhif_fd_nnz(ctypes.byref(make_grid(dim, n)), ctypes.byref(out)))
+    return out.value
+
+
+def assemble_fd(dim: int, n: int, a_cells, b=None, stream=None):
+    """CSR (row_ptr, col, val) of the FD matrix, as device tensors (int32, int32, float64).
+    a_cells: (n+1)^dim cell coefficients on the device, c_1 fastest; b: N values or None."""
+    torch = _torch()
+    dev = a_cells.device
+    N = n ** dim
+    nnz = fd_nnz(dim, n)
+    a_cells = a_cells.contiguous().to(torch.float64)
+    if b is not None:
+        b = b.contiguous().to(torch.float64)
+    rp = torch.empty(N + 1, dtype=torch.int32, device=dev)
+    col = torch.empty(nnz, dtype=torch.int32, device=dev)
+    val = torch.empty(nnz, dtype=torch.float64, device=dev)
+    _check(load_library().rhif_assemble_fd(ctypes.byref(make_grid(dim, n)), _ptr(a_cells), _ptr(b),
+                                           _ptr(rp), _ptr(col), _ptr(val), _stream(stream)))
+    return rp, col, val
+
+
+@dataclass
+class Skeletons:
+    first_dof: List[int]
+    size: List[int]
+    rank: List[int]
+    perm: List[List[int]]
+
+
+class Factor:
+    """An RHIF factorization held by the library (rhif_factor / rhif_destroy)."""
+
+    def __init__(self, dim: int, n: int, csr, leaf: int, eps: float, precond: int = 1,
+                 precision: int = 0, flags: int = 0, stream=None):
+        self._lib = load_library()
+        self.dim, self.n, self.N = dim, n, n ** dim
+        o = Opts()
+        o.leaf, o.eps, o.precond, o.precision, o.flags = leaf, eps, precond, precision, flags
+        rp, col, val = csr
+        h = ctypes.c_void_p()
+        _check(self._lib.rhif_factor(ctypes.byref(make_grid(dim, n)), ctypes.byref(o), _ptr(rp), _ptr(col),
+                                     _ptr(val), _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise RuntimeError("factor has been destroyed")
+        return self._h
+
+    def apply(self, r, out=None, stream=None):
+        """z = F^-1 r for r of shape (N,) or (nrhs, N) (rows are right-hand sides)."""
+        torch = _torch()
+        r = r.contiguous()
+        z = out if out is not None else torch.empty_like(r)
+        nrhs = 1 if r.dim() == 1 else r.shape[0]
+        _check(self._lib.rhif_apply(self.handle, _ptr(r), _ptr(z), nrhs, _stream(stream)))
+        return z
+
+    def matvec(self, x, out=None, stream=None):
+        torch = _torch()
+        y = out if out is not None else torch.empty_like(x)
+        _check(self._lib.rhif_matvec(self.handle, _ptr(x.contiguous()), _ptr(y), _stream(stream)))
+        return y
+
+    def pcg(self, f, rtol: float = 1e-12, maxit: int = 500, out=None, stream=None,
+            raise_on_noconv: bool = True) -> Tuple[object, int, float]:
+        torch = _torch()
+        f = f.contiguous()
+        u = out if out is not None else torch.empty_like(f)
+        it = ctypes.c_int32()
+        rel = ctypes.c_double()
+        st = self._lib.rhif_pcg_solve(self.handle, _ptr(f), _ptr(u), rtol, maxit, ctypes.byref(it),
+                                      ctypes.byref(rel), _stream(stream))
+        if st == RHIF_ENOCONV:
+            if raise_on_noconv:
+                raise NoConvergence(st, self._lib.rhif_last_error().decode(), it.value, rel.value)
+        else:
+            _check(st)
+        return u, it.value, rel.value
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(self._lib.rhif_stats(self.handle, ctypes.byref(s)))
+        L = s.levels
+        return dict(levels=L, root_size=s.root_size, factor_bytes=s.factor_bytes,
+                    n_active=list(s.n_active[: L + 1]), n_cells=list(s.n_cells[: L + 1]),
+                    max_front=list(s.max_front[: L + 1]), n_groups=list(s.n_groups[:L]),
+                    n_skel=list(s.n_skel[:L]), sum_skel_n=list(s.sum_skel_n[:L]),
+                    sum_rank=list(s.sum_rank[:L]), max_rank=list(s.max_rank[:L]),
+                    flops=list(s.flops[: L + 1]), t_total_ms=s.t_total_ms,
+                    t_phase_ms=list(s.t_phase_ms))
+
+    def skeletons(self, level: int) -> Skeletons:
+        ng = ctypes.c_int32()
+        tot = ctypes.c_int64()
+        _check(self._lib.rhif_skeletons(self.handle, level, ctypes.byref(ng), ctypes.byref(tot),
+                                        None, None, None, None))
+        n = ng.value
+        A = ctypes.c_int32 * max(n, 1)
+        fd, sz, rk = A(), A(), A()
+        pm = (ctypes.c_int32 * max(tot.value, 1))()
+        _check(self._lib.rhif_skeletons(self.handle, level, ctypes.byref(ng), ctypes.byref(tot), fd, sz, rk, pm))
+        perms, off = [], 0
+        for e in range(n):
+            perms.append(list(pm[off: off + sz[e]]))
+            off += sz[e]
+        return Skeletons(list(fd[:n]), list(sz[:n]), list(rk[:n]), perms)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.rhif_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def version() -> str:
+    return load_library().rhif_version().decode()
+
+
+# ---------------------------------------------------------------- host-only planner check
+
+_ID_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32))
+_CELL_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                            ctypes.c_int32, ctypes.POINTER(ctypes.c_int32))
+
+
+def plan_dry_run(dim: int, n: int, leaf: int, choose, on_cell=None) -> int:
+    """Run the library's level planner on the host (no GPU) with ID choices from
+    ``choose(level, first_dof, size) -> (k, perm)``; ``on_cell(level, cell, interior,
+    boundary)`` sees every cell with interior unknowns. Returns |S_L|."""
+    lib = load_library()
+    lib.rhif_plan_dry_run.argtypes = [ctypes.POINTER(Grid), ctypes.c_int32, _ID_FN, ctypes.c_void_p, _CELL_FN,
+                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
+    lib.rhif_plan_dry_run.restype = ctypes.c_int
+    lib.rhif_plan_last_error.restype = ctypes.c_char_p
+    errors = []
+
+    def _id(ctx, level, first, size, kp, pp):
+        try:
+            k, perm = choose(level, first, size)
+            kp[0] = int(k)
+            for q in range(size):
+                pp[q] = int(perm[q])
+            return 0
+        except Exception as e:  # reported after the run
+            errors.append(e)
+            return 1
+
+    def _cell(ctx, level, cell, nI, nB, dofs):
+        if on_cell is not None:
+            arr = [dofs[q] for q in range(nI + nB)]
+            on_cell(level, cell, arr[:nI], arr[nI:])
+
+    idf, cellf = _ID_FN(_id), _CELL_FN(_cell)
+    root = ctypes.c_int64()
+    st = lib.rhif_plan_dry_run(ctypes.byref(make_grid(dim, n)), leaf, idf, None, cellf, None, ctypes.byref(root))
+    if errors:
+        raise errors[0]
+    if st != RHIF_OK:
+        raise RhifError(st, lib.rhif_plan_last_error().decode())
+    return root.value

@@ -1,0 +1,114 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on the same seeded
+inputs. Where the interpolative decompositions could legitimately choose differently
+(pivot ties), the oracle replays the GPU's choices and the choices are checked apart."""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.gpu_common import (compare_choices, gpu_choices, gpu_csr, gpu_factor, problem, rel,
+                              to_dev, torch_cuda)
+
+pytestmark = pytest.mark.gpu
+
+U = np.finfo(np.float64).eps
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("d,s", [(2, 13), (3, 6), (2, 64)])
+def test_assembly_bitwise(d, s):
+    """The device assembly reproduces the oracle's CSR exactly (same operation order)."""
+    P, A = problem("two_valued", d, s, 4, 1e-3, seed=3, lo=1e-2, hi=1e2, b_const=0.25 if d == 3 else 0.0)
+    rp, col, val = gpu_csr(P)
+    assert np.array_equal(_host(rp), A.indptr)
+    assert np.array_equal(_host(col), A.indices)
+    assert np.array_equal(_host(val), A.data)
+
+
+@pytest.mark.parametrize("d,s,leaf,precond", [(2, 16, 4, 1), (2, 20, 8, 1), (2, 13, 4, 0), (3, 7, 2, 1),
+                                              (3, 10, 4, 1), (2, 5, 8, 1)])
+def test_eps0_apply_is_dense_solve(d, s, leaf, precond):
+    """eps = 0: F^-1 on the GPU is the exact inverse (nested dissection), so it matches a
+    dense Cholesky solve; PCG stops after one product."""
+    P, A = problem("two_valued", d, s, leaf, 0.0, precond=precond, lo=0.5, hi=2.0)
+    F = gpu_factor(P)
+    f = to_dev(P.f)
+    z = _host(F.apply(f))
+    u = O.dense_solve(A, P.f)
+    assert rel(z, u) < 1e-12
+    uu, it, rr = F.pcg(f, 1e-12, 5)
+    assert it == 1 and rr <= 1e-12
+    F.close()
+
+
+def _parity(P, A, n_rhs=3, apply_tol=1e-11, sol_tol=1e-10, replay_ok=0.02):
+    F = gpu_factor(P)
+    st = F.stats()
+    ch = gpu_choices(F, st["levels"])
+    orc = O.factor(A, P.d, P.s, P.leaf, P.eps, P.precond)
+    total, dr, ds = compare_choices(ch, orc)
+    assert (dr + ds) <= replay_ok * max(total, 1), (total, dr, ds)
+    # replay the GPU's discrete choices in the oracle
+    rep = O.factor(A, P.d, P.s, P.leaf, P.eps, P.precond, replay=ch)
+    assert rep.root_size == st["root_size"]
+    rng = np.random.default_rng(11)
+    worst = 0.0
+    for _ in range(n_rhs):
+        r = rng.standard_normal(P.N)
+        zg = _host(F.apply(to_dev(r)))
+        zo = O.apply_inverse(rep, r)
+        worst = max(worst, rel(zg, zo))
+    assert worst < apply_tol, worst
+    # PCG: same iteration count as the replayed oracle, solutions agree
+    f = to_dev(P.f)
+    ug, itg, rrg = F.pcg(f, 1e-12, 300)
+    res = O.pcg(A, P.f, lambda v: O.apply_inverse(rep, v), 1e-12, 300)
+    assert res.converged and rrg <= 1e-12
+    assert itg == res.iters, (itg, res.iters)
+    assert rel(_host(ug), res.u) < sol_tol
+    F.close()
+    return dict(total=total, diff_rank=dr, diff_set=ds, apply_err=worst, iters=itg)
+
+
+def test_cfg1_parity():
+    """2D 64^2, iid two-valued 1e-2/1e2, leaf 8, eps 1e-3 (the small configuration)."""
+    from workloads import CONFIGS
+    P = CONFIGS["cfg1"]()
+    A = O.assemble_fd(P.d, P.s, P.a_cells, P.b)
+    out = _parity(P, A)
+    print("cfg1", out)
+
+
+@pytest.mark.parametrize("d,s,leaf,eps,kind,precond", [
+    (2, 31, 4, 1e-6, "lognormal", 1), (2, 40, 8, 1e-3, "two_valued", 0), (2, 13, 4, 1e-2, "two_valued", 1),
+    (3, 9, 2, 1e-3, "two_valued", 1), (3, 12, 4, 1e-3, "two_valued", 1)])
+def test_small_parity(d, s, leaf, eps, kind, precond):
+    P, A = problem(kind, d, s, leaf, eps, seed=2, precond=precond, sigma=2.0, lo=1e-2, hi=1e2)
+    out = _parity(P, A)
+    print((d, s, leaf, eps, kind, precond), out)
+
+
+def test_not_spd_is_reported():
+    """A strongly negative reaction term: the device Cholesky of the first cells fails and
+    the library reports loss of positive definiteness at level 0, step E."""
+    from paper_1808_01364_amd import rhif
+    P, A = problem("constant", 2, 16, 4, 1e-3)
+    P.b = np.full(P.N, -1e6)
+    with pytest.raises(rhif.NotSPD) as ei:
+        gpu_factor(P)
+    assert "level 0" in str(ei.value) and "E" in str(ei.value)
+
+
+def test_repeatable_bitwise():
+    """No floating-point atomics: two factorizations and applies give identical bits."""
+    P, A = problem("two_valued", 2, 48, 8, 1e-3, seed=5)
+    csr = gpu_csr(P)
+    r = to_dev(np.random.default_rng(1).standard_normal(P.N))
+    F1 = gpu_factor(P, csr)
+    F2 = gpu_factor(P, csr)
+    z1, z2 = _host(F1.apply(r)), _host(F2.apply(r))
+    assert np.array_equal(z1, z2)
+    F1.close()
+    F2.close()
