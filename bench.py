@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Benchmark: factor + PCG solve throughput of the RHIF library on one MI355X.
+
+One step = rhif_factor of the assembled matrix (planning, every level's elimination,
+block-Jacobi preconditioning, skeletonization, root) followed by rhif_pcg_solve to a
+relative residual of 1e-12 with F^-1 as the preconditioner. The matrix and right-hand side
+are resident in HBM before the timed region. Workload: 2D 5-point FD on a 512 x 512 grid,
+a = exp(3 g) with g a standardized Gaussian random field (correlation length 8 cells,
+seed 1), b = 0, f ~ N(0,1), leaf 16, eps 1e-6, FP64.
+
+Prints one JSON line (see the fields below). --gpus N > 1 is refused: the library runs on
+one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--eps", type=float, default=1e-6)
+    ap.add_argument("--side", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-side", type=int, default=256,
+                    help="side of the window of the same field timed with the CPU oracle")
+    return ap.parse_args()
+
+
+def make_workload(side: int, eps: float):
+    from workloads import make_problem
+    return make_problem("lognormal", 2, side, seed=1, leaf=16, eps=eps, sigma=3.0, corr_len=8.0,
+                        name=f"2d-{side}-lognormal-s3-eps{eps:g}")
+
+
+def cpu_baseline(P, sample_side: int):
+    """The oracle (plain FP64 NumPy/SciPy) on a window of the same coefficient field: the
+    (sample_side+1)^2 cells in the corner of the field, the matching slice of f."""
+    import numpy as np
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    s = sample_side
+    a = np.ascontiguousarray(P.a_cells[: s + 1, : s + 1])
+    f = np.ascontiguousarray(P.f.reshape(P.s, P.s)[:s, :s]).ravel()
+    A = O.assemble_fd(2, s, a, None)
+    t0 = time.perf_counter()
+    F = O.factor(A, 2, s, P.leaf, P.eps, 1)
+    t1 = time.perf_counter()
+    res = O.pcg(A, f, lambda v: O.apply_inverse(F, v), 1e-12, 500)
+    t2 = time.perf_counter()
+    return {"value": s * s / (t2 - t0), "unit": "DOFs/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle factor+PCG on the {s}x{s} corner window of the same field "
+                      f"(N={s*s}, leaf {P.leaf}, eps {P.eps:g}); t_factor {t1-t0:.2f} s, "
+                      f"t_pcg {t2-t1:.2f} s, {res.iters} iterations, host threads {threads} "
+                      f"of {os.cpu_count()} cores"}
+
+
+def main():
+    args = _args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: the RHIF library runs one problem on one GPU; multi-GPU runs are not "
+              "part of this build (how the path would shard is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1808_01364_amd import rhif
+
+    torch.cuda.set_device(0)
+    P = make_workload(args.side, args.eps)
+    dev = "cuda:0"
+    a = torch.tensor(P.a_cells.ravel(), dtype=torch.float64, device=dev)
+    csr = rhif.assemble_fd(2, P.s, a, None)
+    f = torch.tensor(P.f, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    def step(flags):
+        F = rhif.Factor(2, P.s, csr, P.leaf, P.eps, 1, flags=flags)
+        u, it, rr = F.pcg(f, 1e-12, 500)
+        return F, u, it, rr
+
+    # warm-up steps time every kernel class with HIP events to find the dominant kernel
+    per_class = {}
+    for _ in range(max(args.warmup, 1)):
+        F, u, it, rr = step(rhif.FLAG_KERNEL_TIMES)
+        for name, kv in F.stats()["kernels"].items():
+            per_class[name] = per_class.get(name, 0.0) + kv["ms"]
+        F.close()
+    torch.cuda.synchronize()
+    dom = max(per_class, key=per_class.get)
+    dom_id = rhif.KCLASS_NAMES.index(dom)
+    # the timed steps bracket only the dominant kernel's launches with events
+    flags = rhif.FLAG_KERNEL_TIMES | ((1 << dom_id) << rhif.KERNEL_MASK_SHIFT)
+    keep = []
+    t_fac, t_pcg = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ta = time.perf_counter()
+        F = rhif.Factor(2, P.s, csr, P.leaf, P.eps, 1, flags=flags)
+        tb = time.perf_counter()
+        u, it, rr = F.pcg(f, 1e-12, 500)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        t_fac.append(tb - ta)
+        t_pcg.append(tc - tb)
+        keep.append((F, it, rr))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    total = t1 - t0
+    F, it, rr = keep[-1]
+    st = F.stats()
+    kms = kfl = kby = 0.0
+    kl = 0
+    for Fk, _, _ in keep:
+        kv = Fk.stats()["kernels"].get(dom)
+        if kv:
+            kms += kv["ms"]
+            kfl += kv["flops"]
+            kby += kv["bytes"]
+            kl += kv["launches"]
+    hbm_bound = dom in ("apply_up", "apply_down", "apply_gather", "spmv", "vector", "front_csr", "front_extend")
+    if hbm_bound:
+        achieved = kby / (kms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    else:
+        achieved = kfl / (kms * 1e-3) / 1e12
+        roof = {"bound": "mfma" if dom.startswith("elim") or dom == "root" else "alu",
+                "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
+    roof.update({"kernel": dom, "launches": kl, "avg_launch_us": 1e3 * kms / max(kl, 1),
+                 "alg_per_launch": (kby if hbm_bound else kfl) / max(kl, 1),
+                 "share_of_device_time_warmup": per_class[dom] / sum(per_class.values())})
+    Au = F.matvec(u)
+    true_rel = float(torch.linalg.norm(f - Au) / torch.linalg.norm(f))
+    ms = 1e3 * total / args.steps
+    out = {
+        "metric": "factor+solve DOFs/s (PCG to rel. residual 1e-12)",
+        "value": P.N * args.steps / total,
+        "unit": "DOFs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": P.name, "grid": f"{P.s}x{P.s}", "N": P.N, "leaf": P.leaf, "eps": P.eps,
+                   "precond": 1, "pcg_iters": it, "relres": rr, "true_relres": true_rel,
+                   "t_factor_ms": 1e3 * float(np.median(t_fac)), "t_pcg_ms": 1e3 * float(np.median(t_pcg)),
+                   "levels": st["levels"], "root_size": st["root_size"],
+                   "factor_MB": st["factor_bytes"] / 1e6},
+    }
+    out["roofline"] = roof
+    out["kernel_ms_warmup"] = {k: round(v, 4) for k, v in sorted(per_class.items(), key=lambda kv: -kv[1])}
+    for F, _, _ in keep:
+        F.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(P, min(args.cpu_sample_side, P.s))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -66,7 +66,29 @@ typedef struct {
 } rhif_opts;
 
 #define RHIF_FLAG_PHASE_TIMES 1
+#define RHIF_FLAG_KERNEL_TIMES 2   /* bracket kernel launches with HIP events on the
+                                      caller's stream; accumulated in rhif_stats_t        */
+#define RHIF_KERNEL_MASK_SHIFT 8   /* flags bits 8..23: if any is set, time only the kernel
+                                      classes whose bit (1 << class) is set               */
 #define RHIF_MAX_LEVELS 32
+
+/* Kernel classes of rhif_stats_t.kernel_* */
+enum {
+    RHIF_K_FRONT_CSR = 0,     /* level-0 frontal assembly from the CSR matrix            */
+    RHIF_K_FRONT_EXTEND = 1,  /* frontal assembly from the children (levels >= 1)        */
+    RHIF_K_ELIM_LEAF = 2,     /* cell elimination at level 0                             */
+    RHIF_K_ELIM_UPPER = 3,    /* cell elimination at levels >= 1                         */
+    RHIF_K_ROOT = 4,          /* root Cholesky                                           */
+    RHIF_K_PRECOND_CHOL = 5,  /* block-Jacobi: gather + Cholesky of every group          */
+    RHIF_K_PRECOND_SCALE = 6, /* block-Jacobi: two-sided scaling of every cell           */
+    RHIF_K_SKELETONIZE = 7,   /* ID + skeleton elimination of every edge / face          */
+    RHIF_K_APPLY_UP = 8,      /* apply: up-sweep blocks                                  */
+    RHIF_K_APPLY_DOWN = 9,    /* apply: down-sweep blocks                                */
+    RHIF_K_APPLY_GATHER = 10, /* apply: gather of the cells' boundary contributions      */
+    RHIF_K_SPMV = 11,         /* CG: sparse matrix-vector product (+ p.q)                */
+    RHIF_K_VECTOR = 12,       /* CG: dots, axpys, copies                                 */
+    RHIF_NUM_KCLASS = 16
+};
 
 /* Host-side summary of a factorization. Level l in [0, levels) is a skeletonization
  * level; entry [levels] describes the root. */
@@ -85,8 +107,13 @@ typedef struct {
     double  flops[RHIF_MAX_LEVELS + 1];      /* algorithmic flops of the level's kernels */
     double  t_total_ms;                      /* host wall time of rhif_factor            */
     double  t_phase_ms[8];                   /* with RHIF_FLAG_PHASE_TIMES: assemble,
-                                                eliminate, precondition, ID, skeleton
-                                                elimination, plan+upload, root, other    */
+                                                eliminate, precondition, ID + skeleton
+                                                elimination, -, plan+upload, root, -     */
+    /* with RHIF_FLAG_KERNEL_TIMES, accumulated over every call on the handle: */
+    double  kernel_ms[RHIF_NUM_KCLASS];      /* device time (HIP events)                 */
+    int64_t kernel_launches[RHIF_NUM_KCLASS];
+    double  kernel_flops[RHIF_NUM_KCLASS];   /* algorithmic flops of those launches      */
+    double  kernel_bytes[RHIF_NUM_KCLASS];   /* algorithmic HBM bytes of those launches  */
 } rhif_stats_t;
 
 typedef struct rhif_factor_s *rhif_factor_t;

@@ -56,7 +56,7 @@ struct CellGroup {
     int32_t n;
     int64_t loff;    // L_g offset in the group pool
     int32_t owner;   // 1 if this cell holds the group's diagonal block after scaling
-    int32_t pad;
+    int32_t cell;    // index of the cell's CellScaleDesc
 };
 
 struct CellScaleDesc {

@@ -48,13 +48,17 @@ __device__ __forceinline__ unsigned long long err_code(int level, int step, int 
 // Trailing updates of every panel go through the FP64 matrix cores, one 16 x 16 tile per
 // wave at a time. A pivot <= 0 or NaN reports `code` (the smallest code wins) and the
 // factorization continues with pivot 1 so that every wave still finishes.
-// smem: 16*17 doubles for the diagonal block, then panel_cap*17 doubles for the panel.
+// Row tiles of the panel that are exactly zero (structural zeros, e.g. outside the band of
+// a grid interior) are skipped in the trailing update: they contribute nothing.
+// smem: kPotrfSmemFixed doubles (diagonal block and tile flags), then panel_cap*17
+// doubles for the panel.
 // ---------------------------------------------------------------------------------------
 __device__ void wg_potrf_partial(double* __restrict__ A, int ld, int n, int p, double* smem,
                                  int panel_cap, unsigned long long* err, unsigned long long code) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double* Ld = smem;
-    double* Pl = smem + 16 * 17;
+    int* tnz = reinterpret_cast<int*>(smem + 16 * 17);     // kPotrfMaxTiles flags
+    double* Pl = smem + kPotrfSmemFixed;
     for (int j0 = 0; j0 < p; j0 += 16) {
         const int jb = min(16, p - j0);
         const int j1 = j0 + jb;
@@ -93,6 +97,9 @@ __device__ void wg_potrf_partial(double* __restrict__ A, int ld, int n, int p, d
         __syncthreads();
         // (2) panel: rows below the block solve  x L_blk^T = a  (forward substitution).
         const bool lds_panel = (m <= panel_cap);
+        const int nt = (m + 15) >> 4;
+        for (int e = tid; e < nt; e += kWG) tnz[e] = 0;
+        __syncthreads();
         for (int i = j1 + tid; i < n; i += kWG) {
             double a[16];
 #pragma unroll
@@ -106,21 +113,25 @@ __device__ void wg_potrf_partial(double* __restrict__ A, int ld, int n, int p, d
                     a[c] = v / Ld[c * 17 + c];
                 }
             }
+            bool nz = false;
 #pragma unroll
             for (int c = 0; c < 16; ++c) {
                 if (c < jb) A[i + static_cast<size_t>(j0 + c) * ld] = a[c];
                 if (lds_panel) Pl[(i - j1) * 17 + c] = (c < jb) ? a[c] : 0.0;
+                nz = nz || (c < jb && a[c] != 0.0);
             }
+            if (nz) tnz[(i - j1) >> 4] = 1;
         }
         __syncthreads();
-        // (3) trailing update of the lower triangle: A22 -= P P^T on the matrix cores.
-        const int nt = (m + 15) >> 4;
+        // (3) trailing update of the lower triangle: A22 -= P P^T on the matrix cores,
+        //     over the pairs of nonzero row tiles only.
         const int ntiles = nt * (nt + 1) / 2;
         for (int t = wave; t < ntiles; t += kWaves) {
             int ti = static_cast<int>((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
             while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
             while (ti * (ti + 1) / 2 > t) --ti;
             const int tj = t - ti * (ti + 1) / 2;
+            if (!tnz[ti] || !tnz[tj]) continue;
             const int ra = ti * 16 + (lane & 15);
             const int rb = tj * 16 + (lane & 15);
             v4d acc = {0.0, 0.0, 0.0, 0.0};
@@ -471,46 +482,73 @@ __global__ __launch_bounds__(256) void k_precond_groups(const SepDesc* __restric
 // Block-Jacobi step, part 2: every cell's share S of the separator matrix becomes
 // Lambda^-1 S Lambda^-T with Lambda = blockdiag(L_g) over the cell's boundary groups; the
 // diagonal blocks become I in the group's first cell and 0 in the others, so that the
-// assembled matrix has unit block diagonal.
+// assembled matrix has unit block diagonal. One workgroup per (cell, boundary group h)
+// owns the block column h: Y[:, h] = Lambda^-1 S[:, h] L_h^-T (the block column of the
+// symmetric S is its block row transposed, so no other block is read). The block column
+// is staged in LDS when it fits (lds_cap doubles): first independent row solves with L_h,
+// then independent (column, group) solves with the L_g.
 __global__ __launch_bounds__(256) void k_precond_scale(const CellScaleDesc* __restrict__ cd,
                                                        const CellGroup* __restrict__ cg, const double* __restrict__ Lg,
-                                                       double* __restrict__ F) {
-    const CellScaleDesc c = cd[blockIdx.x];
-    double* A = F + c.off;
-    const int ld = c.ld;
-    // rows: U = S Lambda^-T
-    for (int i = threadIdx.x; i < c.nB; i += kWG) {
-        const int row = c.nI + i;
-        for (int e = 0; e < c.g_count; ++e) {
-            const CellGroup h = cg[c.g_begin + e];
-            const double* L = Lg + h.loff;
-            for (int q = 0; q < h.n; ++q) {
-                double v = A[row + static_cast<size_t>(h.off + q) * ld];
-                for (int t = 0; t < q; ++t) v -= L[q + t * h.n] * A[row + static_cast<size_t>(h.off + t) * ld];
-                A[row + static_cast<size_t>(h.off + q) * ld] = v / L[q + q * h.n];
-            }
+                                                       double* __restrict__ F, int lds_cap) {
+    extern __shared__ double smem[];
+    const CellGroup h = cg[blockIdx.x];
+    const CellScaleDesc c = cd[h.cell];
+    const CellGroup* G = cg + c.g_begin;
+    const int nB = c.nB, nh = h.n, ng = c.g_count;
+    const int oh = h.off - c.nI;
+    double* Fc = F + c.off;
+    const bool in_lds = nB * nh + nh * nh <= lds_cap;
+    double* B;        // block column, B[i + j * ldb] = S[i, oh + j]
+    int ldb;
+    const double* Lh;
+    if (in_lds) {
+        double* Ls = smem;
+        B = smem + nh * nh;
+        ldb = nB;
+        for (int x = threadIdx.x; x < nh * nh; x += kWG) Ls[x] = Lg[h.loff + x];
+        for (int x = threadIdx.x; x < nB * nh; x += kWG) {
+            const int i = x % nB, j = x / nB;
+            B[x] = Fc[(c.nI + i) + static_cast<size_t>(h.off + j) * c.ld];
+        }
+        Lh = Ls;
+    } else {
+        B = Fc + c.nI + static_cast<size_t>(h.off) * c.ld;
+        ldb = c.ld;
+        Lh = Lg + h.loff;
+    }
+    __syncthreads();
+    // U = S[:, h] L_h^-T: row i solves u L_h^T = s
+    for (int i = threadIdx.x; i < nB; i += kWG) {
+        for (int q = 0; q < nh; ++q) {
+            double v = B[i + static_cast<size_t>(q) * ldb];
+            for (int r = 0; r < q; ++r) v -= Lh[q + r * nh] * B[i + static_cast<size_t>(r) * ldb];
+            B[i + static_cast<size_t>(q) * ldb] = v / Lh[q + q * nh];
         }
     }
     __syncthreads();
-    // columns: Y = Lambda^-1 U
-    for (int j = threadIdx.x; j < c.nB; j += kWG) {
-        double* colp = A + static_cast<size_t>(c.nI + j) * ld;
-        for (int e = 0; e < c.g_count; ++e) {
-            const CellGroup g = cg[c.g_begin + e];
-            const double* L = Lg + g.loff;
-            for (int q = 0; q < g.n; ++q) {
-                double v = colp[g.off + q];
-                for (int t = 0; t < q; ++t) v -= L[q + t * g.n] * colp[g.off + t];
-                colp[g.off + q] = v / L[q + q * g.n];
-            }
+    // Y = Lambda^-1 U: column j of the block, group g: L_g y = u over the rows of g
+    for (int t = threadIdx.x; t < nh * ng; t += kWG) {
+        const int e = t / nh, j = t % nh;
+        const int o = G[e].off - c.nI, n = G[e].n;
+        const double* L = Lg + G[e].loff;
+        double* col = B + static_cast<size_t>(j) * ldb;
+        for (int q = 0; q < n; ++q) {
+            double v = col[o + q];
+            for (int r = 0; r < q; ++r) v -= L[q + r * n] * col[o + r];
+            col[o + q] = v / L[q + q * n];
         }
     }
     __syncthreads();
-    for (int e = 0; e < c.g_count; ++e) {
-        const CellGroup g = cg[c.g_begin + e];
-        for (int x = threadIdx.x; x < g.n * g.n; x += kWG) {
-            const int a = x % g.n, b = x / g.n;
-            A[(g.off + a) + static_cast<size_t>(g.off + b) * ld] = (g.owner && a == b) ? 1.0 : 0.0;
+    // the diagonal block of h: identity in the group's first cell, zero elsewhere
+    for (int x = threadIdx.x; x < nh * nh; x += kWG) {
+        const int a = x % nh, b = x / nh;
+        B[(oh + a) + static_cast<size_t>(b) * ldb] = (h.owner && a == b) ? 1.0 : 0.0;
+    }
+    if (in_lds) {
+        __syncthreads();
+        for (int x = threadIdx.x; x < nB * nh; x += kWG) {
+            const int i = x % nB, j = x / nB;
+            Fc[(c.nI + i) + static_cast<size_t>(h.off + j) * c.ld] = B[x];
         }
     }
 }
@@ -534,17 +572,25 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
                                                      const CellRef* __restrict__ cells, double* __restrict__ F,
                                                      double* __restrict__ Mpool, double* __restrict__ Tpool,
                                                      double* __restrict__ Gpool, double eps, int32_t* __restrict__ kout,
-                                                     int32_t* __restrict__ pout, int panel_cap, int level,
-                                                     unsigned long long* err) {
+                                                     int32_t* __restrict__ pout, int panel_cap, int staged, int nmax,
+                                                     int rmax, int level, unsigned long long* err) {
     extern __shared__ double smem[];
     const SkelDesc g = sd[blockIdx.x];
     const int n = g.n, r = g.r;
-    double* M = Mpool + g.moff;
+    // LDS: perm ints | nrm2 (nmax) | red (2) | [M (rmax*nmax) | G (nmax^2)] | potrf scratch
+    const int pd = (nmax + 1) / 2 + 1;
+    int* perm = reinterpret_cast<int*>(smem);
+    double* nrm2 = smem + pd;
+    double* red = nrm2 + nmax;
+    double* after = red + 2;
+    double* M = staged ? after : Mpool + g.moff;
+    double* Gw = staged ? after + static_cast<size_t>(rmax) * nmax : Gpool + g.goff;
+    double* psmem = staged ? Gw + static_cast<size_t>(nmax) * nmax : after;
     const int32_t* rw = rows + static_cast<size_t>(g.rows) * 2;
     const CellRef c0 = cells[g.cell[0]];
     CellRef c1 = c0;
     if (g.nslot > 1) c1 = cells[g.cell[1]];
-    // 1. gather M
+    // 1. gather M = A[R_g, g]
     for (int e = threadIdx.x; e < r * n; e += kWG) {
         const int i = e % r, j = e / r;
         const int p1 = rw[2 * i], p2 = rw[2 * i + 1];
@@ -555,9 +601,6 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
     }
     __syncthreads();
     // 2. ID
-    int* perm = reinterpret_cast<int*>(smem);              // n ints
-    double* nrm2 = smem + ((n + 1) / 2 + 1);               // n doubles
-    double* red = nrm2 + n;                                // 2 doubles
     const int k = wg_cpqr(M, r, r, n, eps, perm, nrm2, red);
     const int nr = n - k;
     double* T = Tpool + g.toff;
@@ -572,7 +615,7 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
     if (threadIdx.x == 0) kout[g.gid] = k;
     for (int e = threadIdx.x; e < n; e += kWG) pout[g.poff + e] = perm[e];
     __syncthreads();
-    // 3. zeroed blocks; U = A_hh T goes to the (now free) M scratch
+    // 3. zeroed blocks; U = A_hh T goes to the (now free) M space
     auto Agg = [&](int a, int b) -> double {
         double v = F[c0.off + (g.off[0] + a) + static_cast<size_t>(g.off[0] + b) * c0.ld];
         if (g.nslot > 1) v += F[c1.off + (g.off[1] + a) + static_cast<size_t>(g.off[1] + b) * c1.ld];
@@ -586,7 +629,6 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
         U[e] = v;
     }
     __syncthreads();
-    double* G = Gpool + g.goff;
     for (int e = threadIdx.x; e < n * n; e += kWG) {
         const int a = e % n, b = e / n;
         if (a < b) continue;
@@ -606,19 +648,20 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
         } else {
             v = Agg(perm[a - nr], perm[b - nr]);
         }
-        G[e] = v;
+        Gw[e] = v;
     }
     __syncthreads();
-    // 4. eliminate the redundant unknowns (smem: the perm ints must survive)
-    double* psmem = smem + ((n + 1) / 2 + 1);
-    wg_potrf_partial(G, n, n, nr, psmem, panel_cap, err, err_code(level, 2, blockIdx.x));
-    // 5. write back the skeleton block
+    // 4. eliminate the redundant unknowns
+    wg_potrf_partial(Gw, n, n, nr, psmem, panel_cap, err, err_code(level, 2, blockIdx.x));
+    // 5. write back the skeleton block (and keep G for the apply)
+    double* Gout = Gpool + g.goff;
     for (int e = threadIdx.x; e < n * n; e += kWG) {
         const int a = e % n, b = e / n;
+        if (staged) Gout[e] = Gw[e];
         if (a < k && b < k) {
             // skeleton a, b sit at positions perm[a], perm[b] of the group's ascending order
             F[c0.off + (g.off[0] + perm[a]) + static_cast<size_t>(g.off[0] + perm[b]) * c0.ld] =
-                G[(nr + a) + static_cast<size_t>(nr + b) * n];
+                Gw[(nr + a) + static_cast<size_t>(nr + b) * n];
         }
         if (g.nslot > 1) F[c1.off + (g.off[1] + a) + static_cast<size_t>(g.off[1] + b) * c1.ld] = 0.0;
     }
@@ -820,9 +863,11 @@ __global__ __launch_bounds__(256) void k_dot(int64_t N, const double* __restrict
 // mode 3: rho = sum (initial);   mode 4: beta = sum / rho, rho = sum.
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ part, int nparts, int mode,
                                                   double* __restrict__ sc, double* __restrict__ host_out) {
+    __shared__ double red[kWaves];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x) acc += part[b];
+    const double s = block_sum(acc, red);
     if (threadIdx.x != 0) return;
-    double s = 0.0;
-    for (int b = 0; b < nparts; ++b) s += part[b];
     switch (mode) {
         case 0: sc[6] = s; if (host_out) host_out[0] = s; break;
         case 1: sc[1] = s; sc[2] = sc[0] / s; break;

@@ -18,10 +18,12 @@ __global__ void k_potrf_batch(const FrontDesc* desc, double* pool, int panel_cap
                               unsigned long long* err);
 __global__ void k_precond_groups(const SepDesc* sd, const CellRef* cells, const double* F, double* Lg,
                                  int panel_cap, int level, unsigned long long* err);
-__global__ void k_precond_scale(const CellScaleDesc* cd, const CellGroup* cg, const double* Lg, double* F);
+__global__ void k_precond_scale(const CellScaleDesc* cd, const CellGroup* cg, const double* Lg, double* F,
+                                int lds_cap);
 __global__ void k_skeletonize(const SkelDesc* sd, const int32_t* rows, const CellRef* cells, double* F,
                               double* Mpool, double* Tpool, double* Gpool, double eps, int32_t* kout,
-                              int32_t* pout, int panel_cap, int level, unsigned long long* err);
+                              int32_t* pout, int panel_cap, int staged, int nmax, int rmax, int level,
+                              unsigned long long* err);
 __global__ void k_apply_up(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
                            double* z, double* ybuf, double* ws);
 __global__ void k_apply_down(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
@@ -39,5 +41,7 @@ __global__ void k_fill(int64_t N, double v, double* y);
 __global__ void k_set_u64(unsigned long long* p, unsigned long long v);
 
 constexpr int kApplyDiagDoubles = 32 * 33;   // LDS diagonal block of the apply kernels
+constexpr int kPotrfMaxTiles = 1024;          // frontal order up to 16384
+constexpr int kPotrfSmemFixed = 16 * 17 + kPotrfMaxTiles / 2;   // doubles before the panel
 
 }  // namespace rhif

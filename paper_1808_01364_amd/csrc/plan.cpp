@@ -33,17 +33,55 @@ void PlanScratch::init(int64_t N) {
     cur = 0;
 }
 
+void PlanScratch::reserve(int64_t N) {
+    if (static_cast<int64_t>(mark_stamp.size()) >= N) {
+        cur = 0;
+        return;
+    }
+    init(N);
+}
+
+void LevelPlan::reset() {
+    level = w = nc1 = 0;
+    root = false;
+    for (auto* v : {&gptr, &gdofs, &gslot_cnt, &gslot_cell, &gslot_off, &c_nI, &c_nB, &c_nf, &c_ld, &c_dptr,
+                    &c_dofs, &c_gptr, &c_g, &c_goff, &seps, &skels, &src, &skel_rows, &sep_dofs})
+        v->clear();
+    gcls.clear();
+    c_foff.clear();
+    cell_potrf.clear();
+    cell_ref.clear();
+    tiles.clear();
+    sep_desc.clear();
+    cell_groups.clear();
+    cell_scale.clear();
+    skel_desc.clear();
+    cell_apply.clear();
+    sep_apply.clear();
+    gather.clear();
+    ncells = 0;
+    front_elems = lg_elems = m_elems = t_elems = g_elems = y_elems = ws_elems = 0;
+    skel_ntotal = max_nf = max_sep_n = max_skel_n = 0;
+    flops = alg_elim_flops = alg_prec_chol_flops = alg_prec_scale_flops = alg_front_bytes = 0.0;
+    alg_apply_cell_bytes = alg_apply_sep_bytes = alg_gather_bytes = 0.0;
+}
+
 int num_levels(int s, int leaf) {
     int L = 0;
     while ((static_cast<int64_t>(leaf) << L) <= s) ++L;
     return L;
 }
 
-void build_level(const GridInfo& gi, int level, int leaf, bool root,
-                 const std::vector<int32_t>& active, const LevelPlan* prev,
-                 PlanScratch& scr, int lds_apply_cap, LevelPlan& P) {
+void build_level(const GridInfo& gi, int level, int leaf, bool root, const std::vector<int32_t>& active,
+                 const LevelPlan* prev, PlanScratch& scr, int lds_apply_cap, LevelPlan& P) {
+    build_cells(gi, level, leaf, root, active, prev, scr, lds_apply_cap, P);
+    if (!root) build_separators(gi, scr, lds_apply_cap, P);
+}
+
+void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::vector<int32_t>& active,
+                 const LevelPlan* prev, PlanScratch& scr, int lds_apply_cap, LevelPlan& P) {
     const int d = gi.d, s = gi.s;
-    P = LevelPlan();
+    P.reset();
     P.level = level;
     P.root = root;
     const int64_t w = static_cast<int64_t>(leaf) << level;
@@ -57,19 +95,37 @@ void build_level(const GridInfo& gi, int level, int leaf, bool root,
 
     // ---- classify the active unknowns and bucket them by key (stable) ----
     const size_t na = active.size();
-    std::vector<int32_t> akey(na);
+    std::vector<int32_t>& akey = scr.akey;
+    akey.resize(na);
     scr.count.assign(nkeys + 1, 0);
-    int x[3];
-    for (size_t a = 0; a < na; ++a) {
-        coords(active[a], d, s, x);
-        int64_t K = 0, mul = 1;
-        for (int k = 0; k < d; ++k) {
-            const int key = 2 * static_cast<int>(x[k] / w) + ((x[k] % w) != 0 ? 1 : 0);
-            K += key * mul;
-            mul *= KB;
+    {
+        // The active list is ascending, so the coordinates can be advanced incrementally
+        // from one unknown to the next instead of divided out of the linear index.
+        std::vector<int32_t> keyk(static_cast<size_t>(s) + 1);
+        for (int xk = 1; xk <= s; ++xk) keyk[xk] = 2 * (xk / static_cast<int>(w)) + ((xk % w) != 0 ? 1 : 0);
+        int64_t mulk[3] = {1, KB, static_cast<int64_t>(KB) * KB};
+        int x[3] = {1, 1, 1};
+        int64_t cur_lin = 0;
+        if (na > 0) {
+            coords(active[0], d, s, x);
+            cur_lin = active[0];
         }
-        akey[a] = static_cast<int32_t>(K);
-        scr.count[K + 1]++;
+        for (size_t a = 0; a < na; ++a) {
+            const int64_t i = active[a];
+            int64_t step = i - cur_lin;
+            if (step > 0) {
+                if (step < s - x[0] + 1) {
+                    x[0] += static_cast<int>(step);
+                } else {
+                    coords(i, d, s, x);
+                }
+                cur_lin = i;
+            }
+            int64_t K = 0;
+            for (int k = 0; k < d; ++k) K += keyk[x[k]] * mulk[k];
+            akey[a] = static_cast<int32_t>(K);
+            scr.count[K + 1]++;
+        }
     }
     scr.key2g.assign(nkeys, -1);
     int ngroups = 0;
@@ -186,10 +242,23 @@ void build_level(const GridInfo& gi, int level, int leaf, bool root,
             for (int r0 = 0; r0 < nf; r0 += 64)
                 P.tiles.push_back(Tile{static_cast<int32_t>(ci), r0, c0, 0});
         const int nI = P.c_nI[ci], nB = P.c_nB[ci];
+        P.alg_front_bytes += 8.0 * static_cast<double>(nf) * nf;
         if (nI > 0) {
             P.cell_potrf.push_back(FrontDesc{P.c_foff[ci], P.c_ld[ci], nf, nI, static_cast<int32_t>(ci)});
             const double a = nI, b = nB;
             P.flops += a * a * a / 3.0 + a * a * b + a * b * b;
+            double lwords;
+            if (level == 0 && !root) {
+                double bw = 1.0;
+                for (int k = 1; k < d; ++k) bw *= (leaf - 1);
+                bw = std::min(bw, a);
+                P.alg_elim_flops += a * bw * bw + 2.0 * a * bw * b + b * b * a;
+                lwords = a * (bw + 1.0);
+            } else {
+                P.alg_elim_flops += a * a * a / 3.0 + a * a * b + a * b * b;
+                lwords = a * (a + 1.0) / 2.0;
+            }
+            P.alg_apply_cell_bytes += 8.0 * (lwords + a * b) + 8.0 * (2.0 * a + b);
         }
     }
 
@@ -227,7 +296,8 @@ void build_level(const GridInfo& gi, int level, int leaf, bool root,
 
     // ---- cell apply descriptors and the y scratch ----
     int64_t yoff = 0, ws = 0;
-    std::vector<int64_t> cell_y(ncells, -1);
+    std::vector<int64_t>& cell_y = scr.cell_y;
+    cell_y.assign(ncells, -1);
     for (int64_t ci = 0; ci < ncells; ++ci) {
         const int nI = P.c_nI[ci], nB = P.c_nB[ci];
         if (nI == 0) continue;
@@ -249,11 +319,15 @@ void build_level(const GridInfo& gi, int level, int leaf, bool root,
         yoff += nB;
     }
     P.y_elems = std::max<int64_t>(yoff, 1);
+    P.ws_elems = ws;
+}
 
-    if (root) {
-        P.ws_elems = ws;
-        return;
-    }
+void build_separators(const GridInfo& gi, PlanScratch& scr, int lds_apply_cap, LevelPlan& P) {
+    (void)gi;
+    const int ngroups = static_cast<int>(P.gptr.size()) - 1;
+    const int64_t ncells = P.ncells;
+    const std::vector<int64_t>& cell_y = scr.cell_y;
+    int64_t ws = P.ws_elems;
 
     // ---- separator groups: block Jacobi and the up-sweep gather ----
     int64_t loff = 0;
@@ -277,6 +351,8 @@ void build_level(const GridInfo& gi, int level, int leaf, bool root,
         loff += align_up(static_cast<int64_t>(n) * n, 32);
         P.max_sep_n = std::max(P.max_sep_n, n);
         P.flops += static_cast<double>(n) * n * n / 3.0;
+        P.alg_prec_chol_flops += static_cast<double>(n) * n * n / 3.0;
+        P.alg_apply_sep_bytes += 8.0 * (static_cast<double>(n) * (n + 1) / 2.0 + 2.0 * n);
 
         GatherDesc gd{};
         gd.n = n;
@@ -287,6 +363,7 @@ void build_level(const GridInfo& gi, int level, int leaf, bool root,
             if (cell_y[cc] < 0) continue;
             gd.yoff[gd.nslot++] = cell_y[cc] + (sd.slot_off[sl] - P.c_nI[cc]);
         }
+        P.alg_gather_bytes += 8.0 * n * (gd.nslot + 2.0);
         P.gather.push_back(gd);
 
         ApplyDesc ad{};
@@ -319,9 +396,11 @@ void build_level(const GridInfo& gi, int level, int leaf, bool root,
             cg.n = P.gptr[g + 1] - P.gptr[g];
             cg.loff = g_loff[g];
             cg.owner = (P.gslot_cell[static_cast<size_t>(g) * kMaxSlots] == ci) ? 1 : 0;
+            cg.cell = static_cast<int32_t>(P.cell_scale.size());
             P.cell_groups.push_back(cg);
             const double nb = cs.nB, ng = cg.n;
             P.flops += 2.0 * nb * ng * ng;
+            P.alg_prec_scale_flops += 2.0 * nb * ng * ng;
         }
         cs.g_count = static_cast<int32_t>(P.cell_groups.size()) - cs.g_begin;
         if (cs.nB > 0) P.cell_scale.push_back(cs);
@@ -343,31 +422,37 @@ void build_level(const GridInfo& gi, int level, int leaf, bool root,
             sk.cell[sl] = sl < ns ? P.gslot_cell[static_cast<size_t>(g) * kMaxSlots + sl] : -1;
             sk.off[sl] = sl < ns ? P.gslot_off[static_cast<size_t>(g) * kMaxSlots + sl] : -1;
         }
-        const int32_t st = ++scr.stamp;
+        // rows: the other boundary groups of the first cell (with the second cell's share
+        // added where the group is shared), then the second cell's remaining groups
         int r = 0;
-        {
-            const int c1 = sk.cell[0], o1 = sk.off[0];
-            for (int p = P.c_nI[c1]; p < P.c_nf[c1]; ++p) {
-                if (p >= o1 && p < o1 + n) continue;
-                const int32_t i = P.c_dofs[P.c_dptr[c1] + p];
-                scr.mark_stamp[i] = st;
-                scr.mark_row[i] = r++;
-                P.skel_rows.push_back(p);
-                P.skel_rows.push_back(-1);
+        const int c1 = sk.cell[0];
+        const int c2 = ns == 2 ? sk.cell[1] : -1;
+        auto find_in = [&](int cell, int grp) -> int {
+            for (int e = P.c_gptr[cell]; e < P.c_gptr[cell + 1]; ++e)
+                if (P.c_g[e] == grp) return P.c_goff[e];
+            return -1;
+        };
+        for (int e = P.c_gptr[c1]; e < P.c_gptr[c1 + 1]; ++e) {
+            const int h = P.c_g[e];
+            if (h == g) continue;
+            const int nh = P.gptr[h + 1] - P.gptr[h];
+            const int o2 = c2 >= 0 ? find_in(c2, h) : -1;
+            for (int t = 0; t < nh; ++t) {
+                P.skel_rows.push_back(P.c_goff[e] + t);
+                P.skel_rows.push_back(o2 >= 0 ? o2 + t : -1);
             }
+            r += nh;
         }
-        if (ns == 2) {
-            const int c2 = sk.cell[1], o2 = sk.off[1];
-            for (int p = P.c_nI[c2]; p < P.c_nf[c2]; ++p) {
-                if (p >= o2 && p < o2 + n) continue;
-                const int32_t i = P.c_dofs[P.c_dptr[c2] + p];
-                if (scr.mark_stamp[i] == st) {
-                    P.skel_rows[(static_cast<size_t>(sk.rows) + scr.mark_row[i]) * 2 + 1] = p;
-                } else {
+        if (c2 >= 0) {
+            for (int e = P.c_gptr[c2]; e < P.c_gptr[c2 + 1]; ++e) {
+                const int h = P.c_g[e];
+                if (h == g || find_in(c1, h) >= 0) continue;
+                const int nh = P.gptr[h + 1] - P.gptr[h];
+                for (int t = 0; t < nh; ++t) {
                     P.skel_rows.push_back(-1);
-                    P.skel_rows.push_back(p);
-                    ++r;
+                    P.skel_rows.push_back(P.c_goff[e] + t);
                 }
+                r += nh;
             }
         }
         sk.r = r;
@@ -383,8 +468,6 @@ void build_level(const GridInfo& gi, int level, int leaf, bool root,
         P.skels.push_back(g);
         P.skel_desc.push_back(sk);
         P.max_skel_n = std::max(P.max_skel_n, n);
-        const double rr = r, nn = n;
-        P.flops += 4.0 * rr * nn * nn;   // CPQR bound (k <= n), refined after the ID
     }
     P.skel_ntotal = poff;
     P.m_elems = std::max<int64_t>(moff, 32);
@@ -396,7 +479,10 @@ void build_level(const GridInfo& gi, int level, int leaf, bool root,
 void finish_level(const LevelPlan& P, const int32_t* k, const int32_t* perm, int lds_apply_cap,
                   std::vector<ApplyDesc>& skel_apply, std::vector<int32_t>& skel_dofs,
                   int64_t& ws_elems, const std::vector<int32_t>& active,
-                  std::vector<int32_t>& next_active, PlanScratch& scr, double& flops) {
+                  std::vector<int32_t>& next_active, PlanScratch& scr, double& skel_flops,
+                  double& skel_apply_bytes) {
+    skel_flops = 0.0;
+    skel_apply_bytes = 0.0;
     skel_apply.clear();
     skel_dofs.clear();
     const int32_t st = ++scr.stamp;
@@ -412,9 +498,12 @@ void finish_level(const LevelPlan& P, const int32_t* k, const int32_t* perm, int
         const int32_t* pv = perm + sk.poff;
         const int32_t* gd = P.gdofs.data() + P.gptr[g];
         for (int q = kk; q < n; ++q) scr.mark_stamp[gd[pv[q]]] = st;   // redundant unknowns
-        const double nr = n - kk, kd = kk;
-        flops += nr * nr * nr / 3.0 + nr * nr * kd + nr * kd * kd + nr * kd * kd;
+        const double nr = n - kk, kd = kk, rr = sk.r, nd = n;
+        // ID by pivoted QR of an r x n block to rank k, then the skeleton elimination
+        skel_flops += std::max(0.0, 4.0 * rr * nd * kd - 2.0 * kd * kd * (rr + nd) + 4.0 * kd * kd * kd / 3.0) +
+                      rr * nd + nr * nr * kd + nr * nr * nr / 3.0 + nr * nr * kd + kd * kd * nr;
         if (kk == n) continue;
+        skel_apply_bytes += 8.0 * (nr * (nr + 1.0) / 2.0 + 2.0 * kd * nr) + 8.0 * 2.0 * nd;
         ApplyDesc ad{};
         ad.off = sk.goff;
         ad.toff = (kk > 0) ? sk.toff : -1;
@@ -454,6 +543,11 @@ inline void need(bool ok, const char* what, int64_t a = 0, int64_t b = 0) {
 }  // namespace
 
 void validate_level(const LevelPlan& P, const LevelPlan* prev, int d) {
+    validate_cells(P, prev, d);
+    if (!P.root) validate_separators(P);
+}
+
+void validate_cells(const LevelPlan& P, const LevelPlan* prev, int d) {
     const int64_t ncd = static_cast<int64_t>(P.c_dofs.size());
     for (int c = 0; c < P.ncells; ++c) {
         const CellRef& r = P.cell_ref[c];
@@ -482,6 +576,19 @@ void validate_level(const LevelPlan& P, const LevelPlan* prev, int d) {
             need(pos >= prev->c_nI[c] && pos < prev->c_nf[c], "src child position", pos, prev->c_nf[c]);
         }
     }
+    int64_t ysum = 0;
+    for (const ApplyDesc& a : P.cell_apply) {
+        need(a.nI >= 1 && a.dofs >= 0 && a.dofs + a.nI + a.nB <= ncd, "cell apply dofs");
+        need(a.off >= 0 && a.off + static_cast<int64_t>(a.ld) * (a.nI + a.nB) <= P.front_elems, "cell apply bounds");
+        need(a.ld >= a.nI + a.nB, "cell apply ld");
+        if (a.yoff >= 0) need(a.yoff + a.nB <= P.y_elems, "cell apply y bounds");
+        if (a.wsoff >= 0) need(a.wsoff + a.nI + a.nB <= P.ws_elems, "cell apply ws bounds");
+        ysum += a.nB;
+    }
+    need(ysum <= P.y_elems, "y scratch", ysum, P.y_elems);
+}
+
+void validate_separators(const LevelPlan& P) {
     for (const SepDesc& s : P.sep_desc) {
         need(s.nslot >= 1 && s.nslot <= kMaxSlots, "sep slots", s.nslot, kMaxSlots);
         need(s.n >= 1 && s.loff >= 0 && s.loff + static_cast<int64_t>(s.n) * s.n <= P.lg_elems, "sep L bounds");
@@ -502,6 +609,8 @@ void validate_level(const LevelPlan& P, const LevelPlan* prev, int d) {
             tot += g.n;
         }
         need(tot == cs.nB, "scale groups cover the boundary", tot, cs.nB);
+        for (int e = cs.g_begin; e < cs.g_begin + cs.g_count; ++e)
+            need(&P.cell_scale[P.cell_groups[e].cell] == &cs, "scale group cell index");
     }
     for (const SkelDesc& k : P.skel_desc) {
         need(k.nslot >= 1 && k.nslot <= 2, "skel slots");
@@ -525,16 +634,6 @@ void validate_level(const LevelPlan& P, const LevelPlan* prev, int d) {
         need(k.poff >= 0 && k.poff + k.n <= P.skel_ntotal, "skel perm bounds");
         need(k.gid >= 0 && k.gid < static_cast<int>(P.skel_desc.size()), "skel gid");
     }
-    int64_t ysum = 0;
-    for (const ApplyDesc& a : P.cell_apply) {
-        need(a.nI >= 1 && a.dofs >= 0 && a.dofs + a.nI + a.nB <= ncd, "cell apply dofs");
-        need(a.off >= 0 && a.off + static_cast<int64_t>(a.ld) * (a.nI + a.nB) <= P.front_elems, "cell apply bounds");
-        need(a.ld >= a.nI + a.nB, "cell apply ld");
-        if (a.yoff >= 0) need(a.yoff + a.nB <= P.y_elems, "cell apply y bounds");
-        if (a.wsoff >= 0) need(a.wsoff + a.nI + a.nB <= P.ws_elems, "cell apply ws bounds");
-        ysum += a.nB;
-    }
-    need(ysum <= P.y_elems, "y scratch", ysum, P.y_elems);
     for (const GatherDesc& g : P.gather) {
         need(g.dofs >= 0 && g.dofs + g.n <= static_cast<int64_t>(P.sep_dofs.size()), "gather dofs");
         for (int q = 0; q < g.nslot; ++q) need(g.yoff[q] >= 0 && g.yoff[q] + g.n <= P.y_elems, "gather y bounds");

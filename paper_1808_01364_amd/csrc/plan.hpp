@@ -69,6 +69,18 @@ struct LevelPlan {
     int32_t skel_ntotal = 0;               // sum of skeletonized group sizes
     int32_t max_nf = 0, max_sep_n = 0, max_skel_n = 0;
     double flops = 0.0;                    // algorithmic flops (cells + groups + skeletons)
+    // algorithmic work per launch class (what the method must do, not what a kernel does):
+    // level-0 cell interiors count as banded matrices of bandwidth (m-1)^(d-1)
+    double alg_elim_flops = 0.0;           // cell elimination (potrf + trsm + syrk)
+    double alg_prec_chol_flops = 0.0;      // group Cholesky
+    double alg_prec_scale_flops = 0.0;     // two-sided scaling
+    double alg_front_bytes = 0.0;          // frontal assembly (frontal writes + sources)
+    double alg_apply_cell_bytes = 0.0;     // one sweep over the cells (L, W, vectors)
+    double alg_apply_sep_bytes = 0.0;      // one sweep over the groups (L_g, vectors)
+    double alg_gather_bytes = 0.0;         // one gather
+
+    // Empty every table but keep the allocations (plans are reused across factorizations).
+    void reset();
 };
 
 // Reusable per-factorization scratch sized by N.
@@ -77,9 +89,15 @@ struct PlanScratch {
     std::vector<int32_t> key2g;
     std::vector<int32_t> dof_group[2], dof_tpos[2];
     std::vector<int32_t> mark_stamp, mark_row;
+    std::vector<int32_t> akey;             // per active unknown: its group key
+    std::vector<int64_t> cell_y;           // per cell: its offset in the apply scratch
     int32_t stamp = 0;
     int cur = 0;
     void init(int64_t N);
+    // Make room for N unknowns without clearing what is there: the per-unknown maps are
+    // only read for unknowns written earlier in the same factorization, and the stamps
+    // only grow.
+    void reserve(int64_t N);
 };
 
 // Number of skeletonization levels L: all l >= 0 with 2^l m <= s.
@@ -88,6 +106,13 @@ int num_levels(int s, int leaf);
 // Build the plan of `level` from its sorted active unknowns. `prev` is the plan of the
 // level below (nullptr at level 0) and is used for the extend-add source tables.
 // lds_apply_cap: largest nI + nB staged in LDS by the apply kernels.
+// The work is split in two halves so that the second can overlap device work:
+//   build_cells: groups, cell frontals, assembly tiles, elimination and cell apply tables;
+//   build_separators: block-Jacobi, ID / skeleton and gather tables (not at the root).
+void build_cells(const GridInfo& g, int level, int leaf, bool root, const std::vector<int32_t>& active,
+                 const LevelPlan* prev, PlanScratch& scr, int lds_apply_cap, LevelPlan& out);
+void build_separators(const GridInfo& g, PlanScratch& scr, int lds_apply_cap, LevelPlan& out);
+// Both halves.
 void build_level(const GridInfo& g, int level, int leaf, bool root,
                  const std::vector<int32_t>& active, const LevelPlan* prev,
                  PlanScratch& scr, int lds_apply_cap, LevelPlan& out);
@@ -96,6 +121,8 @@ void build_level(const GridInfo& g, int level, int leaf, bool root,
 // buffers the driver allocates for them (throws std::logic_error otherwise), so that a
 // planning mistake becomes an error return instead of an out-of-bounds access on the GPU.
 // prev: the plan of the level below (its frontals are read by the extend-add).
+void validate_cells(const LevelPlan& lp, const LevelPlan* prev, int d);
+void validate_separators(const LevelPlan& lp);
 void validate_level(const LevelPlan& lp, const LevelPlan* prev, int d);
 
 // Same for the skeleton apply tables built by finish_level.
@@ -109,6 +136,6 @@ void finish_level(const LevelPlan& lp, const int32_t* k, const int32_t* perm,
                   int lds_apply_cap, std::vector<ApplyDesc>& skel_apply,
                   std::vector<int32_t>& skel_dofs, int64_t& ws_elems,
                   const std::vector<int32_t>& active, std::vector<int32_t>& next_active,
-                  PlanScratch& scr, double& flops);
+                  PlanScratch& scr, double& skel_flops, double& skel_apply_bytes);
 
 }  // namespace rhif

@@ -61,9 +61,9 @@ extern "C" rhif_status rhif_plan_dry_run(const rhif_grid* g, int32_t leaf, rhif_
             }
             std::vector<ApplyDesc> sad;
             std::vector<int32_t> sdofs;
-            double fl = 0;
+            double fl = 0, by = 0;
             ws = std::max(ws, P.ws_elems);
-            finish_level(P, ks.data(), perm.data(), 7000, sad, sdofs, ws, active, next, scr, fl);
+            finish_level(P, ks.data(), perm.data(), 7000, sad, sdofs, ws, active, next, scr, fl, by);
             validate_skel_apply(P, sad, sdofs, gi.N);
             active.swap(next);
         }

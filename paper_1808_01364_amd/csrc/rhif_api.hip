@@ -38,43 +38,70 @@ void hipcheck(hipError_t e, const char* what, int line) {
 }
 #define HIPCHK(x) hipcheck((x), #x, __LINE__)
 
-constexpr int kLdsBudgetDoubles = 8192;      // 64 KiB of LDS per workgroup
+constexpr int kLdsBudgetDoubles = 8192;      // 64 KiB of LDS per workgroup (default kernels)
+constexpr int kLdsMaxDoubles = 20480;        // 160 KiB: the gfx950 per-workgroup limit
 constexpr int kApplyCap = kLdsBudgetDoubles - rhif::kApplyDiagDoubles - 32;
 constexpr int kRedBlocks = 1024;              // fixed partial-sum layout of the CG reductions
 
-// Pinned host staging shared by all handles of the process (grow-only).
-struct Pinned {
-    std::mutex mu;
-    char* up = nullptr;
-    size_t up_bytes = 0;
+// Per-thread host state reused across factorizations: pinned staging buffers for the
+// uploads (a ring, each slot fenced by the event of its last copy), a pinned buffer for
+// the small read-backs, and the planner's scratch and level plans (so that repeated
+// factorizations do not pay for fresh allocations and page faults). Kept for the life of
+// the process.
+struct HostCache {
+    static constexpr int kSlots = 3;
+    char* up[kSlots] = {};
+    size_t up_bytes[kSlots] = {};
+    hipEvent_t up_ev[kSlots] = {};
+    bool up_pending[kSlots] = {};
+    int next = 0;
     char* down = nullptr;
     size_t down_bytes = 0;
-    char* get_up(size_t b) {
-        if (b > up_bytes) {
-            if (up) (void)hipHostFree(up);
-            up = nullptr;
-            up_bytes = 0;
-            const size_t nb = std::max(b, up_bytes * 2);
-            HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&up), nb, hipHostMallocDefault));
-            up_bytes = nb;
+    rhif::PlanScratch scr;
+    std::vector<rhif::LevelPlan*> plans;
+    std::vector<int32_t> active, next_active;
+
+    char* get_up(size_t b, int& slot) {
+        slot = next;
+        next = (next + 1) % kSlots;
+        if (up_pending[slot]) {
+            HIPCHK(hipEventSynchronize(up_ev[slot]));
+            up_pending[slot] = false;
         }
-        return up;
+        if (b > up_bytes[slot]) {
+            if (up[slot]) (void)hipHostFree(up[slot]);
+            up[slot] = nullptr;
+            const size_t nb = std::max(b, 2 * up_bytes[slot]);
+            up_bytes[slot] = 0;
+            HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&up[slot]), nb, hipHostMallocDefault));
+            up_bytes[slot] = nb;
+        }
+        return up[slot];
+    }
+    void fence(int slot, hipStream_t s) {
+        if (!up_ev[slot]) HIPCHK(hipEventCreateWithFlags(&up_ev[slot], hipEventDisableTiming));
+        HIPCHK(hipEventRecord(up_ev[slot], s));
+        up_pending[slot] = true;
     }
     char* get_down(size_t b) {
         if (b > down_bytes) {
             if (down) (void)hipHostFree(down);
             down = nullptr;
+            const size_t nb = std::max<size_t>(b, std::max<size_t>(2 * down_bytes, 1 << 16));
             down_bytes = 0;
-            const size_t nb = std::max<size_t>(b, 1 << 16);
             HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&down), nb, hipHostMallocDefault));
             down_bytes = nb;
         }
         return down;
     }
+    rhif::LevelPlan& plan(int lvl) {
+        while (static_cast<int>(plans.size()) <= lvl) plans.push_back(new rhif::LevelPlan());
+        return *plans[lvl];
+    }
 };
-Pinned& pinned() {
-    static Pinned* p = new Pinned();
-    return *p;
+HostCache& host_cache() {
+    thread_local HostCache* c = new HostCache();
+    return *c;
 }
 
 // Packs host arrays into one upload; every sub-array is 256-byte aligned.
@@ -94,14 +121,12 @@ struct Packer {
 };
 
 struct LevelDev {
-    rhif::LevelPlan plan;
+    bool root = false;
     double* front = nullptr;
     double* lg = nullptr;
     double* tp = nullptr;
     double* gp = nullptr;
-    char* tab = nullptr;
-    char* tab2 = nullptr;
-    // device views into tab / tab2
+    // device views into the uploaded tables
     int32_t* cdofs = nullptr;
     rhif::CellRef* cref = nullptr;
     rhif::FrontDesc* potrf = nullptr;
@@ -118,8 +143,11 @@ struct LevelDev {
     int32_t* sepdofs = nullptr;
     rhif::ApplyDesc* skel_ad = nullptr;
     int32_t* skeldofs = nullptr;
-    int n_skel_ad = 0;
+    int n_cell_ad = 0, n_sep_ad = 0, n_gather = 0, n_skel_ad = 0;
     size_t lds_cell = 0, lds_sep = 0, lds_skel = 0;
+    // algorithmic bytes of one apply sweep over each block family
+    double b_cell = 0.0, b_sep = 0.0, b_gather = 0.0, b_skel = 0.0;
+    int64_t bytes = 0;   // device bytes of the factor held for this level
     // ID choices (host)
     std::vector<int32_t> k, perm, first_dof, gsize;
 };
@@ -162,6 +190,41 @@ struct rhif_factor_s {
     rhif_stats_t stats{};
     std::vector<void*> allocs;
     hipStream_t alloc_stream = nullptr;
+    // per-launch device timing (RHIF_FLAG_KERNEL_TIMES)
+    bool ktimes = false;
+    uint32_t kmask = 0xffffu;
+    struct Pend {
+        hipEvent_t a, b;
+        int cls;
+        double fl, by;
+    };
+    std::vector<Pend> pend;
+    std::vector<hipEvent_t> evpool;
+
+    hipEvent_t ev() {
+        if (!evpool.empty()) {
+            hipEvent_t e = evpool.back();
+            evpool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        return e;
+    }
+    void resolve() {
+        for (const Pend& q : pend) {
+            HIPCHK(hipEventSynchronize(q.b));
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, q.a, q.b));
+            stats.kernel_ms[q.cls] += ms;
+            stats.kernel_launches[q.cls] += 1;
+            stats.kernel_flops[q.cls] += q.fl;
+            stats.kernel_bytes[q.cls] += q.by;
+            evpool.push_back(q.a);
+            evpool.push_back(q.b);
+        }
+        pend.clear();
+    }
 
     void* dalloc(size_t bytes) {
         void* ptr = nullptr;
@@ -171,12 +234,37 @@ struct rhif_factor_s {
     }
     void release() {
         (void)hipStreamSynchronize(alloc_stream);
+        for (const Pend& q : pend) {
+            (void)hipEventSynchronize(q.b);
+            evpool.push_back(q.a);
+            evpool.push_back(q.b);
+        }
+        pend.clear();
+        for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+        evpool.clear();
         for (void* ptr : allocs) (void)hipFree(ptr);
         allocs.clear();
     }
 };
 
 namespace {
+
+// Launch with optional HIP-event bracketing on the launch stream.
+#define KTIMED(f, s, cls, fl, by, ...)                                       \
+    do {                                                                     \
+        hipEvent_t ea_ = nullptr;                                            \
+        if ((f)->ktimes && (((f)->kmask >> (cls)) & 1u)) {                   \
+            ea_ = (f)->ev();                                                 \
+            HIPCHK(hipEventRecord(ea_, (s)));                                \
+        }                                                                    \
+        __VA_ARGS__;                                                         \
+        HIPCHK(hipGetLastError());                                           \
+        if (ea_) {                                                           \
+            hipEvent_t eb_ = (f)->ev();                                      \
+            HIPCHK(hipEventRecord(eb_, (s)));                                \
+            (f)->pend.push_back({ea_, eb_, (cls), (fl), (by)});              \
+        }                                                                    \
+    } while (0)
 
 void set_pool_threshold() {
     static std::once_flag once;
@@ -236,25 +324,39 @@ void check_err(rhif_factor_s* f, hipStream_t s) {
 template <class T>
 T* view(char* base, size_t off) { return reinterpret_cast<T*>(base + off); }
 
-void upload(rhif_factor_s* f, Packer& pk, char*& dst, hipStream_t s) {
-    if (pk.total == 0) return;
-    Pinned& pn = pinned();
-    std::lock_guard<std::mutex> lk(pn.mu);
-    char* h = pn.get_up(pk.total);
+// Copies the packed tables to a new device buffer, asynchronously on the stream.
+char* upload(rhif_factor_s* f, Packer& pk, hipStream_t s) {
+    if (pk.total == 0) return nullptr;
+    HostCache& hc = host_cache();
+    int slot = 0;
+    char* h = hc.get_up(pk.total, slot);
     for (size_t e = 0; e < pk.parts.size(); ++e)
         if (pk.parts[e].second) std::memcpy(h + pk.offs[e], pk.parts[e].first, pk.parts[e].second);
-    dst = static_cast<char*>(f->dalloc(pk.total));
+    char* dst = static_cast<char*>(f->dalloc(pk.total));
     HIPCHK(hipMemcpyAsync(dst, h, pk.total, hipMemcpyHostToDevice, s));
-    // the staging buffer is reused by the next upload: wait for this copy
-    HIPCHK(hipStreamSynchronize(s));
+    hc.fence(slot, s);
+    return dst;
 }
 
 int panel_cap_for(int nmax, int reserved_doubles) {
-    const int cap = (kLdsBudgetDoubles - reserved_doubles - 16 * 17) / 17;
+    const int cap = (kLdsBudgetDoubles - reserved_doubles - rhif::kPotrfSmemFixed) / 17;
     return std::max(0, std::min(cap, nmax));
 }
 
-size_t potrf_lds(int cap, int reserved) { return static_cast<size_t>(reserved + 16 * 17 + cap * 17) * sizeof(double); }
+size_t potrf_lds(int cap, int reserved) {
+    return static_cast<size_t>(reserved + rhif::kPotrfSmemFixed + cap * 17) * sizeof(double);
+}
+
+void set_kernel_attributes() {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const int bytes = kLdsMaxDoubles * static_cast<int>(sizeof(double));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_precond_scale),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_skeletonize),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    });
+}
 
 void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, const double* val, hipStream_t s) {
     using namespace rhif;
@@ -273,75 +375,55 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
     HIPCHK(hipMemcpyAsync(f->ci, col, f->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(f->val, val, f->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
 
-    PlanScratch scr;
-    scr.init(g.N);
-    std::vector<int32_t> active(g.N), next;
+    HostCache& hc = host_cache();
+    PlanScratch& scr = hc.scr;
+    scr.reserve(g.N);
+    std::vector<int32_t>& active = hc.active;
+    std::vector<int32_t>& next = hc.next_active;
+    active.resize(g.N);
     for (int64_t i = 0; i < g.N; ++i) active[i] = static_cast<int32_t>(i);
     f->lev.resize(f->L + 1);
     const bool timing = (f->o.flags & RHIF_FLAG_PHASE_TIMES) != 0;
     auto now = [] { return std::chrono::steady_clock::now(); };
-    auto ms_since = [&](std::chrono::steady_clock::time_point t0) {
-        return std::chrono::duration<double, std::milli>(now() - t0).count();
-    };
     auto phase = [&](int idx, std::chrono::steady_clock::time_point t0) {
         if (!timing) return;
         HIPCHK(hipStreamSynchronize(s));
-        f->stats.t_phase_ms[idx] += ms_since(t0);
+        f->stats.t_phase_ms[idx] += std::chrono::duration<double, std::milli>(now() - t0).count();
     };
 
     for (int lvl = 0; lvl <= f->L; ++lvl) {
         const bool root = (lvl == f->L);
         LevelDev& LD = f->lev[lvl];
-        LevelPlan& P = LD.plan;
+        LD.root = root;
+        LevelPlan& P = hc.plan(lvl);
+        const LevelPlan* prevP = lvl > 0 ? &hc.plan(lvl - 1) : nullptr;
         const LevelDev* prev = lvl > 0 ? &f->lev[lvl - 1] : nullptr;
+
+        // ---- plan and upload the cell half ----
         auto t0 = now();
-        build_level(g, lvl, leaf, root, active, prev ? &prev->plan : nullptr, scr, kApplyCap, P);
-        validate_level(P, prev ? &prev->plan : nullptr, d);
+        build_cells(g, lvl, leaf, root, active, prevP, scr, kApplyCap, P);
+        validate_cells(P, prevP, d);
+        if (P.max_nf > 16 * kPotrfMaxTiles) fail(RHIF_ENOMEM, "a frontal matrix is too large for this version");
         f->stats.n_active[lvl] = static_cast<int64_t>(active.size());
         f->stats.n_cells[lvl] = P.ncells;
         f->stats.max_front[lvl] = P.max_nf;
-
-        Packer pk;
-        const size_t o_cdofs = pk.add(P.c_dofs), o_cref = pk.add(P.cell_ref), o_potrf = pk.add(P.cell_potrf),
-                     o_tiles = pk.add(P.tiles), o_src = pk.add(P.src), o_sep = pk.add(P.sep_desc),
-                     o_cg = pk.add(P.cell_groups), o_cs = pk.add(P.cell_scale), o_skd = pk.add(P.skel_desc),
-                     o_rows = pk.add(P.skel_rows), o_cad = pk.add(P.cell_apply), o_sad = pk.add(P.sep_apply),
-                     o_gat = pk.add(P.gather), o_sdofs = pk.add(P.sep_dofs);
-        upload(f, pk, LD.tab, s);
-        char* T = LD.tab;
-        LD.cdofs = view<int32_t>(T, o_cdofs);
-        LD.cref = view<CellRef>(T, o_cref);
-        LD.potrf = view<FrontDesc>(T, o_potrf);
-        LD.tiles = view<Tile>(T, o_tiles);
-        LD.src = view<int32_t>(T, o_src);
-        LD.sep = view<SepDesc>(T, o_sep);
-        LD.cg = view<CellGroup>(T, o_cg);
-        LD.cs = view<CellScaleDesc>(T, o_cs);
-        LD.skd = view<SkelDesc>(T, o_skd);
-        LD.rows = view<int32_t>(T, o_rows);
-        LD.cell_ad = view<ApplyDesc>(T, o_cad);
-        LD.sep_ad = view<ApplyDesc>(T, o_sad);
-        LD.gat = view<GatherDesc>(T, o_gat);
-        LD.sepdofs = view<int32_t>(T, o_sdofs);
-        LD.lds_cell = apply_lds(P.cell_apply);
-        LD.lds_sep = apply_lds(P.sep_apply);
-
-        LD.front = static_cast<double*>(f->dalloc(P.front_elems * sizeof(double)));
-        if (!root) {
-            LD.lg = static_cast<double*>(f->dalloc(P.lg_elems * sizeof(double)));
-            LD.tp = static_cast<double*>(f->dalloc(P.t_elems * sizeof(double)));
-            LD.gp = static_cast<double*>(f->dalloc(P.g_elems * sizeof(double)));
-            if (P.m_elems > f->mp_elems) {
-                f->mp = static_cast<double*>(f->dalloc(P.m_elems * sizeof(double)));
-                f->mp_elems = P.m_elems;
-            }
-            const int64_t kp = static_cast<int64_t>(P.skel_desc.size()) + P.skel_ntotal + 1;
-            if (kp > f->kp_elems) {
-                f->kout = static_cast<int32_t*>(f->dalloc(kp * sizeof(int32_t)));
-                f->pout = static_cast<int32_t*>(f->dalloc(kp * sizeof(int32_t)));
-                f->kp_elems = kp;
-            }
+        {
+            Packer pk;
+            const size_t o_cdofs = pk.add(P.c_dofs), o_cref = pk.add(P.cell_ref), o_potrf = pk.add(P.cell_potrf),
+                         o_tiles = pk.add(P.tiles), o_src = pk.add(P.src), o_cad = pk.add(P.cell_apply);
+            char* T = upload(f, pk, s);
+            LD.cdofs = view<int32_t>(T, o_cdofs);
+            LD.cref = view<CellRef>(T, o_cref);
+            LD.potrf = view<FrontDesc>(T, o_potrf);
+            LD.tiles = view<Tile>(T, o_tiles);
+            LD.src = view<int32_t>(T, o_src);
+            LD.cell_ad = view<ApplyDesc>(T, o_cad);
         }
+        LD.n_cell_ad = static_cast<int>(P.cell_apply.size());
+        LD.lds_cell = apply_lds(P.cell_apply);
+        LD.b_cell = P.alg_apply_cell_bytes;
+        LD.front = static_cast<double*>(f->dalloc(P.front_elems * sizeof(double)));
+        LD.bytes = P.front_elems * 8;
         f->y_elems = std::max(f->y_elems, P.y_elems);
         f->ws_elems = std::max(f->ws_elems, P.ws_elems);
         phase(5, t0);
@@ -349,13 +431,19 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         // ---- frontal assembly ----
         t0 = now();
         if (!P.tiles.empty()) {
-            if (lvl == 0)
-                hipLaunchKernelGGL(k_front_csr, dim3(P.tiles.size()), dim3(256), 0, s, LD.tiles, LD.cref, LD.cdofs, d,
-                                   g.s, P.w, P.nc1, f->rp, f->ci, f->val, LD.front);
-            else
-                hipLaunchKernelGGL(k_front_extend, dim3(P.tiles.size()), dim3(256), 0, s, LD.tiles, LD.cref, LD.src, W,
-                                   prev->cref, prev->front, LD.front);
-            HIPCHK(hipGetLastError());
+            if (lvl == 0) {
+                const double by = P.alg_front_bytes + 12.0 * f->nnz + 4.0 * (g.N + 1);
+                KTIMED(f, s, RHIF_K_FRONT_CSR, 0.0, by,
+                       hipLaunchKernelGGL(k_front_csr, dim3(P.tiles.size()), dim3(256), 0, s, LD.tiles, LD.cref,
+                                          LD.cdofs, d, g.s, P.w, P.nc1, f->rp, f->ci, f->val, LD.front));
+            } else {
+                double rd = 0.0;
+                for (int c = 0; c < prevP->ncells; ++c)
+                    rd += 8.0 * static_cast<double>(prevP->c_nB[c]) * prevP->c_nB[c];
+                KTIMED(f, s, RHIF_K_FRONT_EXTEND, 0.0, P.alg_front_bytes + rd,
+                       hipLaunchKernelGGL(k_front_extend, dim3(P.tiles.size()), dim3(256), 0, s, LD.tiles, LD.cref,
+                                          LD.src, W, prev->cref, prev->front, LD.front));
+            }
         }
         phase(0, t0);
 
@@ -365,25 +453,78 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             int nmax = 0;
             for (const auto& fd : P.cell_potrf) nmax = std::max(nmax, fd.n - std::min(fd.n, 1));
             const int cap = panel_cap_for(nmax, 0);
-            hipLaunchKernelGGL(k_potrf_batch, dim3(P.cell_potrf.size()), dim3(256), potrf_lds(cap, 0), s, LD.potrf,
-                               LD.front, cap, lvl, root ? 3 : 0, f->err);
-            HIPCHK(hipGetLastError());
-            f->stats.flops[lvl] += P.flops;
+            const int cls = root ? RHIF_K_ROOT : (lvl == 0 ? RHIF_K_ELIM_LEAF : RHIF_K_ELIM_UPPER);
+            KTIMED(f, s, cls, P.alg_elim_flops, 0.0,
+                   hipLaunchKernelGGL(k_potrf_batch, dim3(P.cell_potrf.size()), dim3(256), potrf_lds(cap, 0), s,
+                                      LD.potrf, LD.front, cap, lvl, root ? 3 : 0, f->err));
         }
         phase(root ? 6 : 1, t0);
-        if (root) break;
+        if (root) {
+            f->stats.flops[lvl] += P.flops;
+            break;
+        }
+
+        // ---- plan and upload the separator half (overlaps the elimination) ----
+        t0 = now();
+        build_separators(g, scr, kApplyCap, P);
+        validate_separators(P);
+        f->stats.flops[lvl] += P.flops;
+        {
+            Packer pk;
+            const size_t o_sep = pk.add(P.sep_desc), o_cg = pk.add(P.cell_groups), o_cs = pk.add(P.cell_scale),
+                         o_skd = pk.add(P.skel_desc), o_rows = pk.add(P.skel_rows), o_sad = pk.add(P.sep_apply),
+                         o_gat = pk.add(P.gather), o_sdofs = pk.add(P.sep_dofs);
+            char* T = upload(f, pk, s);
+            LD.sep = view<SepDesc>(T, o_sep);
+            LD.cg = view<CellGroup>(T, o_cg);
+            LD.cs = view<CellScaleDesc>(T, o_cs);
+            LD.skd = view<SkelDesc>(T, o_skd);
+            LD.rows = view<int32_t>(T, o_rows);
+            LD.sep_ad = view<ApplyDesc>(T, o_sad);
+            LD.gat = view<GatherDesc>(T, o_gat);
+            LD.sepdofs = view<int32_t>(T, o_sdofs);
+        }
+        LD.n_sep_ad = static_cast<int>(P.sep_apply.size());
+        LD.n_gather = static_cast<int>(P.gather.size());
+        LD.lds_sep = apply_lds(P.sep_apply);
+        LD.b_sep = P.alg_apply_sep_bytes;
+        LD.b_gather = P.alg_gather_bytes;
+        f->ws_elems = std::max(f->ws_elems, P.ws_elems);
+        LD.lg = static_cast<double*>(f->dalloc(P.lg_elems * sizeof(double)));
+        LD.tp = static_cast<double*>(f->dalloc(P.t_elems * sizeof(double)));
+        LD.gp = static_cast<double*>(f->dalloc(P.g_elems * sizeof(double)));
+        LD.bytes += (P.lg_elems + P.t_elems + P.g_elems) * 8;
+        if (P.m_elems > f->mp_elems) {
+            f->mp = static_cast<double*>(f->dalloc(P.m_elems * sizeof(double)));
+            f->mp_elems = P.m_elems;
+        }
+        const int nsk = static_cast<int>(P.skel_desc.size());
+        const int64_t kp = static_cast<int64_t>(nsk) + P.skel_ntotal + 1;
+        if (kp > f->kp_elems) {
+            f->kout = static_cast<int32_t*>(f->dalloc(kp * sizeof(int32_t)));
+            f->pout = static_cast<int32_t*>(f->dalloc(kp * sizeof(int32_t)));
+            f->kp_elems = kp;
+        }
+        phase(5, t0);
 
         // ---- block Jacobi (C_l) ----
         t0 = now();
         if (f->o.precond && !P.sep_desc.empty()) {
             const int cap = panel_cap_for(P.max_sep_n, 0);
-            hipLaunchKernelGGL(k_precond_groups, dim3(P.sep_desc.size()), dim3(256), potrf_lds(cap, 0), s, LD.sep,
-                               LD.cref, LD.front, LD.lg, cap, lvl, f->err);
-            HIPCHK(hipGetLastError());
-            if (!P.cell_scale.empty()) {
-                hipLaunchKernelGGL(k_precond_scale, dim3(P.cell_scale.size()), dim3(256), 0, s, LD.cs, LD.cg, LD.lg,
-                                   LD.front);
-                HIPCHK(hipGetLastError());
+            KTIMED(f, s, RHIF_K_PRECOND_CHOL, P.alg_prec_chol_flops, 0.0,
+                   hipLaunchKernelGGL(k_precond_groups, dim3(P.sep_desc.size()), dim3(256), potrf_lds(cap, 0), s,
+                                      LD.sep, LD.cref, LD.front, LD.lg, cap, lvl, f->err));
+            if (!P.cell_groups.empty()) {
+                int need = 0;
+                for (const auto& cgr : P.cell_groups) {
+                    const int nB = P.cell_scale[cgr.cell].nB;
+                    need = std::max(need, nB * cgr.n + cgr.n * cgr.n);
+                }
+                const int cap2 = std::min(need, kLdsMaxDoubles);
+                KTIMED(f, s, RHIF_K_PRECOND_SCALE, P.alg_prec_scale_flops, 0.0,
+                       hipLaunchKernelGGL(k_precond_scale, dim3(P.cell_groups.size()), dim3(256),
+                                          static_cast<size_t>(cap2) * sizeof(double), s, LD.cs, LD.cg, LD.lg,
+                                          LD.front, cap2));
             }
         }
         f->stats.n_groups[lvl] = f->o.precond ? static_cast<int32_t>(P.sep_desc.size()) : 0;
@@ -391,32 +532,41 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
 
         // ---- skeletonization (K_l) ----
         t0 = now();
-        const int nsk = static_cast<int>(P.skel_desc.size());
-        Pinned& pn = pinned();
-        std::unique_lock<std::mutex> lk(pn.mu);
         int32_t* hk = nullptr;
         int32_t* hp = nullptr;
         if (nsk > 0) {
             const int n = P.max_skel_n;
-            const int base = (n + 1) / 2 + 1;
-            const int cap = panel_cap_for(n, base + 2);
-            const size_t lds = std::max(static_cast<size_t>(base + n + 2) * sizeof(double), potrf_lds(cap, base));
-            hipLaunchKernelGGL(k_skeletonize, dim3(nsk), dim3(256), lds, s, LD.skd, LD.rows, LD.cref, LD.front, f->mp,
-                               LD.tp, LD.gp, f->o.eps, f->kout, f->pout, cap, lvl, f->err);
-            HIPCHK(hipGetLastError());
-            char* h = pn.get_down((nsk + P.skel_ntotal) * sizeof(int32_t) + 64);
+            int rmax = 1;
+            for (const auto& sk : P.skel_desc) rmax = std::max(rmax, sk.r);
+            const int base = (n + 1) / 2 + 1 + n + 2;
+            const int staged_need = base + rmax * n + n * n + kPotrfSmemFixed + 17 * n;
+            const int staged = staged_need <= kLdsMaxDoubles ? 1 : 0;
+            int cap;
+            size_t lds;
+            if (staged) {
+                cap = n;
+                lds = static_cast<size_t>(staged_need) * sizeof(double);
+            } else {
+                cap = panel_cap_for(n, base);
+                lds = potrf_lds(cap, base);
+            }
+            KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                   hipLaunchKernelGGL(k_skeletonize, dim3(nsk), dim3(256), lds, s, LD.skd, LD.rows, LD.cref, LD.front,
+                                      f->mp, LD.tp, LD.gp, f->o.eps, f->kout, f->pout, cap, staged, n, rmax, lvl,
+                                      f->err));
+            char* h = hc.get_down((nsk + P.skel_ntotal) * sizeof(int32_t) + 64);
             hk = reinterpret_cast<int32_t*>(h);
             hp = hk + nsk;
             HIPCHK(hipMemcpyAsync(hk, f->kout, nsk * sizeof(int32_t), hipMemcpyDeviceToHost, s));
             HIPCHK(hipMemcpyAsync(hp, f->pout, P.skel_ntotal * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         }
-        check_err(f, s);   // synchronizes: ranks are on the host now
+        check_err(f, s);   // synchronizes: the ranks are on the host now
         phase(3, t0);
 
+        // ---- skeleton apply tables and the next level's active unknowns ----
         t0 = now();
         LD.k.assign(hk, hk + nsk);
         LD.perm.assign(hp, hp + P.skel_ntotal);
-        lk.unlock();
         LD.first_dof.resize(nsk);
         LD.gsize.resize(nsk);
         int64_t sum_rank = 0;
@@ -434,16 +584,27 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         f->stats.max_rank[lvl] = max_rank;
         std::vector<ApplyDesc> sk_ad;
         std::vector<int32_t> sk_dofs;
-        double fl = 0.0;
-        finish_level(P, LD.k.data(), LD.perm.data(), kApplyCap, sk_ad, sk_dofs, f->ws_elems, active, next, scr, fl);
+        double fl = 0.0, sby = 0.0;
+        finish_level(P, LD.k.data(), LD.perm.data(), kApplyCap, sk_ad, sk_dofs, f->ws_elems, active, next, scr, fl,
+                     sby);
         validate_skel_apply(P, sk_ad, sk_dofs, g.N);
-        f->stats.flops[lvl] += P.flops + fl;
-        Packer pk2;
-        const size_t o_ad = pk2.add(sk_ad), o_dofs = pk2.add(sk_dofs);
-        upload(f, pk2, LD.tab2, s);
-        if (LD.tab2) {
-            LD.skel_ad = view<ApplyDesc>(LD.tab2, o_ad);
-            LD.skeldofs = view<int32_t>(LD.tab2, o_dofs);
+        LD.b_skel = sby;
+        f->stats.flops[lvl] += fl;
+        if (f->ktimes && nsk > 0) {
+            for (auto it = f->pend.rbegin(); it != f->pend.rend(); ++it)
+                if (it->cls == RHIF_K_SKELETONIZE) {
+                    it->fl = fl;
+                    break;
+                }
+        }
+        {
+            Packer pk;
+            const size_t o_ad = pk.add(sk_ad), o_dofs = pk.add(sk_dofs);
+            char* T = upload(f, pk, s);
+            if (T) {
+                LD.skel_ad = view<ApplyDesc>(T, o_ad);
+                LD.skeldofs = view<int32_t>(T, o_dofs);
+            }
         }
         LD.n_skel_ad = static_cast<int>(sk_ad.size());
         LD.lds_skel = apply_lds(sk_ad);
@@ -457,60 +618,55 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
     f->ybuf = static_cast<double*>(f->dalloc(std::max<int64_t>(f->y_elems, 1) * sizeof(double)));
     if (f->ws_elems > 0) f->ws = static_cast<double*>(f->dalloc(f->ws_elems * sizeof(double)));
     int64_t bytes = 0;
-    for (const auto& LD : f->lev) {
-        const auto& P = LD.plan;
-        bytes += (P.front_elems + (P.root ? 0 : P.lg_elems + P.t_elems + P.g_elems)) * 8;
-    }
+    for (const auto& LD : f->lev) bytes += LD.bytes;
     f->stats.factor_bytes = bytes;
     HIPCHK(hipStreamSynchronize(s));
+    f->resolve();
 }
 
-void launch_up(const rhif::ApplyDesc* ad, int n, size_t lds, const double* pool, const double* tp,
-               const int32_t* dofs, double* z, double* ybuf, double* ws, hipStream_t s) {
+void launch_up(rhif_factor_s* f, double by, const rhif::ApplyDesc* ad, int n, size_t lds, const double* pool,
+               const double* tp, const int32_t* dofs, double* z, double* ybuf, double* ws, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(rhif::k_apply_up, dim3(n), dim3(256), lds, s, ad, pool, tp, dofs, z, ybuf, ws);
+    KTIMED(f, s, RHIF_K_APPLY_UP, 0.0, by,
+           hipLaunchKernelGGL(rhif::k_apply_up, dim3(n), dim3(256), lds, s, ad, pool, tp, dofs, z, ybuf, ws));
 }
 
-void launch_down(const rhif::ApplyDesc* ad, int n, size_t lds, const double* pool, const double* tp,
-                 const int32_t* dofs, double* z, double* ws, hipStream_t s) {
+void launch_down(rhif_factor_s* f, double by, const rhif::ApplyDesc* ad, int n, size_t lds, const double* pool,
+                 const double* tp, const int32_t* dofs, double* z, double* ws, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(rhif::k_apply_down, dim3(n), dim3(256), lds, s, ad, pool, tp, dofs, z, ws);
+    KTIMED(f, s, RHIF_K_APPLY_DOWN, 0.0, by,
+           hipLaunchKernelGGL(rhif::k_apply_down, dim3(n), dim3(256), lds, s, ad, pool, tp, dofs, z, ws));
 }
 
 void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
     const int L = f->L;
     for (int lvl = 0; lvl < L; ++lvl) {
         LevelDev& LD = f->lev[lvl];
-        const auto& P = LD.plan;
-        launch_up(LD.cell_ad, static_cast<int>(P.cell_apply.size()), LD.lds_cell, LD.front, nullptr, LD.cdofs, z,
-                  f->ybuf, f->ws, s);
-        if (!P.gather.empty())
-            hipLaunchKernelGGL(rhif::k_sep_gather, dim3(P.gather.size()), dim3(256), 0, s, LD.gat, LD.sepdofs,
-                               f->ybuf, z);
+        launch_up(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.lds_cell, LD.front, nullptr, LD.cdofs, z, f->ybuf,
+                  f->ws, s);
+        if (LD.n_gather > 0)
+            KTIMED(f, s, RHIF_K_APPLY_GATHER, 0.0, LD.b_gather,
+                   hipLaunchKernelGGL(rhif::k_sep_gather, dim3(LD.n_gather), dim3(256), 0, s, LD.gat, LD.sepdofs,
+                                      f->ybuf, z));
         if (f->o.precond)
-            launch_up(LD.sep_ad, static_cast<int>(P.sep_apply.size()), LD.lds_sep, LD.lg, nullptr, LD.sepdofs, z,
-                      nullptr, f->ws, s);
-        launch_up(LD.skel_ad, LD.n_skel_ad, LD.lds_skel, LD.gp, LD.tp, LD.skeldofs, z, nullptr, f->ws, s);
+            launch_up(f, LD.b_sep, LD.sep_ad, LD.n_sep_ad, LD.lds_sep, LD.lg, nullptr, LD.sepdofs, z, nullptr, f->ws,
+                      s);
+        launch_up(f, LD.b_skel, LD.skel_ad, LD.n_skel_ad, LD.lds_skel, LD.gp, LD.tp, LD.skeldofs, z, nullptr, f->ws,
+                  s);
     }
     {
         LevelDev& LD = f->lev[L];
-        const auto& P = LD.plan;
-        launch_up(LD.cell_ad, static_cast<int>(P.cell_apply.size()), LD.lds_cell, LD.front, nullptr, LD.cdofs, z,
-                  f->ybuf, f->ws, s);
-        launch_down(LD.cell_ad, static_cast<int>(P.cell_apply.size()), LD.lds_cell, LD.front, nullptr, LD.cdofs, z,
-                    f->ws, s);
+        launch_up(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.lds_cell, LD.front, nullptr, LD.cdofs, z, f->ybuf,
+                  f->ws, s);
+        launch_down(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.lds_cell, LD.front, nullptr, LD.cdofs, z, f->ws, s);
     }
     for (int lvl = L - 1; lvl >= 0; --lvl) {
         LevelDev& LD = f->lev[lvl];
-        const auto& P = LD.plan;
-        launch_down(LD.skel_ad, LD.n_skel_ad, LD.lds_skel, LD.gp, LD.tp, LD.skeldofs, z, f->ws, s);
+        launch_down(f, LD.b_skel, LD.skel_ad, LD.n_skel_ad, LD.lds_skel, LD.gp, LD.tp, LD.skeldofs, z, f->ws, s);
         if (f->o.precond)
-            launch_down(LD.sep_ad, static_cast<int>(P.sep_apply.size()), LD.lds_sep, LD.lg, nullptr, LD.sepdofs, z,
-                        f->ws, s);
-        launch_down(LD.cell_ad, static_cast<int>(P.cell_apply.size()), LD.lds_cell, LD.front, nullptr, LD.cdofs, z,
-                    f->ws, s);
+            launch_down(f, LD.b_sep, LD.sep_ad, LD.n_sep_ad, LD.lds_sep, LD.lg, nullptr, LD.sepdofs, z, f->ws, s);
+        launch_down(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.lds_cell, LD.front, nullptr, LD.cdofs, z, f->ws, s);
     }
-    HIPCHK(hipGetLastError());
 }
 
 void ensure_pcg(rhif_factor_s* f) {
@@ -579,12 +735,12 @@ rhif_status rhif_assemble_fd(const rhif_grid* g, const double* a_cells, const do
         rp[i + 1] = rp[i] + cnt;
     }
     {
-        Pinned& pn = pinned();
-        std::lock_guard<std::mutex> lk(pn.mu);
-        char* h = pn.get_up((N + 1) * sizeof(int32_t));
+        HostCache& hc = host_cache();
+        int slot = 0;
+        char* h = hc.get_up((N + 1) * sizeof(int32_t), slot);
         std::memcpy(h, rp.data(), (N + 1) * sizeof(int32_t));
         HIPCHK(hipMemcpyAsync(row_ptr, h, (N + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
+        hc.fence(slot, s);
     }
     const double h = 1.0 / (sd + 1);
     const double inv_h2 = 1.0 / (h * h);
@@ -608,6 +764,7 @@ rhif_status rhif_factor(const rhif_grid* g, const rhif_opts* o, const int32_t* r
         if (o->precision != 0) fail(RHIF_EINVAL, "only precision 0 (FP64) is available");
         if (!row_ptr || !col || !val) fail(RHIF_EINVAL, "NULL CSR pointer");
         set_pool_threshold();
+        set_kernel_attributes();
         f = new rhif_factor_s();
         f->alloc_stream = s;
         f->g.d = g->dim;
@@ -615,6 +772,11 @@ rhif_status rhif_factor(const rhif_grid* g, const rhif_opts* o, const int32_t* r
         f->g.N = 1;
         for (int k = 0; k < g->dim; ++k) f->g.N *= g->n[0];
         f->o = *o;
+        f->ktimes = (o->flags & RHIF_FLAG_KERNEL_TIMES) != 0;
+        {
+            const uint32_t m = (static_cast<uint32_t>(o->flags) >> RHIF_KERNEL_MASK_SHIFT) & 0xffffu;
+            f->kmask = m ? m : 0xffffu;
+        }
         f->L = rhif::num_levels(f->g.s, o->leaf);
         if (f->L > RHIF_MAX_LEVELS) fail(RHIF_EINVAL, "too many levels");
         const auto t0 = std::chrono::steady_clock::now();
@@ -684,24 +846,22 @@ rhif_status rhif_pcg_solve(rhif_factor_t f, const double* rhs, double* u, double
     ensure_pcg(f);
     const int64_t N = f->g.N;
     const int gb = grid_for(N);
-    Pinned& pn = pinned();
-    double* hsc = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(pn.mu);
-        hsc = reinterpret_cast<double*>(pn.get_down(64));
-    }
+    double* hsc = reinterpret_cast<double*>(host_cache().get_down(64));
+    const double NB = 8.0 * static_cast<double>(N);
+    const double spmv_by = 12.0 * f->nnz + 4.0 * (N + 1) + 3.0 * NB;
+#define VEC(by, ...) KTIMED(f, s, RHIF_K_VECTOR, 0.0, (by), __VA_ARGS__)
     // r = f, u = 0, ||f||^2
-    hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, rhs, f->r);
-    hipLaunchKernelGGL(rhif::k_fill, dim3(gb), dim3(256), 0, s, N, 0.0, u);
-    hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, s, N, rhs, rhs, f->part);
-    hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(64), 0, s, f->part, gb, 0, f->sc, nullptr);
+    VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, rhs, f->r));
+    VEC(NB, hipLaunchKernelGGL(rhif::k_fill, dim3(gb), dim3(256), 0, s, N, 0.0, u));
+    VEC(NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, s, N, rhs, rhs, f->part));
+    VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, s, f->part, gb, 0, f->sc, nullptr));
     HIPCHK(hipMemcpyAsync(hsc, f->sc + 6, sizeof(double), hipMemcpyDeviceToHost, s));
     // z = F^-1 r, rho = r.z, p = z
-    hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, f->r, f->z);
+    VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, f->r, f->z));
     do_apply_inplace(f, f->z, s);
-    hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, s, N, f->r, f->z, f->part);
-    hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(64), 0, s, f->part, gb, 3, f->sc, nullptr);
-    hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, f->z, f->p);
+    VEC(2 * NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, s, N, f->r, f->z, f->part));
+    VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, s, f->part, gb, 3, f->sc, nullptr));
+    VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, f->z, f->p));
     HIPCHK(hipStreamSynchronize(s));
     const double ff = hsc[0];
     const double fnorm = std::sqrt(ff);
@@ -709,10 +869,13 @@ rhif_status rhif_pcg_solve(rhif_factor_t f, const double* rhs, double* u, double
     double rel = 0.0;
     bool conv = (ff == 0.0);
     while (!conv && it < maxit) {
-        hipLaunchKernelGGL(rhif::k_spmv_dot, dim3(gb), dim3(256), 0, s, N, f->rp, f->ci, f->val, f->p, f->q, f->part);
-        hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(64), 0, s, f->part, gb, 1, f->sc, nullptr);
-        hipLaunchKernelGGL(rhif::k_axpy2, dim3(gb), dim3(256), 0, s, N, f->sc, f->p, f->q, u, f->r, f->part);
-        hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(64), 0, s, f->part, gb, 2, f->sc, nullptr);
+        KTIMED(f, s, RHIF_K_SPMV, 2.0 * f->nnz + 2.0 * N, spmv_by,
+               hipLaunchKernelGGL(rhif::k_spmv_dot, dim3(gb), dim3(256), 0, s, N, f->rp, f->ci, f->val, f->p, f->q,
+                                  f->part));
+        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, s, f->part, gb, 1, f->sc, nullptr));
+        VEC(6 * NB, hipLaunchKernelGGL(rhif::k_axpy2, dim3(gb), dim3(256), 0, s, N, f->sc, f->p, f->q, u, f->r,
+                                       f->part));
+        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, s, f->part, gb, 2, f->sc, nullptr));
         HIPCHK(hipMemcpyAsync(hsc + 1, f->sc + 3, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         ++it;
@@ -721,12 +884,14 @@ rhif_status rhif_pcg_solve(rhif_factor_t f, const double* rhs, double* u, double
             conv = true;
             break;
         }
-        hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, f->r, f->z);
+        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, f->r, f->z));
         do_apply_inplace(f, f->z, s);
-        hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, s, N, f->r, f->z, f->part);
-        hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(64), 0, s, f->part, gb, 4, f->sc, nullptr);
-        hipLaunchKernelGGL(rhif::k_update_p, dim3(gb), dim3(256), 0, s, N, f->sc, f->z, f->p);
+        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, s, N, f->r, f->z, f->part));
+        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, s, f->part, gb, 4, f->sc, nullptr));
+        VEC(3 * NB, hipLaunchKernelGGL(rhif::k_update_p, dim3(gb), dim3(256), 0, s, N, f->sc, f->z, f->p));
     }
+#undef VEC
+    f->resolve();
     HIPCHK(hipGetLastError());
     if (iters) *iters = it;
     if (relres) *relres = rel;
@@ -737,6 +902,7 @@ rhif_status rhif_pcg_solve(rhif_factor_t f, const double* rhs, double* u, double
 rhif_status rhif_stats(rhif_factor_t f, rhif_stats_t* out) {
     API_BEGIN
     if (!f || !out) fail(RHIF_EINVAL, "NULL argument");
+    f->resolve();
     *out = f->stats;
     API_END
 }

@@ -19,6 +19,12 @@ RHIF_OK, RHIF_EINVAL, RHIF_ENOTSPD, RHIF_ENOMEM, RHIF_EDEVICE, RHIF_ENOCONV = ra
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOTSPD", 3: "ENOMEM", 4: "EDEVICE", 5: "ENOCONV"}
 MAX_LEVELS = 32
 FLAG_PHASE_TIMES = 1
+FLAG_KERNEL_TIMES = 2
+KERNEL_MASK_SHIFT = 8
+NUM_KCLASS = 16
+KCLASS_NAMES = ["front_csr", "front_extend", "elim_leaf", "elim_upper", "root", "precond_chol",
+                "precond_scale", "skeletonize", "apply_up", "apply_down", "apply_gather", "spmv",
+                "vector", "-", "-", "-"]
 
 # every function declared in include/rhif.h
 EXPORTED = ["rhif_fd_nnz", "rhif_assemble_fd", "rhif_factor", "rhif_apply", "rhif_pcg_solve",
@@ -64,7 +70,11 @@ class Stats(ctypes.Structure):
                 ("max_rank", ctypes.c_int32 * MAX_LEVELS),
                 ("flops", ctypes.c_double * (MAX_LEVELS + 1)),
                 ("t_total_ms", ctypes.c_double),
-                ("t_phase_ms", ctypes.c_double * 8)]
+                ("t_phase_ms", ctypes.c_double * 8),
+                ("kernel_ms", ctypes.c_double * NUM_KCLASS),
+                ("kernel_launches", ctypes.c_int64 * NUM_KCLASS),
+                ("kernel_flops", ctypes.c_double * NUM_KCLASS),
+                ("kernel_bytes", ctypes.c_double * NUM_KCLASS)]
 
 
 _lib = None
@@ -229,7 +239,10 @@ class Factor:
                     n_skel=list(s.n_skel[:L]), sum_skel_n=list(s.sum_skel_n[:L]),
                     sum_rank=list(s.sum_rank[:L]), max_rank=list(s.max_rank[:L]),
                     flops=list(s.flops[: L + 1]), t_total_ms=s.t_total_ms,
-                    t_phase_ms=list(s.t_phase_ms))
+                    t_phase_ms=list(s.t_phase_ms),
+                    kernels={KCLASS_NAMES[c]: dict(ms=s.kernel_ms[c], launches=s.kernel_launches[c],
+                                                   flops=s.kernel_flops[c], bytes=s.kernel_bytes[c])
+                             for c in range(NUM_KCLASS) if s.kernel_launches[c] > 0})
 
     def skeletons(self, level: int) -> Skeletons:
         ng = ctypes.c_int32()
