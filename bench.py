@@ -35,8 +35,8 @@ def _args():
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--side", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-side", type=int, default=256,
-                    help="side of the window of the same field timed with the CPU oracle")
+    ap.add_argument("--cpu-sample-side", type=int, default=512,
+                    help="side of the (corner) window of the same field timed with the CPU oracle")
     return ap.parse_args()
 
 
@@ -57,6 +57,7 @@ def cpu_baseline(P, sample_side: int):
     except Exception:
         threads = 1
     s = sample_side
+    what = "the full workload" if s == P.s else f"the {s}x{s} corner window of the same field"
     a = np.ascontiguousarray(P.a_cells[: s + 1, : s + 1])
     f = np.ascontiguousarray(P.f.reshape(P.s, P.s)[:s, :s]).ravel()
     A = O.assemble_fd(2, s, a, None)
@@ -66,7 +67,7 @@ def cpu_baseline(P, sample_side: int):
     res = O.pcg(A, f, lambda v: O.apply_inverse(F, v), 1e-12, 500)
     t2 = time.perf_counter()
     return {"value": s * s / (t2 - t0), "unit": "DOFs/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle factor+PCG on the {s}x{s} corner window of the same field "
+            "sample": f"oracle factor+PCG on {what} "
                       f"(N={s*s}, leaf {P.leaf}, eps {P.eps:g}); t_factor {t1-t0:.2f} s, "
                       f"t_pcg {t2-t1:.2f} s, {res.iters} iterations, host threads {threads} "
                       f"of {os.cpu_count()} cores"}
@@ -136,16 +137,19 @@ def main():
             kfl += kv["flops"]
             kby += kv["bytes"]
             kl += kv["launches"]
+    from paper_1808_01364_amd.prof_summary import CLASS_KERNEL, read_traffic
+    traffic = read_traffic(os.path.join(ROOT, "profiles", f"traffic_2d{P.s}_eps{P.eps:g}.txt"),
+                           CLASS_KERNEL.get(dom, ""))
     hbm_bound = dom in ("apply_up", "apply_down", "apply_gather", "spmv", "vector", "front_csr", "front_extend")
     if hbm_bound:
         achieved = kby / (kms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
     else:
         achieved = kfl / (kms * 1e-3) / 1e12
         roof = {"bound": "mfma" if dom.startswith("elim") or dom == "root" else "alu",
                 "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic}
     roof.update({"kernel": dom, "launches": kl, "avg_launch_us": 1e3 * kms / max(kl, 1),
                  "alg_per_launch": (kby if hbm_bound else kfl) / max(kl, 1),
                  "share_of_device_time_warmup": per_class[dom] / sum(per_class.values())})

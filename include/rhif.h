@@ -7,7 +7,7 @@
  * The library factors the SPD finite-difference matrix A of
  *     -div(a grad u) + b u = f   on (0,1)^d, d = 2 or 3, zero Dirichlet data
  * (the problem of Sec. 1, eqs. (1.1)-(1.2), discretized as in Sec. 3.1 / 3.2) into the
- * generalized Cholesky form F = G G^T of eq. (eqF), and applies F^-1 (eq. (eqAinv)) as
+ * generalized Cholesky form F = G G^T of eq. (3.3), and applies F^-1 (eq. (3.2)) as
  * the preconditioner of a CG solve (Sec. 4).
  *
  * Conventions shared by every entry point
@@ -70,6 +70,9 @@ typedef struct {
                                       caller's stream; accumulated in rhif_stats_t        */
 #define RHIF_KERNEL_MASK_SHIFT 8   /* flags bits 8..23: if any is set, time only the kernel
                                       classes whose bit (1 << class) is set               */
+#define RHIF_FLAG_LEAF_SUBLEVELS 4 /* eliminate the leaf interiors by nested dissection on
+                                      cells of width m/2^j >= 4 (exact; same F) instead of
+                                      one dense elimination per leaf                      */
 #define RHIF_MAX_LEVELS 32
 
 /* Kernel classes of rhif_stats_t.kernel_* */
@@ -90,10 +93,10 @@ enum {
     RHIF_NUM_KCLASS = 16
 };
 
-/* Host-side summary of a factorization. Level l in [0, levels) is a skeletonization
- * level; entry [levels] describes the root. */
+/* Host-side summary of a factorization. Per-level arrays are indexed by internal level
+ * (see `sublevels`); entry [levels] describes the root. */
 typedef struct {
-    int32_t levels;                          /* L                                        */
+    int32_t levels;                          /* internal levels (sublevels + L)          */
     int32_t root_size;                       /* |S_L|                                    */
     int64_t factor_bytes;                    /* device bytes held by the factor          */
     int64_t n_active[RHIF_MAX_LEVELS + 1];   /* |S_l| at the start of level l            */
@@ -114,6 +117,11 @@ typedef struct {
     int64_t kernel_launches[RHIF_NUM_KCLASS];
     double  kernel_flops[RHIF_NUM_KCLASS];   /* algorithmic flops of those launches      */
     double  kernel_bytes[RHIF_NUM_KCLASS];   /* algorithmic HBM bytes of those launches  */
+    int32_t sublevels;                       /* leaf sublevels: the per-level arrays above
+                                                are indexed by internal level, of which the
+                                                first `sublevels` eliminate the leaf
+                                                interiors by nested dissection and level
+                                                sublevels + l is skeletonization level l  */
 } rhif_stats_t;
 
 typedef struct rhif_factor_s *rhif_factor_t;
@@ -137,7 +145,7 @@ rhif_status rhif_assemble_fd(const rhif_grid *g, const double *a_cells, const do
  * preconditioned (Sec. 2.3, when precond = 1), and every edge (2D) / face (3D) is
  * skeletonized with a column-pivoted-QR interpolative decomposition at precision eps
  * (Sec. 2.2, all IDs of a level taken from the same matrix); the rest is factored
- * densely (root, eq. (eqF)).
+ * densely (root, eq. (3.3)).
  *  row_ptr, col, val [device] the CSR of A as produced by rhif_assemble_fd (entries may
  *            only couple grid neighbours); the handle keeps its own copy, so the caller
  *            may free these after the call returns.
@@ -151,7 +159,7 @@ rhif_status rhif_factor(const rhif_grid *g, const rhif_opts *o, const int32_t *r
 
 /* z = F^-1 r for nrhs right-hand sides stored one after another (column-major N x nrhs):
  * the up-sweep R_l^T = K_l^T C_l^T E_l^T for l = 0..L-1, the root solve, and the
- * down-sweep R_l = E_l C_l K_l for l = L-1..0 (eq. (eqAinv)).
+ * down-sweep R_l = E_l C_l K_l for l = L-1..0 (eq. (3.2)).
  *  r [device] input (not modified), z [device] output; r == z is allowed.
  * Stream-ordered, never synchronizes. Errors: EINVAL, EDEVICE. */
 rhif_status rhif_apply(rhif_factor_t f, const double *r, double *z, int32_t nrhs,

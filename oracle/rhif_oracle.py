@@ -13,11 +13,11 @@ be read against the paper directly:
 
 * assembly .................. eq. (1.1)-(1.2), 5-/7-point stencils of Sec. 3.1 / 3.2
 * DOF grouping .............. Sec. 3.1 (interior / edge / corner), Sec. 3.2 (+ faces)
-* cell elimination E_l ...... Sec. 2.1, eq. (V_schur) and the Schur complement after it
-* block Jacobi C_l .......... Sec. 2.3, eq. (jacobi-precond)
-* skeletonization K_l ....... Sec. 2.2 (ID, eq. (eq_T), redundant elimination), done
+* cell elimination E_l ...... Sec. 2.1, eq. (2.1) and the Schur complement after it
+* block Jacobi C_l .......... Sec. 2.3, eq. (2.3)
+* skeletonization K_l ....... Sec. 2.2 (ID, eq. (2.2), redundant elimination), done
                                "simultaneously": every ID first, then every Z and E
-* root and F^{-1} ........... Sec. 3.1, eqs. (eqA), (eqAinv), (eqF)
+* root and F^{-1} ........... Sec. 3.1, eqs. (3.1)-(3.3)
 * CG with F^{-1} ............ Sec. 4 (relative residual 1e-12)
 
 Readings where the paper leaves a choice open (each is restated where it is used):
@@ -311,7 +311,7 @@ def cpqr_id(M: np.ndarray, eps: float, forced: Optional[Tuple[int, np.ndarray]] 
 # ----------------------------------------------------------------------------------------
 
 @dataclass
-class CellFactor:            # one E_I (eq. V_schur): L = chol(A_II), W = L^-1 A_BI^T
+class CellFactor:            # one E_I (eq. (2.1)): L = chol(A_II), W = L^-1 A_BI^T
     I: np.ndarray
     B: np.ndarray
     L: np.ndarray
@@ -319,13 +319,13 @@ class CellFactor:            # one E_I (eq. V_schur): L = chol(A_II), W = L^-1 A
 
 
 @dataclass
-class GroupFactor:           # one C_I (eq. jacobi-precond): L_g = chol(A_gg)
+class GroupFactor:           # one C_I (eq. (2.3)): L_g = chol(A_gg)
     idx: np.ndarray
     L: np.ndarray
 
 
 @dataclass
-class SkelFactor:            # one K_I = Z_I E_Itilde (eq. eq_T and the elimination after it)
+class SkelFactor:            # one K_I = Z_I E_Itilde (eq. (2.2) and the elimination after it)
     key: tuple
     group: np.ndarray        # group DOFs, ascending
     hat: np.ndarray          # skeleton DOFs (pivot order)
@@ -437,7 +437,7 @@ def factor(A0: sp.csr_matrix, d: int, s: int, leaf: int, eps: float, precond: in
         active = np.flatnonzero(active_mask)
         groups, gclass = classify(coords, active, w)
 
-        # ---- (1) cell elimination: E_l = prod_i E_{I_i}  (Sec. 2.1, eq. V_schur) ----
+        # ---- (1) cell elimination: E_l = prod_i E_{I_i}  (Sec. 2.1, eq. (2.1)) ----
         upd_r, upd_c, upd_v = [], [], []
         for key in sorted(k for k in groups if gclass[k] == 0):
             I = groups[key]
@@ -502,7 +502,7 @@ def factor(A0: sp.csr_matrix, d: int, s: int, leaf: int, eps: float, precond: in
             Ahh = _sub(A, hat, hat)
             Aht = _sub(A, hat, tilde)                # A_{Ihat, Itilde}
             Att = _sub(A, tilde, tilde)
-            # A~ blocks after zeroing with Z = [[I, 0], [-T, I]] (eq. eq_T and below)
+            # A~ blocks after zeroing with Z = [[I, 0], [-T, I]] (eq. (2.2) and below)
             Att_t = Att - T.T @ Aht - Aht.T @ T + T.T @ Ahh @ T
             Aht_t = Aht - Ahh @ T
             Lt = chol(Att_t, lvl, "K", int(g[0]))
@@ -516,7 +516,7 @@ def factor(A0: sp.csr_matrix, d: int, s: int, leaf: int, eps: float, precond: in
         A = _keep_only(A, active_mask)               # drops A_{R, Itilde} and eliminated rows
         levels.append(lv)
 
-    # ---- root: A_L = B_L B_L^T on the remaining active DOFs (eq. eqF) ----
+    # ---- root: A_L = B_L B_L^T on the remaining active DOFs (eq. (3.3)) ----
     root = np.flatnonzero(active_mask)
     RL = chol(_sub(A, root, root), L, "root", int(root[0]) if len(root) else 0)
     return Factorization(d=d, s=s, leaf=leaf, eps=eps, precond=precond, L=L, N=N,
@@ -524,7 +524,7 @@ def factor(A0: sp.csr_matrix, d: int, s: int, leaf: int, eps: float, precond: in
 
 
 # ----------------------------------------------------------------------------------------
-# Apply F^-1 = R_0 ... R_{L-1} A_L^-1 R_{L-1}^T ... R_0^T,  R_l = E_l C_l K_l  (eq. eqAinv)
+# Apply F^-1 = R_0 ... R_{L-1} A_L^-1 R_{L-1}^T ... R_0^T,  R_l = E_l C_l K_l  (eq. (3.2))
 # ----------------------------------------------------------------------------------------
 
 def apply_inverse(F: Factorization, r: np.ndarray) -> np.ndarray:
@@ -533,7 +533,7 @@ def apply_inverse(F: Factorization, r: np.ndarray) -> np.ndarray:
     z = np.array(r, dtype=np.float64, copy=True)
     tri = sla.solve_triangular
     for lv in F.levels:
-        # E^T: z_I <- L^-1 z_I ; z_B <- z_B - W^T z_I   (E_I^T from eq. V_schur)
+        # E^T: z_I <- L^-1 z_I ; z_B <- z_B - W^T z_I   (E_I^T from eq. (2.1))
         for c in lv.cells:
             zi = tri(c.L, z[c.I], lower=True)
             z[c.I] = zi

@@ -19,6 +19,9 @@ struct FrontDesc {
     int32_t n;       // order
     int32_t p;       // number of leading pivots to eliminate (p <= n)
     int32_t id;      // block id reported on loss of positive definiteness
+    int32_t ext;     // >= 0: offset of ceil(p/16) ints receiving, for every 16-column panel
+                     // of L, the end of its nonzero rows below the diagonal (rows < p)
+    int32_t pad;
 };
 
 // Reference to a cell frontal of some level (for gathers from children / neighbours).
@@ -95,6 +98,8 @@ struct ApplyDesc {
     int32_t nI;
     int32_t nB;
     int32_t dofs;        // offset of nI interior then nB boundary unknowns (global indices)
+    int32_t ext;         // >= 0: per-panel nonzero row ends of L (see FrontDesc::ext)
+    int32_t pad;
 };
 
 // Gather of the up-sweep boundary contributions of the cells for one separator group.

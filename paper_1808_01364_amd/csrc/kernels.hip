@@ -20,6 +20,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kWG = 256;
 constexpr int kWaves = kWG / 64;
+constexpr int kSyrkBatch = 2;   // Schur tiles accumulated per wave at a time
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -38,131 +39,214 @@ __device__ __forceinline__ unsigned long long err_code(int level, int step, int 
 }
 
 // ---------------------------------------------------------------------------------------
-// Workgroup-collective partial Cholesky (right-looking, 16-column panels).
+// Workgroup-collective partial Cholesky (right-looking over the pivots, 16-column panels).
 //
 // On entry the lower triangle of the n x n matrix A (column-major, ld) holds the
 // symmetric matrix [[D, X^T], [X, S]] with D of order p. On exit
 //   A[0:p, 0:p]  = L  with D = L L^T                       (Sec. 2.1: L_I = chol(A_II))
 //   A[p:n, 0:p]  = X L^-T = W^T                             (W = L^-1 A_BI^T)
 //   A[p:n, p:n]  = S - W^T W, stored in full (both triangles)  (the Schur complement)
-// Trailing updates of every panel go through the FP64 matrix cores, one 16 x 16 tile per
-// wave at a time. A pivot <= 0 or NaN reports `code` (the smallest code wins) and the
-// factorization continues with pivot 1 so that every wave still finishes.
-// Row tiles of the panel that are exactly zero (structural zeros, e.g. outside the band of
-// a grid interior) are skipped in the trailing update: they contribute nothing.
+// The panel loop updates only the pivot columns (rows j1..n-1, columns j1..p-1); the
+// Schur complement is formed once at the end, S -= W^T W. Both products run on the FP64
+// matrix cores, one 16 x 16 tile per wave at a time. Row tiles of a panel that are exactly
+// zero (structural zeros, e.g. outside the band of a grid interior) are skipped. If ext is
+// given, ext[t] receives the end of the nonzero rows (< p) of panel t, for the apply.
+// A pivot <= 0 or NaN reports `code` (the smallest code wins) and the factorization
+// continues with pivot 1 so that every wave still finishes.
 // smem: kPotrfSmemFixed doubles (diagonal block and tile flags), then panel_cap*17
 // doubles for the panel.
 // ---------------------------------------------------------------------------------------
 __device__ void wg_potrf_partial(double* __restrict__ A, int ld, int n, int p, double* smem,
-                                 int panel_cap, unsigned long long* err, unsigned long long code) {
+                                 int panel_cap, unsigned long long* err, unsigned long long code,
+                                 int32_t* __restrict__ ext) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double* Ld = smem;
-    int* tnz = reinterpret_cast<int*>(smem + 16 * 17);     // kPotrfMaxTiles flags
+    double* Li = smem + 16 * 17;                           // inverse of the diagonal block
+    int* tnz = reinterpret_cast<int*>(smem + 2 * 16 * 17); // kPotrfMaxTiles flags
     double* Pl = smem + kPotrfSmemFixed;
     for (int j0 = 0; j0 < p; j0 += 16) {
         const int jb = min(16, p - j0);
         const int j1 = j0 + jb;
-        const int m = n - j1;
-        // (1) unblocked Cholesky of the diagonal block in the registers of wave 0:
-        //     lane i holds row i.
+        const int m = n - j1;       // rows below the diagonal block
+        const int mi = p - j1;      // pivot columns still to come
+        // (1) unblocked Cholesky of the diagonal block by wave 0 in LDS (lane i owns row i;
+        //     the LDS operations of one wave complete in order).
         if (wave == 0) {
-            double r[16];
-#pragma unroll
             for (int c = 0; c < 16; ++c)
-                r[c] = (lane < jb && c <= lane) ? A[(j0 + lane) + static_cast<size_t>(j0 + c) * ld] : 0.0;
-#pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                if (c < jb) {
-                    double dcc = __shfl(r[c], c, 64);
-                    if (!(dcc > 0.0) || !(dcc < INFINITY)) {
-                        if (lane == 0) report(err, code);
-                        dcc = 1.0;
+                if (lane < 16)
+                    Ld[lane * 17 + c] =
+                        (lane < jb && c <= lane) ? A[(j0 + lane) + static_cast<size_t>(j0 + c) * ld] : 0.0;
+            for (int c = 0; c < jb; ++c) {
+                double dcc = Ld[c * 17 + c];
+                if (!(dcc > 0.0) || !(dcc < INFINITY)) {
+                    if (lane == 0) report(err, code);
+                    dcc = 1.0;
+                }
+                const double lcc = sqrt(dcc);
+                double lic = 0.0;
+                if (lane > c && lane < jb) {
+                    lic = Ld[lane * 17 + c] / lcc;
+                    Ld[lane * 17 + c] = lic;
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (lane == c) Ld[c * 17 + c] = lcc;
+                if (lane > c && lane < jb)
+                    for (int q = c + 1; q <= lane; ++q) Ld[lane * 17 + q] -= lic * Ld[q * 17 + c];
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (lane < jb)
+                for (int c = 0; c <= lane; ++c) A[(j0 + lane) + static_cast<size_t>(j0 + c) * ld] = Ld[lane * 17 + c];
+            // inverse of the diagonal block, column j by lane j: Li = L_blk^-1 (lower)
+            if (lane < 16) {
+                const int j = lane;
+                for (int i = 0; i < 16; ++i) {
+                    double v = 0.0;
+                    if (j < jb && i < jb && i >= j) {
+                        v = (i == j) ? 1.0 : 0.0;
+                        for (int k = j; k < i; ++k) v -= Ld[i * 17 + k] * Li[k * 17 + j];
+                        v /= Ld[i * 17 + i];
                     }
-                    const double lcc = sqrt(dcc);
-                    if (lane == c) r[c] = lcc;
-                    else if (lane > c) r[c] = r[c] / lcc;
-#pragma unroll
-                    for (int q = c + 1; q < 16; ++q) {
-                        const double lqc = __shfl(r[c], q, 64);
-                        if (q < jb && lane >= q) r[q] -= r[c] * lqc;
-                    }
+                    Li[i * 17 + j] = v;
                 }
             }
-#pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                if (lane < jb && c <= lane) A[(j0 + lane) + static_cast<size_t>(j0 + c) * ld] = r[c];
-                if (lane < 16) Ld[lane * 17 + c] = (lane < jb && c <= lane) ? r[c] : 0.0;
-            }
         }
-        __syncthreads();
-        // (2) panel: rows below the block solve  x L_blk^T = a  (forward substitution).
+        // (2) panel: the rows below the diagonal block solve  x L_blk^T = a.
         const bool lds_panel = (m <= panel_cap);
         const int nt = (m + 15) >> 4;
         for (int e = tid; e < nt; e += kWG) tnz[e] = 0;
         __syncthreads();
-        for (int i = j1 + tid; i < n; i += kWG) {
-            double a[16];
+        // rows below the block become  P = A_panel L_blk^-T  (16-row tiles on the matrix
+        // cores; lane holds P[lane/16 + 4 q][lane % 16])
+        for (int ti = wave; ti < nt; ti += kWaves) {
+            const int ra = ti * 16 + (lane & 15);
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int c = 0; c < 16; ++c) a[c] = (c < jb) ? A[i + static_cast<size_t>(j0 + c) * ld] : 0.0;
-#pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                if (c < jb) {
-                    double v = a[c];
-#pragma unroll
-                    for (int q = 0; q < c; ++q) v -= a[q] * Ld[c * 17 + q];
-                    a[c] = v / Ld[c * 17 + c];
-                }
+            for (int kk = 0; kk < 16; kk += 4) {
+                const int k = kk + (lane >> 4);
+                const double av = (ra < m && k < jb) ? A[(j1 + ra) + static_cast<size_t>(j0 + k) * ld] : 0.0;
+                const double bv = Li[(lane & 15) * 17 + k];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
             }
+            const int c = lane & 15;
             bool nz = false;
 #pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                if (c < jb) A[i + static_cast<size_t>(j0 + c) * ld] = a[c];
-                if (lds_panel) Pl[(i - j1) * 17 + c] = (c < jb) ? a[c] : 0.0;
-                nz = nz || (c < jb && a[c] != 0.0);
+            for (int q = 0; q < 4; ++q) {
+                const int r = ti * 16 + (lane >> 4) + 4 * q;
+                if (r < m && c < jb) {
+                    A[(j1 + r) + static_cast<size_t>(j0 + c) * ld] = acc[q];
+                    nz = nz || acc[q] != 0.0;
+                }
+                if (lds_panel && r < m) Pl[r * 17 + c] = (c < jb) ? acc[q] : 0.0;
             }
-            if (nz) tnz[(i - j1) >> 4] = 1;
+            if (__any(nz) && lane == 0) tnz[ti] = 1;
         }
         __syncthreads();
-        // (3) trailing update of the lower triangle: A22 -= P P^T on the matrix cores,
-        //     over the pairs of nonzero row tiles only.
-        const int ntiles = nt * (nt + 1) / 2;
-        for (int t = wave; t < ntiles; t += kWaves) {
-            int ti = static_cast<int>((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-            while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-            while (ti * (ti + 1) / 2 > t) --ti;
-            const int tj = t - ti * (ti + 1) / 2;
-            if (!tnz[ti] || !tnz[tj]) continue;
+        if (ext != nullptr && tid == 0) {
+            int e = j1;
+            for (int t = 0; t < (mi + 15) / 16; ++t)
+                if (tnz[t]) e = min(p, j1 + 16 * (t + 1));
+            ext[j0 >> 4] = e;
+        }
+        // (3) update of the remaining pivot columns: A[j1:n, j1:p] -= P P[0:mi]^T (lower part)
+        const int nti = (mi + 15) >> 4;
+        for (int t = wave; t < nt * nti; t += kWaves) {
+            const int tj = t % nti, ti = t / nti;
+            if (ti < tj || !tnz[ti] || !tnz[tj]) continue;
             const int ra = ti * 16 + (lane & 15);
             const int rb = tj * 16 + (lane & 15);
             v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int kk = 0; kk < 16; kk += 4) {
                 const int k = kk + (lane >> 4);
-                double a = 0.0, b = 0.0;
+                double av = 0.0, bv = 0.0;
                 if (k < jb) {
                     if (lds_panel) {
-                        if (ra < m) a = Pl[ra * 17 + k];
-                        if (rb < m) b = Pl[rb * 17 + k];
+                        if (ra < m) av = Pl[ra * 17 + k];
+                        if (rb < m) bv = Pl[rb * 17 + k];
                     } else {
-                        if (ra < m) a = A[(j1 + ra) + static_cast<size_t>(j0 + k) * ld];
-                        if (rb < m) b = A[(j1 + rb) + static_cast<size_t>(j0 + k) * ld];
+                        if (ra < m) av = A[(j1 + ra) + static_cast<size_t>(j0 + k) * ld];
+                        if (rb < m) bv = A[(j1 + rb) + static_cast<size_t>(j0 + k) * ld];
                     }
                 }
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
             }
             // lane holds D[lane/16 + 4 q][lane % 16], q = 0..3
             const int col = tj * 16 + (lane & 15);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int row = ti * 16 + (lane >> 4) + 4 * q;
-                if (row < m && col < m && row >= col)
+                if (row < m && col < mi && row >= col)
                     A[(j1 + row) + static_cast<size_t>(j1 + col) * ld] -= acc[q];
             }
         }
         __syncthreads();
     }
-    // the Schur complement in full
+    // (4) the Schur complement, S -= W^T W over the p pivots, lower tiles on the matrix cores.
+    //     16-column blocks of W^T are staged in LDS (when its rows fit the panel buffer);
+    //     every wave accumulates a batch of kSyrkBatch tiles over all pivots.
     const int ms = n - p;
+    const int nts = (ms + 15) >> 4;
+    const int ntl = nts * (nts + 1) / 2;
+    const bool lds_w = ms <= panel_cap;
+    for (int base = 0; base < ntl; base += kWaves * kSyrkBatch) {
+        v4d acc[kSyrkBatch];
+        int tiq[kSyrkBatch], tjq[kSyrkBatch];
+#pragma unroll
+        for (int q = 0; q < kSyrkBatch; ++q) {
+            acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+            const int t = base + wave * kSyrkBatch + q;
+            int ti = static_cast<int>((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+            while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+            while (ti * (ti + 1) / 2 > t) --ti;
+            tiq[q] = t < ntl ? ti : -1;
+            tjq[q] = t - ti * (ti + 1) / 2;
+        }
+        for (int k0 = 0; k0 < p; k0 += 16) {
+            const int kb = min(16, p - k0);
+            if (lds_w) {
+                __syncthreads();
+                for (int e = tid; e < ms * 16; e += kWG) {
+                    const int r = e % ms, c = e / ms;
+                    Pl[r * 17 + c] = (c < kb) ? A[(p + r) + static_cast<size_t>(k0 + c) * ld] : 0.0;
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int q = 0; q < kSyrkBatch; ++q) {
+                if (tiq[q] < 0) continue;
+                const int ra = tiq[q] * 16 + (lane & 15);
+                const int rb = tjq[q] * 16 + (lane & 15);
+#pragma unroll
+                for (int kk = 0; kk < 16; kk += 4) {
+                    const int k = kk + (lane >> 4);
+                    double av = 0.0, bv = 0.0;
+                    if (k < kb) {
+                        if (lds_w) {
+                            if (ra < ms) av = Pl[ra * 17 + k];
+                            if (rb < ms) bv = Pl[rb * 17 + k];
+                        } else {
+                            if (ra < ms) av = A[(p + ra) + static_cast<size_t>(k0 + k) * ld];
+                            if (rb < ms) bv = A[(p + rb) + static_cast<size_t>(k0 + k) * ld];
+                        }
+                    }
+                    acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kSyrkBatch; ++q) {
+            if (tiq[q] < 0) continue;
+            const int col = tjq[q] * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = tiq[q] * 16 + (lane >> 4) + 4 * r;
+                if (row < ms && col < ms && row >= col)
+                    A[(p + row) + static_cast<size_t>(p + col) * ld] -= acc[q][r];
+            }
+        }
+    }
+    __syncthreads();
+    // the Schur complement in full
     for (int e = tid; e < ms * ms; e += kWG) {
         const int i = e % ms, j = e / ms;
         if (i < j) A[(p + i) + static_cast<size_t>(p + j) * ld] = A[(p + j) + static_cast<size_t>(p + i) * ld];
@@ -449,10 +533,12 @@ __global__ __launch_bounds__(256) void k_front_extend(const Tile* __restrict__ t
 
 // Batched partial Cholesky of cell frontals (cell elimination, Sec. 2.1) or of the root.
 __global__ __launch_bounds__(256) void k_potrf_batch(const FrontDesc* __restrict__ desc, double* __restrict__ pool,
-                                                     int panel_cap, int level, int step, unsigned long long* err) {
+                                                     int panel_cap, int level, int step, unsigned long long* err,
+                                                     int32_t* __restrict__ ext) {
     extern __shared__ double smem[];
     const FrontDesc fd = desc[blockIdx.x];
-    wg_potrf_partial(pool + fd.off, fd.ld, fd.n, fd.p, smem, panel_cap, err, err_code(level, step, fd.id));
+    wg_potrf_partial(pool + fd.off, fd.ld, fd.n, fd.p, smem, panel_cap, err, err_code(level, step, fd.id),
+                     (ext != nullptr && fd.ext >= 0) ? ext + fd.ext : nullptr);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -476,7 +562,7 @@ __global__ __launch_bounds__(256) void k_precond_groups(const SepDesc* __restric
         L[e] = v;
     }
     __syncthreads();
-    wg_potrf_partial(L, n, n, n, smem, panel_cap, err, err_code(level, 1, blockIdx.x));
+    wg_potrf_partial(L, n, n, n, smem, panel_cap, err, err_code(level, 1, blockIdx.x), nullptr);
 }
 
 // Block-Jacobi step, part 2: every cell's share S of the separator matrix becomes
@@ -559,7 +645,7 @@ __global__ __launch_bounds__(256) void k_precond_scale(const CellScaleDesc* __re
 //   1. M = A[R_g, g]: the group's columns over the other boundary unknowns of its one or
 //      two cells, the shares of both cells added;
 //   2. ID by column-pivoted QR -> rank k, pivot order, T = R11^-1 R12;
-//   3. the zeroed blocks of eq. (eq_T) in the order (redundant, skeleton):
+//   3. the zeroed blocks of eq. (2.2) in the order (redundant, skeleton):
 //        G = [[A~_tt, A~_ht^T], [A~_ht, A_hh]] with
 //        A~_tt = A_tt - T^T A_ht - A_ht^T T + T^T A_hh T,  A~_ht = A_ht - A_hh T;
 //   4. partial Cholesky of G over the n-k redundant unknowns: L~, W~^T and the new
@@ -574,6 +660,7 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
                                                      double* __restrict__ Gpool, double eps, int32_t* __restrict__ kout,
                                                      int32_t* __restrict__ pout, int panel_cap, int staged, int nmax,
                                                      int rmax, int level, unsigned long long* err) {
+    // staged: bit 0 = M in LDS, bit 1 = G in LDS
     extern __shared__ double smem[];
     const SkelDesc g = sd[blockIdx.x];
     const int n = g.n, r = g.r;
@@ -583,9 +670,11 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
     double* nrm2 = smem + pd;
     double* red = nrm2 + nmax;
     double* after = red + 2;
-    double* M = staged ? after : Mpool + g.moff;
-    double* Gw = staged ? after + static_cast<size_t>(rmax) * nmax : Gpool + g.goff;
-    double* psmem = staged ? Gw + static_cast<size_t>(nmax) * nmax : after;
+    const bool stage_m = (staged & 1) != 0, stage_g = (staged & 2) != 0;
+    double* M = stage_m ? after : Mpool + g.moff;
+    double* gl = stage_m ? after + static_cast<size_t>(rmax) * nmax : after;
+    double* Gw = stage_g ? gl : Gpool + g.goff;
+    double* psmem = stage_g ? gl + static_cast<size_t>(nmax) * nmax : gl;
     const int32_t* rw = rows + static_cast<size_t>(g.rows) * 2;
     const CellRef c0 = cells[g.cell[0]];
     CellRef c1 = c0;
@@ -652,12 +741,12 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
     }
     __syncthreads();
     // 4. eliminate the redundant unknowns
-    wg_potrf_partial(Gw, n, n, nr, psmem, panel_cap, err, err_code(level, 2, blockIdx.x));
+    wg_potrf_partial(Gw, n, n, nr, psmem, panel_cap, err, err_code(level, 2, blockIdx.x), nullptr);
     // 5. write back the skeleton block (and keep G for the apply)
     double* Gout = Gpool + g.goff;
     for (int e = threadIdx.x; e < n * n; e += kWG) {
         const int a = e % n, b = e / n;
-        if (staged) Gout[e] = Gw[e];
+        if (stage_g) Gout[e] = Gw[e];
         if (a < k && b < k) {
             // skeleton a, b sit at positions perm[a], perm[b] of the group's ascending order
             F[c0.off + (g.off[0] + perm[a]) + static_cast<size_t>(g.off[0] + perm[b]) * c0.ld] =
@@ -668,13 +757,14 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
 }
 
 // ---------------------------------------------------------------------------------------
-// Factor apply (eq. (eqAinv)). One workgroup per block; z_I and z_B are staged in LDS (or
+// Factor apply (eq. (3.2)). One workgroup per block; z_I and z_B are staged in LDS (or
 // in a global workspace for oversized blocks). Triangular solves go by 32-row blocks: the
 // diagonal block is solved by one wave from LDS, the rest is a GEMV by all threads.
 // ---------------------------------------------------------------------------------------
 constexpr int kTB = 32;
 
-__device__ void wg_trsv_lower(const double* __restrict__ L, int ld, int n, double* z, double* Dg) {
+// ext (LDS, may be null): per 16-column panel of L, the end of its nonzero rows.
+__device__ void wg_trsv_lower(const double* __restrict__ L, int ld, int n, double* z, double* Dg, const int* ext) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int j0 = 0; j0 < n; j0 += kTB) {
         const int jb = min(kTB, n - j0);
@@ -693,7 +783,12 @@ __device__ void wg_trsv_lower(const double* __restrict__ L, int ld, int n, doubl
             if (lane < jb) z[j0 + lane] = x;
         }
         __syncthreads();
-        for (int i = j0 + jb + tid; i < n; i += kWG) {
+        int iend = n;
+        if (ext != nullptr) {
+            iend = ext[j0 >> 4];
+            if (jb > 16) iend = max(iend, ext[(j0 >> 4) + 1]);
+        }
+        for (int i = j0 + jb + tid; i < iend; i += kWG) {
             double acc = 0.0;
             for (int c = 0; c < jb; ++c) acc += L[i + static_cast<size_t>(j0 + c) * ld] * z[j0 + c];
             z[i] -= acc;
@@ -702,7 +797,7 @@ __device__ void wg_trsv_lower(const double* __restrict__ L, int ld, int n, doubl
     }
 }
 
-__device__ void wg_trsv_lower_t(const double* __restrict__ L, int ld, int n, double* z, double* Dg) {
+__device__ void wg_trsv_lower_t(const double* __restrict__ L, int ld, int n, double* z, double* Dg, const int* ext) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nblk = (n + kTB - 1) / kTB;
     for (int bi = nblk - 1; bi >= 0; --bi) {
@@ -724,6 +819,7 @@ __device__ void wg_trsv_lower_t(const double* __restrict__ L, int ld, int n, dou
         }
         __syncthreads();
         for (int i = tid; i < j0; i += kWG) {
+            if (ext != nullptr && ext[i >> 4] <= j0) continue;   // L[j0.., i] is zero
             double acc = 0.0;
             const double* Li = L + static_cast<size_t>(i) * ld + j0;
             for (int c = 0; c < jb; ++c) acc += Li[c] * z[j0 + c];
@@ -737,11 +833,16 @@ __device__ void wg_trsv_lower_t(const double* __restrict__ L, int ld, int n, dou
 __global__ __launch_bounds__(256) void k_apply_up(const ApplyDesc* __restrict__ ad, const double* __restrict__ pool,
                                                   const double* __restrict__ Tp, const int32_t* __restrict__ dofs,
                                                   double* __restrict__ z, double* __restrict__ ybuf,
-                                                  double* __restrict__ ws) {
+                                                  double* __restrict__ ws, const int32_t* __restrict__ extp) {
     extern __shared__ double smem[];
     const ApplyDesc d = ad[blockIdx.x];
     double* Dg = smem;
-    double* zI = (d.wsoff >= 0) ? ws + d.wsoff : smem + kTB * (kTB + 1);
+    int* ext = (extp != nullptr && d.ext >= 0 && (d.nI + 15) / 16 <= 2 * kApplyExtDoubles)
+                   ? reinterpret_cast<int*>(smem + kApplyDiagDoubles)
+                   : nullptr;
+    if (ext != nullptr)
+        for (int t = threadIdx.x; t < (d.nI + 15) / 16; t += kWG) ext[t] = extp[d.ext + t];
+    double* zI = (d.wsoff >= 0) ? ws + d.wsoff : smem + kApplyDiagDoubles + kApplyExtDoubles;
     double* zB = zI + d.nI;
     const int32_t* di = dofs + d.dofs;
     const int32_t* db = di + d.nI;
@@ -760,24 +861,47 @@ __global__ __launch_bounds__(256) void k_apply_up(const ApplyDesc* __restrict__ 
         __syncthreads();
     }
     const double* A = pool + d.off;
-    wg_trsv_lower(A, d.ld, d.nI, zI, Dg);
+    wg_trsv_lower(A, d.ld, d.nI, zI, Dg, ext);
     for (int i = threadIdx.x; i < d.nI; i += kWG) z[di[i]] = zI[i];
-    for (int b = threadIdx.x; b < d.nB; b += kWG) {
+    // y = W^T z_I: lanes run over 64 outputs, the 4 waves over quarters of the sum
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q0 = (d.nI * wave) / kWaves, q1 = (d.nI * (wave + 1)) / kWaves;
+    for (int b0 = 0; b0 < d.nB; b0 += 64) {
+        const int b = b0 + lane;
         double acc = 0.0;
-        for (int i = 0; i < d.nI; ++i) acc += A[(d.nI + b) + static_cast<size_t>(i) * d.ld] * zI[i];
-        if (d.yoff >= 0) ybuf[d.yoff + b] = acc;
-        else z[db[b]] = zB[b] - acc;
+        if (b < d.nB) {
+            const double* Wb = A + d.nI + b;
+            int i = q0;
+            for (; i + 3 < q1; i += 4)
+                acc += Wb[static_cast<size_t>(i) * d.ld] * zI[i] + Wb[static_cast<size_t>(i + 1) * d.ld] * zI[i + 1] +
+                       Wb[static_cast<size_t>(i + 2) * d.ld] * zI[i + 2] + Wb[static_cast<size_t>(i + 3) * d.ld] * zI[i + 3];
+            for (; i < q1; ++i) acc += Wb[static_cast<size_t>(i) * d.ld] * zI[i];
+        }
+        __syncthreads();
+        Dg[wave * 64 + lane] = acc;
+        __syncthreads();
+        if (wave == 0 && b < d.nB) {
+            const double y = Dg[lane] + Dg[64 + lane] + Dg[128 + lane] + Dg[192 + lane];
+            if (d.yoff >= 0) ybuf[d.yoff + b] = y;
+            else z[db[b]] = zB[b] - y;
+        }
     }
 }
 
 // Down-sweep block: z_I <- L^-T (z_I - W z_B); [z_B -= T z_I].
 __global__ __launch_bounds__(256) void k_apply_down(const ApplyDesc* __restrict__ ad, const double* __restrict__ pool,
                                                     const double* __restrict__ Tp, const int32_t* __restrict__ dofs,
-                                                    double* __restrict__ z, double* __restrict__ ws) {
+                                                    double* __restrict__ z, double* __restrict__ ws,
+                                                    const int32_t* __restrict__ extp) {
     extern __shared__ double smem[];
     const ApplyDesc d = ad[blockIdx.x];
     double* Dg = smem;
-    double* zI = (d.wsoff >= 0) ? ws + d.wsoff : smem + kTB * (kTB + 1);
+    int* ext = (extp != nullptr && d.ext >= 0 && (d.nI + 15) / 16 <= 2 * kApplyExtDoubles)
+                   ? reinterpret_cast<int*>(smem + kApplyDiagDoubles)
+                   : nullptr;
+    if (ext != nullptr)
+        for (int t = threadIdx.x; t < (d.nI + 15) / 16; t += kWG) ext[t] = extp[d.ext + t];
+    double* zI = (d.wsoff >= 0) ? ws + d.wsoff : smem + kApplyDiagDoubles + kApplyExtDoubles;
     double* zB = zI + d.nI;
     const int32_t* di = dofs + d.dofs;
     const int32_t* db = di + d.nI;
@@ -792,7 +916,7 @@ __global__ __launch_bounds__(256) void k_apply_down(const ApplyDesc* __restrict_
         zI[i] -= acc;
     }
     __syncthreads();
-    wg_trsv_lower_t(A, d.ld, d.nI, zI, Dg);
+    wg_trsv_lower_t(A, d.ld, d.nI, zI, Dg, ext);
     for (int i = threadIdx.x; i < d.nI; i += kWG) z[di[i]] = zI[i];
     if (d.toff >= 0) {
         const double* T = Tp + d.toff;

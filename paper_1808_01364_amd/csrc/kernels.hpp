@@ -15,7 +15,7 @@ __global__ void k_front_csr(const Tile* tiles, const CellRef* cells, const int32
 __global__ void k_front_extend(const Tile* tiles, const CellRef* cells, const int32_t* src, int W,
                                const CellRef* child, const double* Fc, double* F);
 __global__ void k_potrf_batch(const FrontDesc* desc, double* pool, int panel_cap, int level, int step,
-                              unsigned long long* err);
+                              unsigned long long* err, int32_t* ext);
 __global__ void k_precond_groups(const SepDesc* sd, const CellRef* cells, const double* F, double* Lg,
                                  int panel_cap, int level, unsigned long long* err);
 __global__ void k_precond_scale(const CellScaleDesc* cd, const CellGroup* cg, const double* Lg, double* F,
@@ -25,9 +25,9 @@ __global__ void k_skeletonize(const SkelDesc* sd, const int32_t* rows, const Cel
                               int32_t* pout, int panel_cap, int staged, int nmax, int rmax, int level,
                               unsigned long long* err);
 __global__ void k_apply_up(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
-                           double* z, double* ybuf, double* ws);
+                           double* z, double* ybuf, double* ws, const int32_t* ext);
 __global__ void k_apply_down(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
-                             double* z, double* ws);
+                             double* z, double* ws, const int32_t* ext);
 __global__ void k_sep_gather(const GatherDesc* gd, const int32_t* dofs, const double* ybuf, double* z);
 __global__ void k_spmv_dot(int64_t N, const int32_t* rp, const int32_t* ci, const double* v, const double* p,
                            double* q, double* part);
@@ -41,7 +41,8 @@ __global__ void k_fill(int64_t N, double v, double* y);
 __global__ void k_set_u64(unsigned long long* p, unsigned long long v);
 
 constexpr int kApplyDiagDoubles = 32 * 33;   // LDS diagonal block of the apply kernels
+constexpr int kApplyExtDoubles = 256;         // LDS panel extents (up to 512 ints, n_I <= 8192)
 constexpr int kPotrfMaxTiles = 1024;          // frontal order up to 16384
-constexpr int kPotrfSmemFixed = 16 * 17 + kPotrfMaxTiles / 2;   // doubles before the panel
+constexpr int kPotrfSmemFixed = 2 * 16 * 17 + kPotrfMaxTiles / 2;   // doubles before the panel
 
 }  // namespace rhif

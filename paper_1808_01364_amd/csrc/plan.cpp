@@ -42,6 +42,7 @@ void PlanScratch::reserve(int64_t N) {
 }
 
 void LevelPlan::reset() {
+    ext_elems = 0;
     level = w = nc1 = 0;
     root = false;
     for (auto* v : {&gptr, &gdofs, &gslot_cnt, &gslot_cell, &gslot_off, &c_nI, &c_nB, &c_nf, &c_ld, &c_dptr,
@@ -64,6 +65,13 @@ void LevelPlan::reset() {
     skel_ntotal = max_nf = max_sep_n = max_skel_n = 0;
     flops = alg_elim_flops = alg_prec_chol_flops = alg_prec_scale_flops = alg_front_bytes = 0.0;
     alg_apply_cell_bytes = alg_apply_sep_bytes = alg_gather_bytes = 0.0;
+}
+
+int inner_leaf(int d, int leaf) {
+    (void)d;
+    int w = leaf;
+    while (w % 2 == 0 && w / 2 >= 4) w /= 2;
+    return w;
 }
 
 int num_levels(int s, int leaf) {
@@ -244,14 +252,19 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
         const int nI = P.c_nI[ci], nB = P.c_nB[ci];
         P.alg_front_bytes += 8.0 * static_cast<double>(nf) * nf;
         if (nI > 0) {
-            P.cell_potrf.push_back(FrontDesc{P.c_foff[ci], P.c_ld[ci], nf, nI, static_cast<int32_t>(ci)});
+            P.cell_potrf.push_back(FrontDesc{P.c_foff[ci], P.c_ld[ci], nf, nI, static_cast<int32_t>(ci),
+                                             static_cast<int32_t>(P.ext_elems), 0});
+            P.ext_elems += (nI + 15) / 16;
             const double a = nI, b = nB;
             P.flops += a * a * a / 3.0 + a * a * b + a * b * b;
+            // a leaf interior (the whole (m-1)^d grid of a leaf cell) is banded with bandwidth
+            // (m-1)^(d-1) in natural order: the method needs only the banded work and words
             double lwords;
-            if (level == 0 && !root) {
-                double bw = 1.0;
-                for (int k = 1; k < d; ++k) bw *= (leaf - 1);
-                bw = std::min(bw, a);
+            double bw = 1.0;
+            for (int k = 1; k < d; ++k) bw *= (leaf - 1);
+            double leaf_int = 1.0;
+            for (int k = 0; k < d; ++k) leaf_int *= (leaf - 1);
+            if (level == 0 && !root && a == leaf_int && bw < a) {
                 P.alg_elim_flops += a * bw * bw + 2.0 * a * bw * b + b * b * a;
                 lwords = a * (bw + 1.0);
             } else {
@@ -298,10 +311,12 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
     int64_t yoff = 0, ws = 0;
     std::vector<int64_t>& cell_y = scr.cell_y;
     cell_y.assign(ncells, -1);
+    size_t next_potrf = 0;
     for (int64_t ci = 0; ci < ncells; ++ci) {
         const int nI = P.c_nI[ci], nB = P.c_nB[ci];
         if (nI == 0) continue;
         ApplyDesc ad{};
+        ad.ext = P.cell_potrf[next_potrf++].ext;
         ad.off = P.c_foff[ci];
         ad.toff = -1;
         ad.yoff = nB > 0 ? yoff : -1;
@@ -367,6 +382,7 @@ void build_separators(const GridInfo& gi, PlanScratch& scr, int lds_apply_cap, L
         P.gather.push_back(gd);
 
         ApplyDesc ad{};
+        ad.ext = -1;
         ad.off = sd.loff;
         ad.toff = -1;
         ad.yoff = -1;
@@ -505,6 +521,7 @@ void finish_level(const LevelPlan& P, const int32_t* k, const int32_t* perm, int
         if (kk == n) continue;
         skel_apply_bytes += 8.0 * (nr * (nr + 1.0) / 2.0 + 2.0 * kd * nr) + 8.0 * 2.0 * nd;
         ApplyDesc ad{};
+        ad.ext = -1;
         ad.off = sk.goff;
         ad.toff = (kk > 0) ? sk.toff : -1;
         ad.yoff = -1;
@@ -565,6 +582,7 @@ void validate_cells(const LevelPlan& P, const LevelPlan* prev, int d) {
         need(f.id >= 0 && f.id < P.ncells, "potrf id");
         const CellRef& r = P.cell_ref[f.id];
         need(f.off == r.off && f.ld == r.ld && f.n == r.nf && f.p >= 1 && f.p <= f.n, "potrf desc");
+        need(f.ext >= 0 && f.ext + (f.p + 15) / 16 <= P.ext_elems, "potrf ext bounds");
     }
     const int W = 1 << d;
     if (prev != nullptr) {
@@ -583,6 +601,7 @@ void validate_cells(const LevelPlan& P, const LevelPlan* prev, int d) {
         need(a.ld >= a.nI + a.nB, "cell apply ld");
         if (a.yoff >= 0) need(a.yoff + a.nB <= P.y_elems, "cell apply y bounds");
         if (a.wsoff >= 0) need(a.wsoff + a.nI + a.nB <= P.ws_elems, "cell apply ws bounds");
+        need(a.ext >= 0 && a.ext + (a.nI + 15) / 16 <= P.ext_elems, "cell apply ext bounds");
         ysum += a.nB;
     }
     need(ysum <= P.y_elems, "y scratch", ysum, P.y_elems);

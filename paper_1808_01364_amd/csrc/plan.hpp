@@ -65,6 +65,7 @@ struct LevelPlan {
     std::vector<GatherDesc> gather;
     std::vector<int32_t> sep_dofs;         // unknowns of every separator group
     int64_t lg_elems = 0, m_elems = 0, t_elems = 0, g_elems = 0, y_elems = 0;
+    int64_t ext_elems = 0;                 // per-panel nonzero row ends of the cells' L
     int64_t ws_elems = 0;                  // global workspace for oversized applies
     int32_t skel_ntotal = 0;               // sum of skeletonized group sizes
     int32_t max_nf = 0, max_sep_n = 0, max_skel_n = 0;
@@ -102,6 +103,13 @@ struct PlanScratch {
 
 // Number of skeletonization levels L: all l >= 0 with 2^l m <= s.
 int num_levels(int s, int leaf);
+
+// Width of the finest cells used to eliminate the leaf interiors. Eliminating a leaf cell's
+// interior is exact, and any elimination order gives the same Schur complement on its
+// boundary (Sec. 2.1); nested dissection inside the leaf (cells of width m/2^j >= 4, no
+// preconditioning or compression at those sublevels) replaces one dense elimination of
+// (m-1)^d unknowns by a few small ones.
+int inner_leaf(int d, int leaf);
 
 // Build the plan of `level` from its sorted active unknowns. `prev` is the plan of the
 // level below (nullptr at level 0) and is used for the extend-add source tables.

@@ -1,5 +1,5 @@
 // Host driver of the C ABI declared in include/rhif.h: the level loop of the factorization
-// (Sec. 3.1 / 3.2 of the paper), the factor apply (eq. (eqAinv)) and the PCG solve (Sec. 4).
+// (Sec. 3.1 / 3.2 of the paper), the factor apply (eq. (3.2)) and the PCG solve (Sec. 4).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,7 +40,7 @@ void hipcheck(hipError_t e, const char* what, int line) {
 
 constexpr int kLdsBudgetDoubles = 8192;      // 64 KiB of LDS per workgroup (default kernels)
 constexpr int kLdsMaxDoubles = 20480;        // 160 KiB: the gfx950 per-workgroup limit
-constexpr int kApplyCap = kLdsBudgetDoubles - rhif::kApplyDiagDoubles - 32;
+constexpr int kApplyCap = kLdsBudgetDoubles - rhif::kApplyDiagDoubles - rhif::kApplyExtDoubles - 32;
 constexpr int kRedBlocks = 1024;              // fixed partial-sum layout of the CG reductions
 
 // Per-thread host state reused across factorizations: pinned staging buffers for the
@@ -122,10 +122,13 @@ struct Packer {
 
 struct LevelDev {
     bool root = false;
+    bool exact = false;     // a leaf sublevel: elimination only
+    bool precond = false;   // block Jacobi applied at this level
     double* front = nullptr;
     double* lg = nullptr;
     double* tp = nullptr;
     double* gp = nullptr;
+    int32_t* ext = nullptr;    // per-panel nonzero row ends of the cells' L
     // device views into the uploaded tables
     int32_t* cdofs = nullptr;
     rhif::CellRef* cref = nullptr;
@@ -156,7 +159,7 @@ size_t apply_lds(const std::vector<rhif::ApplyDesc>& v) {
     int m = 0;
     for (const auto& d : v)
         if (d.wsoff < 0) m = std::max(m, d.nI + d.nB);
-    return static_cast<size_t>(rhif::kApplyDiagDoubles + m) * sizeof(double);
+    return static_cast<size_t>(rhif::kApplyDiagDoubles + rhif::kApplyExtDoubles + m) * sizeof(double);
 }
 
 int grid_for(int64_t N) {
@@ -169,7 +172,10 @@ int grid_for(int64_t N) {
 struct rhif_factor_s {
     rhif::GridInfo g;
     rhif_opts o{};
-    int L = 0;
+    int L = 0;        // internal levels: leaf sublevels (exact elimination) + skeletonization levels
+    int l0 = 0;       // leaf sublevels
+    int w0 = 0;       // width of the finest (sublevel) cells
+    int Lskel = 0;    // skeletonization levels of the paper's level loop
     int64_t nnz = 0;
     int32_t* rp = nullptr;
     int32_t* ci = nullptr;
@@ -311,12 +317,17 @@ void check_err(rhif_factor_s* f, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(&h, f->err, sizeof(h), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (h != ~0ull) {
-        const int level = static_cast<int>(h >> 40);
+        const int ilevel = static_cast<int>(h >> 40);
         const int step = static_cast<int>((h >> 32) & 0xff);
         const int block = static_cast<int>(h & 0xffffffffu);
         char buf[256];
-        std::snprintf(buf, sizeof(buf), "not SPD: Cholesky pivot <= 0 or not finite at level %d, step %s, block %d",
-                      level, step_name(step).c_str(), block);
+        if (step == 3 || ilevel >= f->l0)
+            std::snprintf(buf, sizeof(buf), "not SPD: Cholesky pivot <= 0 or not finite at level %d, step %s, block %d",
+                          step == 3 ? f->Lskel : ilevel - f->l0, step_name(step).c_str(), block);
+        else
+            std::snprintf(buf, sizeof(buf),
+                          "not SPD: Cholesky pivot <= 0 or not finite at level 0, step %s (leaf sublevel %d), "
+                          "block %d", step_name(step).c_str(), ilevel, block);
         fail(RHIF_ENOTSPD, buf);
     }
 }
@@ -363,7 +374,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
     const GridInfo& g = f->g;
     const int d = g.d;
     const int W = 1 << d;
-    const int leaf = f->o.leaf;
+    const int leaf = f->w0;
     f->nnz = fd_nnz(d, g.s);
     f->err = static_cast<unsigned long long*>(f->dalloc(sizeof(unsigned long long)));
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, f->err, ~0ull);
@@ -393,8 +404,11 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
 
     for (int lvl = 0; lvl <= f->L; ++lvl) {
         const bool root = (lvl == f->L);
+        const bool exact = !root && lvl < f->l0;
         LevelDev& LD = f->lev[lvl];
         LD.root = root;
+        LD.exact = exact;
+        LD.precond = f->o.precond && !exact;
         LevelPlan& P = hc.plan(lvl);
         const LevelPlan* prevP = lvl > 0 ? &hc.plan(lvl - 1) : nullptr;
         const LevelDev* prev = lvl > 0 ? &f->lev[lvl - 1] : nullptr;
@@ -423,7 +437,8 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         LD.lds_cell = apply_lds(P.cell_apply);
         LD.b_cell = P.alg_apply_cell_bytes;
         LD.front = static_cast<double*>(f->dalloc(P.front_elems * sizeof(double)));
-        LD.bytes = P.front_elems * 8;
+        LD.ext = static_cast<int32_t*>(f->dalloc(std::max<int64_t>(P.ext_elems, 1) * sizeof(int32_t)));
+        LD.bytes = P.front_elems * 8 + P.ext_elems * 4;
         f->y_elems = std::max(f->y_elems, P.y_elems);
         f->ws_elems = std::max(f->ws_elems, P.ws_elems);
         phase(5, t0);
@@ -456,7 +471,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             const int cls = root ? RHIF_K_ROOT : (lvl == 0 ? RHIF_K_ELIM_LEAF : RHIF_K_ELIM_UPPER);
             KTIMED(f, s, cls, P.alg_elim_flops, 0.0,
                    hipLaunchKernelGGL(k_potrf_batch, dim3(P.cell_potrf.size()), dim3(256), potrf_lds(cap, 0), s,
-                                      LD.potrf, LD.front, cap, lvl, root ? 3 : 0, f->err));
+                                      LD.potrf, LD.front, cap, lvl, root ? 3 : 0, f->err, LD.ext));
         }
         phase(root ? 6 : 1, t0);
         if (root) {
@@ -490,6 +505,25 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         LD.b_sep = P.alg_apply_sep_bytes;
         LD.b_gather = P.alg_gather_bytes;
         f->ws_elems = std::max(f->ws_elems, P.ws_elems);
+        const int nsk_all = static_cast<int>(P.skel_desc.size());
+        if (exact) {
+            // leaf sublevel: no preconditioning, no compression; every separator stays
+            std::vector<int32_t> kk(nsk_all), pp(P.skel_ntotal);
+            for (const auto& sk : P.skel_desc) {
+                kk[sk.gid] = sk.n;
+                for (int q = 0; q < sk.n; ++q) pp[sk.poff + q] = q;
+            }
+            std::vector<ApplyDesc> sk_ad;
+            std::vector<int32_t> sk_dofs;
+            double fl = 0.0, sby = 0.0;
+            finish_level(P, kk.data(), pp.data(), kApplyCap, sk_ad, sk_dofs, f->ws_elems, active, next, scr, fl,
+                         sby);
+            if (!sk_ad.empty()) fail(RHIF_EINVAL, "internal: a leaf sublevel produced skeleton blocks");
+            active.swap(next);
+            phase(5, t0);
+            continue;
+        }
+
         LD.lg = static_cast<double*>(f->dalloc(P.lg_elems * sizeof(double)));
         LD.tp = static_cast<double*>(f->dalloc(P.t_elems * sizeof(double)));
         LD.gp = static_cast<double*>(f->dalloc(P.g_elems * sizeof(double)));
@@ -498,7 +532,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             f->mp = static_cast<double*>(f->dalloc(P.m_elems * sizeof(double)));
             f->mp_elems = P.m_elems;
         }
-        const int nsk = static_cast<int>(P.skel_desc.size());
+        const int nsk = exact ? 0 : static_cast<int>(P.skel_desc.size());
         const int64_t kp = static_cast<int64_t>(nsk) + P.skel_ntotal + 1;
         if (kp > f->kp_elems) {
             f->kout = static_cast<int32_t*>(f->dalloc(kp * sizeof(int32_t)));
@@ -509,7 +543,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
 
         // ---- block Jacobi (C_l) ----
         t0 = now();
-        if (f->o.precond && !P.sep_desc.empty()) {
+        if (LD.precond && !P.sep_desc.empty()) {
             const int cap = panel_cap_for(P.max_sep_n, 0);
             KTIMED(f, s, RHIF_K_PRECOND_CHOL, P.alg_prec_chol_flops, 0.0,
                    hipLaunchKernelGGL(k_precond_groups, dim3(P.sep_desc.size()), dim3(256), potrf_lds(cap, 0), s,
@@ -527,7 +561,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                                           LD.front, cap2));
             }
         }
-        f->stats.n_groups[lvl] = f->o.precond ? static_cast<int32_t>(P.sep_desc.size()) : 0;
+        f->stats.n_groups[lvl] = LD.precond ? static_cast<int32_t>(P.sep_desc.size()) : 0;
         phase(2, t0);
 
         // ---- skeletonization (K_l) ----
@@ -539,13 +573,17 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             int rmax = 1;
             for (const auto& sk : P.skel_desc) rmax = std::max(rmax, sk.r);
             const int base = (n + 1) / 2 + 1 + n + 2;
-            const int staged_need = base + rmax * n + n * n + kPotrfSmemFixed + 17 * n;
-            const int staged = staged_need <= kLdsMaxDoubles ? 1 : 0;
-            int cap;
-            size_t lds;
-            if (staged) {
+            const int full = kPotrfSmemFixed + 17 * n;        // potrf scratch with the whole panel
+            int staged = 0, cap = 0;
+            size_t lds = 0;
+            if (base + rmax * n + n * n + full <= kLdsMaxDoubles) {
+                staged = 3;
                 cap = n;
-                lds = static_cast<size_t>(staged_need) * sizeof(double);
+                lds = static_cast<size_t>(base + rmax * n + n * n + full) * sizeof(double);
+            } else if (base + rmax * n + kPotrfSmemFixed <= kLdsMaxDoubles) {
+                staged = 1;
+                cap = std::min(n, (kLdsMaxDoubles - base - rmax * n - kPotrfSmemFixed) / 17);
+                lds = static_cast<size_t>(base + rmax * n + kPotrfSmemFixed + 17 * cap) * sizeof(double);
             } else {
                 cap = panel_cap_for(n, base);
                 lds = potrf_lds(cap, base);
@@ -625,17 +663,19 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
 }
 
 void launch_up(rhif_factor_s* f, double by, const rhif::ApplyDesc* ad, int n, size_t lds, const double* pool,
-               const double* tp, const int32_t* dofs, double* z, double* ybuf, double* ws, hipStream_t s) {
+               const double* tp, const int32_t* dofs, double* z, double* ybuf, double* ws, hipStream_t s,
+               const int32_t* ext = nullptr) {
     if (n <= 0) return;
     KTIMED(f, s, RHIF_K_APPLY_UP, 0.0, by,
-           hipLaunchKernelGGL(rhif::k_apply_up, dim3(n), dim3(256), lds, s, ad, pool, tp, dofs, z, ybuf, ws));
+           hipLaunchKernelGGL(rhif::k_apply_up, dim3(n), dim3(256), lds, s, ad, pool, tp, dofs, z, ybuf, ws, ext));
 }
 
 void launch_down(rhif_factor_s* f, double by, const rhif::ApplyDesc* ad, int n, size_t lds, const double* pool,
-                 const double* tp, const int32_t* dofs, double* z, double* ws, hipStream_t s) {
+                 const double* tp, const int32_t* dofs, double* z, double* ws, hipStream_t s,
+                 const int32_t* ext = nullptr) {
     if (n <= 0) return;
     KTIMED(f, s, RHIF_K_APPLY_DOWN, 0.0, by,
-           hipLaunchKernelGGL(rhif::k_apply_down, dim3(n), dim3(256), lds, s, ad, pool, tp, dofs, z, ws));
+           hipLaunchKernelGGL(rhif::k_apply_down, dim3(n), dim3(256), lds, s, ad, pool, tp, dofs, z, ws, ext));
 }
 
 void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
@@ -643,12 +683,12 @@ void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
     for (int lvl = 0; lvl < L; ++lvl) {
         LevelDev& LD = f->lev[lvl];
         launch_up(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.lds_cell, LD.front, nullptr, LD.cdofs, z, f->ybuf,
-                  f->ws, s);
+                  f->ws, s, LD.ext);
         if (LD.n_gather > 0)
             KTIMED(f, s, RHIF_K_APPLY_GATHER, 0.0, LD.b_gather,
                    hipLaunchKernelGGL(rhif::k_sep_gather, dim3(LD.n_gather), dim3(256), 0, s, LD.gat, LD.sepdofs,
                                       f->ybuf, z));
-        if (f->o.precond)
+        if (LD.precond)
             launch_up(f, LD.b_sep, LD.sep_ad, LD.n_sep_ad, LD.lds_sep, LD.lg, nullptr, LD.sepdofs, z, nullptr, f->ws,
                       s);
         launch_up(f, LD.b_skel, LD.skel_ad, LD.n_skel_ad, LD.lds_skel, LD.gp, LD.tp, LD.skeldofs, z, nullptr, f->ws,
@@ -657,15 +697,17 @@ void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
     {
         LevelDev& LD = f->lev[L];
         launch_up(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.lds_cell, LD.front, nullptr, LD.cdofs, z, f->ybuf,
-                  f->ws, s);
-        launch_down(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.lds_cell, LD.front, nullptr, LD.cdofs, z, f->ws, s);
+                  f->ws, s, LD.ext);
+        launch_down(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.lds_cell, LD.front, nullptr, LD.cdofs, z, f->ws, s,
+                    LD.ext);
     }
     for (int lvl = L - 1; lvl >= 0; --lvl) {
         LevelDev& LD = f->lev[lvl];
         launch_down(f, LD.b_skel, LD.skel_ad, LD.n_skel_ad, LD.lds_skel, LD.gp, LD.tp, LD.skeldofs, z, f->ws, s);
-        if (f->o.precond)
+        if (LD.precond)
             launch_down(f, LD.b_sep, LD.sep_ad, LD.n_sep_ad, LD.lds_sep, LD.lg, nullptr, LD.sepdofs, z, f->ws, s);
-        launch_down(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.lds_cell, LD.front, nullptr, LD.cdofs, z, f->ws, s);
+        launch_down(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.lds_cell, LD.front, nullptr, LD.cdofs, z, f->ws, s,
+                    LD.ext);
     }
 }
 
@@ -777,7 +819,12 @@ rhif_status rhif_factor(const rhif_grid* g, const rhif_opts* o, const int32_t* r
             const uint32_t m = (static_cast<uint32_t>(o->flags) >> RHIF_KERNEL_MASK_SHIFT) & 0xffffu;
             f->kmask = m ? m : 0xffffu;
         }
-        f->L = rhif::num_levels(f->g.s, o->leaf);
+        f->w0 = (o->flags & RHIF_FLAG_LEAF_SUBLEVELS) ? rhif::inner_leaf(f->g.d, o->leaf) : o->leaf;
+        f->l0 = 0;
+        while ((f->w0 << f->l0) < o->leaf) ++f->l0;
+        f->L = rhif::num_levels(f->g.s, f->w0);
+        f->Lskel = rhif::num_levels(f->g.s, o->leaf);
+        f->stats.sublevels = std::min(f->l0, f->L);
         if (f->L > RHIF_MAX_LEVELS) fail(RHIF_EINVAL, "too many levels");
         const auto t0 = std::chrono::steady_clock::now();
         do_factor(f, row_ptr, col, val, s);
@@ -911,8 +958,8 @@ rhif_status rhif_skeletons(rhif_factor_t f, int32_t level, int32_t* ngroups, int
                            int32_t* size, int32_t* rank, int32_t* perm) {
     API_BEGIN
     if (!f || !ngroups || !total) fail(RHIF_EINVAL, "NULL argument");
-    if (level < 0 || level >= f->L) fail(RHIF_EINVAL, "level out of range");
-    const LevelDev& LD = f->lev[level];
+    if (level < 0 || level >= f->Lskel) fail(RHIF_EINVAL, "level out of range");
+    const LevelDev& LD = f->lev[level + f->l0];
     *ngroups = static_cast<int32_t>(LD.k.size());
     *total = static_cast<int64_t>(LD.perm.size());
     if (first_dof) std::copy(LD.first_dof.begin(), LD.first_dof.end(), first_dof);

@@ -1,0 +1,105 @@
+"""Summaries of rocprofv3 output for profiles/ (short text files with the figures used).
+
+    python -m paper_1808_01364_amd.prof_summary stats  <run_kernel_stats.csv> <out.txt> "<command>"
+    python -m paper_1808_01364_amd.prof_summary traffic <fetch counter csv> <write counter csv> <out.txt> \
+        "<command>" [kernel ...]
+
+The traffic summary scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) by what the same
+counters read for the library's plain copy kernel (k_copy, 2 x 8 x N bytes per dispatch),
+and records the SHA-256 of the kernel source so that stale figures can be recognized.
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import hashlib
+import os
+import statistics
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hip")
+
+# kernel-class name used by bench.py -> device kernel
+CLASS_KERNEL = {"front_csr": "k_front_csr", "front_extend": "k_front_extend", "elim_leaf": "k_potrf_batch",
+                "elim_upper": "k_potrf_batch", "root": "k_potrf_batch", "precond_chol": "k_precond_groups",
+                "precond_scale": "k_precond_scale", "skeletonize": "k_skeletonize", "apply_up": "k_apply_up",
+                "apply_down": "k_apply_down", "apply_gather": "k_sep_gather", "spmv": "k_spmv_dot"}
+
+
+def kernel_source_sha() -> str:
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def _short(name: str) -> str:
+    return name.split("(")[0].replace("rhif::", "")
+
+
+def stats(csv_path: str, out: str, command: str, top: int = 20) -> None:
+    rows = list(csv.DictReader(open(csv_path)))
+    lines = [f"# rocprofv3 --kernel-trace --stats summary", f"command: {command}",
+             f"kernels_hip_sha256: {kernel_source_sha()}", "",
+             f"{'kernel':<28} {'calls':>6} {'total_us':>11} {'avg_us':>9} {'min_us':>9} {'max_us':>9} {'pct':>6}"]
+    for r in rows[:top]:
+        lines.append(f"{_short(r['Name'])[:28]:<28} {int(r['Calls']):>6} {float(r['TotalDurationNs'])/1e3:>11.1f} "
+                     f"{float(r['AverageNs'])/1e3:>9.2f} {float(r['MinNs'])/1e3:>9.2f} {float(r['MaxNs'])/1e3:>9.2f} "
+                     f"{float(r['Percentage']):>6.2f}")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
+def _counter(path: str, counter: str):
+    d = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name") == counter:
+            d[_short(r["Kernel_Name"])].append((float(r["Counter_Value"]), int(r["Grid_Size"])))
+    return d
+
+
+def traffic(fetch_csv: str, write_csv: str, out: str, command: str, kernels=None, N: int = 262144) -> None:
+    f = _counter(fetch_csv, "FETCH_SIZE")
+    w = _counter(write_csv, "WRITE_SIZE")
+    known_kib = 8.0 * N / 1024.0
+    fs = known_kib / statistics.mean(v for v, _ in f["k_copy"])
+    ws = known_kib / statistics.mean(v for v, _ in w["k_copy"])
+    kernels = kernels or sorted(f, key=lambda k: -sum(v for v, _ in f[k]))[:10]
+    lines = ["# HBM traffic per dispatch from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (two runs)",
+             f"command: {command}", f"kernels_hip_sha256: {kernel_source_sha()}",
+             f"copy_kernel: k_copy, {int(known_kib)} KiB read + {int(known_kib)} KiB written per dispatch",
+             f"copy_fetch_scale: {fs:.4f}", f"copy_write_scale: {ws:.4f}", "",
+             f"{'kernel':<22} {'dispatches':>10} {'fetch_KiB':>11} {'write_KiB':>11} {'traffic_bytes':>14}"]
+    for k in kernels:
+        if k not in f:
+            continue
+        fk = statistics.mean(v for v, _ in f[k])
+        wk = statistics.mean(v for v, _ in w.get(k, [(0.0, 0)]))
+        tb = 1024.0 * (fk * fs + wk * ws)
+        lines.append(f"{k:<22} {len(f[k]):>10} {fk:>11.1f} {wk:>11.1f} {tb:>14.0f}")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
+def read_traffic(path: str, kernel: str):
+    """Scaled bytes per dispatch of `kernel` from a traffic summary, or None if the summary is
+    missing, does not list the kernel, or was taken on other kernel source."""
+    if not os.path.exists(path):
+        return None
+    sha = None
+    for ln in open(path):
+        if ln.startswith("kernels_hip_sha256:"):
+            sha = ln.split(":", 1)[1].strip()
+        parts = ln.split()
+        if len(parts) == 5 and parts[0] == kernel:
+            if sha != kernel_source_sha():
+                return None
+            return float(parts[4])
+    return None
+
+
+if __name__ == "__main__":
+    mode = sys.argv[1]
+    if mode == "stats":
+        stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif mode == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6:] or None)
+    else:
+        raise SystemExit(__doc__)

@@ -21,6 +21,7 @@ MAX_LEVELS = 32
 FLAG_PHASE_TIMES = 1
 FLAG_KERNEL_TIMES = 2
 KERNEL_MASK_SHIFT = 8
+FLAG_LEAF_SUBLEVELS = 4
 NUM_KCLASS = 16
 KCLASS_NAMES = ["front_csr", "front_extend", "elim_leaf", "elim_upper", "root", "precond_chol",
                 "precond_scale", "skeletonize", "apply_up", "apply_down", "apply_gather", "spmv",
@@ -74,7 +75,8 @@ class Stats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double * NUM_KCLASS),
                 ("kernel_launches", ctypes.c_int64 * NUM_KCLASS),
                 ("kernel_flops", ctypes.c_double * NUM_KCLASS),
-                ("kernel_bytes", ctypes.c_double * NUM_KCLASS)]
+                ("kernel_bytes", ctypes.c_double * NUM_KCLASS),
+                ("sublevels", ctypes.c_int32)]
 
 
 _lib = None
@@ -233,7 +235,7 @@ class Factor:
         s = Stats()
         _check(self._lib.rhif_stats(self.handle, ctypes.byref(s)))
         L = s.levels
-        return dict(levels=L, root_size=s.root_size, factor_bytes=s.factor_bytes,
+        return dict(levels=L, sublevels=s.sublevels, root_size=s.root_size, factor_bytes=s.factor_bytes,
                     n_active=list(s.n_active[: L + 1]), n_cells=list(s.n_cells[: L + 1]),
                     max_front=list(s.max_front[: L + 1]), n_groups=list(s.n_groups[:L]),
                     n_skel=list(s.n_skel[:L]), sum_skel_n=list(s.sum_skel_n[:L]),

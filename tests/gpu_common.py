@@ -30,7 +30,8 @@ def gpu_factor(P, csr=None, eps=None, precond=None, flags=0):
 
 
 def gpu_choices(F, L):
-    """(level, smallest unknown) -> (k, pivot order) of every ID the GPU took."""
+    """(level, smallest unknown) -> (k, pivot order) of every ID the GPU took; L is the
+    number of skeletonization levels."""
     out = {}
     for lvl in range(L):
         sk = F.skeletons(lvl)

@@ -46,8 +46,9 @@ def test_eps0_apply_is_dense_solve(d, s, leaf, precond):
 def _parity(P, A, n_rhs=3, apply_tol=1e-11, sol_tol=1e-10, replay_ok=0.02):
     F = gpu_factor(P)
     st = F.stats()
-    ch = gpu_choices(F, st["levels"])
+    ch = gpu_choices(F, st["levels"] - st["sublevels"])
     orc = O.factor(A, P.d, P.s, P.leaf, P.eps, P.precond)
+    assert st["levels"] - st["sublevels"] == orc.L
     total, dr, ds = compare_choices(ch, orc)
     assert (dr + ds) <= replay_ok * max(total, 1), (total, dr, ds)
     # replay the GPU's discrete choices in the oracle

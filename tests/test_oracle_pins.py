@@ -184,8 +184,8 @@ def test_degenerate_tree_is_dense_cholesky():
 
 def _dense_R(F, lv, N):
     """R_l = E_l C_l K_l as dense N x N matrices built directly from the paper's
-    definitions: E_I from eq. (V_schur), C_I from eq. (jacobi-precond), K_I = Z_I E_Itilde
-    with Z_I from eq. (eq_T); E_l, C_l, K_l are the products over their index sets."""
+    definitions: E_I from eq. (2.1), C_I from eq. (2.3), K_I = Z_I E_Itilde
+    with Z_I from eq. (2.2); E_l, C_l, K_l are the products over their index sets."""
     def elim(I, B, L, W):
         Em = np.eye(N)
         Linv_T = sla.solve_triangular(L, np.eye(len(I)), lower=True).T      # L^-T
@@ -213,10 +213,10 @@ def _dense_R(F, lv, N):
 
 @pytest.mark.parametrize("d,s,leaf,eps,precond", [(2, 12, 3, 1e-2, 1), (2, 12, 3, 1e-2, 0), (3, 6, 2, 1e-2, 1)])
 def test_apply_equals_paper_operator_product(d, s, leaf, eps, precond):
-    """The sweep apply equals R_0 ... R_{L-1} A_L^-1 R_{L-1}^T ... R_0^T (eq. eqAinv) with
+    """The sweep apply equals R_0 ... R_{L-1} A_L^-1 R_{L-1}^T ... R_0^T (eq. (3.2)) with
     every R_l assembled densely from the paper's matrix definitions, and R^T A R equals
     the identity outside S_L and A_L = B_L B_L^T on S_L up to the dropped ID error
-    (eq. eqA). Catches a swapped sweep order, a missing transpose or a wrong T sign."""
+    (eq. (3.1)). Catches a swapped sweep order, a missing transpose or a wrong T sign."""
     P, A = _prob(d, s, leaf, eps, precond)
     F = O.factor(A, d, s, leaf, eps, precond)
     N = P.N
@@ -233,7 +233,7 @@ def test_apply_equals_paper_operator_product(d, s, leaf, eps, precond):
         r = rng.standard_normal(N)
         z = O.apply_inverse(F, r)
         assert np.linalg.norm(z - Finv @ r) <= 1e-10 * np.linalg.norm(z)
-    # eq. eqA: R^T A R ~ blockdiag(I, A_L) with an O(eps) defect in the scaled norm
+    # eq. (3.1): R^T A R ~ blockdiag(I, A_L) with an O(eps) defect in the scaled norm
     RAR = Rall.T @ A.toarray() @ Rall
     target = np.eye(N)
     target[np.ix_(root, root)] = F.root_L @ F.root_L.T
@@ -242,7 +242,7 @@ def test_apply_equals_paper_operator_product(d, s, leaf, eps, precond):
 
 
 def test_eps0_operator_product_is_exact():
-    """At eps = 0 the congruence R^T A R is exactly blockdiag(I, A_L) (eq. eqA)."""
+    """At eps = 0 the congruence R^T A R is exactly blockdiag(I, A_L) (eq. (3.1))."""
     P, A = _prob(2, 12, 3, 0.0, 1)
     F = O.factor(A, 2, 12, 3, 0.0, 1)
     Rall = np.eye(P.N)
@@ -277,7 +277,7 @@ def test_phif_skeleton_closed_form():
 
 def test_schur_complements_spd_and_Finv_symmetric():
     """Cell Schur complements stay SPD and F^-1 is symmetric positive definite
-    (generalized Cholesky, eq. eqF)."""
+    (generalized Cholesky, eq. (3.3))."""
     P, A = _prob(2, 24, 4, 1e-2, 1, lo=1e-2, hi=1e2)
     F = O.factor(A, 2, 24, 4, 1e-2, 1, check_spd=True)
     assert len(F.schur_min_eig) > 0 and min(F.schur_min_eig) > 0
