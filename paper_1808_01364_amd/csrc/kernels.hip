@@ -38,6 +38,44 @@ __device__ __forceinline__ unsigned long long err_code(int level, int step, int 
            static_cast<unsigned long long>(static_cast<uint32_t>(block));
 }
 
+// Broadcast of lane l's double (l uniform) through scalar registers.
+__device__ __forceinline__ double readlane_d(double x, int l) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(v), l);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(v >> 32), l);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Cholesky factorization and inversion of a 16 x 16 SPD block held by one wave in registers:
+// lane i < 16 holds row i in a[0..i]. On return a[c] = L[i][c] (c <= i) and li[r] =
+// (L^-1)[r][lane] for lane < 16. A pivot <= 0 or NaN reports `code` and continues with 1.
+__device__ __forceinline__ void wave_chol_inv16(double (&a)[16], double (&li)[16], int lane,
+                                                unsigned long long* err, unsigned long long code) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        double dcc = readlane_d(a[c], c);
+        if (!(dcc > 0.0) || !(dcc < INFINITY)) {
+            if (lane == 0) report(err, code);
+            dcc = 1.0;
+        }
+        const double lcc = sqrt(dcc);
+        const double lic = a[c] / lcc;
+        a[c] = (lane == c) ? lcc : (lane > c ? lic : a[c]);
+#pragma unroll
+        for (int q = c + 1; q < 16; ++q) {
+            const double lqc = readlane_d(a[c], q);
+            if (lane >= q) a[q] -= a[c] * lqc;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        double v = (lane == i) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) v -= readlane_d(a[k], i) * li[k];
+        li[i] = v / readlane_d(a[i], i);
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // Workgroup-collective partial Cholesky (right-looking over the pivots, 16-column panels).
 //
@@ -50,17 +88,18 @@ __device__ __forceinline__ unsigned long long err_code(int level, int step, int 
 // Schur complement is formed once at the end, S -= W^T W. Both products run on the FP64
 // matrix cores, one 16 x 16 tile per wave at a time. Row tiles of a panel that are exactly
 // zero (structural zeros, e.g. outside the band of a grid interior) are skipped. If ext is
-// given, ext[t] receives the end of the nonzero rows (< p) of panel t, for the apply.
+// given, ext[t] receives the end of the nonzero rows (< p) of panel t, for the apply; if
+// linv is given, linv[256 t + 16 i + j] receives the inverse of the t-th 16 x 16 diagonal
+// block of L (padded with the identity).
 // A pivot <= 0 or NaN reports `code` (the smallest code wins) and the factorization
 // continues with pivot 1 so that every wave still finishes.
 // smem: kPotrfSmemFixed doubles (diagonal block and tile flags), then panel_cap*17
 // doubles for the panel.
 // ---------------------------------------------------------------------------------------
-__device__ void wg_potrf_partial(double* __restrict__ A, int ld, int n, int p, double* smem,
-                                 int panel_cap, unsigned long long* err, unsigned long long code,
-                                 int32_t* __restrict__ ext) {
+__device__ __forceinline__ void wg_potrf_partial(double* __restrict__ A, int ld, int n, int p, double* smem,
+                                                 int panel_cap, unsigned long long* err, unsigned long long code,
+                                                 int32_t* __restrict__ ext, double* __restrict__ linv = nullptr) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double* Ld = smem;
     double* Li = smem + 16 * 17;                           // inverse of the diagonal block
     int* tnz = reinterpret_cast<int*>(smem + 2 * 16 * 17); // kPotrfMaxTiles flags
     double* Pl = smem + kPotrfSmemFixed;
@@ -69,44 +108,26 @@ __device__ void wg_potrf_partial(double* __restrict__ A, int ld, int n, int p, d
         const int j1 = j0 + jb;
         const int m = n - j1;       // rows below the diagonal block
         const int mi = p - j1;      // pivot columns still to come
-        // (1) unblocked Cholesky of the diagonal block by wave 0 in LDS (lane i owns row i;
-        //     the LDS operations of one wave complete in order).
+        // (1) the diagonal block is factored and inverted by wave 0 in registers (lane i < 16
+        //     holds row i of the block; rows jb..15 are padded with the identity).
         if (wave == 0) {
+            double a[16], li[16];
+#pragma unroll
             for (int c = 0; c < 16; ++c)
-                if (lane < 16)
-                    Ld[lane * 17 + c] =
-                        (lane < jb && c <= lane) ? A[(j0 + lane) + static_cast<size_t>(j0 + c) * ld] : 0.0;
-            for (int c = 0; c < jb; ++c) {
-                double dcc = Ld[c * 17 + c];
-                if (!(dcc > 0.0) || !(dcc < INFINITY)) {
-                    if (lane == 0) report(err, code);
-                    dcc = 1.0;
-                }
-                const double lcc = sqrt(dcc);
-                double lic = 0.0;
-                if (lane > c && lane < jb) {
-                    lic = Ld[lane * 17 + c] / lcc;
-                    Ld[lane * 17 + c] = lic;
-                }
-                __builtin_amdgcn_wave_barrier();
-                if (lane == c) Ld[c * 17 + c] = lcc;
-                if (lane > c && lane < jb)
-                    for (int q = c + 1; q <= lane; ++q) Ld[lane * 17 + q] -= lic * Ld[q * 17 + c];
-                __builtin_amdgcn_wave_barrier();
+                a[c] = (lane < jb && c <= lane) ? A[(j0 + lane) + static_cast<size_t>(j0 + c) * ld]
+                                                : (lane == c ? 1.0 : 0.0);
+            wave_chol_inv16(a, li, lane, err, code);
+            if (lane < jb) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+                    if (c <= lane) A[(j0 + lane) + static_cast<size_t>(j0 + c) * ld] = a[c];
             }
-            if (lane < jb)
-                for (int c = 0; c <= lane; ++c) A[(j0 + lane) + static_cast<size_t>(j0 + c) * ld] = Ld[lane * 17 + c];
-            // inverse of the diagonal block, column j by lane j: Li = L_blk^-1 (lower)
             if (lane < 16) {
-                const int j = lane;
-                for (int i = 0; i < 16; ++i) {
-                    double v = 0.0;
-                    if (j < jb && i < jb && i >= j) {
-                        v = (i == j) ? 1.0 : 0.0;
-                        for (int k = j; k < i; ++k) v -= Ld[i * 17 + k] * Li[k * 17 + j];
-                        v /= Ld[i * 17 + i];
-                    }
-                    Li[i * 17 + j] = v;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) Li[i * 17 + lane] = li[i];
+                if (linv != nullptr) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) linv[(j0 >> 4) * 256 + i * 16 + lane] = li[i];
                 }
             }
         }
@@ -539,6 +560,143 @@ __global__ __launch_bounds__(256) void k_potrf_batch(const FrontDesc* __restrict
     const FrontDesc fd = desc[blockIdx.x];
     wg_potrf_partial(pool + fd.off, fd.ld, fd.n, fd.p, smem, panel_cap, err, err_code(level, step, fd.id),
                      (ext != nullptr && fd.ext >= 0) ? ext + fd.ext : nullptr);
+}
+
+// ---------------------------------------------------------------------------------------
+// The cell elimination of eq. (2.1) in three launches, for levels with few cells (one
+// workgroup per cell would leave most of the chip idle and wait on memory latency):
+//   k_chol_lead:  A_II = L L^T, one workgroup per cell, A_II staged in LDS when it fits;
+//                 also stores the inverses of L's 16 x 16 diagonal blocks;
+//   k_trsm_rows:  W^T = A_BI L^-T, 16 rows per wave, independent across rows;
+//   k_syrk_schur: S = A_BB - W^T W on 32 x 32 blocks, both triangles written.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_chol_lead(const FrontDesc* __restrict__ desc, double* __restrict__ pool,
+                                                   double* __restrict__ linv, int lds_pmax, int level,
+                                                   unsigned long long* err, int32_t* __restrict__ ext) {
+    extern __shared__ double smem[];
+    const FrontDesc fd = desc[blockIdx.x];
+    const int p = fd.p, ld = fd.ld;
+    double* A = pool + fd.off;
+    double* lv = linv + static_cast<size_t>(fd.ext) * 256;
+    int32_t* ex = ext + fd.ext;
+    const unsigned long long code = err_code(level, 0, fd.id);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (p <= lds_pmax) {
+        const int ls = p | 1;
+        double* D = smem + kPotrfSmemFixed;
+        for (int j = wave; j < p; j += kWaves)
+            for (int i = j + lane; i < p; i += 64) D[i + j * ls] = A[i + static_cast<size_t>(j) * ld];
+        __syncthreads();
+        wg_potrf_partial(D, ls, p, p, smem, 0, err, code, ex, lv);
+        for (int j = wave; j < p; j += kWaves)
+            for (int i = j + lane; i < p; i += 64) A[i + static_cast<size_t>(j) * ld] = D[i + j * ls];
+    } else {
+        wg_potrf_partial(A, ld, p, p, smem, 0, err, code, ex, lv);
+    }
+}
+
+// Rows p.. of the cell: W^T = X L^-T by 16-column panels, P_j = (X_j - P_<j L_j,<j^T) Li_j^T
+// with Li_j the stored inverse of the j-th diagonal block. Wave w of block y owns rows
+// p + 16 (4 y + w) ..; its finished panels sit in LDS (pstride doubles per wave, k-major
+// with 17 rows per column). The waves never wait for each other.
+__global__ __launch_bounds__(256) void k_trsm_rows(const FrontDesc* __restrict__ desc, double* __restrict__ pool,
+                                                   const double* __restrict__ linv, int pstride) {
+    extern __shared__ double smem[];
+    const FrontDesc fd = desc[blockIdx.x];
+    const int p = fd.p, m = fd.n - fd.p, ld = fd.ld;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lh = lane >> 4;
+    const int r0 = (static_cast<int>(blockIdx.y) * kWaves + wave) * 16;
+    if (r0 >= m || p == 0) return;
+    double* A = pool + fd.off;
+    const double* lv = linv + static_cast<size_t>(fd.ext) * 256;
+    double* Pw = smem + static_cast<size_t>(wave) * pstride;
+    for (int j0 = 0; j0 < p; j0 += 16) {
+        const int jb = min(16, p - j0);
+        v4d acc;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = r0 + lh + 4 * q;
+            acc[q] = (r < m && lr < jb) ? A[(p + r) + static_cast<size_t>(j0 + lr) * ld] : 0.0;
+        }
+        // acc -= P[:, 0:j0] L[j0:j1, 0:j0]^T  (A operand -P[lr][k], B operand L[j0 + lr][k])
+#pragma unroll 4
+        for (int k0 = 0; k0 < j0; k0 += 4) {
+            const double av = -Pw[(k0 + lh) * 17 + lr];
+            const double bv = (lr < jb) ? A[(j0 + lr) + static_cast<size_t>(k0 + lh) * ld] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+        // through LDS into the operand layout, then P_j = acc Li_j^T
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Pw[(j0 + lr) * 17 + lh + 4 * q] = acc[q];
+        __builtin_amdgcn_wave_barrier();
+        v4d out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            const double av = Pw[(j0 + kk + lh) * 17 + lr];
+            const double bv = lv[(j0 >> 4) * 256 + lr * 16 + kk + lh];
+            out = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, out, 0, 0, 0);
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = r0 + lh + 4 * q;
+            Pw[(j0 + lr) * 17 + lh + 4 * q] = out[q];
+            if (r < m && lr < jb) A[(p + r) + static_cast<size_t>(j0 + lr) * ld] = out[q];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// S = A_BB - W^T W on the 32 x 32 block (bi, bj), bi >= bj (block y of the cell, row-major
+// over the lower triangle); each wave one 16 x 16 tile. The old values are read from the
+// lower triangle only; off-diagonal blocks are written to both triangles.
+__global__ __launch_bounds__(256) void k_syrk_schur(const FrontDesc* __restrict__ desc, double* __restrict__ pool) {
+    const FrontDesc fd = desc[blockIdx.x];
+    const int p = fd.p, ms = fd.n - fd.p, ld = fd.ld;
+    const int nb = (ms + 31) >> 5;
+    const int t = blockIdx.y;
+    if (t >= nb * (nb + 1) / 2) return;
+    int bi = static_cast<int>((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+    while (bi * (bi + 1) / 2 > t) --bi;
+    const int bj = t - bi * (bi + 1) / 2;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lh = lane >> 4;
+    const int ti = 2 * bi + (wave >> 1), tj = 2 * bj + (wave & 1);
+    double* A = pool + fd.off;
+    double* S = A + p + static_cast<size_t>(p) * ld;
+    const double* Wt = A + p;
+    const bool act = ti * 16 < ms && tj * 16 < ms;
+    const int c = tj * 16 + lr;
+    v4d s0 = {0.0, 0.0, 0.0, 0.0}, acc = {0.0, 0.0, 0.0, 0.0};
+    if (act) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = ti * 16 + lh + 4 * q;
+            if (r < ms && c < ms) s0[q] = S[max(r, c) + static_cast<size_t>(min(r, c)) * ld];
+        }
+        const int ra = ti * 16 + lr, rb = tj * 16 + lr;
+#pragma unroll 4
+        for (int k0 = 0; k0 < p; k0 += 4) {
+            const int k = k0 + lh;
+            const double av = (ra < ms && k < p) ? Wt[ra + static_cast<size_t>(k) * ld] : 0.0;
+            const double bv = (rb < ms && k < p) ? Wt[rb + static_cast<size_t>(k) * ld] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+    }
+    if (bi == bj) __syncthreads();   // the waves of a diagonal block read each other's outputs
+    if (act) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = ti * 16 + lh + 4 * q;
+            if (r < ms && c < ms) {
+                const double v = s0[q] - acc[q];
+                S[r + static_cast<size_t>(c) * ld] = v;
+                if (bi != bj) S[c + static_cast<size_t>(r) * ld] = v;
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------------

@@ -16,6 +16,10 @@ __global__ void k_front_extend(const Tile* tiles, const CellRef* cells, const in
                                const CellRef* child, const double* Fc, double* F);
 __global__ void k_potrf_batch(const FrontDesc* desc, double* pool, int panel_cap, int level, int step,
                               unsigned long long* err, int32_t* ext);
+__global__ void k_chol_lead(const FrontDesc* desc, double* pool, double* linv, int lds_pmax, int level,
+                            unsigned long long* err, int32_t* ext);
+__global__ void k_trsm_rows(const FrontDesc* desc, double* pool, const double* linv, int pstride);
+__global__ void k_syrk_schur(const FrontDesc* desc, double* pool);
 __global__ void k_precond_groups(const SepDesc* sd, const CellRef* cells, const double* F, double* Lg,
                                  int panel_cap, int level, unsigned long long* err);
 __global__ void k_precond_scale(const CellScaleDesc* cd, const CellGroup* cg, const double* Lg, double* F,

@@ -41,6 +41,9 @@ void hipcheck(hipError_t e, const char* what, int line) {
 constexpr int kLdsBudgetDoubles = 8192;      // 64 KiB of LDS per workgroup (default kernels)
 constexpr int kLdsMaxDoubles = 20480;        // 160 KiB: the gfx950 per-workgroup limit
 constexpr int kApplyCap = kLdsBudgetDoubles - rhif::kApplyDiagDoubles - rhif::kApplyExtDoubles - 32;
+// largest leading block k_chol_lead factors in LDS ((p|1) p + kPotrfSmemFixed <= 20480 doubles;
+// k_trsm_rows then needs 4 * 17 * 144 doubles)
+constexpr int kCholLdsPmax = 139;
 constexpr int kRedBlocks = 1024;              // fixed partial-sum layout of the CG reductions
 
 // Per-thread host state reused across factorizations: pinned staging buffers for the
@@ -366,6 +369,10 @@ void set_kernel_attributes() {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_skeletonize),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_chol_lead),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_trsm_rows),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     });
 }
 
@@ -465,13 +472,38 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         // ---- cell elimination (E_l; at the root: B_L = chol(A_L)) ----
         t0 = now();
         if (!P.cell_potrf.empty()) {
-            int nmax = 0;
-            for (const auto& fd : P.cell_potrf) nmax = std::max(nmax, fd.n - std::min(fd.n, 1));
-            const int cap = panel_cap_for(nmax, 0);
+            int nmax = 0, pmax = 0, mmax = 0;
+            for (const auto& fd : P.cell_potrf) {
+                nmax = std::max(nmax, fd.n - std::min(fd.n, 1));
+                pmax = std::max(pmax, fd.p);
+                mmax = std::max(mmax, fd.n - fd.p);
+            }
             const int cls = root ? RHIF_K_ROOT : (lvl == 0 ? RHIF_K_ELIM_LEAF : RHIF_K_ELIM_UPPER);
-            KTIMED(f, s, cls, P.alg_elim_flops, 0.0,
-                   hipLaunchKernelGGL(k_potrf_batch, dim3(P.cell_potrf.size()), dim3(256), potrf_lds(cap, 0), s,
-                                      LD.potrf, LD.front, cap, lvl, root ? 3 : 0, f->err, LD.ext));
+            const unsigned ncell = static_cast<unsigned>(P.cell_potrf.size());
+            if (!root && lvl > 0 && pmax <= kCholLdsPmax) {
+                // few cells: Cholesky, row solves and Schur update as three wide launches
+                double* linv = static_cast<double*>(f->dalloc(std::max<int64_t>(P.ext_elems, 1) * 256 * sizeof(double)));
+                const size_t lds1 = static_cast<size_t>(rhif::kPotrfSmemFixed + (pmax | 1) * pmax) * sizeof(double);
+                KTIMED(f, s, cls, P.alg_elim_flops, 0.0,
+                       hipLaunchKernelGGL(k_chol_lead, dim3(ncell), dim3(256), lds1, s, LD.potrf, LD.front, linv,
+                                          kCholLdsPmax, lvl, f->err, LD.ext));
+                if (mmax > 0) {
+                    const int pstride = 17 * ((pmax + 15) / 16) * 16;
+                    KTIMED(f, s, cls, 0.0, 0.0,
+                           hipLaunchKernelGGL(k_trsm_rows, dim3(ncell, (mmax + 63) / 64), dim3(256),
+                                              static_cast<size_t>(4 * pstride) * sizeof(double), s, LD.potrf, LD.front,
+                                              linv, pstride));
+                    const int nb = (mmax + 31) / 32;
+                    KTIMED(f, s, cls, 0.0, 0.0,
+                           hipLaunchKernelGGL(k_syrk_schur, dim3(ncell, nb * (nb + 1) / 2), dim3(256), 0, s, LD.potrf,
+                                              LD.front));
+                }
+            } else {
+                const int cap = panel_cap_for(nmax, 0);
+                KTIMED(f, s, cls, P.alg_elim_flops, 0.0,
+                       hipLaunchKernelGGL(k_potrf_batch, dim3(ncell), dim3(256), potrf_lds(cap, 0), s, LD.potrf,
+                                          LD.front, cap, lvl, root ? 3 : 0, f->err, LD.ext));
+            }
         }
         phase(root ? 6 : 1, t0);
         if (root) {
