@@ -50,7 +50,7 @@ struct SepDesc {
     int32_t slot_off[kMaxSlots];   // frontal position of the group's first unknown
     int64_t loff;                  // offset of L_g (n x n, ld n) in the group pool
     int32_t dofs;                  // offset of its unknowns in the level's group-dof array
-    int32_t pad;
+    int32_t lioff;                 // offset of the inverses of L_g's 16 x 16 diagonal blocks
 };
 
 // One boundary group of one cell, for the two-sided block-Jacobi scaling of the cell.
@@ -60,6 +60,8 @@ struct CellGroup {
     int64_t loff;    // L_g offset in the group pool
     int32_t owner;   // 1 if this cell holds the group's diagonal block after scaling
     int32_t cell;    // index of the cell's CellScaleDesc
+    int32_t lioff;   // offset of the inverses of L_g's 16 x 16 diagonal blocks
+    int32_t pad;
 };
 
 struct CellScaleDesc {

@@ -276,93 +276,164 @@ __device__ __forceinline__ void wg_potrf_partial(double* __restrict__ A, int ld,
 }
 
 // ---------------------------------------------------------------------------------------
-// Workgroup-collective interpolative decomposition by Householder QR with column pivoting
-// (Sec. 2.2). At step j the pivot is the trailing column with the largest 2-norm over rows
-// j.. (recomputed, not downdated; ties to the lowest column); steps continue while
-// |R_jj| > eps |R_11|. Returns k; perm[] (LDS) holds the column order; M holds R in its
-// first k rows (columns in pivot order).
+// Workgroup-collective column-pivoted Householder QR for the interpolative decomposition
+// (Sec. 2.2). M (r x n) is row-major with row stride ldr, in LDS or global memory.
+// Thread t owns column slot t % cw over row chunk t / cw, cw = min(64, the next power of
+// two >= n); with n > 64 it owns the columns slot, slot + 64, ... Columns are never moved:
+// pos[c] is the current position of column c in the pivoted order and perm[j] the column at
+// position j, kept as a QR that swaps columns would keep them. Step j takes, among the
+// columns not chosen yet, the largest 2-norm over rows j.. (recomputed from the current
+// values every step; ties to the lowest current position) and continues while
+// R_jj > eps R_11. Returns the rank k; row i <= j of column perm[j] then holds R[i][j].
+// part: 2 * 256 * ceil(n / cw) doubles; red: 2 doubles.
 // ---------------------------------------------------------------------------------------
-__device__ int wg_cpqr(double* __restrict__ M, int ld, int r, int n, double eps, int* perm,
-                       double* nrm2, double* red) {
+__device__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int r, int n, double eps, int* pos, int* perm,
+                            double* part, double* red) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < n; e += kWG) perm[e] = e;
+    int cw = 1;
+    while (cw < n && cw < 64) cw <<= 1;
+    const int nrc = kWG / cw;
+    const int cl = tid % cw, rc = tid / cw;
+    const int cs = (r + nrc - 1) / nrc;
+    const int i0 = rc * cs, i1 = min(r, i0 + cs);
+    const int nblk = (n + cw - 1) / cw;
+    double* pd = part;                 // dot partials  [blk][rc][cl]
+    double* pn = part + nblk * kWG;    // norm partials [blk][rc][cl]
+    for (int c = tid; c < n; c += kWG) {
+        pos[c] = c;
+        perm[c] = c;
+    }
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int c = blk * cw + cl;
+        double sq = 0.0, sq1 = 0.0;
+        if (c < n) {
+            int i = i0;
+            for (; i + 1 < i1; i += 2) {
+                const double v = M[static_cast<size_t>(i) * ldr + c], u = M[static_cast<size_t>(i + 1) * ldr + c];
+                sq += v * v;
+                sq1 += u * u;
+            }
+            if (i < i1) sq += M[static_cast<size_t>(i) * ldr + c] * M[static_cast<size_t>(i) * ldr + c];
+        }
+        pn[blk * kWG + tid] = sq + sq1;
+    }
     __syncthreads();
     const int kmax = min(r, n);
     double r11 = 0.0;
     int k = 0;
     for (int j = 0; j < kmax; ++j) {
-        for (int c = j + wave; c < n; c += kWaves) {
-            double s = 0.0;
-            for (int i = j + lane; i < r; i += 64) {
-                const double v = M[i + static_cast<size_t>(c) * ld];
-                s += v * v;
-            }
-            s = wave_sum(s);
-            if (lane == 0) nrm2[c] = s;
-        }
-        __syncthreads();
+        // (a) pivot among the columns with pos >= j, by wave 0
         if (wave == 0) {
             double best = -1.0;
-            int bi = n;
-            for (int c = j + lane; c < n; c += 64) {
-                const double v = nrm2[c];
-                if (v > best) {
+            int bpos = 0x7fffffff, bc = -1;
+            for (int c = lane; c < n; c += 64) {
+                const int pp = pos[c];
+                if (pp < j) continue;
+                const int blk = c / cw, sl = c % cw;
+                double v = 0.0;
+                for (int q = 0; q < nrc; ++q) v += pn[blk * kWG + q * cw + sl];
+                if (v > best || (v == best && pp < bpos)) {
                     best = v;
-                    bi = c;
+                    bpos = pp;
+                    bc = c;
                 }
             }
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
                 const double ob = __shfl_xor(best, off, 64);
-                const int oi = __shfl_xor(bi, off, 64);
-                if (ob > best || (ob == best && oi < bi)) {
+                const int op = __shfl_xor(bpos, off, 64);
+                const int oc = __shfl_xor(bc, off, 64);
+                if (ob > best || (ob == best && op < bpos)) {
                     best = ob;
-                    bi = oi;
+                    bpos = op;
+                    bc = oc;
                 }
             }
             if (lane == 0) {
                 red[0] = best;
-                red[1] = static_cast<double>(bi);
+                red[1] = static_cast<double>(bc);
             }
         }
         __syncthreads();
-        const double bn2 = red[0];
-        const int piv = static_cast<int>(red[1]);
-        const double nrm = sqrt(bn2);
+        const double nrm = sqrt(red[0]);
+        const int pc = static_cast<int>(red[1]);
         if (j == 0) r11 = nrm;
         if (!(nrm > eps * r11)) break;
-        if (piv != j) {
-            for (int i = tid; i < r; i += kWG) {
-                const double t0 = M[i + static_cast<size_t>(j) * ld];
-                M[i + static_cast<size_t>(j) * ld] = M[i + static_cast<size_t>(piv) * ld];
-                M[i + static_cast<size_t>(piv) * ld] = t0;
-            }
-            if (tid == 0) {
-                const int t1 = perm[j];
-                perm[j] = perm[piv];
-                perm[piv] = t1;
-            }
-        }
-        __syncthreads();
-        const double x0 = M[j + static_cast<size_t>(j) * ld];
+        // (b) reflector of column pc over rows j..: v = (x0 - alpha, x1, ...), beta = 2 / v^T v
+        const double x0 = M[static_cast<size_t>(j) * ldr + pc];
         const double alpha = -copysign(nrm, x0);
         const double v0 = x0 - alpha;
-        const double beta = 2.0 / (2.0 * nrm * (nrm + fabs(x0)));   // 2 / (v^T v)
-        for (int c = j + 1 + wave; c < n; c += kWaves) {
-            double dot = 0.0;
-            for (int i = j + 1 + lane; i < r; i += 64)
-                dot += M[i + static_cast<size_t>(j) * ld] * M[i + static_cast<size_t>(c) * ld];
-            dot = wave_sum(dot) + v0 * M[j + static_cast<size_t>(c) * ld];
-            const double f = beta * dot;
-            if (lane == 0) M[j + static_cast<size_t>(c) * ld] -= f * v0;
-            for (int i = j + 1 + lane; i < r; i += 64)
-                M[i + static_cast<size_t>(c) * ld] -= f * M[i + static_cast<size_t>(j) * ld];
+        const double beta = 1.0 / (nrm * (nrm + fabs(x0)));
+        // rows of this thread's chunk below row j (row j itself is handled apart)
+        const bool has_j = (i0 <= j && j < i1);
+        const int ib = max(i0, j + 1);
+        // (c) w_c = v^T M[j:, c] for the columns still to choose (the test below gives the
+        //     same answer before and after the position update of this step)
+        for (int blk = 0; blk < nblk; ++blk) {
+            const int c = blk * cw + cl;
+            double w = 0.0;
+            if (c < n && c != pc && pos[c] >= j) {
+                double w1 = 0.0, w2 = 0.0, w3 = 0.0;
+                if (has_j) w = v0 * M[static_cast<size_t>(j) * ldr + c];
+                int i = ib;
+                for (; i + 3 < i1; i += 4) {
+                    const double* Mi = M + static_cast<size_t>(i) * ldr;
+                    w += Mi[pc] * Mi[c];
+                    w1 += Mi[ldr + pc] * Mi[ldr + c];
+                    w2 += Mi[2 * ldr + pc] * Mi[2 * ldr + c];
+                    w3 += Mi[3 * ldr + pc] * Mi[3 * ldr + c];
+                }
+                for (; i < i1; ++i) w += M[static_cast<size_t>(i) * ldr + pc] * M[static_cast<size_t>(i) * ldr + c];
+                w += (w1 + w2) + w3;
+            }
+            pd[blk * kWG + tid] = w;
         }
         __syncthreads();
-        if (tid == 0) M[j + static_cast<size_t>(j) * ld] = alpha;
+        // (d) M[j:, c] -= beta w_c v, and the new squared norms over rows j+1..
+        for (int blk = 0; blk < nblk; ++blk) {
+            const int c = blk * cw + cl;
+            if (c < n && c != pc && pos[c] >= j) {
+                double f = 0.0;
+                for (int q = 0; q < nrc; ++q) f += pd[blk * kWG + q * cw + cl];
+                f *= beta;
+                if (has_j) M[static_cast<size_t>(j) * ldr + c] -= f * v0;
+                double sq = 0.0, sq1 = 0.0, sq2 = 0.0, sq3 = 0.0;
+                int i = ib;
+                for (; i + 3 < i1; i += 4) {
+                    double* Mi = M + static_cast<size_t>(i) * ldr;
+                    const double n0 = Mi[c] - f * Mi[pc];
+                    const double n1 = Mi[ldr + c] - f * Mi[ldr + pc];
+                    const double n2 = Mi[2 * ldr + c] - f * Mi[2 * ldr + pc];
+                    const double n3 = Mi[3 * ldr + c] - f * Mi[3 * ldr + pc];
+                    Mi[c] = n0;
+                    Mi[ldr + c] = n1;
+                    Mi[2 * ldr + c] = n2;
+                    Mi[3 * ldr + c] = n3;
+                    sq += n0 * n0;
+                    sq1 += n1 * n1;
+                    sq2 += n2 * n2;
+                    sq3 += n3 * n3;
+                }
+                for (; i < i1; ++i) {
+                    const double nv = M[static_cast<size_t>(i) * ldr + c] - f * M[static_cast<size_t>(i) * ldr + pc];
+                    M[static_cast<size_t>(i) * ldr + c] = nv;
+                    sq += nv * nv;
+                }
+                pn[blk * kWG + tid] = sq + ((sq1 + sq2) + sq3);
+            }
+        }
+        if (tid == 0) {
+            M[static_cast<size_t>(j) * ldr + pc] = alpha;
+            const int q = pos[pc], cj = perm[j];
+            perm[j] = pc;
+            perm[q] = cj;
+            pos[cj] = q;
+            pos[pc] = j;
+        }
         __syncthreads();
         k = j + 1;
     }
+    __syncthreads();
     return k;
 }
 
@@ -595,38 +666,33 @@ __global__ __launch_bounds__(256) void k_chol_lead(const FrontDesc* __restrict__
     }
 }
 
-// Rows p.. of the cell: W^T = X L^-T by 16-column panels, P_j = (X_j - P_<j L_j,<j^T) Li_j^T
-// with Li_j the stored inverse of the j-th diagonal block. Wave w of block y owns rows
-// p + 16 (4 y + w) ..; its finished panels sit in LDS (pstride doubles per wave, k-major
-// with 17 rows per column). The waves never wait for each other.
-__global__ __launch_bounds__(256) void k_trsm_rows(const FrontDesc* __restrict__ desc, double* __restrict__ pool,
-                                                   const double* __restrict__ linv, int pstride) {
-    extern __shared__ double smem[];
-    const FrontDesc fd = desc[blockIdx.x];
-    const int p = fd.p, m = fd.n - fd.p, ld = fd.ld;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int lr = lane & 15, lh = lane >> 4;
-    const int r0 = (static_cast<int>(blockIdx.y) * kWaves + wave) * 16;
-    if (r0 >= m || p == 0) return;
-    double* A = pool + fd.off;
-    const double* lv = linv + static_cast<size_t>(fd.ext) * 256;
-    double* Pw = smem + static_cast<size_t>(wave) * pstride;
-    for (int j0 = 0; j0 < p; j0 += 16) {
-        const int jb = min(16, p - j0);
+// Wave-level triangular solves with a lower-triangular L (n x n, column-major, ld ldl)
+// whose 16 x 16 diagonal blocks have stored inverses li (256 doubles per block, padded with
+// the identity), on the FP64 matrix cores:
+//   wave_trsm_rlt: rows r0..r0+15 of the column-major m x n block X become X L^-T, by
+//                  16-column panels P_j = (X_j - P_<j L_j,<j^T) Li_j^T;
+//   wave_trsm_ll:  columns c0..c0+15 of the column-major n x nc block Y become L^-1 Y, by
+//                  16-row blocks Y_I = Li_I (Y_I - L_I,<I Y_<I); optionally also written
+//                  transposed to YT (ld ldt).
+// Pw: the wave's LDS scratch, 17 * roundup16(n) doubles (finished panels / row blocks).
+// Lane l holds output rows l/16 + 4q, column l % 16 of a 16 x 16 tile.
+__device__ __forceinline__ void wave_trsm_rlt(double* __restrict__ X, int ldx, int m, int r0, int n,
+                                              const double* __restrict__ L, int ldl, const double* __restrict__ li,
+                                              double* Pw) {
+    const int lane = threadIdx.x & 63, lr = lane & 15, lh = lane >> 4;
+    for (int j0 = 0; j0 < n; j0 += 16) {
+        const int jb = min(16, n - j0);
         v4d acc;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = r0 + lh + 4 * q;
-            acc[q] = (r < m && lr < jb) ? A[(p + r) + static_cast<size_t>(j0 + lr) * ld] : 0.0;
+            acc[q] = (r < m && lr < jb) ? X[r + static_cast<size_t>(j0 + lr) * ldx] : 0.0;
         }
-        // acc -= P[:, 0:j0] L[j0:j1, 0:j0]^T  (A operand -P[lr][k], B operand L[j0 + lr][k])
-#pragma unroll 4
         for (int k0 = 0; k0 < j0; k0 += 4) {
             const double av = -Pw[(k0 + lh) * 17 + lr];
-            const double bv = (lr < jb) ? A[(j0 + lr) + static_cast<size_t>(k0 + lh) * ld] : 0.0;
+            const double bv = (lr < jb) ? L[(j0 + lr) + static_cast<size_t>(k0 + lh) * ldl] : 0.0;
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
         }
-        // through LDS into the operand layout, then P_j = acc Li_j^T
 #pragma unroll
         for (int q = 0; q < 4; ++q) Pw[(j0 + lr) * 17 + lh + 4 * q] = acc[q];
         __builtin_amdgcn_wave_barrier();
@@ -634,7 +700,7 @@ __global__ __launch_bounds__(256) void k_trsm_rows(const FrontDesc* __restrict__
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 4) {
             const double av = Pw[(j0 + kk + lh) * 17 + lr];
-            const double bv = lv[(j0 >> 4) * 256 + lr * 16 + kk + lh];
+            const double bv = li[(j0 >> 4) * 256 + lr * 16 + kk + lh];
             out = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, out, 0, 0, 0);
         }
         __builtin_amdgcn_wave_barrier();
@@ -642,10 +708,66 @@ __global__ __launch_bounds__(256) void k_trsm_rows(const FrontDesc* __restrict__
         for (int q = 0; q < 4; ++q) {
             const int r = r0 + lh + 4 * q;
             Pw[(j0 + lr) * 17 + lh + 4 * q] = out[q];
-            if (r < m && lr < jb) A[(p + r) + static_cast<size_t>(j0 + lr) * ld] = out[q];
+            if (r < m && lr < jb) X[r + static_cast<size_t>(j0 + lr) * ldx] = out[q];
         }
         __builtin_amdgcn_wave_barrier();
     }
+}
+
+__device__ __forceinline__ void wave_trsm_ll(double* __restrict__ Y, int ldy, int n, int c0, int nc,
+                                             const double* __restrict__ L, int ldl, const double* __restrict__ li,
+                                             double* Yb, double* __restrict__ YT, int ldt) {
+    const int lane = threadIdx.x & 63, lr = lane & 15, lh = lane >> 4;
+    const int cb = min(16, nc - c0);
+    for (int i0 = 0; i0 < n; i0 += 16) {
+        v4d acc;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = i0 + lh + 4 * q;
+            acc[q] = (r < n && lr < cb) ? Y[r + static_cast<size_t>(c0 + lr) * ldy] : 0.0;
+        }
+        for (int k0 = 0; k0 < i0; k0 += 4) {
+            const double av = (i0 + lr < n) ? -L[(i0 + lr) + static_cast<size_t>(k0 + lh) * ldl] : 0.0;
+            const double bv = Yb[(k0 + lh) * 17 + lr];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Yb[(i0 + lh + 4 * q) * 17 + lr] = acc[q];
+        __builtin_amdgcn_wave_barrier();
+        v4d out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            const double av = li[(i0 >> 4) * 256 + lr * 16 + kk + lh];
+            const double bv = Yb[(i0 + kk + lh) * 17 + lr];
+            out = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, out, 0, 0, 0);
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = i0 + lh + 4 * q;
+            Yb[r * 17 + lr] = out[q];
+            if (r < n && lr < cb) {
+                Y[r + static_cast<size_t>(c0 + lr) * ldy] = out[q];
+                if (YT != nullptr) YT[(c0 + lr) + static_cast<size_t>(r) * ldt] = out[q];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Rows p.. of the cell: W^T = X L^-T, wave w of block y owning rows p + 16 (4 y + w) ..
+// (pstride doubles of LDS per wave). The waves never wait for each other.
+__global__ __launch_bounds__(256) void k_trsm_rows(const FrontDesc* __restrict__ desc, double* __restrict__ pool,
+                                                   const double* __restrict__ linv, int pstride) {
+    extern __shared__ double smem[];
+    const FrontDesc fd = desc[blockIdx.x];
+    const int p = fd.p, m = fd.n - fd.p;
+    const int wave = threadIdx.x >> 6;
+    const int r0 = (static_cast<int>(blockIdx.y) * kWaves + wave) * 16;
+    if (r0 >= m || p == 0) return;
+    double* A = pool + fd.off;
+    wave_trsm_rlt(A + p, fd.ld, m, r0, p, A, fd.ld, linv + static_cast<size_t>(fd.ext) * 256,
+                  smem + static_cast<size_t>(wave) * pstride);
 }
 
 // S = A_BB - W^T W on the 32 x 32 block (bi, bj), bi >= bj (block y of the cell, row-major
@@ -705,7 +827,8 @@ __global__ __launch_bounds__(256) void k_syrk_schur(const FrontDesc* __restrict_
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_precond_groups(const SepDesc* __restrict__ sd, const CellRef* __restrict__ cells,
                                                         const double* __restrict__ F, double* __restrict__ Lg,
-                                                        int panel_cap, int level, unsigned long long* err) {
+                                                        double* __restrict__ Li, int panel_cap, int level,
+                                                        unsigned long long* err) {
     extern __shared__ double smem[];
     const SepDesc g = sd[blockIdx.x];
     const int n = g.n;
@@ -720,81 +843,48 @@ __global__ __launch_bounds__(256) void k_precond_groups(const SepDesc* __restric
         L[e] = v;
     }
     __syncthreads();
-    wg_potrf_partial(L, n, n, n, smem, panel_cap, err, err_code(level, 1, blockIdx.x), nullptr);
+    wg_potrf_partial(L, n, n, n, smem, panel_cap, err, err_code(level, 1, blockIdx.x), nullptr, Li + g.lioff);
 }
 
 // Block-Jacobi step, part 2: every cell's share S of the separator matrix becomes
 // Lambda^-1 S Lambda^-T with Lambda = blockdiag(L_g) over the cell's boundary groups; the
 // diagonal blocks become I in the group's first cell and 0 in the others, so that the
-// assembled matrix has unit block diagonal. One workgroup per (cell, boundary group h)
-// owns the block column h: Y[:, h] = Lambda^-1 S[:, h] L_h^-T (the block column of the
-// symmetric S is its block row transposed, so no other block is read). The block column
-// is staged in LDS when it fits (lds_cap doubles): first independent row solves with L_h,
-// then independent (column, group) solves with the L_g.
+// assembled matrix has unit block diagonal. One workgroup per block (g, h) of a cell with g
+// after h in the cell's group order: S_gh := L_g^-1 S_gh L_h^-T (rows, then columns, by
+// blocked substitution with the stored inverses of the 16 x 16 diagonal blocks), written
+// also transposed into the (h, g) block. Workgroups with g = h set the diagonal block.
 __global__ __launch_bounds__(256) void k_precond_scale(const CellScaleDesc* __restrict__ cd,
                                                        const CellGroup* __restrict__ cg, const double* __restrict__ Lg,
-                                                       double* __restrict__ F, int lds_cap) {
+                                                       const double* __restrict__ Li, double* __restrict__ F,
+                                                       int pstride) {
     extern __shared__ double smem[];
-    const CellGroup h = cg[blockIdx.x];
-    const CellScaleDesc c = cd[h.cell];
-    const CellGroup* G = cg + c.g_begin;
-    const int nB = c.nB, nh = h.n, ng = c.g_count;
-    const int oh = h.off - c.nI;
+    const CellScaleDesc c = cd[blockIdx.x];
+    const int gc = c.g_count;
+    const int t = blockIdx.y;
+    if (t >= gc * (gc + 1) / 2) return;
+    int eg = static_cast<int>((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((eg + 1) * (eg + 2) / 2 <= t) ++eg;
+    while (eg * (eg + 1) / 2 > t) --eg;
+    const int eh = t - eg * (eg + 1) / 2;
+    const CellGroup G = cg[c.g_begin + eg], H = cg[c.g_begin + eh];
     double* Fc = F + c.off;
-    const bool in_lds = nB * nh + nh * nh <= lds_cap;
-    double* B;        // block column, B[i + j * ldb] = S[i, oh + j]
-    int ldb;
-    const double* Lh;
-    if (in_lds) {
-        double* Ls = smem;
-        B = smem + nh * nh;
-        ldb = nB;
-        for (int x = threadIdx.x; x < nh * nh; x += kWG) Ls[x] = Lg[h.loff + x];
-        for (int x = threadIdx.x; x < nB * nh; x += kWG) {
-            const int i = x % nB, j = x / nB;
-            B[x] = Fc[(c.nI + i) + static_cast<size_t>(h.off + j) * c.ld];
+    const int ld = c.ld;
+    if (eg == eh) {
+        for (int e = threadIdx.x; e < G.n * G.n; e += kWG) {
+            const int a = e % G.n, b = e / G.n;
+            Fc[(G.off + a) + static_cast<size_t>(G.off + b) * ld] = (G.owner && a == b) ? 1.0 : 0.0;
         }
-        Lh = Ls;
-    } else {
-        B = Fc + c.nI + static_cast<size_t>(h.off) * c.ld;
-        ldb = c.ld;
-        Lh = Lg + h.loff;
+        return;
     }
+    const int wave = threadIdx.x >> 6;
+    double* X = Fc + G.off + static_cast<size_t>(H.off) * ld;
+    double* XT = Fc + H.off + static_cast<size_t>(G.off) * ld;
+    double* Pw = smem + static_cast<size_t>(wave) * pstride;
+    for (int r0 = wave * 16; r0 < G.n; r0 += kWaves * 16)
+        wave_trsm_rlt(X, ld, G.n, r0, H.n, Lg + H.loff, H.n, Li + H.lioff, Pw);
     __syncthreads();
-    // U = S[:, h] L_h^-T: row i solves u L_h^T = s
-    for (int i = threadIdx.x; i < nB; i += kWG) {
-        for (int q = 0; q < nh; ++q) {
-            double v = B[i + static_cast<size_t>(q) * ldb];
-            for (int r = 0; r < q; ++r) v -= Lh[q + r * nh] * B[i + static_cast<size_t>(r) * ldb];
-            B[i + static_cast<size_t>(q) * ldb] = v / Lh[q + q * nh];
-        }
-    }
-    __syncthreads();
-    // Y = Lambda^-1 U: column j of the block, group g: L_g y = u over the rows of g
-    for (int t = threadIdx.x; t < nh * ng; t += kWG) {
-        const int e = t / nh, j = t % nh;
-        const int o = G[e].off - c.nI, n = G[e].n;
-        const double* L = Lg + G[e].loff;
-        double* col = B + static_cast<size_t>(j) * ldb;
-        for (int q = 0; q < n; ++q) {
-            double v = col[o + q];
-            for (int r = 0; r < q; ++r) v -= L[q + r * n] * col[o + r];
-            col[o + q] = v / L[q + q * n];
-        }
-    }
-    __syncthreads();
-    // the diagonal block of h: identity in the group's first cell, zero elsewhere
-    for (int x = threadIdx.x; x < nh * nh; x += kWG) {
-        const int a = x % nh, b = x / nh;
-        B[(oh + a) + static_cast<size_t>(b) * ldb] = (h.owner && a == b) ? 1.0 : 0.0;
-    }
-    if (in_lds) {
-        __syncthreads();
-        for (int x = threadIdx.x; x < nB * nh; x += kWG) {
-            const int i = x % nB, j = x / nB;
-            Fc[(c.nI + i) + static_cast<size_t>(h.off + j) * c.ld] = B[x];
-        }
-    }
+    for (int c0 = wave * 16; c0 < H.n; c0 += kWaves * 16)
+        wave_trsm_ll(X, ld, G.n, c0, H.n, Lg + G.loff, G.n, Li + G.lioff, Pw, XT, ld);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -821,88 +911,110 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
     // staged: bit 0 = M in LDS, bit 1 = G in LDS
     extern __shared__ double smem[];
     const SkelDesc g = sd[blockIdx.x];
-    const int n = g.n, r = g.r;
-    // LDS: perm ints | nrm2 (nmax) | red (2) | [M (rmax*nmax) | G (nmax^2)] | potrf scratch
-    const int pd = (nmax + 1) / 2 + 1;
-    int* perm = reinterpret_cast<int*>(smem);
-    double* nrm2 = smem + pd;
-    double* red = nrm2 + nmax;
+    const int n = g.n, r = g.r, ldr = n | 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // LDS: pos, perm ints | QR partials | red (2) | [M (rmax x (nmax|1))] | [G (nmax^2)] | potrf
+    const int ipd = (2 * nmax + 1) / 2 + 1;
+    const int nbm = max(1, (nmax + 63) / 64);
+    int* pos = reinterpret_cast<int*>(smem);
+    int* perm = pos + nmax;
+    double* part = smem + ipd;
+    double* red = part + 2 * kWG * nbm;
     double* after = red + 2;
     const bool stage_m = (staged & 1) != 0, stage_g = (staged & 2) != 0;
     double* M = stage_m ? after : Mpool + g.moff;
-    double* gl = stage_m ? after + static_cast<size_t>(rmax) * nmax : after;
+    double* gl = stage_m ? after + static_cast<size_t>(rmax) * (nmax | 1) : after;
     double* Gw = stage_g ? gl : Gpool + g.goff;
     double* psmem = stage_g ? gl + static_cast<size_t>(nmax) * nmax : gl;
     const int32_t* rw = rows + static_cast<size_t>(g.rows) * 2;
     const CellRef c0 = cells[g.cell[0]];
     CellRef c1 = c0;
     if (g.nslot > 1) c1 = cells[g.cell[1]];
-    // 1. gather M = A[R_g, g]
-    for (int e = threadIdx.x; e < r * n; e += kWG) {
-        const int i = e % r, j = e / r;
-        const int p1 = rw[2 * i], p2 = rw[2 * i + 1];
-        double v = 0.0;
-        if (p1 >= 0) v += F[c0.off + p1 + static_cast<size_t>(g.off[0] + j) * c0.ld];
-        if (p2 >= 0) v += F[c1.off + p2 + static_cast<size_t>(g.off[1] + j) * c1.ld];
-        M[e] = v;
+    // 1. M = A[R_g, g] (row-major), the shares of both cells added
+    for (int j = wave; j < n; j += kWaves) {
+        const double* f0 = F + c0.off + static_cast<size_t>(g.off[0] + j) * c0.ld;
+        const double* f1 = F + c1.off + static_cast<size_t>(g.off[1] + j) * c1.ld;
+        for (int i = lane; i < r; i += 64) {
+            const int p1 = rw[2 * i], p2 = rw[2 * i + 1];
+            double v = 0.0;
+            if (p1 >= 0) v += f0[p1];
+            if (p2 >= 0) v += f1[p2];
+            M[static_cast<size_t>(i) * ldr + j] = v;
+        }
     }
     __syncthreads();
-    // 2. ID
-    const int k = wg_cpqr(M, r, r, n, eps, perm, nrm2, red);
+    // 2. ID: rank k, pivot order, and T = R11^-1 R12 solved in place over R12
+    const int k = wg_cpqr_rows(M, ldr, r, n, eps, pos, perm, part, red);
     const int nr = n - k;
-    double* T = Tpool + g.toff;
-    for (int c = k + threadIdx.x; c < n; c += kWG) {
-        double* Tc = T + static_cast<size_t>(c - k) * k;
+    for (int a = tid; a < nr; a += kWG) {
+        const int pa = perm[k + a];
         for (int i = k - 1; i >= 0; --i) {
-            double v = M[i + static_cast<size_t>(c) * r];
-            for (int e = i + 1; e < k; ++e) v -= M[i + static_cast<size_t>(e) * r] * Tc[e];
-            Tc[i] = v / M[i + static_cast<size_t>(i) * r];
-        }
-    }
-    if (threadIdx.x == 0) kout[g.gid] = k;
-    for (int e = threadIdx.x; e < n; e += kWG) pout[g.poff + e] = perm[e];
-    __syncthreads();
-    // 3. zeroed blocks; U = A_hh T goes to the (now free) M space
-    auto Agg = [&](int a, int b) -> double {
-        double v = F[c0.off + (g.off[0] + a) + static_cast<size_t>(g.off[0] + b) * c0.ld];
-        if (g.nslot > 1) v += F[c1.off + (g.off[1] + a) + static_cast<size_t>(g.off[1] + b) * c1.ld];
-        return v;
-    };
-    double* U = M;
-    for (int e = threadIdx.x; e < k * nr; e += kWG) {
-        const int c = e % k, a = e / k;
-        double v = 0.0;
-        for (int q = 0; q < k; ++q) v += Agg(perm[c], perm[q]) * T[q + static_cast<size_t>(a) * k];
-        U[e] = v;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < n * n; e += kWG) {
-        const int a = e % n, b = e / n;
-        if (a < b) continue;
-        double v;
-        if (b < nr && a < nr) {
-            const int ta = perm[k + a], tb = perm[k + b];
-            v = Agg(ta, tb);
-            for (int c = 0; c < k; ++c) {
-                const int hc = perm[c];
-                v -= T[c + static_cast<size_t>(a) * k] * Agg(hc, tb);
-                v -= Agg(hc, ta) * T[c + static_cast<size_t>(b) * k];
-                v += T[c + static_cast<size_t>(a) * k] * U[c + static_cast<size_t>(b) * k];
+            const double* Ri = M + static_cast<size_t>(i) * ldr;
+            double v = Ri[pa], v1 = 0.0;
+            int e = i + 1;
+            for (; e + 1 < k; e += 2) {
+                v -= Ri[perm[e]] * M[static_cast<size_t>(e) * ldr + pa];
+                v1 -= Ri[perm[e + 1]] * M[static_cast<size_t>(e + 1) * ldr + pa];
             }
-        } else if (b < nr) {
-            const int c = a - nr;
-            v = Agg(perm[c], perm[k + b]) - U[c + static_cast<size_t>(b) * k];
-        } else {
-            v = Agg(perm[a - nr], perm[b - nr]);
+            if (e < k) v -= Ri[perm[e]] * M[static_cast<size_t>(e) * ldr + pa];
+            M[static_cast<size_t>(i) * ldr + pa] = (v + v1) / Ri[perm[i]];
         }
-        Gw[e] = v;
+    }
+    if (tid == 0) kout[g.gid] = k;
+    for (int e = tid; e < n; e += kWG) pout[g.poff + e] = perm[e];
+    __syncthreads();
+    double* T = Tpool + g.toff;
+    for (int e = tid; e < k * nr; e += kWG) {
+        const int i = e % k, a = e / k;
+        T[e] = M[static_cast<size_t>(i) * ldr + perm[k + a]];
+    }
+    // 3. the zeroed blocks of eq. (2.2) in the order (redundant, skeleton). G first holds the
+    //    whole permuted A_gg; then V = A_ht - A_hh T replaces the lower (h, t) block (A_ht
+    //    stays in the upper one), then A~_tt = A_tt - T^T V - A_ht^T T (lower part).
+    for (int y = wave; y < n; y += kWaves) {
+        const int qy = y < nr ? perm[k + y] : perm[y - nr];
+        const double* f0 = F + c0.off + g.off[0] + static_cast<size_t>(g.off[0] + qy) * c0.ld;
+        const double* f1 = F + c1.off + g.off[1] + static_cast<size_t>(g.off[1] + qy) * c1.ld;
+        for (int x = lane; x < n; x += 64) {
+            const int qx = x < nr ? perm[k + x] : perm[x - nr];
+            double v = f0[qx];
+            if (g.nslot > 1) v += f1[qx];
+            Gw[x + static_cast<size_t>(y) * n] = v;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < k * nr; e += kWG) {
+        const int c = e % k, a = e / k;
+        const int pa = perm[k + a];
+        const double* Gc = Gw + (nr + c) + static_cast<size_t>(nr) * n;
+        double v = Gw[(nr + c) + static_cast<size_t>(a) * n], v1 = 0.0;
+        int q = 0;
+        for (; q + 1 < k; q += 2) {
+            v -= Gc[static_cast<size_t>(q) * n] * M[static_cast<size_t>(q) * ldr + pa];
+            v1 -= Gc[static_cast<size_t>(q + 1) * n] * M[static_cast<size_t>(q + 1) * ldr + pa];
+        }
+        if (q < k) v -= Gc[static_cast<size_t>(q) * n] * M[static_cast<size_t>(q) * ldr + pa];
+        Gw[(nr + c) + static_cast<size_t>(a) * n] = v + v1;
+    }
+    __syncthreads();
+    for (int e = tid; e < nr * nr; e += kWG) {
+        const int a = e % nr, b = e / nr;
+        if (a < b) continue;
+        const int pa = perm[k + a], pb = perm[k + b];
+        double v = Gw[a + static_cast<size_t>(b) * n], v1 = 0.0;
+        for (int c = 0; c < k; ++c) {
+            const double* Tc = M + static_cast<size_t>(c) * ldr;
+            v -= Tc[pa] * Gw[(nr + c) + static_cast<size_t>(b) * n];
+            v1 -= Gw[a + static_cast<size_t>(nr + c) * n] * Tc[pb];
+        }
+        Gw[a + static_cast<size_t>(b) * n] = v + v1;
     }
     __syncthreads();
     // 4. eliminate the redundant unknowns
     wg_potrf_partial(Gw, n, n, nr, psmem, panel_cap, err, err_code(level, 2, blockIdx.x), nullptr);
     // 5. write back the skeleton block (and keep G for the apply)
     double* Gout = Gpool + g.goff;
-    for (int e = threadIdx.x; e < n * n; e += kWG) {
+    for (int e = tid; e < n * n; e += kWG) {
         const int a = e % n, b = e / n;
         if (stage_g) Gout[e] = Gw[e];
         if (a < k && b < k) {

@@ -20,10 +20,10 @@ __global__ void k_chol_lead(const FrontDesc* desc, double* pool, double* linv, i
                             unsigned long long* err, int32_t* ext);
 __global__ void k_trsm_rows(const FrontDesc* desc, double* pool, const double* linv, int pstride);
 __global__ void k_syrk_schur(const FrontDesc* desc, double* pool);
-__global__ void k_precond_groups(const SepDesc* sd, const CellRef* cells, const double* F, double* Lg,
+__global__ void k_precond_groups(const SepDesc* sd, const CellRef* cells, const double* F, double* Lg, double* Li,
                                  int panel_cap, int level, unsigned long long* err);
-__global__ void k_precond_scale(const CellScaleDesc* cd, const CellGroup* cg, const double* Lg, double* F,
-                                int lds_cap);
+__global__ void k_precond_scale(const CellScaleDesc* cd, const CellGroup* cg, const double* Lg, const double* Li,
+                                double* F, int pstride);
 __global__ void k_skeletonize(const SkelDesc* sd, const int32_t* rows, const CellRef* cells, double* F,
                               double* Mpool, double* Tpool, double* Gpool, double eps, int32_t* kout,
                               int32_t* pout, int panel_cap, int staged, int nmax, int rmax, int level,

@@ -61,8 +61,8 @@ void LevelPlan::reset() {
     sep_apply.clear();
     gather.clear();
     ncells = 0;
-    front_elems = lg_elems = m_elems = t_elems = g_elems = y_elems = ws_elems = 0;
-    skel_ntotal = max_nf = max_sep_n = max_skel_n = 0;
+    front_elems = lg_elems = li_elems = m_elems = t_elems = g_elems = y_elems = ws_elems = 0;
+    skel_ntotal = max_nf = max_sep_n = max_skel_n = max_cell_groups = 0;
     flops = alg_elim_flops = alg_prec_chol_flops = alg_prec_scale_flops = alg_front_bytes = 0.0;
     alg_apply_cell_bytes = alg_apply_sep_bytes = alg_gather_bytes = 0.0;
 }
@@ -346,7 +346,9 @@ void build_separators(const GridInfo& gi, PlanScratch& scr, int lds_apply_cap, L
 
     // ---- separator groups: block Jacobi and the up-sweep gather ----
     int64_t loff = 0;
+    int32_t lioff = 0;
     std::vector<int64_t> g_loff(ngroups, -1);
+    std::vector<int32_t> g_lioff(ngroups, -1);
     for (int g = 0; g < ngroups; ++g) {
         if (P.gcls[g] == 0) continue;
         const int n = P.gptr[g + 1] - P.gptr[g];
@@ -360,6 +362,9 @@ void build_separators(const GridInfo& gi, PlanScratch& scr, int lds_apply_cap, L
         }
         sd.loff = loff;
         g_loff[g] = loff;
+        sd.lioff = lioff;
+        g_lioff[g] = lioff;
+        lioff += 256 * ((n + 15) / 16);
         sd.dofs = static_cast<int32_t>(P.sep_dofs.size());
         P.sep_dofs.insert(P.sep_dofs.end(), P.gdofs.begin() + P.gptr[g], P.gdofs.begin() + P.gptr[g + 1]);
         P.sep_desc.push_back(sd);
@@ -398,6 +403,7 @@ void build_separators(const GridInfo& gi, PlanScratch& scr, int lds_apply_cap, L
         P.sep_apply.push_back(ad);
     }
     P.lg_elems = std::max<int64_t>(loff, 32);
+    P.li_elems = std::max<int64_t>(lioff, 256);
     for (int64_t ci = 0; ci < ncells; ++ci) {
         CellScaleDesc cs{};
         cs.off = P.c_foff[ci];
@@ -411,6 +417,7 @@ void build_separators(const GridInfo& gi, PlanScratch& scr, int lds_apply_cap, L
             cg.off = P.c_goff[e];
             cg.n = P.gptr[g + 1] - P.gptr[g];
             cg.loff = g_loff[g];
+            cg.lioff = g_lioff[g];
             cg.owner = (P.gslot_cell[static_cast<size_t>(g) * kMaxSlots] == ci) ? 1 : 0;
             cg.cell = static_cast<int32_t>(P.cell_scale.size());
             P.cell_groups.push_back(cg);
@@ -419,7 +426,10 @@ void build_separators(const GridInfo& gi, PlanScratch& scr, int lds_apply_cap, L
             P.alg_prec_scale_flops += 2.0 * nb * ng * ng;
         }
         cs.g_count = static_cast<int32_t>(P.cell_groups.size()) - cs.g_begin;
-        if (cs.nB > 0) P.cell_scale.push_back(cs);
+        if (cs.nB > 0) {
+            P.cell_scale.push_back(cs);
+            P.max_cell_groups = std::max(P.max_cell_groups, cs.g_count);
+        }
     }
 
     // ---- skeletonized groups: rows of M = A[R_g, g] from the one or two cells ----
@@ -473,7 +483,7 @@ void build_separators(const GridInfo& gi, PlanScratch& scr, int lds_apply_cap, L
         }
         sk.r = r;
         sk.moff = moff;
-        moff += align_up(static_cast<int64_t>(std::max(r, 1)) * n, 32);
+        moff += align_up(static_cast<int64_t>(std::max(r, 1)) * (n | 1), 32);   // row-major, odd stride
         sk.toff = toff;
         toff += align_up(static_cast<int64_t>(n) * n / 4 + 1, 32);
         sk.goff = goff;
@@ -611,6 +621,7 @@ void validate_separators(const LevelPlan& P) {
     for (const SepDesc& s : P.sep_desc) {
         need(s.nslot >= 1 && s.nslot <= kMaxSlots, "sep slots", s.nslot, kMaxSlots);
         need(s.n >= 1 && s.loff >= 0 && s.loff + static_cast<int64_t>(s.n) * s.n <= P.lg_elems, "sep L bounds");
+        need(s.lioff >= 0 && s.lioff + 256 * static_cast<int64_t>((s.n + 15) / 16) <= P.li_elems, "sep Li bounds");
         need(s.dofs >= 0 && s.dofs + s.n <= static_cast<int64_t>(P.sep_dofs.size()), "sep dofs");
         for (int q = 0; q < s.nslot; ++q) {
             const int c = s.slot_cell[q];
@@ -625,6 +636,8 @@ void validate_separators(const LevelPlan& P) {
             const CellGroup& g = P.cell_groups[e];
             need(g.off >= cs.nI && g.off + g.n <= cs.nI + cs.nB, "scale group offset");
             need(g.loff >= 0 && g.loff + static_cast<int64_t>(g.n) * g.n <= P.lg_elems, "scale group L");
+            need(g.lioff >= 0 && g.lioff + 256 * static_cast<int64_t>((g.n + 15) / 16) <= P.li_elems,
+                 "scale group Li");
             tot += g.n;
         }
         need(tot == cs.nB, "scale groups cover the boundary", tot, cs.nB);
@@ -647,7 +660,7 @@ void validate_separators(const LevelPlan& P) {
             if (p1 >= 0) need(p1 < P.c_nf[k.cell[0]], "skel row pos1");
             if (p2 >= 0) need(k.nslot == 2 && p2 < P.c_nf[k.cell[1]], "skel row pos2");
         }
-        need(k.moff >= 0 && k.moff + static_cast<int64_t>(std::max(k.r, 1)) * k.n <= P.m_elems, "skel M bounds");
+        need(k.moff >= 0 && k.moff + static_cast<int64_t>(std::max(k.r, 1)) * (k.n | 1) <= P.m_elems, "skel M bounds");
         need(k.toff >= 0 && k.toff + static_cast<int64_t>(k.n) * k.n / 4 + 1 <= P.t_elems, "skel T bounds");
         need(k.goff >= 0 && k.goff + static_cast<int64_t>(k.n) * k.n <= P.g_elems, "skel G bounds");
         need(k.poff >= 0 && k.poff + k.n <= P.skel_ntotal, "skel perm bounds");

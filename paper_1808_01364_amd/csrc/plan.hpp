@@ -64,11 +64,11 @@ struct LevelPlan {
     std::vector<ApplyDesc> sep_apply;
     std::vector<GatherDesc> gather;
     std::vector<int32_t> sep_dofs;         // unknowns of every separator group
-    int64_t lg_elems = 0, m_elems = 0, t_elems = 0, g_elems = 0, y_elems = 0;
+    int64_t lg_elems = 0, li_elems = 0, m_elems = 0, t_elems = 0, g_elems = 0, y_elems = 0;
     int64_t ext_elems = 0;                 // per-panel nonzero row ends of the cells' L
     int64_t ws_elems = 0;                  // global workspace for oversized applies
     int32_t skel_ntotal = 0;               // sum of skeletonized group sizes
-    int32_t max_nf = 0, max_sep_n = 0, max_skel_n = 0;
+    int32_t max_nf = 0, max_sep_n = 0, max_skel_n = 0, max_cell_groups = 0;
     double flops = 0.0;                    // algorithmic flops (cells + groups + skeletons)
     // algorithmic work per launch class (what the method must do, not what a kernel does):
     // level-0 cell interiors count as banded matrices of bandwidth (m-1)^(d-1)

@@ -577,20 +577,18 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         t0 = now();
         if (LD.precond && !P.sep_desc.empty()) {
             const int cap = panel_cap_for(P.max_sep_n, 0);
+            double* li = static_cast<double*>(f->dalloc(P.li_elems * sizeof(double)));
             KTIMED(f, s, RHIF_K_PRECOND_CHOL, P.alg_prec_chol_flops, 0.0,
                    hipLaunchKernelGGL(k_precond_groups, dim3(P.sep_desc.size()), dim3(256), potrf_lds(cap, 0), s,
-                                      LD.sep, LD.cref, LD.front, LD.lg, cap, lvl, f->err));
-            if (!P.cell_groups.empty()) {
-                int need = 0;
-                for (const auto& cgr : P.cell_groups) {
-                    const int nB = P.cell_scale[cgr.cell].nB;
-                    need = std::max(need, nB * cgr.n + cgr.n * cgr.n);
-                }
-                const int cap2 = std::min(need, kLdsMaxDoubles);
+                                      LD.sep, LD.cref, LD.front, LD.lg, li, cap, lvl, f->err));
+            if (!P.cell_scale.empty()) {
+                const int pstride = 17 * ((P.max_sep_n + 15) / 16) * 16;
+                if (4 * pstride > kLdsMaxDoubles) fail(RHIF_ENOMEM, "a separator group is too large for this version");
+                const int gc = P.max_cell_groups;
                 KTIMED(f, s, RHIF_K_PRECOND_SCALE, P.alg_prec_scale_flops, 0.0,
-                       hipLaunchKernelGGL(k_precond_scale, dim3(P.cell_groups.size()), dim3(256),
-                                          static_cast<size_t>(cap2) * sizeof(double), s, LD.cs, LD.cg, LD.lg,
-                                          LD.front, cap2));
+                       hipLaunchKernelGGL(k_precond_scale, dim3(P.cell_scale.size(), gc * (gc + 1) / 2), dim3(256),
+                                          static_cast<size_t>(4 * pstride) * sizeof(double), s, LD.cs, LD.cg, LD.lg,
+                                          li, LD.front, pstride));
             }
         }
         f->stats.n_groups[lvl] = LD.precond ? static_cast<int32_t>(P.sep_desc.size()) : 0;
@@ -604,18 +602,20 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             const int n = P.max_skel_n;
             int rmax = 1;
             for (const auto& sk : P.skel_desc) rmax = std::max(rmax, sk.r);
-            const int base = (n + 1) / 2 + 1 + n + 2;
+            // must match the LDS layout of k_skeletonize
+            const int base = (2 * n + 1) / 2 + 1 + 2 * 256 * std::max(1, (n + 63) / 64) + 2;
+            const int msz = rmax * (n | 1);
             const int full = kPotrfSmemFixed + 17 * n;        // potrf scratch with the whole panel
             int staged = 0, cap = 0;
             size_t lds = 0;
-            if (base + rmax * n + n * n + full <= kLdsMaxDoubles) {
+            if (base + msz + n * n + full <= kLdsMaxDoubles) {
                 staged = 3;
                 cap = n;
-                lds = static_cast<size_t>(base + rmax * n + n * n + full) * sizeof(double);
-            } else if (base + rmax * n + kPotrfSmemFixed <= kLdsMaxDoubles) {
+                lds = static_cast<size_t>(base + msz + n * n + full) * sizeof(double);
+            } else if (base + msz + kPotrfSmemFixed <= kLdsMaxDoubles) {
                 staged = 1;
-                cap = std::min(n, (kLdsMaxDoubles - base - rmax * n - kPotrfSmemFixed) / 17);
-                lds = static_cast<size_t>(base + rmax * n + kPotrfSmemFixed + 17 * cap) * sizeof(double);
+                cap = std::min(n, (kLdsMaxDoubles - base - msz - kPotrfSmemFixed) / 17);
+                lds = static_cast<size_t>(base + msz + kPotrfSmemFixed + 17 * cap) * sizeof(double);
             } else {
                 cap = panel_cap_for(n, base);
                 lds = potrf_lds(cap, base);
