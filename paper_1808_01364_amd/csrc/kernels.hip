@@ -287,8 +287,8 @@ __device__ __forceinline__ void wg_potrf_partial(double* __restrict__ A, int ld,
 // R_jj > eps R_11. Returns the rank k; row i <= j of column perm[j] then holds R[i][j].
 // part: 2 * 256 * ceil(n / cw) doubles; red: 2 doubles.
 // ---------------------------------------------------------------------------------------
-__device__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int r, int n, double eps, int* pos, int* perm,
-                            double* part, double* red) {
+__device__ __forceinline__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int r, int n, double eps, int* pos,
+                                            int* perm, double* part, double* red) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int cw = 1;
     while (cw < n && cw < 64) cw <<= 1;
@@ -902,45 +902,61 @@ __global__ __launch_bounds__(256) void k_precond_scale(const CellScaleDesc* __re
 //      the group's diagonal block is cleared. Couplings of the redundant unknowns to R are
 //      dropped simply by not carrying them to the next level.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict__ sd, const int32_t* __restrict__ rows,
-                                                     const CellRef* __restrict__ cells, double* __restrict__ F,
-                                                     double* __restrict__ Mpool, double* __restrict__ Tpool,
-                                                     double* __restrict__ Gpool, double eps, int32_t* __restrict__ kout,
-                                                     int32_t* __restrict__ pout, int panel_cap, int staged, int nmax,
-                                                     int rmax, int level, unsigned long long* err) {
-    // staged: bit 0 = M in LDS, bit 1 = G in LDS
-    extern __shared__ double smem[];
-    const SkelDesc g = sd[blockIdx.x];
+// LDS: pos, perm ints | row table (2 rmax ints) | QR partials | red (2) |
+//      [M (rmax x (nmax|1))] | [G (nmax^2)] | potrf scratch
+// SM / SG: M / G staged in LDS (else in the global pools), fixed at compile time so that
+// every access has a known address space.
+template <bool SM, bool SG>
+__device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t* __restrict__ rows,
+                                                const CellRef* __restrict__ cells, double* __restrict__ F,
+                                                double* __restrict__ Mpool, double* __restrict__ Tpool,
+                                                double* __restrict__ Gpool, double eps, int32_t* __restrict__ kout,
+                                                int32_t* __restrict__ pout, int panel_cap, int nmax, int rmax,
+                                                int level, unsigned long long* err, double* smem) {
     const int n = g.n, r = g.r, ldr = n | 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // LDS: pos, perm ints | QR partials | red (2) | [M (rmax x (nmax|1))] | [G (nmax^2)] | potrf
     const int ipd = (2 * nmax + 1) / 2 + 1;
     const int nbm = max(1, (nmax + 63) / 64);
     int* pos = reinterpret_cast<int*>(smem);
     int* perm = pos + nmax;
-    double* part = smem + ipd;
+    int* rwl = reinterpret_cast<int*>(smem + ipd);
+    double* part = smem + ipd + rmax;
     double* red = part + 2 * kWG * nbm;
     double* after = red + 2;
-    const bool stage_m = (staged & 1) != 0, stage_g = (staged & 2) != 0;
-    double* M = stage_m ? after : Mpool + g.moff;
-    double* gl = stage_m ? after + static_cast<size_t>(rmax) * (nmax | 1) : after;
-    double* Gw = stage_g ? gl : Gpool + g.goff;
-    double* psmem = stage_g ? gl + static_cast<size_t>(nmax) * nmax : gl;
+    double* __restrict__ M = SM ? after : Mpool + g.moff;
+    double* gl = SM ? after + static_cast<size_t>(rmax) * (nmax | 1) : after;
+    double* __restrict__ Gw = SG ? gl : Gpool + g.goff;
+    double* psmem = SG ? gl + static_cast<size_t>(nmax) * nmax : gl;
     const int32_t* rw = rows + static_cast<size_t>(g.rows) * 2;
     const CellRef c0 = cells[g.cell[0]];
     CellRef c1 = c0;
     if (g.nslot > 1) c1 = cells[g.cell[1]];
-    // 1. M = A[R_g, g] (row-major), the shares of both cells added
-    for (int j = wave; j < n; j += kWaves) {
-        const double* f0 = F + c0.off + static_cast<size_t>(g.off[0] + j) * c0.ld;
-        const double* f1 = F + c1.off + static_cast<size_t>(g.off[1] + j) * c1.ld;
-        for (int i = lane; i < r; i += 64) {
-            const int p1 = rw[2 * i], p2 = rw[2 * i + 1];
-            double v = 0.0;
-            if (p1 >= 0) v += f0[p1];
-            if (p2 >= 0) v += f1[p2];
-            M[static_cast<size_t>(i) * ldr + j] = v;
+    const double* f0 = F + c0.off + static_cast<size_t>(g.off[0]) * c0.ld;
+    const double* f1 = F + c1.off + static_cast<size_t>(g.off[1]) * c1.ld;
+    for (int e = tid; e < 2 * r; e += kWG) rwl[e] = rw[e];
+    __syncthreads();
+    // 1. M = A[R_g, g] (row-major), the shares of both cells added; four independent
+    //    loads in flight per thread
+    const int rn = r * n;
+    for (int e0 = tid; e0 < rn; e0 += 4 * kWG) {
+        double v[4];
+        int dst[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * kWG;
+            v[u] = 0.0;
+            dst[u] = -1;
+            if (e < rn) {
+                const int i = e % r, j = e / r;
+                const int p1 = rwl[2 * i], p2 = rwl[2 * i + 1];
+                if (p1 >= 0) v[u] += f0[p1 + static_cast<size_t>(j) * c0.ld];
+                if (p2 >= 0) v[u] += f1[p2 + static_cast<size_t>(j) * c1.ld];
+                dst[u] = i * ldr + j;
+            }
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (dst[u] >= 0) M[dst[u]] = v[u];
     }
     __syncthreads();
     // 2. ID: rank k, pivot order, and T = R11^-1 R12 solved in place over R12
@@ -971,16 +987,24 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
     // 3. the zeroed blocks of eq. (2.2) in the order (redundant, skeleton). G first holds the
     //    whole permuted A_gg; then V = A_ht - A_hh T replaces the lower (h, t) block (A_ht
     //    stays in the upper one), then A~_tt = A_tt - T^T V - A_ht^T T (lower part).
-    for (int y = wave; y < n; y += kWaves) {
-        const int qy = y < nr ? perm[k + y] : perm[y - nr];
-        const double* f0 = F + c0.off + g.off[0] + static_cast<size_t>(g.off[0] + qy) * c0.ld;
-        const double* f1 = F + c1.off + g.off[1] + static_cast<size_t>(g.off[1] + qy) * c1.ld;
-        for (int x = lane; x < n; x += 64) {
-            const int qx = x < nr ? perm[k + x] : perm[x - nr];
-            double v = f0[qx];
-            if (g.nslot > 1) v += f1[qx];
-            Gw[x + static_cast<size_t>(y) * n] = v;
+    const int nn = n * n;
+    for (int e0 = tid; e0 < nn; e0 += 4 * kWG) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * kWG;
+            v[u] = 0.0;
+            if (e < nn) {
+                const int x = e % n, y = e / n;
+                const int qx = x < nr ? perm[k + x] : perm[x - nr];
+                const int qy = y < nr ? perm[k + y] : perm[y - nr];
+                v[u] = f0[g.off[0] + qx + static_cast<size_t>(qy) * c0.ld];
+                if (g.nslot > 1) v[u] += f1[g.off[1] + qx + static_cast<size_t>(qy) * c1.ld];
+            }
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (e0 + u * kWG < nn) Gw[e0 + u * kWG] = v[u];
     }
     __syncthreads();
     for (int e = tid; e < k * nr; e += kWG) {
@@ -1014,9 +1038,9 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
     wg_potrf_partial(Gw, n, n, nr, psmem, panel_cap, err, err_code(level, 2, blockIdx.x), nullptr);
     // 5. write back the skeleton block (and keep G for the apply)
     double* Gout = Gpool + g.goff;
-    for (int e = tid; e < n * n; e += kWG) {
+    for (int e = tid; e < nn; e += kWG) {
         const int a = e % n, b = e / n;
-        if (stage_g) Gout[e] = Gw[e];
+        if (SG) Gout[e] = Gw[e];
         if (a < k && b < k) {
             // skeleton a, b sit at positions perm[a], perm[b] of the group's ascending order
             F[c0.off + (g.off[0] + perm[a]) + static_cast<size_t>(g.off[0] + perm[b]) * c0.ld] =
@@ -1024,6 +1048,25 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
         }
         if (g.nslot > 1) F[c1.off + (g.off[1] + a) + static_cast<size_t>(g.off[1] + b) * c1.ld] = 0.0;
     }
+}
+
+__global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict__ sd, const int32_t* __restrict__ rows,
+                                                     const CellRef* __restrict__ cells, double* __restrict__ F,
+                                                     double* __restrict__ Mpool, double* __restrict__ Tpool,
+                                                     double* __restrict__ Gpool, double eps, int32_t* __restrict__ kout,
+                                                     int32_t* __restrict__ pout, int panel_cap, int staged, int nmax,
+                                                     int rmax, int level, unsigned long long* err) {
+    extern __shared__ double smem[];
+    const SkelDesc g = sd[blockIdx.x];
+    if (staged == 3)
+        skeletonize_one<true, true>(g, rows, cells, F, Mpool, Tpool, Gpool, eps, kout, pout, panel_cap, nmax, rmax,
+                                    level, err, smem);
+    else if (staged == 1)
+        skeletonize_one<true, false>(g, rows, cells, F, Mpool, Tpool, Gpool, eps, kout, pout, panel_cap, nmax, rmax,
+                                     level, err, smem);
+    else
+        skeletonize_one<false, false>(g, rows, cells, F, Mpool, Tpool, Gpool, eps, kout, pout, panel_cap, nmax, rmax,
+                                      level, err, smem);
 }
 
 // ---------------------------------------------------------------------------------------

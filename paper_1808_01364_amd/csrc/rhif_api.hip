@@ -603,7 +603,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             int rmax = 1;
             for (const auto& sk : P.skel_desc) rmax = std::max(rmax, sk.r);
             // must match the LDS layout of k_skeletonize
-            const int base = (2 * n + 1) / 2 + 1 + 2 * 256 * std::max(1, (n + 63) / 64) + 2;
+            const int base = (2 * n + 1) / 2 + 1 + rmax + 2 * 256 * std::max(1, (n + 63) / 64) + 2;
             const int msz = rmax * (n | 1);
             const int full = kPotrfSmemFixed + 17 * n;        // potrf scratch with the whole panel
             int staged = 0, cap = 0;
