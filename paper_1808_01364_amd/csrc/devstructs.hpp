@@ -87,6 +87,8 @@ struct SkelDesc {
     int64_t goff;        // skeleton block G (n x n): [A~_tt, .; A~_ht, A_hh]
     int32_t gid;         // index into the rank / pivot outputs
     int32_t poff;        // offset of this group's pivot order in the pivot output
+    int32_t lioff;       // inverses of the 16 x 16 diagonal blocks of L~ (room for n)
+    int32_t pad;
 };
 
 // One block of the factor apply: L in [0,nI)^2 and W^T in rows [nI, nI+nB) of columns
@@ -101,7 +103,7 @@ struct ApplyDesc {
     int32_t nB;
     int32_t dofs;        // offset of nI interior then nB boundary unknowns (global indices)
     int32_t ext;         // >= 0: per-panel nonzero row ends of L (see FrontDesc::ext)
-    int32_t pad;
+    int32_t li;          // offset of the inverses of L's 16 x 16 diagonal blocks (256 each)
 };
 
 // Gather of the up-sweep boundary contributions of the cells for one separator group.

@@ -626,11 +626,13 @@ __global__ __launch_bounds__(256) void k_front_extend(const Tile* __restrict__ t
 // Batched partial Cholesky of cell frontals (cell elimination, Sec. 2.1) or of the root.
 __global__ __launch_bounds__(256) void k_potrf_batch(const FrontDesc* __restrict__ desc, double* __restrict__ pool,
                                                      int panel_cap, int level, int step, unsigned long long* err,
-                                                     int32_t* __restrict__ ext) {
+                                                     int32_t* __restrict__ ext, double* __restrict__ linv) {
     extern __shared__ double smem[];
     const FrontDesc fd = desc[blockIdx.x];
+    const bool has = fd.ext >= 0;
     wg_potrf_partial(pool + fd.off, fd.ld, fd.n, fd.p, smem, panel_cap, err, err_code(level, step, fd.id),
-                     (ext != nullptr && fd.ext >= 0) ? ext + fd.ext : nullptr);
+                     (ext != nullptr && has) ? ext + fd.ext : nullptr,
+                     (linv != nullptr && has) ? linv + static_cast<size_t>(fd.ext) * 256 : nullptr);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -910,9 +912,10 @@ template <bool SM, bool SG>
 __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t* __restrict__ rows,
                                                 const CellRef* __restrict__ cells, double* __restrict__ F,
                                                 double* __restrict__ Mpool, double* __restrict__ Tpool,
-                                                double* __restrict__ Gpool, double eps, int32_t* __restrict__ kout,
-                                                int32_t* __restrict__ pout, int panel_cap, int nmax, int rmax,
-                                                int level, unsigned long long* err, double* smem) {
+                                                double* __restrict__ Gpool, double* __restrict__ skli, double eps,
+                                                int32_t* __restrict__ kout, int32_t* __restrict__ pout, int panel_cap,
+                                                int nmax, int rmax, int level, unsigned long long* err,
+                                                double* smem) {
     const int n = g.n, r = g.r, ldr = n | 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ipd = (2 * nmax + 1) / 2 + 1;
@@ -1035,7 +1038,7 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
     }
     __syncthreads();
     // 4. eliminate the redundant unknowns
-    wg_potrf_partial(Gw, n, n, nr, psmem, panel_cap, err, err_code(level, 2, blockIdx.x), nullptr);
+    wg_potrf_partial(Gw, n, n, nr, psmem, panel_cap, err, err_code(level, 2, blockIdx.x), nullptr, skli + g.lioff);
     // 5. write back the skeleton block (and keep G for the apply)
     double* Gout = Gpool + g.goff;
     for (int e = tid; e < nn; e += kWG) {
@@ -1053,19 +1056,20 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
 __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict__ sd, const int32_t* __restrict__ rows,
                                                      const CellRef* __restrict__ cells, double* __restrict__ F,
                                                      double* __restrict__ Mpool, double* __restrict__ Tpool,
-                                                     double* __restrict__ Gpool, double eps, int32_t* __restrict__ kout,
-                                                     int32_t* __restrict__ pout, int panel_cap, int staged, int nmax,
-                                                     int rmax, int level, unsigned long long* err) {
+                                                     double* __restrict__ Gpool, double* __restrict__ skli, double eps,
+                                                     int32_t* __restrict__ kout, int32_t* __restrict__ pout,
+                                                     int panel_cap, int staged, int nmax, int rmax, int level,
+                                                     unsigned long long* err) {
     extern __shared__ double smem[];
     const SkelDesc g = sd[blockIdx.x];
     if (staged == 3)
-        skeletonize_one<true, true>(g, rows, cells, F, Mpool, Tpool, Gpool, eps, kout, pout, panel_cap, nmax, rmax,
+        skeletonize_one<true, true>(g, rows, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout, panel_cap, nmax, rmax,
                                     level, err, smem);
     else if (staged == 1)
-        skeletonize_one<true, false>(g, rows, cells, F, Mpool, Tpool, Gpool, eps, kout, pout, panel_cap, nmax, rmax,
+        skeletonize_one<true, false>(g, rows, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout, panel_cap, nmax, rmax,
                                      level, err, smem);
     else
-        skeletonize_one<false, false>(g, rows, cells, F, Mpool, Tpool, Gpool, eps, kout, pout, panel_cap, nmax, rmax,
+        skeletonize_one<false, false>(g, rows, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout, panel_cap, nmax, rmax,
                                       level, err, smem);
 }
 
@@ -1238,6 +1242,260 @@ __global__ __launch_bounds__(256) void k_apply_down(const ApplyDesc* __restrict_
             for (int a = 0; a < d.nI; ++a) acc += T[c + static_cast<size_t>(a) * d.nB] * zI[a];
             z[db[c]] = zB[c] - acc;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Factor apply, split form for blocks with n_I <= kSplitApplyMaxI: the triangular solves
+// (one workgroup per block) and the W products (one workgroup per 64 rows or columns of a
+// block) are separate launches. The solves go by 16-column panels of L with the stored
+// inverses Li of its diagonal blocks; the next panel's entries of L and rows of Li are
+// loaded into registers while the current panel is processed:
+//   forward  (L z = b):   z_J = Li_J z_J, then z_i -= L[i, J] z_J for the rows below;
+//   backward (L^T z = b): z_J = Li_J^T z_J, then z_k -= L[J, k]^T z_J for k before J.
+// Each thread owns one row (forward) or one column (backward) of a panel.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ void stage_apply_vectors(const ApplyDesc& d, const int32_t* __restrict__ dofs,
+                                                    const double* __restrict__ z, double* zI, double* zB, bool needB,
+                                                    int* ex, const int32_t* __restrict__ extp) {
+    const int32_t* di = dofs + d.dofs;
+    const int nt = (d.nI + 15) / 16;
+    for (int i = threadIdx.x; i < nt * 16; i += kWG) zI[i] = (i < d.nI) ? z[di[i]] : 0.0;
+    if (needB)
+        for (int c = threadIdx.x; c < d.nB; c += kWG) zB[c] = z[di[d.nI + c]];
+    for (int t = threadIdx.x; t < nt; t += kWG) ex[t] = (extp != nullptr && d.ext >= 0) ? extp[d.ext + t] : d.nI;
+}
+
+// Up-sweep solve: [z_I -= T^T z_B]; z_I <- L^-1 z_I.
+__global__ __launch_bounds__(256) void k_apply_trsv_up(const ApplyDesc* __restrict__ ad, const double* __restrict__ pool,
+                                                       const double* __restrict__ lip, const double* __restrict__ Tp,
+                                                       const int32_t* __restrict__ dofs, double* __restrict__ z,
+                                                       const int32_t* __restrict__ extp) {
+    extern __shared__ double smem[];
+    const ApplyDesc d = ad[blockIdx.x];
+    const int nI = d.nI, nB = d.nB, ld = d.ld;
+    const int nt = (nI + 15) / 16;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* zI = smem;
+    double* zB = zI + nt * 16;
+    const bool hasT = d.toff >= 0;
+    int* ex = reinterpret_cast<int*>(zB + (hasT ? nB : 0));
+    stage_apply_vectors(d, dofs, z, zI, zB, hasT, ex, extp);
+    __syncthreads();
+    if (hasT) {
+        const double* T = Tp + d.toff;
+        for (int a = tid; a < nI; a += kWG) {
+            double acc = 0.0, acc1 = 0.0;
+            const double* Ta = T + static_cast<size_t>(a) * nB;
+            int c = 0;
+            for (; c + 1 < nB; c += 2) {
+                acc += Ta[c] * zB[c];
+                acc1 += Ta[c + 1] * zB[c + 1];
+            }
+            if (c < nB) acc += Ta[c] * zB[c];
+            zI[a] -= acc + acc1;
+        }
+        __syncthreads();
+    }
+    const double* L = pool + d.off;
+    const double* li = lip + d.li;
+    const bool solver = (wave == 0 && lane < 16);
+    double lv[16], lr[16], lvn[16], lrn[16];
+    auto load = [&](int t, double (&v)[16], double (&r)[16]) {
+        const int j0 = 16 * t, jb = min(16, nI - j0);
+        const int i = j0 + 16 + tid;
+        const bool ok = i < ex[t];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) v[c] = (ok && c < jb) ? L[i + static_cast<size_t>(j0 + c) * ld] : 0.0;
+        if (solver) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) r[k] = li[t * 256 + lane * 16 + k];
+        }
+    };
+    load(0, lvn, lrn);
+    for (int t = 0; t < nt; ++t) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            lv[c] = lvn[c];
+            lr[c] = lrn[c];
+        }
+        if (t + 1 < nt) load(t + 1, lvn, lrn);
+        const int j0 = 16 * t;
+        if (solver) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) acc += lr[k] * zI[j0 + k];
+            zI[j0 + lane] = acc;
+        }
+        __syncthreads();
+        const int i = j0 + 16 + tid;
+        if (i < ex[t]) {
+            double acc = zI[i];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) acc -= lv[c] * zI[j0 + c];
+            zI[i] = acc;
+        }
+        __syncthreads();
+    }
+    const int32_t* di = dofs + d.dofs;
+    for (int i = tid; i < nI; i += kWG) z[di[i]] = zI[i];
+}
+
+// Down-sweep solve: z_I <- L^-T z_I; [z_B -= T z_I].
+__global__ __launch_bounds__(256) void k_apply_trsv_dn(const ApplyDesc* __restrict__ ad, const double* __restrict__ pool,
+                                                       const double* __restrict__ lip, const double* __restrict__ Tp,
+                                                       const int32_t* __restrict__ dofs, double* __restrict__ z,
+                                                       const int32_t* __restrict__ extp) {
+    extern __shared__ double smem[];
+    const ApplyDesc d = ad[blockIdx.x];
+    const int nI = d.nI, nB = d.nB, ld = d.ld;
+    const int nt = (nI + 15) / 16;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* zI = smem;
+    double* zB = zI + nt * 16;
+    const bool hasT = d.toff >= 0;
+    int* ex = reinterpret_cast<int*>(zB + (hasT ? nB : 0));
+    stage_apply_vectors(d, dofs, z, zI, zB, hasT, ex, extp);
+    __syncthreads();
+    const double* L = pool + d.off;
+    const double* li = lip + d.li;
+    const bool solver = (wave == 0 && lane < 16);
+    double lv[16], lr[16], lvn[16], lrn[16];
+    // thread k owns column k < j0 of the row panel J (rows j0..j0+15)
+    auto load = [&](int t, double (&v)[16], double (&r)[16]) {
+        const int j0 = 16 * t, jb = min(16, nI - j0);
+        const int k = tid;
+        const bool ok = k < j0 && ex[k >> 4] > j0;
+        const double* Lk = L + static_cast<size_t>(k) * ld + j0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = (ok && q < jb) ? Lk[q] : 0.0;
+        if (solver) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) r[q] = li[t * 256 + q * 16 + lane];
+        }
+    };
+    load(nt - 1, lvn, lrn);
+    for (int t = nt - 1; t >= 0; --t) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            lv[c] = lvn[c];
+            lr[c] = lrn[c];
+        }
+        if (t > 0) load(t - 1, lvn, lrn);
+        const int j0 = 16 * t;
+        if (solver) {
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc += lr[q] * zI[j0 + q];
+            zI[j0 + lane] = acc;
+        }
+        __syncthreads();
+        if (tid < j0) {
+            double acc = zI[tid];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc -= lv[q] * zI[j0 + q];
+            zI[tid] = acc;
+        }
+        __syncthreads();
+    }
+    const int32_t* di = dofs + d.dofs;
+    for (int i = tid; i < nI; i += kWG) z[di[i]] = zI[i];
+    if (hasT) {
+        const double* T = Tp + d.toff;
+        for (int c = tid; c < nB; c += kWG) {
+            double acc = 0.0, acc1 = 0.0;
+            int a = 0;
+            for (; a + 1 < nI; a += 2) {
+                acc += T[c + static_cast<size_t>(a) * nB] * zI[a];
+                acc1 += T[c + static_cast<size_t>(a + 1) * nB] * zI[a + 1];
+            }
+            if (a < nI) acc += T[c + static_cast<size_t>(a) * nB] * zI[a];
+            z[di[nI + c]] = zB[c] - (acc + acc1);
+        }
+    }
+}
+
+// Up-sweep product y = W^T z_I for 64 rows b of W^T per workgroup (lanes over b, waves
+// over quarters of the sum, eight loads in flight); y goes to the gather scratch or is
+// subtracted from z_B.
+__global__ __launch_bounds__(256) void k_apply_gemv_up(const ApplyDesc* __restrict__ ad, const double* __restrict__ pool,
+                                                       const int32_t* __restrict__ dofs, double* __restrict__ z,
+                                                       double* __restrict__ ybuf) {
+    extern __shared__ double smem[];
+    const ApplyDesc d = ad[blockIdx.x];
+    const int nI = d.nI, nB = d.nB, ld = d.ld;
+    const int b0 = 64 * static_cast<int>(blockIdx.y);
+    if (b0 >= nB) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* zI = smem;
+    double* red = smem + nI;
+    const int32_t* di = dofs + d.dofs;
+    for (int i = tid; i < nI; i += kWG) zI[i] = z[di[i]];
+    __syncthreads();
+    const int b = b0 + lane;
+    const int q0 = (nI * wave) / kWaves, q1 = (nI * (wave + 1)) / kWaves;
+    double acc = 0.0;
+    if (b < nB) {
+        const double* Wb = pool + d.off + nI + b;
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int i = q0;
+        for (; i + 7 < q1; i += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] += Wb[static_cast<size_t>(i + u) * ld] * zI[i + u];
+        }
+        for (; i < q1; ++i) a[0] += Wb[static_cast<size_t>(i) * ld] * zI[i];
+        acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    }
+    red[wave * 64 + lane] = acc;
+    __syncthreads();
+    if (wave == 0 && b < nB) {
+        const double y = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+        if (d.yoff >= 0) ybuf[d.yoff + b] = y;
+        else z[di[nI + b]] -= y;
+    }
+}
+
+// Down-sweep product z_I -= W z_B for 64 unknowns i of z_I per workgroup: 64 x 64 tiles of
+// W^T are read coalesced (along b) into LDS and summed along b by (i, quarter) threads.
+__global__ __launch_bounds__(256) void k_apply_gemv_dn(const ApplyDesc* __restrict__ ad, const double* __restrict__ pool,
+                                                       const int32_t* __restrict__ dofs, double* __restrict__ z) {
+    extern __shared__ double smem[];
+    const ApplyDesc d = ad[blockIdx.x];
+    const int nI = d.nI, nB = d.nB, ld = d.ld;
+    const int i0 = 64 * static_cast<int>(blockIdx.y);
+    if (i0 >= nI || nB == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* tile = smem;                 // [i][b], stride 65
+    double* zB = smem + 64 * 65;
+    double* red = zB + nB;
+    const int32_t* di = dofs + d.dofs;
+    for (int c = tid; c < nB; c += kWG) zB[c] = z[di[nI + c]];
+    const double* Wt = pool + d.off + nI;
+    double acc = 0.0;
+    for (int bc = 0; bc < nB; bc += 64) {
+        __syncthreads();
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + u * kWG;
+            const int br = e & 63, ir = e >> 6;
+            const int b = bc + br, i = i0 + ir;
+            v[u] = (b < nB && i < nI) ? Wt[b + static_cast<size_t>(i) * ld] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + u * kWG;
+            tile[(e >> 6) * 65 + (e & 63)] = v[u];
+        }
+        __syncthreads();
+        const int bl = min(64, nB - bc);
+        for (int br = wave * 16; br < min(bl, wave * 16 + 16); ++br) acc += tile[lane * 65 + br] * zB[bc + br];
+    }
+    red[wave * 64 + lane] = acc;
+    __syncthreads();
+    if (wave == 0 && i0 + lane < nI) {
+        const double s = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+        z[di[i0 + lane]] -= s;
     }
 }
 

@@ -15,7 +15,7 @@ __global__ void k_front_csr(const Tile* tiles, const CellRef* cells, const int32
 __global__ void k_front_extend(const Tile* tiles, const CellRef* cells, const int32_t* src, int W,
                                const CellRef* child, const double* Fc, double* F);
 __global__ void k_potrf_batch(const FrontDesc* desc, double* pool, int panel_cap, int level, int step,
-                              unsigned long long* err, int32_t* ext);
+                              unsigned long long* err, int32_t* ext, double* linv);
 __global__ void k_chol_lead(const FrontDesc* desc, double* pool, double* linv, int lds_pmax, int level,
                             unsigned long long* err, int32_t* ext);
 __global__ void k_trsm_rows(const FrontDesc* desc, double* pool, const double* linv, int pstride);
@@ -25,13 +25,20 @@ __global__ void k_precond_groups(const SepDesc* sd, const CellRef* cells, const 
 __global__ void k_precond_scale(const CellScaleDesc* cd, const CellGroup* cg, const double* Lg, const double* Li,
                                 double* F, int pstride);
 __global__ void k_skeletonize(const SkelDesc* sd, const int32_t* rows, const CellRef* cells, double* F,
-                              double* Mpool, double* Tpool, double* Gpool, double eps, int32_t* kout,
+                              double* Mpool, double* Tpool, double* Gpool, double* skli, double eps, int32_t* kout,
                               int32_t* pout, int panel_cap, int staged, int nmax, int rmax, int level,
                               unsigned long long* err);
 __global__ void k_apply_up(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
                            double* z, double* ybuf, double* ws, const int32_t* ext);
 __global__ void k_apply_down(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
                              double* z, double* ws, const int32_t* ext);
+__global__ void k_apply_trsv_up(const ApplyDesc* ad, const double* pool, const double* lip, const double* Tp,
+                                const int32_t* dofs, double* z, const int32_t* extp);
+__global__ void k_apply_trsv_dn(const ApplyDesc* ad, const double* pool, const double* lip, const double* Tp,
+                                const int32_t* dofs, double* z, const int32_t* extp);
+__global__ void k_apply_gemv_up(const ApplyDesc* ad, const double* pool, const int32_t* dofs, double* z,
+                                double* ybuf);
+__global__ void k_apply_gemv_dn(const ApplyDesc* ad, const double* pool, const int32_t* dofs, double* z);
 __global__ void k_sep_gather(const GatherDesc* gd, const int32_t* dofs, const double* ybuf, double* z);
 __global__ void k_spmv_dot(int64_t N, const int32_t* rp, const int32_t* ci, const double* v, const double* p,
                            double* q, double* part);
@@ -44,6 +51,7 @@ __global__ void k_copy(int64_t N, const double* x, double* y);
 __global__ void k_fill(int64_t N, double v, double* y);
 __global__ void k_set_u64(unsigned long long* p, unsigned long long v);
 
+constexpr int kSplitApplyMaxI = 272;        // split apply: one row / column per thread and panel
 constexpr int kApplyDiagDoubles = 32 * 33;   // LDS diagonal block of the apply kernels
 constexpr int kApplyExtDoubles = 256;         // LDS panel extents (up to 512 ints, n_I <= 8192)
 constexpr int kPotrfMaxTiles = 1024;          // frontal order up to 16384

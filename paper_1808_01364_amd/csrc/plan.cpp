@@ -61,7 +61,7 @@ void LevelPlan::reset() {
     sep_apply.clear();
     gather.clear();
     ncells = 0;
-    front_elems = lg_elems = li_elems = m_elems = t_elems = g_elems = y_elems = ws_elems = 0;
+    front_elems = lg_elems = li_elems = skli_elems = m_elems = t_elems = g_elems = y_elems = ws_elems = 0;
     skel_ntotal = max_nf = max_sep_n = max_skel_n = max_cell_groups = 0;
     flops = alg_elim_flops = alg_prec_chol_flops = alg_prec_scale_flops = alg_front_bytes = 0.0;
     alg_apply_cell_bytes = alg_apply_sep_bytes = alg_gather_bytes = 0.0;
@@ -317,6 +317,7 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
         if (nI == 0) continue;
         ApplyDesc ad{};
         ad.ext = P.cell_potrf[next_potrf++].ext;
+        ad.li = 256 * ad.ext;
         ad.off = P.c_foff[ci];
         ad.toff = -1;
         ad.yoff = nB > 0 ? yoff : -1;
@@ -388,6 +389,7 @@ void build_separators(const GridInfo& gi, PlanScratch& scr, int lds_apply_cap, L
 
         ApplyDesc ad{};
         ad.ext = -1;
+        ad.li = sd.lioff;
         ad.off = sd.loff;
         ad.toff = -1;
         ad.yoff = -1;
@@ -434,7 +436,7 @@ void build_separators(const GridInfo& gi, PlanScratch& scr, int lds_apply_cap, L
 
     // ---- skeletonized groups: rows of M = A[R_g, g] from the one or two cells ----
     int64_t moff = 0, toff = 0, goff = 0;
-    int32_t poff = 0;
+    int32_t poff = 0, skli = 0;
     for (int g = 0; g < ngroups; ++g) {
         if (P.gcls[g] != 1) continue;
         const int n = P.gptr[g + 1] - P.gptr[g];
@@ -488,6 +490,8 @@ void build_separators(const GridInfo& gi, PlanScratch& scr, int lds_apply_cap, L
         toff += align_up(static_cast<int64_t>(n) * n / 4 + 1, 32);
         sk.goff = goff;
         goff += align_up(static_cast<int64_t>(n) * n, 32);
+        sk.lioff = skli;
+        skli += 256 * ((n + 15) / 16);
         sk.gid = static_cast<int32_t>(P.skels.size());
         sk.poff = poff;
         poff += n;
@@ -499,6 +503,7 @@ void build_separators(const GridInfo& gi, PlanScratch& scr, int lds_apply_cap, L
     P.m_elems = std::max<int64_t>(moff, 32);
     P.t_elems = std::max<int64_t>(toff, 32);
     P.g_elems = std::max<int64_t>(goff, 32);
+    P.skli_elems = std::max<int64_t>(skli, 256);
     P.ws_elems = ws;
 }
 
@@ -532,6 +537,7 @@ void finish_level(const LevelPlan& P, const int32_t* k, const int32_t* perm, int
         skel_apply_bytes += 8.0 * (nr * (nr + 1.0) / 2.0 + 2.0 * kd * nr) + 8.0 * 2.0 * nd;
         ApplyDesc ad{};
         ad.ext = -1;
+        ad.li = sk.lioff;
         ad.off = sk.goff;
         ad.toff = (kk > 0) ? sk.toff : -1;
         ad.yoff = -1;

@@ -64,7 +64,7 @@ struct LevelPlan {
     std::vector<ApplyDesc> sep_apply;
     std::vector<GatherDesc> gather;
     std::vector<int32_t> sep_dofs;         // unknowns of every separator group
-    int64_t lg_elems = 0, li_elems = 0, m_elems = 0, t_elems = 0, g_elems = 0, y_elems = 0;
+    int64_t lg_elems = 0, li_elems = 0, skli_elems = 0, m_elems = 0, t_elems = 0, g_elems = 0, y_elems = 0;
     int64_t ext_elems = 0;                 // per-panel nonzero row ends of the cells' L
     int64_t ws_elems = 0;                  // global workspace for oversized applies
     int32_t skel_ntotal = 0;               // sum of skeletonized group sizes

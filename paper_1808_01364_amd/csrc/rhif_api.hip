@@ -132,6 +132,9 @@ struct LevelDev {
     double* tp = nullptr;
     double* gp = nullptr;
     int32_t* ext = nullptr;    // per-panel nonzero row ends of the cells' L
+    double* linv = nullptr;    // inverses of the 16 x 16 diagonal blocks: cells' L,
+    double* li = nullptr;      //   the block-Jacobi factors L_g,
+    double* skli = nullptr;    //   and the skeleton eliminations' L~
     // device views into the uploaded tables
     int32_t* cdofs = nullptr;
     rhif::CellRef* cref = nullptr;
@@ -151,12 +154,22 @@ struct LevelDev {
     int32_t* skeldofs = nullptr;
     int n_cell_ad = 0, n_sep_ad = 0, n_gather = 0, n_skel_ad = 0;
     size_t lds_cell = 0, lds_sep = 0, lds_skel = 0;
+    // largest n_I / n_B of each block family (split apply when n_I is small enough)
+    int mi_cell = 0, mb_cell = 0, mi_sep = 0, mi_skel = 0, mb_skel = 0;
     // algorithmic bytes of one apply sweep over each block family
     double b_cell = 0.0, b_sep = 0.0, b_gather = 0.0, b_skel = 0.0;
     int64_t bytes = 0;   // device bytes of the factor held for this level
     // ID choices (host)
     std::vector<int32_t> k, perm, first_dof, gsize;
 };
+
+void apply_max(const std::vector<rhif::ApplyDesc>& v, int& mi, int& mb) {
+    mi = mb = 0;
+    for (const auto& d : v) {
+        mi = std::max(mi, d.nI);
+        mb = std::max(mb, d.nB);
+    }
+}
 
 size_t apply_lds(const std::vector<rhif::ApplyDesc>& v) {
     int m = 0;
@@ -373,6 +386,11 @@ void set_kernel_attributes() {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_trsm_rows),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        for (const void* k : {reinterpret_cast<const void*>(&rhif::k_apply_trsv_up),
+                              reinterpret_cast<const void*>(&rhif::k_apply_trsv_dn),
+                              reinterpret_cast<const void*>(&rhif::k_apply_gemv_up),
+                              reinterpret_cast<const void*>(&rhif::k_apply_gemv_dn)})
+            (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     });
 }
 
@@ -442,6 +460,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         }
         LD.n_cell_ad = static_cast<int>(P.cell_apply.size());
         LD.lds_cell = apply_lds(P.cell_apply);
+        apply_max(P.cell_apply, LD.mi_cell, LD.mb_cell);
         LD.b_cell = P.alg_apply_cell_bytes;
         LD.front = static_cast<double*>(f->dalloc(P.front_elems * sizeof(double)));
         LD.ext = static_cast<int32_t*>(f->dalloc(std::max<int64_t>(P.ext_elems, 1) * sizeof(int32_t)));
@@ -480,9 +499,10 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             }
             const int cls = root ? RHIF_K_ROOT : (lvl == 0 ? RHIF_K_ELIM_LEAF : RHIF_K_ELIM_UPPER);
             const unsigned ncell = static_cast<unsigned>(P.cell_potrf.size());
+            LD.linv = static_cast<double*>(f->dalloc(std::max<int64_t>(P.ext_elems, 1) * 256 * sizeof(double)));
+            double* linv = LD.linv;
             if (!root && lvl > 0 && pmax <= kCholLdsPmax) {
                 // few cells: Cholesky, row solves and Schur update as three wide launches
-                double* linv = static_cast<double*>(f->dalloc(std::max<int64_t>(P.ext_elems, 1) * 256 * sizeof(double)));
                 const size_t lds1 = static_cast<size_t>(rhif::kPotrfSmemFixed + (pmax | 1) * pmax) * sizeof(double);
                 KTIMED(f, s, cls, P.alg_elim_flops, 0.0,
                        hipLaunchKernelGGL(k_chol_lead, dim3(ncell), dim3(256), lds1, s, LD.potrf, LD.front, linv,
@@ -502,7 +522,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                 const int cap = panel_cap_for(nmax, 0);
                 KTIMED(f, s, cls, P.alg_elim_flops, 0.0,
                        hipLaunchKernelGGL(k_potrf_batch, dim3(ncell), dim3(256), potrf_lds(cap, 0), s, LD.potrf,
-                                          LD.front, cap, lvl, root ? 3 : 0, f->err, LD.ext));
+                                          LD.front, cap, lvl, root ? 3 : 0, f->err, LD.ext, linv));
             }
         }
         phase(root ? 6 : 1, t0);
@@ -532,6 +552,10 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             LD.sepdofs = view<int32_t>(T, o_sdofs);
         }
         LD.n_sep_ad = static_cast<int>(P.sep_apply.size());
+        {
+            int mb = 0;
+            apply_max(P.sep_apply, LD.mi_sep, mb);
+        }
         LD.n_gather = static_cast<int>(P.gather.size());
         LD.lds_sep = apply_lds(P.sep_apply);
         LD.b_sep = P.alg_apply_sep_bytes;
@@ -577,7 +601,8 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         t0 = now();
         if (LD.precond && !P.sep_desc.empty()) {
             const int cap = panel_cap_for(P.max_sep_n, 0);
-            double* li = static_cast<double*>(f->dalloc(P.li_elems * sizeof(double)));
+            LD.li = static_cast<double*>(f->dalloc(P.li_elems * sizeof(double)));
+            double* li = LD.li;
             KTIMED(f, s, RHIF_K_PRECOND_CHOL, P.alg_prec_chol_flops, 0.0,
                    hipLaunchKernelGGL(k_precond_groups, dim3(P.sep_desc.size()), dim3(256), potrf_lds(cap, 0), s,
                                       LD.sep, LD.cref, LD.front, LD.lg, li, cap, lvl, f->err));
@@ -620,10 +645,11 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                 cap = panel_cap_for(n, base);
                 lds = potrf_lds(cap, base);
             }
+            LD.skli = static_cast<double*>(f->dalloc(P.skli_elems * sizeof(double)));
             KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
                    hipLaunchKernelGGL(k_skeletonize, dim3(nsk), dim3(256), lds, s, LD.skd, LD.rows, LD.cref, LD.front,
-                                      f->mp, LD.tp, LD.gp, f->o.eps, f->kout, f->pout, cap, staged, n, rmax, lvl,
-                                      f->err));
+                                      f->mp, LD.tp, LD.gp, LD.skli, f->o.eps, f->kout, f->pout, cap, staged, n, rmax,
+                                      lvl, f->err));
             char* h = hc.get_down((nsk + P.skel_ntotal) * sizeof(int32_t) + 64);
             hk = reinterpret_cast<int32_t*>(h);
             hp = hk + nsk;
@@ -678,6 +704,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         }
         LD.n_skel_ad = static_cast<int>(sk_ad.size());
         LD.lds_skel = apply_lds(sk_ad);
+        apply_max(sk_ad, LD.mi_skel, LD.mb_skel);
         active.swap(next);
         phase(5, t0);
     }
@@ -710,36 +737,84 @@ void launch_down(rhif_factor_s* f, double by, const rhif::ApplyDesc* ad, int n, 
            hipLaunchKernelGGL(rhif::k_apply_down, dim3(n), dim3(256), lds, s, ad, pool, tp, dofs, z, ws, ext));
 }
 
+// Split apply (solve and product launches) when every block of the family has
+// n_I <= kSplitApplyMaxI and the inverses of the diagonal blocks are there; else the
+// fused kernels.
+bool split_ok(int mi, int mb, const double* lip) {
+    return lip != nullptr && mi <= rhif::kSplitApplyMaxI && 64 * 65 + mb + 256 <= kLdsMaxDoubles &&
+           16 * ((mi + 15) / 16) + mb + (mi + 15) / 16 + 1 <= kLdsMaxDoubles;
+}
+
+size_t trsv_lds(int mi, int mb) {
+    return static_cast<size_t>(16 * ((mi + 15) / 16) + mb + (mi + 15) / 32 + 1) * sizeof(double);
+}
+
+void apply_up_block(rhif_factor_s* f, double by, const rhif::ApplyDesc* ad, int n, int mi, int mb, size_t lds,
+                    const double* pool, const double* lip, const double* tp, const int32_t* dofs, double* z,
+                    double* ybuf, hipStream_t s, const int32_t* ext = nullptr) {
+    if (n <= 0) return;
+    if (!split_ok(mi, mb, lip)) {
+        launch_up(f, by, ad, n, lds, pool, tp, dofs, z, ybuf, f->ws, s, ext);
+        return;
+    }
+    KTIMED(f, s, RHIF_K_APPLY_UP, 0.0, by,
+           hipLaunchKernelGGL(rhif::k_apply_trsv_up, dim3(n), dim3(256), trsv_lds(mi, mb), s, ad, pool, lip, tp, dofs,
+                              z, ext));
+    if (mb > 0)
+        KTIMED(f, s, RHIF_K_APPLY_UP, 0.0, 0.0,
+               hipLaunchKernelGGL(rhif::k_apply_gemv_up, dim3(n, (mb + 63) / 64), dim3(256),
+                                  static_cast<size_t>(mi + 256) * sizeof(double), s, ad, pool, dofs, z, ybuf));
+}
+
+void apply_down_block(rhif_factor_s* f, double by, const rhif::ApplyDesc* ad, int n, int mi, int mb, size_t lds,
+                      const double* pool, const double* lip, const double* tp, const int32_t* dofs, double* z,
+                      hipStream_t s, const int32_t* ext = nullptr) {
+    if (n <= 0) return;
+    if (!split_ok(mi, mb, lip)) {
+        launch_down(f, by, ad, n, lds, pool, tp, dofs, z, f->ws, s, ext);
+        return;
+    }
+    if (mb > 0)
+        KTIMED(f, s, RHIF_K_APPLY_DOWN, 0.0, by,
+               hipLaunchKernelGGL(rhif::k_apply_gemv_dn, dim3(n, (mi + 63) / 64), dim3(256),
+                                  static_cast<size_t>(64 * 65 + mb + 256) * sizeof(double), s, ad, pool, dofs, z));
+    KTIMED(f, s, RHIF_K_APPLY_DOWN, 0.0, mb > 0 ? 0.0 : by,
+           hipLaunchKernelGGL(rhif::k_apply_trsv_dn, dim3(n), dim3(256), trsv_lds(mi, mb), s, ad, pool, lip, tp, dofs,
+                              z, ext));
+}
+
 void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
     const int L = f->L;
     for (int lvl = 0; lvl < L; ++lvl) {
         LevelDev& LD = f->lev[lvl];
-        launch_up(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.lds_cell, LD.front, nullptr, LD.cdofs, z, f->ybuf,
-                  f->ws, s, LD.ext);
+        apply_up_block(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.mi_cell, LD.mb_cell, LD.lds_cell, LD.front, LD.linv,
+                       nullptr, LD.cdofs, z, f->ybuf, s, LD.ext);
         if (LD.n_gather > 0)
             KTIMED(f, s, RHIF_K_APPLY_GATHER, 0.0, LD.b_gather,
                    hipLaunchKernelGGL(rhif::k_sep_gather, dim3(LD.n_gather), dim3(256), 0, s, LD.gat, LD.sepdofs,
                                       f->ybuf, z));
         if (LD.precond)
-            launch_up(f, LD.b_sep, LD.sep_ad, LD.n_sep_ad, LD.lds_sep, LD.lg, nullptr, LD.sepdofs, z, nullptr, f->ws,
-                      s);
-        launch_up(f, LD.b_skel, LD.skel_ad, LD.n_skel_ad, LD.lds_skel, LD.gp, LD.tp, LD.skeldofs, z, nullptr, f->ws,
-                  s);
+            apply_up_block(f, LD.b_sep, LD.sep_ad, LD.n_sep_ad, LD.mi_sep, 0, LD.lds_sep, LD.lg, LD.li, nullptr,
+                           LD.sepdofs, z, nullptr, s);
+        apply_up_block(f, LD.b_skel, LD.skel_ad, LD.n_skel_ad, LD.mi_skel, LD.mb_skel, LD.lds_skel, LD.gp, LD.skli,
+                       LD.tp, LD.skeldofs, z, nullptr, s);
     }
     {
         LevelDev& LD = f->lev[L];
-        launch_up(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.lds_cell, LD.front, nullptr, LD.cdofs, z, f->ybuf,
-                  f->ws, s, LD.ext);
-        launch_down(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.lds_cell, LD.front, nullptr, LD.cdofs, z, f->ws, s,
-                    LD.ext);
+        apply_up_block(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.mi_cell, LD.mb_cell, LD.lds_cell, LD.front, LD.linv,
+                       nullptr, LD.cdofs, z, f->ybuf, s, LD.ext);
+        apply_down_block(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.mi_cell, LD.mb_cell, LD.lds_cell, LD.front,
+                         LD.linv, nullptr, LD.cdofs, z, s, LD.ext);
     }
     for (int lvl = L - 1; lvl >= 0; --lvl) {
         LevelDev& LD = f->lev[lvl];
-        launch_down(f, LD.b_skel, LD.skel_ad, LD.n_skel_ad, LD.lds_skel, LD.gp, LD.tp, LD.skeldofs, z, f->ws, s);
+        apply_down_block(f, LD.b_skel, LD.skel_ad, LD.n_skel_ad, LD.mi_skel, LD.mb_skel, LD.lds_skel, LD.gp, LD.skli,
+                         LD.tp, LD.skeldofs, z, s);
         if (LD.precond)
-            launch_down(f, LD.b_sep, LD.sep_ad, LD.n_sep_ad, LD.lds_sep, LD.lg, nullptr, LD.sepdofs, z, f->ws, s);
-        launch_down(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.lds_cell, LD.front, nullptr, LD.cdofs, z, f->ws, s,
-                    LD.ext);
+            apply_down_block(f, LD.b_sep, LD.sep_ad, LD.n_sep_ad, LD.mi_sep, 0, LD.lds_sep, LD.lg, LD.li, nullptr,
+                             LD.sepdofs, z, s);
+        apply_down_block(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.mi_cell, LD.mb_cell, LD.lds_cell, LD.front,
+                         LD.linv, nullptr, LD.cdofs, z, s, LD.ext);
     }
 }
 
