@@ -79,7 +79,7 @@ struct SkelDesc {
     int32_t n;           // group size
     int32_t r;           // rows of M = A[R_g, g]
     int32_t nslot;       // cells containing the group (1 or 2)
-    int32_t rows;        // offset of the (pos1, pos2) row table
+    int32_t grp;         // group index (its entry in the cells' group lists)
     int32_t cell[2];
     int32_t off[2];      // frontal position of the group's first unknown in each cell
     int64_t moff;        // scratch for M (r x n) and later A_hat,hat T

@@ -21,6 +21,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kWG = 256;
 constexpr int kWaves = kWG / 64;
 constexpr int kSyrkBatch = 2;   // Schur tiles accumulated per wave at a time
+constexpr int kMaxSkelSegs = 64; // row segments of one skeletonized group (2 x 26 in 3D)
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -909,7 +910,8 @@ __global__ __launch_bounds__(256) void k_precond_scale(const CellScaleDesc* __re
 // SM / SG: M / G staged in LDS (else in the global pools), fixed at compile time so that
 // every access has a known address space.
 template <bool SM, bool SG>
-__device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t* __restrict__ rows,
+__device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t* __restrict__ cgptr,
+                                                const int32_t* __restrict__ cgl, const int32_t* __restrict__ cgoff,
                                                 const CellRef* __restrict__ cells, double* __restrict__ F,
                                                 double* __restrict__ Mpool, double* __restrict__ Tpool,
                                                 double* __restrict__ Gpool, double* __restrict__ skli, double eps,
@@ -930,14 +932,80 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
     double* gl = SM ? after + static_cast<size_t>(rmax) * (nmax | 1) : after;
     double* __restrict__ Gw = SG ? gl : Gpool + g.goff;
     double* psmem = SG ? gl + static_cast<size_t>(nmax) * nmax : gl;
-    const int32_t* rw = rows + static_cast<size_t>(g.rows) * 2;
     const CellRef c0 = cells[g.cell[0]];
     CellRef c1 = c0;
     if (g.nslot > 1) c1 = cells[g.cell[1]];
     const double* f0 = F + c0.off + static_cast<size_t>(g.off[0]) * c0.ld;
     const double* f1 = F + c1.off + static_cast<size_t>(g.off[1]) * c1.ld;
-    for (int e = tid; e < 2 * r; e += kWG) rwl[e] = rw[e];
-    __syncthreads();
+    // rows of M: the other boundary groups of cell 0 (with cell 1's position where the group
+    // is shared), then the groups of cell 1 not in cell 0; segments (first row, count,
+    // position in cell 0, position in cell 1) built by one thread in the part buffer
+    {
+        int* seg = reinterpret_cast<int*>(part);
+        int* nseg = seg + 4 * kMaxSkelSegs;
+        if (tid == 0) {
+            int ns = 0, rr = 0;
+            const int a0 = cgptr[g.cell[0]], a1 = cgptr[g.cell[0] + 1];
+            const int b0 = g.nslot > 1 ? cgptr[g.cell[1]] : 0, b1 = g.nslot > 1 ? cgptr[g.cell[1] + 1] : 0;
+            bool ok = true;
+            for (int e = a0; e < a1; ++e) {
+                const int h = cgl[e];
+                if (h == g.grp) continue;
+                const int nh = ((e + 1 < a1) ? cgoff[e + 1] : c0.nf) - cgoff[e];
+                int o2 = -1;
+                for (int f2 = b0; f2 < b1; ++f2)
+                    if (cgl[f2] == h) o2 = cgoff[f2];
+                if (ns < kMaxSkelSegs) {
+                    seg[4 * ns] = rr;
+                    seg[4 * ns + 1] = nh;
+                    seg[4 * ns + 2] = cgoff[e];
+                    seg[4 * ns + 3] = o2;
+                } else {
+                    ok = false;
+                }
+                ++ns;
+                rr += nh;
+            }
+            for (int f2 = b0; f2 < b1; ++f2) {
+                const int h = cgl[f2];
+                if (h == g.grp) continue;
+                bool shared = false;
+                for (int e = a0; e < a1; ++e) shared = shared || (cgl[e] == h);
+                if (shared) continue;
+                const int nh = ((f2 + 1 < b1) ? cgoff[f2 + 1] : c1.nf) - cgoff[f2];
+                if (ns < kMaxSkelSegs) {
+                    seg[4 * ns] = rr;
+                    seg[4 * ns + 1] = nh;
+                    seg[4 * ns + 2] = -1;
+                    seg[4 * ns + 3] = cgoff[f2];
+                } else {
+                    ok = false;
+                }
+                ++ns;
+                rr += nh;
+            }
+            if (!ok || rr != r) {
+                report(err, err_code(level, 7, blockIdx.x));
+                ns = 0;
+            }
+            *nseg = ns;
+        }
+        __syncthreads();
+        const int ns = *nseg;
+        for (int i = tid; i < r; i += kWG) {
+            int p1 = -1, p2 = -1;
+            for (int q = 0; q < ns; ++q) {
+                const int t = i - seg[4 * q];
+                if (t >= 0 && t < seg[4 * q + 1]) {
+                    p1 = seg[4 * q + 2] >= 0 ? seg[4 * q + 2] + t : -1;
+                    p2 = seg[4 * q + 3] >= 0 ? seg[4 * q + 3] + t : -1;
+                }
+            }
+            rwl[2 * i] = p1;
+            rwl[2 * i + 1] = p2;
+        }
+        __syncthreads();
+    }
     // 1. M = A[R_g, g] (row-major), the shares of both cells added; four independent
     //    loads in flight per thread
     const int rn = r * n;
@@ -1053,7 +1121,8 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
     }
 }
 
-__global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict__ sd, const int32_t* __restrict__ rows,
+__global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict__ sd, const int32_t* __restrict__ cgptr,
+                                                     const int32_t* __restrict__ cgl, const int32_t* __restrict__ cgoff,
                                                      const CellRef* __restrict__ cells, double* __restrict__ F,
                                                      double* __restrict__ Mpool, double* __restrict__ Tpool,
                                                      double* __restrict__ Gpool, double* __restrict__ skli, double eps,
@@ -1063,13 +1132,13 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
     extern __shared__ double smem[];
     const SkelDesc g = sd[blockIdx.x];
     if (staged == 3)
-        skeletonize_one<true, true>(g, rows, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout, panel_cap, nmax, rmax,
+        skeletonize_one<true, true>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout, panel_cap, nmax, rmax,
                                     level, err, smem);
     else if (staged == 1)
-        skeletonize_one<true, false>(g, rows, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout, panel_cap, nmax, rmax,
+        skeletonize_one<true, false>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout, panel_cap, nmax, rmax,
                                      level, err, smem);
     else
-        skeletonize_one<false, false>(g, rows, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout, panel_cap, nmax, rmax,
+        skeletonize_one<false, false>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout, panel_cap, nmax, rmax,
                                       level, err, smem);
 }
 

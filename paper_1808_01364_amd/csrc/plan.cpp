@@ -46,7 +46,7 @@ void LevelPlan::reset() {
     level = w = nc1 = 0;
     root = false;
     for (auto* v : {&gptr, &gdofs, &gslot_cnt, &gslot_cell, &gslot_off, &c_nI, &c_nB, &c_nf, &c_ld, &c_dptr,
-                    &c_dofs, &c_gptr, &c_g, &c_goff, &seps, &skels, &src, &skel_rows, &sep_dofs})
+                    &c_dofs, &c_gptr, &c_g, &c_goff, &seps, &skels, &src, &sep_dofs, &sep_sorted})
         v->clear();
     gcls.clear();
     c_foff.clear();
@@ -103,10 +103,64 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
 
     // ---- classify the active unknowns and bucket them by key (stable) ----
     const size_t na = active.size();
-    std::vector<int32_t>& akey = scr.akey;
-    akey.resize(na);
-    scr.count.assign(nkeys + 1, 0);
-    {
+    P.sep_sorted.reserve(na);
+    int ngroups = 0;
+    scr.key2g.assign(nkeys, -1);
+    if (na > 0 && static_cast<int64_t>(na) == gi.N) {
+        // Every unknown is active (the leaf level): the groups are boxes of the grid,
+        // enumerated directly in key order, each in ascending order.
+        P.gdofs.resize(na);
+        P.gptr.clear();
+        P.gcls.clear();
+        size_t at = 0;
+        const int64_t s2 = static_cast<int64_t>(s) * s;
+        for (int64_t K = 0; K < nkeys; ++K) {
+            int lo[3] = {1, 1, 1}, hi[3] = {1, 1, 1};
+            int64_t r = K;
+            int even = 0;
+            bool empty = false;
+            for (int k = 0; k < d; ++k) {
+                const int kk = static_cast<int>(r % KB);
+                r /= KB;
+                const int64_t c = kk >> 1;
+                if (kk & 1) {
+                    lo[k] = static_cast<int>(c * w + 1);
+                    hi[k] = static_cast<int>(std::min<int64_t>((c + 1) * w - 1, s));
+                } else {
+                    ++even;
+                    lo[k] = hi[k] = static_cast<int>(c * w);
+                    if (c * w < 1 || c * w > s) empty = true;
+                }
+                if (lo[k] > hi[k]) empty = true;
+            }
+            if (empty) continue;
+            scr.key2g[K] = ngroups++;
+            P.gptr.push_back(static_cast<int32_t>(at));
+            P.gcls.push_back(static_cast<int8_t>(even));
+            for (int x2 = lo[2]; x2 <= hi[2]; ++x2)
+                for (int x1 = lo[1]; x1 <= hi[1]; ++x1) {
+                    const int64_t base = (d > 2 ? (x2 - 1) * s2 : 0) + (d > 1 ? static_cast<int64_t>(x1 - 1) * s : 0);
+                    for (int x0 = lo[0]; x0 <= hi[0]; ++x0) P.gdofs[at++] = static_cast<int32_t>(base + x0 - 1);
+                }
+        }
+        if (at != na) throw std::logic_error("leaf-level groups do not cover the grid");
+        P.gptr.push_back(static_cast<int32_t>(na));
+        // separator unknowns: some coordinate on a cell boundary
+        const int n2 = d > 2 ? s : 1, n1 = d > 1 ? s : 1;
+        for (int x2 = 1; x2 <= n2; ++x2)
+            for (int x1 = 1; x1 <= n1; ++x1) {
+                const int64_t base = (d > 2 ? (x2 - 1) * s2 : 0) + (d > 1 ? static_cast<int64_t>(x1 - 1) * s : 0);
+                const bool line = (d > 1 && x1 % w == 0) || (d > 2 && x2 % w == 0);
+                if (line) {
+                    for (int x0 = 1; x0 <= s; ++x0) P.sep_sorted.push_back(static_cast<int32_t>(base + x0 - 1));
+                } else {
+                    for (int64_t x0 = w; x0 <= s; x0 += w) P.sep_sorted.push_back(static_cast<int32_t>(base + x0 - 1));
+                }
+            }
+    } else {
+        std::vector<int32_t>& akey = scr.akey;
+        akey.resize(na);
+        scr.count.assign(nkeys + 1, 0);
         // The active list is ascending, so the coordinates can be advanced incrementally
         // from one unknown to the next instead of divided out of the linear index.
         std::vector<int32_t> keyk(static_cast<size_t>(s) + 1);
@@ -130,42 +184,46 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
                 cur_lin = i;
             }
             int64_t K = 0;
-            for (int k = 0; k < d; ++k) K += keyk[x[k]] * mulk[k];
+            int odd = 1;
+            for (int k = 0; k < d; ++k) {
+                K += keyk[x[k]] * mulk[k];
+                odd &= keyk[x[k]];
+            }
             akey[a] = static_cast<int32_t>(K);
             scr.count[K + 1]++;
+            if (!odd) P.sep_sorted.push_back(static_cast<int32_t>(i));
         }
-    }
-    scr.key2g.assign(nkeys, -1);
-    int ngroups = 0;
-    for (int64_t K = 0; K < nkeys; ++K)
-        if (scr.count[K + 1] > 0) scr.key2g[K] = ngroups++;
-    for (int64_t K = 0; K < nkeys; ++K) scr.count[K + 1] += scr.count[K];
-    P.gptr.assign(ngroups + 1, 0);
-    P.gcls.assign(ngroups, 0);
-    for (int64_t K = 0; K < nkeys; ++K) {
-        const int g = scr.key2g[K];
-        if (g < 0) continue;
-        P.gptr[g] = scr.count[K];
-        int64_t r = K;
-        int even = 0;
-        for (int k = 0; k < d; ++k) {
-            if (((r % KB) & 1) == 0) ++even;
-            r /= KB;
+        for (int64_t K = 0; K < nkeys; ++K)
+            if (scr.count[K + 1] > 0) scr.key2g[K] = ngroups++;
+        for (int64_t K = 0; K < nkeys; ++K) scr.count[K + 1] += scr.count[K];
+        P.gptr.assign(ngroups + 1, 0);
+        P.gcls.assign(ngroups, 0);
+        for (int64_t K = 0; K < nkeys; ++K) {
+            const int g = scr.key2g[K];
+            if (g < 0) continue;
+            P.gptr[g] = scr.count[K];
+            int64_t r = K;
+            int even = 0;
+            for (int k = 0; k < d; ++k) {
+                if (((r % KB) & 1) == 0) ++even;
+                r /= KB;
+            }
+            P.gcls[g] = static_cast<int8_t>(even);
         }
-        P.gcls[g] = static_cast<int8_t>(even);
-    }
-    P.gptr[ngroups] = static_cast<int32_t>(na);
-    P.gdofs.assign(na, 0);
-    {
+        P.gptr[ngroups] = static_cast<int32_t>(na);
+        P.gdofs.assign(na, 0);
         std::vector<int32_t> pos(scr.count.begin(), scr.count.end() - 1);
         for (size_t a = 0; a < na; ++a) P.gdofs[pos[akey[a]]++] = active[a];
     }
     const int cur = scr.cur;
-    for (int g = 0; g < ngroups; ++g)
+    // only separator unknowns can be active at the next level
+    for (int g = 0; g < ngroups; ++g) {
+        if (P.gcls[g] == 0) continue;
         for (int t = P.gptr[g]; t < P.gptr[g + 1]; ++t) {
             scr.dof_group[cur][P.gdofs[t]] = g;
             scr.dof_tpos[cur][P.gdofs[t]] = t - P.gptr[g];
         }
+    }
 
     // ---- cells: every geometric cell; frontal = interior, then boundary groups ----
     int64_t ncells = 1;
@@ -280,29 +338,50 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
     if (prev != nullptr) {
         const int pc = 1 - cur;
         const int pnc1 = prev->nc1;
-        P.src.assign(static_cast<size_t>(P.c_dofs.size()) * 2 * W, -1);
+        // parent cell of every cell of the level below
+        std::vector<int32_t>& par_of = scr.par_of;
+        par_of.resize(prev->ncells);
+        for (int64_t cc = 0; cc < prev->ncells; ++cc) {
+            int64_t rr = cc, par = 0, mul = 1;
+            for (int k = 0; k < d; ++k) {
+                par += ((rr % pnc1) / 2) * mul;
+                rr /= pnc1;
+                mul *= nc1;
+            }
+            par_of[cc] = static_cast<int32_t>(par);
+        }
+        P.src.resize(static_cast<size_t>(P.c_dofs.size()) * 2 * W);
+        int32_t* srcp = P.src.data();
         for (int64_t ci = 0; ci < ncells; ++ci) {
+            int last_g2 = -1, nq = 0;
+            int32_t qc[2 * kMaxSlots], qo[2 * kMaxSlots];
             for (int p = P.c_dptr[ci]; p < P.c_dptr[ci + 1]; ++p) {
                 const int32_t i = P.c_dofs[p];
                 const int g2 = scr.dof_group[pc][i];
                 const int t2 = scr.dof_tpos[pc][i];
                 if (g2 < 0) throw std::logic_error("active unknown missing from the level below");
-                int q = 0;
-                for (int sl = 0; sl < prev->gslot_cnt[g2]; ++sl) {
-                    const int cc = prev->gslot_cell[static_cast<size_t>(g2) * kMaxSlots + sl];
-                    int64_t rr = cc, par = 0, mul = 1;
-                    for (int k = 0; k < d; ++k) {
-                        par += ((rr % pnc1) / 2) * mul;
-                        rr /= pnc1;
-                        mul *= nc1;
+                if (g2 != last_g2) {
+                    // the child cells of ci that hold g2, and where
+                    last_g2 = g2;
+                    nq = 0;
+                    for (int sl = 0; sl < prev->gslot_cnt[g2]; ++sl) {
+                        const int cc = prev->gslot_cell[static_cast<size_t>(g2) * kMaxSlots + sl];
+                        if (par_of[cc] != ci) continue;
+                        qc[nq] = cc;
+                        qo[nq] = prev->gslot_off[static_cast<size_t>(g2) * kMaxSlots + sl];
+                        ++nq;
                     }
-                    if (par != ci) continue;
-                    P.src[(static_cast<size_t>(p) * W + q) * 2 + 0] = cc;
-                    P.src[(static_cast<size_t>(p) * W + q) * 2 + 1] =
-                        prev->gslot_off[static_cast<size_t>(g2) * kMaxSlots + sl] + t2;
-                    ++q;
+                    if (nq == 0 || nq > W) throw std::logic_error("frontal unknown without a child source");
                 }
-                if (q == 0) throw std::logic_error("frontal unknown without a child source");
+                int32_t* o = srcp + static_cast<size_t>(p) * W * 2;
+                for (int q = 0; q < nq; ++q) {
+                    o[2 * q] = qc[q];
+                    o[2 * q + 1] = qo[q] + t2;
+                }
+                for (int q = nq; q < W; ++q) {
+                    o[2 * q] = -1;
+                    o[2 * q + 1] = -1;
+                }
             }
         }
     }
@@ -445,42 +524,30 @@ void build_separators(const GridInfo& gi, PlanScratch& scr, int lds_apply_cap, L
         SkelDesc sk{};
         sk.n = n;
         sk.nslot = ns;
-        sk.rows = static_cast<int32_t>(P.skel_rows.size() / 2);
+        sk.grp = g;
         for (int sl = 0; sl < 2; ++sl) {
             sk.cell[sl] = sl < ns ? P.gslot_cell[static_cast<size_t>(g) * kMaxSlots + sl] : -1;
             sk.off[sl] = sl < ns ? P.gslot_off[static_cast<size_t>(g) * kMaxSlots + sl] : -1;
         }
-        // rows: the other boundary groups of the first cell (with the second cell's share
-        // added where the group is shared), then the second cell's remaining groups
+        // rows of M (built on the device in this order): the other boundary groups of the
+        // first cell (with the second cell's share added where the group is shared), then
+        // the second cell's remaining groups
         int r = 0;
         const int c1 = sk.cell[0];
         const int c2 = ns == 2 ? sk.cell[1] : -1;
-        auto find_in = [&](int cell, int grp) -> int {
+        auto in_cell = [&](int cell, int grp) -> bool {
             for (int e = P.c_gptr[cell]; e < P.c_gptr[cell + 1]; ++e)
-                if (P.c_g[e] == grp) return P.c_goff[e];
-            return -1;
+                if (P.c_g[e] == grp) return true;
+            return false;
         };
         for (int e = P.c_gptr[c1]; e < P.c_gptr[c1 + 1]; ++e) {
             const int h = P.c_g[e];
-            if (h == g) continue;
-            const int nh = P.gptr[h + 1] - P.gptr[h];
-            const int o2 = c2 >= 0 ? find_in(c2, h) : -1;
-            for (int t = 0; t < nh; ++t) {
-                P.skel_rows.push_back(P.c_goff[e] + t);
-                P.skel_rows.push_back(o2 >= 0 ? o2 + t : -1);
-            }
-            r += nh;
+            if (h != g) r += P.gptr[h + 1] - P.gptr[h];
         }
         if (c2 >= 0) {
             for (int e = P.c_gptr[c2]; e < P.c_gptr[c2 + 1]; ++e) {
                 const int h = P.c_g[e];
-                if (h == g || find_in(c1, h) >= 0) continue;
-                const int nh = P.gptr[h + 1] - P.gptr[h];
-                for (int t = 0; t < nh; ++t) {
-                    P.skel_rows.push_back(-1);
-                    P.skel_rows.push_back(P.c_goff[e] + t);
-                }
-                r += nh;
+                if (h != g && !in_cell(c1, h)) r += P.gptr[h + 1] - P.gptr[h];
             }
         }
         sk.r = r;
@@ -517,10 +584,6 @@ void finish_level(const LevelPlan& P, const int32_t* k, const int32_t* perm, int
     skel_apply.clear();
     skel_dofs.clear();
     const int32_t st = ++scr.stamp;
-    // interiors are eliminated
-    for (int g = 0; g + 1 < static_cast<int>(P.gptr.size()); ++g)
-        if (P.gcls[g] == 0)
-            for (int t = P.gptr[g]; t < P.gptr[g + 1]; ++t) scr.mark_stamp[P.gdofs[t]] = st;
     for (size_t e = 0; e < P.skel_desc.size(); ++e) {
         const SkelDesc& sk = P.skel_desc[e];
         const int g = P.skels[e];
@@ -554,9 +617,11 @@ void finish_level(const LevelPlan& P, const int32_t* k, const int32_t* perm, int
         for (int q = 0; q < kk; ++q) skel_dofs.push_back(gd[pv[q]]);
         skel_apply.push_back(ad);
     }
+    // the interiors are eliminated; of the separators the redundant unknowns go
+    (void)active;
     next_active.clear();
-    next_active.reserve(active.size());
-    for (int32_t i : active)
+    next_active.reserve(P.sep_sorted.size());
+    for (int32_t i : P.sep_sorted)
         if (scr.mark_stamp[i] != st) next_active.push_back(i);
     scr.cur = 1 - scr.cur;
 }
@@ -581,6 +646,18 @@ void validate_level(const LevelPlan& P, const LevelPlan* prev, int d) {
 }
 
 void validate_cells(const LevelPlan& P, const LevelPlan* prev, int d) {
+    // every cell's boundary groups follow its interior in list order and cover the frontal
+    // (the skeletonization kernel derives group sizes from consecutive offsets)
+    for (int64_t c = 0; c < P.ncells; ++c) {
+        int at = P.c_nI[c];
+        for (int e = P.c_gptr[c]; e < P.c_gptr[c + 1]; ++e) {
+            need(P.c_goff[e] == at, "cell group layout", P.c_goff[e], at);
+            const int h = P.c_g[e];
+            need(h >= 0 && h + 1 < static_cast<int64_t>(P.gptr.size()), "cell group index");
+            at += P.gptr[h + 1] - P.gptr[h];
+        }
+        need(at == P.c_nf[c], "cell groups cover the frontal", at, P.c_nf[c]);
+    }
     const int64_t ncd = static_cast<int64_t>(P.c_dofs.size());
     for (int c = 0; c < P.ncells; ++c) {
         const CellRef& r = P.cell_ref[c];
@@ -652,19 +729,12 @@ void validate_separators(const LevelPlan& P) {
     }
     for (const SkelDesc& k : P.skel_desc) {
         need(k.nslot >= 1 && k.nslot <= 2, "skel slots");
-        need(k.rows >= 0 && 2 * (static_cast<int64_t>(k.rows) + k.r) <= static_cast<int64_t>(P.skel_rows.size()),
-             "skel rows");
+        need(k.grp >= 0 && k.grp + 1 < static_cast<int64_t>(P.gptr.size()) && P.gptr[k.grp + 1] - P.gptr[k.grp] == k.n,
+             "skel group");
         for (int q = 0; q < k.nslot; ++q) {
             const int c = k.cell[q];
             need(c >= 0 && c < P.ncells, "skel cell");
             need(k.off[q] >= P.c_nI[c] && k.off[q] + k.n <= P.c_nf[c], "skel group offset");
-        }
-        for (int i = 0; i < k.r; ++i) {
-            const int p1 = P.skel_rows[2 * (static_cast<int64_t>(k.rows) + i)];
-            const int p2 = P.skel_rows[2 * (static_cast<int64_t>(k.rows) + i) + 1];
-            need(p1 >= 0 || p2 >= 0, "skel row without source");
-            if (p1 >= 0) need(p1 < P.c_nf[k.cell[0]], "skel row pos1");
-            if (p2 >= 0) need(k.nslot == 2 && p2 < P.c_nf[k.cell[1]], "skel row pos2");
         }
         need(k.moff >= 0 && k.moff + static_cast<int64_t>(std::max(k.r, 1)) * (k.n | 1) <= P.m_elems, "skel M bounds");
         need(k.toff >= 0 && k.toff + static_cast<int64_t>(k.n) * k.n / 4 + 1 <= P.t_elems, "skel T bounds");

@@ -47,6 +47,7 @@ struct LevelPlan {
 
     // separator groups (class >= 1) and the skeletonized ones (class 1)
     std::vector<int32_t> seps;
+    std::vector<int32_t> sep_sorted;   // the separator unknowns, ascending
     std::vector<int32_t> skels;
 
     // device-ready tables
@@ -59,7 +60,6 @@ struct LevelPlan {
     std::vector<CellGroup> cell_groups;
     std::vector<CellScaleDesc> cell_scale;
     std::vector<SkelDesc> skel_desc;
-    std::vector<int32_t> skel_rows;        // (pos1, pos2) pairs
     std::vector<ApplyDesc> cell_apply;
     std::vector<ApplyDesc> sep_apply;
     std::vector<GatherDesc> gather;
@@ -90,6 +90,7 @@ struct PlanScratch {
     std::vector<int32_t> key2g;
     std::vector<int32_t> dof_group[2], dof_tpos[2];
     std::vector<int32_t> mark_stamp, mark_row;
+    std::vector<int32_t> par_of;
     std::vector<int32_t> akey;             // per active unknown: its group key
     std::vector<int64_t> cell_y;           // per cell: its offset in the apply scratch
     int32_t stamp = 0;

@@ -145,7 +145,9 @@ struct LevelDev {
     rhif::CellGroup* cg = nullptr;
     rhif::CellScaleDesc* cs = nullptr;
     rhif::SkelDesc* skd = nullptr;
-    int32_t* rows = nullptr;
+    int32_t* cgptr = nullptr;   // boundary groups of every cell: list, entries, frontal offsets
+    int32_t* cgl = nullptr;
+    int32_t* cgoff = nullptr;
     rhif::ApplyDesc* cell_ad = nullptr;
     rhif::ApplyDesc* sep_ad = nullptr;
     rhif::GatherDesc* gat = nullptr;
@@ -337,6 +339,11 @@ void check_err(rhif_factor_s* f, hipStream_t s) {
         const int step = static_cast<int>((h >> 32) & 0xff);
         const int block = static_cast<int>(h & 0xffffffffu);
         char buf[256];
+        if (step == 7) {
+            std::snprintf(buf, sizeof(buf), "internal error: skeleton row table of group %d at level %d disagrees "
+                          "with the plan", block, ilevel);
+            fail(RHIF_EDEVICE, buf);
+        }
         if (step == 3 || ilevel >= f->l0)
             std::snprintf(buf, sizeof(buf), "not SPD: Cholesky pivot <= 0 or not finite at level %d, step %s, block %d",
                           step == 3 ? f->Lskel : ilevel - f->l0, step_name(step).c_str(), block);
@@ -539,14 +546,17 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         {
             Packer pk;
             const size_t o_sep = pk.add(P.sep_desc), o_cg = pk.add(P.cell_groups), o_cs = pk.add(P.cell_scale),
-                         o_skd = pk.add(P.skel_desc), o_rows = pk.add(P.skel_rows), o_sad = pk.add(P.sep_apply),
+                         o_skd = pk.add(P.skel_desc), o_cgp = pk.add(P.c_gptr), o_cgl = pk.add(P.c_g),
+                         o_cgo = pk.add(P.c_goff), o_sad = pk.add(P.sep_apply),
                          o_gat = pk.add(P.gather), o_sdofs = pk.add(P.sep_dofs);
             char* T = upload(f, pk, s);
             LD.sep = view<SepDesc>(T, o_sep);
             LD.cg = view<CellGroup>(T, o_cg);
             LD.cs = view<CellScaleDesc>(T, o_cs);
             LD.skd = view<SkelDesc>(T, o_skd);
-            LD.rows = view<int32_t>(T, o_rows);
+            LD.cgptr = view<int32_t>(T, o_cgp);
+            LD.cgl = view<int32_t>(T, o_cgl);
+            LD.cgoff = view<int32_t>(T, o_cgo);
             LD.sep_ad = view<ApplyDesc>(T, o_sad);
             LD.gat = view<GatherDesc>(T, o_gat);
             LD.sepdofs = view<int32_t>(T, o_sdofs);
@@ -647,7 +657,8 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             }
             LD.skli = static_cast<double*>(f->dalloc(P.skli_elems * sizeof(double)));
             KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
-                   hipLaunchKernelGGL(k_skeletonize, dim3(nsk), dim3(256), lds, s, LD.skd, LD.rows, LD.cref, LD.front,
+                   hipLaunchKernelGGL(k_skeletonize, dim3(nsk), dim3(256), lds, s, LD.skd, LD.cgptr, LD.cgl, LD.cgoff,
+                                      LD.cref, LD.front,
                                       f->mp, LD.tp, LD.gp, LD.skli, f->o.eps, f->kout, f->pout, cap, staged, n, rmax,
                                       lvl, f->err));
             char* h = hc.get_down((nsk + P.skel_ntotal) * sizeof(int32_t) + 64);
