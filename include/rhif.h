@@ -73,6 +73,11 @@ typedef struct {
 #define RHIF_FLAG_LEAF_SUBLEVELS 4 /* eliminate the leaf interiors by nested dissection on
                                       cells of width m/2^j >= 4 (exact; same F) instead of
                                       one dense elimination per leaf                      */
+#define RHIF_FLAG_SOLVE_GRAPHS 8   /* run the factor applies and PCG iterations of the handle
+                                      as HIP graphs, captured at the first rhif_apply /
+                                      rhif_pcg_solve call (pays off when the handle serves
+                                      many solves); ignored while the solve kernels are
+                                      timed with RHIF_FLAG_KERNEL_TIMES                    */
 #define RHIF_MAX_LEVELS 32
 
 /* Kernel classes of rhif_stats_t.kernel_* */

@@ -115,4 +115,24 @@ struct GatherDesc {
     int64_t yoff[kMaxSlots];  // scratch position of the group's first unknown in each cell
 };
 
+// The separator-group part of one level of the factor apply, one workgroup per group: the
+// gather of the cells' contributions (up-sweep), the block-Jacobi factor L_g (preconditioned
+// levels) and, for a skeletonized group with redundant unknowns, its skeleton elimination.
+struct GroupApplyDesc {
+    int32_t n;          // group size
+    int32_t dofs;       // offset of its unknowns (ascending) in the level's group-dof array
+    int32_t nslot;      // cells contributing to the gather
+    int32_t precond;    // 1: apply L_g
+    int64_t yoff[kMaxSlots];
+    int64_t loff;       // L_g (n x n) in the block-Jacobi pool
+    int32_t li;         // inverses of L_g's 16 x 16 diagonal blocks
+    int32_t nr;         // redundant unknowns of the skeleton elimination (0: none)
+    int32_t k;          // skeletons
+    int32_t poff;       // group-local pivot order in the level's pivot array
+    int64_t goff;       // G (n x n) in the skeleton pool
+    int64_t toff;       // T (k x nr, ld k) in the T pool
+    int32_t skli;       // inverses of L~'s 16 x 16 diagonal blocks
+    int32_t pad;
+};
+
 }  // namespace rhif

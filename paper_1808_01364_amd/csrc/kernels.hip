@@ -830,23 +830,44 @@ __global__ __launch_bounds__(256) void k_syrk_schur(const FrontDesc* __restrict_
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_precond_groups(const SepDesc* __restrict__ sd, const CellRef* __restrict__ cells,
                                                         const double* __restrict__ F, double* __restrict__ Lg,
-                                                        double* __restrict__ Li, int panel_cap, int level,
+                                                        double* __restrict__ Li, int panel_cap, int lds_n, int level,
                                                         unsigned long long* err) {
     extern __shared__ double smem[];
-    const SepDesc g = sd[blockIdx.x];
-    const int n = g.n;
-    double* L = Lg + g.loff;
-    for (int e = threadIdx.x; e < n * n; e += kWG) {
-        const int a = e % n, b = e / n;
-        double v = 0.0;
-        for (int sl = 0; sl < g.nslot; ++sl) {
-            const CellRef c = cells[g.slot_cell[sl]];
-            v += F[c.off + (g.slot_off[sl] + a) + static_cast<size_t>(g.slot_off[sl] + b) * c.ld];
-        }
-        L[e] = v;
+    __shared__ int64_t s_off[kMaxSlots];
+    __shared__ int32_t s_ld[kMaxSlots];
+    const SepDesc& gr = sd[blockIdx.x];   // slot arrays indexed through memory
+    const int n = gr.n, ns = gr.nslot;
+    if (threadIdx.x < ns) {
+        const int sl = threadIdx.x;
+        const CellRef c = cells[gr.slot_cell[sl]];
+        s_off[sl] = c.off + gr.slot_off[sl] + static_cast<int64_t>(gr.slot_off[sl]) * c.ld;
+        s_ld[sl] = c.ld;
     }
     __syncthreads();
-    wg_potrf_partial(L, n, n, n, smem, panel_cap, err, err_code(level, 1, blockIdx.x), nullptr, Li + g.lioff);
+    double* L = Lg + gr.loff;
+    const unsigned long long code = err_code(level, 1, blockIdx.x);
+    double* lv = Li + gr.lioff;
+    if (n <= lds_n) {
+        double* D = smem + kPotrfSmemFixed;
+        for (int e = threadIdx.x; e < n * n; e += kWG) {
+            const int a = e % n, b = e / n;
+            double v = 0.0;
+            for (int sl = 0; sl < ns; ++sl) v += F[s_off[sl] + a + static_cast<size_t>(b) * s_ld[sl]];
+            D[e] = v;
+        }
+        __syncthreads();
+        wg_potrf_partial(D, n, n, n, smem, 0, err, code, nullptr, lv);
+        for (int e = threadIdx.x; e < n * n; e += kWG) L[e] = D[e];
+    } else {
+        for (int e = threadIdx.x; e < n * n; e += kWG) {
+            const int a = e % n, b = e / n;
+            double v = 0.0;
+            for (int sl = 0; sl < ns; ++sl) v += F[s_off[sl] + a + static_cast<size_t>(b) * s_ld[sl]];
+            L[e] = v;
+        }
+        __syncthreads();
+        wg_potrf_partial(L, n, n, n, smem, panel_cap, err, code, nullptr, lv);
+    }
 }
 
 // Block-Jacobi step, part 2: every cell's share S of the separator matrix becomes
@@ -1335,6 +1356,108 @@ __device__ __forceinline__ void stage_apply_vectors(const ApplyDesc& d, const in
     for (int t = threadIdx.x; t < nt; t += kWG) ex[t] = (extp != nullptr && d.ext >= 0) ? extp[d.ext + t] : d.nI;
 }
 
+// Workgroup forward solve z <- L^-1 z (z in LDS, n <= kSplitApplyMaxI; ex: per-panel
+// nonzero row ends of L in LDS, or null when L is dense).
+template <bool PREFETCH = true>
+__device__ __forceinline__ void wg_trsv_fwd(const double* __restrict__ L, int ld, int n,
+                                            const double* __restrict__ li, double* zI, const int* ex) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nt = (n + 15) / 16;
+    const bool solver = (wave == 0 && lane < 16);
+    double lv[16], lr[16], lvn[16], lrn[16];
+    auto load = [&](int t, double (&v)[16], double (&r)[16]) {
+        const int j0 = 16 * t, jb = min(16, n - j0);
+        const int i = j0 + 16 + tid;
+        const bool ok = i < (ex != nullptr ? ex[t] : n);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) v[c] = (ok && c < jb) ? L[i + static_cast<size_t>(j0 + c) * ld] : 0.0;
+        if (solver) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) r[k] = li[t * 256 + lane * 16 + k];
+        }
+    };
+    if (PREFETCH) load(0, lvn, lrn);
+    for (int t = 0; t < nt; ++t) {
+        if (PREFETCH) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                lv[c] = lvn[c];
+                lr[c] = lrn[c];
+            }
+            if (t + 1 < nt) load(t + 1, lvn, lrn);
+        } else {
+            load(t, lv, lr);
+        }
+        const int j0 = 16 * t;
+        if (solver) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) acc += lr[k] * zI[j0 + k];
+            zI[j0 + lane] = acc;
+        }
+        __syncthreads();
+        const int i = j0 + 16 + tid;
+        if (i < (ex != nullptr ? ex[t] : n)) {
+            double acc = zI[i];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) acc -= lv[c] * zI[j0 + c];
+            zI[i] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// Workgroup backward solve z <- L^-T z (same conventions).
+template <bool PREFETCH = true>
+__device__ __forceinline__ void wg_trsv_bwd(const double* __restrict__ L, int ld, int n,
+                                            const double* __restrict__ li, double* zI, const int* ex) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nt = (n + 15) / 16;
+    const bool solver = (wave == 0 && lane < 16);
+    double lv[16], lr[16], lvn[16], lrn[16];
+    // thread k owns column k < j0 of the row panel J (rows j0..j0+15)
+    auto load = [&](int t, double (&v)[16], double (&r)[16]) {
+        const int j0 = 16 * t, jb = min(16, n - j0);
+        const int k = tid;
+        const bool ok = k < j0 && (ex == nullptr || ex[k >> 4] > j0);
+        const double* Lk = L + static_cast<size_t>(k) * ld + j0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = (ok && q < jb) ? Lk[q] : 0.0;
+        if (solver) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) r[q] = li[t * 256 + q * 16 + lane];
+        }
+    };
+    if (PREFETCH) load(nt - 1, lvn, lrn);
+    for (int t = nt - 1; t >= 0; --t) {
+        if (PREFETCH) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                lv[c] = lvn[c];
+                lr[c] = lrn[c];
+            }
+            if (t > 0) load(t - 1, lvn, lrn);
+        } else {
+            load(t, lv, lr);
+        }
+        const int j0 = 16 * t;
+        if (solver) {
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc += lr[q] * zI[j0 + q];
+            zI[j0 + lane] = acc;
+        }
+        __syncthreads();
+        if (tid < j0) {
+            double acc = zI[tid];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc -= lv[q] * zI[j0 + q];
+            zI[tid] = acc;
+        }
+        __syncthreads();
+    }
+}
+
 // Up-sweep solve: [z_I -= T^T z_B]; z_I <- L^-1 z_I.
 __global__ __launch_bounds__(256) void k_apply_trsv_up(const ApplyDesc* __restrict__ ad, const double* __restrict__ pool,
                                                        const double* __restrict__ lip, const double* __restrict__ Tp,
@@ -1342,9 +1465,9 @@ __global__ __launch_bounds__(256) void k_apply_trsv_up(const ApplyDesc* __restri
                                                        const int32_t* __restrict__ extp) {
     extern __shared__ double smem[];
     const ApplyDesc d = ad[blockIdx.x];
-    const int nI = d.nI, nB = d.nB, ld = d.ld;
+    const int nI = d.nI, nB = d.nB;
     const int nt = (nI + 15) / 16;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     double* zI = smem;
     double* zB = zI + nt * 16;
     const bool hasT = d.toff >= 0;
@@ -1366,46 +1489,7 @@ __global__ __launch_bounds__(256) void k_apply_trsv_up(const ApplyDesc* __restri
         }
         __syncthreads();
     }
-    const double* L = pool + d.off;
-    const double* li = lip + d.li;
-    const bool solver = (wave == 0 && lane < 16);
-    double lv[16], lr[16], lvn[16], lrn[16];
-    auto load = [&](int t, double (&v)[16], double (&r)[16]) {
-        const int j0 = 16 * t, jb = min(16, nI - j0);
-        const int i = j0 + 16 + tid;
-        const bool ok = i < ex[t];
-#pragma unroll
-        for (int c = 0; c < 16; ++c) v[c] = (ok && c < jb) ? L[i + static_cast<size_t>(j0 + c) * ld] : 0.0;
-        if (solver) {
-#pragma unroll
-            for (int k = 0; k < 16; ++k) r[k] = li[t * 256 + lane * 16 + k];
-        }
-    };
-    load(0, lvn, lrn);
-    for (int t = 0; t < nt; ++t) {
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            lv[c] = lvn[c];
-            lr[c] = lrn[c];
-        }
-        if (t + 1 < nt) load(t + 1, lvn, lrn);
-        const int j0 = 16 * t;
-        if (solver) {
-            double acc = 0.0;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) acc += lr[k] * zI[j0 + k];
-            zI[j0 + lane] = acc;
-        }
-        __syncthreads();
-        const int i = j0 + 16 + tid;
-        if (i < ex[t]) {
-            double acc = zI[i];
-#pragma unroll
-            for (int c = 0; c < 16; ++c) acc -= lv[c] * zI[j0 + c];
-            zI[i] = acc;
-        }
-        __syncthreads();
-    }
+    wg_trsv_fwd(pool + d.off, d.ld, nI, lip + d.li, zI, ex);
     const int32_t* di = dofs + d.dofs;
     for (int i = tid; i < nI; i += kWG) z[di[i]] = zI[i];
 }
@@ -1417,56 +1501,16 @@ __global__ __launch_bounds__(256) void k_apply_trsv_dn(const ApplyDesc* __restri
                                                        const int32_t* __restrict__ extp) {
     extern __shared__ double smem[];
     const ApplyDesc d = ad[blockIdx.x];
-    const int nI = d.nI, nB = d.nB, ld = d.ld;
+    const int nI = d.nI, nB = d.nB;
     const int nt = (nI + 15) / 16;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     double* zI = smem;
     double* zB = zI + nt * 16;
     const bool hasT = d.toff >= 0;
     int* ex = reinterpret_cast<int*>(zB + (hasT ? nB : 0));
     stage_apply_vectors(d, dofs, z, zI, zB, hasT, ex, extp);
     __syncthreads();
-    const double* L = pool + d.off;
-    const double* li = lip + d.li;
-    const bool solver = (wave == 0 && lane < 16);
-    double lv[16], lr[16], lvn[16], lrn[16];
-    // thread k owns column k < j0 of the row panel J (rows j0..j0+15)
-    auto load = [&](int t, double (&v)[16], double (&r)[16]) {
-        const int j0 = 16 * t, jb = min(16, nI - j0);
-        const int k = tid;
-        const bool ok = k < j0 && ex[k >> 4] > j0;
-        const double* Lk = L + static_cast<size_t>(k) * ld + j0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = (ok && q < jb) ? Lk[q] : 0.0;
-        if (solver) {
-#pragma unroll
-            for (int q = 0; q < 16; ++q) r[q] = li[t * 256 + q * 16 + lane];
-        }
-    };
-    load(nt - 1, lvn, lrn);
-    for (int t = nt - 1; t >= 0; --t) {
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            lv[c] = lvn[c];
-            lr[c] = lrn[c];
-        }
-        if (t > 0) load(t - 1, lvn, lrn);
-        const int j0 = 16 * t;
-        if (solver) {
-            double acc = 0.0;
-#pragma unroll
-            for (int q = 0; q < 16; ++q) acc += lr[q] * zI[j0 + q];
-            zI[j0 + lane] = acc;
-        }
-        __syncthreads();
-        if (tid < j0) {
-            double acc = zI[tid];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) acc -= lv[q] * zI[j0 + q];
-            zI[tid] = acc;
-        }
-        __syncthreads();
-    }
+    wg_trsv_bwd(pool + d.off, d.ld, nI, lip + d.li, zI, ex);
     const int32_t* di = dofs + d.dofs;
     for (int i = tid; i < nI; i += kWG) z[di[i]] = zI[i];
     if (hasT) {
@@ -1482,6 +1526,106 @@ __global__ __launch_bounds__(256) void k_apply_trsv_dn(const ApplyDesc* __restri
             z[di[nI + c]] = zB[c] - (acc + acc1);
         }
     }
+}
+
+// Separator groups of one level, one workgroup per group, all on the group's own unknowns
+// staged in LDS (zl in ascending order; zp in the skeleton elimination's order: redundant
+// perm[k..n), then skeletons perm[0..k)).
+//   up:   z_g -= sum of the cells' y shares; [z_g <- L_g^-1 z_g];
+//         [z_r -= T^T z_s; z_r <- L~^-1 z_r; z_s -= W~^T z_r]
+//   down: [z_r -= W~ z_s; z_r <- L~^-T z_r; z_s -= T z_r]; [z_g <- L_g^-T z_g]
+__global__ __launch_bounds__(256) void k_apply_group_up(const GroupApplyDesc* __restrict__ gd,
+                                                        const int32_t* __restrict__ gdofs,
+                                                        const double* __restrict__ ybuf, double* __restrict__ z,
+                                                        const double* __restrict__ Lg, const double* __restrict__ lig,
+                                                        const double* __restrict__ Gp, const double* __restrict__ Tp,
+                                                        const double* __restrict__ skli,
+                                                        const int32_t* __restrict__ perm) {
+    extern __shared__ double smem[];
+    const GroupApplyDesc g = gd[blockIdx.x];
+    const int n = g.n, tid = threadIdx.x;
+    const int np = 16 * ((n + 15) / 16);
+    double* zl = smem;
+    double* zp = smem + np;
+    const int32_t* di = gdofs + g.dofs;
+    const int64_t* yoff = gd[blockIdx.x].yoff;   // indexed through memory, not a private copy
+    for (int t = tid; t < np; t += kWG) {
+        double v = 0.0;
+        if (t < n) {
+            v = z[di[t]];
+            for (int sl = 0; sl < g.nslot; ++sl) v -= ybuf[yoff[sl] + t];
+        }
+        zl[t] = v;
+    }
+    __syncthreads();
+    if (g.precond) wg_trsv_fwd<false>(Lg + g.loff, n, n, lig + g.li, zl, nullptr);
+    if (g.nr > 0) {
+        const int nr = g.nr, k = g.k;
+        const int32_t* pv = perm + g.poff;
+        for (int q = tid; q < np; q += kWG) zp[q] = (q < nr) ? zl[pv[k + q]] : (q < n ? zl[pv[q - nr]] : 0.0);
+        __syncthreads();
+        const double* T = Tp + g.toff;
+        for (int a = tid; a < nr; a += kWG) {
+            double acc = 0.0;
+            for (int c = 0; c < k; ++c) acc += T[c + static_cast<size_t>(a) * k] * zp[nr + c];
+            zp[a] -= acc;
+        }
+        __syncthreads();
+        const double* G = Gp + g.goff;
+        wg_trsv_fwd<false>(G, n, nr, skli + g.skli, zp, nullptr);
+        for (int c = tid; c < k; c += kWG) {
+            double acc = 0.0;
+            for (int a = 0; a < nr; ++a) acc += G[(nr + c) + static_cast<size_t>(a) * n] * zp[a];
+            zp[nr + c] -= acc;
+        }
+        __syncthreads();
+        for (int q = tid; q < n; q += kWG) zl[q < nr ? pv[k + q] : pv[q - nr]] = zp[q];
+        __syncthreads();
+    }
+    for (int t = tid; t < n; t += kWG) z[di[t]] = zl[t];
+}
+
+__global__ __launch_bounds__(256) void k_apply_group_dn(const GroupApplyDesc* __restrict__ gd,
+                                                        const int32_t* __restrict__ gdofs, double* __restrict__ z,
+                                                        const double* __restrict__ Lg, const double* __restrict__ lig,
+                                                        const double* __restrict__ Gp, const double* __restrict__ Tp,
+                                                        const double* __restrict__ skli,
+                                                        const int32_t* __restrict__ perm) {
+    extern __shared__ double smem[];
+    const GroupApplyDesc g = gd[blockIdx.x];
+    const int n = g.n, tid = threadIdx.x;
+    const int np = 16 * ((n + 15) / 16);
+    double* zl = smem;
+    double* zp = smem + np;
+    const int32_t* di = gdofs + g.dofs;
+    for (int t = tid; t < np; t += kWG) zl[t] = (t < n) ? z[di[t]] : 0.0;
+    __syncthreads();
+    if (g.nr > 0) {
+        const int nr = g.nr, k = g.k;
+        const int32_t* pv = perm + g.poff;
+        for (int q = tid; q < np; q += kWG) zp[q] = (q < nr) ? zl[pv[k + q]] : (q < n ? zl[pv[q - nr]] : 0.0);
+        __syncthreads();
+        const double* G = Gp + g.goff;
+        for (int a = tid; a < nr; a += kWG) {
+            double acc = 0.0;
+            const double* Ga = G + static_cast<size_t>(a) * n + nr;
+            for (int c = 0; c < k; ++c) acc += Ga[c] * zp[nr + c];
+            zp[a] -= acc;
+        }
+        __syncthreads();
+        wg_trsv_bwd<false>(G, n, nr, skli + g.skli, zp, nullptr);
+        const double* T = Tp + g.toff;
+        for (int c = tid; c < k; c += kWG) {
+            double acc = 0.0;
+            for (int a = 0; a < nr; ++a) acc += T[c + static_cast<size_t>(a) * k] * zp[a];
+            zp[nr + c] -= acc;
+        }
+        __syncthreads();
+        for (int q = tid; q < n; q += kWG) zl[q < nr ? pv[k + q] : pv[q - nr]] = zp[q];
+        __syncthreads();
+    }
+    if (g.precond) wg_trsv_bwd<false>(Lg + g.loff, n, n, lig + g.li, zl, nullptr);
+    for (int t = tid; t < n; t += kWG) z[di[t]] = zl[t];
 }
 
 // Up-sweep product y = W^T z_I for 64 rows b of W^T per workgroup (lanes over b, waves

@@ -21,7 +21,7 @@ __global__ void k_chol_lead(const FrontDesc* desc, double* pool, double* linv, i
 __global__ void k_trsm_rows(const FrontDesc* desc, double* pool, const double* linv, int pstride);
 __global__ void k_syrk_schur(const FrontDesc* desc, double* pool);
 __global__ void k_precond_groups(const SepDesc* sd, const CellRef* cells, const double* F, double* Lg, double* Li,
-                                 int panel_cap, int level, unsigned long long* err);
+                                 int panel_cap, int lds_n, int level, unsigned long long* err);
 __global__ void k_precond_scale(const CellScaleDesc* cd, const CellGroup* cg, const double* Lg, const double* Li,
                                 double* F, int pstride);
 __global__ void k_skeletonize(const SkelDesc* sd, const int32_t* cgptr, const int32_t* cgl, const int32_t* cgoff,
@@ -40,6 +40,12 @@ __global__ void k_apply_trsv_dn(const ApplyDesc* ad, const double* pool, const d
 __global__ void k_apply_gemv_up(const ApplyDesc* ad, const double* pool, const int32_t* dofs, double* z,
                                 double* ybuf);
 __global__ void k_apply_gemv_dn(const ApplyDesc* ad, const double* pool, const int32_t* dofs, double* z);
+__global__ void k_apply_group_up(const GroupApplyDesc* gd, const int32_t* gdofs, const double* ybuf, double* z,
+                                 const double* Lg, const double* lig, const double* Gp, const double* Tp,
+                                 const double* skli, const int32_t* perm);
+__global__ void k_apply_group_dn(const GroupApplyDesc* gd, const int32_t* gdofs, double* z, const double* Lg,
+                                 const double* lig, const double* Gp, const double* Tp, const double* skli,
+                                 const int32_t* perm);
 __global__ void k_sep_gather(const GatherDesc* gd, const int32_t* dofs, const double* ybuf, double* z);
 __global__ void k_spmv_dot(int64_t N, const int32_t* rp, const int32_t* ci, const double* v, const double* p,
                            double* q, double* part);

@@ -739,6 +739,7 @@ void validate_separators(const LevelPlan& P) {
         need(k.moff >= 0 && k.moff + static_cast<int64_t>(std::max(k.r, 1)) * (k.n | 1) <= P.m_elems, "skel M bounds");
         need(k.toff >= 0 && k.toff + static_cast<int64_t>(k.n) * k.n / 4 + 1 <= P.t_elems, "skel T bounds");
         need(k.goff >= 0 && k.goff + static_cast<int64_t>(k.n) * k.n <= P.g_elems, "skel G bounds");
+        need(k.lioff >= 0 && k.lioff + 256 * static_cast<int64_t>((k.n + 15) / 16) <= P.skli_elems, "skel Li bounds");
         need(k.poff >= 0 && k.poff + k.n <= P.skel_ntotal, "skel perm bounds");
         need(k.gid >= 0 && k.gid < static_cast<int>(P.skel_desc.size()), "skel gid");
     }

@@ -44,6 +44,7 @@ constexpr int kApplyCap = kLdsBudgetDoubles - rhif::kApplyDiagDoubles - rhif::kA
 // largest leading block k_chol_lead factors in LDS ((p|1) p + kPotrfSmemFixed <= 20480 doubles;
 // k_trsm_rows then needs 4 * 17 * 144 doubles)
 constexpr int kCholLdsPmax = 139;
+constexpr int kStaticLdsReserve = 32;         // doubles of static LDS a kernel may declare
 constexpr int kRedBlocks = 1024;              // fixed partial-sum layout of the CG reductions
 
 // Per-thread host state reused across factorizations: pinned staging buffers for the
@@ -52,6 +53,8 @@ constexpr int kRedBlocks = 1024;              // fixed partial-sum layout of the
 // factorizations do not pay for fresh allocations and page faults). Kept for the life of
 // the process.
 struct HostCache {
+    std::vector<rhif::GroupApplyDesc> gad;
+    std::vector<int32_t> skel_of;
     static constexpr int kSlots = 3;
     char* up[kSlots] = {};
     size_t up_bytes[kSlots] = {};
@@ -154,6 +157,9 @@ struct LevelDev {
     int32_t* sepdofs = nullptr;
     rhif::ApplyDesc* skel_ad = nullptr;
     int32_t* skeldofs = nullptr;
+    rhif::GroupApplyDesc* grp_ad = nullptr;   // fused per-group apply (gather, L_g, skeleton)
+    int32_t* permd = nullptr;                 // group-local pivot orders of the level's IDs
+    int n_grp = 0, mn_grp = 0;
     int n_cell_ad = 0, n_sep_ad = 0, n_gather = 0, n_skel_ad = 0;
     size_t lds_cell = 0, lds_sep = 0, lds_skel = 0;
     // largest n_I / n_B of each block family (split apply when n_I is small enough)
@@ -211,6 +217,15 @@ struct rhif_factor_s {
     int64_t kp_elems = 0;
     // PCG workspace
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *part = nullptr, *sc = nullptr;
+    double* hsc = nullptr;                 // pinned host scalars of the PCG (read back by the graphs)
+    const double* graph_u = nullptr;       // solution vector the PCG graphs were captured with
+    // HIP graphs of the solve phase, captured on first use on an internal stream:
+    // [0] z <- F^-1 z;  [1] the first CG update;  [2] one PCG iteration (apply .. next update)
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+    bool graphs_off = false;
+
     rhif_stats_t stats{};
     std::vector<void*> allocs;
     hipStream_t alloc_stream = nullptr;
@@ -224,6 +239,7 @@ struct rhif_factor_s {
     };
     std::vector<Pend> pend;
     std::vector<hipEvent_t> evpool;
+    std::vector<Pend> gpend[3];   // timing events recorded inside the graphs (read after every replay)
 
     hipEvent_t ev() {
         if (!evpool.empty()) {
@@ -234,6 +250,17 @@ struct rhif_factor_s {
         hipEvent_t e;
         HIPCHK(hipEventCreate(&e));
         return e;
+    }
+    // After a replay of graph g has completed: add its recorded kernel times.
+    void resolve_graph(int g) {
+        for (const Pend& q : gpend[g]) {
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, q.a, q.b));
+            stats.kernel_ms[q.cls] += ms;
+            stats.kernel_launches[q.cls] += 1;
+            stats.kernel_flops[q.cls] += q.fl;
+            stats.kernel_bytes[q.cls] += q.by;
+        }
     }
     void resolve() {
         for (const Pend& q : pend) {
@@ -258,6 +285,21 @@ struct rhif_factor_s {
     }
     void release() {
         (void)hipStreamSynchronize(alloc_stream);
+        for (int g = 0; g < 3; ++g) {
+            if (gexec[g]) (void)hipGraphExecDestroy(gexec[g]);
+            if (graph[g]) (void)hipGraphDestroy(graph[g]);
+            gexec[g] = nullptr;
+            graph[g] = nullptr;
+            for (const Pend& q : gpend[g]) {
+                evpool.push_back(q.a);
+                evpool.push_back(q.b);
+            }
+            gpend[g].clear();
+        }
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        cap_stream = nullptr;
+        if (hsc) (void)hipHostFree(hsc);
+        hsc = nullptr;
         for (const Pend& q : pend) {
             (void)hipEventSynchronize(q.b);
             evpool.push_back(q.a);
@@ -391,6 +433,9 @@ void set_kernel_attributes() {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_chol_lead),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        // k_precond_groups also holds a few static LDS words
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_precond_groups),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kStaticLdsReserve * 8);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_trsm_rows),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         for (const void* k : {reinterpret_cast<const void*>(&rhif::k_apply_trsv_up),
@@ -398,6 +443,7 @@ void set_kernel_attributes() {
                               reinterpret_cast<const void*>(&rhif::k_apply_gemv_up),
                               reinterpret_cast<const void*>(&rhif::k_apply_gemv_dn)})
             (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipGetLastError();   // an attribute a runtime does not take must not linger
     });
 }
 
@@ -613,9 +659,14 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             const int cap = panel_cap_for(P.max_sep_n, 0);
             LD.li = static_cast<double*>(f->dalloc(P.li_elems * sizeof(double)));
             double* li = LD.li;
+            // L_g is factored in LDS when the largest group fits
+            const int nm = P.max_sep_n;
+            const bool staged = rhif::kPotrfSmemFixed + nm * nm <= kLdsMaxDoubles - kStaticLdsReserve;
+            const size_t lds_pg = staged ? static_cast<size_t>(rhif::kPotrfSmemFixed + nm * nm) * sizeof(double)
+                                         : potrf_lds(cap, 0);
             KTIMED(f, s, RHIF_K_PRECOND_CHOL, P.alg_prec_chol_flops, 0.0,
-                   hipLaunchKernelGGL(k_precond_groups, dim3(P.sep_desc.size()), dim3(256), potrf_lds(cap, 0), s,
-                                      LD.sep, LD.cref, LD.front, LD.lg, li, cap, lvl, f->err));
+                   hipLaunchKernelGGL(k_precond_groups, dim3(P.sep_desc.size()), dim3(256), lds_pg, s, LD.sep,
+                                      LD.cref, LD.front, LD.lg, li, cap, staged ? nm : 0, lvl, f->err));
             if (!P.cell_scale.empty()) {
                 const int pstride = 17 * ((P.max_sep_n + 15) / 16) * 16;
                 if (4 * pstride > kLdsMaxDoubles) fail(RHIF_ENOMEM, "a separator group is too large for this version");
@@ -704,15 +755,53 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                     break;
                 }
         }
+        // per separator group: gather, block Jacobi and skeleton elimination in one launch
+        std::vector<GroupApplyDesc>& gad = hc.gad;
+        gad.assign(P.sep_desc.size(), GroupApplyDesc{});
+        LD.mn_grp = 0;
+        {
+            std::vector<int32_t>& skel_of = hc.skel_of;
+            skel_of.assign(P.gptr.size(), -1);
+            for (int e = 0; e < nsk; ++e) skel_of[P.skels[e]] = e;
+            for (size_t e = 0; e < P.sep_desc.size(); ++e) {
+                const SepDesc& sd = P.sep_desc[e];
+                const GatherDesc& gt = P.gather[e];
+                GroupApplyDesc& x = gad[e];
+                x.n = sd.n;
+                x.dofs = sd.dofs;
+                x.nslot = gt.nslot;
+                for (int sl = 0; sl < gt.nslot; ++sl) x.yoff[sl] = gt.yoff[sl];
+                x.precond = LD.precond ? 1 : 0;
+                x.loff = sd.loff;
+                x.li = sd.lioff;
+                const int se = skel_of[P.seps[e]];
+                if (se >= 0) {
+                    const SkelDesc& sk = P.skel_desc[se];
+                    const int kk = LD.k[sk.gid];
+                    if (kk < sk.n) {
+                        x.nr = sk.n - kk;
+                        x.k = kk;
+                        x.poff = sk.poff;
+                        x.goff = sk.goff;
+                        x.toff = sk.toff;
+                        x.skli = sk.lioff;
+                    }
+                }
+                LD.mn_grp = std::max(LD.mn_grp, sd.n);
+            }
+        }
         {
             Packer pk;
-            const size_t o_ad = pk.add(sk_ad), o_dofs = pk.add(sk_dofs);
+            const size_t o_ad = pk.add(sk_ad), o_dofs = pk.add(sk_dofs), o_gad = pk.add(gad), o_perm = pk.add(LD.perm);
             char* T = upload(f, pk, s);
             if (T) {
                 LD.skel_ad = view<ApplyDesc>(T, o_ad);
                 LD.skeldofs = view<int32_t>(T, o_dofs);
+                LD.grp_ad = view<GroupApplyDesc>(T, o_gad);
+                LD.permd = view<int32_t>(T, o_perm);
             }
         }
+        LD.n_grp = static_cast<int>(gad.size());
         LD.n_skel_ad = static_cast<int>(sk_ad.size());
         LD.lds_skel = apply_lds(sk_ad);
         apply_max(sk_ad, LD.mi_skel, LD.mb_skel);
@@ -760,6 +849,19 @@ size_t trsv_lds(int mi, int mb) {
     return static_cast<size_t>(16 * ((mi + 15) / 16) + mb + (mi + 15) / 32 + 1) * sizeof(double);
 }
 
+// The fused per-group kernels when every group fits the one-row-per-thread solves and the
+// inverses of the diagonal blocks are there.
+bool group_ok(const LevelDev& LD) {
+    if (LD.n_grp <= 0 || LD.grp_ad == nullptr || LD.mn_grp > rhif::kSplitApplyMaxI) return false;
+    if (LD.precond && LD.li == nullptr) return false;
+    if (LD.n_skel_ad > 0 && LD.skli == nullptr) return false;
+    return true;
+}
+
+size_t group_lds(const LevelDev& LD) {
+    return static_cast<size_t>(2 * 16 * ((LD.mn_grp + 15) / 16)) * sizeof(double);
+}
+
 void apply_up_block(rhif_factor_s* f, double by, const rhif::ApplyDesc* ad, int n, int mi, int mb, size_t lds,
                     const double* pool, const double* lip, const double* tp, const int32_t* dofs, double* z,
                     double* ybuf, hipStream_t s, const int32_t* ext = nullptr) {
@@ -800,6 +902,12 @@ void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
         LevelDev& LD = f->lev[lvl];
         apply_up_block(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.mi_cell, LD.mb_cell, LD.lds_cell, LD.front, LD.linv,
                        nullptr, LD.cdofs, z, f->ybuf, s, LD.ext);
+        if (group_ok(LD)) {
+            KTIMED(f, s, RHIF_K_APPLY_GATHER, 0.0, LD.b_gather + LD.b_sep + LD.b_skel,
+                   hipLaunchKernelGGL(rhif::k_apply_group_up, dim3(LD.n_grp), dim3(256), group_lds(LD), s, LD.grp_ad,
+                                      LD.sepdofs, f->ybuf, z, LD.lg, LD.li, LD.gp, LD.tp, LD.skli, LD.permd));
+            continue;
+        }
         if (LD.n_gather > 0)
             KTIMED(f, s, RHIF_K_APPLY_GATHER, 0.0, LD.b_gather,
                    hipLaunchKernelGGL(rhif::k_sep_gather, dim3(LD.n_gather), dim3(256), 0, s, LD.gat, LD.sepdofs,
@@ -819,11 +927,17 @@ void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
     }
     for (int lvl = L - 1; lvl >= 0; --lvl) {
         LevelDev& LD = f->lev[lvl];
-        apply_down_block(f, LD.b_skel, LD.skel_ad, LD.n_skel_ad, LD.mi_skel, LD.mb_skel, LD.lds_skel, LD.gp, LD.skli,
-                         LD.tp, LD.skeldofs, z, s);
-        if (LD.precond)
-            apply_down_block(f, LD.b_sep, LD.sep_ad, LD.n_sep_ad, LD.mi_sep, 0, LD.lds_sep, LD.lg, LD.li, nullptr,
-                             LD.sepdofs, z, s);
+        if (group_ok(LD)) {
+            KTIMED(f, s, RHIF_K_APPLY_GATHER, 0.0, LD.b_sep + LD.b_skel,
+                   hipLaunchKernelGGL(rhif::k_apply_group_dn, dim3(LD.n_grp), dim3(256), group_lds(LD), s, LD.grp_ad,
+                                      LD.sepdofs, z, LD.lg, LD.li, LD.gp, LD.tp, LD.skli, LD.permd));
+        } else {
+            apply_down_block(f, LD.b_skel, LD.skel_ad, LD.n_skel_ad, LD.mi_skel, LD.mb_skel, LD.lds_skel, LD.gp,
+                             LD.skli, LD.tp, LD.skeldofs, z, s);
+            if (LD.precond)
+                apply_down_block(f, LD.b_sep, LD.sep_ad, LD.n_sep_ad, LD.mi_sep, 0, LD.lds_sep, LD.lg, LD.li, nullptr,
+                                 LD.sepdofs, z, s);
+        }
         apply_down_block(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.mi_cell, LD.mb_cell, LD.lds_cell, LD.front,
                          LD.linv, nullptr, LD.cdofs, z, s, LD.ext);
     }
@@ -838,6 +952,69 @@ void ensure_pcg(rhif_factor_s* f) {
     f->q = static_cast<double*>(f->dalloc(vb));
     f->part = static_cast<double*>(f->dalloc(kRedBlocks * sizeof(double)));
     f->sc = static_cast<double*>(f->dalloc(16 * sizeof(double)));
+    if (hipHostMalloc(reinterpret_cast<void**>(&f->hsc), 64, hipHostMallocDefault) != hipSuccess)
+        fail(RHIF_ENOMEM, "pinned host allocation failed");
+}
+
+void drop_graph(rhif_factor_s* f, int g) {
+    if (f->gexec[g]) (void)hipGraphExecDestroy(f->gexec[g]);
+    if (f->graph[g]) (void)hipGraphDestroy(f->graph[g]);
+    f->gexec[g] = nullptr;
+    f->graph[g] = nullptr;
+    for (const auto& q : f->gpend[g]) {
+        f->evpool.push_back(q.a);
+        f->evpool.push_back(q.b);
+    }
+    f->gpend[g].clear();
+}
+
+// Runs body(stream) as graph g: captured once on the internal stream, then replayed on s.
+// Returns false (nothing launched) if graphs are unavailable or the kernels inside are
+// being timed, and the caller runs body(s) directly.
+template <class Body>
+bool run_graph(rhif_factor_s* f, int g, hipStream_t s, Body body) {
+    if (f->graphs_off || !(f->o.flags & RHIF_FLAG_SOLVE_GRAPHS)) return false;
+    // kernels timed with HIP events run as direct launches (event times of graph nodes are
+    // not available)
+    constexpr uint32_t in_graphs = (1u << RHIF_K_APPLY_UP) | (1u << RHIF_K_APPLY_DOWN) | (1u << RHIF_K_APPLY_GATHER) |
+                                   (1u << RHIF_K_SPMV) | (1u << RHIF_K_VECTOR);
+    if (f->ktimes && (f->kmask & in_graphs)) return false;
+    if (!f->gexec[g]) {
+        if (!f->cap_stream && hipStreamCreateWithFlags(&f->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            f->graphs_off = true;
+            return false;
+        }
+        const size_t np = f->pend.size();
+        hipError_t e = hipStreamBeginCapture(f->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            try {
+                body(f->cap_stream);
+            } catch (...) {
+                e = hipErrorUnknown;
+            }
+            hipGraph_t gr = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(f->cap_stream, &gr);
+            f->graph[g] = gr;
+            if (e == hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&f->gexec[g], f->graph[g], nullptr, nullptr, 0);
+        f->gpend[g].assign(f->pend.begin() + np, f->pend.end());
+        f->pend.resize(np);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            drop_graph(f, g);
+            f->graphs_off = true;
+            return false;
+        }
+    }
+    HIPCHK(hipGraphLaunch(f->gexec[g], s));
+    return true;
+}
+
+void apply_z(rhif_factor_s* f, hipStream_t s, bool& used) {
+    used = run_graph(f, 0, s, [&](hipStream_t cs) { do_apply_inplace(f, f->z, cs); });
+    if (!used) do_apply_inplace(f, f->z, s);
 }
 
 }  // namespace
@@ -980,16 +1157,21 @@ rhif_status rhif_apply(rhif_factor_t f, const double* r, double* z, int32_t nrhs
     API_BEGIN
     if (!f || !r || !z) fail(RHIF_EINVAL, "NULL argument");
     if (nrhs < 0) fail(RHIF_EINVAL, "nrhs < 0");
+    ensure_pcg(f);
     const int64_t N = f->g.N;
+    bool used = false;
     for (int c = 0; c < nrhs; ++c) {
         double* zc = z + c * N;
         const double* rc = r + c * N;
-        if (zc != rc) {
-            hipLaunchKernelGGL(rhif::k_copy, dim3(grid_for(N)), dim3(256), 0, s, N, rc, zc);
-        }
-        do_apply_inplace(f, zc, s);
+        hipLaunchKernelGGL(rhif::k_copy, dim3(grid_for(N)), dim3(256), 0, s, N, rc, f->z);
+        apply_z(f, s, used);
+        hipLaunchKernelGGL(rhif::k_copy, dim3(grid_for(N)), dim3(256), 0, s, N, f->z, zc);
     }
     HIPCHK(hipGetLastError());
+    if (used && !f->gpend[0].empty()) {
+        HIPCHK(hipStreamSynchronize(s));
+        f->resolve_graph(0);
+    }
     API_END
 }
 
@@ -1011,49 +1193,80 @@ rhif_status rhif_pcg_solve(rhif_factor_t f, const double* rhs, double* u, double
     ensure_pcg(f);
     const int64_t N = f->g.N;
     const int gb = grid_for(N);
-    double* hsc = reinterpret_cast<double*>(host_cache().get_down(64));
+    double* hsc = f->hsc;
     const double NB = 8.0 * static_cast<double>(N);
     const double spmv_by = 12.0 * f->nnz + 4.0 * (N + 1) + 3.0 * NB;
-#define VEC(by, ...) KTIMED(f, s, RHIF_K_VECTOR, 0.0, (by), __VA_ARGS__)
-    // r = f, u = 0, ||f||^2
-    VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, rhs, f->r));
-    VEC(NB, hipLaunchKernelGGL(rhif::k_fill, dim3(gb), dim3(256), 0, s, N, 0.0, u));
-    VEC(NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, s, N, rhs, rhs, f->part));
-    VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, s, f->part, gb, 0, f->sc, nullptr));
-    HIPCHK(hipMemcpyAsync(hsc, f->sc + 6, sizeof(double), hipMemcpyDeviceToHost, s));
-    // z = F^-1 r, rho = r.z, p = z
-    VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, f->r, f->z));
-    do_apply_inplace(f, f->z, s);
-    VEC(2 * NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, s, N, f->r, f->z, f->part));
-    VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, s, f->part, gb, 3, f->sc, nullptr));
-    VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, f->z, f->p));
+#define VEC(by, ...) KTIMED(f, cs, RHIF_K_VECTOR, 0.0, (by), __VA_ARGS__)
+    // the graphs hold the solution pointer: capture again for another one
+    if (f->graph_u != u) {
+        drop_graph(f, 1);
+        drop_graph(f, 2);
+        f->graph_u = u;
+    }
+    // q = A p; alpha; u += alpha p, r -= alpha q; |r|^2 -> host
+    auto update = [&](hipStream_t cs) {
+        KTIMED(f, cs, RHIF_K_SPMV, 2.0 * f->nnz + 2.0 * N, spmv_by,
+               hipLaunchKernelGGL(rhif::k_spmv_dot, dim3(gb), dim3(256), 0, cs, N, f->rp, f->ci, f->val, f->p, f->q,
+                                  f->part));
+        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, f->part, gb, 1, f->sc, nullptr));
+        VEC(6 * NB, hipLaunchKernelGGL(rhif::k_axpy2, dim3(gb), dim3(256), 0, cs, N, f->sc, f->p, f->q, u, f->r,
+                                       f->part));
+        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, f->part, gb, 2, f->sc, nullptr));
+        HIPCHK(hipMemcpyAsync(hsc + 1, f->sc + 3, sizeof(double), hipMemcpyDeviceToHost, cs));
+    };
+    // z = F^-1 r; rho = r.z; beta; p = z + beta p; then the next update
+    auto iterate = [&](hipStream_t cs) {
+        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, cs, N, f->r, f->z));
+        do_apply_inplace(f, f->z, cs);
+        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, cs, N, f->r, f->z, f->part));
+        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, f->part, gb, 4, f->sc, nullptr));
+        VEC(3 * NB, hipLaunchKernelGGL(rhif::k_update_p, dim3(gb), dim3(256), 0, cs, N, f->sc, f->z, f->p));
+        update(cs);
+    };
+    {
+        hipStream_t cs = s;
+        // r = f, u = 0, ||f||^2
+        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, cs, N, rhs, f->r));
+        VEC(NB, hipLaunchKernelGGL(rhif::k_fill, dim3(gb), dim3(256), 0, cs, N, 0.0, u));
+        VEC(NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, cs, N, rhs, rhs, f->part));
+        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, f->part, gb, 0, f->sc, nullptr));
+        HIPCHK(hipMemcpyAsync(hsc, f->sc + 6, sizeof(double), hipMemcpyDeviceToHost, cs));
+        // z = F^-1 r, rho = r.z, p = z
+        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, cs, N, f->r, f->z));
+    }
+    bool g0 = false;
+    apply_z(f, s, g0);
+    {
+        hipStream_t cs = s;
+        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, cs, N, f->r, f->z, f->part));
+        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, f->part, gb, 3, f->sc, nullptr));
+        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, cs, N, f->z, f->p));
+    }
     HIPCHK(hipStreamSynchronize(s));
+    if (g0) f->resolve_graph(0);
     const double ff = hsc[0];
     const double fnorm = std::sqrt(ff);
     int it = 0;
     double rel = 0.0;
     bool conv = (ff == 0.0);
+    int last = -1;   // graph whose replay the next synchronization completes
+    if (!conv && maxit > 0) {
+        if (run_graph(f, 1, s, update)) last = 1;
+        else update(s);
+    }
     while (!conv && it < maxit) {
-        KTIMED(f, s, RHIF_K_SPMV, 2.0 * f->nnz + 2.0 * N, spmv_by,
-               hipLaunchKernelGGL(rhif::k_spmv_dot, dim3(gb), dim3(256), 0, s, N, f->rp, f->ci, f->val, f->p, f->q,
-                                  f->part));
-        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, s, f->part, gb, 1, f->sc, nullptr));
-        VEC(6 * NB, hipLaunchKernelGGL(rhif::k_axpy2, dim3(gb), dim3(256), 0, s, N, f->sc, f->p, f->q, u, f->r,
-                                       f->part));
-        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, s, f->part, gb, 2, f->sc, nullptr));
-        HIPCHK(hipMemcpyAsync(hsc + 1, f->sc + 3, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        if (last >= 0) f->resolve_graph(last);
+        last = -1;
         ++it;
         rel = std::sqrt(hsc[1]) / fnorm;
         if (rel <= rtol) {
             conv = true;
             break;
         }
-        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, f->r, f->z));
-        do_apply_inplace(f, f->z, s);
-        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, s, N, f->r, f->z, f->part));
-        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, s, f->part, gb, 4, f->sc, nullptr));
-        VEC(3 * NB, hipLaunchKernelGGL(rhif::k_update_p, dim3(gb), dim3(256), 0, s, N, f->sc, f->z, f->p));
+        if (it >= maxit) break;
+        if (run_graph(f, 2, s, iterate)) last = 2;
+        else iterate(s);
     }
 #undef VEC
     f->resolve();

@@ -22,6 +22,7 @@ FLAG_PHASE_TIMES = 1
 FLAG_KERNEL_TIMES = 2
 KERNEL_MASK_SHIFT = 8
 FLAG_LEAF_SUBLEVELS = 4
+FLAG_SOLVE_GRAPHS = 8
 NUM_KCLASS = 16
 KCLASS_NAMES = ["front_csr", "front_extend", "elim_leaf", "elim_upper", "root", "precond_chol",
                 "precond_scale", "skeletonize", "apply_up", "apply_down", "apply_gather", "spmv",
