@@ -21,7 +21,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kWG = 256;
 constexpr int kWaves = kWG / 64;
 constexpr int kSyrkBatch = 2;   // Schur tiles accumulated per wave at a time
-constexpr int kMaxSkelSegs = 64; // row segments of one skeletonized group (2 x 26 in 3D)
+constexpr int kLeafTilesPerWave = 4;   // Schur tiles a wave of the leaf kernel accumulates in registers
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -52,6 +52,7 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
 // (L^-1)[r][lane] for lane < 16. A pivot <= 0 or NaN reports `code` and continues with 1.
 __device__ __forceinline__ void wave_chol_inv16(double (&a)[16], double (&li)[16], int lane,
                                                 unsigned long long* err, unsigned long long code) {
+    double rinv[16];   // 1 / L[c][c], the same in every lane
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
         double dcc = readlane_d(a[c], c);
@@ -60,7 +61,8 @@ __device__ __forceinline__ void wave_chol_inv16(double (&a)[16], double (&li)[16
             dcc = 1.0;
         }
         const double lcc = sqrt(dcc);
-        const double lic = a[c] / lcc;
+        rinv[c] = 1.0 / lcc;
+        const double lic = a[c] * rinv[c];
         a[c] = (lane == c) ? lcc : (lane > c ? lic : a[c]);
 #pragma unroll
         for (int q = c + 1; q < 16; ++q) {
@@ -73,7 +75,7 @@ __device__ __forceinline__ void wave_chol_inv16(double (&a)[16], double (&li)[16
         double v = (lane == i) ? 1.0 : 0.0;
 #pragma unroll
         for (int k = 0; k < i; ++k) v -= readlane_d(a[k], i) * li[k];
-        li[i] = v / readlane_d(a[i], i);
+        li[i] = v * rinv[i];
     }
 }
 
@@ -637,6 +639,264 @@ __global__ __launch_bounds__(256) void k_potrf_batch(const FrontDesc* __restrict
 }
 
 // ---------------------------------------------------------------------------------------
+// Leaf-cell elimination (eq. (2.1)) when A_II is banded with bandwidth <= 16 in its natural
+// order (the interior box of a leaf cell: bandwidth = the box's row length), so that L is
+// block bidiagonal in 16 x 16 blocks. For J = 0, 1, ...:
+//   L_JJ = chol(D_JJ - L_J,J-1 L_J,J-1^T),  Li_J = L_JJ^-1,  L_J+1,J = D_J+1,J Li_J^T   (wave 0)
+//   W^T_J = (X_J - W^T_J-1 L_J,J-1^T) Li_J^T        (16 boundary rows per wave and tile)
+// then S = A_BB - W^T W on the matrix cores, both triangles written. These are the factors
+// of the dense partial Cholesky; only the structural zeros outside the band are skipped.
+// LDS (dynamic): L_J,J-1 double buffer (2 x 272), Li_J (272), per wave a transfer tile
+// (272) and tpw tiles of W^T_J-1 (tpw x 272), then two buffers of (2 + row tiles) x 272 for
+// the next block's operands, loaded by waves 1..3 while wave 0 factors the current block.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_leaf_elim(const FrontDesc* __restrict__ desc, double* __restrict__ pool,
+                                                   double* __restrict__ linv, int tpw, int level,
+                                                   unsigned long long* err, int32_t* __restrict__ ext) {
+    extern __shared__ double smem[];
+    constexpr int TS = 16 * 17;
+    const FrontDesc fd = desc[blockIdx.x];
+    double* A = pool + fd.off;
+    const int ld = fd.ld, p = fd.p, m = fd.n - fd.p;
+    const int nb = (p + 15) / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lh = lane >> 4;
+    const int ntile = (m + 15) / 16;
+    double* Lsb = smem;                 // [2][TS]: L_J,J-1 by parity of J
+    double* Lis = smem + 2 * TS;        // Li_J, row-major
+    double* Tw = smem + 3 * TS + wave * TS;                  // this wave's transfer tile
+    double* Pw = smem + 7 * TS + static_cast<size_t>(wave) * tpw * TS;   // this wave's W^T_J-1 tiles
+    // operands of block J, loaded during the previous block by waves 1..3 (by parity of J):
+    // D_JJ (row-major), D_J+1,J (row-major) and the X_J row tiles (row-major per tile)
+    double* Buf = smem + (7 + 4 * tpw) * TS;
+    const int bufsz = (2 + ntile) * TS;
+    double* lv = linv + static_cast<size_t>(fd.ext) * 256;
+    const unsigned long long code = err_code(level, 0, fd.id);
+    // S -= W^T W accumulated block by block in registers of waves 1..3 while wave 0 factors
+    // the next diagonal block (up to kLeafTilesPerWave lower tiles per wave); otherwise
+    // formed at the end from W^T in memory
+    const int ntl = ntile * (ntile + 1) / 2;
+    const bool inc = ntl <= 3 * kLeafTilesPerWave;
+    v4d sacc[kLeafTilesPerWave];
+#pragma unroll
+    for (int u = 0; u < kLeafTilesPerWave; ++u) sacc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+    auto tile_ij = [](int t, int& ti, int& tj) {
+        ti = static_cast<int>((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        while (ti * (ti + 1) / 2 > t) --ti;
+        tj = t - ti * (ti + 1) / 2;
+    };
+    // rank-16 update with the W^T tiles of the block just finished (P tiles of every wave)
+    auto syrk_step = [&]() {
+#pragma unroll
+        for (int u = 0; u < kLeafTilesPerWave; ++u) {
+            const int t = (wave - 1) + 3 * u;
+            if (t >= ntl) break;
+            int ti, tj;
+            tile_ij(t, ti, tj);
+            const double* Pa = smem + 7 * TS + static_cast<size_t>(ti & 3) * tpw * TS + (ti >> 2) * TS;
+            const double* Pb = smem + 7 * TS + static_cast<size_t>(tj & 3) * tpw * TS + (tj >> 2) * TS;
+#pragma unroll
+            for (int kk = 0; kk < 16; kk += 4)
+                sacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(Pa[lr * 17 + kk + lh], Pb[lr * 17 + kk + lh], sacc[u],
+                                                              0, 0, 0);
+        }
+    };
+    auto prefetch = [&](int J, int t0, int stride) {
+        double* B = Buf + (J & 1) * bufsz;
+        const int j0 = 16 * J, jb = min(16, p - j0), rb = min(16, p - j0 - 16);
+        // 256 elements per 16 x 16 tile: element e = row * 16 + col
+        for (int e = t0; e < (2 + ntile) * 256; e += stride) {
+            const int tile = e >> 8, r = (e >> 4) & 15, c = e & 15;
+            double v;
+            if (tile == 0) v = (r < jb && c <= r) ? A[(j0 + r) + static_cast<size_t>(j0 + c) * ld] : 0.0;
+            else if (tile == 1) v = (r < rb && c < jb) ? A[(j0 + 16 + r) + static_cast<size_t>(j0 + c) * ld] : 0.0;
+            else {
+                const int rr = 16 * (tile - 2) + r;
+                v = (rr < m && c < jb) ? A[(p + rr) + static_cast<size_t>(j0 + c) * ld] : 0.0;
+            }
+            B[tile * TS + r * 17 + c] = v;
+        }
+    };
+    prefetch(0, threadIdx.x, kWG);
+    __syncthreads();
+    for (int J = 0; J < nb; ++J) {
+        const int j0 = 16 * J, jb = min(16, p - j0);
+        const double* Lprev = Lsb + (J & 1) * TS;
+        const double* B = Buf + (J & 1) * bufsz;
+        if (wave == 0) {
+            double a[16], li[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) a[c] = (lane < 16) ? B[lane * 17 + c] : 0.0;
+            if (lane >= jb && lane < 16) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) a[c] = (lane == c) ? 1.0 : 0.0;
+            }
+            if (J > 0) {
+                // D_JJ -= L_J,J-1 L_J,J-1^T (rows and columns < jb are real)
+                v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < 16; kk += 4) {
+                    const double x = Lprev[lr * 17 + kk + lh];
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) Tw[(lh + 4 * q) * 17 + lr] = acc[q];
+                __builtin_amdgcn_wave_barrier();
+                if (lane < jb) {
+#pragma unroll
+                    for (int c = 0; c < 16; ++c)
+                        if (c <= lane) a[c] -= Tw[lane * 17 + c];
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            wave_chol_inv16(a, li, lane, err, code);
+            if (lane < jb) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+                    if (c <= lane) A[(j0 + lane) + static_cast<size_t>(j0 + c) * ld] = a[c];
+            }
+            if (lane < 16) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    Lis[i * 17 + lane] = li[i];
+                    lv[J * 256 + i * 16 + lane] = li[i];
+                }
+            }
+            if (lane == 0) ext[fd.ext + J] = min(p, j0 + 32);
+        } else {
+            if (inc && J > 0) syrk_step();
+            if (J + 1 < nb) prefetch(J + 1, threadIdx.x - 64, kWG - 64);
+        }
+        __syncthreads();
+        // W^T_J for this wave's row tiles
+        int slot = 0;
+        for (int t = wave; t < ntile; t += kWaves, ++slot) {
+            const int r0 = 16 * t;
+            double* P = Pw + slot * TS;
+            const double* X = B + (2 + t) * TS;
+            v4d acc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = X[(lh + 4 * q) * 17 + lr];
+            if (J > 0) {
+#pragma unroll
+                for (int kk = 0; kk < 16; kk += 4) {
+                    const double av = -P[lr * 17 + kk + lh];
+                    const double bv = Lprev[lr * 17 + kk + lh];
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Tw[(lh + 4 * q) * 17 + lr] = acc[q];
+            __builtin_amdgcn_wave_barrier();
+            v4d out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 16; kk += 4) {
+                const double av = Tw[lr * 17 + kk + lh];
+                const double bv = Lis[lr * 17 + kk + lh];
+                out = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, out, 0, 0, 0);
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + lh + 4 * q;
+                P[(lh + 4 * q) * 17 + lr] = out[q];
+                if (r < m && lr < jb) A[(p + r) + static_cast<size_t>(j0 + lr) * ld] = out[q];
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        // L_J+1,J = D_J+1,J Li_J^T by wave 0, into the other buffer
+        if (wave == 0 && J + 1 < nb) {
+            const int rb = min(16, p - j0 - 16);
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+            const double* Dsub = B + TS;
+#pragma unroll
+            for (int kk = 0; kk < 16; kk += 4) {
+                const double av = Dsub[lr * 17 + kk + lh];
+                const double bv = Lis[lr * 17 + kk + lh];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            }
+            double* Lnext = Lsb + ((J + 1) & 1) * TS;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = lh + 4 * q;
+                Lnext[r * 17 + lr] = acc[q];
+                if (r < rb && lr < jb) A[(j0 + 16 + r) + static_cast<size_t>(j0 + lr) * ld] = acc[q];
+            }
+        }
+        __syncthreads();
+    }
+    // S = A_BB - W^T W, each lower element written with its mirror by one lane (S stays
+    // exactly symmetric)
+    double* S = A + p + static_cast<size_t>(p) * ld;
+    if (inc) {
+        if (wave == 0) return;
+        syrk_step();   // the last block
+#pragma unroll
+        for (int u = 0; u < kLeafTilesPerWave; ++u) {
+            const int t = (wave - 1) + 3 * u;
+            if (t >= ntl) break;
+            int ti, tj;
+            tile_ij(t, ti, tj);
+            const int c = tj * 16 + lr;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = ti * 16 + lh + 4 * q;
+                if (r < m && c < m && r >= c) {
+                    const double v = S[r + static_cast<size_t>(c) * ld] - sacc[u][q];
+                    S[r + static_cast<size_t>(c) * ld] = v;
+                    S[c + static_cast<size_t>(r) * ld] = v;
+                }
+            }
+        }
+        return;
+    }
+    const double* Wt = A + p;
+    for (int t = wave; t < ntl; t += kWaves) {
+        int ti, tj;
+        tile_ij(t, ti, tj);
+        const int c = tj * 16 + lr;
+        v4d s0 = {0.0, 0.0, 0.0, 0.0}, acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = ti * 16 + lh + 4 * q;
+            if (r < m && c < m) s0[q] = S[max(r, c) + static_cast<size_t>(min(r, c)) * ld];
+        }
+        const int ra = ti * 16 + lr, rb = tj * 16 + lr;
+        const double* Wa = Wt + ra;
+        const double* Wb = Wt + rb;
+        const bool oka = ra < m, okb = rb < m;
+        int k0 = 0;
+        for (; k0 + 16 <= p; k0 += 16) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const size_t col = static_cast<size_t>(k0 + 4 * u + lh) * ld;
+                av[u] = oka ? Wa[col] : 0.0;
+                bv[u] = okb ? Wb[col] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+        }
+        for (; k0 < p; k0 += 4) {
+            const int kq = k0 + lh;
+            const double av = (oka && kq < p) ? Wa[static_cast<size_t>(kq) * ld] : 0.0;
+            const double bv = (okb && kq < p) ? Wb[static_cast<size_t>(kq) * ld] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = ti * 16 + lh + 4 * q;
+            if (r < m && c < m && r >= c) {
+                const double v = s0[q] - acc[q];
+                S[r + static_cast<size_t>(c) * ld] = v;
+                S[c + static_cast<size_t>(r) * ld] = v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // The cell elimination of eq. (2.1) in three launches, for levels with few cells (one
 // workgroup per cell would leave most of the chip idle and wait on memory latency):
 //   k_chol_lead:  A_II = L L^T, one workgroup per cell, A_II staged in LDS when it fits;
@@ -774,8 +1034,8 @@ __global__ __launch_bounds__(256) void k_trsm_rows(const FrontDesc* __restrict__
 }
 
 // S = A_BB - W^T W on the 32 x 32 block (bi, bj), bi >= bj (block y of the cell, row-major
-// over the lower triangle); each wave one 16 x 16 tile. The old values are read from the
-// lower triangle only; off-diagonal blocks are written to both triangles.
+// over the lower triangle); each wave one 16 x 16 tile of the lower triangle. The old values
+// are read from the lower triangle; each lower element is written with its mirror.
 __global__ __launch_bounds__(256) void k_syrk_schur(const FrontDesc* __restrict__ desc, double* __restrict__ pool) {
     const FrontDesc fd = desc[blockIdx.x];
     const int p = fd.p, ms = fd.n - fd.p, ld = fd.ld;
@@ -792,7 +1052,7 @@ __global__ __launch_bounds__(256) void k_syrk_schur(const FrontDesc* __restrict_
     double* A = pool + fd.off;
     double* S = A + p + static_cast<size_t>(p) * ld;
     const double* Wt = A + p;
-    const bool act = ti * 16 < ms && tj * 16 < ms;
+    const bool act = ti * 16 < ms && tj * 16 < ms && ti >= tj;
     const int c = tj * 16 + lr;
     v4d s0 = {0.0, 0.0, 0.0, 0.0}, acc = {0.0, 0.0, 0.0, 0.0};
     if (act) {
@@ -810,15 +1070,15 @@ __global__ __launch_bounds__(256) void k_syrk_schur(const FrontDesc* __restrict_
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
         }
     }
-    if (bi == bj) __syncthreads();   // the waves of a diagonal block read each other's outputs
+    // each lower element (r >= c) is written with its mirror by the one lane that read it
     if (act) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = ti * 16 + lh + 4 * q;
-            if (r < ms && c < ms) {
+            if (r < ms && c < ms && r >= c) {
                 const double v = s0[q] - acc[q];
                 S[r + static_cast<size_t>(c) * ld] = v;
-                if (bi != bj) S[c + static_cast<size_t>(r) * ld] = v;
+                S[c + static_cast<size_t>(r) * ld] = v;
             }
         }
     }
@@ -926,6 +1186,100 @@ __global__ __launch_bounds__(256) void k_precond_scale(const CellScaleDesc* __re
 //      the group's diagonal block is cleared. Couplings of the redundant unknowns to R are
 //      dropped simply by not carrying them to the next level.
 // ---------------------------------------------------------------------------------------
+// The row table of M = A[R_g, g] (Sec. 2.2): R_g is the other boundary groups of the
+// group's first cell (with the second cell's position where the group is shared), then the
+// second cell's groups not in the first. rwl[2 i], rwl[2 i + 1] receive row i's position in
+// either cell (-1: none). The cells' group lists are staged in LDS by all threads, then one
+// thread builds the segments (first row, count, positions); a row count that disagrees with
+// the plan is reported. scratch: 4 * kMaxSkelSegs + 2 + 4 * kMaxCellGroups ints.
+__device__ __forceinline__ void build_row_table(const SkelDesc& g, const int32_t* __restrict__ cgptr,
+                                                const int32_t* __restrict__ cgl, const int32_t* __restrict__ cgoff,
+                                                int nf0, int nf1, int r, int* rwl, int* scratch, int level,
+                                                unsigned long long* err) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    int* seg = scratch;
+    int* nseg = seg + 4 * kMaxSkelSegs;
+    int* lst = nseg + 2;   // [4][kMaxCellGroups]: groups and offsets of cell 0, then of cell 1
+    const int a0 = cgptr[g.cell[0]], na = min(cgptr[g.cell[0] + 1] - a0, kMaxCellGroups);
+    const int b0 = g.nslot > 1 ? cgptr[g.cell[1]] : 0;
+    const int nbl = g.nslot > 1 ? min(cgptr[g.cell[1] + 1] - b0, kMaxCellGroups) : 0;
+    const bool fits = (cgptr[g.cell[0] + 1] - a0) <= kMaxCellGroups &&
+                      (g.nslot < 2 || cgptr[g.cell[1] + 1] - b0 <= kMaxCellGroups);
+    for (int e = tid; e < na; e += nthr) {
+        lst[e] = cgl[a0 + e];
+        lst[kMaxCellGroups + e] = cgoff[a0 + e];
+    }
+    for (int e = tid; e < nbl; e += nthr) {
+        lst[2 * kMaxCellGroups + e] = cgl[b0 + e];
+        lst[3 * kMaxCellGroups + e] = cgoff[b0 + e];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int ns = 0, rr = 0;
+        bool ok = fits;
+        const int* ga = lst;
+        const int* oa = lst + kMaxCellGroups;
+        const int* gb = lst + 2 * kMaxCellGroups;
+        const int* ob = lst + 3 * kMaxCellGroups;
+        for (int e = 0; e < na; ++e) {
+            const int h = ga[e];
+            if (h == g.grp) continue;
+            const int nh = ((e + 1 < na) ? oa[e + 1] : nf0) - oa[e];
+            int o2 = -1;
+            for (int f2 = 0; f2 < nbl; ++f2)
+                if (gb[f2] == h) o2 = ob[f2];
+            if (ns < kMaxSkelSegs) {
+                seg[4 * ns] = rr;
+                seg[4 * ns + 1] = nh;
+                seg[4 * ns + 2] = oa[e];
+                seg[4 * ns + 3] = o2;
+            } else {
+                ok = false;
+            }
+            ++ns;
+            rr += nh;
+        }
+        for (int f2 = 0; f2 < nbl; ++f2) {
+            const int h = gb[f2];
+            if (h == g.grp) continue;
+            bool shared = false;
+            for (int e = 0; e < na; ++e) shared = shared || (ga[e] == h);
+            if (shared) continue;
+            const int nh = ((f2 + 1 < nbl) ? ob[f2 + 1] : nf1) - ob[f2];
+            if (ns < kMaxSkelSegs) {
+                seg[4 * ns] = rr;
+                seg[4 * ns + 1] = nh;
+                seg[4 * ns + 2] = -1;
+                seg[4 * ns + 3] = ob[f2];
+            } else {
+                ok = false;
+            }
+            ++ns;
+            rr += nh;
+        }
+        if (!ok || rr != r) {
+            report(err, err_code(level, 7, blockIdx.x));
+            ns = 0;
+        }
+        *nseg = ns;
+    }
+    __syncthreads();
+    const int ns = *nseg;
+    for (int i = tid; i < r; i += nthr) {
+        int p1 = -1, p2 = -1;
+        for (int q = 0; q < ns; ++q) {
+            const int t = i - seg[4 * q];
+            if (t >= 0 && t < seg[4 * q + 1]) {
+                p1 = seg[4 * q + 2] >= 0 ? seg[4 * q + 2] + t : -1;
+                p2 = seg[4 * q + 3] >= 0 ? seg[4 * q + 3] + t : -1;
+            }
+        }
+        rwl[2 * i] = p1;
+        rwl[2 * i + 1] = p2;
+    }
+    __syncthreads();
+}
+
 // LDS: pos, perm ints | row table (2 rmax ints) | QR partials | red (2) |
 //      [M (rmax x (nmax|1))] | [G (nmax^2)] | potrf scratch
 // SM / SG: M / G staged in LDS (else in the global pools), fixed at compile time so that
@@ -958,75 +1312,7 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
     if (g.nslot > 1) c1 = cells[g.cell[1]];
     const double* f0 = F + c0.off + static_cast<size_t>(g.off[0]) * c0.ld;
     const double* f1 = F + c1.off + static_cast<size_t>(g.off[1]) * c1.ld;
-    // rows of M: the other boundary groups of cell 0 (with cell 1's position where the group
-    // is shared), then the groups of cell 1 not in cell 0; segments (first row, count,
-    // position in cell 0, position in cell 1) built by one thread in the part buffer
-    {
-        int* seg = reinterpret_cast<int*>(part);
-        int* nseg = seg + 4 * kMaxSkelSegs;
-        if (tid == 0) {
-            int ns = 0, rr = 0;
-            const int a0 = cgptr[g.cell[0]], a1 = cgptr[g.cell[0] + 1];
-            const int b0 = g.nslot > 1 ? cgptr[g.cell[1]] : 0, b1 = g.nslot > 1 ? cgptr[g.cell[1] + 1] : 0;
-            bool ok = true;
-            for (int e = a0; e < a1; ++e) {
-                const int h = cgl[e];
-                if (h == g.grp) continue;
-                const int nh = ((e + 1 < a1) ? cgoff[e + 1] : c0.nf) - cgoff[e];
-                int o2 = -1;
-                for (int f2 = b0; f2 < b1; ++f2)
-                    if (cgl[f2] == h) o2 = cgoff[f2];
-                if (ns < kMaxSkelSegs) {
-                    seg[4 * ns] = rr;
-                    seg[4 * ns + 1] = nh;
-                    seg[4 * ns + 2] = cgoff[e];
-                    seg[4 * ns + 3] = o2;
-                } else {
-                    ok = false;
-                }
-                ++ns;
-                rr += nh;
-            }
-            for (int f2 = b0; f2 < b1; ++f2) {
-                const int h = cgl[f2];
-                if (h == g.grp) continue;
-                bool shared = false;
-                for (int e = a0; e < a1; ++e) shared = shared || (cgl[e] == h);
-                if (shared) continue;
-                const int nh = ((f2 + 1 < b1) ? cgoff[f2 + 1] : c1.nf) - cgoff[f2];
-                if (ns < kMaxSkelSegs) {
-                    seg[4 * ns] = rr;
-                    seg[4 * ns + 1] = nh;
-                    seg[4 * ns + 2] = -1;
-                    seg[4 * ns + 3] = cgoff[f2];
-                } else {
-                    ok = false;
-                }
-                ++ns;
-                rr += nh;
-            }
-            if (!ok || rr != r) {
-                report(err, err_code(level, 7, blockIdx.x));
-                ns = 0;
-            }
-            *nseg = ns;
-        }
-        __syncthreads();
-        const int ns = *nseg;
-        for (int i = tid; i < r; i += kWG) {
-            int p1 = -1, p2 = -1;
-            for (int q = 0; q < ns; ++q) {
-                const int t = i - seg[4 * q];
-                if (t >= 0 && t < seg[4 * q + 1]) {
-                    p1 = seg[4 * q + 2] >= 0 ? seg[4 * q + 2] + t : -1;
-                    p2 = seg[4 * q + 3] >= 0 ? seg[4 * q + 3] + t : -1;
-                }
-            }
-            rwl[2 * i] = p1;
-            rwl[2 * i + 1] = p2;
-        }
-        __syncthreads();
-    }
+    build_row_table(g, cgptr, cgl, cgoff, c0.nf, c1.nf, r, rwl, reinterpret_cast<int*>(part), level, err);
     // 1. M = A[R_g, g] (row-major), the shares of both cells added; four independent
     //    loads in flight per thread
     const int rn = r * n;
@@ -1054,19 +1340,22 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
     // 2. ID: rank k, pivot order, and T = R11^-1 R12 solved in place over R12
     const int k = wg_cpqr_rows(M, ldr, r, n, eps, pos, perm, part, red);
     const int nr = n - k;
-    for (int a = tid; a < nr; a += kWG) {
-        const int pa = perm[k + a];
-        for (int i = k - 1; i >= 0; --i) {
-            const double* Ri = M + static_cast<size_t>(i) * ldr;
-            double v = Ri[pa], v1 = 0.0;
-            int e = i + 1;
-            for (; e + 1 < k; e += 2) {
-                v -= Ri[perm[e]] * M[static_cast<size_t>(e) * ldr + pa];
-                v1 -= Ri[perm[e + 1]] * M[static_cast<size_t>(e + 1) * ldr + pa];
-            }
-            if (e < k) v -= Ri[perm[e]] * M[static_cast<size_t>(e) * ldr + pa];
-            M[static_cast<size_t>(i) * ldr + pa] = (v + v1) / Ri[perm[i]];
+    // column-oriented back substitution, every (row, column) update of a step in parallel:
+    // t_i = x_i / R_ii, then x_e -= R_ei t_i for e < i
+    for (int i = k - 1; i >= 0; --i) {
+        const double* Ri = M + static_cast<size_t>(i) * ldr;
+        const int pi = perm[i];
+        for (int a = tid; a < nr; a += kWG) {
+            const int pa = perm[k + a];
+            M[static_cast<size_t>(i) * ldr + pa] = Ri[pa] / Ri[pi];
         }
+        __syncthreads();
+        for (int idx = tid; idx < i * nr; idx += kWG) {
+            const int e = idx % i, a = idx / i;
+            const int pa = perm[k + a];
+            M[static_cast<size_t>(e) * ldr + pa] -= M[static_cast<size_t>(e) * ldr + pi] * Ri[pa];
+        }
+        __syncthreads();
     }
     if (tid == 0) kout[g.gid] = k;
     for (int e = tid; e < n; e += kWG) pout[g.poff + e] = perm[e];

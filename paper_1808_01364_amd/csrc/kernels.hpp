@@ -16,6 +16,8 @@ __global__ void k_front_extend(const Tile* tiles, const CellRef* cells, const in
                                const CellRef* child, const double* Fc, double* F);
 __global__ void k_potrf_batch(const FrontDesc* desc, double* pool, int panel_cap, int level, int step,
                               unsigned long long* err, int32_t* ext, double* linv);
+__global__ void k_leaf_elim(const FrontDesc* desc, double* pool, double* linv, int tpw, int level,
+                            unsigned long long* err, int32_t* ext);
 __global__ void k_chol_lead(const FrontDesc* desc, double* pool, double* linv, int lds_pmax, int level,
                             unsigned long long* err, int32_t* ext);
 __global__ void k_trsm_rows(const FrontDesc* desc, double* pool, const double* linv, int pstride);
@@ -58,6 +60,8 @@ __global__ void k_copy(int64_t N, const double* x, double* y);
 __global__ void k_fill(int64_t N, double v, double* y);
 __global__ void k_set_u64(unsigned long long* p, unsigned long long v);
 
+constexpr int kMaxSkelSegs = 64;     // row segments of one skeletonized group (2 x 26 in 3D)
+constexpr int kMaxCellGroups = 32;   // boundary groups of one cell (26 in 3D)
 constexpr int kSplitApplyMaxI = 272;        // split apply: one row / column per thread and panel
 constexpr int kApplyDiagDoubles = 32 * 33;   // LDS diagonal block of the apply kernels
 constexpr int kApplyExtDoubles = 256;         // LDS panel extents (up to 512 ints, n_I <= 8192)

@@ -23,21 +23,17 @@ inline void coords(int64_t i, int d, int s, int* x) {
 }  // namespace
 
 void PlanScratch::init(int64_t N) {
-    for (int t = 0; t < 2; ++t) {
-        dof_group[t].assign(N, -1);
-        dof_tpos[t].assign(N, -1);
-    }
     mark_stamp.assign(N, 0);
     mark_row.assign(N, 0);
     stamp = 0;
-    cur = 0;
+    act_g2.clear();
+    act_t2.clear();
 }
 
 void PlanScratch::reserve(int64_t N) {
-    if (static_cast<int64_t>(mark_stamp.size()) >= N) {
-        cur = 0;
-        return;
-    }
+    act_g2.clear();
+    act_t2.clear();
+    if (static_cast<int64_t>(mark_stamp.size()) >= N) return;
     init(N);
 }
 
@@ -46,7 +42,8 @@ void LevelPlan::reset() {
     level = w = nc1 = 0;
     root = false;
     for (auto* v : {&gptr, &gdofs, &gslot_cnt, &gslot_cell, &gslot_off, &c_nI, &c_nB, &c_nf, &c_ld, &c_dptr,
-                    &c_dofs, &c_gptr, &c_g, &c_goff, &seps, &skels, &src, &sep_dofs, &sep_sorted})
+                    &c_dofs, &c_gptr, &c_g, &c_goff, &seps, &skels, &src, &sep_dofs, &sep_sorted, &sep_g, &sep_t,
+                    &g_g2, &g_t2, &c_g2, &c_t2})
         v->clear();
     gcls.clear();
     c_foff.clear();
@@ -112,6 +109,8 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
         P.gdofs.resize(na);
         P.gptr.clear();
         P.gcls.clear();
+        scr.box_lo.clear();
+        scr.box_n.clear();
         size_t at = 0;
         const int64_t s2 = static_cast<int64_t>(s) * s;
         for (int64_t K = 0; K < nkeys; ++K) {
@@ -137,6 +136,10 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
             scr.key2g[K] = ngroups++;
             P.gptr.push_back(static_cast<int32_t>(at));
             P.gcls.push_back(static_cast<int8_t>(even));
+            for (int k = 0; k < 3; ++k) {
+                scr.box_lo.push_back(lo[k]);
+                scr.box_n.push_back(hi[k] - lo[k] + 1);
+            }
             for (int x2 = lo[2]; x2 <= hi[2]; ++x2)
                 for (int x1 = lo[1]; x1 <= hi[1]; ++x1) {
                     const int64_t base = (d > 2 ? (x2 - 1) * s2 : 0) + (d > 1 ? static_cast<int64_t>(x1 - 1) * s : 0);
@@ -145,16 +148,30 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
         }
         if (at != na) throw std::logic_error("leaf-level groups do not cover the grid");
         P.gptr.push_back(static_cast<int32_t>(na));
-        // separator unknowns: some coordinate on a cell boundary
+        // separator unknowns (some coordinate on a cell boundary), ascending, with their
+        // group and position in it
         const int n2 = d > 2 ? s : 1, n1 = d > 1 ? s : 1;
+        std::vector<int32_t> keyk(static_cast<size_t>(s) + 1);
+        for (int xk = 1; xk <= s; ++xk) keyk[xk] = 2 * (xk / static_cast<int>(w)) + ((xk % w) != 0 ? 1 : 0);
+        auto put = [&](int64_t base, int x0, int x1, int x2) {
+            const int64_t K = keyk[x0] + (d > 1 ? static_cast<int64_t>(keyk[x1]) * KB : 0) +
+                              (d > 2 ? static_cast<int64_t>(keyk[x2]) * KB * KB : 0);
+            const int g = scr.key2g[K];
+            const int* lo = scr.box_lo.data() + 3 * g;
+            const int* nb = scr.box_n.data() + 3 * g;
+            const int t = (x0 - lo[0]) + nb[0] * ((d > 1 ? x1 - lo[1] : 0) + nb[1] * (d > 2 ? x2 - lo[2] : 0));
+            P.sep_sorted.push_back(static_cast<int32_t>(base + x0 - 1));
+            P.sep_g.push_back(g);
+            P.sep_t.push_back(t);
+        };
         for (int x2 = 1; x2 <= n2; ++x2)
             for (int x1 = 1; x1 <= n1; ++x1) {
                 const int64_t base = (d > 2 ? (x2 - 1) * s2 : 0) + (d > 1 ? static_cast<int64_t>(x1 - 1) * s : 0);
                 const bool line = (d > 1 && x1 % w == 0) || (d > 2 && x2 % w == 0);
                 if (line) {
-                    for (int x0 = 1; x0 <= s; ++x0) P.sep_sorted.push_back(static_cast<int32_t>(base + x0 - 1));
+                    for (int x0 = 1; x0 <= s; ++x0) put(base, x0, x1, x2);
                 } else {
-                    for (int64_t x0 = w; x0 <= s; x0 += w) P.sep_sorted.push_back(static_cast<int32_t>(base + x0 - 1));
+                    for (int64_t x0 = w; x0 <= s; x0 += w) put(base, static_cast<int>(x0), x1, x2);
                 }
             }
     } else {
@@ -212,18 +229,32 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
         }
         P.gptr[ngroups] = static_cast<int32_t>(na);
         P.gdofs.assign(na, 0);
+        // the unknowns go to their groups in ascending order, with their sources at the level
+        // below (aligned with the active list) if there is one; the separators' group and
+        // position are recorded in the ascending order of sep_sorted
+        const bool src_in = prev != nullptr && scr.act_g2.size() == na;
+        if (prev != nullptr && !src_in) throw std::logic_error("active unknowns without their sources");
+        if (src_in) {
+            P.g_g2.assign(na, 0);
+            P.g_t2.assign(na, 0);
+        }
         std::vector<int32_t> pos(scr.count.begin(), scr.count.end() - 1);
-        for (size_t a = 0; a < na; ++a) P.gdofs[pos[akey[a]]++] = active[a];
-    }
-    const int cur = scr.cur;
-    // only separator unknowns can be active at the next level
-    for (int g = 0; g < ngroups; ++g) {
-        if (P.gcls[g] == 0) continue;
-        for (int t = P.gptr[g]; t < P.gptr[g + 1]; ++t) {
-            scr.dof_group[cur][P.gdofs[t]] = g;
-            scr.dof_tpos[cur][P.gdofs[t]] = t - P.gptr[g];
+        for (size_t a = 0; a < na; ++a) {
+            const int32_t K = akey[a];
+            const int32_t at = pos[K]++;
+            P.gdofs[at] = active[a];
+            if (src_in) {
+                P.g_g2[at] = scr.act_g2[a];
+                P.g_t2[at] = scr.act_t2[a];
+            }
+            const int g = scr.key2g[K];
+            if (P.gcls[g] != 0) {
+                P.sep_g.push_back(g);
+                P.sep_t.push_back(at - P.gptr[g]);
+            }
         }
     }
+    if (P.sep_g.size() != P.sep_sorted.size()) throw std::logic_error("separator bookkeeping");
 
     // ---- cells: every geometric cell; frontal = interior, then boundary groups ----
     int64_t ncells = 1;
@@ -262,6 +293,10 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
         if (gI >= 0) {
             nI = P.gptr[gI + 1] - P.gptr[gI];
             P.c_dofs.insert(P.c_dofs.end(), P.gdofs.begin() + P.gptr[gI], P.gdofs.begin() + P.gptr[gI + 1]);
+            if (prev != nullptr) {
+                P.c_g2.insert(P.c_g2.end(), P.g_g2.begin() + P.gptr[gI], P.g_g2.begin() + P.gptr[gI + 1]);
+                P.c_t2.insert(P.c_t2.end(), P.g_t2.begin() + P.gptr[gI], P.g_t2.begin() + P.gptr[gI + 1]);
+            }
         }
         int nf = nI;
         for (int t = 0; t < n3; ++t) {
@@ -286,6 +321,10 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
             P.gslot_cell[static_cast<size_t>(g) * kMaxSlots + sl] = static_cast<int32_t>(ci);
             P.gslot_off[static_cast<size_t>(g) * kMaxSlots + sl] = nf;
             P.c_dofs.insert(P.c_dofs.end(), P.gdofs.begin() + P.gptr[g], P.gdofs.begin() + P.gptr[g + 1]);
+            if (prev != nullptr) {
+                P.c_g2.insert(P.c_g2.end(), P.g_g2.begin() + P.gptr[g], P.g_g2.begin() + P.gptr[g + 1]);
+                P.c_t2.insert(P.c_t2.end(), P.g_t2.begin() + P.gptr[g], P.g_t2.begin() + P.gptr[g + 1]);
+            }
             nf += ng;
         }
         P.c_gptr[ci + 1] = static_cast<int32_t>(P.c_g.size());
@@ -336,7 +375,6 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
     // ---- extend-add sources from the children (level >= 1) ----
     const int W = 1 << d;
     if (prev != nullptr) {
-        const int pc = 1 - cur;
         const int pnc1 = prev->nc1;
         // parent cell of every cell of the level below
         std::vector<int32_t>& par_of = scr.par_of;
@@ -356,10 +394,10 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
             int last_g2 = -1, nq = 0;
             int32_t qc[2 * kMaxSlots], qo[2 * kMaxSlots];
             for (int p = P.c_dptr[ci]; p < P.c_dptr[ci + 1]; ++p) {
-                const int32_t i = P.c_dofs[p];
-                const int g2 = scr.dof_group[pc][i];
-                const int t2 = scr.dof_tpos[pc][i];
-                if (g2 < 0) throw std::logic_error("active unknown missing from the level below");
+                const int g2 = P.c_g2[p];
+                const int t2 = P.c_t2[p];
+                if (g2 < 0 || g2 + 1 >= static_cast<int64_t>(prev->gptr.size()))
+                    throw std::logic_error("active unknown missing from the level below");
                 if (g2 != last_g2) {
                     // the child cells of ci that hold g2, and where
                     last_g2 = g2;
@@ -621,9 +659,17 @@ void finish_level(const LevelPlan& P, const int32_t* k, const int32_t* perm, int
     (void)active;
     next_active.clear();
     next_active.reserve(P.sep_sorted.size());
-    for (int32_t i : P.sep_sorted)
-        if (scr.mark_stamp[i] != st) next_active.push_back(i);
-    scr.cur = 1 - scr.cur;
+    scr.nxt_g2.clear();
+    scr.nxt_t2.clear();
+    for (size_t q = 0; q < P.sep_sorted.size(); ++q) {
+        const int32_t i = P.sep_sorted[q];
+        if (scr.mark_stamp[i] == st) continue;
+        next_active.push_back(i);
+        scr.nxt_g2.push_back(P.sep_g[q]);
+        scr.nxt_t2.push_back(P.sep_t[q]);
+    }
+    scr.act_g2.swap(scr.nxt_g2);
+    scr.act_t2.swap(scr.nxt_t2);
 }
 
 }  // namespace rhif

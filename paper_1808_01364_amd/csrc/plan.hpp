@@ -48,6 +48,9 @@ struct LevelPlan {
     // separator groups (class >= 1) and the skeletonized ones (class 1)
     std::vector<int32_t> seps;
     std::vector<int32_t> sep_sorted;   // the separator unknowns, ascending
+    std::vector<int32_t> sep_g, sep_t; // their group and position in it (aligned)
+    std::vector<int32_t> g_g2, g_t2;   // sources at the level below, aligned with gdofs
+    std::vector<int32_t> c_g2, c_t2;   // and with c_dofs
     std::vector<int32_t> skels;
 
     // device-ready tables
@@ -88,17 +91,18 @@ struct LevelPlan {
 struct PlanScratch {
     std::vector<int32_t> count;            // key buckets
     std::vector<int32_t> key2g;
-    std::vector<int32_t> dof_group[2], dof_tpos[2];
+    // per active unknown (aligned with the active list): its group and position in it at the
+    // level below, i.e. where its row sits in a child frontal (set by finish_level)
+    std::vector<int32_t> act_g2, act_t2, nxt_g2, nxt_t2;
+    std::vector<int32_t> box_lo, box_n;    // leaf-level group boxes
     std::vector<int32_t> mark_stamp, mark_row;
     std::vector<int32_t> par_of;
     std::vector<int32_t> akey;             // per active unknown: its group key
     std::vector<int64_t> cell_y;           // per cell: its offset in the apply scratch
     int32_t stamp = 0;
-    int cur = 0;
     void init(int64_t N);
-    // Make room for N unknowns without clearing what is there: the per-unknown maps are
-    // only read for unknowns written earlier in the same factorization, and the stamps
-    // only grow.
+    // Make room for N unknowns without clearing the stamps (they only grow); starts a new
+    // factorization (no sources at the leaf level).
     void reserve(int64_t N);
 };
 

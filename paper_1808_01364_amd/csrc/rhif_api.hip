@@ -433,6 +433,8 @@ void set_kernel_attributes() {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_chol_lead),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_leaf_elim),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         // k_precond_groups also holds a few static LDS words
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_precond_groups),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes - kStaticLdsReserve * 8);
@@ -554,7 +556,18 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             const unsigned ncell = static_cast<unsigned>(P.cell_potrf.size());
             LD.linv = static_cast<double*>(f->dalloc(std::max<int64_t>(P.ext_elems, 1) * 256 * sizeof(double)));
             double* linv = LD.linv;
-            if (!root && lvl > 0 && pmax <= kCholLdsPmax) {
+            int bw = 1;   // bandwidth of a leaf interior box in natural order
+            for (int k = 1; k < d; ++k) bw *= (P.w - 1);
+            if (!root && lvl == 0 && bw <= 16) {
+                // leaf interiors: block-bidiagonal Cholesky factors
+                const int nt = (mmax + 15) / 16;
+                const int tpw = (nt + 3) / 4;
+                const size_t lds0 =
+                    static_cast<size_t>((7 + 4 * std::max(tpw, 1) + 2 * (2 + nt)) * 16 * 17) * sizeof(double);
+                KTIMED(f, s, cls, P.alg_elim_flops, 0.0,
+                       hipLaunchKernelGGL(k_leaf_elim, dim3(ncell), dim3(256), lds0, s, LD.potrf, LD.front, linv,
+                                          std::max(tpw, 1), lvl, f->err, LD.ext));
+            } else if (!root && lvl > 0 && pmax <= kCholLdsPmax) {
                 // few cells: Cholesky, row solves and Schur update as three wide launches
                 const size_t lds1 = static_cast<size_t>(rhif::kPotrfSmemFixed + (pmax | 1) * pmax) * sizeof(double);
                 KTIMED(f, s, cls, P.alg_elim_flops, 0.0,
