@@ -139,7 +139,7 @@ def main():
             kl += kv["launches"]
     from paper_1808_01364_amd.prof_summary import CLASS_KERNEL, read_traffic
     traffic = read_traffic(os.path.join(ROOT, "profiles", f"traffic_2d{P.s}_eps{P.eps:g}.txt"),
-                           CLASS_KERNEL.get(dom, ""))
+                           CLASS_KERNEL.get(dom, ()))
     hbm_bound = dom in ("apply_up", "apply_down", "apply_gather", "spmv", "vector", "front_csr", "front_extend")
     if hbm_bound:
         achieved = kby / (kms * 1e-3) / 1e9

@@ -20,11 +20,16 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hip")
 
-# kernel-class name used by bench.py -> device kernel
-CLASS_KERNEL = {"front_csr": "k_front_csr", "front_extend": "k_front_extend", "elim_leaf": "k_potrf_batch",
-                "elim_upper": "k_potrf_batch", "root": "k_potrf_batch", "precond_chol": "k_precond_groups",
-                "precond_scale": "k_precond_scale", "skeletonize": "k_skeletonize", "apply_up": "k_apply_up",
-                "apply_down": "k_apply_down", "apply_gather": "k_sep_gather", "spmv": "k_spmv_dot"}
+# kernel-class name used by bench.py -> the device kernels launched under it
+CLASS_KERNEL = {"front_csr": ("k_front_csr",), "front_extend": ("k_front_extend",),
+                "elim_leaf": ("k_leaf_elim", "k_potrf_batch"),
+                "elim_upper": ("k_chol_lead", "k_trsm_rows", "k_syrk_schur", "k_potrf_batch"),
+                "root": ("k_potrf_batch",), "precond_chol": ("k_precond_groups",),
+                "precond_scale": ("k_precond_scale",), "skeletonize": ("k_skeletonize",),
+                "apply_up": ("k_apply_trsv_up", "k_apply_gemv_up", "k_apply_up"),
+                "apply_down": ("k_apply_trsv_dn", "k_apply_gemv_dn", "k_apply_down"),
+                "apply_gather": ("k_apply_group_up", "k_apply_group_dn", "k_sep_gather"),
+                "spmv": ("k_spmv_dot",)}
 
 
 def kernel_source_sha() -> str:
@@ -62,7 +67,7 @@ def traffic(fetch_csv: str, write_csv: str, out: str, command: str, kernels=None
     known_kib = 8.0 * N / 1024.0
     fs = known_kib / statistics.mean(v for v, _ in f["k_copy"])
     ws = known_kib / statistics.mean(v for v, _ in w["k_copy"])
-    kernels = kernels or sorted(f, key=lambda k: -sum(v for v, _ in f[k]))[:10]
+    kernels = kernels or sorted(f, key=lambda k: -sum(v for v, _ in f[k]))[:20]
     lines = ["# HBM traffic per dispatch from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (two runs)",
              f"command: {command}", f"kernels_hip_sha256: {kernel_source_sha()}",
              f"copy_kernel: k_copy, {int(known_kib)} KiB read + {int(known_kib)} KiB written per dispatch",
@@ -78,21 +83,27 @@ def traffic(fetch_csv: str, write_csv: str, out: str, command: str, kernels=None
     open(out, "w").write("\n".join(lines) + "\n")
 
 
-def read_traffic(path: str, kernel: str):
-    """Scaled bytes per dispatch of `kernel` from a traffic summary, or None if the summary is
-    missing, does not list the kernel, or was taken on other kernel source."""
+def read_traffic(path: str, kernels):
+    """Scaled HBM bytes per dispatch over `kernels` (a name or a tuple of names; dispatch-weighted
+    mean) from a traffic summary, or None if the summary is missing, lists none of them, or was
+    taken on other kernel source."""
+    if isinstance(kernels, str):
+        kernels = (kernels,)
     if not os.path.exists(path):
         return None
     sha = None
+    tot = 0.0
+    nd = 0
     for ln in open(path):
         if ln.startswith("kernels_hip_sha256:"):
             sha = ln.split(":", 1)[1].strip()
         parts = ln.split()
-        if len(parts) == 5 and parts[0] == kernel:
-            if sha != kernel_source_sha():
-                return None
-            return float(parts[4])
-    return None
+        if len(parts) == 5 and parts[0] in kernels:
+            tot += int(parts[1]) * float(parts[4])
+            nd += int(parts[1])
+    if sha != kernel_source_sha() or nd == 0:
+        return None
+    return tot / nd
 
 
 if __name__ == "__main__":
