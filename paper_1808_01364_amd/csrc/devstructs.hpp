@@ -38,8 +38,12 @@ struct Tile {
     int32_t cell;
     int32_t r0;
     int32_t c0;
-    int32_t pad;
+    int32_t shape;   // 0: 64 x 64; else kTileBand | rows << 8 | cols (rows, cols <= 64)
 };
+constexpr int32_t kTileBand = 1 << 30;   // write only the diagonal and first subdiagonal 16 x 16 blocks
+inline int32_t tile_shape(int rows, int cols, bool band) {
+    return (band ? kTileBand : 0) | (rows << 8) | cols;
+}
 
 // A separator group for the block-Jacobi step: where its diagonal block sits in every
 // cell frontal that contains it, and where its Cholesky factor goes.

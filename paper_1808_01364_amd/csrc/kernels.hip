@@ -520,55 +520,81 @@ __global__ __launch_bounds__(256) void k_assemble_fd(int d, int s, double inv_h2
 // Level-0 frontal assembly: frontal element (p, q) of cell c is A[i, j] (i, j its unknowns)
 // when c is the first cell (lowest index) whose closure contains both i and j, else 0.
 // Every entry of A lands in exactly one frontal, so the frontals add up to A.
+// One workgroup per tile (Tile::shape); with kTileBand only the elements of the diagonal
+// and first subdiagonal 16 x 16 blocks are written. The coordinates and the range of cells
+// whose closure holds each of the tile's column unknowns are staged in LDS once per tile.
 // ---------------------------------------------------------------------------------------
+// Coordinates x_k (1-based) of unknown i and, per axis, the cells lo_k..hi_k whose
+// closure holds it (a coordinate on a cell boundary belongs to both neighbours).
+__device__ __forceinline__ void unknown_cells(int i, int d, int s, int w, int nc1, int* x, int* lo, int* hi) {
+    int rr = i;
+    for (int k = 0; k < 3; ++k) {
+        x[k] = 0;
+        lo[k] = hi[k] = 0;
+        if (k < d) {
+            const int a = rr % s + 1;
+            rr /= s;
+            x[k] = a;
+            const int c = a / w;
+            const bool on = (a % w) == 0;
+            lo[k] = on ? max(c - 1, 0) : c;
+            hi[k] = on ? min(c, nc1 - 1) : c;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_front_csr(const Tile* __restrict__ tiles, const CellRef* __restrict__ cells,
                                                    const int32_t* __restrict__ cdofs, int d, int s, int w, int nc1,
                                                    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                                    const double* __restrict__ val, double* __restrict__ F) {
+    __shared__ int cq_info[64 * 10];   // per tile column: unknown, x[3], lo[3], hi[3]
     const Tile t = tiles[blockIdx.x];
     const CellRef cr = cells[t.cell];
     const int nf = cr.nf;
-    const int p = t.r0 + (threadIdx.x & 63);
-    const bool prow = p < nf;
-    int xi[3] = {0, 0, 0};
-    int i = 0;
-    if (prow) {
-        i = cdofs[cr.dptr + p];
-        int rr = i;
-        for (int k = 0; k < d; ++k) {
-            xi[k] = rr % s + 1;
-            rr /= s;
+    const int nrow = t.shape ? (t.shape >> 8) & 0xff : 64, ncol = t.shape ? t.shape & 0xff : 64;
+    const bool band = (t.shape & kTileBand) != 0;
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 64) {
+        const int q = t.c0 + lane;
+        int* ci = cq_info + lane * 10;
+        if (lane < ncol && q < nf) {
+            const int j = cdofs[cr.dptr + q];
+            ci[0] = j;
+            unknown_cells(j, d, s, w, nc1, ci + 1, ci + 4, ci + 7);
         }
     }
-    for (int cq = threadIdx.x >> 6; cq < 64; cq += 4) {
+    const int p = t.r0 + lane;
+    const bool prow = lane < nrow && p < nf;
+    int i = 0, xi[3], alo[3], ahi[3];
+    if (prow) {
+        i = cdofs[cr.dptr + p];
+        unknown_cells(i, d, s, w, nc1, xi, alo, ahi);
+    }
+    __syncthreads();
+    if (!prow) return;
+    for (int cq = threadIdx.x >> 6; cq < ncol; cq += 4) {
         const int q = t.c0 + cq;
-        if (q >= nf || !prow) continue;
-        const int j = cdofs[cr.dptr + q];
-        int xj[3];
-        int rr = j;
-        int dist = 0;
-        for (int k = 0; k < d; ++k) {
-            xj[k] = rr % s + 1;
-            rr /= s;
-            dist += abs(xj[k] - xi[k]);
+        if (q >= nf) break;
+        if (band) {
+            const int db = (p >> 4) - (q >> 4);
+            if (db < 0 || db > 1) continue;
         }
+        const int* ci = cq_info + cq * 10;
+        int dist = 0;
+        for (int k = 0; k < d; ++k) dist += abs(ci[1 + k] - xi[k]);
         double v = 0.0;
         if (dist <= 1) {
             // first common cell, axis by axis
             int64_t own = 0, mul = 1;
             bool ok = true;
             for (int k = 0; k < d; ++k) {
-                const int a = xi[k], bb = xj[k];
-                const int alo = (a % w) ? a / w : max(a / w - 1, 0);
-                const int ahi = (a % w) ? a / w : min(a / w, nc1 - 1);
-                const int blo = (bb % w) ? bb / w : max(bb / w - 1, 0);
-                const int bhi = (bb % w) ? bb / w : min(bb / w, nc1 - 1);
-                const int lo = max(alo, blo), hi = min(ahi, bhi);
+                const int lo = max(alo[k], ci[4 + k]), hi = min(ahi[k], ci[7 + k]);
                 if (lo > hi) ok = false;
                 own += lo * mul;
                 mul *= nc1;
             }
             if (ok && own == t.cell) {
+                const int j = ci[0];
                 for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
                     if (col[e] == j) {
                         v = val[e];

@@ -340,14 +340,32 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
     P.front_elems = std::max<int64_t>(foff, 32);
 
     // ---- batched descriptors of the cells ----
+    const bool banded = leaf_interior_banded(d, level, root, P.w);
     for (int64_t ci = 0; ci < ncells; ++ci) {
         P.cell_ref.push_back(CellRef{P.c_foff[ci], P.c_ld[ci], P.c_nI[ci], P.c_nf[ci], P.c_dptr[ci]});
         const int nf = P.c_nf[ci];
-        for (int c0 = 0; c0 < nf; c0 += 64)
-            for (int r0 = 0; r0 < nf; r0 += 64)
-                P.tiles.push_back(Tile{static_cast<int32_t>(ci), r0, c0, 0});
         const int nI = P.c_nI[ci], nB = P.c_nB[ci];
-        P.alg_front_bytes += 8.0 * static_cast<double>(nf) * nf;
+        const int32_t cc = static_cast<int32_t>(ci);
+        if (banded && nI > 0) {
+            // the interior band (three 16-wide column blocks per tile), then the boundary rows
+            // of the interior columns and the boundary block; the rest is never read
+            for (int j0 = 0; j0 < nI; j0 += 48)
+                P.tiles.push_back(Tile{cc, j0, j0, tile_shape(std::min(64, nI - j0), std::min(48, nI - j0), true)});
+            for (int part = 0; part < 2; ++part) {
+                const int cend = part == 0 ? nI : nf;
+                for (int c0 = part == 0 ? 0 : nI; c0 < cend; c0 += 64)
+                    for (int r0 = nI; r0 < nf; r0 += 64)
+                        P.tiles.push_back(
+                            Tile{cc, r0, c0, tile_shape(std::min(64, nf - r0), std::min(64, cend - c0), false)});
+            }
+            double band = 0.0;
+            for (int j0 = 0; j0 < nI; j0 += 16) band += std::min(16, nI - j0) * (std::min(32, nI - j0) + 0.0);
+            P.alg_front_bytes += 8.0 * (band + static_cast<double>(nB) * nf);
+        } else {
+            for (int c0 = 0; c0 < nf; c0 += 64)
+                for (int r0 = 0; r0 < nf; r0 += 64) P.tiles.push_back(Tile{cc, r0, c0, 0});
+            P.alg_front_bytes += 8.0 * static_cast<double>(nf) * nf;
+        }
         if (nI > 0) {
             P.cell_potrf.push_back(FrontDesc{P.c_foff[ci], P.c_ld[ci], nf, nI, static_cast<int32_t>(ci),
                                              static_cast<int32_t>(P.ext_elems), 0});
@@ -716,6 +734,12 @@ void validate_cells(const LevelPlan& P, const LevelPlan* prev, int d) {
     for (const Tile& t : P.tiles) {
         need(t.cell >= 0 && t.cell < P.ncells, "tile cell", t.cell, P.ncells);
         need(t.r0 >= 0 && t.r0 < P.cell_ref[t.cell].nf && t.c0 >= 0 && t.c0 < P.cell_ref[t.cell].nf, "tile origin");
+        if (t.shape != 0) {
+            const int rows = (t.shape >> 8) & 0xff, cols = t.shape & 0xff;
+            need(rows >= 1 && rows <= 64 && cols >= 1 && cols <= 64 && (t.shape & ~(kTileBand | 0xffff)) == 0,
+                 "tile shape", rows, cols);
+            need(t.r0 + rows <= P.cell_ref[t.cell].nf && t.c0 + cols <= P.cell_ref[t.cell].nf, "tile extent");
+        }
     }
     for (const FrontDesc& f : P.cell_potrf) {
         need(f.id >= 0 && f.id < P.ncells, "potrf id");

@@ -106,6 +106,16 @@ struct PlanScratch {
     void reserve(int64_t N);
 };
 
+// Leaf cells (level 0, not the root) whose interior, in natural order, has bandwidth
+// (w - 1)^(d - 1) <= 16: their Cholesky factor is block bidiagonal in 16 x 16 blocks, and
+// only those blocks, the boundary rows and the boundary block of the frontal are used.
+inline bool leaf_interior_banded(int d, int level, bool root, int w) {
+    if (level != 0 || root) return false;
+    int bw = 1;
+    for (int k = 1; k < d; ++k) bw *= (w - 1);
+    return bw <= 16;
+}
+
 // Number of skeletonization levels L: all l >= 0 with 2^l m <= s.
 int num_levels(int s, int leaf);
 

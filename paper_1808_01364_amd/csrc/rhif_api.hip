@@ -556,9 +556,8 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             const unsigned ncell = static_cast<unsigned>(P.cell_potrf.size());
             LD.linv = static_cast<double*>(f->dalloc(std::max<int64_t>(P.ext_elems, 1) * 256 * sizeof(double)));
             double* linv = LD.linv;
-            int bw = 1;   // bandwidth of a leaf interior box in natural order
-            for (int k = 1; k < d; ++k) bw *= (P.w - 1);
-            if (!root && lvl == 0 && bw <= 16) {
+            // the frontal tiles of such cells skip what the banded elimination never reads
+            if (leaf_interior_banded(d, lvl, root, P.w)) {
                 // leaf interiors: block-bidiagonal Cholesky factors
                 const int nt = (mmax + 15) / 16;
                 const int tpw = (nt + 3) / 4;
