@@ -78,6 +78,10 @@ typedef struct {
                                       rhif_pcg_solve call (pays off when the handle serves
                                       many solves); ignored while the solve kernels are
                                       timed with RHIF_FLAG_KERNEL_TIMES                    */
+#define RHIF_FLAG_GLOBAL_STAGING 16 /* keep the operands of the block-Jacobi and ID kernels
+                                       in global memory even where they fit in LDS: the path
+                                       that groups too large for LDS take (same results;
+                                       slower); for testing that path on small problems  */
 #define RHIF_MAX_LEVELS 32
 
 /* Kernel classes of rhif_stats_t.kernel_* */

@@ -963,14 +963,18 @@ __global__ __launch_bounds__(256) void k_chol_lead(const FrontDesc* __restrict__
 //   wave_trsm_ll:  columns c0..c0+15 of the column-major n x nc block Y become L^-1 Y, by
 //                  16-row blocks Y_I = Li_I (Y_I - L_I,<I Y_<I); optionally also written
 //                  transposed to YT (ld ldt).
-// Pw: the wave's LDS scratch, 17 * roundup16(n) doubles (finished panels / row blocks).
+// Pw: the wave's LDS scratch, 17 * roundup16(n) doubles (finished panels / row blocks);
+// with HL = false only one 16 x 17 tile, and the finished panels are read back from X / Y in
+// global memory (each wave reads only what it wrote itself, after a device-scope fence).
 // Lane l holds output rows l/16 + 4q, column l % 16 of a 16 x 16 tile.
+template <bool HL = true>
 __device__ __forceinline__ void wave_trsm_rlt(double* __restrict__ X, int ldx, int m, int r0, int n,
                                               const double* __restrict__ L, int ldl, const double* __restrict__ li,
                                               double* Pw) {
     const int lane = threadIdx.x & 63, lr = lane & 15, lh = lane >> 4;
     for (int j0 = 0; j0 < n; j0 += 16) {
         const int jb = min(16, n - j0);
+        double* Pt = HL ? Pw + j0 * 17 : Pw;
         v4d acc;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -978,17 +982,21 @@ __device__ __forceinline__ void wave_trsm_rlt(double* __restrict__ X, int ldx, i
             acc[q] = (r < m && lr < jb) ? X[r + static_cast<size_t>(j0 + lr) * ldx] : 0.0;
         }
         for (int k0 = 0; k0 < j0; k0 += 4) {
-            const double av = -Pw[(k0 + lh) * 17 + lr];
+            double av;
+            if constexpr (HL)
+                av = -Pw[(k0 + lh) * 17 + lr];
+            else
+                av = (r0 + lr < m) ? -X[(r0 + lr) + static_cast<size_t>(k0 + lh) * ldx] : 0.0;
             const double bv = (lr < jb) ? L[(j0 + lr) + static_cast<size_t>(k0 + lh) * ldl] : 0.0;
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Pw[(j0 + lr) * 17 + lh + 4 * q] = acc[q];
+        for (int q = 0; q < 4; ++q) Pt[lr * 17 + lh + 4 * q] = acc[q];
         __builtin_amdgcn_wave_barrier();
         v4d out = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 4) {
-            const double av = Pw[(j0 + kk + lh) * 17 + lr];
+            const double av = Pt[(kk + lh) * 17 + lr];
             const double bv = li[(j0 >> 4) * 256 + lr * 16 + kk + lh];
             out = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, out, 0, 0, 0);
         }
@@ -996,19 +1004,22 @@ __device__ __forceinline__ void wave_trsm_rlt(double* __restrict__ X, int ldx, i
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = r0 + lh + 4 * q;
-            Pw[(j0 + lr) * 17 + lh + 4 * q] = out[q];
+            if constexpr (HL) Pt[lr * 17 + lh + 4 * q] = out[q];
             if (r < m && lr < jb) X[r + static_cast<size_t>(j0 + lr) * ldx] = out[q];
         }
+        if constexpr (!HL) __threadfence();
         __builtin_amdgcn_wave_barrier();
     }
 }
 
+template <bool HL = true>
 __device__ __forceinline__ void wave_trsm_ll(double* __restrict__ Y, int ldy, int n, int c0, int nc,
                                              const double* __restrict__ L, int ldl, const double* __restrict__ li,
                                              double* Yb, double* __restrict__ YT, int ldt) {
     const int lane = threadIdx.x & 63, lr = lane & 15, lh = lane >> 4;
     const int cb = min(16, nc - c0);
     for (int i0 = 0; i0 < n; i0 += 16) {
+        double* Yt = HL ? Yb + i0 * 17 : Yb;
         v4d acc;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -1017,29 +1028,34 @@ __device__ __forceinline__ void wave_trsm_ll(double* __restrict__ Y, int ldy, in
         }
         for (int k0 = 0; k0 < i0; k0 += 4) {
             const double av = (i0 + lr < n) ? -L[(i0 + lr) + static_cast<size_t>(k0 + lh) * ldl] : 0.0;
-            const double bv = Yb[(k0 + lh) * 17 + lr];
+            double bv;
+            if constexpr (HL)
+                bv = Yb[(k0 + lh) * 17 + lr];
+            else
+                bv = (lr < cb) ? Y[(k0 + lh) + static_cast<size_t>(c0 + lr) * ldy] : 0.0;
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Yb[(i0 + lh + 4 * q) * 17 + lr] = acc[q];
+        for (int q = 0; q < 4; ++q) Yt[(lh + 4 * q) * 17 + lr] = acc[q];
         __builtin_amdgcn_wave_barrier();
         v4d out = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 4) {
             const double av = li[(i0 >> 4) * 256 + lr * 16 + kk + lh];
-            const double bv = Yb[(i0 + kk + lh) * 17 + lr];
+            const double bv = Yt[(kk + lh) * 17 + lr];
             out = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, out, 0, 0, 0);
         }
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = i0 + lh + 4 * q;
-            Yb[r * 17 + lr] = out[q];
+            if constexpr (HL) Yt[(lh + 4 * q) * 17 + lr] = out[q];
             if (r < n && lr < cb) {
                 Y[r + static_cast<size_t>(c0 + lr) * ldy] = out[q];
                 if (YT != nullptr) YT[(c0 + lr) + static_cast<size_t>(r) * ldt] = out[q];
             }
         }
+        if constexpr (!HL) __threadfence();
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -1189,12 +1205,23 @@ __global__ __launch_bounds__(256) void k_precond_scale(const CellScaleDesc* __re
     const int wave = threadIdx.x >> 6;
     double* X = Fc + G.off + static_cast<size_t>(H.off) * ld;
     double* XT = Fc + H.off + static_cast<size_t>(G.off) * ld;
-    double* Pw = smem + static_cast<size_t>(wave) * pstride;
-    for (int r0 = wave * 16; r0 < G.n; r0 += kWaves * 16)
-        wave_trsm_rlt(X, ld, G.n, r0, H.n, Lg + H.loff, H.n, Li + H.lioff, Pw);
-    __syncthreads();
-    for (int c0 = wave * 16; c0 < H.n; c0 += kWaves * 16)
-        wave_trsm_ll(X, ld, G.n, c0, H.n, Lg + G.loff, G.n, Li + G.lioff, Pw, XT, ld);
+    if (pstride > 0) {
+        double* Pw = smem + static_cast<size_t>(wave) * pstride;
+        for (int r0 = wave * 16; r0 < G.n; r0 += kWaves * 16)
+            wave_trsm_rlt(X, ld, G.n, r0, H.n, Lg + H.loff, H.n, Li + H.lioff, Pw);
+        __syncthreads();
+        for (int c0 = wave * 16; c0 < H.n; c0 += kWaves * 16)
+            wave_trsm_ll(X, ld, G.n, c0, H.n, Lg + G.loff, G.n, Li + G.lioff, Pw, XT, ld);
+    } else {
+        // groups too large for LDS strips: finished panels are read back from the frontal
+        double* Pw = smem + wave * 16 * 17;
+        for (int r0 = wave * 16; r0 < G.n; r0 += kWaves * 16)
+            wave_trsm_rlt<false>(X, ld, G.n, r0, H.n, Lg + H.loff, H.n, Li + H.lioff, Pw);
+        __threadfence();
+        __syncthreads();
+        for (int c0 = wave * 16; c0 < H.n; c0 += kWaves * 16)
+            wave_trsm_ll<false>(X, ld, G.n, c0, H.n, Lg + G.loff, G.n, Li + G.lioff, Pw, XT, ld);
+    }
 }
 
 // ---------------------------------------------------------------------------------------

@@ -673,20 +673,22 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             double* li = LD.li;
             // L_g is factored in LDS when the largest group fits
             const int nm = P.max_sep_n;
-            const bool staged = rhif::kPotrfSmemFixed + nm * nm <= kLdsMaxDoubles - kStaticLdsReserve;
+            const bool gstage = (f->o.flags & RHIF_FLAG_GLOBAL_STAGING) != 0;
+            const bool staged = !gstage && rhif::kPotrfSmemFixed + nm * nm <= kLdsMaxDoubles - kStaticLdsReserve;
             const size_t lds_pg = staged ? static_cast<size_t>(rhif::kPotrfSmemFixed + nm * nm) * sizeof(double)
                                          : potrf_lds(cap, 0);
             KTIMED(f, s, RHIF_K_PRECOND_CHOL, P.alg_prec_chol_flops, 0.0,
                    hipLaunchKernelGGL(k_precond_groups, dim3(P.sep_desc.size()), dim3(256), lds_pg, s, LD.sep,
                                       LD.cref, LD.front, LD.lg, li, cap, staged ? nm : 0, lvl, f->err));
             if (!P.cell_scale.empty()) {
-                const int pstride = 17 * ((P.max_sep_n + 15) / 16) * 16;
-                if (4 * pstride > kLdsMaxDoubles) fail(RHIF_ENOMEM, "a separator group is too large for this version");
+                // per wave a strip of finished panels in LDS, or (larger groups) one 16 x 17 tile
+                int pstride = 17 * ((P.max_sep_n + 15) / 16) * 16;
+                if (gstage || 4 * pstride > kLdsMaxDoubles) pstride = 0;
+                const size_t lds_sc = static_cast<size_t>(pstride > 0 ? 4 * pstride : 4 * 16 * 17) * sizeof(double);
                 const int gc = P.max_cell_groups;
                 KTIMED(f, s, RHIF_K_PRECOND_SCALE, P.alg_prec_scale_flops, 0.0,
                        hipLaunchKernelGGL(k_precond_scale, dim3(P.cell_scale.size(), gc * (gc + 1) / 2), dim3(256),
-                                          static_cast<size_t>(4 * pstride) * sizeof(double), s, LD.cs, LD.cg, LD.lg,
-                                          li, LD.front, pstride));
+                                          lds_sc, s, LD.cs, LD.cg, LD.lg, li, LD.front, pstride));
             }
         }
         f->stats.n_groups[lvl] = LD.precond ? static_cast<int32_t>(P.sep_desc.size()) : 0;
@@ -706,7 +708,10 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             const int full = kPotrfSmemFixed + 17 * n;        // potrf scratch with the whole panel
             int staged = 0, cap = 0;
             size_t lds = 0;
-            if (base + msz + n * n + full <= kLdsMaxDoubles) {
+            if (f->o.flags & RHIF_FLAG_GLOBAL_STAGING) {
+                cap = panel_cap_for(n, base);
+                lds = potrf_lds(cap, base);
+            } else if (base + msz + n * n + full <= kLdsMaxDoubles) {
                 staged = 3;
                 cap = n;
                 lds = static_cast<size_t>(base + msz + n * n + full) * sizeof(double);

@@ -23,6 +23,7 @@ FLAG_KERNEL_TIMES = 2
 KERNEL_MASK_SHIFT = 8
 FLAG_LEAF_SUBLEVELS = 4
 FLAG_SOLVE_GRAPHS = 8
+FLAG_GLOBAL_STAGING = 16
 NUM_KCLASS = 16
 KCLASS_NAMES = ["front_csr", "front_extend", "elim_leaf", "elim_upper", "root", "precond_chol",
                 "precond_scale", "skeletonize", "apply_up", "apply_down", "apply_gather", "spmv",

@@ -43,8 +43,8 @@ def test_eps0_apply_is_dense_solve(d, s, leaf, precond):
     F.close()
 
 
-def _parity(P, A, n_rhs=3, apply_tol=1e-11, sol_tol=1e-10, replay_ok=0.02):
-    F = gpu_factor(P)
+def _parity(P, A, n_rhs=3, apply_tol=1e-11, sol_tol=1e-10, replay_ok=0.02, flags=0):
+    F = gpu_factor(P, flags=flags)
     st = F.stats()
     ch = gpu_choices(F, st["levels"] - st["sublevels"])
     orc = O.factor(A, P.d, P.s, P.leaf, P.eps, P.precond)
@@ -89,6 +89,16 @@ def test_small_parity(d, s, leaf, eps, kind, precond):
     P, A = problem(kind, d, s, leaf, eps, seed=2, precond=precond, sigma=2.0, lo=1e-2, hi=1e2)
     out = _parity(P, A)
     print((d, s, leaf, eps, kind, precond), out)
+
+
+@pytest.mark.parametrize("d,s,leaf,eps", [(2, 31, 4, 1e-6), (3, 12, 4, 1e-3)])
+def test_global_staging_parity(d, s, leaf, eps):
+    """The paths that groups too large for LDS take (block-Jacobi scaling and ID operands in
+    global memory), forced on small problems, agree with the oracle like the LDS paths."""
+    from paper_1808_01364_amd import rhif
+    P, A = problem("two_valued", d, s, leaf, eps, seed=4, lo=1e-2, hi=1e2)
+    out = _parity(P, A, flags=rhif.FLAG_GLOBAL_STAGING)
+    print((d, s, leaf, eps), out)
 
 
 def test_not_spd_is_reported():
