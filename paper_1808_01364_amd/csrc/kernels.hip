@@ -929,17 +929,21 @@ __global__ __launch_bounds__(256) void k_leaf_elim(const FrontDesc* __restrict__
 //                 also stores the inverses of L's 16 x 16 diagonal blocks;
 //   k_trsm_rows:  W^T = A_BI L^-T, 16 rows per wave, independent across rows;
 //   k_syrk_schur: S = A_BB - W^T W on 32 x 32 blocks, both triangles written.
+// Large interiors are eliminated panel by panel with the same three kernels (right-looking
+// blocked Cholesky): for a panel of columns j0..j0+b, each is given the trailing frontal
+// A[j0:n, j0:n] with p = b, so the TRSM covers every row below the panel and the SYRK
+// updates the whole trailing matrix (interior rows included).
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_chol_lead(const FrontDesc* __restrict__ desc, double* __restrict__ pool,
-                                                   double* __restrict__ linv, int lds_pmax, int level,
+                                                   double* __restrict__ linv, int lds_pmax, int level, int step,
                                                    unsigned long long* err, int32_t* __restrict__ ext) {
     extern __shared__ double smem[];
     const FrontDesc fd = desc[blockIdx.x];
     const int p = fd.p, ld = fd.ld;
     double* A = pool + fd.off;
     double* lv = linv + static_cast<size_t>(fd.ext) * 256;
-    int32_t* ex = ext + fd.ext;
-    const unsigned long long code = err_code(level, 0, fd.id);
+    int32_t* ex = ext != nullptr ? ext + fd.ext : nullptr;
+    const unsigned long long code = err_code(level, step, fd.id);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (p <= lds_pmax) {
         const int ls = p | 1;

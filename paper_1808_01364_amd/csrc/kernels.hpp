@@ -18,7 +18,7 @@ __global__ void k_potrf_batch(const FrontDesc* desc, double* pool, int panel_cap
                               unsigned long long* err, int32_t* ext, double* linv);
 __global__ void k_leaf_elim(const FrontDesc* desc, double* pool, double* linv, int tpw, int level,
                             unsigned long long* err, int32_t* ext);
-__global__ void k_chol_lead(const FrontDesc* desc, double* pool, double* linv, int lds_pmax, int level,
+__global__ void k_chol_lead(const FrontDesc* desc, double* pool, double* linv, int lds_pmax, int level, int step,
                             unsigned long long* err, int32_t* ext);
 __global__ void k_trsm_rows(const FrontDesc* desc, double* pool, const double* linv, int pstride);
 __global__ void k_syrk_schur(const FrontDesc* desc, double* pool);

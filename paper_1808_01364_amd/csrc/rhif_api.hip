@@ -44,6 +44,7 @@ constexpr int kApplyCap = kLdsBudgetDoubles - rhif::kApplyDiagDoubles - rhif::kA
 // largest leading block k_chol_lead factors in LDS ((p|1) p + kPotrfSmemFixed <= 20480 doubles;
 // k_trsm_rows then needs 4 * 17 * 144 doubles)
 constexpr int kCholLdsPmax = 139;
+constexpr int kElimPanel = 128;   // panel width of the elimination of large interiors
 constexpr int kStaticLdsReserve = 32;         // doubles of static LDS a kernel may declare
 constexpr int kRedBlocks = 1024;              // fixed partial-sum layout of the CG reductions
 
@@ -566,12 +567,63 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                 KTIMED(f, s, cls, P.alg_elim_flops, 0.0,
                        hipLaunchKernelGGL(k_leaf_elim, dim3(ncell), dim3(256), lds0, s, LD.potrf, LD.front, linv,
                                           std::max(tpw, 1), lvl, f->err, LD.ext));
-            } else if (!root && lvl > 0 && pmax <= kCholLdsPmax) {
+            } else if (pmax > kCholLdsPmax) {
+                // large interiors (3D upper levels, roots): panel by panel, each panel's
+                // Cholesky, row solves and trailing update as three launches over all cells
+                const int nq = (pmax + kElimPanel - 1) / kElimPanel;
+                std::vector<rhif::FrontDesc> pd;
+                std::vector<int32_t> pd_off(nq + 1, 0), pd_mrow(nq, 0);
+                std::vector<int32_t> ext_all(std::max<int64_t>(P.ext_elems, 1), 0);
+                for (int q = 0; q < nq; ++q) {
+                    const int j0 = q * kElimPanel;
+                    for (const auto& fd : P.cell_potrf) {
+                        if (fd.p <= j0) continue;
+                        rhif::FrontDesc e = fd;
+                        e.off = fd.off + j0 + static_cast<int64_t>(j0) * fd.ld;
+                        e.n = fd.n - j0;
+                        e.p = std::min(kElimPanel, fd.p - j0);
+                        e.ext = fd.ext + j0 / 16;
+                        pd.push_back(e);
+                        pd_mrow[q] = std::max(pd_mrow[q], e.n - e.p);
+                    }
+                    pd_off[q + 1] = static_cast<int32_t>(pd.size());
+                }
+                // the apply's row extents of L: every panel column block runs to the interior's end
+                for (const auto& fd : P.cell_potrf)
+                    for (int t = 0; t < (fd.p + 15) / 16; ++t) ext_all[fd.ext + t] = fd.p;
+                Packer pk;
+                const size_t o_pd = pk.add(pd), o_ext = pk.add(ext_all);
+                char* T = upload(f, pk, s);
+                HIPCHK(hipMemcpyAsync(LD.ext, T + o_ext, ext_all.size() * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                      s));
+                const rhif::FrontDesc* pdd = view<rhif::FrontDesc>(T, o_pd);
+                const size_t lds1 =
+                    static_cast<size_t>(rhif::kPotrfSmemFixed + (kElimPanel | 1) * kElimPanel) * sizeof(double);
+                const int pstride = 17 * kElimPanel;
+                for (int q = 0; q < nq; ++q) {
+                    const unsigned nc = static_cast<unsigned>(pd_off[q + 1] - pd_off[q]);
+                    const rhif::FrontDesc* dq = pdd + pd_off[q];
+                    KTIMED(f, s, cls, q == 0 ? P.alg_elim_flops : 0.0, 0.0,
+                           hipLaunchKernelGGL(k_chol_lead, dim3(nc), dim3(256), lds1, s, dq, LD.front, linv,
+                                              kElimPanel, lvl, root ? 3 : 0, f->err, nullptr));
+                    const int mr = pd_mrow[q];
+                    if (mr > 0) {
+                        KTIMED(f, s, cls, 0.0, 0.0,
+                               hipLaunchKernelGGL(k_trsm_rows, dim3(nc, (mr + 63) / 64), dim3(256),
+                                                  static_cast<size_t>(4 * pstride) * sizeof(double), s, dq, LD.front,
+                                                  linv, pstride));
+                        const int nb = (mr + 31) / 32;
+                        KTIMED(f, s, cls, 0.0, 0.0,
+                               hipLaunchKernelGGL(k_syrk_schur, dim3(nc, nb * (nb + 1) / 2), dim3(256), 0, s, dq,
+                                                  LD.front));
+                    }
+                }
+            } else if (!root && lvl > 0) {
                 // few cells: Cholesky, row solves and Schur update as three wide launches
                 const size_t lds1 = static_cast<size_t>(rhif::kPotrfSmemFixed + (pmax | 1) * pmax) * sizeof(double);
                 KTIMED(f, s, cls, P.alg_elim_flops, 0.0,
                        hipLaunchKernelGGL(k_chol_lead, dim3(ncell), dim3(256), lds1, s, LD.potrf, LD.front, linv,
-                                          kCholLdsPmax, lvl, f->err, LD.ext));
+                                          kCholLdsPmax, lvl, 0, f->err, LD.ext));
                 if (mmax > 0) {
                     const int pstride = 17 * ((pmax + 15) / 16) * 16;
                     KTIMED(f, s, cls, 0.0, 0.0,

@@ -84,7 +84,9 @@ def test_cfg1_parity():
 
 @pytest.mark.parametrize("d,s,leaf,eps,kind,precond", [
     (2, 31, 4, 1e-6, "lognormal", 1), (2, 40, 8, 1e-3, "two_valued", 0), (2, 13, 4, 1e-2, "two_valued", 1),
-    (3, 9, 2, 1e-3, "two_valued", 1), (3, 12, 4, 1e-3, "two_valued", 1)])
+    (3, 9, 2, 1e-3, "two_valued", 1), (3, 12, 4, 1e-3, "two_valued", 1),
+    # interiors and a root larger than one elimination panel (128 columns)
+    (3, 20, 4, 1e-3, "two_valued", 1)])
 def test_small_parity(d, s, leaf, eps, kind, precond):
     P, A = problem(kind, d, s, leaf, eps, seed=2, precond=precond, sigma=2.0, lo=1e-2, hi=1e2)
     out = _parity(P, A)
