@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <stdexcept>
@@ -194,6 +195,71 @@ int grid_for(int64_t N) {
 
 }  // namespace
 
+// Device memory of factor handles. Every handle bump-allocates from chunks that it takes
+// from a per-device cache of freed chunks (hipMalloc only on a miss) and returns them when
+// it is destroyed, after the device has finished with them: a factorization then performs
+// no allocation call once the cache holds chunks of the sizes it needs.
+class ChunkCache {
+public:
+    static ChunkCache& of_device(int dev) {
+        static std::mutex mu;
+        static std::map<int, ChunkCache*> all;
+        std::lock_guard<std::mutex> lk(mu);
+        ChunkCache*& c = all[dev];
+        if (!c) c = new ChunkCache();
+        return *c;
+    }
+    // A chunk of at least `want` bytes (and at most twice as large if taken from the cache).
+    void* take(size_t want, size_t& got) {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            auto it = free_.lower_bound(want);
+            if (it != free_.end() && it->first <= 2 * want) {
+                got = it->first;
+                void* p = it->second;
+                free_.erase(it);
+                cached_ -= got;
+                return p;
+            }
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            trim(0);   // give the cached chunks back to the device and try once more
+            if (hipMalloc(&p, want) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+        }
+        got = want;
+        return p;
+    }
+    void give(void* p, size_t bytes) {
+        std::lock_guard<std::mutex> lk(mu_);
+        free_.emplace(bytes, p);
+        cached_ += bytes;
+        if (cached_ > kMaxCached) trim_locked(kMaxCached);
+    }
+    void trim(size_t keep) {
+        std::lock_guard<std::mutex> lk(mu_);
+        trim_locked(keep);
+    }
+
+private:
+    static constexpr size_t kMaxCached = size_t(64) << 30;   // bytes kept for reuse per device
+    void trim_locked(size_t keep) {
+        while (cached_ > keep && !free_.empty()) {
+            auto it = std::prev(free_.end());   // largest first
+            (void)hipFree(it->second);
+            cached_ -= it->first;
+            free_.erase(it);
+        }
+    }
+    std::mutex mu_;
+    std::multimap<size_t, void*> free_;
+    size_t cached_ = 0;
+};
+
 struct rhif_factor_s {
     rhif::GridInfo g;
     rhif_opts o{};
@@ -228,8 +294,14 @@ struct rhif_factor_s {
     bool graphs_off = false;
 
     rhif_stats_t stats{};
-    std::vector<void*> allocs;
-    hipStream_t alloc_stream = nullptr;
+    struct Chunk {
+        void* p;
+        size_t bytes;
+    };
+    std::vector<Chunk> chunks;   // device memory of the handle (from ChunkCache)
+    char* chunk_cur = nullptr;
+    size_t chunk_left = 0;
+    int device = 0;
     // per-launch device timing (RHIF_FLAG_KERNEL_TIMES)
     bool ktimes = false;
     uint32_t kmask = 0xffffu;
@@ -278,14 +350,25 @@ struct rhif_factor_s {
         pend.clear();
     }
 
+    static constexpr size_t kChunkBytes = size_t(64) << 20;
     void* dalloc(size_t bytes) {
-        void* ptr = nullptr;
-        HIPCHK(hipMallocAsync(&ptr, std::max<size_t>(bytes, 256), alloc_stream));
-        allocs.push_back(ptr);
+        const size_t b = (std::max<size_t>(bytes, 256) + 255) / 256 * 256;
+        if (b > chunk_left) {
+            size_t got = 0;
+            void* p = ChunkCache::of_device(device).take(std::max(b, kChunkBytes), got);
+            if (!p) fail(RHIF_ENOMEM, "device allocation failed");
+            chunks.push_back({p, got});
+            chunk_cur = static_cast<char*>(p);
+            chunk_left = got;
+        }
+        void* ptr = chunk_cur;
+        chunk_cur += b;
+        chunk_left -= b;
         return ptr;
     }
     void release() {
-        (void)hipStreamSynchronize(alloc_stream);
+        // the chunks go back to the cache only once no work of this handle can still use them
+        (void)hipDeviceSynchronize();
         for (int g = 0; g < 3; ++g) {
             if (gexec[g]) (void)hipGraphExecDestroy(gexec[g]);
             if (graph[g]) (void)hipGraphDestroy(graph[g]);
@@ -309,8 +392,11 @@ struct rhif_factor_s {
         pend.clear();
         for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
         evpool.clear();
-        for (void* ptr : allocs) (void)hipFree(ptr);
-        allocs.clear();
+        ChunkCache& cc = ChunkCache::of_device(device);
+        for (const Chunk& c : chunks) cc.give(c.p, c.bytes);
+        chunks.clear();
+        chunk_cur = nullptr;
+        chunk_left = 0;
     }
 };
 
@@ -332,18 +418,6 @@ namespace {
             (f)->pend.push_back({ea_, eb_, (cls), (fl), (by)});              \
         }                                                                    \
     } while (0)
-
-void set_pool_threshold() {
-    static std::once_flag once;
-    std::call_once(once, [] {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess) return;
-        hipMemPool_t pool;
-        if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess) return;
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    });
-}
 
 void validate_grid(const rhif_grid* g) {
     if (!g) fail(RHIF_EINVAL, "grid is NULL");
@@ -1169,10 +1243,9 @@ rhif_status rhif_factor(const rhif_grid* g, const rhif_opts* o, const int32_t* r
         if (o->precond != 0 && o->precond != 1) fail(RHIF_EINVAL, "precond must be 0 or 1");
         if (o->precision != 0) fail(RHIF_EINVAL, "only precision 0 (FP64) is available");
         if (!row_ptr || !col || !val) fail(RHIF_EINVAL, "NULL CSR pointer");
-        set_pool_threshold();
         set_kernel_attributes();
         f = new rhif_factor_s();
-        f->alloc_stream = s;
+        HIPCHK(hipGetDevice(&f->device));
         f->g.d = g->dim;
         f->g.s = g->n[0];
         f->g.N = 1;
