@@ -109,11 +109,14 @@ def main():
     dom_id = rhif.KCLASS_NAMES.index(dom)
     # the timed steps bracket only the dominant kernel's launches with events
     flags = rhif.FLAG_KERNEL_TIMES | ((1 << dom_id) << rhif.KERNEL_MASK_SHIFT)
-    keep = []
+    # every step factors, solves and frees its factor, so that the next step reuses its
+    # device memory (the steady state of a solver that serves one system after another)
+    kvs = []
     t_fac, t_pcg = [], []
+    F = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         ta = time.perf_counter()
         F = rhif.Factor(2, P.s, csr, P.leaf, P.eps, 1, flags=flags)
         tb = time.perf_counter()
@@ -122,16 +125,16 @@ def main():
         tc = time.perf_counter()
         t_fac.append(tb - ta)
         t_pcg.append(tc - tb)
-        keep.append((F, it, rr))
+        kvs.append(F.stats()["kernels"].get(dom))
+        if k + 1 < args.steps:
+            F.close()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     total = t1 - t0
-    F, it, rr = keep[-1]
     st = F.stats()
     kms = kfl = kby = 0.0
     kl = 0
-    for Fk, _, _ in keep:
-        kv = Fk.stats()["kernels"].get(dom)
+    for kv in kvs:
         if kv:
             kms += kv["ms"]
             kfl += kv["flops"]
@@ -177,8 +180,7 @@ def main():
     }
     out["roofline"] = roof
     out["kernel_ms_warmup"] = {k: round(v, 4) for k, v in sorted(per_class.items(), key=lambda kv: -kv[1])}
-    for F, _, _ in keep:
-        F.close()
+    F.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, min(args.cpu_sample_side, P.s))
     print(json.dumps(out), flush=True)

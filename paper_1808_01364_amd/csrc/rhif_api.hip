@@ -195,6 +195,39 @@ int grid_for(int64_t N) {
 
 }  // namespace
 
+// Pinned host words for the PCG scalars of a handle: 64-byte slots carved from pages that
+// are allocated once and recycled between handles (no pinned allocation per handle).
+class PinnedSlots {
+public:
+    static PinnedSlots& get() {
+        static PinnedSlots* p = new PinnedSlots();
+        return *p;
+    }
+    double* take() {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (free_.empty()) {
+            char* page = nullptr;
+            if (hipHostMalloc(reinterpret_cast<void**>(&page), kPage, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+            for (size_t o = 0; o < kPage; o += kSlot) free_.push_back(reinterpret_cast<double*>(page + o));
+        }
+        double* p = free_.back();
+        free_.pop_back();
+        return p;
+    }
+    void give(double* p) {
+        std::lock_guard<std::mutex> lk(mu_);
+        free_.push_back(p);
+    }
+
+private:
+    static constexpr size_t kPage = 4096, kSlot = 64;
+    std::mutex mu_;
+    std::vector<double*> free_;
+};
+
 // Device memory of factor handles. Every handle bump-allocates from chunks that it takes
 // from a per-device cache of freed chunks (hipMalloc only on a miss) and returns them when
 // it is destroyed, after the device has finished with them: a factorization then performs
@@ -382,7 +415,7 @@ struct rhif_factor_s {
         }
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         cap_stream = nullptr;
-        if (hsc) (void)hipHostFree(hsc);
+        if (hsc) PinnedSlots::get().give(hsc);
         hsc = nullptr;
         for (const Pend& q : pend) {
             (void)hipEventSynchronize(q.b);
@@ -1095,7 +1128,8 @@ void ensure_pcg(rhif_factor_s* f) {
     f->q = static_cast<double*>(f->dalloc(vb));
     f->part = static_cast<double*>(f->dalloc(kRedBlocks * sizeof(double)));
     f->sc = static_cast<double*>(f->dalloc(16 * sizeof(double)));
-    if (hipHostMalloc(reinterpret_cast<void**>(&f->hsc), 64, hipHostMallocDefault) != hipSuccess)
+    f->hsc = PinnedSlots::get().take();
+    if (f->hsc == nullptr)
         fail(RHIF_ENOMEM, "pinned host allocation failed");
 }
 
