@@ -379,12 +379,23 @@ __device__ __forceinline__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int
                 double w1 = 0.0, w2 = 0.0, w3 = 0.0;
                 if (has_j) w = v0 * M[static_cast<size_t>(j) * ldr + c];
                 int i = ib;
-                for (; i + 3 < i1; i += 4) {
+                // eight rows per round, every load issued before the products
+                for (; i + 7 < i1; i += 8) {
                     const double* Mi = M + static_cast<size_t>(i) * ldr;
-                    w += Mi[pc] * Mi[c];
-                    w1 += Mi[ldr + pc] * Mi[ldr + c];
-                    w2 += Mi[2 * ldr + pc] * Mi[2 * ldr + c];
-                    w3 += Mi[3 * ldr + pc] * Mi[3 * ldr + c];
+                    double a[8], b[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        a[u] = Mi[u * ldr + pc];
+                        b[u] = Mi[u * ldr + c];
+                    }
+                    w += a[0] * b[0];
+                    w1 += a[1] * b[1];
+                    w2 += a[2] * b[2];
+                    w3 += a[3] * b[3];
+                    w += a[4] * b[4];
+                    w1 += a[5] * b[5];
+                    w2 += a[6] * b[6];
+                    w3 += a[7] * b[7];
                 }
                 for (; i < i1; ++i) w += M[static_cast<size_t>(i) * ldr + pc] * M[static_cast<size_t>(i) * ldr + c];
                 w += (w1 + w2) + w3;
@@ -402,20 +413,27 @@ __device__ __forceinline__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int
                 if (has_j) M[static_cast<size_t>(j) * ldr + c] -= f * v0;
                 double sq = 0.0, sq1 = 0.0, sq2 = 0.0, sq3 = 0.0;
                 int i = ib;
-                for (; i + 3 < i1; i += 4) {
+                for (; i + 7 < i1; i += 8) {
                     double* Mi = M + static_cast<size_t>(i) * ldr;
-                    const double n0 = Mi[c] - f * Mi[pc];
-                    const double n1 = Mi[ldr + c] - f * Mi[ldr + pc];
-                    const double n2 = Mi[2 * ldr + c] - f * Mi[2 * ldr + pc];
-                    const double n3 = Mi[3 * ldr + c] - f * Mi[3 * ldr + pc];
-                    Mi[c] = n0;
-                    Mi[ldr + c] = n1;
-                    Mi[2 * ldr + c] = n2;
-                    Mi[3 * ldr + c] = n3;
-                    sq += n0 * n0;
-                    sq1 += n1 * n1;
-                    sq2 += n2 * n2;
-                    sq3 += n3 * n3;
+                    double a[8], b[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        a[u] = Mi[u * ldr + pc];
+                        b[u] = Mi[u * ldr + c];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        b[u] -= f * a[u];
+                        Mi[u * ldr + c] = b[u];
+                    }
+                    sq += b[0] * b[0];
+                    sq1 += b[1] * b[1];
+                    sq2 += b[2] * b[2];
+                    sq3 += b[3] * b[3];
+                    sq += b[4] * b[4];
+                    sq1 += b[5] * b[5];
+                    sq2 += b[6] * b[6];
+                    sq3 += b[7] * b[7];
                 }
                 for (; i < i1; ++i) {
                     const double nv = M[static_cast<size_t>(i) * ldr + c] - f * M[static_cast<size_t>(i) * ldr + pc];
@@ -1246,9 +1264,9 @@ __global__ __launch_bounds__(256) void k_precond_scale(const CellScaleDesc* __re
 // The row table of M = A[R_g, g] (Sec. 2.2): R_g is the other boundary groups of the
 // group's first cell (with the second cell's position where the group is shared), then the
 // second cell's groups not in the first. rwl[2 i], rwl[2 i + 1] receive row i's position in
-// either cell (-1: none). The cells' group lists are staged in LDS by all threads, then one
-// thread builds the segments (first row, count, positions); a row count that disagrees with
-// the plan is reported. scratch: 4 * kMaxSkelSegs + 2 + 4 * kMaxCellGroups ints.
+// either cell (-1: none). The cells' group lists are staged in LDS by all threads, then the
+// first wave builds the segments (first row, count, positions), one lane per list entry; a
+// row count that disagrees with the plan is reported. scratch: 4 * kMaxSkelSegs + 2 + 4 * kMaxCellGroups ints.
 __device__ __forceinline__ void build_row_table(const SkelDesc& g, const int32_t* __restrict__ cgptr,
                                                 const int32_t* __restrict__ cgl, const int32_t* __restrict__ cgoff,
                                                 int nf0, int nf1, int r, int* rwl, int* scratch, int level,
@@ -1271,54 +1289,60 @@ __device__ __forceinline__ void build_row_table(const SkelDesc& g, const int32_t
         lst[3 * kMaxCellGroups + e] = cgoff[b0 + e];
     }
     __syncthreads();
-    if (tid == 0) {
-        int ns = 0, rr = 0;
-        bool ok = fits;
+    if (tid < 64) {
+        // wave 0, one lane per list entry: lanes 0..31 the first cell's groups in order, lanes
+        // 32..63 the second cell's; a wave prefix sum places every kept group's rows
+        const int lane = tid;
         const int* ga = lst;
         const int* oa = lst + kMaxCellGroups;
         const int* gb = lst + 2 * kMaxCellGroups;
         const int* ob = lst + 3 * kMaxCellGroups;
-        for (int e = 0; e < na; ++e) {
-            const int h = ga[e];
-            if (h == g.grp) continue;
-            const int nh = ((e + 1 < na) ? oa[e + 1] : nf0) - oa[e];
-            int o2 = -1;
-            for (int f2 = 0; f2 < nbl; ++f2)
-                if (gb[f2] == h) o2 = ob[f2];
-            if (ns < kMaxSkelSegs) {
-                seg[4 * ns] = rr;
-                seg[4 * ns + 1] = nh;
-                seg[4 * ns + 2] = oa[e];
-                seg[4 * ns + 3] = o2;
-            } else {
-                ok = false;
+        bool keep = false;
+        int nh = 0, p1 = -1, p2 = -1;
+        if (lane < 32) {
+            const int e = lane;
+            if (e < na && ga[e] != g.grp) {
+                const int h = ga[e];
+                keep = true;
+                nh = ((e + 1 < na) ? oa[e + 1] : nf0) - oa[e];
+                p1 = oa[e];
+                for (int f2 = 0; f2 < nbl; ++f2)
+                    if (gb[f2] == h) p2 = ob[f2];
             }
-            ++ns;
-            rr += nh;
-        }
-        for (int f2 = 0; f2 < nbl; ++f2) {
-            const int h = gb[f2];
-            if (h == g.grp) continue;
-            bool shared = false;
-            for (int e = 0; e < na; ++e) shared = shared || (ga[e] == h);
-            if (shared) continue;
-            const int nh = ((f2 + 1 < nbl) ? ob[f2 + 1] : nf1) - ob[f2];
-            if (ns < kMaxSkelSegs) {
-                seg[4 * ns] = rr;
-                seg[4 * ns + 1] = nh;
-                seg[4 * ns + 2] = -1;
-                seg[4 * ns + 3] = ob[f2];
-            } else {
-                ok = false;
+        } else {
+            const int f2 = lane - 32;
+            if (f2 < nbl && gb[f2] != g.grp) {
+                const int h = gb[f2];
+                bool shared = false;
+                for (int e = 0; e < na; ++e) shared = shared || (ga[e] == h);
+                if (!shared) {
+                    keep = true;
+                    nh = ((f2 + 1 < nbl) ? ob[f2 + 1] : nf1) - ob[f2];
+                    p2 = ob[f2];
+                }
             }
-            ++ns;
-            rr += nh;
         }
-        if (!ok || rr != r) {
-            report(err, err_code(level, 7, blockIdx.x));
-            ns = 0;
+        const unsigned long long km = __ballot(keep);
+        const int idx = __popcll(km & ((1ull << lane) - 1ull));
+        const int ns = __popcll(km);
+        int incl = nh;   // inclusive prefix sum of the kept groups' sizes
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += o;
         }
-        *nseg = ns;
+        const int total = __shfl(incl, 63, 64);
+        if (keep && idx < kMaxSkelSegs) {
+            seg[4 * idx] = incl - nh;
+            seg[4 * idx + 1] = nh;
+            seg[4 * idx + 2] = p1;
+            seg[4 * idx + 3] = p2;
+        }
+        if (lane == 0) {
+            const bool ok = fits && ns <= kMaxSkelSegs && total == r;
+            if (!ok) report(err, err_code(level, 7, blockIdx.x));
+            *nseg = ok ? ns : 0;
+        }
     }
     __syncthreads();
     const int ns = *nseg;
@@ -1370,14 +1394,14 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
     const double* f0 = F + c0.off + static_cast<size_t>(g.off[0]) * c0.ld;
     const double* f1 = F + c1.off + static_cast<size_t>(g.off[1]) * c1.ld;
     build_row_table(g, cgptr, cgl, cgoff, c0.nf, c1.nf, r, rwl, reinterpret_cast<int*>(part), level, err);
-    // 1. M = A[R_g, g] (row-major), the shares of both cells added; four independent
+    // 1. M = A[R_g, g] (row-major), the shares of both cells added; eight independent
     //    loads in flight per thread
     const int rn = r * n;
-    for (int e0 = tid; e0 < rn; e0 += 4 * kWG) {
-        double v[4];
-        int dst[4];
+    for (int e0 = tid; e0 < rn; e0 += 8 * kWG) {
+        double v[8];
+        int dst[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             const int e = e0 + u * kWG;
             v[u] = 0.0;
             dst[u] = -1;
@@ -1390,7 +1414,7 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 8; ++u)
             if (dst[u] >= 0) M[dst[u]] = v[u];
     }
     __syncthreads();
@@ -1499,14 +1523,14 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
     extern __shared__ double smem[];
     const SkelDesc g = sd[blockIdx.x];
     if (staged == 3)
-        skeletonize_one<true, true>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout, panel_cap, nmax, rmax,
-                                    level, err, smem);
+        skeletonize_one<true, true>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout,
+                                    panel_cap, nmax, rmax, level, err, smem);
     else if (staged == 1)
-        skeletonize_one<true, false>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout, panel_cap, nmax, rmax,
-                                     level, err, smem);
+        skeletonize_one<true, false>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout,
+                                     panel_cap, nmax, rmax, level, err, smem);
     else
-        skeletonize_one<false, false>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout, panel_cap, nmax, rmax,
-                                      level, err, smem);
+        skeletonize_one<false, false>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout,
+                                      panel_cap, nmax, rmax, level, err, smem);
 }
 
 // ---------------------------------------------------------------------------------------
