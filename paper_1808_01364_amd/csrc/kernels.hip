@@ -633,25 +633,37 @@ __global__ __launch_bounds__(256) void k_front_extend(const Tile* __restrict__ t
                                                       const int32_t* __restrict__ src, int W,
                                                       const CellRef* __restrict__ child, const double* __restrict__ Fc,
                                                       double* __restrict__ F) {
+    // the tile's column sources (2 W ints per column, W <= 8), staged once
+    __shared__ int32_t qs[64 * 16];
     const Tile t = tiles[blockIdx.x];
     const CellRef cr = cells[t.cell];
     const int nf = cr.nf;
+    const int ncol = min(64, nf - t.c0);
+    const int32_t* sc = src + static_cast<size_t>(cr.dptr + t.c0) * 2 * W;
+    for (int e = threadIdx.x; e < ncol * 2 * W; e += kWG) qs[e] = sc[e];
+    // the row's sources: child, and the element offset of the row in that child's frontal
     const int p = t.r0 + (threadIdx.x & 63);
-    if (p >= nf) return;
-    int pc[8], pp[8];
+    const bool prow = p < nf;
+    int pc[8], cld[8];
+    int64_t coff[8];
     int np = 0;
-    const int32_t* sp = src + static_cast<size_t>(cr.dptr + p) * 2 * W;
-    for (int a = 0; a < W; ++a) {
-        const int c = sp[2 * a];
-        if (c < 0) break;
-        pc[np] = c;
-        pp[np] = sp[2 * a + 1];
-        ++np;
+    if (prow) {
+        const int32_t* sp = src + static_cast<size_t>(cr.dptr + p) * 2 * W;
+        for (int a = 0; a < W; ++a) {
+            const int c = sp[2 * a];
+            if (c < 0) break;
+            const CellRef ch = child[c];
+            pc[np] = c;
+            coff[np] = ch.off + sp[2 * a + 1];
+            cld[np] = ch.ld;
+            ++np;
+        }
     }
-    for (int cq = threadIdx.x >> 6; cq < 64; cq += 4) {
+    __syncthreads();
+    if (!prow) return;
+    for (int cq = threadIdx.x >> 6; cq < ncol; cq += 4) {
         const int q = t.c0 + cq;
-        if (q >= nf) break;
-        const int32_t* sq = src + static_cast<size_t>(cr.dptr + q) * 2 * W;
+        const int32_t* sq = qs + cq * 2 * W;
         double v = 0.0;
         int b = 0;
         for (int a = 0; a < np; ++a) {
@@ -661,10 +673,7 @@ __global__ __launch_bounds__(256) void k_front_extend(const Tile* __restrict__ t
                 if (cb < 0 || cb >= pc[a]) break;
                 ++b;
             }
-            if (b < W && sq[2 * b] == pc[a]) {
-                const CellRef ch = child[pc[a]];
-                v += Fc[ch.off + pp[a] + static_cast<size_t>(sq[2 * b + 1]) * ch.ld];
-            }
+            if (b < W && sq[2 * b] == pc[a]) v += Fc[coff[a] + static_cast<size_t>(sq[2 * b + 1]) * cld[a]];
         }
         F[cr.off + p + static_cast<size_t>(q) * cr.ld] = v;
     }
