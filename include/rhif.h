@@ -183,6 +183,20 @@ rhif_status rhif_apply(rhif_factor_t f, const double *r, double *z, int32_t nrhs
 rhif_status rhif_pcg_solve(rhif_factor_t f, const double *rhs, double *u, double rtol,
                            int32_t maxit, int32_t *iters, double *relres, hipStream_t s);
 
+/* Adjoint of the solve with respect to theta = log a (the adjoint-gradient extension of the
+ * solver; the operator is eq. (1.1) with the Sec. 3.1 / 3.2 stencils): for every grid cell c,
+ *   grad[c] = -a_c * lambda^T (dA/da_c) u
+ *           = -a_c 2^(1-d) h^-2 sum over the cell's grid edges (x, x+e_k) of
+ *             (lambda(x+e_k) - lambda(x)) (u(x+e_k) - u(x)),      values at ghosts = 0,
+ * which is dL/dtheta_c for a loss L(u) of the solution of A u = f when A lambda = dL/du
+ * (A is symmetric, so lambda comes from the same factorization). b does not depend on a.
+ *  a_cells [device] (n+1)^d cell coefficients, x_1 fastest (as for rhif_assemble_fd)
+ *  u, lam  [device] N values each (solution and adjoint solution)
+ *  grad    [device] (n+1)^d outputs, caller-owned
+ * Stream-ordered on s. Errors: EINVAL for a malformed grid or a NULL pointer. */
+rhif_status rhif_grad_log_a(const rhif_grid *g, const double *a_cells, const double *u, const double *lam,
+                            double *grad, hipStream_t s);
+
 /* y = A x with the handle's copy of A (x, y [device] N doubles). */
 rhif_status rhif_matvec(rhif_factor_t f, const double *x, double *y, hipStream_t s);
 

@@ -14,4 +14,5 @@ from .rhif_oracle import (  # noqa: F401
     apply_inverse,
     pcg,
     dense_solve,
+    grad_log_a,
 )

@@ -624,6 +624,43 @@ def pcg(A: sp.csr_matrix, f: np.ndarray, precond=None, rtol: float = 1e-12, maxi
     return PCGResult(u, it, hist[-1], true_rel, converged, hist)
 
 
+def grad_log_a(d: int, s: int, a_cells: np.ndarray, u: np.ndarray, lam: np.ndarray) -> np.ndarray:
+    """Gradient with respect to theta = log a of a loss L(u) of the solution of A u = f,
+    given the adjoint solution lam = A^-1 dL/du (A is symmetric):
+        dL/dtheta_c = -a_c * lam^T (dA/da_c) u.
+    With the cell-wise form of the operator (eq. (1.1) with reading R2, the bilinear version
+    of fd_energy), lam^T (dA/da_c) u is 2^(1-d) / h^2 times the sum, over the grid edges
+    (p, p + e_k) of cell c, of (lam(p + e_k) - lam(p)) * (u(p + e_k) - u(p)), with the values
+    at the Dirichlet ghosts 0. Cell c = (c_1..c_d), c_k in 0..s, has the grid points with
+    x_k in {c_k, c_k + 1} as corners. Plain loops over cells and edges."""
+    h = 1.0 / (s + 1)
+    a_cells = np.asarray(a_cells, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64).ravel()
+    lam = np.asarray(lam, dtype=np.float64).ravel()
+
+    def val(v, x):
+        if any(xk < 1 or xk > s for xk in x):
+            return 0.0
+        return v[sum((xk - 1) * s ** k for k, xk in enumerate(x))]
+
+    a_flat = a_cells.ravel()   # indexed [c_d, ..., c_1]: c_1 fastest
+    g = np.zeros((s + 1) ** d)
+    for c in range((s + 1) ** d):
+        cc = [(c // (s + 1) ** k) % (s + 1) for k in range(d)]
+        acc = 0.0
+        for k in range(d):
+            others = [j for j in range(d) if j != k]
+            for shifts in product((0, 1), repeat=d - 1):
+                p = list(cc)
+                for j, sh in zip(others, shifts):
+                    p[j] = cc[j] + sh
+                q = list(p)
+                q[k] += 1
+                acc += (val(lam, q) - val(lam, p)) * (val(u, q) - val(u, p))
+        g[c] = -a_flat[c] * acc * 2.0 ** (1 - d) / (h * h)
+    return g.reshape(a_cells.shape)
+
+
 def dense_solve(A: sp.csr_matrix, f: np.ndarray) -> np.ndarray:
     """Brute force: dense Cholesky solve (small problems only)."""
     Ad = A.toarray()

@@ -459,6 +459,64 @@ __device__ __forceinline__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int
 }
 
 // ---------------------------------------------------------------------------------------
+// Adjoint of the solve with respect to the log-coefficients theta = log a (one thread per
+// grid cell). A depends on a_c through the cell's share of the stencil (eq. (1.1) with the
+// edge rule of the assembly below): every grid edge (x, x + e_k) of cell c carries
+// a_c 2^(1-d) / h^2 of its edge coefficient, so
+//   lambda^T (dA/da_c) u = 2^(1-d) h^-2 sum over the cell's edges of
+//                          (lambda(x + e_k) - lambda(x)) (u(x + e_k) - u(x))
+// (values at the Dirichlet ghosts are 0) and the gradient of a loss L(u) with
+// A lambda = dL/du is dL/dtheta_c = -a_c lambda^T (dA/da_c) u. Cell c = (c_1..c_d),
+// c_k in 0..s, x_1 fastest, has corners x_k in {c_k, c_k + 1}.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double grid_value(const double* v, int d, int s, const int* x) {
+    int64_t lin = 0, mul = 1;
+    for (int k = 0; k < d; ++k) {
+        if (x[k] < 1 || x[k] > s) return 0.0;
+        lin += static_cast<int64_t>(x[k] - 1) * mul;
+        mul *= s;
+    }
+    return v[lin];
+}
+
+__global__ __launch_bounds__(256) void k_grad_log_a(int d, int s, double inv_h2, const double* __restrict__ a,
+                                                    const double* __restrict__ u, const double* __restrict__ lam,
+                                                    double* __restrict__ g) {
+    int64_t nc = 1;
+    for (int k = 0; k < d; ++k) nc *= (s + 1);
+    for (int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; c < nc;
+         c += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        int cc[3] = {0, 0, 0};
+        int64_t r = c;
+        for (int k = 0; k < d; ++k) {
+            cc[k] = static_cast<int>(r % (s + 1));
+            r /= (s + 1);
+        }
+        double acc = 0.0;
+        for (int k = 0; k < d; ++k) {
+            // the 2^(d-1) edges along axis k: the other coordinates at c_j or c_j + 1
+            for (int t = 0; t < (1 << (d - 1)); ++t) {
+                int x[3], y[3];
+                int bit = 0;
+                for (int j = 0; j < d; ++j) {
+                    if (j == k) {
+                        x[j] = cc[j];
+                        y[j] = cc[j] + 1;
+                    } else {
+                        x[j] = y[j] = cc[j] + ((t >> bit) & 1);
+                        ++bit;
+                    }
+                }
+                const double du = grid_value(u, d, s, y) - grid_value(u, d, s, x);
+                const double dl = grid_value(lam, d, s, y) - grid_value(lam, d, s, x);
+                acc += dl * du;
+            }
+        }
+        g[c] = -a[c] * acc * inv_h2 / static_cast<double>(1 << (d - 1));
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // Assembly of A = h^-2 K(a) + diag(b) (5-point / 7-point, Sec. 3.1 / 3.2): one thread per
 // row; the row pointer was filled on the host.
 // ---------------------------------------------------------------------------------------

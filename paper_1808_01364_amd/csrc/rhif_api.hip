@@ -1351,6 +1351,21 @@ rhif_status rhif_apply(rhif_factor_t f, const double* r, double* z, int32_t nrhs
     API_END
 }
 
+rhif_status rhif_grad_log_a(const rhif_grid* g, const double* a_cells, const double* u, const double* lam,
+                            double* grad, hipStream_t s) {
+    API_BEGIN
+    validate_grid(g);
+    if (!a_cells || !u || !lam || !grad) fail(RHIF_EINVAL, "NULL device pointer");
+    const int d = g->dim, sd = g->n[0];
+    int64_t nc = 1;
+    for (int k = 0; k < d; ++k) nc *= (sd + 1);
+    const double h = 1.0 / (sd + 1);
+    const int grid = static_cast<int>(std::min<int64_t>((nc + 255) / 256, 65535));
+    hipLaunchKernelGGL(rhif::k_grad_log_a, dim3(grid), dim3(256), 0, s, d, sd, 1.0 / (h * h), a_cells, u, lam, grad);
+    HIPCHK(hipGetLastError());
+    API_END
+}
+
 rhif_status rhif_matvec(rhif_factor_t f, const double* x, double* y, hipStream_t s) {
     API_BEGIN
     if (!f || !x || !y) fail(RHIF_EINVAL, "NULL argument");

@@ -31,8 +31,8 @@ KCLASS_NAMES = ["front_csr", "front_extend", "elim_leaf", "elim_upper", "root", 
 
 # every function declared in include/rhif.h
 EXPORTED = ["rhif_fd_nnz", "rhif_assemble_fd", "rhif_factor", "rhif_apply", "rhif_pcg_solve",
-            "rhif_matvec", "rhif_stats", "rhif_skeletons", "rhif_destroy", "rhif_last_error",
-            "rhif_version"]
+            "rhif_matvec", "rhif_grad_log_a", "rhif_stats", "rhif_skeletons", "rhif_destroy",
+            "rhif_last_error", "rhif_version"]
 
 
 class RhifError(RuntimeError):
@@ -101,6 +101,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rhif_pcg_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int32, c_i32p,
                                    ctypes.POINTER(ctypes.c_double), vp]
     lib.rhif_matvec.argtypes = [vp, vp, vp, vp]
+    lib.rhif_grad_log_a.argtypes = [ctypes.POINTER(Grid), vp, vp, vp, vp, vp]
     lib.rhif_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.rhif_skeletons.argtypes = [vp, ctypes.c_int32, c_i32p, ctypes.POINTER(ctypes.c_int64), c_i32p, c_i32p,
                                    c_i32p, c_i32p]
@@ -171,6 +172,19 @@ def assemble_fd(dim: int, n: int, a_cells, b=None, stream=None):
     _check(load_library().rhif_assemble_fd(ctypes.byref(make_grid(dim, n)), _ptr(a_cells), _ptr(b),
                                            _ptr(rp), _ptr(col), _ptr(val), _stream(stream)))
     return rp, col, val
+
+
+def grad_log_a(dim: int, n: int, a_cells, u, lam, stream=None):
+    """Per-cell -a_c lam^T (dA/da_c) u as a device tensor of (n+1)^dim values (c_1 fastest):
+    the gradient with respect to log a of a loss of the solution u when A lam = dL/du."""
+    torch = _torch()
+    a_cells = a_cells.contiguous().to(torch.float64)
+    u = u.contiguous().to(torch.float64)
+    lam = lam.contiguous().to(torch.float64)
+    g = torch.empty_like(a_cells)
+    _check(load_library().rhif_grad_log_a(ctypes.byref(make_grid(dim, n)), _ptr(a_cells), _ptr(u), _ptr(lam),
+                                          _ptr(g), _stream(stream)))
+    return g
 
 
 @dataclass

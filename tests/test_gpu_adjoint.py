@@ -1,0 +1,158 @@
+"""Adjoint gradient with respect to theta = log a (the solver's adjoint extension), through the
+C ABI: the per-cell gradient kernel against the oracle's formula, the autograd solve against
+dense torch autograd on a 32^2 grid, and against central finite differences of the loss on
+20 cells of a 256^2 problem (perturbation solves with the library)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.gpu_common import rel, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("d,s", [(2, 37), (3, 9)])
+def test_grad_kernel_parity(d, s):
+    """rhif_grad_log_a equals the oracle's cell-by-cell formula on random inputs."""
+    from paper_1808_01364_amd import rhif
+    rng = np.random.default_rng(7)
+    a = np.exp(rng.standard_normal((s + 1,) * d))
+    u = rng.standard_normal(s ** d)
+    lam = rng.standard_normal(s ** d)
+    g = _host(rhif.grad_log_a(d, s, to_dev(a), to_dev(u), to_dev(lam)))
+    ref = O.grad_log_a(d, s, a, u, lam).ravel()
+    assert rel(g, ref) < 1e-13
+
+
+def _inverse_problem(s, leaf):
+    """theta = GRF(sigma 1, corr 8, seed 3); u_obs = the solution for a second field (seed 4)
+    plus 1 % Gaussian noise; f ~ N(0, 1) from default_rng(5)."""
+    from workloads.fields import gaussian_random_field
+    theta = gaussian_random_field(np.random.default_rng(3), 2, s, 8.0)
+    a_true = np.exp(gaussian_random_field(np.random.default_rng(4), 2, s, 8.0))
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal(s * s)
+    A = O.assemble_fd(2, s, a_true, None)
+    u_true = O.dense_solve(A, f) if s <= 64 else None
+    return theta, a_true, f, u_true, rng
+
+
+def _dense_torch_loss(theta_t, f, u_obs, s):
+    """0.5 |u - u_obs|^2 with A(exp theta) built densely by torch from the same stencil rule
+    (edge coefficient = mean of the cells containing the edge, A = h^-2 sum w (e_p - e_q)^2
+    terms, ghost endpoints dropped) and solved with torch.linalg.solve."""
+    import torch
+    h = 1.0 / (s + 1)
+    a = torch.exp(theta_t)                     # indexed [c_2, c_1]
+    N = s * s
+    rows, cols, vals = [], [], []
+
+    def lin(x1, x2):
+        return (x2 - 1) * s + (x1 - 1)
+
+    # edges along x_1: from (x1, x2) to (x1 + 1, x2), x1 in 0..s, x2 in 1..s
+    for x2 in range(1, s + 1):
+        for x1 in range(0, s + 1):
+            w = 0.5 * (a[x2 - 1, x1] + a[x2, x1]) / (h * h)
+            for p, q in [((x1, x2), (x1 + 1, x2))]:
+                pv = 1 <= p[0] <= s
+                qv = 1 <= q[0] <= s
+                if pv:
+                    rows.append(lin(*p)); cols.append(lin(*p)); vals.append(w)
+                if qv:
+                    rows.append(lin(*q)); cols.append(lin(*q)); vals.append(w)
+                if pv and qv:
+                    rows += [lin(*p), lin(*q)]; cols += [lin(*q), lin(*p)]; vals += [-w, -w]
+    # edges along x_2
+    for x1 in range(1, s + 1):
+        for x2 in range(0, s + 1):
+            w = 0.5 * (a[x2, x1 - 1] + a[x2, x1]) / (h * h)
+            p, q = (x1, x2), (x1, x2 + 1)
+            pv = 1 <= p[1] <= s
+            qv = 1 <= q[1] <= s
+            if pv:
+                rows.append(lin(*p)); cols.append(lin(*p)); vals.append(w)
+            if qv:
+                rows.append(lin(*q)); cols.append(lin(*q)); vals.append(w)
+            if pv and qv:
+                rows += [lin(*p), lin(*q)]; cols += [lin(*q), lin(*p)]; vals += [-w, -w]
+    A = torch.zeros(N, N, dtype=torch.float64)
+    A = A.index_put((torch.tensor(rows), torch.tensor(cols)), torch.stack(vals), accumulate=True)
+    u = torch.linalg.solve(A, torch.tensor(f))
+    return 0.5 * torch.sum((u - torch.tensor(u_obs)) ** 2)
+
+
+def test_adjoint_matches_dense_autograd_32():
+    """32^2, leaf 8, eps 1e-6: the gradient of 0.5 |u - u_obs|^2 through the autograd solve
+    (factor + PCG forward, adjoint PCG + gradient kernel backward) equals dense torch
+    autograd of the same loss (CPU, FP64) to 1e-6 relative."""
+    torch = torch_cuda()
+    from paper_1808_01364_amd.adjoint import solve_log_a
+    s = 32
+    theta, a_true, f, u_true, rng = _inverse_problem(s, 8)
+    u_obs = u_true + 0.01 * np.sqrt(np.mean(u_true ** 2)) * rng.standard_normal(s * s)
+    th = to_dev(theta).reshape(theta.shape).requires_grad_(True)
+    u = solve_log_a(th, to_dev(f), 2, s, leaf=8, eps=1e-6)
+    loss = 0.5 * torch.sum((u - to_dev(u_obs)) ** 2)
+    loss.backward()
+    g = _host(th.grad)
+    th_c = torch.tensor(theta, requires_grad=True)
+    ref_loss = _dense_torch_loss(th_c, f, u_obs, s)
+    ref_loss.backward()
+    ref = th_c.grad.numpy()
+    print("loss", float(loss), float(ref_loss), "grad rel err", rel(g, ref), flush=True)
+    assert abs(float(loss) - float(ref_loss)) <= 1e-9 * abs(float(ref_loss))
+    assert rel(g, ref) < 1e-6
+
+
+def test_adjoint_matches_central_differences_256():
+    """256^2, leaf 16, eps 1e-6: dL/dtheta_c on 20 random cells against central differences
+    with step 1e-4. Each difference uses perturbation solves, so that no cancellation of
+    two full losses occurs: with r = u - u_obs and A(theta +- delta e_c) du = -(dA) u,
+    L(theta +- delta e_c) - L(theta) = <r, du> + 0.5 |du|^2."""
+    torch = torch_cuda()
+    from paper_1808_01364_amd import rhif
+    from paper_1808_01364_amd.adjoint import solve_log_a
+    s, leaf, eps = 256, 16, 1e-6
+    theta, a_true, f, _, rng = _inverse_problem(s, leaf)
+    fd_ = to_dev(f)
+    # u_obs: the solution for the second field plus 1 % noise
+    Ft = rhif.Factor(2, s, rhif.assemble_fd(2, s, to_dev(a_true)), leaf, eps, 1)
+    ut, _, _ = Ft.pcg(fd_, 1e-12, 500)
+    Ft.close()
+    ut = _host(ut)
+    u_obs = ut + 0.01 * np.sqrt(np.mean(ut ** 2)) * rng.standard_normal(s * s)
+    th = to_dev(theta).reshape(theta.shape).requires_grad_(True)
+    u = solve_log_a(th, fd_, 2, s, leaf=leaf, eps=eps)
+    uo = to_dev(u_obs)
+    loss = 0.5 * torch.sum((u - uo) ** 2)
+    loss.backward()
+    r = u.detach() - uo
+    g = _host(th.grad).ravel()
+    a0 = np.exp(theta)
+    csr0 = rhif.assemble_fd(2, s, to_dev(a0))
+    F0 = rhif.Factor(2, s, csr0, leaf, eps, 1)
+    Au0 = F0.matvec(u.detach())
+    F0.close()
+    cells = rng.choice((s + 1) ** 2, size=20, replace=False)
+    delta = 1e-4
+    fd = []
+    for c in cells:
+        dl = []
+        for sign in (1.0, -1.0):
+            th2 = theta.ravel().copy()
+            th2[c] += sign * delta
+            F = rhif.Factor(2, s, rhif.assemble_fd(2, s, to_dev(np.exp(th2))), leaf, eps, 1)
+            dA_u = F.matvec(u.detach()) - Au0
+            du, _, _ = F.pcg(-dA_u, 1e-12, 500)
+            F.close()
+            dl.append(float(torch.dot(r, du) + 0.5 * torch.dot(du, du)))
+        fd.append((dl[0] - dl[1]) / (2 * delta))
+    fd = np.array(fd)
+    err = np.linalg.norm(g[cells] - fd) / np.linalg.norm(fd)
+    print("fd rel err on 20 cells", err, flush=True)
+    assert err < 1e-6
