@@ -332,6 +332,19 @@ struct rhif_factor_s {
         size_t bytes;
     };
     std::vector<Chunk> chunks;   // device memory of the handle (from ChunkCache)
+    // the last work of the handle on every stream it was used on (its memory may be reused
+    // once these have completed)
+    std::vector<std::pair<hipStream_t, hipEvent_t>> done_ev;
+    void mark(hipStream_t st) {
+        hipEvent_t e = nullptr;
+        for (auto& p : done_ev)
+            if (p.first == st) e = p.second;
+        if (!e) {
+            HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            done_ev.emplace_back(st, e);
+        }
+        HIPCHK(hipEventRecord(e, st));
+    }
     char* chunk_cur = nullptr;
     size_t chunk_left = 0;
     int device = 0;
@@ -401,7 +414,11 @@ struct rhif_factor_s {
     }
     void release() {
         // the chunks go back to the cache only once no work of this handle can still use them
-        (void)hipDeviceSynchronize();
+        for (auto& p : done_ev) {
+            (void)hipEventSynchronize(p.second);
+            (void)hipEventDestroy(p.second);
+        }
+        done_ev.clear();
         for (int g = 0; g < 3; ++g) {
             if (gexec[g]) (void)hipGraphExecDestroy(gexec[g]);
             if (graph[g]) (void)hipGraphDestroy(graph[g]);
@@ -1299,6 +1316,7 @@ rhif_status rhif_factor(const rhif_grid* g, const rhif_opts* o, const int32_t* r
         if (f->L > RHIF_MAX_LEVELS) fail(RHIF_EINVAL, "too many levels");
         const auto t0 = std::chrono::steady_clock::now();
         do_factor(f, row_ptr, col, val, s);
+        f->mark(s);
         f->stats.t_total_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         *out = f;
@@ -1315,6 +1333,7 @@ rhif_status rhif_factor(const rhif_grid* g, const rhif_opts* o, const int32_t* r
     } catch (const std::bad_alloc&) {
         g_last_error = "host allocation failed";
         if (f) {
+            (void)hipStreamSynchronize(s);
             f->release();
             delete f;
         }
@@ -1322,6 +1341,7 @@ rhif_status rhif_factor(const rhif_grid* g, const rhif_opts* o, const int32_t* r
     } catch (const std::exception& e) {
         g_last_error = std::string("internal error: ") + e.what();
         if (f) {
+            (void)hipStreamSynchronize(s);
             f->release();
             delete f;
         }
@@ -1344,6 +1364,7 @@ rhif_status rhif_apply(rhif_factor_t f, const double* r, double* z, int32_t nrhs
         hipLaunchKernelGGL(rhif::k_copy, dim3(grid_for(N)), dim3(256), 0, s, N, f->z, zc);
     }
     HIPCHK(hipGetLastError());
+    f->mark(s);
     if (used && !f->gpend[0].empty()) {
         HIPCHK(hipStreamSynchronize(s));
         f->resolve_graph(0);
@@ -1373,6 +1394,7 @@ rhif_status rhif_matvec(rhif_factor_t f, const double* x, double* y, hipStream_t
     const int64_t N = f->g.N;
     hipLaunchKernelGGL(rhif::k_spmv_dot, dim3(grid_for(N)), dim3(256), 0, s, N, f->rp, f->ci, f->val, x, y, f->part);
     HIPCHK(hipGetLastError());
+    f->mark(s);
     API_END
 }
 
@@ -1462,6 +1484,7 @@ rhif_status rhif_pcg_solve(rhif_factor_t f, const double* rhs, double* u, double
 #undef VEC
     f->resolve();
     HIPCHK(hipGetLastError());
+    f->mark(s);
     if (iters) *iters = it;
     if (relres) *relres = rel;
     if (!conv) fail(RHIF_ENOCONV, "PCG did not reach the tolerance within maxit iterations");
