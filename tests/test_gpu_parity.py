@@ -103,6 +103,20 @@ def test_global_staging_parity(d, s, leaf, eps):
     print((d, s, leaf, eps), out)
 
 
+@pytest.mark.parametrize("d,s,leaf,eps,kind,precond,b", [
+    (2, 1, 8, 1e-6, "two_valued", 1, 0.0),     # one unknown: the root is the whole problem
+    (3, 1, 4, 1e-3, "two_valued", 1, 0.0),
+    (2, 2, 2, 1e-6, "two_valued", 1, 0.0),     # the smallest grid with a level
+    (2, 24, 4, 1e-6, "lognormal", 1, 1.0),     # reaction term b > 0
+    (3, 9, 2, 1e-3, "two_valued", 0, 0.0),     # HIF (no block Jacobi) in 3D
+    (2, 33, 4, 1e-6, "paper", 1, 0.0),         # the paper's quantized field, ragged side
+])
+def test_edge_cases(d, s, leaf, eps, kind, precond, b):
+    P, A = problem(kind, d, s, leaf, eps, seed=8, precond=precond, sigma=2.0, lo=1e-2, hi=1e2, b_const=b)
+    out = _parity(P, A)
+    print((d, s, leaf, eps, kind, precond, b), out)
+
+
 def test_not_spd_is_reported():
     """A strongly negative reaction term: the device Cholesky of the first cells fails and
     the library reports loss of positive definiteness at level 0, step E."""
