@@ -1895,6 +1895,86 @@ __device__ __forceinline__ void wg_trsv_bwd(const double* __restrict__ L, int ld
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Triangular solves of the apply for banded leaf cells, whose L (from k_leaf_elim) is block
+// bidiagonal in 16 x 16 blocks: in steps of 16 rows,
+//   up   (L z = b):   z_J = Li_J (b_J - L_J,J-1 z_J-1),            J = 0, 1, ...
+//   down (L^T z = b): z_J = Li_J^T (b_J - L_J+1,J^T z_J+1),        J = nb-1, ..., 0
+// with the stored inverses Li_J of the diagonal blocks. Each step's two 16 x 16 blocks are
+// streamed kBandDepth steps ahead by all threads (one element of each per thread) and
+// staged in LDS, so that the chain of steps waits on LDS rather than on memory.
+// ---------------------------------------------------------------------------------------
+constexpr int kBandDepth = 4;
+
+template <bool UP>
+__global__ __launch_bounds__(256) void k_apply_band(const ApplyDesc* __restrict__ ad, const double* __restrict__ pool,
+                                                    const double* __restrict__ lip, const int32_t* __restrict__ dofs,
+                                                    double* __restrict__ z) {
+    extern __shared__ double smem[];
+    constexpr int TS = 16 * 17;
+    const ApplyDesc d = ad[blockIdx.x];
+    const int nI = d.nI, nb = (nI + 15) / 16, ld = d.ld;
+    const double* A = pool + d.off;
+    const double* li = lip + d.li;
+    const int tid = threadIdx.x, er = tid >> 4, ec = tid & 15;
+    double* zI = smem;               // 16 nb
+    double* Lt = zI + 16 * nb;       // the step's off-diagonal block, [row][col]
+    double* Lit = Lt + TS;           // the step's diagonal-block inverse, [row][col]
+    double* yv = Lit + TS;           // 16
+    const int32_t* di = dofs + d.dofs;
+    for (int i = tid; i < 16 * nb; i += kWG) zI[i] = i < nI ? z[di[i]] : 0.0;
+    // operands of step q: UP L_J,J-1 (rows 16J.., cols 16J-16..), DOWN L_J+1,J; and Li_J
+    auto blk = [&](int q, double& lv, double& liv) {
+        lv = 0.0;
+        liv = 0.0;
+        if (q >= nb) return;
+        const int J = UP ? q : nb - 1 - q, j0 = 16 * J;
+        if (UP) {
+            if (J > 0 && j0 + er < nI) lv = A[(j0 + er) + static_cast<size_t>(j0 - 16 + ec) * ld];
+        } else {
+            if (j0 + 16 + er < nI) lv = A[(j0 + 16 + er) + static_cast<size_t>(j0 + ec) * ld];
+        }
+        liv = li[J * 256 + tid];
+    };
+    double lr[kBandDepth], lir[kBandDepth];
+#pragma unroll
+    for (int sl = 0; sl < kBandDepth; ++sl) blk(sl, lr[sl], lir[sl]);
+    for (int q0 = 0; q0 < nb; q0 += kBandDepth) {
+#pragma unroll
+        for (int sl = 0; sl < kBandDepth; ++sl) {
+            const int q = q0 + sl;
+            if (q >= nb) break;
+            Lt[er * 17 + ec] = lr[sl];
+            Lit[er * 17 + ec] = lir[sl];
+            blk(q + kBandDepth, lr[sl], lir[sl]);
+            __syncthreads();
+            if (tid < 16) {
+                const int i = tid;
+                const int J = UP ? q : nb - 1 - q, j0 = 16 * J;
+                double acc = zI[j0 + i];
+                if (UP && J > 0) {
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) acc -= Lt[i * 17 + c] * zI[j0 - 16 + c];
+                } else if (!UP && J + 1 < nb) {
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) acc -= Lt[c * 17 + i] * zI[j0 + 16 + c];
+                }
+                yv[i] = acc;
+                __builtin_amdgcn_wave_barrier();
+                double v = 0.0;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) v += (UP ? Lit[i * 17 + k] : Lit[k * 17 + i]) * yv[k];
+                zI[j0 + i] = v;
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < nI; i += kWG) z[di[i]] = zI[i];
+}
+
+template __global__ void k_apply_band<true>(const ApplyDesc*, const double*, const double*, const int32_t*, double*);
+template __global__ void k_apply_band<false>(const ApplyDesc*, const double*, const double*, const int32_t*, double*);
+
 // Up-sweep solve: [z_I -= T^T z_B]; z_I <- L^-1 z_I.
 __global__ __launch_bounds__(256) void k_apply_trsv_up(const ApplyDesc* __restrict__ ad, const double* __restrict__ pool,
                                                        const double* __restrict__ lip, const double* __restrict__ Tp,

@@ -41,6 +41,9 @@ __global__ void k_apply_trsv_up(const ApplyDesc* ad, const double* pool, const d
                                 const int32_t* dofs, double* z, const int32_t* extp);
 __global__ void k_apply_trsv_dn(const ApplyDesc* ad, const double* pool, const double* lip, const double* Tp,
                                 const int32_t* dofs, double* z, const int32_t* extp);
+template <bool UP>
+__global__ void k_apply_band(const ApplyDesc* ad, const double* pool, const double* lip, const int32_t* dofs,
+                             double* z);
 __global__ void k_apply_gemv_up(const ApplyDesc* ad, const double* pool, const int32_t* dofs, double* z,
                                 double* ybuf);
 __global__ void k_apply_gemv_dn(const ApplyDesc* ad, const double* pool, const int32_t* dofs, double* z);

@@ -131,6 +131,7 @@ struct Packer {
 struct LevelDev {
     bool root = false;
     bool exact = false;     // a leaf sublevel: elimination only
+    bool leaf_banded = false;   // cells factored by k_leaf_elim (block-bidiagonal L)
     bool precond = false;   // block Jacobi applied at this level
     double* front = nullptr;
     double* lg = nullptr;
@@ -684,6 +685,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             // the frontal tiles of such cells skip what the banded elimination never reads
             if (leaf_interior_banded(d, lvl, root, P.w)) {
                 // leaf interiors: block-bidiagonal Cholesky factors
+                LD.leaf_banded = true;
                 const int nt = (mmax + 15) / 16;
                 const int tpw = (nt + 3) / 4;
                 const size_t lds0 =
@@ -1055,17 +1057,27 @@ size_t group_lds(const LevelDev& LD) {
     return static_cast<size_t>(2 * 16 * ((LD.mn_grp + 15) / 16)) * sizeof(double);
 }
 
+// LDS of k_apply_band for interiors of up to mi unknowns.
+size_t band_lds(int mi) {
+    return static_cast<size_t>(16 * ((mi + 15) / 16) + 2 * 16 * 17 + 16) * sizeof(double);
+}
+
 void apply_up_block(rhif_factor_s* f, double by, const rhif::ApplyDesc* ad, int n, int mi, int mb, size_t lds,
                     const double* pool, const double* lip, const double* tp, const int32_t* dofs, double* z,
-                    double* ybuf, hipStream_t s, const int32_t* ext = nullptr) {
+                    double* ybuf, hipStream_t s, const int32_t* ext = nullptr, bool band = false) {
     if (n <= 0) return;
     if (!split_ok(mi, mb, lip)) {
         launch_up(f, by, ad, n, lds, pool, tp, dofs, z, ybuf, f->ws, s, ext);
         return;
     }
-    KTIMED(f, s, RHIF_K_APPLY_UP, 0.0, by,
-           hipLaunchKernelGGL(rhif::k_apply_trsv_up, dim3(n), dim3(256), trsv_lds(mi, mb), s, ad, pool, lip, tp, dofs,
-                              z, ext));
+    if (band)
+        KTIMED(f, s, RHIF_K_APPLY_UP, 0.0, by,
+               hipLaunchKernelGGL(rhif::k_apply_band<true>, dim3(n), dim3(256), band_lds(mi), s, ad, pool, lip, dofs,
+                                  z));
+    else
+        KTIMED(f, s, RHIF_K_APPLY_UP, 0.0, by,
+               hipLaunchKernelGGL(rhif::k_apply_trsv_up, dim3(n), dim3(256), trsv_lds(mi, mb), s, ad, pool, lip, tp,
+                                  dofs, z, ext));
     if (mb > 0)
         KTIMED(f, s, RHIF_K_APPLY_UP, 0.0, 0.0,
                hipLaunchKernelGGL(rhif::k_apply_gemv_up, dim3(n, (mb + 63) / 64), dim3(256),
@@ -1074,7 +1086,7 @@ void apply_up_block(rhif_factor_s* f, double by, const rhif::ApplyDesc* ad, int 
 
 void apply_down_block(rhif_factor_s* f, double by, const rhif::ApplyDesc* ad, int n, int mi, int mb, size_t lds,
                       const double* pool, const double* lip, const double* tp, const int32_t* dofs, double* z,
-                      hipStream_t s, const int32_t* ext = nullptr) {
+                      hipStream_t s, const int32_t* ext = nullptr, bool band = false) {
     if (n <= 0) return;
     if (!split_ok(mi, mb, lip)) {
         launch_down(f, by, ad, n, lds, pool, tp, dofs, z, f->ws, s, ext);
@@ -1084,9 +1096,14 @@ void apply_down_block(rhif_factor_s* f, double by, const rhif::ApplyDesc* ad, in
         KTIMED(f, s, RHIF_K_APPLY_DOWN, 0.0, by,
                hipLaunchKernelGGL(rhif::k_apply_gemv_dn, dim3(n, (mi + 63) / 64), dim3(256),
                                   static_cast<size_t>(64 * 65 + mb + 256) * sizeof(double), s, ad, pool, dofs, z));
-    KTIMED(f, s, RHIF_K_APPLY_DOWN, 0.0, mb > 0 ? 0.0 : by,
-           hipLaunchKernelGGL(rhif::k_apply_trsv_dn, dim3(n), dim3(256), trsv_lds(mi, mb), s, ad, pool, lip, tp, dofs,
-                              z, ext));
+    if (band)
+        KTIMED(f, s, RHIF_K_APPLY_DOWN, 0.0, mb > 0 ? 0.0 : by,
+               hipLaunchKernelGGL(rhif::k_apply_band<false>, dim3(n), dim3(256), band_lds(mi), s, ad, pool, lip, dofs,
+                                  z));
+    else
+        KTIMED(f, s, RHIF_K_APPLY_DOWN, 0.0, mb > 0 ? 0.0 : by,
+               hipLaunchKernelGGL(rhif::k_apply_trsv_dn, dim3(n), dim3(256), trsv_lds(mi, mb), s, ad, pool, lip, tp,
+                                  dofs, z, ext));
 }
 
 void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
@@ -1094,7 +1111,7 @@ void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
     for (int lvl = 0; lvl < L; ++lvl) {
         LevelDev& LD = f->lev[lvl];
         apply_up_block(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.mi_cell, LD.mb_cell, LD.lds_cell, LD.front, LD.linv,
-                       nullptr, LD.cdofs, z, f->ybuf, s, LD.ext);
+                       nullptr, LD.cdofs, z, f->ybuf, s, LD.ext, LD.leaf_banded);
         if (group_ok(LD)) {
             KTIMED(f, s, RHIF_K_APPLY_GATHER, 0.0, LD.b_gather + LD.b_sep + LD.b_skel,
                    hipLaunchKernelGGL(rhif::k_apply_group_up, dim3(LD.n_grp), dim3(256), group_lds(LD), s, LD.grp_ad,
@@ -1132,7 +1149,7 @@ void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
                                  LD.sepdofs, z, s);
         }
         apply_down_block(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.mi_cell, LD.mb_cell, LD.lds_cell, LD.front,
-                         LD.linv, nullptr, LD.cdofs, z, s, LD.ext);
+                         LD.linv, nullptr, LD.cdofs, z, s, LD.ext, LD.leaf_banded);
     }
 }
 
