@@ -13,6 +13,7 @@
 
 #include "devstructs.hpp"
 #include "kernels.hpp"
+#include "leafgeom.hpp"
 
 namespace rhif {
 
@@ -590,6 +591,18 @@ __global__ __launch_bounds__(256) void k_assemble_fd(int d, int s, double inv_h2
                 ++e;
             }
     }
+}
+
+// ---------------------------------------------------------------------------------------
+// Level-0 frontal unknowns: position p of cell c gets its grid index from the closed form
+// leaf_frontal_dof (interior box, then the boundary boxes by slot code), one thread per
+// position.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_leaf_dofs(const CellRef* __restrict__ cells, int d, int s, int w, int nc1,
+                                                   int32_t* __restrict__ cdofs) {
+    const CellRef cr = cells[blockIdx.x];
+    for (int p = threadIdx.x; p < cr.nf; p += kWG)
+        cdofs[cr.dptr + p] = leaf_frontal_dof(d, s, w, nc1, static_cast<int>(blockIdx.x), p);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -12,6 +12,7 @@ __global__ void k_assemble_fd(int d, int s, double inv_h2, const double* a, cons
                               const int32_t* row_ptr, int32_t* col, double* val);
 __global__ void k_grad_log_a(int d, int s, double inv_h2, const double* a, const double* u, const double* lam,
                              double* g);
+__global__ void k_leaf_dofs(const CellRef* cells, int d, int s, int w, int nc1, int32_t* cdofs);
 __global__ void k_front_csr(const Tile* tiles, const CellRef* cells, const int32_t* cdofs, int d, int s, int w,
                             int nc1, const int32_t* row_ptr, const int32_t* col, const double* val, double* F);
 __global__ void k_front_extend(const Tile* tiles, const CellRef* cells, const int32_t* src, int W,

@@ -41,6 +41,7 @@ void LevelPlan::reset() {
     ext_elems = 0;
     level = w = nc1 = 0;
     root = false;
+    dofs_on_device = lists_pending = false;
     for (auto* v : {&gptr, &gdofs, &gslot_cnt, &gslot_cell, &gslot_off, &c_nI, &c_nB, &c_nf, &c_ld, &c_dptr,
                     &c_dofs, &c_gptr, &c_g, &c_goff, &seps, &skels, &src, &sep_dofs, &sep_sorted, &sep_g, &sep_t,
                     &g_g2, &g_t2, &c_g2, &c_t2})
@@ -83,8 +84,59 @@ void build_level(const GridInfo& gi, int level, int leaf, bool root, const std::
     if (!root) build_separators(gi, scr, lds_apply_cap, P);
 }
 
+void fill_leaf_lists(const GridInfo& gi, PlanScratch& scr, LevelPlan& P) {
+    const int d = gi.d, s = gi.s;
+    const int64_t w = P.w;
+    const int KB = 2 * P.nc1 + 2;
+    const int ngroups = static_cast<int>(P.gptr.size()) - 1;
+    const int64_t s2 = static_cast<int64_t>(s) * s;
+    P.gdofs.resize(gi.N);
+    // every group's box in ascending order
+    for (int g = 0; g < ngroups; ++g) {
+        const int* lo = scr.box_lo.data() + 3 * g;
+        const int* nb = scr.box_n.data() + 3 * g;
+        int32_t* out = P.gdofs.data() + P.gptr[g];
+        for (int x2 = lo[2]; x2 < lo[2] + nb[2]; ++x2)
+            for (int x1 = lo[1]; x1 < lo[1] + nb[1]; ++x1) {
+                const int64_t base = (d > 2 ? (x2 - 1) * s2 : 0) + (d > 1 ? static_cast<int64_t>(x1 - 1) * s : 0);
+                for (int x0 = lo[0]; x0 < lo[0] + nb[0]; ++x0) *out++ = static_cast<int32_t>(base + x0 - 1);
+            }
+        if (out != P.gdofs.data() + P.gptr[g + 1]) throw std::logic_error("leaf group box size");
+    }
+    // separator unknowns (some coordinate on a cell boundary), ascending, with their group
+    // and position in it
+    P.sep_sorted.clear();
+    P.sep_g.clear();
+    P.sep_t.clear();
+    const int n2 = d > 2 ? s : 1, n1 = d > 1 ? s : 1;
+    std::vector<int32_t> keyk(static_cast<size_t>(s) + 1);
+    for (int xk = 1; xk <= s; ++xk) keyk[xk] = 2 * (xk / static_cast<int>(w)) + ((xk % w) != 0 ? 1 : 0);
+    auto put = [&](int64_t base, int x0, int x1, int x2) {
+        const int64_t K = keyk[x0] + (d > 1 ? static_cast<int64_t>(keyk[x1]) * KB : 0) +
+                          (d > 2 ? static_cast<int64_t>(keyk[x2]) * KB * KB : 0);
+        const int g = scr.key2g[K];
+        const int* lo = scr.box_lo.data() + 3 * g;
+        const int* nb = scr.box_n.data() + 3 * g;
+        const int t = (x0 - lo[0]) + nb[0] * ((d > 1 ? x1 - lo[1] : 0) + nb[1] * (d > 2 ? x2 - lo[2] : 0));
+        P.sep_sorted.push_back(static_cast<int32_t>(base + x0 - 1));
+        P.sep_g.push_back(g);
+        P.sep_t.push_back(t);
+    };
+    for (int x2 = 1; x2 <= n2; ++x2)
+        for (int x1 = 1; x1 <= n1; ++x1) {
+            const int64_t base = (d > 2 ? (x2 - 1) * s2 : 0) + (d > 1 ? static_cast<int64_t>(x1 - 1) * s : 0);
+            const bool line = (d > 1 && x1 % w == 0) || (d > 2 && x2 % w == 0);
+            if (line) {
+                for (int x0 = 1; x0 <= s; ++x0) put(base, x0, x1, x2);
+            } else {
+                for (int64_t x0 = w; x0 <= s; x0 += w) put(base, static_cast<int>(x0), x1, x2);
+            }
+        }
+    P.lists_pending = false;
+}
+
 void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::vector<int32_t>& active,
-                 const LevelPlan* prev, PlanScratch& scr, int lds_apply_cap, LevelPlan& P) {
+                 const LevelPlan* prev, PlanScratch& scr, int lds_apply_cap, LevelPlan& P, bool dofs_on_device) {
     const int d = gi.d, s = gi.s;
     P.reset();
     P.level = level;
@@ -106,13 +158,11 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
     if (na > 0 && static_cast<int64_t>(na) == gi.N) {
         // Every unknown is active (the leaf level): the groups are boxes of the grid,
         // enumerated directly in key order, each in ascending order.
-        P.gdofs.resize(na);
         P.gptr.clear();
         P.gcls.clear();
         scr.box_lo.clear();
         scr.box_n.clear();
         size_t at = 0;
-        const int64_t s2 = static_cast<int64_t>(s) * s;
         for (int64_t K = 0; K < nkeys; ++K) {
             int lo[3] = {1, 1, 1}, hi[3] = {1, 1, 1};
             int64_t r = K;
@@ -136,44 +186,21 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
             scr.key2g[K] = ngroups++;
             P.gptr.push_back(static_cast<int32_t>(at));
             P.gcls.push_back(static_cast<int8_t>(even));
+            int64_t cnt = 1;
             for (int k = 0; k < 3; ++k) {
                 scr.box_lo.push_back(lo[k]);
                 scr.box_n.push_back(hi[k] - lo[k] + 1);
+                cnt *= hi[k] - lo[k] + 1;
             }
-            for (int x2 = lo[2]; x2 <= hi[2]; ++x2)
-                for (int x1 = lo[1]; x1 <= hi[1]; ++x1) {
-                    const int64_t base = (d > 2 ? (x2 - 1) * s2 : 0) + (d > 1 ? static_cast<int64_t>(x1 - 1) * s : 0);
-                    for (int x0 = lo[0]; x0 <= hi[0]; ++x0) P.gdofs[at++] = static_cast<int32_t>(base + x0 - 1);
-                }
+            at += static_cast<size_t>(cnt);
         }
         if (at != na) throw std::logic_error("leaf-level groups do not cover the grid");
         P.gptr.push_back(static_cast<int32_t>(na));
-        // separator unknowns (some coordinate on a cell boundary), ascending, with their
-        // group and position in it
-        const int n2 = d > 2 ? s : 1, n1 = d > 1 ? s : 1;
-        std::vector<int32_t> keyk(static_cast<size_t>(s) + 1);
-        for (int xk = 1; xk <= s; ++xk) keyk[xk] = 2 * (xk / static_cast<int>(w)) + ((xk % w) != 0 ? 1 : 0);
-        auto put = [&](int64_t base, int x0, int x1, int x2) {
-            const int64_t K = keyk[x0] + (d > 1 ? static_cast<int64_t>(keyk[x1]) * KB : 0) +
-                              (d > 2 ? static_cast<int64_t>(keyk[x2]) * KB * KB : 0);
-            const int g = scr.key2g[K];
-            const int* lo = scr.box_lo.data() + 3 * g;
-            const int* nb = scr.box_n.data() + 3 * g;
-            const int t = (x0 - lo[0]) + nb[0] * ((d > 1 ? x1 - lo[1] : 0) + nb[1] * (d > 2 ? x2 - lo[2] : 0));
-            P.sep_sorted.push_back(static_cast<int32_t>(base + x0 - 1));
-            P.sep_g.push_back(g);
-            P.sep_t.push_back(t);
-        };
-        for (int x2 = 1; x2 <= n2; ++x2)
-            for (int x1 = 1; x1 <= n1; ++x1) {
-                const int64_t base = (d > 2 ? (x2 - 1) * s2 : 0) + (d > 1 ? static_cast<int64_t>(x1 - 1) * s : 0);
-                const bool line = (d > 1 && x1 % w == 0) || (d > 2 && x2 % w == 0);
-                if (line) {
-                    for (int x0 = 1; x0 <= s; ++x0) put(base, x0, x1, x2);
-                } else {
-                    for (int64_t x0 = w; x0 <= s; x0 += w) put(base, static_cast<int>(x0), x1, x2);
-                }
-            }
+        // the groups' unknowns and the separator lists now, or later (fill_leaf_lists) when
+        // the device writes the cells' frontal unknowns itself
+        P.dofs_on_device = dofs_on_device;
+        P.lists_pending = true;
+        if (!dofs_on_device) fill_leaf_lists(gi, scr, P);
     } else {
         std::vector<int32_t>& akey = scr.akey;
         akey.resize(na);
@@ -270,7 +297,8 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
     P.gslot_cnt.assign(ngroups, 0);
     P.gslot_cell.assign(static_cast<size_t>(ngroups) * kMaxSlots, -1);
     P.gslot_off.assign(static_cast<size_t>(ngroups) * kMaxSlots, -1);
-    P.c_dofs.reserve(na + na / 2);
+    if (!P.dofs_on_device) P.c_dofs.reserve(na + na / 2);
+    int32_t ndofs = 0;
     int n3 = 1;
     for (int k = 0; k < d; ++k) n3 *= 3;
     int64_t foff = 0;
@@ -281,7 +309,7 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
             c[k] = static_cast<int>(r % nc1);
             r /= nc1;
         }
-        P.c_dptr[ci] = static_cast<int32_t>(P.c_dofs.size());
+        P.c_dptr[ci] = ndofs;
         // interior group
         int64_t KI = 0, mul = 1;
         for (int k = 0; k < d; ++k) {
@@ -292,7 +320,8 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
         int nI = 0;
         if (gI >= 0) {
             nI = P.gptr[gI + 1] - P.gptr[gI];
-            P.c_dofs.insert(P.c_dofs.end(), P.gdofs.begin() + P.gptr[gI], P.gdofs.begin() + P.gptr[gI + 1]);
+            if (!P.dofs_on_device)
+                P.c_dofs.insert(P.c_dofs.end(), P.gdofs.begin() + P.gptr[gI], P.gdofs.begin() + P.gptr[gI + 1]);
             if (prev != nullptr) {
                 P.c_g2.insert(P.c_g2.end(), P.g_g2.begin() + P.gptr[gI], P.g_g2.begin() + P.gptr[gI + 1]);
                 P.c_t2.insert(P.c_t2.end(), P.g_t2.begin() + P.gptr[gI], P.g_t2.begin() + P.gptr[gI + 1]);
@@ -320,7 +349,8 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
             if (sl >= kMaxSlots) throw std::logic_error("group in too many cells");
             P.gslot_cell[static_cast<size_t>(g) * kMaxSlots + sl] = static_cast<int32_t>(ci);
             P.gslot_off[static_cast<size_t>(g) * kMaxSlots + sl] = nf;
-            P.c_dofs.insert(P.c_dofs.end(), P.gdofs.begin() + P.gptr[g], P.gdofs.begin() + P.gptr[g + 1]);
+            if (!P.dofs_on_device)
+                P.c_dofs.insert(P.c_dofs.end(), P.gdofs.begin() + P.gptr[g], P.gdofs.begin() + P.gptr[g + 1]);
             if (prev != nullptr) {
                 P.c_g2.insert(P.c_g2.end(), P.g_g2.begin() + P.gptr[g], P.g_g2.begin() + P.gptr[g + 1]);
                 P.c_t2.insert(P.c_t2.end(), P.g_t2.begin() + P.gptr[g], P.g_t2.begin() + P.gptr[g + 1]);
@@ -328,6 +358,7 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
             nf += ng;
         }
         P.c_gptr[ci + 1] = static_cast<int32_t>(P.c_g.size());
+        ndofs += nf;
         P.c_nI[ci] = nI;
         P.c_nB[ci] = nf - nI;
         P.c_nf[ci] = nf;
@@ -336,7 +367,9 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
         foff += align_up(static_cast<int64_t>(P.c_ld[ci]) * nf, 32);
         P.max_nf = std::max(P.max_nf, nf);
     }
-    P.c_dptr[ncells] = static_cast<int32_t>(P.c_dofs.size());
+    P.c_dptr[ncells] = ndofs;
+    if (!P.dofs_on_device && static_cast<int64_t>(P.c_dofs.size()) != ndofs)
+        throw std::logic_error("cell dof bookkeeping");
     P.front_elems = std::max<int64_t>(foff, 32);
 
     // ---- batched descriptors of the cells ----
@@ -474,6 +507,7 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
 }
 
 void build_separators(const GridInfo& gi, PlanScratch& scr, int lds_apply_cap, LevelPlan& P) {
+    if (P.lists_pending) throw std::logic_error("leaf groups without their unknowns");
     (void)gi;
     const int ngroups = static_cast<int>(P.gptr.size()) - 1;
     const int64_t ncells = P.ncells;
@@ -635,6 +669,7 @@ void finish_level(const LevelPlan& P, const int32_t* k, const int32_t* perm, int
                   int64_t& ws_elems, const std::vector<int32_t>& active,
                   std::vector<int32_t>& next_active, PlanScratch& scr, double& skel_flops,
                   double& skel_apply_bytes) {
+    if (P.lists_pending) throw std::logic_error("leaf groups without their unknowns");
     skel_flops = 0.0;
     skel_apply_bytes = 0.0;
     skel_apply.clear();
@@ -722,7 +757,9 @@ void validate_cells(const LevelPlan& P, const LevelPlan* prev, int d) {
         }
         need(at == P.c_nf[c], "cell groups cover the frontal", at, P.c_nf[c]);
     }
-    const int64_t ncd = static_cast<int64_t>(P.c_dofs.size());
+    need(static_cast<int64_t>(P.c_dptr.size()) == P.ncells + 1, "cell dof offsets");
+    const int64_t ncd = P.c_dptr[P.ncells];
+    need(P.dofs_on_device || static_cast<int64_t>(P.c_dofs.size()) == ncd, "cell dofs", P.c_dofs.size(), ncd);
     for (int c = 0; c < P.ncells; ++c) {
         const CellRef& r = P.cell_ref[c];
         need(r.nf == P.c_nI[c] + P.c_nB[c], "cell nf");

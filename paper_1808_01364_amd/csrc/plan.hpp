@@ -26,6 +26,11 @@ struct LevelPlan {
     int w = 0;
     int nc1 = 0;        // cells per axis
     bool root = false;  // the last level: one cell, everything interior
+    // level 0 only: the cells' frontal unknowns (c_dofs) are written by the device from the
+    // closed form of leafgeom.hpp (c_dofs stays empty; c_dptr holds the offsets), and the
+    // groups' unknowns and separator lists wait for fill_leaf_lists
+    bool dofs_on_device = false;
+    bool lists_pending = false;
 
     // groups (ascending key), their unknowns ascending
     std::vector<int32_t> gptr;      // ngroups + 1
@@ -132,8 +137,13 @@ int inner_leaf(int d, int leaf);
 // The work is split in two halves so that the second can overlap device work:
 //   build_cells: groups, cell frontals, assembly tiles, elimination and cell apply tables;
 //   build_separators: block-Jacobi, ID / skeleton and gather tables (not at the root).
+// dofs_on_device (used at level 0 only, where every unknown is active): leave c_dofs to the
+// device and defer gdofs and the separator lists to fill_leaf_lists, which must run before
+// build_separators; the cell tables are complete without them.
 void build_cells(const GridInfo& g, int level, int leaf, bool root, const std::vector<int32_t>& active,
-                 const LevelPlan* prev, PlanScratch& scr, int lds_apply_cap, LevelPlan& out);
+                 const LevelPlan* prev, PlanScratch& scr, int lds_apply_cap, LevelPlan& out,
+                 bool dofs_on_device = false);
+void fill_leaf_lists(const GridInfo& g, PlanScratch& scr, LevelPlan& out);
 void build_separators(const GridInfo& g, PlanScratch& scr, int lds_apply_cap, LevelPlan& out);
 // Both halves.
 void build_level(const GridInfo& g, int level, int leaf, bool root,

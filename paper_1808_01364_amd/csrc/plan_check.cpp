@@ -4,6 +4,7 @@
 #include <vector>
 
 #include "../../include/rhif_plan.h"
+#include "leafgeom.hpp"
 #include "plan.hpp"
 
 namespace {
@@ -38,6 +39,16 @@ extern "C" rhif_status rhif_plan_dry_run(const rhif_grid* g, int32_t leaf, rhif_
             LevelPlan& P = plans[lvl];
             build_level(gi, lvl, leaf, root, active, lvl ? &plans[lvl - 1] : nullptr, scr, 7000, P);
             validate_level(P, lvl ? &plans[lvl - 1] : nullptr, gi.d);
+            if (lvl == 0) {
+                // the closed form the device uses for the leaf cells' frontal unknowns
+                for (int c = 0; c < P.ncells; ++c) {
+                    for (int q = 0; q < P.c_nf[c]; ++q)
+                        if (leaf_frontal_dof(gi.d, gi.s, P.w, P.nc1, c, q) != P.c_dofs[P.c_dptr[c] + q])
+                            throw std::logic_error("closed-form leaf frontal unknowns differ from the plan");
+                    if (leaf_frontal_dof(gi.d, gi.s, P.w, P.nc1, c, P.c_nf[c]) != -1)
+                        throw std::logic_error("closed-form leaf frontal is larger than the plan's");
+                }
+            }
             if (cell)
                 for (int c = 0; c < P.ncells; ++c)
                     if (P.c_nI[c] > 0)

@@ -621,7 +621,9 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
 
         // ---- plan and upload the cell half ----
         auto t0 = now();
-        build_cells(g, lvl, leaf, root, active, prevP, scr, kApplyCap, P);
+        // level 0: the device writes the cells' frontal unknowns from their closed form, and
+        // the host fills the groups' lists while the first kernels run
+        build_cells(g, lvl, leaf, root, active, prevP, scr, kApplyCap, P, lvl == 0);
         validate_cells(P, prevP, d);
         if (P.max_nf > 16 * kPotrfMaxTiles) fail(RHIF_ENOMEM, "a frontal matrix is too large for this version");
         f->stats.n_active[lvl] = static_cast<int64_t>(active.size());
@@ -632,7 +634,9 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             const size_t o_cdofs = pk.add(P.c_dofs), o_cref = pk.add(P.cell_ref), o_potrf = pk.add(P.cell_potrf),
                          o_tiles = pk.add(P.tiles), o_src = pk.add(P.src), o_cad = pk.add(P.cell_apply);
             char* T = upload(f, pk, s);
-            LD.cdofs = view<int32_t>(T, o_cdofs);
+            LD.cdofs = P.dofs_on_device
+                           ? static_cast<int32_t*>(f->dalloc(std::max<int64_t>(P.c_dptr[P.ncells], 1) * sizeof(int32_t)))
+                           : view<int32_t>(T, o_cdofs);
             LD.cref = view<CellRef>(T, o_cref);
             LD.potrf = view<FrontDesc>(T, o_potrf);
             LD.tiles = view<Tile>(T, o_tiles);
@@ -652,6 +656,10 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
 
         // ---- frontal assembly ----
         t0 = now();
+        if (P.dofs_on_device && P.ncells > 0)
+            KTIMED(f, s, RHIF_K_FRONT_CSR, 0.0, 4.0 * P.c_dptr[P.ncells],
+                   hipLaunchKernelGGL(k_leaf_dofs, dim3(P.ncells), dim3(256), 0, s, LD.cref, d, g.s, P.w, P.nc1,
+                                      LD.cdofs));
         if (!P.tiles.empty()) {
             if (lvl == 0) {
                 const double by = P.alg_front_bytes + 12.0 * f->nnz + 4.0 * (g.N + 1);
@@ -769,6 +777,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             }
         }
         phase(root ? 6 : 1, t0);
+        if (P.lists_pending) fill_leaf_lists(g, scr, P);
         if (root) {
             f->stats.flops[lvl] += P.flops;
             break;

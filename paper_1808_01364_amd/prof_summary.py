@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hip")
 
 # kernel-class name used by bench.py -> the device kernels launched under it
-CLASS_KERNEL = {"front_csr": ("k_front_csr",), "front_extend": ("k_front_extend",),
+CLASS_KERNEL = {"front_csr": ("k_front_csr", "k_leaf_dofs"), "front_extend": ("k_front_extend",),
                 "elim_leaf": ("k_leaf_elim", "k_potrf_batch"),
                 "elim_upper": ("k_chol_lead", "k_trsm_rows", "k_syrk_schur", "k_potrf_batch"),
                 "root": ("k_potrf_batch",), "precond_chol": ("k_precond_groups",),
