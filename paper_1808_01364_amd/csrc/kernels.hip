@@ -750,6 +750,67 @@ __global__ __launch_bounds__(256) void k_front_extend(const Tile* __restrict__ t
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Extend-add source table of a level >= 1 (read by k_front_extend): for frontal position p of
+// cell c, the children of c whose closures hold the unknown (the cells of the level below
+// that contain its group g2 there, in slot order) and the unknown's position t2 + the
+// group's offset in each child's frontal; unused pairs are -1. One thread per position.
+// Entries that contradict the plan (group out of range, no child or more than W, a position
+// outside the child's boundary block) are reported as step 6 and left at -1.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_extend_src(const CellRef* __restrict__ cells, const int32_t* __restrict__ g2,
+                                                    const int32_t* __restrict__ t2, int ngroups2,
+                                                    const int32_t* __restrict__ gslot_cnt,
+                                                    const int32_t* __restrict__ gslot_cell,
+                                                    const int32_t* __restrict__ gslot_off,
+                                                    const CellRef* __restrict__ child, int nchild, int d, int pnc1,
+                                                    int nc1, int W, int level, int32_t* __restrict__ src,
+                                                    unsigned long long* err) {
+    const int c = blockIdx.x;
+    const CellRef cr = cells[c];
+    for (int p = threadIdx.x; p < cr.nf; p += kWG) {
+        const int64_t e = static_cast<int64_t>(cr.dptr) + p;
+        int32_t* o = src + e * 2 * W;
+        for (int q = 0; q < 2 * W; ++q) o[q] = -1;
+        const int g = g2[e], t = t2[e];
+        if (g < 0 || g >= ngroups2) {
+            report(err, err_code(level, 6, c));
+            continue;
+        }
+        const int nsl = min(gslot_cnt[g], kMaxSlots);
+        int nq = 0;
+        bool ok = true;
+        for (int sl = 0; sl < nsl; ++sl) {
+            const int cc = gslot_cell[g * kMaxSlots + sl];
+            if (cc < 0 || cc >= nchild) {
+                ok = false;
+                break;
+            }
+            // parent of child cc: its coordinates halved
+            int rr = cc, par = 0, mul = 1;
+            for (int k = 0; k < d; ++k) {
+                par += ((rr % pnc1) >> 1) * mul;
+                rr /= pnc1;
+                mul *= nc1;
+            }
+            if (par != c) continue;
+            const int pos = gslot_off[g * kMaxSlots + sl] + t;
+            const CellRef ch = child[cc];
+            if (nq >= W || pos < ch.nI || pos >= ch.nf) {
+                ok = false;
+                break;
+            }
+            o[2 * nq] = cc;
+            o[2 * nq + 1] = pos;
+            ++nq;
+        }
+        if (!ok || nq == 0) {
+            for (int q = 0; q < 2 * W; ++q) o[q] = -1;
+            report(err, err_code(level, 6, c));
+        }
+    }
+}
+
 // Batched partial Cholesky of cell frontals (cell elimination, Sec. 2.1) or of the root.
 __global__ __launch_bounds__(256) void k_potrf_batch(const FrontDesc* __restrict__ desc, double* __restrict__ pool,
                                                      int panel_cap, int level, int step, unsigned long long* err,

@@ -15,6 +15,10 @@ __global__ void k_grad_log_a(int d, int s, double inv_h2, const double* a, const
 __global__ void k_leaf_dofs(const CellRef* cells, int d, int s, int w, int nc1, int32_t* cdofs);
 __global__ void k_front_csr(const Tile* tiles, const CellRef* cells, const int32_t* cdofs, int d, int s, int w,
                             int nc1, const int32_t* row_ptr, const int32_t* col, const double* val, double* F);
+__global__ void k_extend_src(const CellRef* cells, const int32_t* g2, const int32_t* t2, int ngroups2,
+                             const int32_t* gslot_cnt, const int32_t* gslot_cell, const int32_t* gslot_off,
+                             const CellRef* child, int nchild, int d, int pnc1, int nc1, int W, int level,
+                             int32_t* src, unsigned long long* err);
 __global__ void k_front_extend(const Tile* tiles, const CellRef* cells, const int32_t* src, int W,
                                const CellRef* child, const double* Fc, double* F);
 __global__ void k_potrf_batch(const FrontDesc* desc, double* pool, int panel_cap, int level, int step,

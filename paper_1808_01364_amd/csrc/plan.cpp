@@ -41,7 +41,7 @@ void LevelPlan::reset() {
     ext_elems = 0;
     level = w = nc1 = 0;
     root = false;
-    dofs_on_device = lists_pending = false;
+    dofs_on_device = lists_pending = src_on_device = false;
     for (auto* v : {&gptr, &gdofs, &gslot_cnt, &gslot_cell, &gslot_off, &c_nI, &c_nB, &c_nf, &c_ld, &c_dptr,
                     &c_dofs, &c_gptr, &c_g, &c_goff, &seps, &skels, &src, &sep_dofs, &sep_sorted, &sep_g, &sep_t,
                     &g_g2, &g_t2, &c_g2, &c_t2})
@@ -136,7 +136,7 @@ void fill_leaf_lists(const GridInfo& gi, PlanScratch& scr, LevelPlan& P) {
 }
 
 void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::vector<int32_t>& active,
-                 const LevelPlan* prev, PlanScratch& scr, int lds_apply_cap, LevelPlan& P, bool dofs_on_device) {
+                 const LevelPlan* prev, PlanScratch& scr, int lds_apply_cap, LevelPlan& P, bool device_tables) {
     const int d = gi.d, s = gi.s;
     P.reset();
     P.level = level;
@@ -198,9 +198,9 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
         P.gptr.push_back(static_cast<int32_t>(na));
         // the groups' unknowns and the separator lists now, or later (fill_leaf_lists) when
         // the device writes the cells' frontal unknowns itself
-        P.dofs_on_device = dofs_on_device;
+        P.dofs_on_device = device_tables;
         P.lists_pending = true;
-        if (!dofs_on_device) fill_leaf_lists(gi, scr, P);
+        if (!device_tables) fill_leaf_lists(gi, scr, P);
     } else {
         std::vector<int32_t>& akey = scr.akey;
         akey.resize(na);
@@ -425,7 +425,8 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
 
     // ---- extend-add sources from the children (level >= 1) ----
     const int W = 1 << d;
-    if (prev != nullptr) {
+    P.src_on_device = prev != nullptr && device_tables;
+    if (prev != nullptr && !P.src_on_device) {
         const int pnc1 = prev->nc1;
         // parent cell of every cell of the level below
         std::vector<int32_t>& par_of = scr.par_of;
@@ -785,7 +786,10 @@ void validate_cells(const LevelPlan& P, const LevelPlan* prev, int d) {
         need(f.ext >= 0 && f.ext + (f.p + 15) / 16 <= P.ext_elems, "potrf ext bounds");
     }
     const int W = 1 << d;
-    if (prev != nullptr) {
+    if (prev != nullptr && P.src_on_device) {
+        need(static_cast<int64_t>(P.c_g2.size()) == ncd && static_cast<int64_t>(P.c_t2.size()) == ncd,
+             "extend-add source lists", P.c_g2.size(), ncd);
+    } else if (prev != nullptr) {
         need(static_cast<int64_t>(P.src.size()) == ncd * 2 * W, "src size", P.src.size(), ncd * 2 * W);
         for (int64_t e = 0; e < ncd * W; ++e) {
             const int c = P.src[2 * e], pos = P.src[2 * e + 1];

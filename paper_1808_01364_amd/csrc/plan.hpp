@@ -31,6 +31,9 @@ struct LevelPlan {
     // groups' unknowns and separator lists wait for fill_leaf_lists
     bool dofs_on_device = false;
     bool lists_pending = false;
+    // levels >= 1: the extend-add source table (src) is built by the device from c_g2 / c_t2
+    // and the level below's slot tables (src stays empty)
+    bool src_on_device = false;
 
     // groups (ascending key), their unknowns ascending
     std::vector<int32_t> gptr;      // ngroups + 1
@@ -137,12 +140,12 @@ int inner_leaf(int d, int leaf);
 // The work is split in two halves so that the second can overlap device work:
 //   build_cells: groups, cell frontals, assembly tiles, elimination and cell apply tables;
 //   build_separators: block-Jacobi, ID / skeleton and gather tables (not at the root).
-// dofs_on_device (used at level 0 only, where every unknown is active): leave c_dofs to the
-// device and defer gdofs and the separator lists to fill_leaf_lists, which must run before
-// build_separators; the cell tables are complete without them.
+// device_tables: leave the largest per-unknown table to the device. At level 0 (every unknown
+// active) that is c_dofs, and gdofs and the separator lists wait for fill_leaf_lists, which
+// must run before build_separators; at levels >= 1 it is the extend-add source table src.
 void build_cells(const GridInfo& g, int level, int leaf, bool root, const std::vector<int32_t>& active,
                  const LevelPlan* prev, PlanScratch& scr, int lds_apply_cap, LevelPlan& out,
-                 bool dofs_on_device = false);
+                 bool device_tables = false);
 void fill_leaf_lists(const GridInfo& g, PlanScratch& scr, LevelPlan& out);
 void build_separators(const GridInfo& g, PlanScratch& scr, int lds_apply_cap, LevelPlan& out);
 // Both halves.

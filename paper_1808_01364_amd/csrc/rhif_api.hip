@@ -147,6 +147,11 @@ struct LevelDev {
     rhif::FrontDesc* potrf = nullptr;
     rhif::Tile* tiles = nullptr;
     int32_t* src = nullptr;
+    int32_t* cg2 = nullptr;       // per frontal unknown: its group and position at the level below
+    int32_t* ct2 = nullptr;
+    int32_t* gslot_cnt = nullptr; // per group: the cells containing it and its frontal offsets there
+    int32_t* gslot_cell = nullptr;
+    int32_t* gslot_off = nullptr;
     rhif::SepDesc* sep = nullptr;
     rhif::CellGroup* cg = nullptr;
     rhif::CellScaleDesc* cs = nullptr;
@@ -494,6 +499,7 @@ std::string step_name(int st) {
         case 1: return "C (block-Jacobi)";
         case 2: return "K (skeleton elimination)";
         case 3: return "root";
+        case 6: return "extend-add source table";
         default: return "?";
     }
 }
@@ -507,6 +513,11 @@ void check_err(rhif_factor_s* f, hipStream_t s) {
         const int step = static_cast<int>((h >> 32) & 0xff);
         const int block = static_cast<int>(h & 0xffffffffu);
         char buf[256];
+        if (step == 6) {
+            std::snprintf(buf, sizeof(buf), "internal error: extend-add sources of cell %d at level %d disagree "
+                          "with the plan", block, ilevel);
+            fail(RHIF_EDEVICE, buf);
+        }
         if (step == 7) {
             std::snprintf(buf, sizeof(buf), "internal error: skeleton row table of group %d at level %d disagrees "
                           "with the plan", block, ilevel);
@@ -621,9 +632,10 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
 
         // ---- plan and upload the cell half ----
         auto t0 = now();
-        // level 0: the device writes the cells' frontal unknowns from their closed form, and
-        // the host fills the groups' lists while the first kernels run
-        build_cells(g, lvl, leaf, root, active, prevP, scr, kApplyCap, P, lvl == 0);
+        // the largest per-unknown table is built by the device: at level 0 the cells' frontal
+        // unknowns (closed form; the host fills the groups' lists while the first kernels
+        // run), above it the extend-add sources
+        build_cells(g, lvl, leaf, root, active, prevP, scr, kApplyCap, P, true);
         validate_cells(P, prevP, d);
         if (P.max_nf > 16 * kPotrfMaxTiles) fail(RHIF_ENOMEM, "a frontal matrix is too large for this version");
         f->stats.n_active[lvl] = static_cast<int64_t>(active.size());
@@ -632,15 +644,20 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         {
             Packer pk;
             const size_t o_cdofs = pk.add(P.c_dofs), o_cref = pk.add(P.cell_ref), o_potrf = pk.add(P.cell_potrf),
-                         o_tiles = pk.add(P.tiles), o_src = pk.add(P.src), o_cad = pk.add(P.cell_apply);
+                         o_tiles = pk.add(P.tiles), o_src = pk.add(P.src), o_cad = pk.add(P.cell_apply),
+                         o_g2 = pk.add(P.c_g2), o_t2 = pk.add(P.c_t2);
             char* T = upload(f, pk, s);
+            LD.cg2 = view<int32_t>(T, o_g2);
+            LD.ct2 = view<int32_t>(T, o_t2);
             LD.cdofs = P.dofs_on_device
                            ? static_cast<int32_t*>(f->dalloc(std::max<int64_t>(P.c_dptr[P.ncells], 1) * sizeof(int32_t)))
                            : view<int32_t>(T, o_cdofs);
             LD.cref = view<CellRef>(T, o_cref);
             LD.potrf = view<FrontDesc>(T, o_potrf);
             LD.tiles = view<Tile>(T, o_tiles);
-            LD.src = view<int32_t>(T, o_src);
+            LD.src = P.src_on_device ? static_cast<int32_t*>(f->dalloc(
+                                           std::max<int64_t>(P.c_dptr[P.ncells], 1) * 2 * W * sizeof(int32_t)))
+                                     : view<int32_t>(T, o_src);
             LD.cell_ad = view<ApplyDesc>(T, o_cad);
         }
         LD.n_cell_ad = static_cast<int>(P.cell_apply.size());
@@ -667,6 +684,12 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                        hipLaunchKernelGGL(k_front_csr, dim3(P.tiles.size()), dim3(256), 0, s, LD.tiles, LD.cref,
                                           LD.cdofs, d, g.s, P.w, P.nc1, f->rp, f->ci, f->val, LD.front));
             } else {
+                if (P.src_on_device)
+                    KTIMED(f, s, RHIF_K_FRONT_EXTEND, 0.0, 4.0 * (2.0 + 2.0 * W) * P.c_dptr[P.ncells],
+                           hipLaunchKernelGGL(k_extend_src, dim3(P.ncells), dim3(256), 0, s, LD.cref, LD.cg2, LD.ct2,
+                                              static_cast<int>(prevP->gptr.size()) - 1, prev->gslot_cnt,
+                                              prev->gslot_cell, prev->gslot_off, prev->cref, prevP->ncells, d,
+                                              prevP->nc1, P.nc1, W, lvl, LD.src, f->err));
                 double rd = 0.0;
                 for (int c = 0; c < prevP->ncells; ++c)
                     rd += 8.0 * static_cast<double>(prevP->c_nB[c]) * prevP->c_nB[c];
@@ -793,8 +816,12 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             const size_t o_sep = pk.add(P.sep_desc), o_cg = pk.add(P.cell_groups), o_cs = pk.add(P.cell_scale),
                          o_skd = pk.add(P.skel_desc), o_cgp = pk.add(P.c_gptr), o_cgl = pk.add(P.c_g),
                          o_cgo = pk.add(P.c_goff), o_sad = pk.add(P.sep_apply),
-                         o_gat = pk.add(P.gather), o_sdofs = pk.add(P.sep_dofs);
+                         o_gat = pk.add(P.gather), o_sdofs = pk.add(P.sep_dofs),
+                         o_gsc = pk.add(P.gslot_cnt), o_gsl = pk.add(P.gslot_cell), o_gso = pk.add(P.gslot_off);
             char* T = upload(f, pk, s);
+            LD.gslot_cnt = view<int32_t>(T, o_gsc);
+            LD.gslot_cell = view<int32_t>(T, o_gsl);
+            LD.gslot_off = view<int32_t>(T, o_gso);
             LD.sep = view<SepDesc>(T, o_sep);
             LD.cg = view<CellGroup>(T, o_cg);
             LD.cs = view<CellScaleDesc>(T, o_cs);
