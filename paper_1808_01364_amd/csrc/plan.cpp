@@ -665,17 +665,16 @@ void build_separators(const GridInfo& gi, PlanScratch& scr, int lds_apply_cap, L
     P.ws_elems = ws;
 }
 
-void finish_level(const LevelPlan& P, const int32_t* k, const int32_t* perm, int lds_apply_cap,
-                  std::vector<ApplyDesc>& skel_apply, std::vector<int32_t>& skel_dofs,
-                  int64_t& ws_elems, const std::vector<int32_t>& active,
-                  std::vector<int32_t>& next_active, PlanScratch& scr, double& skel_flops,
-                  double& skel_apply_bytes) {
+void skel_apply_tables(const LevelPlan& P, const int32_t* k, const int32_t* perm, int lds_apply_cap,
+                       std::vector<ApplyDesc>& skel_apply, std::vector<int32_t>& skel_dofs, int64_t& ws_elems,
+                       double& skel_flops, double& skel_apply_bytes) {
     if (P.lists_pending) throw std::logic_error("leaf groups without their unknowns");
     skel_flops = 0.0;
     skel_apply_bytes = 0.0;
     skel_apply.clear();
-    skel_dofs.clear();
-    const int32_t st = ++scr.stamp;
+    skel_apply.reserve(P.skel_desc.size());
+    skel_dofs.resize(std::max<int32_t>(P.skel_ntotal, 0));
+    size_t ndofs = 0;
     for (size_t e = 0; e < P.skel_desc.size(); ++e) {
         const SkelDesc& sk = P.skel_desc[e];
         const int g = P.skels[e];
@@ -683,7 +682,6 @@ void finish_level(const LevelPlan& P, const int32_t* k, const int32_t* perm, int
         const int kk = k[sk.gid];
         const int32_t* pv = perm + sk.poff;
         const int32_t* gd = P.gdofs.data() + P.gptr[g];
-        for (int q = kk; q < n; ++q) scr.mark_stamp[gd[pv[q]]] = st;   // redundant unknowns
         const double nr = n - kk, kd = kk, rr = sk.r, nd = n;
         // ID by pivoted QR of an r x n block to rank k, then the skeleton elimination
         skel_flops += std::max(0.0, 4.0 * rr * nd * kd - 2.0 * kd * kd * (rr + nd) + 4.0 * kd * kd * kd / 3.0) +
@@ -704,26 +702,56 @@ void finish_level(const LevelPlan& P, const int32_t* k, const int32_t* perm, int
         ad.ld = n;
         ad.nI = n - kk;
         ad.nB = kk;
-        ad.dofs = static_cast<int32_t>(skel_dofs.size());
-        for (int q = kk; q < n; ++q) skel_dofs.push_back(gd[pv[q]]);
-        for (int q = 0; q < kk; ++q) skel_dofs.push_back(gd[pv[q]]);
+        ad.dofs = static_cast<int32_t>(ndofs);
+        // redundant unknowns first, then the skeleton
+        int32_t* o = skel_dofs.data() + ndofs;
+        for (int q = kk; q < n; ++q) *o++ = gd[pv[q]];
+        for (int q = 0; q < kk; ++q) *o++ = gd[pv[q]];
+        ndofs += n;
         skel_apply.push_back(ad);
     }
-    // the interiors are eliminated; of the separators the redundant unknowns go
-    (void)active;
-    next_active.clear();
-    next_active.reserve(P.sep_sorted.size());
-    scr.nxt_g2.clear();
-    scr.nxt_t2.clear();
-    for (size_t q = 0; q < P.sep_sorted.size(); ++q) {
-        const int32_t i = P.sep_sorted[q];
-        if (scr.mark_stamp[i] == st) continue;
-        next_active.push_back(i);
-        scr.nxt_g2.push_back(P.sep_g[q]);
-        scr.nxt_t2.push_back(P.sep_t[q]);
+    skel_dofs.resize(ndofs);
+}
+
+void next_active_set(const LevelPlan& P, const int32_t* k, const int32_t* perm, std::vector<int32_t>& next_active,
+                     PlanScratch& scr) {
+    if (P.lists_pending) throw std::logic_error("leaf groups without their unknowns");
+    const int32_t st = ++scr.stamp;
+    for (size_t e = 0; e < P.skel_desc.size(); ++e) {
+        const SkelDesc& sk = P.skel_desc[e];
+        const int32_t* pv = perm + sk.poff;
+        const int32_t* gd = P.gdofs.data() + P.gptr[P.skels[e]];
+        for (int q = k[sk.gid]; q < sk.n; ++q) scr.mark_stamp[gd[pv[q]]] = st;   // redundant unknowns
     }
+    // the interiors are eliminated; of the separators the redundant unknowns go
+    const size_t ns = P.sep_sorted.size();
+    next_active.resize(ns);
+    scr.nxt_g2.resize(ns);
+    scr.nxt_t2.resize(ns);
+    // branch-free compaction: every entry is written, the cursor advances for the kept ones
+    size_t m = 0;
+    for (size_t q = 0; q < ns; ++q) {
+        const int32_t i = P.sep_sorted[q];
+        next_active[m] = i;
+        scr.nxt_g2[m] = P.sep_g[q];
+        scr.nxt_t2[m] = P.sep_t[q];
+        m += scr.mark_stamp[i] != st ? 1 : 0;
+    }
+    next_active.resize(m);
+    scr.nxt_g2.resize(m);
+    scr.nxt_t2.resize(m);
     scr.act_g2.swap(scr.nxt_g2);
     scr.act_t2.swap(scr.nxt_t2);
+}
+
+void finish_level(const LevelPlan& P, const int32_t* k, const int32_t* perm, int lds_apply_cap,
+                  std::vector<ApplyDesc>& skel_apply, std::vector<int32_t>& skel_dofs,
+                  int64_t& ws_elems, const std::vector<int32_t>& active,
+                  std::vector<int32_t>& next_active, PlanScratch& scr, double& skel_flops,
+                  double& skel_apply_bytes) {
+    (void)active;
+    skel_apply_tables(P, k, perm, lds_apply_cap, skel_apply, skel_dofs, ws_elems, skel_flops, skel_apply_bytes);
+    next_active_set(P, k, perm, next_active, scr);
 }
 
 }  // namespace rhif

@@ -168,6 +168,14 @@ void validate_skel_apply(const LevelPlan& lp, const std::vector<ApplyDesc>& ad,
 // After the IDs of a level: given ranks k and pivot orders (positions into each group's
 // ascending unknowns), build the apply descriptors of the skeleton blocks and the active
 // unknowns of the next level.
+// The two halves of finish_level: the skeleton apply tables (and the level's skeletonization
+// flops and apply bytes), and the next level's active unknowns with their sources (which is
+// all the next level's plan needs).
+void skel_apply_tables(const LevelPlan& lp, const int32_t* k, const int32_t* perm, int lds_apply_cap,
+                       std::vector<ApplyDesc>& skel_apply, std::vector<int32_t>& skel_dofs, int64_t& ws_elems,
+                       double& skel_flops, double& skel_apply_bytes);
+void next_active_set(const LevelPlan& lp, const int32_t* k, const int32_t* perm, std::vector<int32_t>& next_active,
+                     PlanScratch& scr);
 void finish_level(const LevelPlan& lp, const int32_t* k, const int32_t* perm,
                   int lds_apply_cap, std::vector<ApplyDesc>& skel_apply,
                   std::vector<int32_t>& skel_dofs, int64_t& ws_elems,

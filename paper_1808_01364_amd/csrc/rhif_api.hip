@@ -619,6 +619,80 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         f->stats.t_phase_ms[idx] += std::chrono::duration<double, std::milli>(now() - t0).count();
     };
 
+    // The skeleton apply tables of level lv (ranks and pivots known): descriptors, the fused
+    // per-group apply table and their upload. Nothing of the next level depends on them, so
+    // they are built while the next level's first kernels run.
+    int pending_skel = -1;
+    auto finish_skel_tables = [&](int lv) {
+        LevelDev& LD = f->lev[lv];
+        const LevelPlan& P = hc.plan(lv);
+        const int nsk = static_cast<int>(LD.k.size());
+        std::vector<ApplyDesc> sk_ad;
+        std::vector<int32_t> sk_dofs;
+        double fl = 0.0, sby = 0.0;
+        skel_apply_tables(P, LD.k.data(), LD.perm.data(), kApplyCap, sk_ad, sk_dofs, f->ws_elems, fl, sby);
+        validate_skel_apply(P, sk_ad, sk_dofs, g.N);
+        LD.b_skel = sby;
+        f->stats.flops[lv] += fl;
+        if (f->ktimes && nsk > 0) {
+            for (auto it = f->pend.rbegin(); it != f->pend.rend(); ++it)
+                if (it->cls == RHIF_K_SKELETONIZE) {
+                    it->fl = fl;
+                    break;
+                }
+        }
+        // per separator group: gather, block Jacobi and skeleton elimination in one launch
+        std::vector<GroupApplyDesc>& gad = hc.gad;
+        gad.assign(P.sep_desc.size(), GroupApplyDesc{});
+        LD.mn_grp = 0;
+        {
+            std::vector<int32_t>& skel_of = hc.skel_of;
+            skel_of.assign(P.gptr.size(), -1);
+            for (int e = 0; e < nsk; ++e) skel_of[P.skels[e]] = e;
+            for (size_t e = 0; e < P.sep_desc.size(); ++e) {
+                const SepDesc& sd = P.sep_desc[e];
+                const GatherDesc& gt = P.gather[e];
+                GroupApplyDesc& x = gad[e];
+                x.n = sd.n;
+                x.dofs = sd.dofs;
+                x.nslot = gt.nslot;
+                for (int sl = 0; sl < gt.nslot; ++sl) x.yoff[sl] = gt.yoff[sl];
+                x.precond = LD.precond ? 1 : 0;
+                x.loff = sd.loff;
+                x.li = sd.lioff;
+                const int se = skel_of[P.seps[e]];
+                if (se >= 0) {
+                    const SkelDesc& sk = P.skel_desc[se];
+                    const int kk = LD.k[sk.gid];
+                    if (kk < sk.n) {
+                        x.nr = sk.n - kk;
+                        x.k = kk;
+                        x.poff = sk.poff;
+                        x.goff = sk.goff;
+                        x.toff = sk.toff;
+                        x.skli = sk.lioff;
+                    }
+                }
+                LD.mn_grp = std::max(LD.mn_grp, sd.n);
+            }
+        }
+        {
+            Packer pk;
+            const size_t o_ad = pk.add(sk_ad), o_dofs = pk.add(sk_dofs), o_gad = pk.add(gad), o_perm = pk.add(LD.perm);
+            char* T = upload(f, pk, s);
+            if (T) {
+                LD.skel_ad = view<ApplyDesc>(T, o_ad);
+                LD.skeldofs = view<int32_t>(T, o_dofs);
+                LD.grp_ad = view<GroupApplyDesc>(T, o_gad);
+                LD.permd = view<int32_t>(T, o_perm);
+            }
+        }
+        LD.n_grp = static_cast<int>(gad.size());
+        LD.n_skel_ad = static_cast<int>(sk_ad.size());
+        LD.lds_skel = apply_lds(sk_ad);
+        apply_max(sk_ad, LD.mi_skel, LD.mb_skel);
+    };
+
     for (int lvl = 0; lvl <= f->L; ++lvl) {
         const bool root = (lvl == f->L);
         const bool exact = !root && lvl < f->l0;
@@ -801,6 +875,10 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         }
         phase(root ? 6 : 1, t0);
         if (P.lists_pending) fill_leaf_lists(g, scr, P);
+        if (pending_skel >= 0) {
+            finish_skel_tables(pending_skel);
+            pending_skel = -1;
+        }
         if (root) {
             f->stats.flops[lvl] += P.flops;
             break;
@@ -952,7 +1030,8 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         check_err(f, s);   // synchronizes: the ranks are on the host now
         phase(3, t0);
 
-        // ---- skeleton apply tables and the next level's active unknowns ----
+        // ---- the next level's active unknowns; this level's skeleton apply tables are built
+        //      after the next level's first launches (finish_skel_tables) ----
         t0 = now();
         LD.k.assign(hk, hk + nsk);
         LD.perm.assign(hp, hp + P.skel_ntotal);
@@ -971,74 +1050,12 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         f->stats.sum_skel_n[lvl] = P.skel_ntotal;
         f->stats.sum_rank[lvl] = sum_rank;
         f->stats.max_rank[lvl] = max_rank;
-        std::vector<ApplyDesc> sk_ad;
-        std::vector<int32_t> sk_dofs;
-        double fl = 0.0, sby = 0.0;
-        finish_level(P, LD.k.data(), LD.perm.data(), kApplyCap, sk_ad, sk_dofs, f->ws_elems, active, next, scr, fl,
-                     sby);
-        validate_skel_apply(P, sk_ad, sk_dofs, g.N);
-        LD.b_skel = sby;
-        f->stats.flops[lvl] += fl;
-        if (f->ktimes && nsk > 0) {
-            for (auto it = f->pend.rbegin(); it != f->pend.rend(); ++it)
-                if (it->cls == RHIF_K_SKELETONIZE) {
-                    it->fl = fl;
-                    break;
-                }
-        }
-        // per separator group: gather, block Jacobi and skeleton elimination in one launch
-        std::vector<GroupApplyDesc>& gad = hc.gad;
-        gad.assign(P.sep_desc.size(), GroupApplyDesc{});
-        LD.mn_grp = 0;
-        {
-            std::vector<int32_t>& skel_of = hc.skel_of;
-            skel_of.assign(P.gptr.size(), -1);
-            for (int e = 0; e < nsk; ++e) skel_of[P.skels[e]] = e;
-            for (size_t e = 0; e < P.sep_desc.size(); ++e) {
-                const SepDesc& sd = P.sep_desc[e];
-                const GatherDesc& gt = P.gather[e];
-                GroupApplyDesc& x = gad[e];
-                x.n = sd.n;
-                x.dofs = sd.dofs;
-                x.nslot = gt.nslot;
-                for (int sl = 0; sl < gt.nslot; ++sl) x.yoff[sl] = gt.yoff[sl];
-                x.precond = LD.precond ? 1 : 0;
-                x.loff = sd.loff;
-                x.li = sd.lioff;
-                const int se = skel_of[P.seps[e]];
-                if (se >= 0) {
-                    const SkelDesc& sk = P.skel_desc[se];
-                    const int kk = LD.k[sk.gid];
-                    if (kk < sk.n) {
-                        x.nr = sk.n - kk;
-                        x.k = kk;
-                        x.poff = sk.poff;
-                        x.goff = sk.goff;
-                        x.toff = sk.toff;
-                        x.skli = sk.lioff;
-                    }
-                }
-                LD.mn_grp = std::max(LD.mn_grp, sd.n);
-            }
-        }
-        {
-            Packer pk;
-            const size_t o_ad = pk.add(sk_ad), o_dofs = pk.add(sk_dofs), o_gad = pk.add(gad), o_perm = pk.add(LD.perm);
-            char* T = upload(f, pk, s);
-            if (T) {
-                LD.skel_ad = view<ApplyDesc>(T, o_ad);
-                LD.skeldofs = view<int32_t>(T, o_dofs);
-                LD.grp_ad = view<GroupApplyDesc>(T, o_gad);
-                LD.permd = view<int32_t>(T, o_perm);
-            }
-        }
-        LD.n_grp = static_cast<int>(gad.size());
-        LD.n_skel_ad = static_cast<int>(sk_ad.size());
-        LD.lds_skel = apply_lds(sk_ad);
-        apply_max(sk_ad, LD.mi_skel, LD.mb_skel);
+        next_active_set(P, LD.k.data(), LD.perm.data(), next, scr);
+        pending_skel = lvl;
         active.swap(next);
         phase(5, t0);
     }
+    if (pending_skel >= 0) finish_skel_tables(pending_skel);
     check_err(f, s);
     f->stats.levels = f->L;
     f->stats.root_size = static_cast<int32_t>(active.size());
