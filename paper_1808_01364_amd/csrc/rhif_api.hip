@@ -324,6 +324,7 @@ struct rhif_factor_s {
     // PCG workspace
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *part = nullptr, *sc = nullptr;
     double* hsc = nullptr;                 // pinned host scalars of the PCG (read back by the graphs)
+    hipEvent_t sc_ev = nullptr;            // recorded after a scalar's copy to hsc
     const double* graph_u = nullptr;       // solution vector the PCG graphs were captured with
     // HIP graphs of the solve phase, captured on first use on an internal stream:
     // [0] z <- F^-1 z;  [1] the first CG update;  [2] one PCG iteration (apply .. next update)
@@ -438,6 +439,8 @@ struct rhif_factor_s {
         }
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         cap_stream = nullptr;
+        if (sc_ev) (void)hipEventDestroy(sc_ev);
+        sc_ev = nullptr;
         if (hsc) PinnedSlots::get().give(hsc);
         hsc = nullptr;
         for (const Pend& q : pend) {
@@ -1218,6 +1221,7 @@ void ensure_pcg(rhif_factor_s* f) {
     f->hsc = PinnedSlots::get().take();
     if (f->hsc == nullptr)
         fail(RHIF_ENOMEM, "pinned host allocation failed");
+    HIPCHK(hipEventCreateWithFlags(&f->sc_ev, hipEventDisableTiming));
 }
 
 void drop_graph(rhif_factor_s* f, int g) {
@@ -1235,6 +1239,15 @@ void drop_graph(rhif_factor_s* f, int g) {
 // Runs body(stream) as graph g: captured once on the internal stream, then replayed on s.
 // Returns false (nothing launched) if graphs are unavailable or the kernels inside are
 // being timed, and the caller runs body(s) directly.
+// Whether the solve phase runs as HIP graphs (the flag is set, capture works, and none of
+// the kernels inside is being timed).
+bool graphs_wanted(const rhif_factor_s* f) {
+    if (f->graphs_off || !(f->o.flags & RHIF_FLAG_SOLVE_GRAPHS)) return false;
+    constexpr uint32_t in_graphs = (1u << RHIF_K_APPLY_UP) | (1u << RHIF_K_APPLY_DOWN) | (1u << RHIF_K_APPLY_GATHER) |
+                                   (1u << RHIF_K_SPMV) | (1u << RHIF_K_VECTOR);
+    return !(f->ktimes && (f->kmask & in_graphs));
+}
+
 template <class Body>
 bool run_graph(rhif_factor_s* f, int g, hipStream_t s, Body body) {
     if (f->graphs_off || !(f->o.flags & RHIF_FLAG_SOLVE_GRAPHS)) return false;
@@ -1497,14 +1510,21 @@ rhif_status rhif_pcg_solve(rhif_factor_t f, const double* rhs, double* u, double
         VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, f->part, gb, 2, f->sc, nullptr));
         HIPCHK(hipMemcpyAsync(hsc + 1, f->sc + 3, sizeof(double), hipMemcpyDeviceToHost, cs));
     };
-    // z = F^-1 r; rho = r.z; beta; p = z + beta p; then the next update
-    auto iterate = [&](hipStream_t cs) {
+    // z = F^-1 r; rho = r.z; beta (touches neither u, r nor p)
+    auto precondition = [&](hipStream_t cs) {
         VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, cs, N, f->r, f->z));
         do_apply_inplace(f, f->z, cs);
         VEC(2 * NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, cs, N, f->r, f->z, f->part));
         VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, f->part, gb, 4, f->sc, nullptr));
+    };
+    // p = z + beta p; then the next update
+    auto advance = [&](hipStream_t cs) {
         VEC(3 * NB, hipLaunchKernelGGL(rhif::k_update_p, dim3(gb), dim3(256), 0, cs, N, f->sc, f->z, f->p));
         update(cs);
+    };
+    auto iterate = [&](hipStream_t cs) {
+        precondition(cs);
+        advance(cs);
     };
     {
         hipStream_t cs = s;
@@ -1514,6 +1534,7 @@ rhif_status rhif_pcg_solve(rhif_factor_t f, const double* rhs, double* u, double
         VEC(NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, cs, N, rhs, rhs, f->part));
         VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, f->part, gb, 0, f->sc, nullptr));
         HIPCHK(hipMemcpyAsync(hsc, f->sc + 6, sizeof(double), hipMemcpyDeviceToHost, cs));
+        HIPCHK(hipEventRecord(f->sc_ev, cs));
         // z = F^-1 r, rho = r.z, p = z
         VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, cs, N, f->r, f->z));
     }
@@ -1525,31 +1546,70 @@ rhif_status rhif_pcg_solve(rhif_factor_t f, const double* rhs, double* u, double
         VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, f->part, gb, 3, f->sc, nullptr));
         VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, cs, N, f->z, f->p));
     }
-    HIPCHK(hipStreamSynchronize(s));
-    if (g0) f->resolve_graph(0);
-    const double ff = hsc[0];
-    const double fnorm = std::sqrt(ff);
     int it = 0;
     double rel = 0.0;
-    bool conv = (ff == 0.0);
-    int last = -1;   // graph whose replay the next synchronization completes
-    if (!conv && maxit > 0) {
-        if (run_graph(f, 1, s, update)) last = 1;
-        else update(s);
-    }
-    while (!conv && it < maxit) {
+    bool conv = false;
+    if (g0 || graphs_wanted(f)) {
         HIPCHK(hipStreamSynchronize(s));
-        if (last >= 0) f->resolve_graph(last);
-        last = -1;
-        ++it;
-        rel = std::sqrt(hsc[1]) / fnorm;
-        if (rel <= rtol) {
-            conv = true;
-            break;
+        if (g0) f->resolve_graph(0);
+        const double ff = hsc[0];
+        const double fnorm = std::sqrt(ff);
+        conv = (ff == 0.0);
+        int last = -1;   // graph whose replay the next synchronization completes
+        if (!conv && maxit > 0) {
+            if (run_graph(f, 1, s, update)) last = 1;
+            else update(s);
         }
-        if (it >= maxit) break;
-        if (run_graph(f, 2, s, iterate)) last = 2;
-        else iterate(s);
+        while (!conv && it < maxit) {
+            HIPCHK(hipStreamSynchronize(s));
+            if (last >= 0) f->resolve_graph(last);
+            last = -1;
+            ++it;
+            rel = std::sqrt(hsc[1]) / fnorm;
+            if (rel <= rtol) {
+                conv = true;
+                break;
+            }
+            if (it >= maxit) break;
+            if (run_graph(f, 2, s, iterate)) last = 2;
+            else iterate(s);
+        }
+    } else {
+        // Direct launches. The host waits only for the residual norm (an event after its
+        // copy); while it decides, the stream already preconditions the new residual
+        // (z = F^-1 r and r.z change neither u, r nor p, so an iteration that turns out not
+        // to be needed leaves the solution untouched). The look-ahead is skipped when the
+        // observed rate predicts convergence at the next check (within 10x of rtol), so that
+        // a finished solve rarely leaves an unneeded apply behind. The stream runs the same
+        // kernels in the same order as without look-ahead.
+        HIPCHK(hipEventSynchronize(f->sc_ev));   // ||f||^2, copied before the first apply
+        const double ff = hsc[0];
+        const double fnorm = std::sqrt(ff);
+        conv = (ff == 0.0);
+        if (!conv && maxit > 0) {
+            update(s);
+            HIPCHK(hipEventRecord(f->sc_ev, s));
+            bool ahead = maxit > 1;
+            if (ahead) precondition(s);
+            double prev = 1.0;   // ||r_0|| / ||f||
+            while (true) {
+                HIPCHK(hipEventSynchronize(f->sc_ev));
+                ++it;
+                rel = std::sqrt(hsc[1]) / fnorm;
+                if (rel <= rtol) {
+                    conv = true;
+                    break;
+                }
+                if (it >= maxit) break;
+                if (!ahead) precondition(s);
+                advance(s);
+                HIPCHK(hipEventRecord(f->sc_ev, s));
+                const double predicted = prev > 0.0 ? rel * (rel / prev) : rel;
+                prev = rel;
+                ahead = it + 1 < maxit && !(predicted <= 10.0 * rtol);
+                if (ahead) precondition(s);
+            }
+        }
     }
 #undef VEC
     f->resolve();
