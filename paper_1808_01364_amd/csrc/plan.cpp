@@ -24,15 +24,14 @@ inline void coords(int64_t i, int d, int s, int* x) {
 
 void PlanScratch::init(int64_t N) {
     mark_stamp.assign(N, 0);
-    mark_row.assign(N, 0);
     stamp = 0;
-    act_g2.clear();
-    act_t2.clear();
+    keep_ptr.clear();
+    keep_t.clear();
 }
 
 void PlanScratch::reserve(int64_t N) {
-    act_g2.clear();
-    act_t2.clear();
+    keep_ptr.clear();
+    keep_t.clear();
     if (static_cast<int64_t>(mark_stamp.size()) >= N) return;
     init(N);
 }
@@ -43,8 +42,7 @@ void LevelPlan::reset() {
     root = false;
     dofs_on_device = lists_pending = src_on_device = false;
     for (auto* v : {&gptr, &gdofs, &gslot_cnt, &gslot_cell, &gslot_off, &c_nI, &c_nB, &c_nf, &c_ld, &c_dptr,
-                    &c_dofs, &c_gptr, &c_g, &c_goff, &seps, &skels, &src, &sep_dofs, &sep_sorted, &sep_g, &sep_t,
-                    &g_g2, &g_t2, &c_g2, &c_t2})
+                    &c_dofs, &c_gptr, &c_g, &c_goff, &seps, &skels, &src, &sep_dofs, &g_g2, &g_t2, &c_g2, &c_t2})
         v->clear();
     gcls.clear();
     c_foff.clear();
@@ -78,16 +76,14 @@ int num_levels(int s, int leaf) {
     return L;
 }
 
-void build_level(const GridInfo& gi, int level, int leaf, bool root, const std::vector<int32_t>& active,
-                 const LevelPlan* prev, PlanScratch& scr, int lds_apply_cap, LevelPlan& P) {
-    build_cells(gi, level, leaf, root, active, prev, scr, lds_apply_cap, P);
+void build_level(const GridInfo& gi, int level, int leaf, bool root, int64_t n_active, const LevelPlan* prev,
+                 PlanScratch& scr, int lds_apply_cap, LevelPlan& P) {
+    build_cells(gi, level, leaf, root, n_active, prev, scr, lds_apply_cap, P);
     if (!root) build_separators(gi, scr, lds_apply_cap, P);
 }
 
 void fill_leaf_lists(const GridInfo& gi, PlanScratch& scr, LevelPlan& P) {
     const int d = gi.d, s = gi.s;
-    const int64_t w = P.w;
-    const int KB = 2 * P.nc1 + 2;
     const int ngroups = static_cast<int>(P.gptr.size()) - 1;
     const int64_t s2 = static_cast<int64_t>(s) * s;
     P.gdofs.resize(gi.N);
@@ -103,40 +99,11 @@ void fill_leaf_lists(const GridInfo& gi, PlanScratch& scr, LevelPlan& P) {
             }
         if (out != P.gdofs.data() + P.gptr[g + 1]) throw std::logic_error("leaf group box size");
     }
-    // separator unknowns (some coordinate on a cell boundary), ascending, with their group
-    // and position in it
-    P.sep_sorted.clear();
-    P.sep_g.clear();
-    P.sep_t.clear();
-    const int n2 = d > 2 ? s : 1, n1 = d > 1 ? s : 1;
-    std::vector<int32_t> keyk(static_cast<size_t>(s) + 1);
-    for (int xk = 1; xk <= s; ++xk) keyk[xk] = 2 * (xk / static_cast<int>(w)) + ((xk % w) != 0 ? 1 : 0);
-    auto put = [&](int64_t base, int x0, int x1, int x2) {
-        const int64_t K = keyk[x0] + (d > 1 ? static_cast<int64_t>(keyk[x1]) * KB : 0) +
-                          (d > 2 ? static_cast<int64_t>(keyk[x2]) * KB * KB : 0);
-        const int g = scr.key2g[K];
-        const int* lo = scr.box_lo.data() + 3 * g;
-        const int* nb = scr.box_n.data() + 3 * g;
-        const int t = (x0 - lo[0]) + nb[0] * ((d > 1 ? x1 - lo[1] : 0) + nb[1] * (d > 2 ? x2 - lo[2] : 0));
-        P.sep_sorted.push_back(static_cast<int32_t>(base + x0 - 1));
-        P.sep_g.push_back(g);
-        P.sep_t.push_back(t);
-    };
-    for (int x2 = 1; x2 <= n2; ++x2)
-        for (int x1 = 1; x1 <= n1; ++x1) {
-            const int64_t base = (d > 2 ? (x2 - 1) * s2 : 0) + (d > 1 ? static_cast<int64_t>(x1 - 1) * s : 0);
-            const bool line = (d > 1 && x1 % w == 0) || (d > 2 && x2 % w == 0);
-            if (line) {
-                for (int x0 = 1; x0 <= s; ++x0) put(base, x0, x1, x2);
-            } else {
-                for (int64_t x0 = w; x0 <= s; x0 += w) put(base, static_cast<int>(x0), x1, x2);
-            }
-        }
     P.lists_pending = false;
 }
 
-void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::vector<int32_t>& active,
-                 const LevelPlan* prev, PlanScratch& scr, int lds_apply_cap, LevelPlan& P, bool device_tables) {
+void build_cells(const GridInfo& gi, int level, int leaf, bool root, int64_t n_active, const LevelPlan* prev,
+                 PlanScratch& scr, int lds_apply_cap, LevelPlan& P, bool device_tables) {
     const int d = gi.d, s = gi.s;
     P.reset();
     P.level = level;
@@ -150,12 +117,13 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
     int64_t nkeys = 1;
     for (int k = 0; k < d; ++k) nkeys *= KB;
 
-    // ---- classify the active unknowns and bucket them by key (stable) ----
-    const size_t na = active.size();
-    P.sep_sorted.reserve(na);
+    // ---- classify the active unknowns and bucket them by key ----
+    int64_t na = 0;
     int ngroups = 0;
     scr.key2g.assign(nkeys, -1);
-    if (na > 0 && static_cast<int64_t>(na) == gi.N) {
+    if (prev == nullptr) {
+        if (n_active != gi.N) throw std::logic_error("the leaf level starts with every unknown active");
+        na = gi.N;
         // Every unknown is active (the leaf level): the groups are boxes of the grid,
         // enumerated directly in key order, each in ascending order.
         P.gptr.clear();
@@ -194,48 +162,48 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
             }
             at += static_cast<size_t>(cnt);
         }
-        if (at != na) throw std::logic_error("leaf-level groups do not cover the grid");
+        if (static_cast<int64_t>(at) != na) throw std::logic_error("leaf-level groups do not cover the grid");
         P.gptr.push_back(static_cast<int32_t>(na));
-        // the groups' unknowns and the separator lists now, or later (fill_leaf_lists) when
-        // the device writes the cells' frontal unknowns itself
+        // the groups' unknowns now, or later (fill_leaf_lists) when the device writes the
+        // cells' frontal unknowns itself
         P.dofs_on_device = device_tables;
         P.lists_pending = true;
         if (!device_tables) fill_leaf_lists(gi, scr, P);
     } else {
-        std::vector<int32_t>& akey = scr.akey;
-        akey.resize(na);
-        scr.count.assign(nkeys + 1, 0);
-        // The active list is ascending, so the coordinates can be advanced incrementally
-        // from one unknown to the next instead of divided out of the linear index.
+        // Levels >= 1: the kept unknowns of every group of the level below (ascending
+        // positions, from next_active_set). The unknowns of one group there share one key
+        // here, so groups move as a whole; the parts of a group are then put in ascending
+        // order (in 3D the faces below that tile a face here interleave).
+        const LevelPlan& Q = *prev;
+        const int ng2 = static_cast<int>(Q.gptr.size()) - 1;
+        if (static_cast<int>(scr.keep_ptr.size()) != ng2 + 1 || scr.keep_ptr[ng2] != n_active)
+            throw std::logic_error("kept unknowns of the level below are missing");
         std::vector<int32_t> keyk(static_cast<size_t>(s) + 1);
         for (int xk = 1; xk <= s; ++xk) keyk[xk] = 2 * (xk / static_cast<int>(w)) + ((xk % w) != 0 ? 1 : 0);
-        int64_t mulk[3] = {1, KB, static_cast<int64_t>(KB) * KB};
-        int x[3] = {1, 1, 1};
-        int64_t cur_lin = 0;
-        if (na > 0) {
-            coords(active[0], d, s, x);
-            cur_lin = active[0];
-        }
-        for (size_t a = 0; a < na; ++a) {
-            const int64_t i = active[a];
-            int64_t step = i - cur_lin;
-            if (step > 0) {
-                if (step < s - x[0] + 1) {
-                    x[0] += static_cast<int>(step);
-                } else {
-                    coords(i, d, s, x);
-                }
-                cur_lin = i;
-            }
+        const int64_t mulk[3] = {1, KB, static_cast<int64_t>(KB) * KB};
+        const uint32_t us = static_cast<uint32_t>(s);
+        auto key_of = [&](int32_t i) {   // unknowns are int32 indices: 32-bit divisions
+            uint32_t r = static_cast<uint32_t>(i);
             int64_t K = 0;
-            int odd = 1;
             for (int k = 0; k < d; ++k) {
-                K += keyk[x[k]] * mulk[k];
-                odd &= keyk[x[k]];
+                const uint32_t q = r / us;
+                K += keyk[r - q * us + 1] * mulk[k];
+                r = q;
             }
-            akey[a] = static_cast<int32_t>(K);
-            scr.count[K + 1]++;
-            if (!odd) P.sep_sorted.push_back(static_cast<int32_t>(i));
+            return K;
+        };
+        std::vector<int32_t>& gkey = scr.akey;
+        gkey.assign(ng2, -1);
+        scr.count.assign(nkeys + 1, 0);
+        for (int g2 = 0; g2 < ng2; ++g2) {
+            const int b = scr.keep_ptr[g2], e = scr.keep_ptr[g2 + 1];
+            if (e == b) continue;
+            const int32_t* gd = Q.gdofs.data() + Q.gptr[g2];
+            const int64_t K = key_of(gd[scr.keep_t[b]]);
+            if (key_of(gd[scr.keep_t[e - 1]]) != K) throw std::logic_error("a group of the level below spans two groups");
+            gkey[g2] = static_cast<int32_t>(K);
+            scr.count[K + 1] += e - b;
+            na += e - b;
         }
         for (int64_t K = 0; K < nkeys; ++K)
             if (scr.count[K + 1] > 0) scr.key2g[K] = ngroups++;
@@ -255,33 +223,48 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, const std::
             P.gcls[g] = static_cast<int8_t>(even);
         }
         P.gptr[ngroups] = static_cast<int32_t>(na);
-        P.gdofs.assign(na, 0);
-        // the unknowns go to their groups in ascending order, with their sources at the level
-        // below (aligned with the active list) if there is one; the separators' group and
-        // position are recorded in the ascending order of sep_sorted
-        const bool src_in = prev != nullptr && scr.act_g2.size() == na;
-        if (prev != nullptr && !src_in) throw std::logic_error("active unknowns without their sources");
-        if (src_in) {
-            P.g_g2.assign(na, 0);
-            P.g_t2.assign(na, 0);
-        }
-        std::vector<int32_t> pos(scr.count.begin(), scr.count.end() - 1);
-        for (size_t a = 0; a < na; ++a) {
-            const int32_t K = akey[a];
-            const int32_t at = pos[K]++;
-            P.gdofs[at] = active[a];
-            if (src_in) {
-                P.g_g2[at] = scr.act_g2[a];
-                P.g_t2[at] = scr.act_t2[a];
+        P.gdofs.resize(na);
+        P.g_g2.resize(na);
+        P.g_t2.resize(na);
+        std::vector<int32_t>& pos = scr.pos;
+        pos.assign(scr.count.begin(), scr.count.end() - 1);
+        for (int g2 = 0; g2 < ng2; ++g2) {
+            const int K = gkey[g2];
+            if (K < 0) continue;
+            const int32_t* gd = Q.gdofs.data() + Q.gptr[g2];
+            int at = pos[K];
+            for (int e = scr.keep_ptr[g2]; e < scr.keep_ptr[g2 + 1]; ++e) {
+                const int t = scr.keep_t[e];
+                P.gdofs[at] = gd[t];
+                P.g_g2[at] = g2;
+                P.g_t2[at] = t;
+                ++at;
             }
-            const int g = scr.key2g[K];
-            if (P.gcls[g] != 0) {
-                P.sep_g.push_back(g);
-                P.sep_t.push_back(at - P.gptr[g]);
+            pos[K] = at;
+        }
+        std::vector<int32_t>& ord = scr.ord;
+        std::vector<int32_t>& tmp = scr.tmp;
+        for (int g = 0; g < ngroups; ++g) {
+            const int b = P.gptr[g], e = P.gptr[g + 1];
+            bool sorted = true;
+            for (int q = b + 1; q < e && sorted; ++q) sorted = P.gdofs[q] > P.gdofs[q - 1];
+            if (sorted) continue;
+            ord.resize(e - b);
+            for (int q = 0; q < e - b; ++q) ord[q] = b + q;
+            std::sort(ord.begin(), ord.end(), [&](int32_t u, int32_t v) { return P.gdofs[u] < P.gdofs[v]; });
+            tmp.resize(3 * static_cast<size_t>(e - b));
+            for (int q = 0; q < e - b; ++q) {
+                tmp[3 * q] = P.gdofs[ord[q]];
+                tmp[3 * q + 1] = P.g_g2[ord[q]];
+                tmp[3 * q + 2] = P.g_t2[ord[q]];
+            }
+            for (int q = 0; q < e - b; ++q) {
+                P.gdofs[b + q] = tmp[3 * q];
+                P.g_g2[b + q] = tmp[3 * q + 1];
+                P.g_t2[b + q] = tmp[3 * q + 2];
             }
         }
     }
-    if (P.sep_g.size() != P.sep_sorted.size()) throw std::logic_error("separator bookkeeping");
 
     // ---- cells: every geometric cell; frontal = interior, then boundary groups ----
     int64_t ncells = 1;
@@ -713,45 +696,69 @@ void skel_apply_tables(const LevelPlan& P, const int32_t* k, const int32_t* perm
     skel_dofs.resize(ndofs);
 }
 
-void next_active_set(const LevelPlan& P, const int32_t* k, const int32_t* perm, std::vector<int32_t>& next_active,
-                     PlanScratch& scr) {
+int64_t next_active_set(const LevelPlan& P, const int32_t* k, const int32_t* perm, PlanScratch& scr) {
     if (P.lists_pending) throw std::logic_error("leaf groups without their unknowns");
-    const int32_t st = ++scr.stamp;
+    // the interiors are eliminated; the separator groups keep their unknowns, the skeletonized
+    // ones only their skeleton
+    const int ng = static_cast<int>(P.gptr.size()) - 1;
+    std::vector<int32_t>& kp = scr.keep_ptr;
+    kp.assign(ng + 1, 0);
+    for (int g = 0; g < ng; ++g) kp[g + 1] = P.gcls[g] != 0 ? P.gptr[g + 1] - P.gptr[g] : 0;
+    std::vector<int32_t>& sk_of = scr.skel_of;
+    sk_of.assign(ng, -1);
     for (size_t e = 0; e < P.skel_desc.size(); ++e) {
-        const SkelDesc& sk = P.skel_desc[e];
-        const int32_t* pv = perm + sk.poff;
-        const int32_t* gd = P.gdofs.data() + P.gptr[P.skels[e]];
-        for (int q = k[sk.gid]; q < sk.n; ++q) scr.mark_stamp[gd[pv[q]]] = st;   // redundant unknowns
+        const int g = P.skels[e];
+        const int kk = k[P.skel_desc[e].gid];
+        if (kk < 0 || kk > P.skel_desc[e].n) throw std::logic_error("rank out of range");
+        sk_of[g] = static_cast<int32_t>(e);
+        kp[g + 1] = kk;
     }
-    // the interiors are eliminated; of the separators the redundant unknowns go
-    const size_t ns = P.sep_sorted.size();
-    next_active.resize(ns);
-    scr.nxt_g2.resize(ns);
-    scr.nxt_t2.resize(ns);
-    // branch-free compaction: every entry is written, the cursor advances for the kept ones
-    size_t m = 0;
-    for (size_t q = 0; q < ns; ++q) {
-        const int32_t i = P.sep_sorted[q];
-        next_active[m] = i;
-        scr.nxt_g2[m] = P.sep_g[q];
-        scr.nxt_t2[m] = P.sep_t[q];
-        m += scr.mark_stamp[i] != st ? 1 : 0;
+    for (int g = 0; g < ng; ++g) kp[g + 1] += kp[g];
+    std::vector<int32_t>& kt = scr.keep_t;
+    kt.resize(kp[ng] + 1);   // one slack entry for the branch-free compaction below
+    // (plain local pointers: the stamps, the output and the counters do not alias)
+    int32_t* __restrict__ mark = scr.mark_stamp.data();
+    int32_t* __restrict__ out = kt.data();
+    const int32_t* __restrict__ kpp = kp.data();
+    int32_t stamp = scr.stamp;
+    for (int g = 0; g < ng; ++g) {
+        int32_t* o = out + kpp[g];
+        const int n = kpp[g + 1] - kpp[g];
+        const int e = sk_of[g];
+        if (e < 0) {
+            for (int t = 0; t < n; ++t) o[t] = t;
+            continue;
+        }
+        // skeleton positions in ascending order
+        const int nn = P.skel_desc[e].n;
+        const int32_t* pv = perm + P.skel_desc[e].poff;
+        bool bad = false;
+        for (int q = 0; q < n; ++q) bad |= static_cast<uint32_t>(pv[q]) >= static_cast<uint32_t>(nn);
+        if (bad) throw std::logic_error("pivot position out of range");
+        if (nn <= 64) {
+            uint64_t m = 0;
+            for (int q = 0; q < n; ++q) m |= uint64_t(1) << pv[q];
+            for (; m != 0; m &= m - 1) *o++ = __builtin_ctzll(m);
+        } else {
+            const int32_t st = ++stamp;
+            for (int q = 0; q < n; ++q) mark[pv[q]] = st;
+            for (int t = 0; t < nn; ++t) {
+                *o = t;
+                o += mark[t] == st ? 1 : 0;
+            }
+        }
+        if (o != out + kpp[g + 1]) throw std::logic_error("pivot order is not a permutation");
     }
-    next_active.resize(m);
-    scr.nxt_g2.resize(m);
-    scr.nxt_t2.resize(m);
-    scr.act_g2.swap(scr.nxt_g2);
-    scr.act_t2.swap(scr.nxt_t2);
+    scr.stamp = stamp;
+    kt.resize(kp[ng]);
+    return kp[ng];
 }
 
-void finish_level(const LevelPlan& P, const int32_t* k, const int32_t* perm, int lds_apply_cap,
-                  std::vector<ApplyDesc>& skel_apply, std::vector<int32_t>& skel_dofs,
-                  int64_t& ws_elems, const std::vector<int32_t>& active,
-                  std::vector<int32_t>& next_active, PlanScratch& scr, double& skel_flops,
-                  double& skel_apply_bytes) {
-    (void)active;
+int64_t finish_level(const LevelPlan& P, const int32_t* k, const int32_t* perm, int lds_apply_cap,
+                     std::vector<ApplyDesc>& skel_apply, std::vector<int32_t>& skel_dofs, int64_t& ws_elems,
+                     PlanScratch& scr, double& skel_flops, double& skel_apply_bytes) {
     skel_apply_tables(P, k, perm, lds_apply_cap, skel_apply, skel_dofs, ws_elems, skel_flops, skel_apply_bytes);
-    next_active_set(P, k, perm, next_active, scr);
+    return next_active_set(P, k, perm, scr);
 }
 
 }  // namespace rhif

@@ -55,8 +55,6 @@ struct LevelPlan {
 
     // separator groups (class >= 1) and the skeletonized ones (class 1)
     std::vector<int32_t> seps;
-    std::vector<int32_t> sep_sorted;   // the separator unknowns, ascending
-    std::vector<int32_t> sep_g, sep_t; // their group and position in it (aligned)
     std::vector<int32_t> g_g2, g_t2;   // sources at the level below, aligned with gdofs
     std::vector<int32_t> c_g2, c_t2;   // and with c_dofs
     std::vector<int32_t> skels;
@@ -99,18 +97,19 @@ struct LevelPlan {
 struct PlanScratch {
     std::vector<int32_t> count;            // key buckets
     std::vector<int32_t> key2g;
-    // per active unknown (aligned with the active list): its group and position in it at the
-    // level below, i.e. where its row sits in a child frontal (set by finish_level)
-    std::vector<int32_t> act_g2, act_t2, nxt_g2, nxt_t2;
+    // the unknowns that stay active, per group of the level just finished: positions in the
+    // group's ascending list (set by next_active_set, read by the next level's build_cells)
+    std::vector<int32_t> keep_ptr, keep_t;
     std::vector<int32_t> box_lo, box_n;    // leaf-level group boxes
-    std::vector<int32_t> mark_stamp, mark_row;
+    std::vector<int32_t> mark_stamp;
     std::vector<int32_t> par_of;
-    std::vector<int32_t> akey;             // per active unknown: its group key
+    std::vector<int32_t> akey;             // per group of the level below: its key here
+    std::vector<int32_t> pos, ord, tmp, skel_of;
     std::vector<int64_t> cell_y;           // per cell: its offset in the apply scratch
     int32_t stamp = 0;
     void init(int64_t N);
     // Make room for N unknowns without clearing the stamps (they only grow); starts a new
-    // factorization (no sources at the leaf level).
+    // factorization (nothing kept from a level below).
     void reserve(int64_t N);
 };
 
@@ -134,23 +133,23 @@ int num_levels(int s, int leaf);
 // (m-1)^d unknowns by a few small ones.
 int inner_leaf(int d, int leaf);
 
-// Build the plan of `level` from its sorted active unknowns. `prev` is the plan of the
-// level below (nullptr at level 0) and is used for the extend-add source tables.
+// Build the plan of `level` with n_active active unknowns: at level 0 every unknown, above it
+// the unknowns next_active_set kept from the level below. `prev` is the plan of the level
+// below (nullptr at level 0); its groups and the kept lists in scr give this level's groups,
+// and it is used for the extend-add source tables.
 // lds_apply_cap: largest nI + nB staged in LDS by the apply kernels.
 // The work is split in two halves so that the second can overlap device work:
 //   build_cells: groups, cell frontals, assembly tiles, elimination and cell apply tables;
 //   build_separators: block-Jacobi, ID / skeleton and gather tables (not at the root).
 // device_tables: leave the largest per-unknown table to the device. At level 0 (every unknown
-// active) that is c_dofs, and gdofs and the separator lists wait for fill_leaf_lists, which
-// must run before build_separators; at levels >= 1 it is the extend-add source table src.
-void build_cells(const GridInfo& g, int level, int leaf, bool root, const std::vector<int32_t>& active,
-                 const LevelPlan* prev, PlanScratch& scr, int lds_apply_cap, LevelPlan& out,
-                 bool device_tables = false);
+// active) that is c_dofs, and gdofs waits for fill_leaf_lists, which must run before
+// build_separators; at levels >= 1 it is the extend-add source table src.
+void build_cells(const GridInfo& g, int level, int leaf, bool root, int64_t n_active, const LevelPlan* prev,
+                 PlanScratch& scr, int lds_apply_cap, LevelPlan& out, bool device_tables = false);
 void fill_leaf_lists(const GridInfo& g, PlanScratch& scr, LevelPlan& out);
 void build_separators(const GridInfo& g, PlanScratch& scr, int lds_apply_cap, LevelPlan& out);
 // Both halves.
-void build_level(const GridInfo& g, int level, int leaf, bool root,
-                 const std::vector<int32_t>& active, const LevelPlan* prev,
+void build_level(const GridInfo& g, int level, int leaf, bool root, int64_t n_active, const LevelPlan* prev,
                  PlanScratch& scr, int lds_apply_cap, LevelPlan& out);
 
 // Check that every offset and size in the device tables of a level stays inside the
@@ -165,21 +164,18 @@ void validate_level(const LevelPlan& lp, const LevelPlan* prev, int d);
 void validate_skel_apply(const LevelPlan& lp, const std::vector<ApplyDesc>& ad,
                          const std::vector<int32_t>& dofs, int64_t N);
 
-// After the IDs of a level: given ranks k and pivot orders (positions into each group's
-// ascending unknowns), build the apply descriptors of the skeleton blocks and the active
-// unknowns of the next level.
-// The two halves of finish_level: the skeleton apply tables (and the level's skeletonization
-// flops and apply bytes), and the next level's active unknowns with their sources (which is
-// all the next level's plan needs).
+// After the IDs of a level, given ranks k and pivot orders (positions into each group's
+// ascending unknowns): skel_apply_tables builds the apply descriptors of the skeleton blocks
+// (and the level's skeletonization flops and apply bytes); next_active_set records, per
+// group, which unknowns stay active (all of a separator group, the skeleton of a
+// skeletonized one, none of an interior), which is all the next level's plan needs, and
+// returns their number; finish_level does both.
 void skel_apply_tables(const LevelPlan& lp, const int32_t* k, const int32_t* perm, int lds_apply_cap,
                        std::vector<ApplyDesc>& skel_apply, std::vector<int32_t>& skel_dofs, int64_t& ws_elems,
                        double& skel_flops, double& skel_apply_bytes);
-void next_active_set(const LevelPlan& lp, const int32_t* k, const int32_t* perm, std::vector<int32_t>& next_active,
-                     PlanScratch& scr);
-void finish_level(const LevelPlan& lp, const int32_t* k, const int32_t* perm,
-                  int lds_apply_cap, std::vector<ApplyDesc>& skel_apply,
-                  std::vector<int32_t>& skel_dofs, int64_t& ws_elems,
-                  const std::vector<int32_t>& active, std::vector<int32_t>& next_active,
-                  PlanScratch& scr, double& skel_flops, double& skel_apply_bytes);
+int64_t next_active_set(const LevelPlan& lp, const int32_t* k, const int32_t* perm, PlanScratch& scr);
+int64_t finish_level(const LevelPlan& lp, const int32_t* k, const int32_t* perm, int lds_apply_cap,
+                     std::vector<ApplyDesc>& skel_apply, std::vector<int32_t>& skel_dofs, int64_t& ws_elems,
+                     PlanScratch& scr, double& skel_flops, double& skel_apply_bytes);
 
 }  // namespace rhif

@@ -30,14 +30,13 @@ extern "C" rhif_status rhif_plan_dry_run(const rhif_grid* g, int32_t leaf, rhif_
         const int L = num_levels(gi.s, leaf);
         PlanScratch scr;
         scr.init(gi.N);
-        std::vector<int32_t> active(gi.N), next;
-        for (int64_t i = 0; i < gi.N; ++i) active[i] = static_cast<int32_t>(i);
+        int64_t n_active = gi.N;
         std::vector<LevelPlan> plans(L + 1);
         int64_t ws = 0;
         for (int lvl = 0; lvl <= L; ++lvl) {
             const bool root = lvl == L;
             LevelPlan& P = plans[lvl];
-            build_level(gi, lvl, leaf, root, active, lvl ? &plans[lvl - 1] : nullptr, scr, 7000, P);
+            build_level(gi, lvl, leaf, root, n_active, lvl ? &plans[lvl - 1] : nullptr, scr, 7000, P);
             validate_level(P, lvl ? &plans[lvl - 1] : nullptr, gi.d);
             if (lvl == 0) {
                 // the closed form the device uses for the leaf cells' frontal unknowns
@@ -74,11 +73,10 @@ extern "C" rhif_status rhif_plan_dry_run(const rhif_grid* g, int32_t leaf, rhif_
             std::vector<int32_t> sdofs;
             double fl = 0, by = 0;
             ws = std::max(ws, P.ws_elems);
-            finish_level(P, ks.data(), perm.data(), 7000, sad, sdofs, ws, active, next, scr, fl, by);
+            n_active = finish_level(P, ks.data(), perm.data(), 7000, sad, sdofs, ws, scr, fl, by);
             validate_skel_apply(P, sad, sdofs, gi.N);
-            active.swap(next);
         }
-        if (root_size) *root_size = static_cast<int64_t>(active.size());
+        if (root_size) *root_size = n_active;
         g_plan_error.clear();
         return RHIF_OK;
     } catch (const std::exception& e) {

@@ -67,7 +67,6 @@ struct HostCache {
     size_t down_bytes = 0;
     rhif::PlanScratch scr;
     std::vector<rhif::LevelPlan*> plans;
-    std::vector<int32_t> active, next_active;
 
     char* get_up(size_t b, int& slot) {
         slot = next;
@@ -299,6 +298,8 @@ private:
     size_t cached_ = 0;
 };
 
+constexpr int kKbufHead = 4;   // ints before the ID outputs: the 64-bit error word, padded
+
 struct rhif_factor_s {
     rhif::GridInfo g;
     rhif_opts o{};
@@ -318,7 +319,8 @@ struct rhif_factor_s {
     int64_t y_elems = 0;
     double* ws = nullptr;
     int64_t ws_elems = 0;
-    int32_t* kout = nullptr;  // per-level ID outputs (largest level)
+    int32_t* kbuf = nullptr;  // error word (kKbufHead ints), then the level's ID outputs
+    int32_t* kout = nullptr;  // per-level ID outputs (inside kbuf)
     int32_t* pout = nullptr;
     int64_t kp_elems = 0;
     // PCG workspace
@@ -507,10 +509,8 @@ std::string step_name(int st) {
     }
 }
 
-void check_err(rhif_factor_s* f, hipStream_t s) {
-    unsigned long long h = 0;
-    HIPCHK(hipMemcpyAsync(&h, f->err, sizeof(h), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+// Turns the device error word (~0: no error) into an error return.
+void raise_err(rhif_factor_s* f, unsigned long long h) {
     if (h != ~0ull) {
         const int ilevel = static_cast<int>(h >> 40);
         const int step = static_cast<int>((h >> 32) & 0xff);
@@ -535,6 +535,13 @@ void check_err(rhif_factor_s* f, hipStream_t s) {
                           "block %d", step_name(step).c_str(), ilevel, block);
         fail(RHIF_ENOTSPD, buf);
     }
+}
+
+void check_err(rhif_factor_s* f, hipStream_t s) {
+    unsigned long long h = 0;
+    HIPCHK(hipMemcpyAsync(&h, f->err, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    raise_err(f, h);
 }
 
 template <class T>
@@ -596,7 +603,9 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
     const int W = 1 << d;
     const int leaf = f->w0;
     f->nnz = fd_nnz(d, g.s);
-    f->err = static_cast<unsigned long long*>(f->dalloc(sizeof(unsigned long long)));
+    // the error word leads the block of the ID outputs, so that one copy reads back both
+    f->kbuf = static_cast<int32_t*>(f->dalloc(kKbufHead * sizeof(int32_t)));
+    f->err = reinterpret_cast<unsigned long long*>(f->kbuf);
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, f->err, ~0ull);
     // the handle keeps its own copy of A
     f->rp = static_cast<int32_t*>(f->dalloc((g.N + 1) * sizeof(int32_t)));
@@ -609,10 +618,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
     HostCache& hc = host_cache();
     PlanScratch& scr = hc.scr;
     scr.reserve(g.N);
-    std::vector<int32_t>& active = hc.active;
-    std::vector<int32_t>& next = hc.next_active;
-    active.resize(g.N);
-    for (int64_t i = 0; i < g.N; ++i) active[i] = static_cast<int32_t>(i);
+    int64_t n_active = g.N;   // unknowns active at the current level
     f->lev.resize(f->L + 1);
     const bool timing = (f->o.flags & RHIF_FLAG_PHASE_TIMES) != 0;
     auto now = [] { return std::chrono::steady_clock::now(); };
@@ -712,10 +718,10 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         // the largest per-unknown table is built by the device: at level 0 the cells' frontal
         // unknowns (closed form; the host fills the groups' lists while the first kernels
         // run), above it the extend-add sources
-        build_cells(g, lvl, leaf, root, active, prevP, scr, kApplyCap, P, true);
+        build_cells(g, lvl, leaf, root, n_active, prevP, scr, kApplyCap, P, true);
         validate_cells(P, prevP, d);
         if (P.max_nf > 16 * kPotrfMaxTiles) fail(RHIF_ENOMEM, "a frontal matrix is too large for this version");
-        f->stats.n_active[lvl] = static_cast<int64_t>(active.size());
+        f->stats.n_active[lvl] = n_active;
         f->stats.n_cells[lvl] = P.ncells;
         f->stats.max_front[lvl] = P.max_nf;
         {
@@ -935,10 +941,8 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             std::vector<ApplyDesc> sk_ad;
             std::vector<int32_t> sk_dofs;
             double fl = 0.0, sby = 0.0;
-            finish_level(P, kk.data(), pp.data(), kApplyCap, sk_ad, sk_dofs, f->ws_elems, active, next, scr, fl,
-                         sby);
+            n_active = finish_level(P, kk.data(), pp.data(), kApplyCap, sk_ad, sk_dofs, f->ws_elems, scr, fl, sby);
             if (!sk_ad.empty()) fail(RHIF_EINVAL, "internal: a leaf sublevel produced skeleton blocks");
-            active.swap(next);
             phase(5, t0);
             continue;
         }
@@ -954,10 +958,17 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         const int nsk = exact ? 0 : static_cast<int>(P.skel_desc.size());
         const int64_t kp = static_cast<int64_t>(nsk) + P.skel_ntotal + 1;
         if (kp > f->kp_elems) {
-            f->kout = static_cast<int32_t*>(f->dalloc(kp * sizeof(int32_t)));
-            f->pout = static_cast<int32_t*>(f->dalloc(kp * sizeof(int32_t)));
+            // a larger block: the error word so far moves along (stream-ordered after every
+            // kernel that may have set it)
+            int32_t* nb = static_cast<int32_t*>(f->dalloc((kKbufHead + kp) * sizeof(int32_t)));
+            HIPCHK(hipMemcpyAsync(nb, f->kbuf, sizeof(unsigned long long), hipMemcpyDeviceToDevice, s));
+            f->kbuf = nb;
+            f->err = reinterpret_cast<unsigned long long*>(nb);
             f->kp_elems = kp;
         }
+        // ranks, then the pivot orders, right after the error word
+        f->kout = f->kbuf + kKbufHead;
+        f->pout = f->kout + nsk;
         phase(5, t0);
 
         // ---- block Jacobi (C_l) ----
@@ -1024,13 +1035,20 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                                       LD.cref, LD.front,
                                       f->mp, LD.tp, LD.gp, LD.skli, f->o.eps, f->kout, f->pout, cap, staged, n, rmax,
                                       lvl, f->err));
-            char* h = hc.get_down((nsk + P.skel_ntotal) * sizeof(int32_t) + 64);
-            hk = reinterpret_cast<int32_t*>(h);
+            // error word, ranks and pivot orders in one copy; synchronizes: the ranks are on
+            // the host now
+            const size_t nb = (kKbufHead + nsk + static_cast<size_t>(P.skel_ntotal)) * sizeof(int32_t);
+            char* h = hc.get_down(nb + 64);
+            HIPCHK(hipMemcpyAsync(h, f->kbuf, nb, hipMemcpyDeviceToHost, s));
+            hk = reinterpret_cast<int32_t*>(h) + kKbufHead;
             hp = hk + nsk;
-            HIPCHK(hipMemcpyAsync(hk, f->kout, nsk * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipMemcpyAsync(hp, f->pout, P.skel_ntotal * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            unsigned long long e = 0;
+            std::memcpy(&e, h, sizeof(e));
+            raise_err(f, e);
+        } else {
+            check_err(f, s);
         }
-        check_err(f, s);   // synchronizes: the ranks are on the host now
         phase(3, t0);
 
         // ---- the next level's active unknowns; this level's skeleton apply tables are built
@@ -1053,16 +1071,15 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         f->stats.sum_skel_n[lvl] = P.skel_ntotal;
         f->stats.sum_rank[lvl] = sum_rank;
         f->stats.max_rank[lvl] = max_rank;
-        next_active_set(P, LD.k.data(), LD.perm.data(), next, scr);
+        n_active = next_active_set(P, LD.k.data(), LD.perm.data(), scr);
         pending_skel = lvl;
-        active.swap(next);
         phase(5, t0);
     }
     if (pending_skel >= 0) finish_skel_tables(pending_skel);
     check_err(f, s);
     f->stats.levels = f->L;
-    f->stats.root_size = static_cast<int32_t>(active.size());
-    f->stats.n_active[f->L] = static_cast<int64_t>(active.size());
+    f->stats.root_size = static_cast<int32_t>(n_active);
+    f->stats.n_active[f->L] = n_active;
     f->ybuf = static_cast<double*>(f->dalloc(std::max<int64_t>(f->y_elems, 1) * sizeof(double)));
     if (f->ws_elems > 0) f->ws = static_cast<double*>(f->dalloc(f->ws_elems * sizeof(double)));
     int64_t bytes = 0;
