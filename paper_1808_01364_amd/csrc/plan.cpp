@@ -126,44 +126,54 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, int64_t n_a
         na = gi.N;
         // Every unknown is active (the leaf level): the groups are boxes of the grid,
         // enumerated directly in key order, each in ascending order.
-        P.gptr.clear();
-        P.gcls.clear();
-        scr.box_lo.clear();
-        scr.box_n.clear();
-        size_t at = 0;
-        for (int64_t K = 0; K < nkeys; ++K) {
-            int lo[3] = {1, 1, 1}, hi[3] = {1, 1, 1};
-            int64_t r = K;
-            int even = 0;
-            bool empty = false;
-            for (int k = 0; k < d; ++k) {
-                const int kk = static_cast<int>(r % KB);
-                r /= KB;
-                const int64_t c = kk >> 1;
-                if (kk & 1) {
-                    lo[k] = static_cast<int>(c * w + 1);
-                    hi[k] = static_cast<int>(std::min<int64_t>((c + 1) * w - 1, s));
-                } else {
-                    ++even;
-                    lo[k] = hi[k] = static_cast<int>(c * w);
-                    if (c * w < 1 || c * w > s) empty = true;
-                }
-                if (lo[k] > hi[k]) empty = true;
+        // per axis and key component kk: the interval's first point and length (0: empty)
+        std::vector<int32_t> ax_lo(KB), ax_n(KB);
+        for (int kk = 0; kk < KB; ++kk) {
+            const int64_t c = kk >> 1;
+            int64_t lo, hi;
+            if (kk & 1) {
+                lo = c * w + 1;
+                hi = std::min<int64_t>((c + 1) * w - 1, s);
+            } else {
+                lo = hi = c * w;
+                if (c * w < 1 || c * w > s) hi = lo - 1;
             }
-            if (empty) continue;
-            scr.key2g[K] = ngroups++;
-            P.gptr.push_back(static_cast<int32_t>(at));
-            P.gcls.push_back(static_cast<int8_t>(even));
-            int64_t cnt = 1;
-            for (int k = 0; k < 3; ++k) {
-                scr.box_lo.push_back(lo[k]);
-                scr.box_n.push_back(hi[k] - lo[k] + 1);
-                cnt *= hi[k] - lo[k] + 1;
-            }
-            at += static_cast<size_t>(cnt);
+            ax_lo[kk] = static_cast<int32_t>(lo);
+            ax_n[kk] = static_cast<int32_t>(std::max<int64_t>(hi - lo + 1, 0));
         }
-        if (static_cast<int64_t>(at) != na) throw std::logic_error("leaf-level groups do not cover the grid");
-        P.gptr.push_back(static_cast<int32_t>(na));
+        const int K1 = d > 1 ? KB : 1, K2 = d > 2 ? KB : 1;
+        const int64_t ng_max = nkeys;
+        P.gptr.resize(ng_max + 1);
+        P.gcls.resize(ng_max);
+        scr.box_lo.resize(3 * ng_max);
+        scr.box_n.resize(3 * ng_max);
+        int64_t at = 0;
+        for (int k2 = 0; k2 < K2; ++k2)
+            for (int k1 = 0; k1 < K1; ++k1)
+                for (int k0 = 0; k0 < KB; ++k0) {
+                    const int n0 = ax_n[k0], n1 = d > 1 ? ax_n[k1] : 1, n2 = d > 2 ? ax_n[k2] : 1;
+                    if (n0 == 0 || n1 == 0 || n2 == 0) continue;
+                    const int64_t K = k0 + static_cast<int64_t>(KB) * (k1 + static_cast<int64_t>(KB) * k2);
+                    const int g = ngroups++;
+                    scr.key2g[K] = g;
+                    P.gptr[g] = static_cast<int32_t>(at);
+                    P.gcls[g] = static_cast<int8_t>(((k0 & 1) == 0) + (d > 1 && (k1 & 1) == 0) + (d > 2 && (k2 & 1) == 0));
+                    int32_t* bl = scr.box_lo.data() + 3 * g;
+                    int32_t* bn = scr.box_n.data() + 3 * g;
+                    bl[0] = ax_lo[k0];
+                    bl[1] = d > 1 ? ax_lo[k1] : 1;
+                    bl[2] = d > 2 ? ax_lo[k2] : 1;
+                    bn[0] = n0;
+                    bn[1] = n1;
+                    bn[2] = n2;
+                    at += static_cast<int64_t>(n0) * n1 * n2;
+                }
+        P.gptr.resize(ngroups + 1);
+        P.gcls.resize(ngroups);
+        scr.box_lo.resize(3 * static_cast<size_t>(ngroups));
+        scr.box_n.resize(3 * static_cast<size_t>(ngroups));
+        if (at != na) throw std::logic_error("leaf-level groups do not cover the grid");
+        P.gptr[ngroups] = static_cast<int32_t>(na);
         // the groups' unknowns now, or later (fill_leaf_lists) when the device writes the
         // cells' frontal unknowns itself
         P.dofs_on_device = device_tables;
@@ -357,6 +367,13 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, int64_t n_a
 
     // ---- batched descriptors of the cells ----
     const bool banded = leaf_interior_banded(d, level, root, P.w);
+    // (sums in locals: the table appends below would otherwise force them through memory)
+    double front_bytes = 0.0, flops = 0.0, elim_flops = 0.0, apply_bytes = 0.0;
+    int64_t ext_elems = P.ext_elems;
+    double bw = 1.0, leaf_int = 1.0;
+    for (int k = 1; k < d; ++k) bw *= (leaf - 1);
+    for (int k = 0; k < d; ++k) leaf_int *= (leaf - 1);
+    P.cell_ref.reserve(ncells);
     for (int64_t ci = 0; ci < ncells; ++ci) {
         P.cell_ref.push_back(CellRef{P.c_foff[ci], P.c_ld[ci], P.c_nI[ci], P.c_nf[ci], P.c_dptr[ci]});
         const int nf = P.c_nf[ci];
@@ -376,35 +393,36 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, int64_t n_a
             }
             double band = 0.0;
             for (int j0 = 0; j0 < nI; j0 += 16) band += std::min(16, nI - j0) * (std::min(32, nI - j0) + 0.0);
-            P.alg_front_bytes += 8.0 * (band + static_cast<double>(nB) * nf);
+            front_bytes += 8.0 * (band + static_cast<double>(nB) * nf);
         } else {
             for (int c0 = 0; c0 < nf; c0 += 64)
                 for (int r0 = 0; r0 < nf; r0 += 64) P.tiles.push_back(Tile{cc, r0, c0, 0});
-            P.alg_front_bytes += 8.0 * static_cast<double>(nf) * nf;
+            front_bytes += 8.0 * static_cast<double>(nf) * nf;
         }
         if (nI > 0) {
             P.cell_potrf.push_back(FrontDesc{P.c_foff[ci], P.c_ld[ci], nf, nI, static_cast<int32_t>(ci),
-                                             static_cast<int32_t>(P.ext_elems), 0});
-            P.ext_elems += (nI + 15) / 16;
+                                             static_cast<int32_t>(ext_elems), 0});
+            ext_elems += (nI + 15) / 16;
             const double a = nI, b = nB;
-            P.flops += a * a * a / 3.0 + a * a * b + a * b * b;
+            flops += a * a * a / 3.0 + a * a * b + a * b * b;
             // a leaf interior (the whole (m-1)^d grid of a leaf cell) is banded with bandwidth
             // (m-1)^(d-1) in natural order: the method needs only the banded work and words
             double lwords;
-            double bw = 1.0;
-            for (int k = 1; k < d; ++k) bw *= (leaf - 1);
-            double leaf_int = 1.0;
-            for (int k = 0; k < d; ++k) leaf_int *= (leaf - 1);
             if (level == 0 && !root && a == leaf_int && bw < a) {
-                P.alg_elim_flops += a * bw * bw + 2.0 * a * bw * b + b * b * a;
+                elim_flops += a * bw * bw + 2.0 * a * bw * b + b * b * a;
                 lwords = a * (bw + 1.0);
             } else {
-                P.alg_elim_flops += a * a * a / 3.0 + a * a * b + a * b * b;
+                elim_flops += a * a * a / 3.0 + a * a * b + a * b * b;
                 lwords = a * (a + 1.0) / 2.0;
             }
-            P.alg_apply_cell_bytes += 8.0 * (lwords + a * b) + 8.0 * (2.0 * a + b);
+            apply_bytes += 8.0 * (lwords + a * b) + 8.0 * (2.0 * a + b);
         }
     }
+    P.alg_front_bytes += front_bytes;
+    P.flops += flops;
+    P.alg_elim_flops += elim_flops;
+    P.alg_apply_cell_bytes += apply_bytes;
+    P.ext_elems = ext_elems;
 
     // ---- extend-add sources from the children (level >= 1) ----
     const int W = 1 << d;
