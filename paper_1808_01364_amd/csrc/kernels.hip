@@ -107,13 +107,10 @@ __device__ __forceinline__ void wg_potrf_partial(double* __restrict__ A, int ld,
     double* Li = smem + 16 * 17;                           // inverse of the diagonal block
     int* tnz = reinterpret_cast<int*>(smem + 2 * 16 * 17); // kPotrfMaxTiles flags
     double* Pl = smem + kPotrfSmemFixed;
-    for (int j0 = 0; j0 < p; j0 += 16) {
-        const int jb = min(16, p - j0);
-        const int j1 = j0 + jb;
-        const int m = n - j1;       // rows below the diagonal block
-        const int mi = p - j1;      // pivot columns still to come
-        // (1) the diagonal block is factored and inverted by wave 0 in registers (lane i < 16
-        //     holds row i of the block; rows jb..15 are padded with the identity).
+    // the diagonal block at c0 is factored and inverted by wave 0 in registers (lane i < 16
+    // holds row i of the block; rows past the last pivot are padded with the identity)
+    auto factor_diag = [&](int c0) {
+        const int j0 = c0, jb = min(16, p - c0);
         if (wave == 0) {
             double a[16], li[16];
 #pragma unroll
@@ -135,6 +132,58 @@ __device__ __forceinline__ void wg_potrf_partial(double* __restrict__ A, int ld,
                 }
             }
         }
+    };
+    // one 16 x 16 tile (ti, tj) of the update A[j1:n, j1:p] -= P P[0:mi]^T (lower part) after the
+    // panel at j0 (jb columns)
+    auto update_tile = [&](int j0, int jb, int ti, int tj, bool lds_panel) {
+        const int j1 = j0 + jb, m = n - j1, mi = p - j1;
+        const int ra = ti * 16 + (lane & 15);
+        const int rb = tj * 16 + (lane & 15);
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            const int k = kk + (lane >> 4);
+            double av = 0.0, bv = 0.0;
+            if (k < jb) {
+                if (lds_panel) {
+                    if (ra < m) av = Pl[ra * 17 + k];
+                    if (rb < m) bv = Pl[rb * 17 + k];
+                } else {
+                    if (ra < m) av = A[(j1 + ra) + static_cast<size_t>(j0 + k) * ld];
+                    if (rb < m) bv = A[(j1 + rb) + static_cast<size_t>(j0 + k) * ld];
+                }
+            }
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+        // lane holds D[lane/16 + 4 q][lane % 16], q = 0..3
+        const int col = tj * 16 + (lane & 15);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = ti * 16 + (lane >> 4) + 4 * q;
+            if (row < m && col < mi && row >= col) A[(j1 + row) + static_cast<size_t>(j1 + col) * ld] -= acc[q];
+        }
+    };
+    // Right-looking over 16-column blocks with look-ahead: after the panel of a block, its
+    // update first covers the next block column; then wave 0 factors the next diagonal block
+    // while the other waves update the rest. Every tile is computed as without look-ahead.
+    int jp = -1, jbp = 0, ntp = 0, ntip = 0;   // the previous block and its update's tile counts
+    bool ldsp = false;
+    for (int j0 = 0;; j0 += 16) {
+        if (wave == 0) {
+            if (j0 < p) factor_diag(j0);
+        } else if (jp >= 0) {
+            for (int t = wave - 1; t < ntp * ntip; t += kWaves - 1) {
+                const int tj = t % ntip, ti = t / ntip;
+                if (tj == 0 || ti < tj || !tnz[ti] || !tnz[tj]) continue;
+                update_tile(jp, jbp, ti, tj, ldsp);
+            }
+        }
+        __syncthreads();
+        if (j0 >= p) break;
+        const int jb = min(16, p - j0);
+        const int j1 = j0 + jb;
+        const int m = n - j1;       // rows below the diagonal block
+        const int mi = p - j1;      // pivot columns still to come
         // (2) panel: the rows below the diagonal block solve  x L_blk^T = a.
         const bool lds_panel = (m <= panel_cap);
         const int nt = (m + 15) >> 4;
@@ -172,39 +221,19 @@ __device__ __forceinline__ void wg_potrf_partial(double* __restrict__ A, int ld,
                 if (tnz[t]) e = min(p, j1 + 16 * (t + 1));
             ext[j0 >> 4] = e;
         }
-        // (3) update of the remaining pivot columns: A[j1:n, j1:p] -= P P[0:mi]^T (lower part)
+        // (3) update of the remaining pivot columns A[j1:n, j1:p] -= P P[0:mi]^T: here the next
+        //     block column (tj = 0), the rest at the top of the next round
         const int nti = (mi + 15) >> 4;
-        for (int t = wave; t < nt * nti; t += kWaves) {
-            const int tj = t % nti, ti = t / nti;
-            if (ti < tj || !tnz[ti] || !tnz[tj]) continue;
-            const int ra = ti * 16 + (lane & 15);
-            const int rb = tj * 16 + (lane & 15);
-            v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int kk = 0; kk < 16; kk += 4) {
-                const int k = kk + (lane >> 4);
-                double av = 0.0, bv = 0.0;
-                if (k < jb) {
-                    if (lds_panel) {
-                        if (ra < m) av = Pl[ra * 17 + k];
-                        if (rb < m) bv = Pl[rb * 17 + k];
-                    } else {
-                        if (ra < m) av = A[(j1 + ra) + static_cast<size_t>(j0 + k) * ld];
-                        if (rb < m) bv = A[(j1 + rb) + static_cast<size_t>(j0 + k) * ld];
-                    }
-                }
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-            }
-            // lane holds D[lane/16 + 4 q][lane % 16], q = 0..3
-            const int col = tj * 16 + (lane & 15);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int row = ti * 16 + (lane >> 4) + 4 * q;
-                if (row < m && col < mi && row >= col)
-                    A[(j1 + row) + static_cast<size_t>(j1 + col) * ld] -= acc[q];
-            }
+        if (nti > 0) {
+            for (int ti = wave; ti < nt; ti += kWaves)
+                if (tnz[ti] && tnz[0]) update_tile(j0, jb, ti, 0, lds_panel);
+            __syncthreads();
         }
-        __syncthreads();
+        jp = j0;
+        jbp = jb;
+        ntp = nt;
+        ntip = nti;
+        ldsp = lds_panel;
     }
     // (4) the Schur complement, S -= W^T W over the p pivots, lower tiles on the matrix cores.
     //     16-column blocks of W^T are staged in LDS (when its rows fit the panel buffer);
