@@ -1136,8 +1136,21 @@ __global__ __launch_bounds__(256) void k_chol_lead(const FrontDesc* __restrict__
     if (p <= lds_pmax) {
         const int ls = p | 1;
         double* D = smem + kPotrfSmemFixed;
-        for (int j = wave; j < p; j += kWaves)
-            for (int i = j + lane; i < p; i += 64) D[i + j * ls] = A[i + static_cast<size_t>(j) * ld];
+        // lower triangle into LDS, eight loads in flight per thread before their stores
+        const int pp = p * p;
+        for (int e0 = threadIdx.x; e0 < pp; e0 += 8 * kWG) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * kWG, i = e % p, j = e / p;
+                v[u] = (e < pp && i >= j) ? A[i + static_cast<size_t>(j) * ld] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * kWG, i = e % p, j = e / p;
+                if (e < pp && i >= j) D[i + j * ls] = v[u];
+            }
+        }
         __syncthreads();
         wg_potrf_partial(D, ls, p, p, smem, 0, err, code, ex, lv);
         for (int j = wave; j < p; j += kWaves)
