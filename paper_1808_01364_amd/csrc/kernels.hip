@@ -860,9 +860,11 @@ __global__ __launch_bounds__(256) void k_potrf_batch(const FrontDesc* __restrict
 //   W^T_J = (X_J - W^T_J-1 L_J,J-1^T) Li_J^T        (16 boundary rows per wave and tile)
 // then S = A_BB - W^T W on the matrix cores, both triangles written. These are the factors
 // of the dense partial Cholesky; only the structural zeros outside the band are skipped.
-// LDS (dynamic): L_J,J-1 double buffer (2 x 272), Li_J (272), per wave a transfer tile
-// (272) and tpw tiles of W^T_J-1 (tpw x 272), then two buffers of (2 + row tiles) x 272 for
-// the next block's operands, loaded by waves 1..3 while wave 0 factors the current block.
+// LDS (dynamic): L_J,J-1 double buffer (2 x 272), Li_J and L_JJ by parity (4 x 272), per
+// wave a transfer tile (272) and tpw tiles of W^T_J-1 (tpw x 272), then two buffers of
+// (2 + row tiles) x 272 for the next block's operands, loaded by waves 1..3 while wave 0
+// factors the current block. Waves 1..3 also store block J's L_JJ and Li_J from LDS during
+// round J + 1, so that wave 0 only factors.
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_leaf_elim(const FrontDesc* __restrict__ desc, double* __restrict__ pool,
                                                    double* __restrict__ linv, int tpw, int level,
@@ -877,12 +879,13 @@ __global__ __launch_bounds__(256) void k_leaf_elim(const FrontDesc* __restrict__
     const int lr = lane & 15, lh = lane >> 4;
     const int ntile = (m + 15) / 16;
     double* Lsb = smem;                 // [2][TS]: L_J,J-1 by parity of J
-    double* Lis = smem + 2 * TS;        // Li_J, row-major
-    double* Tw = smem + 3 * TS + wave * TS;                  // this wave's transfer tile
-    double* Pw = smem + 7 * TS + static_cast<size_t>(wave) * tpw * TS;   // this wave's W^T_J-1 tiles
+    double* Lis0 = smem + 2 * TS;       // [2][TS]: Li_J by parity of J, row-major
+    double* Ljj0 = smem + 4 * TS;       // [2][TS]: L_JJ by parity of J, row-major
+    double* Tw = smem + 6 * TS + wave * TS;                  // this wave's transfer tile
+    double* Pw = smem + 10 * TS + static_cast<size_t>(wave) * tpw * TS;  // this wave's W^T_J-1 tiles
     // operands of block J, loaded during the previous block by waves 1..3 (by parity of J):
     // D_JJ (row-major), D_J+1,J (row-major) and the X_J row tiles (row-major per tile)
-    double* Buf = smem + (7 + 4 * tpw) * TS;
+    double* Buf = smem + (10 + 4 * tpw) * TS;
     const int bufsz = (2 + ntile) * TS;
     double* lv = linv + static_cast<size_t>(fd.ext) * 256;
     const unsigned long long code = err_code(level, 0, fd.id);
@@ -908,8 +911,8 @@ __global__ __launch_bounds__(256) void k_leaf_elim(const FrontDesc* __restrict__
             if (t >= ntl) break;
             int ti, tj;
             tile_ij(t, ti, tj);
-            const double* Pa = smem + 7 * TS + static_cast<size_t>(ti & 3) * tpw * TS + (ti >> 2) * TS;
-            const double* Pb = smem + 7 * TS + static_cast<size_t>(tj & 3) * tpw * TS + (tj >> 2) * TS;
+            const double* Pa = smem + 10 * TS + static_cast<size_t>(ti & 3) * tpw * TS + (ti >> 2) * TS;
+            const double* Pb = smem + 10 * TS + static_cast<size_t>(tj & 3) * tpw * TS + (tj >> 2) * TS;
 #pragma unroll
             for (int kk = 0; kk < 16; kk += 4)
                 sacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(Pa[lr * 17 + kk + lh], Pb[lr * 17 + kk + lh], sacc[u],
@@ -932,12 +935,26 @@ __global__ __launch_bounds__(256) void k_leaf_elim(const FrontDesc* __restrict__
             B[tile * TS + r * 17 + c] = v;
         }
     };
+    // block K's L_KK (lower part) and Li_K from LDS to the frontal and linv, by waves 1..3
+    auto store_diag = [&](int K) {
+        const int k0 = 16 * K, kb = min(16, p - k0);
+        const double* Lk = Ljj0 + (K & 1) * TS;
+        const double* Ik = Lis0 + (K & 1) * TS;
+        for (int e = threadIdx.x - 64; e < 256; e += kWG - 64) {
+            const int r = e >> 4, c = e & 15;
+            if (r < kb && c <= r) A[(k0 + r) + static_cast<size_t>(k0 + c) * ld] = Lk[r * 17 + c];
+            lv[K * 256 + e] = Ik[r * 17 + c];
+        }
+        if (threadIdx.x == 64) ext[fd.ext + K] = min(p, k0 + 32);
+    };
     prefetch(0, threadIdx.x, kWG);
     __syncthreads();
     for (int J = 0; J < nb; ++J) {
         const int j0 = 16 * J, jb = min(16, p - j0);
         const double* Lprev = Lsb + (J & 1) * TS;
         const double* B = Buf + (J & 1) * bufsz;
+        double* Lis = Lis0 + (J & 1) * TS;
+        double* Ljj = Ljj0 + (J & 1) * TS;
         if (wave == 0) {
             double a[16], li[16];
 #pragma unroll
@@ -965,21 +982,16 @@ __global__ __launch_bounds__(256) void k_leaf_elim(const FrontDesc* __restrict__
                 __builtin_amdgcn_wave_barrier();
             }
             wave_chol_inv16(a, li, lane, err, code);
-            if (lane < jb) {
-#pragma unroll
-                for (int c = 0; c < 16; ++c)
-                    if (c <= lane) A[(j0 + lane) + static_cast<size_t>(j0 + c) * ld] = a[c];
-            }
             if (lane < 16) {
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
                     Lis[i * 17 + lane] = li[i];
-                    lv[J * 256 + i * 16 + lane] = li[i];
+                    Ljj[lane * 17 + i] = a[i];
                 }
             }
-            if (lane == 0) ext[fd.ext + J] = min(p, j0 + 32);
         } else {
             if (inc && J > 0) syrk_step();
+            if (J > 0) store_diag(J - 1);
             if (J + 1 < nb) prefetch(J + 1, threadIdx.x - 64, kWG - 64);
         }
         __syncthreads();
@@ -1040,6 +1052,7 @@ __global__ __launch_bounds__(256) void k_leaf_elim(const FrontDesc* __restrict__
         }
         __syncthreads();
     }
+    if (wave != 0 && nb > 0) store_diag(nb - 1);
     // S = A_BB - W^T W, each lower element written with its mirror by one lane (S stays
     // exactly symmetric)
     double* S = A + p + static_cast<size_t>(p) * ld;

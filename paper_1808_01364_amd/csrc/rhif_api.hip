@@ -803,7 +803,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                 const int nt = (mmax + 15) / 16;
                 const int tpw = (nt + 3) / 4;
                 const size_t lds0 =
-                    static_cast<size_t>((7 + 4 * std::max(tpw, 1) + 2 * (2 + nt)) * 16 * 17) * sizeof(double);
+                    static_cast<size_t>((10 + 4 * std::max(tpw, 1) + 2 * (2 + nt)) * 16 * 17) * sizeof(double);
                 KTIMED(f, s, cls, P.alg_elim_flops, 0.0,
                        hipLaunchKernelGGL(k_leaf_elim, dim3(ncell), dim3(256), lds0, s, LD.potrf, LD.front, linv,
                                           std::max(tpw, 1), lvl, f->err, LD.ext));
