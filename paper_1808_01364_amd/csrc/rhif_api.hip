@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <array>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -89,6 +90,25 @@ struct HostCache {
         if (!up_ev[slot]) HIPCHK(hipEventCreateWithFlags(&up_ev[slot], hipEventDisableTiming));
         HIPCHK(hipEventRecord(up_ev[slot], s));
         up_pending[slot] = true;
+    }
+    // per device: a stream for table uploads that may overlap the kernels of the factor's
+    // stream, and events that order them (round robin)
+    std::vector<hipStream_t> side;
+    std::vector<std::array<hipEvent_t, 4>> side_ev;
+    std::vector<int> side_next;
+    hipStream_t side_stream(int dev, hipEvent_t& ev) {
+        if (static_cast<int>(side.size()) <= dev) {
+            side.resize(dev + 1, nullptr);
+            side_ev.resize(dev + 1);
+            side_next.resize(dev + 1, 0);
+        }
+        if (!side[dev]) {
+            HIPCHK(hipStreamCreateWithFlags(&side[dev], hipStreamNonBlocking));
+            for (auto& e : side_ev[dev]) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        }
+        ev = side_ev[dev][side_next[dev]];
+        side_next[dev] = (side_next[dev] + 1) % 4;
+        return side[dev];
     }
     char* get_down(size_t b) {
         if (b > down_bytes) {
@@ -561,6 +581,26 @@ char* upload(rhif_factor_s* f, Packer& pk, hipStream_t s) {
     return dst;
 }
 
+// The same on the upload stream, so that the copy overlaps the kernels already queued on s;
+// s waits for it before anything queued after this call. (The destination is fresh memory
+// of the handle, so the copy depends on nothing queued before.)
+char* upload_side(rhif_factor_s* f, Packer& pk, hipStream_t s) {
+    if (pk.total == 0) return nullptr;
+    HostCache& hc = host_cache();
+    hipEvent_t ev = nullptr;
+    hipStream_t cs = hc.side_stream(f->device, ev);
+    int slot = 0;
+    char* h = hc.get_up(pk.total, slot);
+    for (size_t e = 0; e < pk.parts.size(); ++e)
+        if (pk.parts[e].second) std::memcpy(h + pk.offs[e], pk.parts[e].first, pk.parts[e].second);
+    char* dst = static_cast<char*>(f->dalloc(pk.total));
+    HIPCHK(hipMemcpyAsync(dst, h, pk.total, hipMemcpyHostToDevice, cs));
+    hc.fence(slot, cs);
+    HIPCHK(hipEventRecord(ev, cs));
+    HIPCHK(hipStreamWaitEvent(s, ev, 0));
+    return dst;
+}
+
 int panel_cap_for(int nmax, int reserved_doubles) {
     const int cap = (kLdsBudgetDoubles - reserved_doubles - rhif::kPotrfSmemFixed) / 17;
     return std::max(0, std::min(cap, nmax));
@@ -688,7 +728,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         {
             Packer pk;
             const size_t o_ad = pk.add(sk_ad), o_dofs = pk.add(sk_dofs), o_gad = pk.add(gad), o_perm = pk.add(LD.perm);
-            char* T = upload(f, pk, s);
+            char* T = upload_side(f, pk, s);
             if (T) {
                 LD.skel_ad = view<ApplyDesc>(T, o_ad);
                 LD.skeldofs = view<int32_t>(T, o_dofs);
@@ -905,7 +945,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                          o_cgo = pk.add(P.c_goff), o_sad = pk.add(P.sep_apply),
                          o_gat = pk.add(P.gather), o_sdofs = pk.add(P.sep_dofs),
                          o_gsc = pk.add(P.gslot_cnt), o_gsl = pk.add(P.gslot_cell), o_gso = pk.add(P.gslot_off);
-            char* T = upload(f, pk, s);
+            char* T = upload_side(f, pk, s);
             LD.gslot_cnt = view<int32_t>(T, o_gsc);
             LD.gslot_cell = view<int32_t>(T, o_gsl);
             LD.gslot_off = view<int32_t>(T, o_gso);
