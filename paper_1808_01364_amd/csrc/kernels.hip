@@ -761,21 +761,32 @@ __global__ __launch_bounds__(256) void k_front_extend(const Tile* __restrict__ t
     }
     __syncthreads();
     if (!prow) return;
-    for (int cq = threadIdx.x >> 6; cq < ncol; cq += 4) {
-        const int q = t.c0 + cq;
-        const int32_t* sq = qs + cq * 2 * W;
-        double v = 0.0;
-        int b = 0;
-        for (int a = 0; a < np; ++a) {
-            // both source lists are sorted by child index
-            while (b < W) {
-                const int cb = sq[2 * b];
-                if (cb < 0 || cb >= pc[a]) break;
-                ++b;
+    // four columns per thread and pass, every load of the pass issued before the sums; a
+    // child holds the column at most once, and the shares are added in the row's child order
+    const int wave = threadIdx.x >> 6;
+    for (int cq0 = wave; cq0 < ncol; cq0 += 16) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int cq = cq0 + 4 * u;
+            v[u] = 0.0;
+            if (cq >= ncol) continue;
+            const int32_t* sq = qs + cq * 2 * W;
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                if (a >= np) break;
+                int off = -1;
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+                    if (b < W && sq[2 * b] == pc[a]) off = sq[2 * b + 1];
+                if (off >= 0) v[u] += Fc[coff[a] + static_cast<size_t>(off) * cld[a]];
             }
-            if (b < W && sq[2 * b] == pc[a]) v += Fc[coff[a] + static_cast<size_t>(sq[2 * b + 1]) * cld[a]];
         }
-        F[cr.off + p + static_cast<size_t>(q) * cr.ld] = v;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int cq = cq0 + 4 * u;
+            if (cq < ncol) F[cr.off + p + static_cast<size_t>(t.c0 + cq) * cr.ld] = v[u];
+        }
     }
 }
 
