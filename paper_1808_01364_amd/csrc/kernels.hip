@@ -684,9 +684,27 @@ __global__ __launch_bounds__(256) void k_front_csr(const Tile* __restrict__ tile
     const int p = t.r0 + lane;
     const bool prow = lane < nrow && p < nf;
     int i = 0, xi[3], alo[3], ahi[3];
+    // the row's matrix entries (a stencil row has at most 2d + 1 <= 7), held in registers;
+    // longer rows are searched in memory
+    int rc[7];
+    double rv[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        rc[k] = -1;
+        rv[k] = 0.0;
+    }
+    bool longrow = false;
     if (prow) {
         i = cdofs[cr.dptr + p];
         unknown_cells(i, d, s, w, nc1, xi, alo, ahi);
+        const int e0 = row_ptr[i], ne = row_ptr[i + 1] - e0;
+        longrow = ne > 7;
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+            if (k < ne) {
+                rc[k] = col[e0 + k];
+                rv[k] = val[e0 + k];
+            }
     }
     __syncthreads();
     if (!prow) return;
@@ -713,11 +731,17 @@ __global__ __launch_bounds__(256) void k_front_csr(const Tile* __restrict__ tile
             }
             if (ok && own == t.cell) {
                 const int j = ci[0];
-                for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
-                    if (col[e] == j) {
-                        v = val[e];
-                        break;
-                    }
+                if (longrow) {
+                    for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+                        if (col[e] == j) {
+                            v = val[e];
+                            break;
+                        }
+                } else {
+#pragma unroll
+                    for (int k = 6; k >= 0; --k)
+                        if (rc[k] == j) v = rv[k];
+                }
             }
         }
         F[cr.off + p + static_cast<size_t>(q) * cr.ld] = v;
