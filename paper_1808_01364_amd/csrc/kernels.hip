@@ -2215,19 +2215,50 @@ __global__ __launch_bounds__(256) void k_apply_trsv_dn(const ApplyDesc* __restri
 //   up:   z_g -= sum of the cells' y shares; [z_g <- L_g^-1 z_g];
 //         [z_r -= T^T z_s; z_r <- L~^-1 z_r; z_s -= W~^T z_r]
 //   down: [z_r -= W~ z_s; z_r <- L~^-T z_r; z_s -= T z_r]; [z_g <- L_g^-T z_g]
+// T (k x nr, column-major) and G's off-diagonal block G[nr + c, a] (as gk[c + a k]) of a
+// skeletonized group into LDS, eight loads in flight per thread.
+__device__ __forceinline__ void stage_tg(const double* __restrict__ T, const double* __restrict__ G, int n, int nr,
+                                         int k, double* tk, double* gk) {
+    const int kn = k * nr;
+    for (int e0 = threadIdx.x; e0 < 2 * kn; e0 += 8 * kWG) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kWG;
+            v[u] = 0.0;
+            if (e < kn) v[u] = T[e];
+            else if (e < 2 * kn) {
+                const int f = e - kn, c = f % k, a = f / k;
+                v[u] = G[(nr + c) + static_cast<size_t>(a) * n];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kWG;
+            if (e < kn) tk[e] = v[u];
+            else if (e < 2 * kn) gk[e - kn] = v[u];
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_apply_group_up(const GroupApplyDesc* __restrict__ gd,
                                                         const int32_t* __restrict__ gdofs,
                                                         const double* __restrict__ ybuf, double* __restrict__ z,
                                                         const double* __restrict__ Lg, const double* __restrict__ lig,
                                                         const double* __restrict__ Gp, const double* __restrict__ Tp,
                                                         const double* __restrict__ skli,
-                                                        const int32_t* __restrict__ perm) {
+                                                        const int32_t* __restrict__ perm, int tkcap) {
     extern __shared__ double smem[];
     const GroupApplyDesc g = gd[blockIdx.x];
     const int n = g.n, tid = threadIdx.x;
     const int np = 16 * ((n + 15) / 16);
     double* zl = smem;
     double* zp = smem + np;
+    // T and G's off-diagonal block staged in LDS (when the level's largest fit), loaded first
+    const bool stg = g.nr > 0 && tkcap > 0;
+    double* tk = smem + 2 * np;
+    double* gk = tk + g.k * g.nr;
+    if (stg) stage_tg(Tp + g.toff, Gp + g.goff, n, g.nr, g.k, tk, gk);
     const int32_t* di = gdofs + g.dofs;
     const int64_t* yoff = gd[blockIdx.x].yoff;   // indexed through memory, not a private copy
     for (int t = tid; t < np; t += kWG) {
@@ -2245,7 +2276,7 @@ __global__ __launch_bounds__(256) void k_apply_group_up(const GroupApplyDesc* __
         const int32_t* pv = perm + g.poff;
         for (int q = tid; q < np; q += kWG) zp[q] = (q < nr) ? zl[pv[k + q]] : (q < n ? zl[pv[q - nr]] : 0.0);
         __syncthreads();
-        const double* T = Tp + g.toff;
+        const double* T = stg ? tk : Tp + g.toff;
         for (int a = tid; a < nr; a += kWG) {
             double acc = 0.0;
             for (int c = 0; c < k; ++c) acc += T[c + static_cast<size_t>(a) * k] * zp[nr + c];
@@ -2256,7 +2287,10 @@ __global__ __launch_bounds__(256) void k_apply_group_up(const GroupApplyDesc* __
         wg_trsv_fwd<false>(G, n, nr, skli + g.skli, zp, nullptr);
         for (int c = tid; c < k; c += kWG) {
             double acc = 0.0;
-            for (int a = 0; a < nr; ++a) acc += G[(nr + c) + static_cast<size_t>(a) * n] * zp[a];
+            if (stg)
+                for (int a = 0; a < nr; ++a) acc += gk[c + a * k] * zp[a];
+            else
+                for (int a = 0; a < nr; ++a) acc += G[(nr + c) + static_cast<size_t>(a) * n] * zp[a];
             zp[nr + c] -= acc;
         }
         __syncthreads();
@@ -2271,13 +2305,17 @@ __global__ __launch_bounds__(256) void k_apply_group_dn(const GroupApplyDesc* __
                                                         const double* __restrict__ Lg, const double* __restrict__ lig,
                                                         const double* __restrict__ Gp, const double* __restrict__ Tp,
                                                         const double* __restrict__ skli,
-                                                        const int32_t* __restrict__ perm) {
+                                                        const int32_t* __restrict__ perm, int tkcap) {
     extern __shared__ double smem[];
     const GroupApplyDesc g = gd[blockIdx.x];
     const int n = g.n, tid = threadIdx.x;
     const int np = 16 * ((n + 15) / 16);
     double* zl = smem;
     double* zp = smem + np;
+    const bool stg = g.nr > 0 && tkcap > 0;
+    double* tk = smem + 2 * np;
+    double* gk = tk + g.k * g.nr;
+    if (stg) stage_tg(Tp + g.toff, Gp + g.goff, n, g.nr, g.k, tk, gk);
     const int32_t* di = gdofs + g.dofs;
     for (int t = tid; t < np; t += kWG) zl[t] = (t < n) ? z[di[t]] : 0.0;
     __syncthreads();
@@ -2289,13 +2327,17 @@ __global__ __launch_bounds__(256) void k_apply_group_dn(const GroupApplyDesc* __
         const double* G = Gp + g.goff;
         for (int a = tid; a < nr; a += kWG) {
             double acc = 0.0;
-            const double* Ga = G + static_cast<size_t>(a) * n + nr;
-            for (int c = 0; c < k; ++c) acc += Ga[c] * zp[nr + c];
+            if (stg)
+                for (int c = 0; c < k; ++c) acc += gk[c + a * k] * zp[nr + c];
+            else {
+                const double* Ga = G + static_cast<size_t>(a) * n + nr;
+                for (int c = 0; c < k; ++c) acc += Ga[c] * zp[nr + c];
+            }
             zp[a] -= acc;
         }
         __syncthreads();
         wg_trsv_bwd<false>(G, n, nr, skli + g.skli, zp, nullptr);
-        const double* T = Tp + g.toff;
+        const double* T = stg ? tk : Tp + g.toff;
         for (int c = tid; c < k; c += kWG) {
             double acc = 0.0;
             for (int a = 0; a < nr; ++a) acc += T[c + static_cast<size_t>(a) * k] * zp[a];

@@ -54,10 +54,10 @@ __global__ void k_apply_gemv_up(const ApplyDesc* ad, const double* pool, const i
 __global__ void k_apply_gemv_dn(const ApplyDesc* ad, const double* pool, const int32_t* dofs, double* z);
 __global__ void k_apply_group_up(const GroupApplyDesc* gd, const int32_t* gdofs, const double* ybuf, double* z,
                                  const double* Lg, const double* lig, const double* Gp, const double* Tp,
-                                 const double* skli, const int32_t* perm);
+                                 const double* skli, const int32_t* perm, int tkcap);
 __global__ void k_apply_group_dn(const GroupApplyDesc* gd, const int32_t* gdofs, double* z, const double* Lg,
                                  const double* lig, const double* Gp, const double* Tp, const double* skli,
-                                 const int32_t* perm);
+                                 const int32_t* perm, int tkcap);
 __global__ void k_sep_gather(const GatherDesc* gd, const int32_t* dofs, const double* ybuf, double* z);
 __global__ void k_spmv_dot(int64_t N, const int32_t* rp, const int32_t* ci, const double* v, const double* p,
                            double* q, double* part);

@@ -187,6 +187,7 @@ struct LevelDev {
     rhif::GroupApplyDesc* grp_ad = nullptr;   // fused per-group apply (gather, L_g, skeleton)
     int32_t* permd = nullptr;                 // group-local pivot orders of the level's IDs
     int n_grp = 0, mn_grp = 0;
+    int tk_cap = 0;               // largest k (n - k) of the level's skeletonized groups, if staged
     int n_cell_ad = 0, n_sep_ad = 0, n_gather = 0, n_skel_ad = 0;
     size_t lds_cell = 0, lds_sep = 0, lds_skel = 0;
     // largest n_I / n_B of each block family (split apply when n_I is small enough)
@@ -318,6 +319,7 @@ private:
     size_t cached_ = 0;
 };
 
+constexpr int kGroupStageMax = 8192;   // doubles of T and G blocks a group apply stages in LDS
 constexpr int kKbufHead = 4;   // ints before the ID outputs: the 64-bit error word, padded
 
 struct rhif_factor_s {
@@ -618,6 +620,10 @@ void set_kernel_attributes() {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_skeletonize),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_apply_group_up),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_apply_group_dn),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_chol_lead),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_leaf_elim),
@@ -694,6 +700,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         std::vector<GroupApplyDesc>& gad = hc.gad;
         gad.assign(P.sep_desc.size(), GroupApplyDesc{});
         LD.mn_grp = 0;
+        LD.tk_cap = 0;
         {
             std::vector<int32_t>& skel_of = hc.skel_of;
             skel_of.assign(P.gptr.size(), -1);
@@ -723,6 +730,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                     }
                 }
                 LD.mn_grp = std::max(LD.mn_grp, sd.n);
+                LD.tk_cap = std::max(LD.tk_cap, x.k * x.nr);
             }
         }
         {
@@ -737,6 +745,8 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             }
         }
         LD.n_grp = static_cast<int>(gad.size());
+        // T and G's off-diagonal block of a group go through LDS when the largest fit
+        if (2 * LD.tk_cap > kGroupStageMax) LD.tk_cap = 0;
         LD.n_skel_ad = static_cast<int>(sk_ad.size());
         LD.lds_skel = apply_lds(sk_ad);
         apply_max(sk_ad, LD.mi_skel, LD.mb_skel);
@@ -1167,7 +1177,7 @@ bool group_ok(const LevelDev& LD) {
 }
 
 size_t group_lds(const LevelDev& LD) {
-    return static_cast<size_t>(2 * 16 * ((LD.mn_grp + 15) / 16)) * sizeof(double);
+    return static_cast<size_t>(2 * 16 * ((LD.mn_grp + 15) / 16) + 2 * LD.tk_cap) * sizeof(double);
 }
 
 // LDS of k_apply_band for interiors of up to mi unknowns.
@@ -1228,7 +1238,8 @@ void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
         if (group_ok(LD)) {
             KTIMED(f, s, RHIF_K_APPLY_GATHER, 0.0, LD.b_gather + LD.b_sep + LD.b_skel,
                    hipLaunchKernelGGL(rhif::k_apply_group_up, dim3(LD.n_grp), dim3(256), group_lds(LD), s, LD.grp_ad,
-                                      LD.sepdofs, f->ybuf, z, LD.lg, LD.li, LD.gp, LD.tp, LD.skli, LD.permd));
+                                      LD.sepdofs, f->ybuf, z, LD.lg, LD.li, LD.gp, LD.tp, LD.skli, LD.permd,
+                                      LD.tk_cap));
             continue;
         }
         if (LD.n_gather > 0)
@@ -1253,7 +1264,7 @@ void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
         if (group_ok(LD)) {
             KTIMED(f, s, RHIF_K_APPLY_GATHER, 0.0, LD.b_sep + LD.b_skel,
                    hipLaunchKernelGGL(rhif::k_apply_group_dn, dim3(LD.n_grp), dim3(256), group_lds(LD), s, LD.grp_ad,
-                                      LD.sepdofs, z, LD.lg, LD.li, LD.gp, LD.tp, LD.skli, LD.permd));
+                                      LD.sepdofs, z, LD.lg, LD.li, LD.gp, LD.tp, LD.skli, LD.permd, LD.tk_cap));
         } else {
             apply_down_block(f, LD.b_skel, LD.skel_ad, LD.n_skel_ad, LD.mi_skel, LD.mb_skel, LD.lds_skel, LD.gp,
                              LD.skli, LD.tp, LD.skeldofs, z, s);
