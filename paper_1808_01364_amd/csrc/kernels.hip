@@ -2375,6 +2375,16 @@ __global__ __launch_bounds__(256) void k_apply_gemv_up(const ApplyDesc* __restri
         const double* Wb = pool + d.off + nI + b;
         double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int i = q0;
+        // sixteen loads in flight, two rounds of the eight partial sums
+        for (; i + 15 < q1; i += 16) {
+            double x[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) x[u] = Wb[static_cast<size_t>(i + u) * ld];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] += x[u] * zI[i + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] += x[8 + u] * zI[i + 8 + u];
+        }
         for (; i + 7 < q1; i += 8) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) a[u] += Wb[static_cast<size_t>(i + u) * ld] * zI[i + u];
