@@ -125,7 +125,7 @@ def main():
         tc = time.perf_counter()
         t_fac.append(tb - ta)
         t_pcg.append(tc - tb)
-        kvs.append(F.stats()["kernels"].get(dom))
+        kvs.append(F.kernel_class(dom))
         if k + 1 < args.steps:
             F.close()
     torch.cuda.synchronize()
@@ -141,7 +141,8 @@ def main():
             kby += kv["bytes"]
             kl += kv["launches"]
     from paper_1808_01364_amd.prof_summary import CLASS_KERNEL, read_traffic
-    traffic = read_traffic(os.path.join(ROOT, "profiles", f"traffic_2d{P.s}_eps{P.eps:g}.txt"),
+    eps_tag = f"{P.eps:g}".replace("e-0", "e-")   # 1e-06 -> 1e-6, as the profile files are named
+    traffic = read_traffic(os.path.join(ROOT, "profiles", f"traffic_2d{P.s}_eps{eps_tag}.txt"),
                            CLASS_KERNEL.get(dom, ()))
     hbm_bound = dom in ("apply_up", "apply_down", "apply_gather", "spmv", "vector", "front_csr", "front_extend")
     if hbm_bound:

@@ -262,6 +262,19 @@ class Factor:
                                                    flops=s.kernel_flops[c], bytes=s.kernel_bytes[c])
                              for c in range(NUM_KCLASS) if s.kernel_launches[c] > 0})
 
+    def kernel_class(self, name: str):
+        """The HIP-event timing of one kernel class (dict of ms, launches, flops, bytes, or None):
+        the part of stats() a timing loop needs, without building the whole dictionary."""
+        s = getattr(self, "_stats_buf", None)
+        if s is None:
+            s = self._stats_buf = Stats()
+        _check(self._lib.rhif_stats(self.handle, ctypes.byref(s)))
+        c = KCLASS_NAMES.index(name)
+        if s.kernel_launches[c] <= 0:
+            return None
+        return dict(ms=s.kernel_ms[c], launches=s.kernel_launches[c], flops=s.kernel_flops[c],
+                    bytes=s.kernel_bytes[c])
+
     def skeletons(self, level: int) -> Skeletons:
         ng = ctypes.c_int32()
         tot = ctypes.c_int64()
