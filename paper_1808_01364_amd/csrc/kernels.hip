@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "devstructs.hpp"
 #include "kernels.hpp"
@@ -318,10 +319,11 @@ __device__ __forceinline__ void wg_potrf_partial(double* __restrict__ A, int ld,
 // columns not chosen yet, the largest 2-norm over rows j.. (recomputed from the current
 // values every step; ties to the lowest current position) and continues while
 // R_jj > eps R_11. Returns the rank k; row i <= j of column perm[j] then holds R[i][j].
-// part: 2 * 256 * ceil(n / cw) doubles; red: 2 doubles.
+// part: 2 * 256 * ceil(n / cw) doubles.
 // ---------------------------------------------------------------------------------------
+template <int UR>
 __device__ __forceinline__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int r, int n, double eps, int* pos,
-                                            int* perm, double* part, double* red) {
+                                            int* perm, double* part) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int cw = 1;
     while (cw < n && cw < 64) cw <<= 1;
@@ -355,41 +357,35 @@ __device__ __forceinline__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int
     double r11 = 0.0;
     int k = 0;
     for (int j = 0; j < kmax; ++j) {
-        // (a) pivot among the columns with pos >= j, by wave 0
-        if (wave == 0) {
-            double best = -1.0;
-            int bpos = 0x7fffffff, bc = -1;
-            for (int c = lane; c < n; c += 64) {
-                const int pp = pos[c];
-                if (pp < j) continue;
-                const int blk = c / cw, sl = c % cw;
-                double v = 0.0;
-                for (int q = 0; q < nrc; ++q) v += pn[blk * kWG + q * cw + sl];
-                if (v > best || (v == best && pp < bpos)) {
-                    best = v;
-                    bpos = pp;
-                    bc = c;
-                }
-            }
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ob = __shfl_xor(best, off, 64);
-                const int op = __shfl_xor(bpos, off, 64);
-                const int oc = __shfl_xor(bc, off, 64);
-                if (ob > best || (ob == best && op < bpos)) {
-                    best = ob;
-                    bpos = op;
-                    bc = oc;
-                }
-            }
-            if (lane == 0) {
-                red[0] = best;
-                red[1] = static_cast<double>(bc);
+        // (a) pivot among the columns with pos >= j; every wave reduces the same partials in
+        //     the same order, so all of them reach the same choice without a barrier
+        double best = -1.0;
+        int bpos = 0x7fffffff, bc = -1;
+        for (int c = lane; c < n; c += 64) {
+            const int pp = pos[c];
+            if (pp < j) continue;
+            const int blk = c / cw, sl = c % cw;
+            double v = 0.0;
+            for (int q = 0; q < nrc; ++q) v += pn[blk * kWG + q * cw + sl];
+            if (v > best || (v == best && pp < bpos)) {
+                best = v;
+                bpos = pp;
+                bc = c;
             }
         }
-        __syncthreads();
-        const double nrm = sqrt(red[0]);
-        const int pc = static_cast<int>(red[1]);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int op = __shfl_xor(bpos, off, 64);
+            const int oc = __shfl_xor(bc, off, 64);
+            if (ob > best || (ob == best && op < bpos)) {
+                best = ob;
+                bpos = op;
+                bc = oc;
+            }
+        }
+        const double nrm = sqrt(best);
+        const int pc = bc;
         if (j == 0) r11 = nrm;
         if (!(nrm > eps * r11)) break;
         // (b) reflector of column pc over rows j..: v = (x0 - alpha, x1, ...), beta = 2 / v^T v
@@ -408,24 +404,30 @@ __device__ __forceinline__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int
             if (c < n && c != pc && pos[c] >= j) {
                 double w1 = 0.0, w2 = 0.0, w3 = 0.0;
                 if (has_j) w = v0 * M[static_cast<size_t>(j) * ldr + c];
-                int i = ib;
-                // eight rows per round, every load issued before the products
-                for (; i + 7 < i1; i += 8) {
+                // rows by rounds of UR (then at most one of eight), every load of a round issued
+                // before its products; row i goes to the accumulator of i mod 4
+                auto round = [&](auto cu, int i) {
+                    constexpr int R = decltype(cu)::value;
                     const double* Mi = M + static_cast<size_t>(i) * ldr;
-                    double a[8], b[8];
+                    double a[R], b[R];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
+                    for (int u = 0; u < R; ++u) {
                         a[u] = Mi[u * ldr + pc];
                         b[u] = Mi[u * ldr + c];
                     }
-                    w += a[0] * b[0];
-                    w1 += a[1] * b[1];
-                    w2 += a[2] * b[2];
-                    w3 += a[3] * b[3];
-                    w += a[4] * b[4];
-                    w1 += a[5] * b[5];
-                    w2 += a[6] * b[6];
-                    w3 += a[7] * b[7];
+#pragma unroll
+                    for (int u = 0; u < R; u += 4) {
+                        w += a[u] * b[u];
+                        w1 += a[u + 1] * b[u + 1];
+                        w2 += a[u + 2] * b[u + 2];
+                        w3 += a[u + 3] * b[u + 3];
+                    }
+                };
+                int i = ib;
+                for (; i + UR - 1 < i1; i += UR) round(std::integral_constant<int, UR>{}, i);
+                if (UR > 8 && i + 7 < i1) {
+                    round(std::integral_constant<int, 8>{}, i);
+                    i += 8;
                 }
                 for (; i < i1; ++i) w += M[static_cast<size_t>(i) * ldr + pc] * M[static_cast<size_t>(i) * ldr + c];
                 w += (w1 + w2) + w3;
@@ -442,28 +444,33 @@ __device__ __forceinline__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int
                 f *= beta;
                 if (has_j) M[static_cast<size_t>(j) * ldr + c] -= f * v0;
                 double sq = 0.0, sq1 = 0.0, sq2 = 0.0, sq3 = 0.0;
-                int i = ib;
-                for (; i + 7 < i1; i += 8) {
+                auto round = [&](auto cu, int i) {
+                    constexpr int R = decltype(cu)::value;
                     double* Mi = M + static_cast<size_t>(i) * ldr;
-                    double a[8], b[8];
+                    double a[R], b[R];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
+                    for (int u = 0; u < R; ++u) {
                         a[u] = Mi[u * ldr + pc];
                         b[u] = Mi[u * ldr + c];
                     }
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
+                    for (int u = 0; u < R; ++u) {
                         b[u] -= f * a[u];
                         Mi[u * ldr + c] = b[u];
                     }
-                    sq += b[0] * b[0];
-                    sq1 += b[1] * b[1];
-                    sq2 += b[2] * b[2];
-                    sq3 += b[3] * b[3];
-                    sq += b[4] * b[4];
-                    sq1 += b[5] * b[5];
-                    sq2 += b[6] * b[6];
-                    sq3 += b[7] * b[7];
+#pragma unroll
+                    for (int u = 0; u < R; u += 4) {
+                        sq += b[u] * b[u];
+                        sq1 += b[u + 1] * b[u + 1];
+                        sq2 += b[u + 2] * b[u + 2];
+                        sq3 += b[u + 3] * b[u + 3];
+                    }
+                };
+                int i = ib;
+                for (; i + UR - 1 < i1; i += UR) round(std::integral_constant<int, UR>{}, i);
+                if (UR > 8 && i + 7 < i1) {
+                    round(std::integral_constant<int, 8>{}, i);
+                    i += 8;
                 }
                 for (; i < i1; ++i) {
                     const double nv = M[static_cast<size_t>(i) * ldr + c] - f * M[static_cast<size_t>(i) * ldr + pc];
@@ -1592,7 +1599,7 @@ __device__ __forceinline__ void build_row_table(const SkelDesc& g, const int32_t
     __syncthreads();
 }
 
-// LDS: pos, perm ints | row table (2 rmax ints) | QR partials | red (2) |
+// LDS: pos, perm ints | row table (2 rmax ints) | QR partials |
 //      [M (rmax x (nmax|1))] | [G (nmax^2)] | potrf scratch
 // SM / SG: M / G staged in LDS (else in the global pools), fixed at compile time so that
 // every access has a known address space.
@@ -1613,8 +1620,7 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
     int* perm = pos + nmax;
     int* rwl = reinterpret_cast<int*>(smem + ipd);
     double* part = smem + ipd + rmax;
-    double* red = part + 2 * kWG * nbm;
-    double* after = red + 2;
+    double* after = part + 2 * kWG * nbm;
     double* __restrict__ M = SM ? after : Mpool + g.moff;
     double* gl = SM ? after + static_cast<size_t>(rmax) * (nmax | 1) : after;
     double* __restrict__ Gw = SG ? gl : Gpool + g.goff;
@@ -1650,7 +1656,7 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
     }
     __syncthreads();
     // 2. ID: rank k, pivot order, and T = R11^-1 R12 solved in place over R12
-    const int k = wg_cpqr_rows(M, ldr, r, n, eps, pos, perm, part, red);
+    const int k = wg_cpqr_rows<SM ? 8 : 16>(M, ldr, r, n, eps, pos, perm, part);
     const int nr = n - k;
     // column-oriented back substitution, every (row, column) update of a step in parallel:
     // t_i = x_i / R_ii, then x_e -= R_ei t_i for e < i
@@ -1743,26 +1749,31 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
     }
 }
 
+// STAGED: 3 = M and G in LDS, 1 = M in LDS, 0 = both in the global pools. One kernel per
+// layout, so that the LDS forms keep the register budget of their own code.
+template <int STAGED>
 __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict__ sd, const int32_t* __restrict__ cgptr,
                                                      const int32_t* __restrict__ cgl, const int32_t* __restrict__ cgoff,
                                                      const CellRef* __restrict__ cells, double* __restrict__ F,
                                                      double* __restrict__ Mpool, double* __restrict__ Tpool,
                                                      double* __restrict__ Gpool, double* __restrict__ skli, double eps,
                                                      int32_t* __restrict__ kout, int32_t* __restrict__ pout,
-                                                     int panel_cap, int staged, int nmax, int rmax, int level,
+                                                     int panel_cap, int nmax, int rmax, int level,
                                                      unsigned long long* err) {
     extern __shared__ double smem[];
     const SkelDesc g = sd[blockIdx.x];
-    if (staged == 3)
-        skeletonize_one<true, true>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout,
-                                    panel_cap, nmax, rmax, level, err, smem);
-    else if (staged == 1)
-        skeletonize_one<true, false>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout,
-                                     panel_cap, nmax, rmax, level, err, smem);
-    else
-        skeletonize_one<false, false>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout, pout,
-                                      panel_cap, nmax, rmax, level, err, smem);
+    skeletonize_one<STAGED != 0, STAGED == 3>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout,
+                                              pout, panel_cap, nmax, rmax, level, err, smem);
 }
+
+#define RHIF_SKEL_INST(S)                                                                                          \
+    template __global__ void k_skeletonize<S>(const SkelDesc*, const int32_t*, const int32_t*, const int32_t*,     \
+                                              const CellRef*, double*, double*, double*, double*, double*, double, \
+                                              int32_t*, int32_t*, int, int, int, int, unsigned long long*);
+RHIF_SKEL_INST(0)
+RHIF_SKEL_INST(1)
+RHIF_SKEL_INST(3)
+#undef RHIF_SKEL_INST
 
 // ---------------------------------------------------------------------------------------
 // Factor apply (eq. (3.2)). One workgroup per block; z_I and z_B are staged in LDS (or

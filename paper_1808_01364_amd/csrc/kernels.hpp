@@ -33,11 +33,11 @@ __global__ void k_precond_groups(const SepDesc* sd, const CellRef* cells, const 
                                  int panel_cap, int lds_n, int level, unsigned long long* err);
 __global__ void k_precond_scale(const CellScaleDesc* cd, const CellGroup* cg, const double* Lg, const double* Li,
                                 double* F, int pstride);
+template <int STAGED>
 __global__ void k_skeletonize(const SkelDesc* sd, const int32_t* cgptr, const int32_t* cgl, const int32_t* cgoff,
                               const CellRef* cells, double* F,
                               double* Mpool, double* Tpool, double* Gpool, double* skli, double eps, int32_t* kout,
-                              int32_t* pout, int panel_cap, int staged, int nmax, int rmax, int level,
-                              unsigned long long* err);
+                              int32_t* pout, int panel_cap, int nmax, int rmax, int level, unsigned long long* err);
 __global__ void k_apply_up(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
                            double* z, double* ybuf, double* ws, const int32_t* ext);
 __global__ void k_apply_down(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,

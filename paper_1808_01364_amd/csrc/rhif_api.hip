@@ -618,7 +618,11 @@ void set_kernel_attributes() {
         const int bytes = kLdsMaxDoubles * static_cast<int>(sizeof(double));
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_precond_scale),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_skeletonize),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_skeletonize<0>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_skeletonize<1>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_skeletonize<3>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_apply_group_up),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -1059,7 +1063,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             int rmax = 1;
             for (const auto& sk : P.skel_desc) rmax = std::max(rmax, sk.r);
             // must match the LDS layout of k_skeletonize
-            const int base = (2 * n + 1) / 2 + 1 + rmax + 2 * 256 * std::max(1, (n + 63) / 64) + 2;
+            const int base = (2 * n + 1) / 2 + 1 + rmax + 2 * 256 * std::max(1, (n + 63) / 64);
             const int msz = rmax * (n | 1);
             const int full = kPotrfSmemFixed + 17 * n;        // potrf scratch with the whole panel
             int staged = 0, cap = 0;
@@ -1081,10 +1085,10 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             }
             LD.skli = static_cast<double*>(f->dalloc(P.skli_elems * sizeof(double)));
             KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
-                   hipLaunchKernelGGL(k_skeletonize, dim3(nsk), dim3(256), lds, s, LD.skd, LD.cgptr, LD.cgl, LD.cgoff,
-                                      LD.cref, LD.front,
-                                      f->mp, LD.tp, LD.gp, LD.skli, f->o.eps, f->kout, f->pout, cap, staged, n, rmax,
-                                      lvl, f->err));
+                   hipLaunchKernelGGL(staged == 3 ? k_skeletonize<3> : staged == 1 ? k_skeletonize<1> : k_skeletonize<0>,
+                                      dim3(nsk), dim3(256), lds, s, LD.skd, LD.cgptr, LD.cgl, LD.cgoff, LD.cref, LD.front,
+                                      f->mp, LD.tp, LD.gp, LD.skli, f->o.eps, f->kout, f->pout, cap, n, rmax, lvl,
+                                      f->err));
             // error word, ranks and pivot orders in one copy; synchronizes: the ranks are on
             // the host now
             const size_t nb = (kKbufHead + nsk + static_cast<size_t>(P.skel_ntotal)) * sizeof(int32_t);
