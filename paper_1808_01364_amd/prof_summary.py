@@ -38,7 +38,12 @@ def kernel_source_sha() -> str:
 
 
 def _short(name: str) -> str:
-    return name.split("(")[0].replace("rhif::", "")
+    """The kernel's base name: no namespace, return type or template arguments (the forms of
+    one kernel template are counted together)."""
+    base = name.split("(")[0].replace("rhif::", "")
+    if base.startswith("void "):
+        base = base[5:]
+    return base.split("<")[0]
 
 
 def stats(csv_path: str, out: str, command: str, top: int = 20) -> None:
@@ -46,10 +51,17 @@ def stats(csv_path: str, out: str, command: str, top: int = 20) -> None:
     lines = [f"# rocprofv3 --kernel-trace --stats summary", f"command: {command}",
              f"kernels_hip_sha256: {kernel_source_sha()}", "",
              f"{'kernel':<28} {'calls':>6} {'total_us':>11} {'avg_us':>9} {'min_us':>9} {'max_us':>9} {'pct':>6}"]
-    for r in rows[:top]:
-        lines.append(f"{_short(r['Name'])[:28]:<28} {int(r['Calls']):>6} {float(r['TotalDurationNs'])/1e3:>11.1f} "
-                     f"{float(r['AverageNs'])/1e3:>9.2f} {float(r['MinNs'])/1e3:>9.2f} {float(r['MaxNs'])/1e3:>9.2f} "
-                     f"{float(r['Percentage']):>6.2f}")
+    agg = {}
+    for r in rows:
+        a = agg.setdefault(_short(r["Name"]), [0, 0.0, float("inf"), 0.0, 0.0])
+        a[0] += int(r["Calls"])
+        a[1] += float(r["TotalDurationNs"])
+        a[2] = min(a[2], float(r["MinNs"]))
+        a[3] = max(a[3], float(r["MaxNs"]))
+        a[4] += float(r["Percentage"])
+    for name, (calls, tot, mn, mx, pct) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
+        lines.append(f"{name[:28]:<28} {calls:>6} {tot/1e3:>11.1f} {tot/calls/1e3:>9.2f} {mn/1e3:>9.2f} "
+                     f"{mx/1e3:>9.2f} {pct:>6.2f}")
     open(out, "w").write("\n".join(lines) + "\n")
 
 
