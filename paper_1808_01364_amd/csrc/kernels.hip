@@ -1749,10 +1749,12 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
     }
 }
 
-// STAGED: 3 = M and G in LDS, 1 = M in LDS, 0 = both in the global pools. One kernel per
-// layout, so that the LDS forms keep the register budget of their own code.
+// STAGED: 3 = M and G in LDS, 1 = M in LDS, 0 = both in the global pools; 4 = the layout of 3
+// compiled for kSkelWavesMany waves per SIMD (fewer registers), for launches with many more
+// groups than compute units, where more resident groups per CU hide the latency of each.
+// One kernel per form, so that each keeps the register budget of its own code.
 template <int STAGED>
-__global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict__ sd, const int32_t* __restrict__ cgptr,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STAGED == 4 ? kSkelWavesMany : 1))) void k_skeletonize(const SkelDesc* __restrict__ sd, const int32_t* __restrict__ cgptr,
                                                      const int32_t* __restrict__ cgl, const int32_t* __restrict__ cgoff,
                                                      const CellRef* __restrict__ cells, double* __restrict__ F,
                                                      double* __restrict__ Mpool, double* __restrict__ Tpool,
@@ -1762,7 +1764,7 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
                                                      unsigned long long* err) {
     extern __shared__ double smem[];
     const SkelDesc g = sd[blockIdx.x];
-    skeletonize_one<STAGED != 0, STAGED == 3>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout,
+    skeletonize_one<STAGED != 0, STAGED >= 3>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout,
                                               pout, panel_cap, nmax, rmax, level, err, smem);
 }
 
@@ -1773,6 +1775,7 @@ __global__ __launch_bounds__(256) void k_skeletonize(const SkelDesc* __restrict_
 RHIF_SKEL_INST(0)
 RHIF_SKEL_INST(1)
 RHIF_SKEL_INST(3)
+RHIF_SKEL_INST(4)
 #undef RHIF_SKEL_INST
 
 // ---------------------------------------------------------------------------------------

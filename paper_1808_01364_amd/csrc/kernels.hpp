@@ -33,6 +33,8 @@ __global__ void k_precond_groups(const SepDesc* sd, const CellRef* cells, const 
                                  int panel_cap, int lds_n, int level, unsigned long long* err);
 __global__ void k_precond_scale(const CellScaleDesc* cd, const CellGroup* cg, const double* Lg, const double* Li,
                                 double* F, int pstride);
+// waves per SIMD of the skeletonization form for launches with many groups per CU
+constexpr int kSkelWavesMany = 4;
 template <int STAGED>
 __global__ void k_skeletonize(const SkelDesc* sd, const int32_t* cgptr, const int32_t* cgl, const int32_t* cgoff,
                               const CellRef* cells, double* F,

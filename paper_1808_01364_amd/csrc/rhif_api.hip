@@ -624,6 +624,8 @@ void set_kernel_attributes() {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_skeletonize<3>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_skeletonize<4>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_apply_group_up),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_apply_group_dn),
@@ -1075,6 +1077,9 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                 staged = 3;
                 cap = n;
                 lds = static_cast<size_t>(base + msz + n * n + full) * sizeof(double);
+                // far more groups than the 256 CUs hold at two per CU: the form that keeps more
+                // of them resident per CU, when their LDS allows it
+                if (nsk > 2 * 256 && kSkelWavesMany * lds <= kLdsMaxDoubles * sizeof(double)) staged = 4;
             } else if (base + msz + kPotrfSmemFixed <= kLdsMaxDoubles) {
                 staged = 1;
                 cap = std::min(n, (kLdsMaxDoubles - base - msz - kPotrfSmemFixed) / 17);
@@ -1085,7 +1090,10 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             }
             LD.skli = static_cast<double*>(f->dalloc(P.skli_elems * sizeof(double)));
             KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
-                   hipLaunchKernelGGL(staged == 3 ? k_skeletonize<3> : staged == 1 ? k_skeletonize<1> : k_skeletonize<0>,
+                   hipLaunchKernelGGL(staged == 4   ? k_skeletonize<4>
+                                      : staged == 3 ? k_skeletonize<3>
+                                      : staged == 1 ? k_skeletonize<1>
+                                                    : k_skeletonize<0>,
                                       dim3(nsk), dim3(256), lds, s, LD.skd, LD.cgptr, LD.cgl, LD.cgoff, LD.cref, LD.front,
                                       f->mp, LD.tp, LD.gp, LD.skli, f->o.eps, f->kout, f->pout, cap, n, rmax, lvl,
                                       f->err));
