@@ -70,9 +70,7 @@ typedef struct {
                                       caller's stream; accumulated in rhif_stats_t        */
 #define RHIF_KERNEL_MASK_SHIFT 8   /* flags bits 8..23: if any is set, time only the kernel
                                       classes whose bit (1 << class) is set               */
-#define RHIF_FLAG_LEAF_SUBLEVELS 4 /* eliminate the leaf interiors by nested dissection on
-                                      cells of width m/2^j >= 4 (exact; same F) instead of
-                                      one dense elimination per leaf                      */
+/* flags bit 2 (value 4) is reserved: rhif_factor rejects it with EINVAL */
 #define RHIF_FLAG_SOLVE_GRAPHS 8   /* run the factor applies and PCG iterations of the handle
                                       as HIP graphs, captured at the first rhif_apply /
                                       rhif_pcg_solve call (pays off when the handle serves
@@ -102,10 +100,10 @@ enum {
     RHIF_NUM_KCLASS = 16
 };
 
-/* Host-side summary of a factorization. Per-level arrays are indexed by internal level
- * (see `sublevels`); entry [levels] describes the root. */
+/* Host-side summary of a factorization. Per-level arrays are indexed by level l = 0..L-1;
+ * entry [levels] describes the root. */
 typedef struct {
-    int32_t levels;                          /* internal levels (sublevels + L)          */
+    int32_t levels;                          /* L, the number of levels before the root  */
     int32_t root_size;                       /* |S_L|                                    */
     int64_t factor_bytes;                    /* device bytes held by the factor          */
     int64_t n_active[RHIF_MAX_LEVELS + 1];   /* |S_l| at the start of level l            */
@@ -126,11 +124,7 @@ typedef struct {
     int64_t kernel_launches[RHIF_NUM_KCLASS];
     double  kernel_flops[RHIF_NUM_KCLASS];   /* algorithmic flops of those launches      */
     double  kernel_bytes[RHIF_NUM_KCLASS];   /* algorithmic HBM bytes of those launches  */
-    int32_t sublevels;                       /* leaf sublevels: the per-level arrays above
-                                                are indexed by internal level, of which the
-                                                first `sublevels` eliminate the leaf
-                                                interiors by nested dissection and level
-                                                sublevels + l is skeletonization level l  */
+    int32_t sublevels;                       /* always 0 (reserved)                      */
 } rhif_stats_t;
 
 typedef struct rhif_factor_s *rhif_factor_t;

@@ -247,7 +247,8 @@ def chol(Ablk: np.ndarray, level: int, step: str, block: int) -> np.ndarray:
     return Lf
 
 
-def cpqr_id(M: np.ndarray, eps: float, forced: Optional[Tuple[int, np.ndarray]] = None):
+def cpqr_id(M: np.ndarray, eps: float, forced: Optional[Tuple[int, np.ndarray]] = None,
+            trace: Optional[dict] = None):
     """Interpolative decomposition of the columns of M (Sec. 2.2, reading R3).
 
     Householder QR with column pivoting: at step j the pivot is the trailing column of
@@ -259,7 +260,13 @@ def cpqr_id(M: np.ndarray, eps: float, forced: Optional[Tuple[int, np.ndarray]] 
     forced = (k, perm) replays a given rank and pivot order (QR of M[:, perm] without
     pivot search) so that arithmetic can be compared apart from discrete choices.
 
-    Returns (k, perm, T, rdiag) with rdiag the |R_jj| of the steps taken."""
+    Returns (k, perm, T, rdiag) with rdiag the |R_jj| of the steps taken.
+
+    trace, if a dict, receives what decides the discrete choices (for telling a legitimate
+    tie from a wrong choice; the arithmetic is unchanged): "norms", per pivot step, the
+    trailing column norms indexed by original column (NaN for columns already chosen), and
+    "stop_norm", the largest trailing norm at the step where the rank test failed (NaN if
+    every step passed)."""
     M = np.array(M, dtype=np.float64, copy=True)
     r, n = M.shape
     perm = np.arange(n)
@@ -271,9 +278,16 @@ def cpqr_id(M: np.ndarray, eps: float, forced: Optional[Tuple[int, np.ndarray]] 
     rdiag = []
     r11 = 0.0
     k = 0
+    if trace is not None:
+        trace["norms"] = []
+        trace["stop_norm"] = float("nan")
     for j in range(kmax):
         if forced is None:
             norms = np.sqrt(np.sum(M[j:, j:] ** 2, axis=0))
+            if trace is not None:
+                byc = np.full(n, np.nan)
+                byc[perm[j:]] = norms
+                trace["norms"].append(byc)
             p = j + int(np.argmax(norms))          # argmax returns the first maximum
             if p != j:
                 M[:, [j, p]] = M[:, [p, j]]
@@ -286,6 +300,8 @@ def cpqr_id(M: np.ndarray, eps: float, forced: Optional[Tuple[int, np.ndarray]] 
         if j == 0:
             r11 = nrm
         if forced is None and not (nrm > eps * r11):
+            if trace is not None:
+                trace["stop_norm"] = nrm
             break
         x0 = M[j, j]
         alpha = -math.copysign(nrm, x0) if nrm > 0 else 0.0
@@ -335,6 +351,7 @@ class SkelFactor:            # one K_I = Z_I E_Itilde (eq. (2.2) and the elimina
     Lt: np.ndarray           # chol of A~_{Itilde,Itilde}
     Wt: np.ndarray           # Lt^-1 A~_{Ihat,Itilde}^T
     rdiag: np.ndarray
+    trace: Optional[dict] = None   # cpqr_id's record of the pivot norms (not replayed IDs)
 
 
 @dataclass
@@ -492,10 +509,11 @@ def factor(A0: sp.csr_matrix, d: int, s: int, leaf: int, eps: float, precond: in
             rowmask[g] = False                       # R = every other active DOF
             M = col[rowmask]
             forced = None if replay is None else replay.get((lvl, int(g[0])))
-            k, perm, T, rdiag = cpqr_id(M, eps, forced)
-            ids.append((key, g, k, perm, T, rdiag))
+            tr = {} if forced is None else None
+            k, perm, T, rdiag = cpqr_id(M, eps, forced, trace=tr)
+            ids.append((key, g, k, perm, T, rdiag, tr))
         assign = []
-        for key, g, k, perm, T, rdiag in ids:
+        for key, g, k, perm, T, rdiag, tr in ids:
             n = len(g)
             hat = g[perm[:k]]
             tilde = g[perm[k:]]
@@ -509,7 +527,7 @@ def factor(A0: sp.csr_matrix, d: int, s: int, leaf: int, eps: float, precond: in
             Wt = sla.solve_triangular(Lt, Aht_t.T, lower=True) if n - k > 0 else np.zeros((0, k))
             Ahh_new = Ahh - Wt.T @ Wt
             lv.skels.append(SkelFactor(key=key, group=g, hat=hat, tilde=tilde, perm=perm, T=T,
-                                       Lt=Lt, Wt=Wt, rdiag=rdiag))
+                                       Lt=Lt, Wt=Wt, rdiag=rdiag, trace=tr))
             assign.append((hat, hat, Ahh_new))
             active_mask[tilde] = False
         A = _assign_blocks(A, assign)

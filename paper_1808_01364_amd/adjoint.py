@@ -16,30 +16,44 @@ from . import rhif
 class _SolveLogA(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta, f, dim, n, b, leaf, eps, rtol, maxit):
+        N = n ** dim
+        rhif._need((theta.detach().reshape(-1), "theta", (n + 1) ** dim), (f.detach().reshape(-1), "f", N),
+                   *([(b.detach().reshape(-1), "b", N)] if b is not None else []))
         a = torch.exp(theta.detach()).contiguous()
-        csr = rhif.assemble_fd(dim, n, a.reshape(-1), b)
+        csr = rhif.assemble_fd(dim, n, a.reshape(-1), None if b is None else b.detach().reshape(-1))
         F = rhif.Factor(dim, n, csr, leaf, eps, 1)
         u, it, rr = F.pcg(f.detach().reshape(-1).contiguous(), rtol, maxit)
+        # the factor is kept for the adjoint solve of the (single) backward pass and released
+        # there; it is released with the graph if no backward pass runs
         ctx.F = F
-        ctx.dims = (dim, n, rtol, maxit, f.shape)
+        ctx.dims = (dim, n, rtol, maxit, f.shape, None if b is None else b.shape)
         ctx.iters = it
         ctx.save_for_backward(a, u)
         return u
 
     @staticmethod
     def backward(ctx, gu):
-        a, u = ctx.saved_tensors
-        dim, n, rtol, maxit, fshape = ctx.dims
         F = ctx.F
-        lam, it, rr = F.pcg(gu.reshape(-1).contiguous(), rtol, maxit)
+        if F is None:
+            raise RuntimeError("solve_log_a: the factorization was released after the first backward pass; "
+                               "a second backward pass (retain_graph=True) needs a new forward solve")
+        a, u = ctx.saved_tensors
+        dim, n, rtol, maxit, fshape, bshape = ctx.dims
+        try:
+            lam, it, rr = F.pcg(gu.reshape(-1).contiguous(), rtol, maxit)
+        finally:
+            F.close()
+            ctx.F = None
         g = rhif.grad_log_a(dim, n, a.reshape(-1), u, lam).reshape(a.shape)
-        F.close()
-        ctx.F = None
-        return g, lam.reshape(fshape), None, None, None, None, None, None, None
+        # A = h^-2 K(a) + diag(b): dL/db_i = -lam_i u_i
+        gb = (-(lam * u)).reshape(bshape) if bshape is not None and ctx.needs_input_grad[4] else None
+        return g, lam.reshape(fshape), None, None, gb, None, None, None, None
 
 
 def solve_log_a(theta: torch.Tensor, f: torch.Tensor, dim: int, n: int, b: torch.Tensor | None = None,
                 leaf: int = 16, eps: float = 1e-6, rtol: float = 1e-12, maxit: int = 500) -> torch.Tensor:
     """u with A(exp theta) u = f, differentiable with respect to theta ((n+1)^dim cell values,
-    c_1 fastest) and f (N values). theta, f and b are float64 device tensors."""
+    c_1 fastest), f (N values) and the reaction term b (N values or None). theta, f and b are
+    float64 device tensors. One backward pass per forward solve: the factorization is
+    released after it."""
     return _SolveLogA.apply(theta, f, dim, n, b, leaf, eps, rtol, maxit)

@@ -63,13 +63,6 @@ void LevelPlan::reset() {
     alg_apply_cell_bytes = alg_apply_sep_bytes = alg_gather_bytes = 0.0;
 }
 
-int inner_leaf(int d, int leaf) {
-    (void)d;
-    int w = leaf;
-    while (w % 2 == 0 && w / 2 >= 4) w /= 2;
-    return w;
-}
-
 int num_levels(int s, int leaf) {
     int L = 0;
     while ((static_cast<int64_t>(leaf) << L) <= s) ++L;

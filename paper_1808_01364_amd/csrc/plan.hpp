@@ -126,13 +126,6 @@ inline bool leaf_interior_banded(int d, int level, bool root, int w) {
 // Number of skeletonization levels L: all l >= 0 with 2^l m <= s.
 int num_levels(int s, int leaf);
 
-// Width of the finest cells used to eliminate the leaf interiors. Eliminating a leaf cell's
-// interior is exact, and any elimination order gives the same Schur complement on its
-// boundary (Sec. 2.1); nested dissection inside the leaf (cells of width m/2^j >= 4, no
-// preconditioning or compression at those sublevels) replaces one dense elimination of
-// (m-1)^d unknowns by a few small ones.
-int inner_leaf(int d, int leaf);
-
 // Build the plan of `level` with n_active active unknowns: at level 0 every unknown, above it
 // the unknowns next_active_set kept from the level below. `prev` is the plan of the level
 // below (nullptr at level 0); its groups and the kept lists in scr give this level's groups,

@@ -49,6 +49,7 @@ constexpr int kCholLdsPmax = 139;
 constexpr int kElimPanel = 128;   // panel width of the elimination of large interiors
 constexpr int kStaticLdsReserve = 32;         // doubles of static LDS a kernel may declare
 constexpr int kRedBlocks = 1024;              // fixed partial-sum layout of the CG reductions
+constexpr int32_t kRemovedFlags = 4;          // option bits that no longer exist
 
 // Per-thread host state reused across factorizations: pinned staging buffers for the
 // uploads (a ring, each slot fenced by the event of its last copy), a pinned buffer for
@@ -149,7 +150,6 @@ struct Packer {
 
 struct LevelDev {
     bool root = false;
-    bool exact = false;     // a leaf sublevel: elimination only
     bool leaf_banded = false;   // cells factored by k_leaf_elim (block-bidiagonal L)
     bool precond = false;   // block Jacobi applied at this level
     double* front = nullptr;
@@ -325,10 +325,8 @@ constexpr int kKbufHead = 4;   // ints before the ID outputs: the 64-bit error w
 struct rhif_factor_s {
     rhif::GridInfo g;
     rhif_opts o{};
-    int L = 0;        // internal levels: leaf sublevels (exact elimination) + skeletonization levels
-    int l0 = 0;       // leaf sublevels
-    int w0 = 0;       // width of the finest (sublevel) cells
-    int Lskel = 0;    // skeletonization levels of the paper's level loop
+    int L = 0;        // skeletonization levels of the paper's level loop (the root is level L)
+    int Lskel = 0;    // the same count (kept for the ID getter)
     int64_t nnz = 0;
     int32_t* rp = nullptr;
     int32_t* ci = nullptr;
@@ -548,13 +546,8 @@ void raise_err(rhif_factor_s* f, unsigned long long h) {
                           "with the plan", block, ilevel);
             fail(RHIF_EDEVICE, buf);
         }
-        if (step == 3 || ilevel >= f->l0)
-            std::snprintf(buf, sizeof(buf), "not SPD: Cholesky pivot <= 0 or not finite at level %d, step %s, block %d",
-                          step == 3 ? f->Lskel : ilevel - f->l0, step_name(step).c_str(), block);
-        else
-            std::snprintf(buf, sizeof(buf),
-                          "not SPD: Cholesky pivot <= 0 or not finite at level 0, step %s (leaf sublevel %d), "
-                          "block %d", step_name(step).c_str(), ilevel, block);
+        std::snprintf(buf, sizeof(buf), "not SPD: Cholesky pivot <= 0 or not finite at level %d, step %s, block %d",
+                      step == 3 ? f->Lskel : ilevel, step_name(step).c_str(), block);
         fail(RHIF_ENOTSPD, buf);
     }
 }
@@ -653,7 +646,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
     const GridInfo& g = f->g;
     const int d = g.d;
     const int W = 1 << d;
-    const int leaf = f->w0;
+    const int leaf = f->o.leaf;
     f->nnz = fd_nnz(d, g.s);
     // the error word leads the block of the ID outputs, so that one copy reads back both
     f->kbuf = static_cast<int32_t*>(f->dalloc(kKbufHead * sizeof(int32_t)));
@@ -760,11 +753,9 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
 
     for (int lvl = 0; lvl <= f->L; ++lvl) {
         const bool root = (lvl == f->L);
-        const bool exact = !root && lvl < f->l0;
         LevelDev& LD = f->lev[lvl];
         LD.root = root;
-        LD.exact = exact;
-        LD.precond = f->o.precond && !exact;
+        LD.precond = f->o.precond != 0;
         LevelPlan& P = hc.plan(lvl);
         const LevelPlan* prevP = lvl > 0 ? &hc.plan(lvl - 1) : nullptr;
         const LevelDev* prev = lvl > 0 ? &f->lev[lvl - 1] : nullptr;
@@ -986,23 +977,6 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         LD.b_sep = P.alg_apply_sep_bytes;
         LD.b_gather = P.alg_gather_bytes;
         f->ws_elems = std::max(f->ws_elems, P.ws_elems);
-        const int nsk_all = static_cast<int>(P.skel_desc.size());
-        if (exact) {
-            // leaf sublevel: no preconditioning, no compression; every separator stays
-            std::vector<int32_t> kk(nsk_all), pp(P.skel_ntotal);
-            for (const auto& sk : P.skel_desc) {
-                kk[sk.gid] = sk.n;
-                for (int q = 0; q < sk.n; ++q) pp[sk.poff + q] = q;
-            }
-            std::vector<ApplyDesc> sk_ad;
-            std::vector<int32_t> sk_dofs;
-            double fl = 0.0, sby = 0.0;
-            n_active = finish_level(P, kk.data(), pp.data(), kApplyCap, sk_ad, sk_dofs, f->ws_elems, scr, fl, sby);
-            if (!sk_ad.empty()) fail(RHIF_EINVAL, "internal: a leaf sublevel produced skeleton blocks");
-            phase(5, t0);
-            continue;
-        }
-
         LD.lg = static_cast<double*>(f->dalloc(P.lg_elems * sizeof(double)));
         LD.tp = static_cast<double*>(f->dalloc(P.t_elems * sizeof(double)));
         LD.gp = static_cast<double*>(f->dalloc(P.g_elems * sizeof(double)));
@@ -1011,7 +985,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             f->mp = static_cast<double*>(f->dalloc(P.m_elems * sizeof(double)));
             f->mp_elems = P.m_elems;
         }
-        const int nsk = exact ? 0 : static_cast<int>(P.skel_desc.size());
+        const int nsk = static_cast<int>(P.skel_desc.size());
         const int64_t kp = static_cast<int64_t>(nsk) + P.skel_ntotal + 1;
         if (kp > f->kp_elems) {
             // a larger block: the error word so far moves along (stream-ordered after every
@@ -1374,6 +1348,175 @@ void apply_z(rhif_factor_s* f, hipStream_t s, bool& used) {
     if (!used) do_apply_inplace(f, f->z, s);
 }
 
+struct PcgWs {
+    double *r, *z, *p, *q, *part, *sc;
+    double* hsc;   // pinned host scalars, or nullptr
+};
+
+// The PCG of rhif_pcg_solve on the workspace w (r, z, p, q: N doubles each; part: kRedBlocks
+// doubles of partial sums; sc: 16 scalars). With w.hsc (pinned host scalars) the host waits on
+// events and looks ahead; without it every scalar is read
+// with a copy to host memory of the caller's thread and a stream synchronization, and no
+// graph is used.
+void pcg_run(rhif_factor_s* f, const PcgWs& w, const double* rhs, double* u, double rtol, int32_t maxit,
+             int32_t* iters, double* relres, hipStream_t s) {
+    const int64_t N = f->g.N;
+    const int gb = grid_for(N);
+    double host_sc[2] = {0.0, 0.0};
+    const bool pinned = w.hsc != nullptr;
+    double* hsc = pinned ? w.hsc : host_sc;
+    const double NB = 8.0 * static_cast<double>(N);
+    const double spmv_by = 12.0 * f->nnz + 4.0 * (N + 1) + 3.0 * NB;
+#define VEC(by, ...) KTIMED(f, cs, RHIF_K_VECTOR, 0.0, (by), __VA_ARGS__)
+    // the graphs hold the solution pointer: capture again for another one
+    if (pinned && f->graph_u != u) {
+        drop_graph(f, 1);
+        drop_graph(f, 2);
+        f->graph_u = u;
+    }
+    // q = A p; alpha; u += alpha p, r -= alpha q; |r|^2 -> host
+    auto update = [&](hipStream_t cs) {
+        KTIMED(f, cs, RHIF_K_SPMV, 2.0 * f->nnz + 2.0 * N, spmv_by,
+               hipLaunchKernelGGL(rhif::k_spmv_dot, dim3(gb), dim3(256), 0, cs, N, f->rp, f->ci, f->val, w.p, w.q,
+                                  w.part));
+        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, w.part, gb, 1, w.sc, nullptr));
+        VEC(6 * NB, hipLaunchKernelGGL(rhif::k_axpy2, dim3(gb), dim3(256), 0, cs, N, w.sc, w.p, w.q, u, w.r,
+                                       w.part));
+        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, w.part, gb, 2, w.sc, nullptr));
+        HIPCHK(hipMemcpyAsync(hsc + 1, w.sc + 3, sizeof(double), hipMemcpyDeviceToHost, cs));
+        if (!pinned) HIPCHK(hipStreamSynchronize(cs));
+    };
+    // z = F^-1 r; rho = r.z; beta (touches neither u, r nor p)
+    auto precondition = [&](hipStream_t cs) {
+        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, cs, N, w.r, w.z));
+        do_apply_inplace(f, w.z, cs);
+        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, cs, N, w.r, w.z, w.part));
+        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, w.part, gb, 4, w.sc, nullptr));
+    };
+    // p = z + beta p; then the next update
+    auto advance = [&](hipStream_t cs) {
+        VEC(3 * NB, hipLaunchKernelGGL(rhif::k_update_p, dim3(gb), dim3(256), 0, cs, N, w.sc, w.z, w.p));
+        update(cs);
+    };
+    auto iterate = [&](hipStream_t cs) {
+        precondition(cs);
+        advance(cs);
+    };
+    {
+        hipStream_t cs = s;
+        // r = f, u = 0, ||f||^2
+        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, cs, N, rhs, w.r));
+        VEC(NB, hipLaunchKernelGGL(rhif::k_fill, dim3(gb), dim3(256), 0, cs, N, 0.0, u));
+        VEC(NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, cs, N, rhs, rhs, w.part));
+        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, w.part, gb, 0, w.sc, nullptr));
+        HIPCHK(hipMemcpyAsync(hsc, w.sc + 6, sizeof(double), hipMemcpyDeviceToHost, cs));
+        if (pinned) HIPCHK(hipEventRecord(f->sc_ev, cs));
+        else HIPCHK(hipStreamSynchronize(cs));
+        // z = F^-1 r, rho = r.z, p = z
+        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, cs, N, w.r, w.z));
+    }
+    bool g0 = false;
+    if (pinned) apply_z(f, s, g0);
+    else do_apply_inplace(f, w.z, s);
+    {
+        hipStream_t cs = s;
+        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, cs, N, w.r, w.z, w.part));
+        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, w.part, gb, 3, w.sc, nullptr));
+        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, cs, N, w.z, w.p));
+    }
+    int it = 0;
+    double rel = 0.0;
+    bool conv = false;
+    if (!pinned) {
+        // plain loop: every scalar read synchronizes the stream
+        const double ff = hsc[0];
+        const double fnorm = std::sqrt(ff);
+        conv = (ff == 0.0);
+        while (!conv && it < maxit) {
+            update(s);
+            ++it;
+            rel = std::sqrt(hsc[1]) / fnorm;
+            if (rel <= rtol) {
+                conv = true;
+                break;
+            }
+            if (it >= maxit) break;
+            precondition(s);
+            hipStream_t cs = s;
+            VEC(3 * NB, hipLaunchKernelGGL(rhif::k_update_p, dim3(gb), dim3(256), 0, cs, N, w.sc, w.z, w.p));
+        }
+    } else if (g0 || graphs_wanted(f)) {
+        HIPCHK(hipStreamSynchronize(s));
+        if (g0) f->resolve_graph(0);
+        const double ff = hsc[0];
+        const double fnorm = std::sqrt(ff);
+        conv = (ff == 0.0);
+        int last = -1;   // graph whose replay the next synchronization completes
+        if (!conv && maxit > 0) {
+            if (run_graph(f, 1, s, update)) last = 1;
+            else update(s);
+        }
+        while (!conv && it < maxit) {
+            HIPCHK(hipStreamSynchronize(s));
+            if (last >= 0) f->resolve_graph(last);
+            last = -1;
+            ++it;
+            rel = std::sqrt(hsc[1]) / fnorm;
+            if (rel <= rtol) {
+                conv = true;
+                break;
+            }
+            if (it >= maxit) break;
+            if (run_graph(f, 2, s, iterate)) last = 2;
+            else iterate(s);
+        }
+    } else {
+        // Direct launches. The host waits only for the residual norm (an event after its
+        // copy); while it decides, the stream already preconditions the new residual
+        // (z = F^-1 r and r.z change neither u, r nor p, so an iteration that turns out not
+        // to be needed leaves the solution untouched). The look-ahead is skipped when the
+        // observed rate predicts convergence at the next check (within 10x of rtol), so that
+        // a finished solve rarely leaves an unneeded apply behind. The stream runs the same
+        // kernels in the same order as without look-ahead.
+        HIPCHK(hipEventSynchronize(f->sc_ev));   // ||f||^2, copied before the first apply
+        const double ff = hsc[0];
+        const double fnorm = std::sqrt(ff);
+        conv = (ff == 0.0);
+        if (!conv && maxit > 0) {
+            update(s);
+            HIPCHK(hipEventRecord(f->sc_ev, s));
+            bool ahead = maxit > 1;
+            if (ahead) precondition(s);
+            double prev = 1.0;   // ||r_0|| / ||f||
+            while (true) {
+                HIPCHK(hipEventSynchronize(f->sc_ev));
+                ++it;
+                rel = std::sqrt(hsc[1]) / fnorm;
+                if (rel <= rtol) {
+                    conv = true;
+                    break;
+                }
+                if (it >= maxit) break;
+                if (!ahead) precondition(s);
+                advance(s);
+                HIPCHK(hipEventRecord(f->sc_ev, s));
+                const double predicted = prev > 0.0 ? rel * (rel / prev) : rel;
+                prev = rel;
+                ahead = it + 1 < maxit && !(predicted <= 10.0 * rtol);
+                if (ahead) precondition(s);
+            }
+        }
+    }
+#undef VEC
+    if (pinned) f->resolve();
+    HIPCHK(hipGetLastError());
+    f->mark(s);
+    if (iters) *iters = it;
+    if (relres) *relres = rel;
+    if (!conv) fail(RHIF_ENOCONV, "PCG did not reach the tolerance within maxit iterations");
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -1456,6 +1599,7 @@ rhif_status rhif_factor(const rhif_grid* g, const rhif_opts* o, const int32_t* r
         if (!(o->eps >= 0.0) || !(o->eps < 1.0)) fail(RHIF_EINVAL, "eps must be in [0, 1)");
         if (o->precond != 0 && o->precond != 1) fail(RHIF_EINVAL, "precond must be 0 or 1");
         if (o->precision != 0) fail(RHIF_EINVAL, "only precision 0 (FP64) is available");
+        if (o->flags & kRemovedFlags) fail(RHIF_EINVAL, "flag bit 2 (leaf sublevels) is not supported");
         if (!row_ptr || !col || !val) fail(RHIF_EINVAL, "NULL CSR pointer");
         set_kernel_attributes();
         f = new rhif_factor_s();
@@ -1470,12 +1614,9 @@ rhif_status rhif_factor(const rhif_grid* g, const rhif_opts* o, const int32_t* r
             const uint32_t m = (static_cast<uint32_t>(o->flags) >> RHIF_KERNEL_MASK_SHIFT) & 0xffffu;
             f->kmask = m ? m : 0xffffu;
         }
-        f->w0 = (o->flags & RHIF_FLAG_LEAF_SUBLEVELS) ? rhif::inner_leaf(f->g.d, o->leaf) : o->leaf;
-        f->l0 = 0;
-        while ((f->w0 << f->l0) < o->leaf) ++f->l0;
-        f->L = rhif::num_levels(f->g.s, f->w0);
-        f->Lskel = rhif::num_levels(f->g.s, o->leaf);
-        f->stats.sublevels = std::min(f->l0, f->L);
+        f->L = rhif::num_levels(f->g.s, o->leaf);
+        f->Lskel = f->L;
+        f->stats.sublevels = 0;
         if (f->L > RHIF_MAX_LEVELS) fail(RHIF_EINVAL, "too many levels");
         const auto t0 = std::chrono::steady_clock::now();
         do_factor(f, row_ptr, col, val, s);
@@ -1567,137 +1708,8 @@ rhif_status rhif_pcg_solve(rhif_factor_t f, const double* rhs, double* u, double
     if (!f || !rhs || !u) fail(RHIF_EINVAL, "NULL argument");
     if (maxit < 0 || !(rtol >= 0.0)) fail(RHIF_EINVAL, "bad maxit or rtol");
     ensure_pcg(f);
-    const int64_t N = f->g.N;
-    const int gb = grid_for(N);
-    double* hsc = f->hsc;
-    const double NB = 8.0 * static_cast<double>(N);
-    const double spmv_by = 12.0 * f->nnz + 4.0 * (N + 1) + 3.0 * NB;
-#define VEC(by, ...) KTIMED(f, cs, RHIF_K_VECTOR, 0.0, (by), __VA_ARGS__)
-    // the graphs hold the solution pointer: capture again for another one
-    if (f->graph_u != u) {
-        drop_graph(f, 1);
-        drop_graph(f, 2);
-        f->graph_u = u;
-    }
-    // q = A p; alpha; u += alpha p, r -= alpha q; |r|^2 -> host
-    auto update = [&](hipStream_t cs) {
-        KTIMED(f, cs, RHIF_K_SPMV, 2.0 * f->nnz + 2.0 * N, spmv_by,
-               hipLaunchKernelGGL(rhif::k_spmv_dot, dim3(gb), dim3(256), 0, cs, N, f->rp, f->ci, f->val, f->p, f->q,
-                                  f->part));
-        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, f->part, gb, 1, f->sc, nullptr));
-        VEC(6 * NB, hipLaunchKernelGGL(rhif::k_axpy2, dim3(gb), dim3(256), 0, cs, N, f->sc, f->p, f->q, u, f->r,
-                                       f->part));
-        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, f->part, gb, 2, f->sc, nullptr));
-        HIPCHK(hipMemcpyAsync(hsc + 1, f->sc + 3, sizeof(double), hipMemcpyDeviceToHost, cs));
-    };
-    // z = F^-1 r; rho = r.z; beta (touches neither u, r nor p)
-    auto precondition = [&](hipStream_t cs) {
-        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, cs, N, f->r, f->z));
-        do_apply_inplace(f, f->z, cs);
-        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, cs, N, f->r, f->z, f->part));
-        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, f->part, gb, 4, f->sc, nullptr));
-    };
-    // p = z + beta p; then the next update
-    auto advance = [&](hipStream_t cs) {
-        VEC(3 * NB, hipLaunchKernelGGL(rhif::k_update_p, dim3(gb), dim3(256), 0, cs, N, f->sc, f->z, f->p));
-        update(cs);
-    };
-    auto iterate = [&](hipStream_t cs) {
-        precondition(cs);
-        advance(cs);
-    };
-    {
-        hipStream_t cs = s;
-        // r = f, u = 0, ||f||^2
-        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, cs, N, rhs, f->r));
-        VEC(NB, hipLaunchKernelGGL(rhif::k_fill, dim3(gb), dim3(256), 0, cs, N, 0.0, u));
-        VEC(NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, cs, N, rhs, rhs, f->part));
-        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, f->part, gb, 0, f->sc, nullptr));
-        HIPCHK(hipMemcpyAsync(hsc, f->sc + 6, sizeof(double), hipMemcpyDeviceToHost, cs));
-        HIPCHK(hipEventRecord(f->sc_ev, cs));
-        // z = F^-1 r, rho = r.z, p = z
-        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, cs, N, f->r, f->z));
-    }
-    bool g0 = false;
-    apply_z(f, s, g0);
-    {
-        hipStream_t cs = s;
-        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, cs, N, f->r, f->z, f->part));
-        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, f->part, gb, 3, f->sc, nullptr));
-        VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, cs, N, f->z, f->p));
-    }
-    int it = 0;
-    double rel = 0.0;
-    bool conv = false;
-    if (g0 || graphs_wanted(f)) {
-        HIPCHK(hipStreamSynchronize(s));
-        if (g0) f->resolve_graph(0);
-        const double ff = hsc[0];
-        const double fnorm = std::sqrt(ff);
-        conv = (ff == 0.0);
-        int last = -1;   // graph whose replay the next synchronization completes
-        if (!conv && maxit > 0) {
-            if (run_graph(f, 1, s, update)) last = 1;
-            else update(s);
-        }
-        while (!conv && it < maxit) {
-            HIPCHK(hipStreamSynchronize(s));
-            if (last >= 0) f->resolve_graph(last);
-            last = -1;
-            ++it;
-            rel = std::sqrt(hsc[1]) / fnorm;
-            if (rel <= rtol) {
-                conv = true;
-                break;
-            }
-            if (it >= maxit) break;
-            if (run_graph(f, 2, s, iterate)) last = 2;
-            else iterate(s);
-        }
-    } else {
-        // Direct launches. The host waits only for the residual norm (an event after its
-        // copy); while it decides, the stream already preconditions the new residual
-        // (z = F^-1 r and r.z change neither u, r nor p, so an iteration that turns out not
-        // to be needed leaves the solution untouched). The look-ahead is skipped when the
-        // observed rate predicts convergence at the next check (within 10x of rtol), so that
-        // a finished solve rarely leaves an unneeded apply behind. The stream runs the same
-        // kernels in the same order as without look-ahead.
-        HIPCHK(hipEventSynchronize(f->sc_ev));   // ||f||^2, copied before the first apply
-        const double ff = hsc[0];
-        const double fnorm = std::sqrt(ff);
-        conv = (ff == 0.0);
-        if (!conv && maxit > 0) {
-            update(s);
-            HIPCHK(hipEventRecord(f->sc_ev, s));
-            bool ahead = maxit > 1;
-            if (ahead) precondition(s);
-            double prev = 1.0;   // ||r_0|| / ||f||
-            while (true) {
-                HIPCHK(hipEventSynchronize(f->sc_ev));
-                ++it;
-                rel = std::sqrt(hsc[1]) / fnorm;
-                if (rel <= rtol) {
-                    conv = true;
-                    break;
-                }
-                if (it >= maxit) break;
-                if (!ahead) precondition(s);
-                advance(s);
-                HIPCHK(hipEventRecord(f->sc_ev, s));
-                const double predicted = prev > 0.0 ? rel * (rel / prev) : rel;
-                prev = rel;
-                ahead = it + 1 < maxit && !(predicted <= 10.0 * rtol);
-                if (ahead) precondition(s);
-            }
-        }
-    }
-#undef VEC
-    f->resolve();
-    HIPCHK(hipGetLastError());
-    f->mark(s);
-    if (iters) *iters = it;
-    if (relres) *relres = rel;
-    if (!conv) fail(RHIF_ENOCONV, "PCG did not reach the tolerance within maxit iterations");
+    const PcgWs w{f->r, f->z, f->p, f->q, f->part, f->sc, f->hsc};
+    pcg_run(f, w, rhs, u, rtol, maxit, iters, relres, s);
     API_END
 }
 
@@ -1714,7 +1726,7 @@ rhif_status rhif_skeletons(rhif_factor_t f, int32_t level, int32_t* ngroups, int
     API_BEGIN
     if (!f || !ngroups || !total) fail(RHIF_EINVAL, "NULL argument");
     if (level < 0 || level >= f->Lskel) fail(RHIF_EINVAL, "level out of range");
-    const LevelDev& LD = f->lev[level + f->l0];
+    const LevelDev& LD = f->lev[level];
     *ngroups = static_cast<int32_t>(LD.k.size());
     *total = static_cast<int64_t>(LD.perm.size());
     if (first_dof) std::copy(LD.first_dof.begin(), LD.first_dof.end(), first_dof);

@@ -21,7 +21,6 @@ MAX_LEVELS = 32
 FLAG_PHASE_TIMES = 1
 FLAG_KERNEL_TIMES = 2
 KERNEL_MASK_SHIFT = 8
-FLAG_LEAF_SUBLEVELS = 4
 FLAG_SOLVE_GRAPHS = 8
 FLAG_GLOBAL_STAGING = 16
 NUM_KCLASS = 16
@@ -141,6 +140,28 @@ def _ptr(t) -> int:
     return int(t.data_ptr()) if t is not None else 0
 
 
+def _need(*specs):
+    """Check tensors handed to the library before any device work. Each spec is
+    (tensor, name, numel) or (tensor, name, numel, dtype); dtype defaults to float64. First
+    every tensor's dtype, size (the kernels read and write exactly `numel` elements through
+    its pointer) and contiguity, then that every one lives on a GPU. Raises ValueError."""
+    for spec in specs:
+        t, name, numel = spec[:3]
+        dtype = spec[3] if len(spec) > 3 else "float64"
+        if t is None or not hasattr(t, "data_ptr"):
+            raise ValueError(f"{name} must be a torch tensor")
+        if str(t.dtype) != f"torch.{dtype}":
+            raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+        if t.numel() != numel:
+            raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+    for spec in specs:
+        t, name = spec[:2]
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must be a GPU (cuda) tensor, got device {t.device}")
+
+
 def make_grid(dim: int, n: int) -> Grid:
     g = Grid()
     g.dim = dim
@@ -159,13 +180,11 @@ def fd_nnz(dim: int, n: int) -> int:
 def assemble_fd(dim: int, n: int, a_cells, b=None, stream=None):
     """CSR (row_ptr, col, val) of the FD matrix, as device tensors (int32, int32, float64).
     a_cells: (n+1)^dim cell coefficients on the device, c_1 fastest; b: N values or None."""
+    N = n ** dim
+    _need((a_cells, "a_cells", (n + 1) ** dim), *([(b, "b", N)] if b is not None else []))
     torch = _torch()
     dev = a_cells.device
-    N = n ** dim
     nnz = fd_nnz(dim, n)
-    a_cells = a_cells.contiguous().to(torch.float64)
-    if b is not None:
-        b = b.contiguous().to(torch.float64)
     rp = torch.empty(N + 1, dtype=torch.int32, device=dev)
     col = torch.empty(nnz, dtype=torch.int32, device=dev)
     val = torch.empty(nnz, dtype=torch.float64, device=dev)
@@ -177,10 +196,9 @@ def assemble_fd(dim: int, n: int, a_cells, b=None, stream=None):
 def grad_log_a(dim: int, n: int, a_cells, u, lam, stream=None):
     """Per-cell -a_c lam^T (dA/da_c) u as a device tensor of (n+1)^dim values (c_1 fastest):
     the gradient with respect to log a of a loss of the solution u when A lam = dL/du."""
+    N = n ** dim
+    _need((a_cells, "a_cells", (n + 1) ** dim), (u, "u", N), (lam, "lam", N))
     torch = _torch()
-    a_cells = a_cells.contiguous().to(torch.float64)
-    u = u.contiguous().to(torch.float64)
-    lam = lam.contiguous().to(torch.float64)
     g = torch.empty_like(a_cells)
     _check(load_library().rhif_grad_log_a(ctypes.byref(make_grid(dim, n)), _ptr(a_cells), _ptr(u), _ptr(lam),
                                           _ptr(g), _stream(stream)))
@@ -200,11 +218,14 @@ class Factor:
 
     def __init__(self, dim: int, n: int, csr, leaf: int, eps: float, precond: int = 1,
                  precision: int = 0, flags: int = 0, stream=None):
-        self._lib = load_library()
+        self._h = None
         self.dim, self.n, self.N = dim, n, n ** dim
+        rp, col, val = csr
+        nnz = fd_nnz(dim, n)
+        _need((rp, "row_ptr", self.N + 1, "int32"), (col, "col", nnz, "int32"), (val, "val", nnz))
+        self._lib = load_library()
         o = Opts()
         o.leaf, o.eps, o.precond, o.precision, o.flags = leaf, eps, precond, precision, flags
-        rp, col, val = csr
         h = ctypes.c_void_p()
         _check(self._lib.rhif_factor(ctypes.byref(make_grid(dim, n)), ctypes.byref(o), _ptr(rp), _ptr(col),
                                      _ptr(val), _stream(stream), ctypes.byref(h)))
@@ -218,28 +239,33 @@ class Factor:
 
     def apply(self, r, out=None, stream=None):
         """z = F^-1 r for r of shape (N,) or (nrhs, N) (rows are right-hand sides)."""
-        torch = _torch()
-        r = r.contiguous()
-        z = out if out is not None else torch.empty_like(r)
+        if r is None or r.dim() not in (1, 2) or r.shape[-1] != self.N:
+            raise ValueError(f"r must have shape ({self.N},) or (nrhs, {self.N})")
         nrhs = 1 if r.dim() == 1 else r.shape[0]
+        if out is not None and tuple(out.shape) != tuple(r.shape):
+            raise ValueError(f"out must have the shape of r, {tuple(r.shape)}")
+        _need((r, "r", nrhs * self.N), *([(out, "out", nrhs * self.N)] if out is not None else []))
+        torch = _torch()
+        z = out if out is not None else torch.empty_like(r)
         _check(self._lib.rhif_apply(self.handle, _ptr(r), _ptr(z), nrhs, _stream(stream)))
         return z
 
     def matvec(self, x, out=None, stream=None):
+        _need((x, "x", self.N), *([(out, "out", self.N)] if out is not None else []))
         torch = _torch()
         y = out if out is not None else torch.empty_like(x)
-        _check(self._lib.rhif_matvec(self.handle, _ptr(x.contiguous()), _ptr(y), _stream(stream)))
+        _check(self._lib.rhif_matvec(self.handle, _ptr(x), _ptr(y), _stream(stream)))
         return y
 
     def pcg(self, f, rtol: float = 1e-12, maxit: int = 500, out=None, stream=None,
             raise_on_noconv: bool = True) -> Tuple[object, int, float]:
+        """(u, iterations, final relative residual) of the PCG solve A u = f."""
+        _need((f, "f", self.N), *([(out, "out", self.N)] if out is not None else []))
         torch = _torch()
-        f = f.contiguous()
         u = out if out is not None else torch.empty_like(f)
         it = ctypes.c_int32()
         rel = ctypes.c_double()
-        st = self._lib.rhif_pcg_solve(self.handle, _ptr(f), _ptr(u), rtol, maxit, ctypes.byref(it),
-                                      ctypes.byref(rel), _stream(stream))
+        st = self._lib.rhif_pcg_solve(self.handle, _ptr(f), _ptr(u), rtol, maxit, ctypes.byref(it), ctypes.byref(rel), _stream(stream))
         if st == RHIF_ENOCONV:
             if raise_on_noconv:
                 raise NoConvergence(st, self._lib.rhif_last_error().decode(), it.value, rel.value)

@@ -41,7 +41,7 @@ def _inverse_problem(s, leaf):
     return theta, a_true, f, u_true, rng
 
 
-def _dense_torch_loss(theta_t, f, u_obs, s):
+def _dense_torch_loss(theta_t, f, u_obs, s, b_t=None):
     """0.5 |u - u_obs|^2 with A(exp theta) built densely by torch from the same stencil rule
     (edge coefficient = mean of the cells containing the edge, A = h^-2 sum w (e_p - e_q)^2
     terms, ghost endpoints dropped) and solved with torch.linalg.solve."""
@@ -82,6 +82,8 @@ def _dense_torch_loss(theta_t, f, u_obs, s):
                 rows += [lin(*p), lin(*q)]; cols += [lin(*q), lin(*p)]; vals += [-w, -w]
     A = torch.zeros(N, N, dtype=torch.float64)
     A = A.index_put((torch.tensor(rows), torch.tensor(cols)), torch.stack(vals), accumulate=True)
+    if b_t is not None:
+        A = A + torch.diag(b_t)
     u = torch.linalg.solve(A, torch.tensor(f))
     return 0.5 * torch.sum((u - torch.tensor(u_obs)) ** 2)
 
@@ -107,6 +109,32 @@ def test_adjoint_matches_dense_autograd_32():
     print("loss", float(loss), float(ref_loss), "grad rel err", rel(g, ref), flush=True)
     assert abs(float(loss) - float(ref_loss)) <= 1e-9 * abs(float(ref_loss))
     assert rel(g, ref) < 1e-6
+
+
+def test_adjoint_reaction_gradient_and_single_backward():
+    """With a reaction term b that requires a gradient, dL/db (= -lam u) and dL/dtheta match
+    dense torch autograd at 32^2; a second backward pass through the same solve is refused
+    with a clear error (the factorization is released after the first)."""
+    torch = torch_cuda()
+    from paper_1808_01364_amd.adjoint import solve_log_a
+    s = 32
+    theta, a_true, f, u_true, rng = _inverse_problem(s, 8)
+    u_obs = u_true + 0.01 * np.sqrt(np.mean(u_true ** 2)) * rng.standard_normal(s * s)
+    b = 50.0 + 10.0 * np.random.default_rng(9).random(s * s)
+    th = to_dev(theta).reshape(theta.shape).requires_grad_(True)
+    bd = to_dev(b).requires_grad_(True)
+    u = solve_log_a(th, to_dev(f), 2, s, b=bd, leaf=8, eps=1e-6)
+    loss = 0.5 * torch.sum((u - to_dev(u_obs)) ** 2)
+    loss.backward(retain_graph=True)
+    th_c = torch.tensor(theta, requires_grad=True)
+    b_c = torch.tensor(b, requires_grad=True)
+    ref_loss = _dense_torch_loss(th_c, f, u_obs, s, b_c)
+    ref_loss.backward()
+    eg, eb = rel(_host(th.grad), th_c.grad.numpy()), rel(_host(bd.grad), b_c.grad.numpy())
+    print("theta grad", eg, "b grad", eb, flush=True)
+    assert eg < 1e-6 and eb < 1e-6
+    with pytest.raises(RuntimeError, match="second backward"):
+        loss.backward()
 
 
 def test_adjoint_matches_central_differences_256():

@@ -5,8 +5,8 @@ import numpy as np
 import pytest
 
 import oracle as O
-from tests.gpu_common import (compare_choices, gpu_choices, gpu_csr, gpu_factor, problem, rel,
-                              to_dev, torch_cuda)
+from tests.gpu_common import (gpu_choices, gpu_csr, gpu_factor, parity_check, problem, rel, rel_max, to_dev,
+                              torch_cuda)
 
 pytestmark = pytest.mark.gpu
 
@@ -43,34 +43,20 @@ def test_eps0_apply_is_dense_solve(d, s, leaf, precond):
     F.close()
 
 
-def _parity(P, A, n_rhs=3, apply_tol=1e-11, sol_tol=1e-10, replay_ok=0.02, flags=0):
-    F = gpu_factor(P, flags=flags)
-    st = F.stats()
-    ch = gpu_choices(F, st["levels"] - st["sublevels"])
-    orc = O.factor(A, P.d, P.s, P.leaf, P.eps, P.precond)
-    assert st["levels"] - st["sublevels"] == orc.L
-    total, dr, ds = compare_choices(ch, orc)
-    assert (dr + ds) <= replay_ok * max(total, 1), (total, dr, ds)
-    # replay the GPU's discrete choices in the oracle
-    rep = O.factor(A, P.d, P.s, P.leaf, P.eps, P.precond, replay=ch)
-    assert rep.root_size == st["root_size"]
-    rng = np.random.default_rng(11)
-    worst = 0.0
-    for _ in range(n_rhs):
-        r = rng.standard_normal(P.N)
-        zg = _host(F.apply(to_dev(r)))
-        zo = O.apply_inverse(rep, r)
-        worst = max(worst, rel(zg, zo))
-    assert worst < apply_tol, worst
-    # PCG: same iteration count as the replayed oracle, solutions agree
-    f = to_dev(P.f)
-    ug, itg, rrg = F.pcg(f, 1e-12, 300)
-    res = O.pcg(A, P.f, lambda v: O.apply_inverse(rep, v), 1e-12, 300)
-    assert res.converged and rrg <= 1e-12
-    assert itg == res.iters, (itg, res.iters)
-    assert rel(_host(ug), res.u) < sol_tol
-    F.close()
-    return dict(total=total, diff_rank=dr, diff_set=ds, apply_err=worst, iters=itg)
+def _parity(P, A, **kw):
+    return parity_check(P, A, **kw)
+
+
+@pytest.mark.parametrize("d,s,leaf,eps,kind,hi", [
+    (2, 64, 8, 1e-3, "constant", 1.0),       # a = 1 on the 64^2 geometry
+    (2, 64, 8, 1e-3, "two_valued", 10.0),    # the 64^2 geometry at contrast 10
+    (2, 64, 8, 1e-6, "two_valued", 10.0),
+    (3, 12, 4, 1e-3, "constant", 1.0)])
+def test_well_conditioned_apply_100u(d, s, leaf, eps, kind, hi):
+    """On well-conditioned inputs the applies agree with the replayed oracle to 100 u."""
+    P, A = problem(kind, d, s, leaf, eps, seed=0, lo=1.0, hi=hi)
+    out = _parity(P, A, well_conditioned=True)
+    print((d, s, leaf, eps, kind, hi), out)
 
 
 def test_cfg1_parity():
@@ -139,3 +125,63 @@ def test_repeatable_bitwise():
     assert np.array_equal(z1, z2)
     F1.close()
     F2.close()
+
+
+def test_solve_graphs_parity():
+    """RHIF_FLAG_SOLVE_GRAPHS: the applies and PCG iterations replayed as HIP graphs give the
+    same bits as direct launches, also after a second solve into another output buffer
+    (the graphs are captured again for it), and agree with the replayed oracle."""
+    from paper_1808_01364_amd import rhif
+    torch = torch_cuda()
+    P, A = problem("two_valued", 2, 64, 8, 1e-3, seed=0, lo=1e-2, hi=1e2)
+    csr = gpu_csr(P)
+    Fg = gpu_factor(P, csr, flags=rhif.FLAG_SOLVE_GRAPHS)
+    Fd = gpu_factor(P, csr)
+    r = to_dev(np.random.default_rng(3).standard_normal(P.N))
+    zg1, zg2, zd = _host(Fg.apply(r)), _host(Fg.apply(r)), _host(Fd.apply(r))
+    assert np.array_equal(zg1, zd) and np.array_equal(zg2, zd)
+    f = to_dev(P.f)
+    out1 = torch.empty_like(f)
+    out2 = torch.empty_like(f)
+    u1, it1, _ = Fg.pcg(f, 1e-12, 300, out=out1)
+    u2, it2, _ = Fg.pcg(f, 1e-12, 300, out=out2)
+    u3, it3, _ = Fg.pcg(f, 1e-12, 300, out=out1)
+    ud, itd, _ = Fd.pcg(f, 1e-12, 300)
+    assert it1 == it2 == it3 == itd
+    for uu in (u1, u2, u3):
+        assert np.array_equal(_host(uu), _host(ud))
+    st = Fg.stats()
+    ch = gpu_choices(Fg, st["levels"])
+    rep = O.factor(A, P.d, P.s, P.leaf, P.eps, P.precond, replay=ch)
+    res = O.pcg(A, P.f, lambda v: O.apply_inverse(rep, v), 1e-12, 300)
+    assert res.iters == it1 and rel(_host(u2), res.u) < 1e-10
+    Fg.close()
+    Fd.close()
+
+
+def test_apply_several_rhs():
+    """rhif_apply with nrhs = 3 (right-hand sides one after another), into a separate output
+    and in place (r == z), against the replayed oracle at 100 u (a = 1)."""
+    torch = torch_cuda()
+    P, A = problem("constant", 2, 64, 8, 1e-3)
+    F = gpu_factor(P)
+    st = F.stats()
+    rep = O.factor(A, P.d, P.s, P.leaf, P.eps, P.precond, replay=gpu_choices(F, st["levels"]))
+    R = np.random.default_rng(5).standard_normal((3, P.N))
+    Rd = torch.tensor(R, dtype=torch.float64, device="cuda")
+    Z = _host(F.apply(Rd))
+    F.apply(Rd, out=Rd)          # in place
+    Zi = _host(Rd)
+    assert np.array_equal(Z, Zi)
+    for j in range(3):
+        zo = O.apply_inverse(rep, R[j])
+        assert rel(Z[j], zo) <= 100 * U and rel_max(Z[j], zo) <= 100 * U, (j, rel(Z[j], zo))
+    F.close()
+
+
+def test_removed_flag_is_rejected():
+    """Option bit 2 (the former leaf sublevels) is refused before any device work."""
+    from paper_1808_01364_amd import rhif
+    P, A = problem("constant", 2, 16, 4, 1e-3)
+    with pytest.raises(rhif.RhifError, match="not supported"):
+        gpu_factor(P, flags=4)
