@@ -177,6 +177,25 @@ rhif_status rhif_apply(rhif_factor_t f, const double *r, double *z, int32_t nrhs
 rhif_status rhif_pcg_solve(rhif_factor_t f, const double *rhs, double *u, double rtol,
                            int32_t maxit, int32_t *iters, double *relres, hipStream_t s);
 
+/* Largest N that rhif_pcg_solve_noalloc accepts. */
+#define RHIF_NOALLOC_MAX_N (1 << 20)
+
+/* rhif_pcg_solve for callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid allocation calls): the same CG iteration (same kernels in the
+ * same order, so the same iterates), with its workspace (the vectors r, z, p, q and the
+ * reduction scalars, 4 N + 1040 doubles) in a device array of the library sized for
+ * N <= RHIF_NOALLOC_MAX_N (32 MiB, held on every GPU the library runs on until the process
+ * ends). The call makes no allocation (no hipMalloc / hipFree / pinned host memory / event
+ * or graph creation); it reads each scalar back with a copy to the calling thread's host
+ * memory and a synchronization of s, and records no kernel timings.
+ *  rhs [device] N doubles, u [device] N doubles (output), as for rhif_pcg_solve.
+ * Every call on one GPU uses the same workspace: calls that overlap on one GPU (several
+ * host threads, or several streams) race and must be serialized by the caller. The handle
+ * must belong to the current device.
+ * Errors: EINVAL (NULL argument, N > RHIF_NOALLOC_MAX_N, another device), EDEVICE, ENOCONV. */
+rhif_status rhif_pcg_solve_noalloc(rhif_factor_t f, const double *rhs, double *u, double rtol,
+                                   int32_t maxit, int32_t *iters, double *relres, hipStream_t s);
+
 /* Adjoint of the solve with respect to theta = log a (the adjoint-gradient extension of the
  * solver; the operator is eq. (1.1) with the Sec. 3.1 / 3.2 stencils): for every grid cell c,
  *   grad[c] = -a_c * lambda^T (dA/da_c) u

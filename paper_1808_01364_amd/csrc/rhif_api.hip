@@ -1353,9 +1353,31 @@ struct PcgWs {
     double* hsc;   // pinned host scalars, or nullptr
 };
 
+// Workspace of rhif_pcg_solve_noalloc: the CG vectors r, z, p, q (N doubles each), the
+// partial sums of the reductions and the scalar slots, for N <= RHIF_NOALLOC_MAX_N. It is a
+// file-scope device array, so calling the entry point allocates nothing; each GPU holds its
+// own copy for the life of the process. Host code reaches it only through the address that
+// hipGetSymbolAddress returns per device (the array's name is not a device address on the
+// host).
+constexpr int64_t kNoAllocDoubles = 4 * int64_t(RHIF_NOALLOC_MAX_N) + kRedBlocks + 16;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+double* noalloc_scratch(int dev) {
+    static std::mutex mu;
+    static std::map<int, double*> addr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it != addr.end()) return it->second;
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(RHIF_EDEVICE, "hipGetSymbolAddress returned no address for the workspace");
+    addr[dev] = static_cast<double*>(ptr);
+    return static_cast<double*>(ptr);
+}
+
 // The PCG of rhif_pcg_solve on the workspace w (r, z, p, q: N doubles each; part: kRedBlocks
 // doubles of partial sums; sc: 16 scalars). With w.hsc (pinned host scalars) the host waits on
-// events and looks ahead; without it every scalar is read
+// events and looks ahead; without it (the no-allocation entry point) every scalar is read
 // with a copy to host memory of the caller's thread and a stream synchronization, and no
 // graph is used.
 void pcg_run(rhif_factor_s* f, const PcgWs& w, const double* rhs, double* u, double rtol, int32_t maxit,
@@ -1710,6 +1732,40 @@ rhif_status rhif_pcg_solve(rhif_factor_t f, const double* rhs, double* u, double
     ensure_pcg(f);
     const PcgWs w{f->r, f->z, f->p, f->q, f->part, f->sc, f->hsc};
     pcg_run(f, w, rhs, u, rtol, maxit, iters, relres, s);
+    API_END
+}
+
+rhif_status rhif_pcg_solve_noalloc(rhif_factor_t f, const double* rhs, double* u, double rtol, int32_t maxit,
+                                   int32_t* iters, double* relres, hipStream_t s) {
+    API_BEGIN
+    if (!f || !rhs || !u) fail(RHIF_EINVAL, "NULL argument");
+    if (maxit < 0 || !(rtol >= 0.0)) fail(RHIF_EINVAL, "bad maxit or rtol");
+    if (f->g.N > RHIF_NOALLOC_MAX_N) {
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "rhif_pcg_solve_noalloc: N = %lld exceeds RHIF_NOALLOC_MAX_N = %d",
+                      static_cast<long long>(f->g.N), RHIF_NOALLOC_MAX_N);
+        fail(RHIF_EINVAL, buf);
+    }
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != f->device) fail(RHIF_EINVAL, "rhif_pcg_solve_noalloc: the current device is not the handle's");
+    double* base = noalloc_scratch(dev);
+    const int64_t N = f->g.N;
+    const PcgWs w{base, base + N, base + 2 * N, base + 3 * N, base + 4 * N, base + 4 * N + kRedBlocks, nullptr};
+    // the scalar slots start cleared (a fill kernel, not a memset node, so that a caller may
+    // capture the call); the vectors are written before they are read
+    hipLaunchKernelGGL(rhif::k_fill, dim3(1), dim3(256), 0, s, int64_t(16), 0.0, w.sc);
+    HIPCHK(hipGetLastError());
+    // no kernel timing here: its events would be created on demand
+    const bool kt = f->ktimes;
+    f->ktimes = false;
+    try {
+        pcg_run(f, w, rhs, u, rtol, maxit, iters, relres, s);
+    } catch (...) {
+        f->ktimes = kt;
+        throw;
+    }
+    f->ktimes = kt;
     API_END
 }
 

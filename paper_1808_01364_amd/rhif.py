@@ -24,13 +24,14 @@ KERNEL_MASK_SHIFT = 8
 FLAG_SOLVE_GRAPHS = 8
 FLAG_GLOBAL_STAGING = 16
 NUM_KCLASS = 16
+NOALLOC_MAX_N = 1 << 20
 KCLASS_NAMES = ["front_csr", "front_extend", "elim_leaf", "elim_upper", "root", "precond_chol",
                 "precond_scale", "skeletonize", "apply_up", "apply_down", "apply_gather", "spmv",
                 "vector", "-", "-", "-"]
 
 # every function declared in include/rhif.h
 EXPORTED = ["rhif_fd_nnz", "rhif_assemble_fd", "rhif_factor", "rhif_apply", "rhif_pcg_solve",
-            "rhif_matvec", "rhif_grad_log_a", "rhif_stats", "rhif_skeletons", "rhif_destroy",
+            "rhif_pcg_solve_noalloc", "rhif_matvec", "rhif_grad_log_a", "rhif_stats", "rhif_skeletons", "rhif_destroy",
             "rhif_last_error", "rhif_version"]
 
 
@@ -99,6 +100,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rhif_apply.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
     lib.rhif_pcg_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int32, c_i32p,
                                    ctypes.POINTER(ctypes.c_double), vp]
+    lib.rhif_pcg_solve_noalloc.argtypes = lib.rhif_pcg_solve.argtypes
     lib.rhif_matvec.argtypes = [vp, vp, vp, vp]
     lib.rhif_grad_log_a.argtypes = [ctypes.POINTER(Grid), vp, vp, vp, vp, vp]
     lib.rhif_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -258,14 +260,16 @@ class Factor:
         return y
 
     def pcg(self, f, rtol: float = 1e-12, maxit: int = 500, out=None, stream=None,
-            raise_on_noconv: bool = True) -> Tuple[object, int, float]:
-        """(u, iterations, final relative residual) of the PCG solve A u = f."""
+            raise_on_noconv: bool = True, noalloc: bool = False) -> Tuple[object, int, float]:
+        """(u, iterations, final relative residual) of the PCG solve A u = f. noalloc=True calls
+        rhif_pcg_solve_noalloc (workspace in the library's device array; needs `out`)."""
         _need((f, "f", self.N), *([(out, "out", self.N)] if out is not None else []))
         torch = _torch()
         u = out if out is not None else torch.empty_like(f)
         it = ctypes.c_int32()
         rel = ctypes.c_double()
-        st = self._lib.rhif_pcg_solve(self.handle, _ptr(f), _ptr(u), rtol, maxit, ctypes.byref(it), ctypes.byref(rel), _stream(stream))
+        fn = self._lib.rhif_pcg_solve_noalloc if noalloc else self._lib.rhif_pcg_solve
+        st = fn(self.handle, _ptr(f), _ptr(u), rtol, maxit, ctypes.byref(it), ctypes.byref(rel), _stream(stream))
         if st == RHIF_ENOCONV:
             if raise_on_noconv:
                 raise NoConvergence(st, self._lib.rhif_last_error().decode(), it.value, rel.value)
