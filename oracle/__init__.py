@@ -12,6 +12,11 @@ from .rhif_oracle import (  # noqa: F401
     cpqr_id,
     factor,
     apply_inverse,
+    apply_ginv,
+    apply_ginv_t,
+    apply_forward,
+    estimate_ea,
+    estimate_es,
     pcg,
     dense_solve,
     grad_log_a,

@@ -593,6 +593,130 @@ def apply_inverse(F: Factorization, r: np.ndarray) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------------------
+# The two halves of F^-1 = G^-T G^-1, the forward product F x = G G^T x, and the paper's
+# accuracy measures e_a = ||A - F|| / ||A|| and e_s = ||I - G^-1 A G^-T|| (Sec. 3.1, eq. (3.3);
+# Sec. 4), estimated by power iteration.
+# ----------------------------------------------------------------------------------------
+
+def apply_ginv(F: Factorization, r: np.ndarray) -> np.ndarray:
+    """G^-1 r: the up-sweep R_0^T .. R_{L-1}^T of eq. (3.2), then the forward solve with the
+    root factor B_L (A_L = B_L B_L^T), so that apply_ginv_t(apply_ginv(r)) = F^-1 r."""
+    z = np.array(r, dtype=np.float64, copy=True)
+    tri = sla.solve_triangular
+    for lv in F.levels:
+        for c in lv.cells:
+            zi = tri(c.L, z[c.I], lower=True)
+            z[c.I] = zi
+            if len(c.B):
+                z[c.B] -= c.W.T @ zi
+        for g in lv.groups:
+            z[g.idx] = tri(g.L, z[g.idx], lower=True)
+        for sk in lv.skels:
+            if len(sk.tilde) == 0:
+                continue
+            zt = tri(sk.Lt, z[sk.tilde] - sk.T.T @ z[sk.hat], lower=True)
+            z[sk.tilde] = zt
+            if len(sk.hat):
+                z[sk.hat] -= sk.Wt.T @ zt
+    if len(F.root_idx):
+        z[F.root_idx] = tri(F.root_L, z[F.root_idx], lower=True)
+    return z
+
+
+def apply_ginv_t(F: Factorization, y: np.ndarray) -> np.ndarray:
+    """G^-T y: the backward solve with B_L^T, then the down-sweep R_{L-1} .. R_0."""
+    z = np.array(y, dtype=np.float64, copy=True)
+    tri = sla.solve_triangular
+    if len(F.root_idx):
+        z[F.root_idx] = tri(F.root_L.T, z[F.root_idx], lower=False)
+    for lv in reversed(F.levels):
+        for sk in lv.skels:
+            if len(sk.tilde) == 0:
+                continue
+            zt = tri(sk.Lt.T, z[sk.tilde] - (sk.Wt @ z[sk.hat] if len(sk.hat) else 0.0), lower=False)
+            z[sk.tilde] = zt
+            if len(sk.hat):
+                z[sk.hat] -= sk.T @ zt
+        for g in lv.groups:
+            z[g.idx] = tri(g.L.T, z[g.idx], lower=False)
+        for c in lv.cells:
+            z[c.I] = tri(c.L.T, z[c.I] - (c.W @ z[c.B] if len(c.B) else 0.0), lower=False)
+    return z
+
+
+def apply_forward(F: Factorization, x: np.ndarray) -> np.ndarray:
+    """F x = G G^T x, the generalized Cholesky form of eq. (3.3), by undoing each step of the
+    two sweeps in reverse order: G^T x undoes the down-sweep (level 0 first: E_0, then C_0,
+    then K_0, ...) and the backward root solve; G y undoes the forward root solve and the
+    up-sweep (level L-1 first: K^T, C^T, E^T)."""
+    z = np.array(x, dtype=np.float64, copy=True)
+    # G^T x: inverse of the down-sweep, E then C then K at every level, levels 0 .. L-1
+    for lv in F.levels:
+        for c in lv.cells:                 # z_I <- L^T z_I + W z_B  (undoes z_I <- L^-T (z_I - W z_B))
+            z[c.I] = c.L.T @ z[c.I] + (c.W @ z[c.B] if len(c.B) else 0.0)
+        for g in lv.groups:                # z_g <- L_g^T z_g
+            z[g.idx] = g.L.T @ z[g.idx]
+        for sk in lv.skels:                # z_h += T z_t ; z_t <- L~^T z_t + W~ z_h
+            if len(sk.tilde) == 0:
+                continue
+            if len(sk.hat):
+                z[sk.hat] += sk.T @ z[sk.tilde]
+            z[sk.tilde] = sk.Lt.T @ z[sk.tilde] + (sk.Wt @ z[sk.hat] if len(sk.hat) else 0.0)
+    if len(F.root_idx):                    # B_L^T undoes the backward root solve
+        z[F.root_idx] = F.root_L.T @ z[F.root_idx]
+    # G y: the forward root solve, then the up-sweep undone from level L-1 down to 0
+    if len(F.root_idx):
+        z[F.root_idx] = F.root_L @ z[F.root_idx]
+    for lv in reversed(F.levels):
+        for sk in lv.skels:                # z_h += W~^T z_t ; z_t <- L~ z_t + T^T z_h
+            if len(sk.tilde) == 0:
+                continue
+            if len(sk.hat):
+                z[sk.hat] += sk.Wt.T @ z[sk.tilde]
+            z[sk.tilde] = sk.Lt @ z[sk.tilde] + sk.T.T @ z[sk.hat]
+        for g in lv.groups:                # z_g <- L_g z_g
+            z[g.idx] = g.L @ z[g.idx]
+        for c in lv.cells:                 # z_B += W^T z_I ; z_I <- L z_I
+            if len(c.B):
+                z[c.B] += c.W.T @ z[c.I]
+            z[c.I] = c.L @ z[c.I]
+    return z
+
+
+def _power_norm(op, n: int, seed: int = 0, rtol: float = 1e-2, maxit: int = 50) -> float:
+    """||M||_2 of a symmetric operator M = op by power iteration on M^2 (so the dominant
+    eigenvalue in magnitude is found even when M is indefinite): Gaussian start (seed),
+    stop when the estimate changes by less than rtol (relative), at most maxit products."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(n)
+    v /= np.linalg.norm(v)
+    est = 0.0
+    for _ in range(maxit):
+        w = op(op(v))
+        nw = float(np.linalg.norm(w))
+        new = np.sqrt(nw)
+        if nw == 0.0:
+            return 0.0
+        v = w / nw
+        if est > 0.0 and abs(new - est) <= rtol * new:
+            return new
+        est = new
+    return est
+
+
+def estimate_ea(A: sp.csr_matrix, F: Factorization, seed: int = 0, rtol: float = 1e-2, maxit: int = 50) -> float:
+    """e_a = ||A - F||_2 / ||A||_2 (Sec. 4), both norms by power iteration."""
+    na = _power_norm(lambda x: A @ x, A.shape[0], seed, rtol, maxit)
+    nd = _power_norm(lambda x: A @ x - apply_forward(F, x), A.shape[0], seed, rtol, maxit)
+    return nd / na if na > 0 else 0.0
+
+
+def estimate_es(A: sp.csr_matrix, F: Factorization, seed: int = 0, rtol: float = 1e-2, maxit: int = 50) -> float:
+    """e_s = ||I - G^-1 A G^-T||_2 (Sec. 4) by power iteration on the symmetric operator."""
+    return _power_norm(lambda x: x - apply_ginv(F, A @ apply_ginv_t(F, x)), A.shape[0], seed, rtol, maxit)
+
+
+# ----------------------------------------------------------------------------------------
 # Preconditioned CG (Sec. 4: CG with F^-1 to relative residual 1e-12)
 # ----------------------------------------------------------------------------------------
 
