@@ -35,6 +35,8 @@ def _args():
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--side", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP32-mixed leg, the uneven batch and the 2048^2 point")
     ap.add_argument("--cpu-sample-side", type=int, default=512,
                     help="side of the (corner) window of the same field timed with the CPU oracle")
     return ap.parse_args()
@@ -73,6 +75,111 @@ def cpu_baseline(P, sample_side: int):
                       f"of {os.cpu_count()} cores"}
 
 
+HBM_CLASSES = ("apply_up", "apply_down", "apply_gather", "spmv", "vector", "front_csr", "front_extend")
+MFMA_CLASSES = ("elim_leaf", "elim_upper", "root")
+
+
+def class_rows(kernels):
+    """Per kernel class: device time, launches, algorithmic work and the fraction of the
+    roofline that bounds it (HBM bytes for the memory-bound classes, FP64 flops otherwise)."""
+    rows = {}
+    for name, kv in kernels.items():
+        ms = kv["ms"]
+        if ms <= 0:
+            continue
+        if name in HBM_CLASSES:
+            ach = kv["bytes"] / (ms * 1e-3) / 1e9
+            rows[name] = {"ms": round(ms, 4), "launches": kv["launches"], "bound": "hbm", "alg_bytes": kv["bytes"],
+                          "achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4)}
+        else:
+            ach = kv["flops"] / (ms * 1e-3) / 1e12
+            rows[name] = {"ms": round(ms, 4), "launches": kv["launches"],
+                          "bound": "mfma" if name in MFMA_CLASSES else "alu", "alg_flops": kv["flops"],
+                          "achieved_TFLOPs": round(ach, 4), "frac": round(ach / FP64_PEAK_TFLOPS, 5)}
+    return rows
+
+
+def timed_solve(rhif, torch, P, csr, f, precision=0, reps=3):
+    """Median factor and PCG times (ms) of `reps` factor+solve steps after one warm-up."""
+    tf, tp, it = [], [], 0
+    for k in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = rhif.Factor(P.d, P.s, csr, P.leaf, P.eps, 1, precision=precision)
+        t1 = time.perf_counter()
+        u, it, rr = F.pcg(f, 1e-12, 500)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        F.close()
+        if k > 0:
+            tf.append(1e3 * (t1 - t0))
+            tp.append(1e3 * (t2 - t1))
+    import numpy as np
+    return float(np.median(tf)), float(np.median(tp)), it, rr
+
+
+def extras(rhif, torch, P, csr, f):
+    """The FP32-mixed factor on the same workload; the uneven batch (64 problems, sides from
+    {128, 192, 256, 384, 512}, a = exp(2 g), eps 1e-4): plain FP64 one by one against the
+    FP32-mixed autotuned batch; and a problem too large for the on-chip caches (2048^2, the
+    same field recipe, seed 7) with the per-class roofline of its kernels."""
+    import numpy as np
+    from paper_1808_01364_amd import batch
+    from workloads import make_problem
+    from workloads.fields import batch_problem
+    out = {}
+    f64 = timed_solve(rhif, torch, P, csr, f, 0)
+    f32 = timed_solve(rhif, torch, P, csr, f, 1)
+    out["fp32_mixed"] = {
+        "workload": P.name, "fp64": {"t_factor_ms": f64[0], "t_pcg_ms": f64[1], "pcg_iters": f64[2],
+                                     "dofs_per_s": P.N / ((f64[0] + f64[1]) * 1e-3)},
+        "fp32_mixed": {"t_factor_ms": f32[0], "t_pcg_ms": f32[1], "pcg_iters": f32[2], "relres": f32[3],
+                       "dofs_per_s": P.N / ((f32[0] + f32[1]) * 1e-3)}}
+    # the uneven batch
+    probs = [batch_problem(k, 1e-4) for k in range(64)]
+    dofs = sum(q.N for q in probs)
+    dev = "cuda:0"
+    items64 = [batch.BatchItem(2, q.s, torch.tensor(q.a_cells.ravel(), dtype=torch.float64, device=dev),
+                               torch.tensor(q.f, dtype=torch.float64, device=dev), None, q.leaf, q.eps, 0)
+               for q in probs]
+    items32 = [batch.BatchItem(it.dim, it.n, it.a_cells, it.f, None, it.leaf, it.eps, 1) for it in items64]
+    for it in items64[:4]:
+        batch.solve_one(it)                                   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [batch.solve_one(it) for it in items64]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ns, order = batch.autotune(items32)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    bat = batch.solve_many(items32, ns, order)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    out["batch"] = {"problems": len(probs), "dofs": dofs,
+                    "fp64_one_by_one_dofs_per_s": dofs / (t1 - t0),
+                    "fp32_mixed_autotuned_batch_dofs_per_s": dofs / (t3 - t2),
+                    "speedup": (t1 - t0) / (t3 - t2), "autotuned": {"streams": ns, "order": order},
+                    "max_iters": {"fp64": max(r[1] for r in seq), "fp32_batch": max(r[1] for r in bat)},
+                    "worst_relres_fp32_batch": max(r[2] for r in bat)}
+    del items64, items32, seq, bat
+    # out of the on-chip caches: 2048^2
+    Q = make_problem("lognormal", 2, 2048, seed=7, leaf=16, eps=P.eps, sigma=3.0, corr_len=8.0,
+                     name=f"2d-2048-lognormal-s3-eps{P.eps:g}-seed7")
+    aq = torch.tensor(Q.a_cells.ravel(), dtype=torch.float64, device=dev)
+    cq = rhif.assemble_fd(2, Q.s, aq, None)
+    fq = torch.tensor(Q.f, dtype=torch.float64, device=dev)
+    tq = timed_solve(rhif, torch, Q, cq, fq, 0, reps=2)
+    F = rhif.Factor(2, Q.s, cq, Q.leaf, Q.eps, 1, flags=rhif.FLAG_KERNEL_TIMES)
+    F.pcg(fq, 1e-12, 500)
+    rows = class_rows(F.stats()["kernels"])
+    F.close()
+    out["out_of_cache_2048"] = {"workload": Q.name, "N": Q.N, "t_factor_ms": tq[0], "t_pcg_ms": tq[1],
+                                "pcg_iters": tq[2], "dofs_per_s": Q.N / ((tq[0] + tq[1]) * 1e-3),
+                                "classes": rows}
+    return out
+
+
 def main():
     args = _args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -99,10 +206,14 @@ def main():
 
     # warm-up steps time every kernel class with HIP events to find the dominant kernel
     per_class = {}
+    warm_kernels = {}
     for _ in range(max(args.warmup, 1)):
         F, u, it, rr = step(rhif.FLAG_KERNEL_TIMES)
         for name, kv in F.stats()["kernels"].items():
             per_class[name] = per_class.get(name, 0.0) + kv["ms"]
+            acc = warm_kernels.setdefault(name, {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
+            for key in acc:
+                acc[key] += kv[key]
         F.close()
     torch.cuda.synchronize()
     dom = max(per_class, key=per_class.get)
@@ -181,7 +292,10 @@ def main():
     }
     out["roofline"] = roof
     out["kernel_ms_warmup"] = {k: round(v, 4) for k, v in sorted(per_class.items(), key=lambda kv: -kv[1])}
+    out["classes"] = class_rows(warm_kernels)
     F.close()
+    if not args.no_extras:
+        out["extras"] = extras(rhif, torch, P, csr, f)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, min(args.cpu_sample_side, P.s))
     print(json.dumps(out), flush=True)

@@ -55,7 +55,17 @@ typedef struct {
  *            eps = 0 keeps every column (exact nested dissection).
  *  precond   1 = block-Jacobi preconditioning of every separator group before each
  *            skeletonization (the paper's PHIF, Sec. 3.1 step 2); 0 = plain HIF.
- *  precision 0 = FP64 throughout (the only value accepted by this version).
+ *  precision 0 = FP64 throughout.
+ *            1 = FP32-mixed: the interpolative decompositions (the matrix M = A[R_g, g], its
+ *            column-pivoted QR and T = R11^-1 R12) in FP32; everything else FP64.
+ *            2 = as 1, and the Schur products S = A_BB - W^T W of the cell eliminations
+ *            (level 0 and the final product of the upper levels) on the FP32 matrix cores
+ *            with FP32 accumulation.
+ *            In both, every Cholesky factor (cell interiors, block Jacobi, skeleton
+ *            eliminations, root), the stored factor and the apply stay FP64, and
+ *            rhif_pcg_solve on such a factor uses the flexible (Polak-Ribiere) CG update
+ *            with FP64 residuals and inner products, so that CG refines the solution to the
+ *            requested tolerance.
  *  flags     bit 0: record per-phase device times (adds one sync per phase). */
 typedef struct {
     int32_t leaf;
@@ -177,13 +187,32 @@ rhif_status rhif_apply(rhif_factor_t f, const double *r, double *z, int32_t nrhs
 rhif_status rhif_pcg_solve(rhif_factor_t f, const double *rhs, double *u, double rtol,
                            int32_t maxit, int32_t *iters, double *relres, hipStream_t s);
 
+/* One half of the factor apply: F^-1 = G^-T G^-1 with F = G G^T (eq. (3.3)).
+ *  which = 0: z = G^-1 r (the up-sweep R_0^T .. R_{L-1}^T of eq. (3.2), then the forward
+ *             solve with the root factor B_L, A_L = B_L B_L^T);
+ *  which = 1: z = G^-T r (the backward solve with B_L^T, then the down-sweep).
+ *  r, z [device] N doubles; r == z is allowed. Stream-ordered. Errors: EINVAL, EDEVICE. */
+rhif_status rhif_apply_half(rhif_factor_t f, const double *r, double *z, int32_t which, hipStream_t s);
+
+/* The solve error e_s = ||I - G^-1 A G^-T||_2 of the factorization (Sec. 4, the paper's
+ * measure of preconditioner quality), by power iteration on the square of the symmetric
+ * operator I - G^-1 A G^-T from the start vector v0: each iteration applies the operator
+ * twice and normalizes; it stops when the estimate changes by at most rtol (relative) or
+ * after maxit iterations.
+ *  v0 [device] N doubles (the caller's random start vector; not modified)
+ *  es [host] the estimate; iters [host, may be NULL] iterations taken.
+ * Synchronizes the stream once per iteration. Errors: EINVAL (zero start, bad maxit/rtol),
+ * EDEVICE. */
+rhif_status rhif_estimate_es(rhif_factor_t f, const double *v0, int32_t maxit, double rtol, double *es,
+                             int32_t *iters, hipStream_t s);
+
 /* Largest N that rhif_pcg_solve_noalloc accepts. */
 #define RHIF_NOALLOC_MAX_N (1 << 20)
 
 /* rhif_pcg_solve for callers that cannot allocate (code under HIP graph capture, serving
  * loops, harnesses that forbid allocation calls): the same CG iteration (same kernels in the
  * same order, so the same iterates), with its workspace (the vectors r, z, p, q and the
- * reduction scalars, 4 N + 1040 doubles) in a device array of the library sized for
+ * reduction scalars, 4 N + 2064 doubles) in a device array of the library sized for
  * N <= RHIF_NOALLOC_MAX_N (32 MiB, held on every GPU the library runs on until the process
  * ends). The call makes no allocation (no hipMalloc / hipFree / pinned host memory / event
  * or graph creation); it reads each scalar back with a copy to the calling thread's host

@@ -19,6 +19,7 @@
 namespace rhif {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kWG = 256;
 constexpr int kWaves = kWG / 64;
@@ -321,9 +322,10 @@ __device__ __forceinline__ void wg_potrf_partial(double* __restrict__ A, int ld,
 // R_jj > eps R_11. Returns the rank k; row i <= j of column perm[j] then holds R[i][j].
 // part: 2 * 256 * ceil(n / cw) doubles.
 // ---------------------------------------------------------------------------------------
-template <int UR>
-__device__ __forceinline__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int r, int n, double eps, int* pos,
-                                            int* perm, double* part) {
+template <int UR, typename MR>
+__device__ __forceinline__ int wg_cpqr_rows(MR* __restrict__ M, int ldr, int r, int n, double eps, int* pos,
+                                            int* perm, double* part_) {
+    MR* part = reinterpret_cast<MR*>(part_);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int cw = 1;
     while (cw < n && cw < 64) cw <<= 1;
@@ -332,19 +334,19 @@ __device__ __forceinline__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int
     const int cs = (r + nrc - 1) / nrc;
     const int i0 = rc * cs, i1 = min(r, i0 + cs);
     const int nblk = (n + cw - 1) / cw;
-    double* pd = part;                 // dot partials  [blk][rc][cl]
-    double* pn = part + nblk * kWG;    // norm partials [blk][rc][cl]
+    MR* pd = part;                 // dot partials  [blk][rc][cl]
+    MR* pn = part + nblk * kWG;    // norm partials [blk][rc][cl]
     for (int c = tid; c < n; c += kWG) {
         pos[c] = c;
         perm[c] = c;
     }
     for (int blk = 0; blk < nblk; ++blk) {
         const int c = blk * cw + cl;
-        double sq = 0.0, sq1 = 0.0;
+        MR sq = 0.0, sq1 = 0.0;
         if (c < n) {
             int i = i0;
             for (; i + 1 < i1; i += 2) {
-                const double v = M[static_cast<size_t>(i) * ldr + c], u = M[static_cast<size_t>(i + 1) * ldr + c];
+                const MR v = M[static_cast<size_t>(i) * ldr + c], u = M[static_cast<size_t>(i + 1) * ldr + c];
                 sq += v * v;
                 sq1 += u * u;
             }
@@ -354,18 +356,18 @@ __device__ __forceinline__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int
     }
     __syncthreads();
     const int kmax = min(r, n);
-    double r11 = 0.0;
+    MR r11 = 0.0;
     int k = 0;
     for (int j = 0; j < kmax; ++j) {
         // (a) pivot among the columns with pos >= j; every wave reduces the same partials in
         //     the same order, so all of them reach the same choice without a barrier
-        double best = -1.0;
+        MR best = -1;
         int bpos = 0x7fffffff, bc = -1;
         for (int c = lane; c < n; c += 64) {
             const int pp = pos[c];
             if (pp < j) continue;
             const int blk = c / cw, sl = c % cw;
-            double v = 0.0;
+            MR v = 0.0;
             for (int q = 0; q < nrc; ++q) v += pn[blk * kWG + q * cw + sl];
             if (v > best || (v == best && pp < bpos)) {
                 best = v;
@@ -375,7 +377,7 @@ __device__ __forceinline__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
-            const double ob = __shfl_xor(best, off, 64);
+            const MR ob = __shfl_xor(best, off, 64);
             const int op = __shfl_xor(bpos, off, 64);
             const int oc = __shfl_xor(bc, off, 64);
             if (ob > best || (ob == best && op < bpos)) {
@@ -384,15 +386,15 @@ __device__ __forceinline__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int
                 bc = oc;
             }
         }
-        const double nrm = sqrt(best);
+        const MR nrm = sqrt(best);
         const int pc = bc;
         if (j == 0) r11 = nrm;
-        if (!(nrm > eps * r11)) break;
+        if (!(nrm > static_cast<MR>(eps) * r11)) break;
         // (b) reflector of column pc over rows j..: v = (x0 - alpha, x1, ...), beta = 2 / v^T v
-        const double x0 = M[static_cast<size_t>(j) * ldr + pc];
-        const double alpha = -copysign(nrm, x0);
-        const double v0 = x0 - alpha;
-        const double beta = 1.0 / (nrm * (nrm + fabs(x0)));
+        const MR x0 = M[static_cast<size_t>(j) * ldr + pc];
+        const MR alpha = -copysign(nrm, x0);
+        const MR v0 = x0 - alpha;
+        const MR beta = MR(1) / (nrm * (nrm + fabs(x0)));
         // rows of this thread's chunk below row j (row j itself is handled apart)
         const bool has_j = (i0 <= j && j < i1);
         const int ib = max(i0, j + 1);
@@ -400,16 +402,16 @@ __device__ __forceinline__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int
         //     same answer before and after the position update of this step)
         for (int blk = 0; blk < nblk; ++blk) {
             const int c = blk * cw + cl;
-            double w = 0.0;
+            MR w = 0.0;
             if (c < n && c != pc && pos[c] >= j) {
-                double w1 = 0.0, w2 = 0.0, w3 = 0.0;
+                MR w1 = 0.0, w2 = 0.0, w3 = 0.0;
                 if (has_j) w = v0 * M[static_cast<size_t>(j) * ldr + c];
                 // rows by rounds of UR (then at most one of eight), every load of a round issued
                 // before its products; row i goes to the accumulator of i mod 4
                 auto round = [&](auto cu, int i) {
                     constexpr int R = decltype(cu)::value;
-                    const double* Mi = M + static_cast<size_t>(i) * ldr;
-                    double a[R], b[R];
+                    const MR* Mi = M + static_cast<size_t>(i) * ldr;
+                    MR a[R], b[R];
 #pragma unroll
                     for (int u = 0; u < R; ++u) {
                         a[u] = Mi[u * ldr + pc];
@@ -439,15 +441,15 @@ __device__ __forceinline__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int
         for (int blk = 0; blk < nblk; ++blk) {
             const int c = blk * cw + cl;
             if (c < n && c != pc && pos[c] >= j) {
-                double f = 0.0;
+                MR f = 0.0;
                 for (int q = 0; q < nrc; ++q) f += pd[blk * kWG + q * cw + cl];
                 f *= beta;
                 if (has_j) M[static_cast<size_t>(j) * ldr + c] -= f * v0;
-                double sq = 0.0, sq1 = 0.0, sq2 = 0.0, sq3 = 0.0;
+                MR sq = 0.0, sq1 = 0.0, sq2 = 0.0, sq3 = 0.0;
                 auto round = [&](auto cu, int i) {
                     constexpr int R = decltype(cu)::value;
-                    double* Mi = M + static_cast<size_t>(i) * ldr;
-                    double a[R], b[R];
+                    MR* Mi = M + static_cast<size_t>(i) * ldr;
+                    MR a[R], b[R];
 #pragma unroll
                     for (int u = 0; u < R; ++u) {
                         a[u] = Mi[u * ldr + pc];
@@ -473,7 +475,7 @@ __device__ __forceinline__ int wg_cpqr_rows(double* __restrict__ M, int ldr, int
                     i += 8;
                 }
                 for (; i < i1; ++i) {
-                    const double nv = M[static_cast<size_t>(i) * ldr + c] - f * M[static_cast<size_t>(i) * ldr + pc];
+                    const MR nv = M[static_cast<size_t>(i) * ldr + c] - f * M[static_cast<size_t>(i) * ldr + pc];
                     M[static_cast<size_t>(i) * ldr + c] = nv;
                     sq += nv * nv;
                 }
@@ -908,6 +910,9 @@ __global__ __launch_bounds__(256) void k_potrf_batch(const FrontDesc* __restrict
 // factors the current block. Waves 1..3 also store block J's L_JJ and Li_J from LDS during
 // round J + 1, so that wave 0 only factors.
 // ---------------------------------------------------------------------------------------
+// F32: the Schur product W^T W on the FP32 matrix cores with FP32 accumulation (operands
+// rounded to FP32; L, W^T and S stay FP64).
+template <bool F32>
 __global__ __launch_bounds__(256) void k_leaf_elim(const FrontDesc* __restrict__ desc, double* __restrict__ pool,
                                                    double* __restrict__ linv, int tpw, int level,
                                                    unsigned long long* err, int32_t* __restrict__ ext) {
@@ -937,8 +942,14 @@ __global__ __launch_bounds__(256) void k_leaf_elim(const FrontDesc* __restrict__
     const int ntl = ntile * (ntile + 1) / 2;
     const bool inc = ntl <= 3 * kLeafTilesPerWave;
     v4d sacc[kLeafTilesPerWave];
+    v4f saccf[kLeafTilesPerWave];
 #pragma unroll
-    for (int u = 0; u < kLeafTilesPerWave; ++u) sacc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int u = 0; u < kLeafTilesPerWave; ++u) {
+        sacc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+        saccf[u] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    // row of register q of a 16 x 16 product tile (FP32: 4 (lane / 16) + q; FP64: lane / 16 + 4 q)
+    auto prow = [&](int q) { return F32 ? 4 * lh + q : lh + 4 * q; };
     auto tile_ij = [](int t, int& ti, int& tj) {
         ti = static_cast<int>((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
         while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
@@ -956,9 +967,15 @@ __global__ __launch_bounds__(256) void k_leaf_elim(const FrontDesc* __restrict__
             const double* Pa = smem + 10 * TS + static_cast<size_t>(ti & 3) * tpw * TS + (ti >> 2) * TS;
             const double* Pb = smem + 10 * TS + static_cast<size_t>(tj & 3) * tpw * TS + (tj >> 2) * TS;
 #pragma unroll
-            for (int kk = 0; kk < 16; kk += 4)
-                sacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(Pa[lr * 17 + kk + lh], Pb[lr * 17 + kk + lh], sacc[u],
-                                                              0, 0, 0);
+            for (int kk = 0; kk < 16; kk += 4) {
+                if constexpr (F32)
+                    saccf[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(static_cast<float>(Pa[lr * 17 + kk + lh]),
+                                                                   static_cast<float>(Pb[lr * 17 + kk + lh]),
+                                                                   saccf[u], 0, 0, 0);
+                else
+                    sacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(Pa[lr * 17 + kk + lh], Pb[lr * 17 + kk + lh],
+                                                                  sacc[u], 0, 0, 0);
+            }
         }
     };
     auto prefetch = [&](int J, int t0, int stride) {
@@ -1110,9 +1127,10 @@ __global__ __launch_bounds__(256) void k_leaf_elim(const FrontDesc* __restrict__
             const int c = tj * 16 + lr;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int r = ti * 16 + lh + 4 * q;
+                const int r = ti * 16 + prow(q);
+                const double sq = F32 ? static_cast<double>(saccf[u][q]) : sacc[u][q];
                 if (r < m && c < m && r >= c) {
-                    const double v = S[r + static_cast<size_t>(c) * ld] - sacc[u][q];
+                    const double v = S[r + static_cast<size_t>(c) * ld] - sq;
                     S[r + static_cast<size_t>(c) * ld] = v;
                     S[c + static_cast<size_t>(r) * ld] = v;
                 }
@@ -1126,15 +1144,23 @@ __global__ __launch_bounds__(256) void k_leaf_elim(const FrontDesc* __restrict__
         tile_ij(t, ti, tj);
         const int c = tj * 16 + lr;
         v4d s0 = {0.0, 0.0, 0.0, 0.0}, acc = {0.0, 0.0, 0.0, 0.0};
+        v4f accf = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int r = ti * 16 + lh + 4 * q;
+            const int r = ti * 16 + prow(q);
             if (r < m && c < m) s0[q] = S[max(r, c) + static_cast<size_t>(min(r, c)) * ld];
         }
         const int ra = ti * 16 + lr, rb = tj * 16 + lr;
         const double* Wa = Wt + ra;
         const double* Wb = Wt + rb;
         const bool oka = ra < m, okb = rb < m;
+        auto mac = [&](double av, double bv) {
+            if constexpr (F32)
+                accf = __builtin_amdgcn_mfma_f32_16x16x4f32(static_cast<float>(av), static_cast<float>(bv), accf, 0,
+                                                           0, 0);
+            else
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        };
         int k0 = 0;
         for (; k0 + 16 <= p; k0 += 16) {
             double av[4], bv[4];
@@ -1145,17 +1171,21 @@ __global__ __launch_bounds__(256) void k_leaf_elim(const FrontDesc* __restrict__
                 bv[u] = okb ? Wb[col] : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+            for (int u = 0; u < 4; ++u) mac(av[u], bv[u]);
         }
         for (; k0 < p; k0 += 4) {
             const int kq = k0 + lh;
             const double av = (oka && kq < p) ? Wa[static_cast<size_t>(kq) * ld] : 0.0;
             const double bv = (okb && kq < p) ? Wb[static_cast<size_t>(kq) * ld] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            mac(av, bv);
+        }
+        if constexpr (F32) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = static_cast<double>(accf[q]);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int r = ti * 16 + lh + 4 * q;
+            const int r = ti * 16 + prow(q);
             if (r < m && c < m && r >= c) {
                 const double v = s0[q] - acc[q];
                 S[r + static_cast<size_t>(c) * ld] = v;
@@ -1164,6 +1194,11 @@ __global__ __launch_bounds__(256) void k_leaf_elim(const FrontDesc* __restrict__
         }
     }
 }
+
+template __global__ void k_leaf_elim<false>(const FrontDesc*, double*, double*, int, int, unsigned long long*,
+                                            int32_t*);
+template __global__ void k_leaf_elim<true>(const FrontDesc*, double*, double*, int, int, unsigned long long*,
+                                           int32_t*);
 
 // ---------------------------------------------------------------------------------------
 // The cell elimination of eq. (2.1) in three launches, for levels with few cells (one
@@ -1338,6 +1373,10 @@ __global__ __launch_bounds__(256) void k_trsm_rows(const FrontDesc* __restrict__
 // S = A_BB - W^T W on the 32 x 32 block (bi, bj), bi >= bj (block y of the cell, row-major
 // over the lower triangle); each wave one 16 x 16 tile of the lower triangle. The old values
 // are read from the lower triangle; each lower element is written with its mirror.
+// F32: the product W^T W on the FP32 matrix cores with FP32 accumulation (operands rounded
+// to FP32; S and the subtraction stay FP64). The FP32 16 x 16 x 4 product leaves row
+// 4 (lane / 16) + q of its tile in register q; the FP64 one row lane / 16 + 4 q.
+template <bool F32>
 __global__ __launch_bounds__(256) void k_syrk_schur(const FrontDesc* __restrict__ desc, double* __restrict__ pool) {
     const FrontDesc fd = desc[blockIdx.x];
     const int p = fd.p, ms = fd.n - fd.p, ld = fd.ld;
@@ -1356,11 +1395,13 @@ __global__ __launch_bounds__(256) void k_syrk_schur(const FrontDesc* __restrict_
     const double* Wt = A + p;
     const bool act = ti * 16 < ms && tj * 16 < ms && ti >= tj;
     const int c = tj * 16 + lr;
+    auto row_of = [&](int q) { return F32 ? ti * 16 + 4 * lh + q : ti * 16 + lh + 4 * q; };
     v4d s0 = {0.0, 0.0, 0.0, 0.0}, acc = {0.0, 0.0, 0.0, 0.0};
+    v4f accf = {0.0f, 0.0f, 0.0f, 0.0f};
     if (act) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int r = ti * 16 + lh + 4 * q;
+            const int r = row_of(q);
             if (r < ms && c < ms) s0[q] = S[max(r, c) + static_cast<size_t>(min(r, c)) * ld];
         }
         const int ra = ti * 16 + lr, rb = tj * 16 + lr;
@@ -1369,14 +1410,22 @@ __global__ __launch_bounds__(256) void k_syrk_schur(const FrontDesc* __restrict_
             const int k = k0 + lh;
             const double av = (ra < ms && k < p) ? Wt[ra + static_cast<size_t>(k) * ld] : 0.0;
             const double bv = (rb < ms && k < p) ? Wt[rb + static_cast<size_t>(k) * ld] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            if constexpr (F32)
+                accf = __builtin_amdgcn_mfma_f32_16x16x4f32(static_cast<float>(av), static_cast<float>(bv), accf, 0,
+                                                           0, 0);
+            else
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+        if constexpr (F32) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = static_cast<double>(accf[q]);
         }
     }
     // each lower element (r >= c) is written with its mirror by the one lane that read it
     if (act) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int r = ti * 16 + lh + 4 * q;
+            const int r = row_of(q);
             if (r < ms && c < ms && r >= c) {
                 const double v = s0[q] - acc[q];
                 S[r + static_cast<size_t>(c) * ld] = v;
@@ -1385,6 +1434,8 @@ __global__ __launch_bounds__(256) void k_syrk_schur(const FrontDesc* __restrict_
         }
     }
 }
+template __global__ void k_syrk_schur<false>(const FrontDesc*, double*);
+template __global__ void k_syrk_schur<true>(const FrontDesc*, double*);
 
 // ---------------------------------------------------------------------------------------
 // Block-Jacobi step (Sec. 2.3), part 1: for every separator group g, gather its diagonal
@@ -1603,7 +1654,8 @@ __device__ __forceinline__ void build_row_table(const SkelDesc& g, const int32_t
 //      [M (rmax x (nmax|1))] | [G (nmax^2)] | potrf scratch
 // SM / SG: M / G staged in LDS (else in the global pools), fixed at compile time so that
 // every access has a known address space.
-template <bool SM, bool SG>
+// MR: arithmetic of the ID (M, its QR and T); double, or float in the mixed-precision form.
+template <bool SM, bool SG, typename MR>
 __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t* __restrict__ cgptr,
                                                 const int32_t* __restrict__ cgl, const int32_t* __restrict__ cgoff,
                                                 const CellRef* __restrict__ cells, double* __restrict__ F,
@@ -1621,8 +1673,10 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
     int* rwl = reinterpret_cast<int*>(smem + ipd);
     double* part = smem + ipd + rmax;
     double* after = part + 2 * kWG * nbm;
-    double* __restrict__ M = SM ? after : Mpool + g.moff;
-    double* gl = SM ? after + static_cast<size_t>(rmax) * (nmax | 1) : after;
+    MR* __restrict__ M = SM ? reinterpret_cast<MR*>(after) : reinterpret_cast<MR*>(Mpool + g.moff);
+    // M occupies rmax (nmax | 1) values of MR, rounded up to whole doubles
+    const size_t m_doubles = (static_cast<size_t>(rmax) * (nmax | 1) * sizeof(MR) + sizeof(double) - 1) / sizeof(double);
+    double* gl = SM ? after + m_doubles : after;
     double* __restrict__ Gw = SG ? gl : Gpool + g.goff;
     double* psmem = SG ? gl + static_cast<size_t>(nmax) * nmax : gl;
     const CellRef c0 = cells[g.cell[0]];
@@ -1652,16 +1706,16 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            if (dst[u] >= 0) M[dst[u]] = v[u];
+            if (dst[u] >= 0) M[dst[u]] = static_cast<MR>(v[u]);
     }
     __syncthreads();
     // 2. ID: rank k, pivot order, and T = R11^-1 R12 solved in place over R12
-    const int k = wg_cpqr_rows<SM ? 8 : 16>(M, ldr, r, n, eps, pos, perm, part);
+    const int k = wg_cpqr_rows<SM ? 8 : 16, MR>(M, ldr, r, n, eps, pos, perm, part);
     const int nr = n - k;
     // column-oriented back substitution, every (row, column) update of a step in parallel:
     // t_i = x_i / R_ii, then x_e -= R_ei t_i for e < i
     for (int i = k - 1; i >= 0; --i) {
-        const double* Ri = M + static_cast<size_t>(i) * ldr;
+        const MR* Ri = M + static_cast<size_t>(i) * ldr;
         const int pi = perm[i];
         for (int a = tid; a < nr; a += kWG) {
             const int pa = perm[k + a];
@@ -1681,7 +1735,7 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
     double* T = Tpool + g.toff;
     for (int e = tid; e < k * nr; e += kWG) {
         const int i = e % k, a = e / k;
-        T[e] = M[static_cast<size_t>(i) * ldr + perm[k + a]];
+        T[e] = static_cast<double>(M[static_cast<size_t>(i) * ldr + perm[k + a]]);
     }
     // 3. the zeroed blocks of eq. (2.2) in the order (redundant, skeleton). G first holds the
     //    whole permuted A_gg; then V = A_ht - A_hh T replaces the lower (h, t) block (A_ht
@@ -1713,10 +1767,10 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
         double v = Gw[(nr + c) + static_cast<size_t>(a) * n], v1 = 0.0;
         int q = 0;
         for (; q + 1 < k; q += 2) {
-            v -= Gc[static_cast<size_t>(q) * n] * M[static_cast<size_t>(q) * ldr + pa];
-            v1 -= Gc[static_cast<size_t>(q + 1) * n] * M[static_cast<size_t>(q + 1) * ldr + pa];
+            v -= Gc[static_cast<size_t>(q) * n] * static_cast<double>(M[static_cast<size_t>(q) * ldr + pa]);
+            v1 -= Gc[static_cast<size_t>(q + 1) * n] * static_cast<double>(M[static_cast<size_t>(q + 1) * ldr + pa]);
         }
-        if (q < k) v -= Gc[static_cast<size_t>(q) * n] * M[static_cast<size_t>(q) * ldr + pa];
+        if (q < k) v -= Gc[static_cast<size_t>(q) * n] * static_cast<double>(M[static_cast<size_t>(q) * ldr + pa]);
         Gw[(nr + c) + static_cast<size_t>(a) * n] = v + v1;
     }
     __syncthreads();
@@ -1726,9 +1780,9 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
         const int pa = perm[k + a], pb = perm[k + b];
         double v = Gw[a + static_cast<size_t>(b) * n], v1 = 0.0;
         for (int c = 0; c < k; ++c) {
-            const double* Tc = M + static_cast<size_t>(c) * ldr;
-            v -= Tc[pa] * Gw[(nr + c) + static_cast<size_t>(b) * n];
-            v1 -= Gw[a + static_cast<size_t>(nr + c) * n] * Tc[pb];
+            const MR* Tc = M + static_cast<size_t>(c) * ldr;
+            v -= static_cast<double>(Tc[pa]) * Gw[(nr + c) + static_cast<size_t>(b) * n];
+            v1 -= Gw[a + static_cast<size_t>(nr + c) * n] * static_cast<double>(Tc[pb]);
         }
         Gw[a + static_cast<size_t>(b) * n] = v + v1;
     }
@@ -1753,7 +1807,7 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
 // compiled for kSkelWavesMany waves per SIMD (fewer registers), for launches with many more
 // groups than compute units, where more resident groups per CU hide the latency of each.
 // One kernel per form, so that each keeps the register budget of its own code.
-template <int STAGED>
+template <int STAGED, typename MR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STAGED == 4 ? kSkelWavesMany : 1))) void k_skeletonize(const SkelDesc* __restrict__ sd, const int32_t* __restrict__ cgptr,
                                                      const int32_t* __restrict__ cgl, const int32_t* __restrict__ cgoff,
                                                      const CellRef* __restrict__ cells, double* __restrict__ F,
@@ -1764,19 +1818,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STAGED == 4
                                                      unsigned long long* err) {
     extern __shared__ double smem[];
     const SkelDesc g = sd[blockIdx.x];
-    skeletonize_one<STAGED != 0, STAGED >= 3>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout,
+    skeletonize_one<STAGED != 0, STAGED >= 3, MR>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout,
                                               pout, panel_cap, nmax, rmax, level, err, smem);
 }
 
-#define RHIF_SKEL_INST(S)                                                                                          \
-    template __global__ void k_skeletonize<S>(const SkelDesc*, const int32_t*, const int32_t*, const int32_t*,     \
-                                              const CellRef*, double*, double*, double*, double*, double*, double, \
-                                              int32_t*, int32_t*, int, int, int, int, unsigned long long*);
-RHIF_SKEL_INST(0)
-RHIF_SKEL_INST(1)
-RHIF_SKEL_INST(3)
-RHIF_SKEL_INST(4)
+#define RHIF_SKEL_INST(S, MR)                                                                                      \
+    template __global__ void k_skeletonize<S, MR>(const SkelDesc*, const int32_t*, const int32_t*, const int32_t*, \
+                                                  const CellRef*, double*, double*, double*, double*, double*,     \
+                                                  double, int32_t*, int32_t*, int, int, int, int,                 \
+                                                  unsigned long long*);
+RHIF_SKEL_INST(0, double)
+RHIF_SKEL_INST(1, double)
+RHIF_SKEL_INST(3, double)
+RHIF_SKEL_INST(4, double)
+RHIF_SKEL_INST(0, float)
+RHIF_SKEL_INST(1, float)
+RHIF_SKEL_INST(3, float)
+RHIF_SKEL_INST(4, float)
 #undef RHIF_SKEL_INST
+
 
 // ---------------------------------------------------------------------------------------
 // Factor apply (eq. (3.2)). One workgroup per block; z_I and z_B are staged in LDS (or
@@ -2529,25 +2589,35 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
         case 2: sc[3] = s; if (host_out) host_out[0] = s; break;
         case 3: sc[0] = s; break;
         case 4: sc[4] = s; sc[5] = s / sc[0]; sc[0] = s; break;
+        case 5: sc[7] = s; break;                                        // r_new . z_old
+        case 6: sc[4] = s; sc[5] = (s - sc[7]) / sc[0]; sc[0] = s; break;  // Polak-Ribiere beta
         default: break;
     }
 }
 
 // u += alpha p ; r -= alpha q ; partial sums of r . r
+// With zold (the flexible, Polak-Ribiere form of the iteration), also partial sums of
+// r_new . zold into part2.
 __global__ __launch_bounds__(256) void k_axpy2(int64_t N, const double* __restrict__ sc, const double* __restrict__ p,
                                                const double* __restrict__ q, double* __restrict__ u, double* __restrict__ r,
-                                               double* __restrict__ part) {
+                                               double* __restrict__ part, const double* __restrict__ zold,
+                                               double* __restrict__ part2) {
     __shared__ double red[kWaves];
     const double alpha = sc[2];
-    double acc = 0.0;
+    double acc = 0.0, acc2 = 0.0;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; i < N; i += static_cast<int64_t>(gridDim.x) * kWG) {
         u[i] += alpha * p[i];
         const double ri = r[i] - alpha * q[i];
         r[i] = ri;
         acc += ri * ri;
+        if (zold != nullptr) acc2 += ri * zold[i];
     }
     const double t = block_sum(acc, red);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
+    if (zold != nullptr) {
+        const double t2 = block_sum(acc2, red);
+        if (threadIdx.x == 0) part2[blockIdx.x] = t2;
+    }
 }
 
 // p = z + beta p
@@ -2563,6 +2633,12 @@ __global__ __launch_bounds__(256) void k_copy(int64_t N, const double* __restric
         y[i] = x[i];
 }
 
+// y = a x + b y
+__global__ __launch_bounds__(256) void k_axpby(int64_t N, double a, const double* __restrict__ x, double b,
+                                               double* __restrict__ y) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; i < N; i += static_cast<int64_t>(gridDim.x) * kWG)
+        y[i] = a * x[i] + b * y[i];
+}
 __global__ __launch_bounds__(256) void k_fill(int64_t N, double v, double* __restrict__ y) {
     for (int64_t i = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; i < N; i += static_cast<int64_t>(gridDim.x) * kWG)
         y[i] = v;

@@ -23,11 +23,13 @@ __global__ void k_front_extend(const Tile* tiles, const CellRef* cells, const in
                                const CellRef* child, const double* Fc, double* F);
 __global__ void k_potrf_batch(const FrontDesc* desc, double* pool, int panel_cap, int level, int step,
                               unsigned long long* err, int32_t* ext, double* linv);
+template <bool F32>
 __global__ void k_leaf_elim(const FrontDesc* desc, double* pool, double* linv, int tpw, int level,
                             unsigned long long* err, int32_t* ext);
 __global__ void k_chol_lead(const FrontDesc* desc, double* pool, double* linv, int lds_pmax, int level, int step,
                             unsigned long long* err, int32_t* ext);
 __global__ void k_trsm_rows(const FrontDesc* desc, double* pool, const double* linv, int pstride);
+template <bool F32>
 __global__ void k_syrk_schur(const FrontDesc* desc, double* pool);
 __global__ void k_precond_groups(const SepDesc* sd, const CellRef* cells, const double* F, double* Lg, double* Li,
                                  int panel_cap, int lds_n, int level, unsigned long long* err);
@@ -35,7 +37,7 @@ __global__ void k_precond_scale(const CellScaleDesc* cd, const CellGroup* cg, co
                                 double* F, int pstride);
 // waves per SIMD of the skeletonization form for launches with many groups per CU
 constexpr int kSkelWavesMany = 4;
-template <int STAGED>
+template <int STAGED, typename MR>
 __global__ void k_skeletonize(const SkelDesc* sd, const int32_t* cgptr, const int32_t* cgl, const int32_t* cgoff,
                               const CellRef* cells, double* F,
                               double* Mpool, double* Tpool, double* Gpool, double* skli, double eps, int32_t* kout,
@@ -66,10 +68,11 @@ __global__ void k_spmv_dot(int64_t N, const int32_t* rp, const int32_t* ci, cons
 __global__ void k_dot(int64_t N, const double* x, const double* y, double* part);
 __global__ void k_finalize(const double* part, int nparts, int mode, double* sc, double* host_out);
 __global__ void k_axpy2(int64_t N, const double* sc, const double* p, const double* q, double* u, double* r,
-                        double* part);
+                        double* part, const double* zold, double* part2);
 __global__ void k_update_p(int64_t N, const double* sc, const double* z, double* p);
 __global__ void k_copy(int64_t N, const double* x, double* y);
 __global__ void k_fill(int64_t N, double v, double* y);
+__global__ void k_axpby(int64_t N, double a, const double* x, double b, double* y);
 __global__ void k_set_u64(unsigned long long* p, unsigned long long v);
 
 constexpr int kMaxSkelSegs = 64;     // row segments of one skeletonized group (2 x 26 in 3D)

@@ -611,21 +611,24 @@ void set_kernel_attributes() {
         const int bytes = kLdsMaxDoubles * static_cast<int>(sizeof(double));
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_precond_scale),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_skeletonize<0>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_skeletonize<1>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_skeletonize<3>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_skeletonize<4>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        for (const void* k : {reinterpret_cast<const void*>(&rhif::k_skeletonize<0, double>),
+                              reinterpret_cast<const void*>(&rhif::k_skeletonize<1, double>),
+                              reinterpret_cast<const void*>(&rhif::k_skeletonize<3, double>),
+                              reinterpret_cast<const void*>(&rhif::k_skeletonize<4, double>),
+                              reinterpret_cast<const void*>(&rhif::k_skeletonize<0, float>),
+                              reinterpret_cast<const void*>(&rhif::k_skeletonize<1, float>),
+                              reinterpret_cast<const void*>(&rhif::k_skeletonize<3, float>),
+                              reinterpret_cast<const void*>(&rhif::k_skeletonize<4, float>)})
+            (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_apply_group_up),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_apply_group_dn),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_chol_lead),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_leaf_elim),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_leaf_elim<false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_leaf_elim<true>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         // k_precond_groups also holds a few static LDS words
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_precond_groups),
@@ -647,6 +650,12 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
     const int d = g.d;
     const int W = 1 << d;
     const int leaf = f->o.leaf;
+    // precision 1: the interpolative decompositions in FP32; precision 2: also the Schur
+    // products of the cell eliminations (level 0 and the upper levels' final
+    // S = A_BB - W^T W) on the FP32 matrix cores. Cholesky factors, block Jacobi and every
+    // stored factor value stay FP64.
+    const bool f32 = f->o.precision >= 1;
+    const bool f32schur = f->o.precision == 2;
     f->nnz = fd_nnz(d, g.s);
     // the error word leads the block of the ID outputs, so that one copy reads back both
     f->kbuf = static_cast<int32_t*>(f->dalloc(kKbufHead * sizeof(int32_t)));
@@ -852,7 +861,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                 const size_t lds0 =
                     static_cast<size_t>((10 + 4 * std::max(tpw, 1) + 2 * (2 + nt)) * 16 * 17) * sizeof(double);
                 KTIMED(f, s, cls, P.alg_elim_flops, 0.0,
-                       hipLaunchKernelGGL(k_leaf_elim, dim3(ncell), dim3(256), lds0, s, LD.potrf, LD.front, linv,
+                       hipLaunchKernelGGL(f32schur ? k_leaf_elim<true> : k_leaf_elim<false>, dim3(ncell), dim3(256), lds0, s, LD.potrf, LD.front, linv,
                                           std::max(tpw, 1), lvl, f->err, LD.ext));
             } else if (pmax > kCholLdsPmax) {
                 // large interiors (3D upper levels, roots): panel by panel, each panel's
@@ -901,8 +910,8 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                                                   linv, pstride));
                         const int nb = (mr + 31) / 32;
                         KTIMED(f, s, cls, 0.0, 0.0,
-                               hipLaunchKernelGGL(k_syrk_schur, dim3(nc, nb * (nb + 1) / 2), dim3(256), 0, s, dq,
-                                                  LD.front));
+                               hipLaunchKernelGGL(k_syrk_schur<false>, dim3(nc, nb * (nb + 1) / 2), dim3(256), 0, s,
+                                                  dq, LD.front));
                     }
                 }
             } else if (!root && lvl > 0) {
@@ -919,8 +928,8 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                                               linv, pstride));
                     const int nb = (mmax + 31) / 32;
                     KTIMED(f, s, cls, 0.0, 0.0,
-                           hipLaunchKernelGGL(k_syrk_schur, dim3(ncell, nb * (nb + 1) / 2), dim3(256), 0, s, LD.potrf,
-                                              LD.front));
+                           hipLaunchKernelGGL(f32schur ? k_syrk_schur<true> : k_syrk_schur<false>,
+                                              dim3(ncell, nb * (nb + 1) / 2), dim3(256), 0, s, LD.potrf, LD.front));
                 }
             } else {
                 const int cap = panel_cap_for(nmax, 0);
@@ -1040,7 +1049,8 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             for (const auto& sk : P.skel_desc) rmax = std::max(rmax, sk.r);
             // must match the LDS layout of k_skeletonize
             const int base = (2 * n + 1) / 2 + 1 + rmax + 2 * 256 * std::max(1, (n + 63) / 64);
-            const int msz = rmax * (n | 1);
+            // M in doubles of LDS (FP32 values take half)
+            const int msz = f32 ? (rmax * (n | 1) + 1) / 2 : rmax * (n | 1);
             const int full = kPotrfSmemFixed + 17 * n;        // potrf scratch with the whole panel
             int staged = 0, cap = 0;
             size_t lds = 0;
@@ -1064,10 +1074,14 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             }
             LD.skli = static_cast<double*>(f->dalloc(P.skli_elems * sizeof(double)));
             KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
-                   hipLaunchKernelGGL(staged == 4   ? k_skeletonize<4>
-                                      : staged == 3 ? k_skeletonize<3>
-                                      : staged == 1 ? k_skeletonize<1>
-                                                    : k_skeletonize<0>,
+                   hipLaunchKernelGGL(f32 ? (staged == 4   ? k_skeletonize<4, float>
+                                             : staged == 3 ? k_skeletonize<3, float>
+                                             : staged == 1 ? k_skeletonize<1, float>
+                                                           : k_skeletonize<0, float>)
+                                          : (staged == 4   ? k_skeletonize<4, double>
+                                             : staged == 3 ? k_skeletonize<3, double>
+                                             : staged == 1 ? k_skeletonize<1, double>
+                                                           : k_skeletonize<0, double>),
                                       dim3(nsk), dim3(256), lds, s, LD.skd, LD.cgptr, LD.cgl, LD.cgoff, LD.cref, LD.front,
                                       f->mp, LD.tp, LD.gp, LD.skli, f->o.eps, f->kout, f->pout, cap, n, rmax, lvl,
                                       f->err));
@@ -1215,7 +1229,8 @@ void apply_down_block(rhif_factor_s* f, double by, const rhif::ApplyDesc* ad, in
                                   dofs, z, ext));
 }
 
-void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
+// z <- G^-1 z: the up-sweep of every level, then the forward solve with the root factor.
+void do_apply_up(rhif_factor_s* f, double* z, hipStream_t s) {
     const int L = f->L;
     for (int lvl = 0; lvl < L; ++lvl) {
         LevelDev& LD = f->lev[lvl];
@@ -1238,10 +1253,16 @@ void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
         apply_up_block(f, LD.b_skel, LD.skel_ad, LD.n_skel_ad, LD.mi_skel, LD.mb_skel, LD.lds_skel, LD.gp, LD.skli,
                        LD.tp, LD.skeldofs, z, nullptr, s);
     }
+    LevelDev& LD = f->lev[L];
+    apply_up_block(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.mi_cell, LD.mb_cell, LD.lds_cell, LD.front, LD.linv,
+                   nullptr, LD.cdofs, z, f->ybuf, s, LD.ext);
+}
+
+// z <- G^-T z: the backward solve with the root factor, then the down-sweep of every level.
+void do_apply_down(rhif_factor_s* f, double* z, hipStream_t s) {
+    const int L = f->L;
     {
         LevelDev& LD = f->lev[L];
-        apply_up_block(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.mi_cell, LD.mb_cell, LD.lds_cell, LD.front, LD.linv,
-                       nullptr, LD.cdofs, z, f->ybuf, s, LD.ext);
         apply_down_block(f, LD.b_cell, LD.cell_ad, LD.n_cell_ad, LD.mi_cell, LD.mb_cell, LD.lds_cell, LD.front,
                          LD.linv, nullptr, LD.cdofs, z, s, LD.ext);
     }
@@ -1263,6 +1284,12 @@ void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
     }
 }
 
+// z <- F^-1 z = G^-T G^-1 z (eq. (3.2))
+void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
+    do_apply_up(f, z, s);
+    do_apply_down(f, z, s);
+}
+
 void ensure_pcg(rhif_factor_s* f) {
     if (f->r) return;
     const size_t vb = f->g.N * sizeof(double);
@@ -1270,7 +1297,7 @@ void ensure_pcg(rhif_factor_s* f) {
     f->z = static_cast<double*>(f->dalloc(vb));
     f->p = static_cast<double*>(f->dalloc(vb));
     f->q = static_cast<double*>(f->dalloc(vb));
-    f->part = static_cast<double*>(f->dalloc(kRedBlocks * sizeof(double)));
+    f->part = static_cast<double*>(f->dalloc(2 * kRedBlocks * sizeof(double)));
     f->sc = static_cast<double*>(f->dalloc(16 * sizeof(double)));
     f->hsc = PinnedSlots::get().take();
     if (f->hsc == nullptr)
@@ -1359,7 +1386,7 @@ struct PcgWs {
 // own copy for the life of the process. Host code reaches it only through the address that
 // hipGetSymbolAddress returns per device (the array's name is not a device address on the
 // host).
-constexpr int64_t kNoAllocDoubles = 4 * int64_t(RHIF_NOALLOC_MAX_N) + kRedBlocks + 16;
+constexpr int64_t kNoAllocDoubles = 4 * int64_t(RHIF_NOALLOC_MAX_N) + 2 * kRedBlocks + 16;
 static __device__ __align__(256) double scratch[kNoAllocDoubles];
 
 double* noalloc_scratch(int dev) {
@@ -1375,7 +1402,7 @@ double* noalloc_scratch(int dev) {
     return static_cast<double*>(ptr);
 }
 
-// The PCG of rhif_pcg_solve on the workspace w (r, z, p, q: N doubles each; part: kRedBlocks
+// The PCG of rhif_pcg_solve on the workspace w (r, z, p, q: N doubles each; part: 2 kRedBlocks
 // doubles of partial sums; sc: 16 scalars). With w.hsc (pinned host scalars) the host waits on
 // events and looks ahead; without it (the no-allocation entry point) every scalar is read
 // with a copy to host memory of the caller's thread and a stream synchronization, and no
@@ -1384,6 +1411,10 @@ void pcg_run(rhif_factor_s* f, const PcgWs& w, const double* rhs, double* u, dou
              int32_t* iters, double* relres, hipStream_t s) {
     const int64_t N = f->g.N;
     const int gb = grid_for(N);
+    // a factor computed partly in FP32 is applied as a slightly inexact preconditioner: the
+    // flexible (Polak-Ribiere) beta keeps CG robust to that, with the residual and every
+    // inner product in FP64
+    const bool flex = f->o.precision >= 1;
     double host_sc[2] = {0.0, 0.0};
     const bool pinned = w.hsc != nullptr;
     double* hsc = pinned ? w.hsc : host_sc;
@@ -1402,9 +1433,12 @@ void pcg_run(rhif_factor_s* f, const PcgWs& w, const double* rhs, double* u, dou
                hipLaunchKernelGGL(rhif::k_spmv_dot, dim3(gb), dim3(256), 0, cs, N, f->rp, f->ci, f->val, w.p, w.q,
                                   w.part));
         VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, w.part, gb, 1, w.sc, nullptr));
-        VEC(6 * NB, hipLaunchKernelGGL(rhif::k_axpy2, dim3(gb), dim3(256), 0, cs, N, w.sc, w.p, w.q, u, w.r,
-                                       w.part));
+        VEC((flex ? 7 : 6) * NB, hipLaunchKernelGGL(rhif::k_axpy2, dim3(gb), dim3(256), 0, cs, N, w.sc, w.p, w.q, u,
+                                                    w.r, w.part, flex ? w.z : nullptr, w.part + kRedBlocks));
         VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, w.part, gb, 2, w.sc, nullptr));
+        if (flex)
+            VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, w.part + kRedBlocks, gb, 5, w.sc,
+                                        nullptr));
         HIPCHK(hipMemcpyAsync(hsc + 1, w.sc + 3, sizeof(double), hipMemcpyDeviceToHost, cs));
         if (!pinned) HIPCHK(hipStreamSynchronize(cs));
     };
@@ -1413,7 +1447,8 @@ void pcg_run(rhif_factor_s* f, const PcgWs& w, const double* rhs, double* u, dou
         VEC(2 * NB, hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, cs, N, w.r, w.z));
         do_apply_inplace(f, w.z, cs);
         VEC(2 * NB, hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, cs, N, w.r, w.z, w.part));
-        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, w.part, gb, 4, w.sc, nullptr));
+        VEC(0.0, hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, cs, w.part, gb, flex ? 6 : 4, w.sc,
+                                    nullptr));
     };
     // p = z + beta p; then the next update
     auto advance = [&](hipStream_t cs) {
@@ -1545,7 +1580,7 @@ extern "C" {
 
 const char* rhif_last_error(void) { return g_last_error.c_str(); }
 
-const char* rhif_version(void) { return "rhif 0.1 (gfx950, FP64)"; }
+const char* rhif_version(void) { return "rhif 0.2 (gfx950; FP64 and FP32-mixed factorizations)"; }
 
 #define API_BEGIN try {
 #define API_END                                                   \
@@ -1620,7 +1655,8 @@ rhif_status rhif_factor(const rhif_grid* g, const rhif_opts* o, const int32_t* r
         if (o->leaf < 2) fail(RHIF_EINVAL, "leaf must be >= 2");
         if (!(o->eps >= 0.0) || !(o->eps < 1.0)) fail(RHIF_EINVAL, "eps must be in [0, 1)");
         if (o->precond != 0 && o->precond != 1) fail(RHIF_EINVAL, "precond must be 0 or 1");
-        if (o->precision != 0) fail(RHIF_EINVAL, "only precision 0 (FP64) is available");
+        if (o->precision < 0 || o->precision > 2)
+            fail(RHIF_EINVAL, "precision must be 0 (FP64), 1 (FP32 ID) or 2 (FP32 ID and Schur products)");
         if (o->flags & kRemovedFlags) fail(RHIF_EINVAL, "flag bit 2 (leaf sublevels) is not supported");
         if (!row_ptr || !col || !val) fail(RHIF_EINVAL, "NULL CSR pointer");
         set_kernel_attributes();
@@ -1698,6 +1734,80 @@ rhif_status rhif_apply(rhif_factor_t f, const double* r, double* z, int32_t nrhs
     API_END
 }
 
+rhif_status rhif_apply_half(rhif_factor_t f, const double* r, double* z, int32_t which, hipStream_t s) {
+    API_BEGIN
+    if (!f || !r || !z) fail(RHIF_EINVAL, "NULL argument");
+    if (which != 0 && which != 1) fail(RHIF_EINVAL, "which must be 0 (G^-1) or 1 (G^-T)");
+    ensure_pcg(f);
+    const int64_t N = f->g.N;
+    hipLaunchKernelGGL(rhif::k_copy, dim3(grid_for(N)), dim3(256), 0, s, N, r, f->z);
+    if (which == 0) do_apply_up(f, f->z, s);
+    else do_apply_down(f, f->z, s);
+    hipLaunchKernelGGL(rhif::k_copy, dim3(grid_for(N)), dim3(256), 0, s, N, f->z, z);
+    HIPCHK(hipGetLastError());
+    f->resolve();
+    f->mark(s);
+    API_END
+}
+
+rhif_status rhif_estimate_es(rhif_factor_t f, const double* v0, int32_t maxit, double rtol, double* es,
+                             int32_t* iters, hipStream_t s) {
+    API_BEGIN
+    if (!f || !v0 || !es) fail(RHIF_EINVAL, "NULL argument");
+    if (maxit < 1 || !(rtol >= 0.0)) fail(RHIF_EINVAL, "bad maxit or rtol");
+    ensure_pcg(f);
+    const int64_t N = f->g.N;
+    const int gb = grid_for(N);
+    double* v = f->p;
+    double* w = f->q;
+    double* t = f->z;
+    double* hsc = f->hsc;
+    // |x|^2 of a device vector to the host (synchronizes the stream)
+    auto norm2 = [&](const double* x) {
+        hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, s, N, x, x, f->part);
+        hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, s, f->part, gb, 3, f->sc, nullptr);
+        HIPCHK(hipMemcpyAsync(hsc, f->sc, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return hsc[0];
+    };
+    // y = x - G^-1 A G^-T x
+    auto op = [&](const double* x, double* y) {
+        hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, x, t);
+        do_apply_down(f, t, s);
+        hipLaunchKernelGGL(rhif::k_spmv_dot, dim3(gb), dim3(256), 0, s, N, f->rp, f->ci, f->val, t, y, f->part);
+        do_apply_up(f, y, s);
+        hipLaunchKernelGGL(rhif::k_axpby, dim3(gb), dim3(256), 0, s, N, 1.0, x, -1.0, y);
+    };
+    const double n0 = norm2(v0);
+    if (!(n0 > 0.0)) fail(RHIF_EINVAL, "start vector is zero");
+    hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, v0, v);
+    hipLaunchKernelGGL(rhif::k_axpby, dim3(gb), dim3(256), 0, s, N, 0.0, v, 1.0 / std::sqrt(n0), v);
+    double est = 0.0;
+    int it = 0;
+    while (it < maxit) {
+        ++it;
+        op(v, f->r);
+        op(f->r, w);
+        const double nw = norm2(w);
+        const double now = std::sqrt(std::sqrt(nw));
+        if (nw == 0.0) {
+            est = 0.0;
+            break;
+        }
+        hipLaunchKernelGGL(rhif::k_axpby, dim3(gb), dim3(256), 0, s, N, 0.0, v, 1.0 / std::sqrt(nw), w);
+        std::swap(v, w);
+        const bool done = est > 0.0 && std::fabs(now - est) <= rtol * now;
+        est = now;
+        if (done) break;
+    }
+    HIPCHK(hipGetLastError());
+    f->resolve();
+    f->mark(s);
+    *es = est;
+    if (iters) *iters = it;
+    API_END
+}
+
 rhif_status rhif_grad_log_a(const rhif_grid* g, const double* a_cells, const double* u, const double* lam,
                             double* grad, hipStream_t s) {
     API_BEGIN
@@ -1751,7 +1861,7 @@ rhif_status rhif_pcg_solve_noalloc(rhif_factor_t f, const double* rhs, double* u
     if (dev != f->device) fail(RHIF_EINVAL, "rhif_pcg_solve_noalloc: the current device is not the handle's");
     double* base = noalloc_scratch(dev);
     const int64_t N = f->g.N;
-    const PcgWs w{base, base + N, base + 2 * N, base + 3 * N, base + 4 * N, base + 4 * N + kRedBlocks, nullptr};
+    const PcgWs w{base, base + N, base + 2 * N, base + 3 * N, base + 4 * N, base + 4 * N + 2 * kRedBlocks, nullptr};
     // the scalar slots start cleared (a fill kernel, not a memset node, so that a caller may
     // capture the call); the vectors are written before they are read
     hipLaunchKernelGGL(rhif::k_fill, dim3(1), dim3(256), 0, s, int64_t(16), 0.0, w.sc);

@@ -31,7 +31,7 @@ KCLASS_NAMES = ["front_csr", "front_extend", "elim_leaf", "elim_upper", "root", 
 
 # every function declared in include/rhif.h
 EXPORTED = ["rhif_fd_nnz", "rhif_assemble_fd", "rhif_factor", "rhif_apply", "rhif_pcg_solve",
-            "rhif_pcg_solve_noalloc", "rhif_matvec", "rhif_grad_log_a", "rhif_stats", "rhif_skeletons", "rhif_destroy",
+            "rhif_pcg_solve_noalloc", "rhif_apply_half", "rhif_estimate_es", "rhif_matvec", "rhif_grad_log_a", "rhif_stats", "rhif_skeletons", "rhif_destroy",
             "rhif_last_error", "rhif_version"]
 
 
@@ -102,6 +102,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                    ctypes.POINTER(ctypes.c_double), vp]
     lib.rhif_pcg_solve_noalloc.argtypes = lib.rhif_pcg_solve.argtypes
     lib.rhif_matvec.argtypes = [vp, vp, vp, vp]
+    lib.rhif_apply_half.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
+    lib.rhif_estimate_es.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                     c_i32p, vp]
     lib.rhif_grad_log_a.argtypes = [ctypes.POINTER(Grid), vp, vp, vp, vp, vp]
     lib.rhif_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.rhif_skeletons.argtypes = [vp, ctypes.c_int32, c_i32p, ctypes.POINTER(ctypes.c_int64), c_i32p, c_i32p,
@@ -251,6 +254,29 @@ class Factor:
         z = out if out is not None else torch.empty_like(r)
         _check(self._lib.rhif_apply(self.handle, _ptr(r), _ptr(z), nrhs, _stream(stream)))
         return z
+
+    def apply_half(self, r, transpose: bool = False, out=None, stream=None):
+        """z = G^-1 r (transpose=False) or G^-T r (transpose=True), F = G G^T."""
+        _need((r, "r", self.N), *([(out, "out", self.N)] if out is not None else []))
+        torch = _torch()
+        z = out if out is not None else torch.empty_like(r)
+        _check(self._lib.rhif_apply_half(self.handle, _ptr(r), _ptr(z), 1 if transpose else 0, _stream(stream)))
+        return z
+
+    def estimate_es(self, v0=None, seed: int = 0, maxit: int = 50, rtol: float = 1e-2, stream=None):
+        """(e_s, iterations): ||I - G^-1 A G^-T||_2 by power iteration (Sec. 4). The start vector
+        is v0 (device, N values) or, if None, numpy.random.default_rng(seed).standard_normal(N)."""
+        torch = _torch()
+        if v0 is None:
+            import numpy as np
+            v0 = torch.tensor(np.random.default_rng(seed).standard_normal(self.N), dtype=torch.float64,
+                              device="cuda")
+        _need((v0, "v0", self.N))
+        es = ctypes.c_double()
+        it = ctypes.c_int32()
+        _check(self._lib.rhif_estimate_es(self.handle, _ptr(v0), maxit, rtol, ctypes.byref(es), ctypes.byref(it),
+                                          _stream(stream)))
+        return es.value, it.value
 
     def matvec(self, x, out=None, stream=None):
         _need((x, "x", self.N), *([(out, "out", self.N)] if out is not None else []))

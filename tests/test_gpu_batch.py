@@ -1,6 +1,7 @@
 """Batches of uneven problems solved concurrently on several streams (the batched-solver
 extension): the solutions, iteration counts and residuals equal those of solving the
-problems one by one, bit for bit, since no kernel's arithmetic depends on the interleaving."""
+problems one by one, bit for bit, since no kernel's arithmetic depends on the interleaving;
+the FP32-mixed, autotuned batch agrees with the oracle problem by problem."""
 import time
 
 import numpy as np
@@ -33,8 +34,37 @@ def test_batch_equals_one_by_one():
     dofs = sum(P.s * P.s for P in probs)
     print(f"sides {[P.s for P in probs]}: one by one {dofs / (t1 - t0) / 1e6:.1f} M DOFs/s, "
           f"4 streams {dofs / (t2 - t1) / 1e6:.1f}, 2 streams {dofs / (t3 - t2) / 1e6:.1f}", flush=True)
+    bat3 = solve_many(items, nstreams=3, order="largest_first")
+    for (u1, i1, r1), (u2, i2, r2) in zip(seq, bat3):
+        assert i1 == i2 and r1 == r2 and torch.equal(u1, u2)
     for (u1, i1, r1), (u2, i2, r2) in zip(seq, bat2):
         assert i1 == i2 and r1 == r2 and torch.equal(u1, u2)
     for (u1, i1, r1), (u2, i2, r2) in zip(seq, bat):
         assert i1 == i2 and r1 == r2 and r1 <= 1e-12
         assert torch.equal(u1, u2)
+
+
+@pytest.mark.timeout(300)
+def test_mixed_autotuned_batch_against_oracle():
+    """Problems 11, 14, 1, 6 of the uneven batch (sides 128, 128, 256, 256; a = exp(2 g),
+    eps 1e-4) solved as one FP32-mixed, autotuned batch: every solution agrees with the
+    oracle's (its own FP64 factorization and PCG to 1e-12) to 1e-9, and every residual
+    reaches 1e-12."""
+    import oracle as O
+    from paper_1808_01364_amd import batch
+    from workloads.fields import batch_problem
+    torch_cuda()
+    probs = [batch_problem(k) for k in (11, 14, 1, 6)]
+    items = [batch.BatchItem(2, P.s, to_dev(P.a_cells), to_dev(P.f), None, P.leaf, P.eps, precision=1)
+             for P in probs]
+    ns, order = batch.autotune(items, sample=4, verbose=True)
+    out = batch.solve_many(items)
+    for P, (u, it, rr) in zip(probs, out):
+        A = O.assemble_fd(2, P.s, P.a_cells, None)
+        F = O.factor(A, 2, P.s, P.leaf, P.eps, 1)
+        ref = O.pcg(A, P.f, lambda v: O.apply_inverse(F, v), 1e-12, 300)
+        e = float(np.linalg.norm(u.cpu().numpy() - ref.u) / np.linalg.norm(ref.u))
+        print(f"side {P.s}: iterations {it} (oracle {ref.iters}), relres {rr:.1e}, error vs oracle {e:.2e}",
+              flush=True)
+        assert rr <= 1e-12 and e <= 1e-9
+    print("autotuned:", ns, order)
