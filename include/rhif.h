@@ -90,6 +90,11 @@ typedef struct {
                                        in global memory even where they fit in LDS: the path
                                        that groups too large for LDS take (same results;
                                        slower); for testing that path on small problems  */
+#define RHIF_FLAG_SKEL_MULTI 32     /* take the interpolative decompositions of every level with
+                                       the multi-workgroup form (the form for groups whose M is
+                                       too large for one workgroup: one launch per pivot step
+                                       over row blocks of M); for testing that form on small
+                                       problems                                          */
 #define RHIF_MAX_LEVELS 32
 
 /* Kernel classes of rhif_stats_t.kernel_* */

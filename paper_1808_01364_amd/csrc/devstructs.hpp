@@ -95,6 +95,16 @@ struct SkelDesc {
     int32_t pad;
 };
 
+// State of one group's multi-workgroup interpolative decomposition between the step kernels.
+struct BigState {
+    double r11;          // |R_11|
+    double v0, alpha, beta;   // reflector of the current step: v = (x0 - alpha, x1, ...), beta = 2 / v^T v
+    int32_t pc;          // pivot column of the current step
+    int32_t active;      // 0 once the rank test failed or every column was taken
+    int32_t k;           // steps taken (the rank once inactive)
+    int32_t pad;
+};
+
 // One block of the factor apply: L in [0,nI)^2 and W^T in rows [nI, nI+nB) of columns
 // [0, nI) of the matrix at `off`; optionally an interpolation matrix T (nB x nI, ld nB).
 struct ApplyDesc {

@@ -1556,6 +1556,19 @@ __global__ __launch_bounds__(256) void k_precond_scale(const CellScaleDesc* __re
 // either cell (-1: none). The cells' group lists are staged in LDS by all threads, then the
 // first wave builds the segments (first row, count, positions), one lane per list entry; a
 // row count that disagrees with the plan is reported. scratch: 4 * kMaxSkelSegs + 2 + 4 * kMaxCellGroups ints.
+// Frontal rows p1 (first cell), p2 (second cell) of row i of M from the row segments (-1: the
+// cell holds no share of that row).
+__device__ __forceinline__ void seg_row(const int* seg, int ns, int i, int& p1, int& p2) {
+    p1 = p2 = -1;
+    for (int q = 0; q < ns; ++q) {
+        const int t = i - seg[4 * q];
+        if (t >= 0 && t < seg[4 * q + 1]) {
+            p1 = seg[4 * q + 2] >= 0 ? seg[4 * q + 2] + t : -1;
+            p2 = seg[4 * q + 3] >= 0 ? seg[4 * q + 3] + t : -1;
+        }
+    }
+}
+
 __device__ __forceinline__ void build_row_table(const SkelDesc& g, const int32_t* __restrict__ cgptr,
                                                 const int32_t* __restrict__ cgl, const int32_t* __restrict__ cgoff,
                                                 int nf0, int nf1, int r, int* rwl, int* scratch, int level,
@@ -1634,16 +1647,11 @@ __device__ __forceinline__ void build_row_table(const SkelDesc& g, const int32_t
         }
     }
     __syncthreads();
+    if (rwl == nullptr) return;   // segments only (in scratch; their count at scratch[4 kMaxSkelSegs])
     const int ns = *nseg;
     for (int i = tid; i < r; i += nthr) {
         int p1 = -1, p2 = -1;
-        for (int q = 0; q < ns; ++q) {
-            const int t = i - seg[4 * q];
-            if (t >= 0 && t < seg[4 * q + 1]) {
-                p1 = seg[4 * q + 2] >= 0 ? seg[4 * q + 2] + t : -1;
-                p2 = seg[4 * q + 3] >= 0 ? seg[4 * q + 3] + t : -1;
-            }
-        }
+        seg_row(seg, ns, i, p1, p2);
         rwl[2 * i] = p1;
         rwl[2 * i + 1] = p2;
     }
@@ -1654,6 +1662,89 @@ __device__ __forceinline__ void build_row_table(const SkelDesc& g, const int32_t
 //      [M (rmax x (nmax|1))] | [G (nmax^2)] | potrf scratch
 // SM / SG: M / G staged in LDS (else in the global pools), fixed at compile time so that
 // every access has a known address space.
+// Steps 3-5 of the skeletonization of one group, after its ID (rank k, pivot order perm in
+// LDS, T = R11^-1 R12 held in rows 0..k-1 of M at the redundant columns): the zeroed blocks of
+// eq. (2.2), the elimination of the redundant unknowns (partial Cholesky of G) and the write-
+// back of the new skeleton block. G (n x n, ld n) is Gw, in LDS (SG) or the global pool.
+template <bool SG, typename MR>
+__device__ __forceinline__ void skel_eliminate(const SkelDesc& g, int k, const int* perm, const MR* __restrict__ M,
+                                               int ldr, const CellRef* __restrict__ cells, double* __restrict__ F,
+                                               double* __restrict__ Gpool, double* __restrict__ Gw, double* psmem,
+                                               double* __restrict__ skli, int panel_cap, int level,
+                                               unsigned long long* err, int block_id) {
+    const int n = g.n, nr = n - k;
+    const int tid = threadIdx.x;
+    const CellRef c0 = cells[g.cell[0]];
+    CellRef c1 = c0;
+    if (g.nslot > 1) c1 = cells[g.cell[1]];
+    const double* f0 = F + c0.off + static_cast<size_t>(g.off[0]) * c0.ld;
+    const double* f1 = F + c1.off + static_cast<size_t>(g.off[1]) * c1.ld;
+    // 3. the zeroed blocks of eq. (2.2) in the order (redundant, skeleton). G first holds the
+    //    whole permuted A_gg; then V = A_ht - A_hh T replaces the lower (h, t) block (A_ht
+    //    stays in the upper one), then A~_tt = A_tt - T^T V - A_ht^T T (lower part).
+    const int nn = n * n;
+    for (int e0 = tid; e0 < nn; e0 += 4 * kWG) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * kWG;
+            v[u] = 0.0;
+            if (e < nn) {
+                const int x = e % n, y = e / n;
+                const int qx = x < nr ? perm[k + x] : perm[x - nr];
+                const int qy = y < nr ? perm[k + y] : perm[y - nr];
+                v[u] = f0[g.off[0] + qx + static_cast<size_t>(qy) * c0.ld];
+                if (g.nslot > 1) v[u] += f1[g.off[1] + qx + static_cast<size_t>(qy) * c1.ld];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (e0 + u * kWG < nn) Gw[e0 + u * kWG] = v[u];
+    }
+    __syncthreads();
+    for (int e = tid; e < k * nr; e += kWG) {
+        const int c = e % k, a = e / k;
+        const int pa = perm[k + a];
+        const double* Gc = Gw + (nr + c) + static_cast<size_t>(nr) * n;
+        double v = Gw[(nr + c) + static_cast<size_t>(a) * n], v1 = 0.0;
+        int q = 0;
+        for (; q + 1 < k; q += 2) {
+            v -= Gc[static_cast<size_t>(q) * n] * static_cast<double>(M[static_cast<size_t>(q) * ldr + pa]);
+            v1 -= Gc[static_cast<size_t>(q + 1) * n] * static_cast<double>(M[static_cast<size_t>(q + 1) * ldr + pa]);
+        }
+        if (q < k) v -= Gc[static_cast<size_t>(q) * n] * static_cast<double>(M[static_cast<size_t>(q) * ldr + pa]);
+        Gw[(nr + c) + static_cast<size_t>(a) * n] = v + v1;
+    }
+    __syncthreads();
+    for (int e = tid; e < nr * nr; e += kWG) {
+        const int a = e % nr, b = e / nr;
+        if (a < b) continue;
+        const int pa = perm[k + a], pb = perm[k + b];
+        double v = Gw[a + static_cast<size_t>(b) * n], v1 = 0.0;
+        for (int c = 0; c < k; ++c) {
+            const MR* Tc = M + static_cast<size_t>(c) * ldr;
+            v -= static_cast<double>(Tc[pa]) * Gw[(nr + c) + static_cast<size_t>(b) * n];
+            v1 -= Gw[a + static_cast<size_t>(nr + c) * n] * static_cast<double>(Tc[pb]);
+        }
+        Gw[a + static_cast<size_t>(b) * n] = v + v1;
+    }
+    __syncthreads();
+    // 4. eliminate the redundant unknowns
+    wg_potrf_partial(Gw, n, n, nr, psmem, panel_cap, err, err_code(level, 2, block_id), nullptr, skli + g.lioff);
+    // 5. write back the skeleton block (and keep G for the apply)
+    double* Gout = Gpool + g.goff;
+    for (int e = tid; e < nn; e += kWG) {
+        const int a = e % n, b = e / n;
+        if (SG) Gout[e] = Gw[e];
+        if (a < k && b < k) {
+            // skeleton a, b sit at positions perm[a], perm[b] of the group's ascending order
+            F[c0.off + (g.off[0] + perm[a]) + static_cast<size_t>(g.off[0] + perm[b]) * c0.ld] =
+                Gw[(nr + a) + static_cast<size_t>(nr + b) * n];
+        }
+        if (g.nslot > 1) F[c1.off + (g.off[1] + a) + static_cast<size_t>(g.off[1] + b) * c1.ld] = 0.0;
+    }
+}
+
 // MR: arithmetic of the ID (M, its QR and T); double, or float in the mixed-precision form.
 template <bool SM, bool SG, typename MR>
 __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t* __restrict__ cgptr,
@@ -1737,70 +1828,8 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
         const int i = e % k, a = e / k;
         T[e] = static_cast<double>(M[static_cast<size_t>(i) * ldr + perm[k + a]]);
     }
-    // 3. the zeroed blocks of eq. (2.2) in the order (redundant, skeleton). G first holds the
-    //    whole permuted A_gg; then V = A_ht - A_hh T replaces the lower (h, t) block (A_ht
-    //    stays in the upper one), then A~_tt = A_tt - T^T V - A_ht^T T (lower part).
-    const int nn = n * n;
-    for (int e0 = tid; e0 < nn; e0 += 4 * kWG) {
-        double v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = e0 + u * kWG;
-            v[u] = 0.0;
-            if (e < nn) {
-                const int x = e % n, y = e / n;
-                const int qx = x < nr ? perm[k + x] : perm[x - nr];
-                const int qy = y < nr ? perm[k + y] : perm[y - nr];
-                v[u] = f0[g.off[0] + qx + static_cast<size_t>(qy) * c0.ld];
-                if (g.nslot > 1) v[u] += f1[g.off[1] + qx + static_cast<size_t>(qy) * c1.ld];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (e0 + u * kWG < nn) Gw[e0 + u * kWG] = v[u];
-    }
-    __syncthreads();
-    for (int e = tid; e < k * nr; e += kWG) {
-        const int c = e % k, a = e / k;
-        const int pa = perm[k + a];
-        const double* Gc = Gw + (nr + c) + static_cast<size_t>(nr) * n;
-        double v = Gw[(nr + c) + static_cast<size_t>(a) * n], v1 = 0.0;
-        int q = 0;
-        for (; q + 1 < k; q += 2) {
-            v -= Gc[static_cast<size_t>(q) * n] * static_cast<double>(M[static_cast<size_t>(q) * ldr + pa]);
-            v1 -= Gc[static_cast<size_t>(q + 1) * n] * static_cast<double>(M[static_cast<size_t>(q + 1) * ldr + pa]);
-        }
-        if (q < k) v -= Gc[static_cast<size_t>(q) * n] * static_cast<double>(M[static_cast<size_t>(q) * ldr + pa]);
-        Gw[(nr + c) + static_cast<size_t>(a) * n] = v + v1;
-    }
-    __syncthreads();
-    for (int e = tid; e < nr * nr; e += kWG) {
-        const int a = e % nr, b = e / nr;
-        if (a < b) continue;
-        const int pa = perm[k + a], pb = perm[k + b];
-        double v = Gw[a + static_cast<size_t>(b) * n], v1 = 0.0;
-        for (int c = 0; c < k; ++c) {
-            const MR* Tc = M + static_cast<size_t>(c) * ldr;
-            v -= static_cast<double>(Tc[pa]) * Gw[(nr + c) + static_cast<size_t>(b) * n];
-            v1 -= Gw[a + static_cast<size_t>(nr + c) * n] * static_cast<double>(Tc[pb]);
-        }
-        Gw[a + static_cast<size_t>(b) * n] = v + v1;
-    }
-    __syncthreads();
-    // 4. eliminate the redundant unknowns
-    wg_potrf_partial(Gw, n, n, nr, psmem, panel_cap, err, err_code(level, 2, blockIdx.x), nullptr, skli + g.lioff);
-    // 5. write back the skeleton block (and keep G for the apply)
-    double* Gout = Gpool + g.goff;
-    for (int e = tid; e < nn; e += kWG) {
-        const int a = e % n, b = e / n;
-        if (SG) Gout[e] = Gw[e];
-        if (a < k && b < k) {
-            // skeleton a, b sit at positions perm[a], perm[b] of the group's ascending order
-            F[c0.off + (g.off[0] + perm[a]) + static_cast<size_t>(g.off[0] + perm[b]) * c0.ld] =
-                Gw[(nr + a) + static_cast<size_t>(nr + b) * n];
-        }
-        if (g.nslot > 1) F[c1.off + (g.off[1] + a) + static_cast<size_t>(g.off[1] + b) * c1.ld] = 0.0;
-    }
+    skel_eliminate<SG, MR>(g, k, perm, M, ldr, cells, F, Gpool, Gw, psmem, skli, panel_cap, level, err,
+                           blockIdx.x);
 }
 
 // STAGED: 3 = M and G in LDS, 1 = M in LDS, 0 = both in the global pools; 4 = the layout of 3
@@ -1836,6 +1865,298 @@ RHIF_SKEL_INST(1, float)
 RHIF_SKEL_INST(3, float)
 RHIF_SKEL_INST(4, float)
 #undef RHIF_SKEL_INST
+
+// ---------------------------------------------------------------------------------------
+// Interpolative decompositions of large groups across many workgroups (the faces of the upper
+// 3D levels: M = A[R_g, g] of thousands of rows and hundreds of columns, in the global pool).
+// The same column-pivoted Householder QR as wg_cpqr_rows (Sec. 2.2, the recomputed trailing
+// norms, ties to the lowest position, rank test |R_jj| > eps |R_11|), but every step is spread
+// over the row blocks of kBigRows rows of every group of the level: k_big_pivot (one
+// workgroup per group) picks the pivot from the blocks' norm partials and forms the reflector,
+// k_big_dot forms the blocks' partials of v^T M, and k_big_update sums them (fixed order),
+// updates its rows and leaves the new norm partials. The host launches the three per step.
+// Then k_big_trisolve solves T = R11^-1 R12 in place (one thread per redundant column), and
+// k_big_finish performs the zeroing and the elimination of the redundant unknowns.
+// ---------------------------------------------------------------------------------------
+constexpr int kBigRows = 256;
+static_assert(kBigRows == kBigRowsHost, "row blocks of the multi-workgroup ID");
+
+template <typename MR>
+__global__ __launch_bounds__(256) void k_big_gather(const SkelDesc* __restrict__ sd, const int32_t* __restrict__ cgptr,
+                                                    const int32_t* __restrict__ cgl, const int32_t* __restrict__ cgoff,
+                                                    const CellRef* __restrict__ cells, const double* __restrict__ F,
+                                                    double* __restrict__ Mpool, double* __restrict__ nrm,
+                                                    int32_t* __restrict__ pos, int32_t* __restrict__ pout,
+                                                    BigState* __restrict__ st, int nmax, int nblk, int level,
+                                                    unsigned long long* err) {
+    __shared__ int seg[4 * kMaxSkelSegs + 2 + 4 * kMaxCellGroups];
+    __shared__ int rows[2 * kBigRows];
+    const int gi = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+    const SkelDesc g = sd[gi];
+    const int n = g.n, r = g.r, ldr = n | 1;
+    const CellRef c0 = cells[g.cell[0]];
+    CellRef c1 = c0;
+    if (g.nslot > 1) c1 = cells[g.cell[1]];
+    build_row_table(g, cgptr, cgl, cgoff, c0.nf, c1.nf, r, nullptr, seg, level, err);
+    const int ns = seg[4 * kMaxSkelSegs];
+    const double* f0 = F + c0.off + static_cast<size_t>(g.off[0]) * c0.ld;
+    const double* f1 = F + c1.off + static_cast<size_t>(g.off[1]) * c1.ld;
+    MR* M = reinterpret_cast<MR*>(Mpool + g.moff);
+    const int i0 = b * kBigRows, i1 = min(r, i0 + kBigRows);
+    double* np = nrm + (static_cast<size_t>(gi) * nblk + b) * nmax;
+    for (int i = i0 + tid; i < i1; i += kWG) {
+        int p1, p2;
+        seg_row(seg, ns, i, p1, p2);
+        rows[2 * (i - i0)] = p1;
+        rows[2 * (i - i0) + 1] = p2;
+    }
+    __syncthreads();
+    for (int c = tid; c < n; c += kWG) {
+        MR sq = 0;
+        for (int i = i0; i < i1; ++i) {
+            const int p1 = rows[2 * (i - i0)], p2 = rows[2 * (i - i0) + 1];
+            double v = 0.0;
+            if (p1 >= 0) v += f0[p1 + static_cast<size_t>(c) * c0.ld];
+            if (p2 >= 0) v += f1[p2 + static_cast<size_t>(c) * c1.ld];
+            const MR x = static_cast<MR>(v);
+            M[static_cast<size_t>(i) * ldr + c] = x;
+            sq += x * x;
+        }
+        np[c] = static_cast<double>(sq);
+    }
+    if (b == 0) {
+        for (int c = tid; c < n; c += kWG) {
+            pos[static_cast<size_t>(gi) * nmax + c] = c;
+            pout[g.poff + c] = c;
+        }
+        if (tid == 0) {
+            BigState z{};
+            z.active = 1;
+            st[gi] = z;
+        }
+    }
+}
+
+template <typename MR>
+__global__ __launch_bounds__(256) void k_big_pivot(const SkelDesc* __restrict__ sd, const double* __restrict__ Mpool,
+                                                   const double* __restrict__ nrm, int32_t* __restrict__ pos,
+                                                   int32_t* __restrict__ pout, BigState* __restrict__ st, double eps,
+                                                   int j, int nmax, int nblk, int32_t* __restrict__ kout) {
+    __shared__ double rb[kWaves];
+    __shared__ int rp[kWaves], rc[kWaves];
+    const int gi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (!st[gi].active) return;
+    const SkelDesc g = sd[gi];
+    const int n = g.n, r = g.r, ldr = n | 1;
+    const int nb = (r + kBigRows - 1) / kBigRows;
+    if (j >= min(r, n)) {   // every column taken
+        if (tid == 0) {
+            st[gi].active = 0;
+            st[gi].k = j;
+            kout[g.gid] = j;
+        }
+        return;
+    }
+    const int32_t* pg = pos + static_cast<size_t>(gi) * nmax;
+    double best = -1.0;
+    int bpos = 0x7fffffff, bc = -1;
+    for (int c = tid; c < n; c += kWG) {
+        const int pp = pg[c];
+        if (pp < j) continue;
+        MR v = 0;
+        for (int b = 0; b < nb; ++b) v += static_cast<MR>(nrm[(static_cast<size_t>(gi) * nblk + b) * nmax + c]);
+        const double vd = static_cast<double>(v);
+        if (vd > best || (vd == best && pp < bpos)) {
+            best = vd;
+            bpos = pp;
+            bc = c;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int op = __shfl_xor(bpos, off, 64);
+        const int oc = __shfl_xor(bc, off, 64);
+        if (ob > best || (ob == best && op < bpos)) {
+            best = ob;
+            bpos = op;
+            bc = oc;
+        }
+    }
+    if (lane == 0) {
+        rb[wave] = best;
+        rp[wave] = bpos;
+        rc[wave] = bc;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    for (int w = 1; w < kWaves; ++w)
+        if (rb[w] > best || (rb[w] == best && rp[w] < bpos)) {
+            best = rb[w];
+            bpos = rp[w];
+            bc = rc[w];
+        }
+    BigState s = st[gi];
+    const MR nv = sqrt(static_cast<MR>(best));
+    if (j == 0) s.r11 = static_cast<double>(nv);
+    if (!(nv > static_cast<MR>(eps) * static_cast<MR>(s.r11))) {
+        s.active = 0;
+        s.k = j;
+        kout[g.gid] = j;
+        st[gi] = s;
+        return;
+    }
+    const MR* M = reinterpret_cast<const MR*>(Mpool + g.moff);
+    const MR x0 = M[static_cast<size_t>(j) * ldr + bc];
+    const MR alpha = -copysign(nv, x0);
+    s.pc = bc;
+    s.v0 = static_cast<double>(x0 - alpha);
+    s.alpha = static_cast<double>(alpha);
+    s.beta = static_cast<double>(MR(1) / (nv * (nv + fabs(x0))));
+    s.k = j + 1;
+    st[gi] = s;
+    // the pivot order: column bc moves to position j
+    int32_t* pw = pos + static_cast<size_t>(gi) * nmax;
+    const int q = pw[bc], cj = pout[g.poff + j];
+    pout[g.poff + j] = bc;
+    pout[g.poff + q] = cj;
+    pw[cj] = q;
+    pw[bc] = j;
+}
+
+template <typename MR>
+__global__ __launch_bounds__(256) void k_big_dot(const SkelDesc* __restrict__ sd, const double* __restrict__ Mpool,
+                                                 const int32_t* __restrict__ pos, const BigState* __restrict__ st,
+                                                 double* __restrict__ wpart, int j, int nmax, int nblk) {
+    const int gi = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+    const BigState s = st[gi];
+    if (!s.active) return;
+    const SkelDesc g = sd[gi];
+    const int n = g.n, r = g.r, ldr = n | 1;
+    const int i0 = max(j, b * kBigRows), i1 = min(r, b * kBigRows + kBigRows);
+    if (b * kBigRows >= r) return;
+    const MR* M = reinterpret_cast<const MR*>(Mpool + g.moff);
+    const int32_t* pg = pos + static_cast<size_t>(gi) * nmax;
+    double* wp = wpart + (static_cast<size_t>(gi) * nblk + b) * nmax;
+    const MR v0 = static_cast<MR>(s.v0);
+    for (int c = tid; c < n; c += kWG) {
+        if (pg[c] <= j) continue;
+        MR w0 = 0, w1 = 0;
+        int i = i0;
+        if (i == j && i < i1) {   // row j lies in this block
+            w0 = v0 * M[static_cast<size_t>(j) * ldr + c];
+            ++i;
+        }
+        for (; i + 1 < i1; i += 2) {
+            w0 += M[static_cast<size_t>(i) * ldr + s.pc] * M[static_cast<size_t>(i) * ldr + c];
+            w1 += M[static_cast<size_t>(i + 1) * ldr + s.pc] * M[static_cast<size_t>(i + 1) * ldr + c];
+        }
+        if (i < i1) w0 += M[static_cast<size_t>(i) * ldr + s.pc] * M[static_cast<size_t>(i) * ldr + c];
+        wp[c] = static_cast<double>(w0 + w1);
+    }
+}
+
+template <typename MR>
+__global__ __launch_bounds__(256) void k_big_update(const SkelDesc* __restrict__ sd, double* __restrict__ Mpool,
+                                                    double* __restrict__ nrm, const int32_t* __restrict__ pos,
+                                                    const BigState* __restrict__ st, const double* __restrict__ wpart,
+                                                    int j, int nmax, int nblk) {
+    const int gi = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+    const BigState s = st[gi];
+    if (!s.active) return;
+    const SkelDesc g = sd[gi];
+    const int n = g.n, r = g.r, ldr = n | 1;
+    if (b * kBigRows >= r) return;
+    const int nb = (r + kBigRows - 1) / kBigRows;
+    const int i0 = max(j, b * kBigRows), i1 = min(r, b * kBigRows + kBigRows);
+    MR* M = reinterpret_cast<MR*>(Mpool + g.moff);
+    const int32_t* pg = pos + static_cast<size_t>(gi) * nmax;
+    double* np = nrm + (static_cast<size_t>(gi) * nblk + b) * nmax;
+    const MR v0 = static_cast<MR>(s.v0), beta = static_cast<MR>(s.beta);
+    for (int c = tid; c < n; c += kWG) {
+        if (pg[c] <= j) continue;
+        MR w = 0;
+        for (int q = 0; q < nb; ++q) w += static_cast<MR>(wpart[(static_cast<size_t>(gi) * nblk + q) * nmax + c]);
+        const MR f = beta * w;
+        MR sq = 0;
+        int i = i0;
+        if (i == j && i < i1) {   // row j lies in this block
+            M[static_cast<size_t>(j) * ldr + c] -= f * v0;
+            ++i;
+        }
+        for (; i < i1; ++i) {
+            const MR nvv = M[static_cast<size_t>(i) * ldr + c] - f * M[static_cast<size_t>(i) * ldr + s.pc];
+            M[static_cast<size_t>(i) * ldr + c] = nvv;
+            sq += nvv * nvv;
+        }
+        np[c] = static_cast<double>(sq);
+    }
+    // R[j][pc] = alpha, by the block holding row j (no block reads it during this step)
+    if (tid == 0 && b * kBigRows <= j && j < b * kBigRows + kBigRows)
+        M[static_cast<size_t>(j) * ldr + s.pc] = static_cast<MR>(s.alpha);
+}
+
+// T = R11^-1 R12 in place over R12, one thread per redundant column (back substitution
+// with the columns of R11 read from the pool).
+template <typename MR>
+__global__ __launch_bounds__(64) void k_big_trisolve(const SkelDesc* __restrict__ sd, double* __restrict__ Mpool,
+                                                     const int32_t* __restrict__ pout, const BigState* __restrict__ st,
+                                                     double* __restrict__ Tpool) {
+    const int gi = blockIdx.x;
+    const SkelDesc g = sd[gi];
+    const int n = g.n, ldr = n | 1, k = st[gi].k, nr = n - k;
+    const int a = blockIdx.y * 64 + threadIdx.x;
+    if (a >= nr) return;
+    MR* M = reinterpret_cast<MR*>(Mpool + g.moff);
+    const int32_t* perm = pout + g.poff;
+    const int pa = perm[k + a];
+    for (int i = k - 1; i >= 0; --i) {
+        const int pi = perm[i];
+        const MR ti = M[static_cast<size_t>(i) * ldr + pa] / M[static_cast<size_t>(i) * ldr + pi];
+        M[static_cast<size_t>(i) * ldr + pa] = ti;
+        for (int e = 0; e < i; ++e) M[static_cast<size_t>(e) * ldr + pa] -= M[static_cast<size_t>(e) * ldr + pi] * ti;
+    }
+    double* T = Tpool + g.toff;
+    for (int i = 0; i < k; ++i) T[i + static_cast<size_t>(a) * k] = static_cast<double>(M[static_cast<size_t>(i) * ldr + pa]);
+}
+
+// Steps 3-5 for groups whose ID the kernels above took: rank and pivot order from kout / pout,
+// T in M; G in the global pool.
+template <typename MR>
+__global__ __launch_bounds__(256) void k_big_finish(const SkelDesc* __restrict__ sd, const CellRef* __restrict__ cells,
+                                                    double* __restrict__ F, const double* __restrict__ Mpool,
+                                                    double* __restrict__ Gpool, double* __restrict__ skli,
+                                                    const int32_t* __restrict__ kout, const int32_t* __restrict__ pout,
+                                                    int panel_cap, int nmax, int level, unsigned long long* err) {
+    extern __shared__ double smem[];
+    const SkelDesc g = sd[blockIdx.x];
+    int* perm = reinterpret_cast<int*>(smem);
+    double* psmem = smem + (nmax + 1) / 2 + 1;
+    for (int e = threadIdx.x; e < g.n; e += kWG) perm[e] = pout[g.poff + e];
+    __syncthreads();
+    const MR* M = reinterpret_cast<const MR*>(Mpool + g.moff);
+    skel_eliminate<false, MR>(g, kout[g.gid], perm, M, g.n | 1, cells, F, Gpool, Gpool + g.goff, psmem, skli, panel_cap,
+                              level, err, blockIdx.x);
+}
+
+#define RHIF_BIG_INST(MR)                                                                                          \
+    template __global__ void k_big_gather<MR>(const SkelDesc*, const int32_t*, const int32_t*, const int32_t*,     \
+                                              const CellRef*, const double*, double*, double*, int32_t*, int32_t*, \
+                                              BigState*, int, int, int, unsigned long long*);                     \
+    template __global__ void k_big_pivot<MR>(const SkelDesc*, const double*, const double*, int32_t*, int32_t*,    \
+                                             BigState*, double, int, int, int, int32_t*);                         \
+    template __global__ void k_big_dot<MR>(const SkelDesc*, const double*, const int32_t*, const BigState*,        \
+                                           double*, int, int, int);                                               \
+    template __global__ void k_big_update<MR>(const SkelDesc*, double*, double*, const int32_t*, const BigState*,  \
+                                              const double*, int, int, int);                                      \
+    template __global__ void k_big_trisolve<MR>(const SkelDesc*, double*, const int32_t*, const BigState*,         \
+                                                double*);                                                         \
+    template __global__ void k_big_finish<MR>(const SkelDesc*, const CellRef*, double*, const double*, double*,    \
+                                              double*, const int32_t*, const int32_t*, int, int, int,             \
+                                              unsigned long long*);
+RHIF_BIG_INST(double)
+RHIF_BIG_INST(float)
+#undef RHIF_BIG_INST
 
 
 // ---------------------------------------------------------------------------------------

@@ -42,6 +42,28 @@ __global__ void k_skeletonize(const SkelDesc* sd, const int32_t* cgptr, const in
                               const CellRef* cells, double* F,
                               double* Mpool, double* Tpool, double* Gpool, double* skli, double eps, int32_t* kout,
                               int32_t* pout, int panel_cap, int nmax, int rmax, int level, unsigned long long* err);
+// interpolative decompositions of large groups across many workgroups
+template <typename MR>
+__global__ void k_big_gather(const SkelDesc* sd, const int32_t* cgptr, const int32_t* cgl, const int32_t* cgoff,
+                             const CellRef* cells, const double* F, double* Mpool, double* nrm, int32_t* pos,
+                             int32_t* pout, BigState* st, int nmax, int nblk, int level, unsigned long long* err);
+template <typename MR>
+__global__ void k_big_pivot(const SkelDesc* sd, const double* Mpool, const double* nrm, int32_t* pos, int32_t* pout,
+                            BigState* st, double eps, int j, int nmax, int nblk, int32_t* kout);
+template <typename MR>
+__global__ void k_big_dot(const SkelDesc* sd, const double* Mpool, const int32_t* pos, const BigState* st,
+                          double* wpart, int j, int nmax, int nblk);
+template <typename MR>
+__global__ void k_big_update(const SkelDesc* sd, double* Mpool, double* nrm, const int32_t* pos, const BigState* st,
+                             const double* wpart, int j, int nmax, int nblk);
+template <typename MR>
+__global__ void k_big_trisolve(const SkelDesc* sd, double* Mpool, const int32_t* pout, const BigState* st,
+                               double* Tpool);
+template <typename MR>
+__global__ void k_big_finish(const SkelDesc* sd, const CellRef* cells, double* F, const double* Mpool, double* Gpool,
+                             double* skli, const int32_t* kout, const int32_t* pout, int panel_cap, int nmax,
+                             int level, unsigned long long* err);
+constexpr int kBigRowsHost = 256;   // rows of M per workgroup in the kernels above
 __global__ void k_apply_up(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
                            double* z, double* ybuf, double* ws, const int32_t* ext);
 __global__ void k_apply_down(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,

@@ -50,6 +50,9 @@ constexpr int kElimPanel = 128;   // panel width of the elimination of large int
 constexpr int kStaticLdsReserve = 32;         // doubles of static LDS a kernel may declare
 constexpr int kRedBlocks = 1024;              // fixed partial-sum layout of the CG reductions
 constexpr int32_t kRemovedFlags = 4;          // option bits that no longer exist
+constexpr int64_t kBigSkelElems = 1 << 18;    // M (rows x columns) from which the ID spreads over
+                                              // many workgroups per group
+constexpr int kBigCheck = 16;                 // steps between the host's checks for active groups
 
 // Per-thread host state reused across factorizations: pinned staging buffers for the
 // uploads (a ring, each slot fenced by the event of its last copy), a pinned buffer for
@@ -611,7 +614,9 @@ void set_kernel_attributes() {
         const int bytes = kLdsMaxDoubles * static_cast<int>(sizeof(double));
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_precond_scale),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        for (const void* k : {reinterpret_cast<const void*>(&rhif::k_skeletonize<0, double>),
+        for (const void* k : {reinterpret_cast<const void*>(&rhif::k_big_finish<double>),
+                              reinterpret_cast<const void*>(&rhif::k_big_finish<float>),
+                              reinterpret_cast<const void*>(&rhif::k_skeletonize<0, double>),
                               reinterpret_cast<const void*>(&rhif::k_skeletonize<1, double>),
                               reinterpret_cast<const void*>(&rhif::k_skeletonize<3, double>),
                               reinterpret_cast<const void*>(&rhif::k_skeletonize<4, double>),
@@ -1073,6 +1078,61 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                 lds = potrf_lds(cap, base);
             }
             LD.skli = static_cast<double*>(f->dalloc(P.skli_elems * sizeof(double)));
+            // groups whose M is too large for LDS and has many rows (the upper 3D levels): the
+            // ID spread over row blocks of kBigRowsHost rows, one launch per step for all groups
+            const bool big = (f->o.flags & RHIF_FLAG_SKEL_MULTI) ||
+                             (staged == 0 && !(f->o.flags & RHIF_FLAG_GLOBAL_STAGING) &&
+                              static_cast<int64_t>(rmax) * n >= kBigSkelElems);
+            if (big) {
+                const int nblk = (rmax + kBigRowsHost - 1) / kBigRowsHost;
+                double* nrm = static_cast<double*>(f->dalloc(static_cast<size_t>(nsk) * nblk * n * sizeof(double)));
+                double* wpart = static_cast<double*>(f->dalloc(static_cast<size_t>(nsk) * nblk * n * sizeof(double)));
+                int32_t* posb = static_cast<int32_t*>(f->dalloc(static_cast<size_t>(nsk) * n * sizeof(int32_t)));
+                BigState* bst = static_cast<BigState*>(f->dalloc(static_cast<size_t>(nsk) * sizeof(BigState)));
+                int jmax = 0;
+                for (const auto& sk : P.skel_desc) jmax = std::max(jmax, std::min(sk.r, sk.n));
+                const dim3 gb2(nsk, nblk);
+                KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                       hipLaunchKernelGGL(f32 ? k_big_gather<float> : k_big_gather<double>, gb2, dim3(256), 0, s,
+                                          LD.skd, LD.cgptr, LD.cgl, LD.cgoff, LD.cref, LD.front, f->mp, nrm, posb,
+                                          f->pout, bst, n, nblk, lvl, f->err));
+                BigState* hst = reinterpret_cast<BigState*>(hc.get_down(static_cast<size_t>(nsk) * sizeof(BigState) + 64));
+                // every group takes at most jmax steps (the last one only records the rank); the
+                // host checks every kBigCheck steps whether any group is still active
+                for (int j = 0; j <= jmax; ++j) {
+                    KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                           hipLaunchKernelGGL(f32 ? k_big_pivot<float> : k_big_pivot<double>, dim3(nsk), dim3(256), 0,
+                                              s, LD.skd, f->mp, nrm, posb, f->pout, bst, f->o.eps, j, n, nblk,
+                                              f->kout));
+                    if (j == jmax) break;
+                    KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                           hipLaunchKernelGGL(f32 ? k_big_dot<float> : k_big_dot<double>, gb2, dim3(256), 0, s, LD.skd,
+                                              f->mp, posb, bst, wpart, j, n, nblk));
+                    KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                           hipLaunchKernelGGL(f32 ? k_big_update<float> : k_big_update<double>, gb2, dim3(256), 0, s,
+                                              LD.skd, f->mp, nrm, posb, bst, wpart, j, n, nblk));
+                    if ((j + 1) % kBigCheck == 0) {
+                        HIPCHK(hipMemcpyAsync(hst, bst, static_cast<size_t>(nsk) * sizeof(BigState),
+                                              hipMemcpyDeviceToHost, s));
+                        HIPCHK(hipStreamSynchronize(s));
+                        bool any = false;
+                        for (int e = 0; e < nsk; ++e) any = any || hst[e].active;
+                        if (!any) break;
+                    }
+                }
+                // a group still active after jmax steps took every column: its rank is set by
+                // the last pivot launch (j == min(r, n))
+                KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                       hipLaunchKernelGGL(f32 ? k_big_trisolve<float> : k_big_trisolve<double>,
+                                          dim3(nsk, (n + 63) / 64), dim3(64), 0, s, LD.skd, f->mp, f->pout, bst,
+                                          LD.tp));
+                const int fbase = (n + 1) / 2 + 1;
+                const int fcap = panel_cap_for(n, fbase);
+                KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                       hipLaunchKernelGGL(f32 ? k_big_finish<float> : k_big_finish<double>, dim3(nsk), dim3(256),
+                                          potrf_lds(fcap, fbase), s, LD.skd, LD.cref, LD.front, f->mp, LD.gp, LD.skli,
+                                          f->kout, f->pout, fcap, n, lvl, f->err));
+            } else
             KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
                    hipLaunchKernelGGL(f32 ? (staged == 4   ? k_skeletonize<4, float>
                                              : staged == 3 ? k_skeletonize<3, float>

@@ -23,6 +23,7 @@ FLAG_KERNEL_TIMES = 2
 KERNEL_MASK_SHIFT = 8
 FLAG_SOLVE_GRAPHS = 8
 FLAG_GLOBAL_STAGING = 16
+FLAG_SKEL_MULTI = 32
 NUM_KCLASS = 16
 NOALLOC_MAX_N = 1 << 20
 KCLASS_NAMES = ["front_csr", "front_extend", "elim_leaf", "elim_upper", "root", "precond_chol",

@@ -79,6 +79,28 @@ def test_small_parity(d, s, leaf, eps, kind, precond):
     print((d, s, leaf, eps, kind, precond), out)
 
 
+@pytest.mark.parametrize("d,s,leaf,eps,precision", [(2, 31, 4, 1e-6, 0), (2, 64, 16, 1e-3, 0), (3, 12, 4, 1e-3, 0),
+                                                     (3, 16, 4, 1e-3, 0), (2, 40, 8, 1e-6, 1)])
+def test_multi_workgroup_id_parity(d, s, leaf, eps, precision):
+    """RHIF_FLAG_SKEL_MULTI: the interpolative decompositions of every level taken by the form
+    that spreads each group's column-pivoted QR over row blocks (one launch per step), which
+    the large faces of the upper 3D levels take by default; it agrees with the oracle like the
+    one-workgroup forms (FP64), and converges in the FP32-mixed form."""
+    from paper_1808_01364_amd import rhif
+    P, A = problem("two_valued", d, s, leaf, eps, seed=7, lo=1e-2, hi=1e2)
+    if precision == 0:
+        out = _parity(P, A, flags=rhif.FLAG_SKEL_MULTI)
+        print((d, s, leaf, eps), out)
+        return
+    csr = gpu_csr(P)
+    F = rhif.Factor(P.d, P.s, csr, P.leaf, P.eps, 1, precision=precision, flags=rhif.FLAG_SKEL_MULTI)
+    u, it, rr = F.pcg(to_dev(P.f), 1e-12, 300)
+    ref = O.dense_solve(A, P.f)
+    print((d, s, leaf, eps, precision), it, rr, rel(_host(u), ref))
+    assert rr <= 1e-12 and rel(_host(u), ref) <= 1e-10
+    F.close()
+
+
 @pytest.mark.parametrize("d,s,leaf,eps", [(2, 31, 4, 1e-6), (3, 12, 4, 1e-3)])
 def test_global_staging_parity(d, s, leaf, eps):
     """The paths that groups too large for LDS take (block-Jacobi scaling and ID operands in
