@@ -211,6 +211,17 @@ rhif_status rhif_apply_half(rhif_factor_t f, const double *r, double *z, int32_t
 rhif_status rhif_estimate_es(rhif_factor_t f, const double *v0, int32_t maxit, double rtol, double *es,
                              int32_t *iters, hipStream_t s);
 
+/* y = F x = G G^T x, the forward product of the factorization (eq. (3.3)): every step of
+ * the two sweeps of eq. (3.2) undone in reverse order, with products by the stored factors
+ * instead of solves. x, y [device] N doubles (x == y allowed). Stream-ordered. */
+rhif_status rhif_apply_forward(rhif_factor_t f, const double *x, double *y, hipStream_t s);
+
+/* The apply error e_a = ||A - F||_2 / ||A||_2 of the factorization (Sec. 4), both norms by
+ * power iteration from the start vector v0, as for rhif_estimate_es.
+ *  ea [host] the estimate; iters [host, may be NULL] the larger of the two iteration counts. */
+rhif_status rhif_estimate_ea(rhif_factor_t f, const double *v0, int32_t maxit, double rtol, double *ea,
+                             int32_t *iters, hipStream_t s);
+
 /* Largest N that rhif_pcg_solve_noalloc accepts. */
 #define RHIF_NOALLOC_MAX_N (1 << 20)
 

@@ -2160,6 +2160,106 @@ RHIF_BIG_INST(float)
 
 
 // ---------------------------------------------------------------------------------------
+// The forward product F x = G G^T x (eq. (3.3)) for the apply error e_a = ||A - F|| / ||A||
+// (Sec. 4): every block of the apply (a cell's E: L and W^T in its frontal; a group's C: L_g;
+// a skeleton's K: L~, W~^T and T) undone with products instead of solves, in the reverse
+// order of the sweeps. One workgroup per block, operands read from HBM (a diagnostic, not a
+// hot path). Rows of L past the panel extents (banded leaf interiors) are structural zeros
+// and are skipped, as in the apply.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ int l_rows_end(const ApplyDesc& d, const int32_t* ext, int col) {
+    return (d.ext >= 0 && ext != nullptr) ? min(d.nI, static_cast<int>(ext[d.ext + col / 16])) : d.nI;
+}
+
+// Undo of a down-sweep block (part of G^T x): with T (a skeleton block), z_B += T z_I first;
+// then z_I <- L^T z_I + W z_B.
+__global__ __launch_bounds__(256) void k_fwd_gt(const ApplyDesc* __restrict__ ad, const double* __restrict__ pool,
+                                                const double* __restrict__ Tp, const int32_t* __restrict__ dofs,
+                                                const int32_t* __restrict__ ext, double* __restrict__ z) {
+    const ApplyDesc d = ad[blockIdx.x];
+    const int nI = d.nI, nB = d.nB, ld = d.ld, tid = threadIdx.x;
+    const double* A = pool + d.off;
+    const int32_t* di = dofs + d.dofs;
+    const int32_t* db = di + nI;
+    if (d.toff >= 0) {
+        const double* T = Tp + d.toff;
+        for (int h = tid; h < nB; h += kWG) {
+            double acc = 0.0;
+            for (int t = 0; t < nI; ++t) acc += T[h + static_cast<size_t>(t) * nB] * z[di[t]];
+            z[db[h]] += acc;
+        }
+        __syncthreads();
+    }
+    // rows in increasing chunks: the new z_I[i] reads the old z_I[e], e >= i
+    for (int c0 = 0; c0 < nI; c0 += kWG) {
+        const int i = c0 + tid;
+        double acc = 0.0;
+        if (i < nI) {
+            const double* col = A + static_cast<size_t>(i) * ld;
+            const int e1 = l_rows_end(d, ext, i);
+            for (int e = i; e < e1; ++e) acc += col[e] * z[di[e]];
+            for (int b = 0; b < nB; ++b) acc += col[nI + b] * z[db[b]];
+        }
+        __syncthreads();
+        if (i < nI) z[di[i]] = acc;
+        __syncthreads();
+    }
+}
+
+// Undo of an up-sweep block (part of G y): y = W^T z_I (to the scratch at yoff, summed into the
+// shared z_B by k_fwd_gather; or added to z_B in place), z_I <- L z_I, and with T (a skeleton
+// block) z_I += T^T z_B last.
+__global__ __launch_bounds__(256) void k_fwd_g(const ApplyDesc* __restrict__ ad, const double* __restrict__ pool,
+                                               const double* __restrict__ Tp, const int32_t* __restrict__ dofs,
+                                               const int32_t* __restrict__ ext, double* __restrict__ z,
+                                               double* __restrict__ ybuf) {
+    const ApplyDesc d = ad[blockIdx.x];
+    const int nI = d.nI, nB = d.nB, ld = d.ld, tid = threadIdx.x;
+    const double* A = pool + d.off;
+    const int32_t* di = dofs + d.dofs;
+    const int32_t* db = di + nI;
+    for (int b = tid; b < nB; b += kWG) {
+        double acc = 0.0;
+        for (int i = 0; i < nI; ++i) acc += A[(nI + b) + static_cast<size_t>(i) * ld] * z[di[i]];
+        if (d.yoff >= 0) ybuf[d.yoff + b] = acc;
+        else z[db[b]] += acc;
+    }
+    __syncthreads();
+    // rows in decreasing chunks: the new z_I[i] reads the old z_I[e], e <= i
+    for (int c1 = nI; c1 > 0; c1 -= kWG) {
+        const int i = c1 - kWG + tid;
+        double acc = 0.0;
+        if (i >= 0) {
+            for (int e = 0; e <= i; ++e)
+                if (i < l_rows_end(d, ext, e)) acc += A[i + static_cast<size_t>(e) * ld] * z[di[e]];
+        }
+        __syncthreads();
+        if (i >= 0) z[di[i]] = acc;
+        __syncthreads();
+    }
+    if (d.toff >= 0) {
+        const double* T = Tp + d.toff;
+        for (int t = tid; t < nI; t += kWG) {
+            double acc = 0.0;
+            for (int h = 0; h < nB; ++h) acc += T[h + static_cast<size_t>(t) * nB] * z[db[h]];
+            z[di[t]] += acc;
+        }
+    }
+}
+
+// z_g += the cells' contributions y of every separator group (the shared boundary unknowns).
+__global__ __launch_bounds__(256) void k_fwd_gather(const GatherDesc* __restrict__ gd, const int32_t* __restrict__ dofs,
+                                                    const double* __restrict__ ybuf, double* __restrict__ z) {
+    const GatherDesc g = gd[blockIdx.x];
+    for (int t = threadIdx.x; t < g.n; t += kWG) {
+        const int i = dofs[g.dofs + t];
+        double v = z[i];
+        for (int sl = 0; sl < g.nslot; ++sl) v += ybuf[g.yoff[sl] + t];
+        z[i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // Factor apply (eq. (3.2)). One workgroup per block; z_I and z_B are staged in LDS (or
 // in a global workspace for oversized blocks). Triangular solves go by 32-row blocks: the
 // diagonal block is solved by one wave from LDS, the rest is a GEMV by all threads.

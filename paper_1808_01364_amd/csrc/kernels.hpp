@@ -64,6 +64,11 @@ __global__ void k_big_finish(const SkelDesc* sd, const CellRef* cells, double* F
                              double* skli, const int32_t* kout, const int32_t* pout, int panel_cap, int nmax,
                              int level, unsigned long long* err);
 constexpr int kBigRowsHost = 256;   // rows of M per workgroup in the kernels above
+__global__ void k_fwd_gt(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
+                         const int32_t* ext, double* z);
+__global__ void k_fwd_g(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
+                        const int32_t* ext, double* z, double* ybuf);
+__global__ void k_fwd_gather(const GatherDesc* gd, const int32_t* dofs, const double* ybuf, double* z);
 __global__ void k_apply_up(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
                            double* z, double* ybuf, double* ws, const int32_t* ext);
 __global__ void k_apply_down(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,

@@ -1350,6 +1350,83 @@ void do_apply_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
     do_apply_down(f, z, s);
 }
 
+// z <- F z = G G^T z (eq. (3.3)): G^T undoes the down-sweep (levels 0 .. L-1: E, C, K) and the
+// backward root solve; G undoes the forward root solve and the up-sweep (levels L-1 .. 0: K, C,
+// then E with the cells' boundary contributions gathered into the shared unknowns).
+void do_forward_inplace(rhif_factor_s* f, double* z, hipStream_t s) {
+    const int L = f->L;
+    auto gt = [&](const rhif::ApplyDesc* ad, int n, const double* pool, const double* tp, const int32_t* dofs,
+                  const int32_t* ext) {
+        if (n > 0) hipLaunchKernelGGL(rhif::k_fwd_gt, dim3(n), dim3(256), 0, s, ad, pool, tp, dofs, ext, z);
+    };
+    auto gg = [&](const rhif::ApplyDesc* ad, int n, const double* pool, const double* tp, const int32_t* dofs,
+                  const int32_t* ext) {
+        if (n > 0) hipLaunchKernelGGL(rhif::k_fwd_g, dim3(n), dim3(256), 0, s, ad, pool, tp, dofs, ext, z, f->ybuf);
+    };
+    for (int lvl = 0; lvl < L; ++lvl) {
+        const LevelDev& LD = f->lev[lvl];
+        gt(LD.cell_ad, LD.n_cell_ad, LD.front, nullptr, LD.cdofs, LD.ext);
+        if (LD.precond) gt(LD.sep_ad, LD.n_sep_ad, LD.lg, nullptr, LD.sepdofs, nullptr);
+        gt(LD.skel_ad, LD.n_skel_ad, LD.gp, LD.tp, LD.skeldofs, nullptr);
+    }
+    const LevelDev& R = f->lev[L];
+    gt(R.cell_ad, R.n_cell_ad, R.front, nullptr, R.cdofs, R.ext);
+    gg(R.cell_ad, R.n_cell_ad, R.front, nullptr, R.cdofs, R.ext);
+    for (int lvl = L - 1; lvl >= 0; --lvl) {
+        const LevelDev& LD = f->lev[lvl];
+        gg(LD.skel_ad, LD.n_skel_ad, LD.gp, LD.tp, LD.skeldofs, nullptr);
+        if (LD.precond) gg(LD.sep_ad, LD.n_sep_ad, LD.lg, nullptr, LD.sepdofs, nullptr);
+        gg(LD.cell_ad, LD.n_cell_ad, LD.front, nullptr, LD.cdofs, LD.ext);
+        if (LD.n_gather > 0)
+            hipLaunchKernelGGL(rhif::k_fwd_gather, dim3(LD.n_gather), dim3(256), 0, s, LD.gat, LD.sepdofs, f->ybuf, z);
+    }
+    HIPCHK(hipGetLastError());
+}
+
+// ||op||_2 of a symmetric operator by power iteration on op^2 from the unit vector along v0:
+// the estimate sqrt(||op(op(v))||) after each normalized step, until it changes by at most rtol
+// (relative) or after maxit steps. op(x, y) writes y = op x; uses f->p, f->q, f->r.
+template <class Op>
+double power_norm(rhif_factor_s* f, const double* v0, int maxit, double rtol, Op op, int* iters, hipStream_t s) {
+    const int64_t N = f->g.N;
+    const int gb = grid_for(N);
+    double* v = f->p;
+    double* w = f->q;
+    double* hsc = f->hsc;
+    auto norm2 = [&](const double* x) {
+        hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, s, N, x, x, f->part);
+        hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, s, f->part, gb, 3, f->sc, nullptr);
+        HIPCHK(hipMemcpyAsync(hsc, f->sc, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return hsc[0];
+    };
+    const double n0 = norm2(v0);
+    if (!(n0 > 0.0)) fail(RHIF_EINVAL, "start vector is zero");
+    hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, v0, v);
+    hipLaunchKernelGGL(rhif::k_axpby, dim3(gb), dim3(256), 0, s, N, 0.0, v, 1.0 / std::sqrt(n0), v);
+    double est = 0.0;
+    int it = 0;
+    while (it < maxit) {
+        ++it;
+        op(v, f->r);
+        op(f->r, w);
+        const double nw = norm2(w);
+        const double now = std::sqrt(std::sqrt(nw));
+        if (nw == 0.0) {
+            est = 0.0;
+            break;
+        }
+        hipLaunchKernelGGL(rhif::k_axpby, dim3(gb), dim3(256), 0, s, N, 0.0, v, 1.0 / std::sqrt(nw), w);
+        std::swap(v, w);
+        const bool done = est > 0.0 && std::fabs(now - est) <= rtol * now;
+        est = now;
+        if (done) break;
+    }
+    HIPCHK(hipGetLastError());
+    if (iters) *iters = it;
+    return est;
+}
+
 void ensure_pcg(rhif_factor_s* f) {
     if (f->r) return;
     const size_t vb = f->g.N * sizeof(double);
@@ -1818,18 +1895,7 @@ rhif_status rhif_estimate_es(rhif_factor_t f, const double* v0, int32_t maxit, d
     ensure_pcg(f);
     const int64_t N = f->g.N;
     const int gb = grid_for(N);
-    double* v = f->p;
-    double* w = f->q;
     double* t = f->z;
-    double* hsc = f->hsc;
-    // |x|^2 of a device vector to the host (synchronizes the stream)
-    auto norm2 = [&](const double* x) {
-        hipLaunchKernelGGL(rhif::k_dot, dim3(gb), dim3(256), 0, s, N, x, x, f->part);
-        hipLaunchKernelGGL(rhif::k_finalize, dim3(1), dim3(256), 0, s, f->part, gb, 3, f->sc, nullptr);
-        HIPCHK(hipMemcpyAsync(hsc, f->sc, sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        return hsc[0];
-    };
     // y = x - G^-1 A G^-T x
     auto op = [&](const double* x, double* y) {
         hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, x, t);
@@ -1838,33 +1904,53 @@ rhif_status rhif_estimate_es(rhif_factor_t f, const double* v0, int32_t maxit, d
         do_apply_up(f, y, s);
         hipLaunchKernelGGL(rhif::k_axpby, dim3(gb), dim3(256), 0, s, N, 1.0, x, -1.0, y);
     };
-    const double n0 = norm2(v0);
-    if (!(n0 > 0.0)) fail(RHIF_EINVAL, "start vector is zero");
-    hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, v0, v);
-    hipLaunchKernelGGL(rhif::k_axpby, dim3(gb), dim3(256), 0, s, N, 0.0, v, 1.0 / std::sqrt(n0), v);
-    double est = 0.0;
     int it = 0;
-    while (it < maxit) {
-        ++it;
-        op(v, f->r);
-        op(f->r, w);
-        const double nw = norm2(w);
-        const double now = std::sqrt(std::sqrt(nw));
-        if (nw == 0.0) {
-            est = 0.0;
-            break;
-        }
-        hipLaunchKernelGGL(rhif::k_axpby, dim3(gb), dim3(256), 0, s, N, 0.0, v, 1.0 / std::sqrt(nw), w);
-        std::swap(v, w);
-        const bool done = est > 0.0 && std::fabs(now - est) <= rtol * now;
-        est = now;
-        if (done) break;
-    }
-    HIPCHK(hipGetLastError());
+    *es = power_norm(f, v0, maxit, rtol, op, &it, s);
     f->resolve();
     f->mark(s);
-    *es = est;
     if (iters) *iters = it;
+    API_END
+}
+
+rhif_status rhif_apply_forward(rhif_factor_t f, const double* x, double* y, hipStream_t s) {
+    API_BEGIN
+    if (!f || !x || !y) fail(RHIF_EINVAL, "NULL argument");
+    ensure_pcg(f);
+    const int64_t N = f->g.N;
+    hipLaunchKernelGGL(rhif::k_copy, dim3(grid_for(N)), dim3(256), 0, s, N, x, f->z);
+    do_forward_inplace(f, f->z, s);
+    hipLaunchKernelGGL(rhif::k_copy, dim3(grid_for(N)), dim3(256), 0, s, N, f->z, y);
+    HIPCHK(hipGetLastError());
+    f->mark(s);
+    API_END
+}
+
+rhif_status rhif_estimate_ea(rhif_factor_t f, const double* v0, int32_t maxit, double rtol, double* ea,
+                             int32_t* iters, hipStream_t s) {
+    API_BEGIN
+    if (!f || !v0 || !ea) fail(RHIF_EINVAL, "NULL argument");
+    if (maxit < 1 || !(rtol >= 0.0)) fail(RHIF_EINVAL, "bad maxit or rtol");
+    ensure_pcg(f);
+    const int64_t N = f->g.N;
+    const int gb = grid_for(N);
+    double* t = f->z;
+    auto opA = [&](const double* x, double* y) {
+        hipLaunchKernelGGL(rhif::k_spmv_dot, dim3(gb), dim3(256), 0, s, N, f->rp, f->ci, f->val, x, y, f->part);
+    };
+    // y = A x - F x
+    auto opD = [&](const double* x, double* y) {
+        hipLaunchKernelGGL(rhif::k_copy, dim3(gb), dim3(256), 0, s, N, x, t);
+        do_forward_inplace(f, t, s);
+        hipLaunchKernelGGL(rhif::k_spmv_dot, dim3(gb), dim3(256), 0, s, N, f->rp, f->ci, f->val, x, y, f->part);
+        hipLaunchKernelGGL(rhif::k_axpby, dim3(gb), dim3(256), 0, s, N, -1.0, t, 1.0, y);
+    };
+    int ia = 0, id = 0;
+    const double na = power_norm(f, v0, maxit, rtol, opA, &ia, s);
+    const double nd = power_norm(f, v0, maxit, rtol, opD, &id, s);
+    *ea = na > 0.0 ? nd / na : 0.0;
+    f->resolve();
+    f->mark(s);
+    if (iters) *iters = std::max(ia, id);
     API_END
 }
 

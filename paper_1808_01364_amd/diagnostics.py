@@ -1,7 +1,8 @@
 """Quality measures of a factorization, as the paper reports them (Sec. 4, Tables 1-2): the
-root size |S_L|, the solve error e_s = ||I - G^-1 A G^-T|| (power iteration on the GPU,
-rhif_estimate_es) and the PCG iteration count n_i to a relative residual of 1e-12, for the
-recursively preconditioned factorization (PHIF) against plain HIF on the same problem.
+root size |S_L|, the apply error e_a = ||A - F|| / ||A|| and the solve error
+e_s = ||I - G^-1 A G^-T|| (power iteration on the GPU: rhif_estimate_ea, rhif_estimate_es) and
+the PCG iteration count n_i to a relative residual of 1e-12, for the recursively preconditioned
+factorization (PHIF) against plain HIF on the same problem.
 
     python -m paper_1808_01364_amd.diagnostics 2 1023 8 1e-4 1e-6     # dim side leaf eps...
 
@@ -17,7 +18,7 @@ from . import rhif
 
 
 def trend_row(P, precond: int, seed: int = 0, maxit: int = 500) -> dict:
-    """|S_L|, e_s, n_i and the factor / solve times of one problem (a workloads.Problem) with
+    """|S_L|, e_a, e_s, n_i and the factor / solve times of one problem (a workloads.Problem) with
     block-Jacobi preconditioning on (PHIF) or off (HIF)."""
     import torch
     dev = "cuda"
@@ -33,6 +34,7 @@ def trend_row(P, precond: int, seed: int = 0, maxit: int = 500) -> dict:
         return {"N": P.N, "eps": P.eps, "method": "PHIF" if precond else "HIF", "not_spd": str(e)}
     t1 = time.perf_counter()
     st = F.stats()
+    ea, ea_it = F.estimate_ea(seed=seed)
     es, es_it = F.estimate_es(seed=seed)
     try:
         u, it, rr = F.pcg(f, 1e-12, maxit)
@@ -41,8 +43,8 @@ def trend_row(P, precond: int, seed: int = 0, maxit: int = 500) -> dict:
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     F.close()
-    return {"N": P.N, "eps": P.eps, "method": "PHIF" if precond else "HIF", "S_L": st["root_size"], "e_s": es,
-            "e_s_iters": es_it, "n_i": it, "relres": rr, "t_factor_ms": 1e3 * (t1 - t0)}
+    return {"N": P.N, "eps": P.eps, "method": "PHIF" if precond else "HIF", "S_L": st["root_size"], "e_a": ea,
+            "e_s": es, "e_a_iters": ea_it, "e_s_iters": es_it, "n_i": it, "relres": rr, "t_factor_ms": 1e3 * (t1 - t0)}
 
 
 def main(argv):

@@ -3,7 +3,11 @@
     python -m paper_1808_01364_amd.prof_summary stats  <run_kernel_stats.csv> <out.txt> "<command>"
     python -m paper_1808_01364_amd.prof_summary traffic <fetch counter csv> <write counter csv> <out.txt> \
         "<command>" [kernel ...]
+    python -m paper_1808_01364_amd.prof_summary mfma <counter csv> <out.txt> "<command>"
 
+The mfma summary gives, per kernel, the matrix-core busy fraction
+SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs) over its dispatches (1024 SIMDs: 256 CUs of
+4) and the FP64 / FP32 matrix flops (SQ_INSTS_VALU_MFMA_MOPS_* x 512).
 The traffic summary scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) by what the same
 counters read for the library's plain copy kernel (k_copy, 2 x 8 x N bytes per dispatch),
 and records the SHA-256 of the kernel source so that stale figures can be recognized.
@@ -95,6 +99,33 @@ def traffic(fetch_csv: str, write_csv: str, out: str, command: str, kernels=None
     open(out, "w").write("\n".join(lines) + "\n")
 
 
+SIMDS = 1024
+
+
+def mfma(csv_path: str, out: str, command: str, top: int = 24) -> None:
+    vals = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    for r in csv.DictReader(open(csv_path)):
+        k = _short(r["Kernel_Name"])
+        vals[k][r["Counter_Name"]] += float(r["Counter_Value"])
+        disp[k].add(r.get("Dispatch_Id", ""))
+    lines = ["# matrix-core use per kernel from rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES "
+             "SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_BUSY_CYCLES GRBM_GUI_ACTIVE",
+             f"command: {command}", f"kernels_hip_sha256: {kernel_source_sha()}",
+             "mfma_busy = sum SQ_VALU_MFMA_BUSY_CYCLES / (sum GRBM_GUI_ACTIVE x 1024 SIMDs) over the dispatches", "",
+             f"{'kernel':<22} {'dispatches':>10} {'mfma_busy':>10} {'f64_mfma_GFLOP':>15} {'f32_mfma_GFLOP':>15}"]
+    rows = []
+    for k, v in vals.items():
+        gui = v.get("GRBM_GUI_ACTIVE", 0.0)
+        busy = v.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (gui * SIMDS) if gui > 0 else 0.0
+        rows.append((k, len(disp[k]), busy, 512.0 * v.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) / 1e9,
+                     512.0 * v.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) / 1e9, gui))
+    rows.sort(key=lambda t: -t[5])
+    for k, nd, busy, g64, g32, _ in rows[:top]:
+        lines.append(f"{k[:22]:<22} {nd:>10} {busy:>10.4f} {g64:>15.3f} {g32:>15.3f}")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
 def read_traffic(path: str, kernels):
     """Scaled HBM bytes per dispatch over `kernels` (a name or a tuple of names; dispatch-weighted
     mean) from a traffic summary, or None if the summary is missing, lists none of them, or was
@@ -124,5 +155,7 @@ if __name__ == "__main__":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif mode == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6:] or None)
+    elif mode == "mfma":
+        mfma(sys.argv[2], sys.argv[3], sys.argv[4])
     else:
         raise SystemExit(__doc__)

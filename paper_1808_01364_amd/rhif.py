@@ -32,7 +32,8 @@ KCLASS_NAMES = ["front_csr", "front_extend", "elim_leaf", "elim_upper", "root", 
 
 # every function declared in include/rhif.h
 EXPORTED = ["rhif_fd_nnz", "rhif_assemble_fd", "rhif_factor", "rhif_apply", "rhif_pcg_solve",
-            "rhif_pcg_solve_noalloc", "rhif_apply_half", "rhif_estimate_es", "rhif_matvec", "rhif_grad_log_a", "rhif_stats", "rhif_skeletons", "rhif_destroy",
+            "rhif_pcg_solve_noalloc", "rhif_apply_half", "rhif_estimate_es",
+            "rhif_apply_forward", "rhif_estimate_ea", "rhif_matvec", "rhif_grad_log_a", "rhif_stats", "rhif_skeletons", "rhif_destroy",
             "rhif_last_error", "rhif_version"]
 
 
@@ -104,6 +105,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rhif_pcg_solve_noalloc.argtypes = lib.rhif_pcg_solve.argtypes
     lib.rhif_matvec.argtypes = [vp, vp, vp, vp]
     lib.rhif_apply_half.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
+    lib.rhif_apply_forward.argtypes = [vp, vp, vp, vp]
+    lib.rhif_estimate_ea.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                     c_i32p, vp]
     lib.rhif_estimate_es.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                      c_i32p, vp]
     lib.rhif_grad_log_a.argtypes = [ctypes.POINTER(Grid), vp, vp, vp, vp, vp]
@@ -264,15 +268,37 @@ class Factor:
         _check(self._lib.rhif_apply_half(self.handle, _ptr(r), _ptr(z), 1 if transpose else 0, _stream(stream)))
         return z
 
-    def estimate_es(self, v0=None, seed: int = 0, maxit: int = 50, rtol: float = 1e-2, stream=None):
-        """(e_s, iterations): ||I - G^-1 A G^-T||_2 by power iteration (Sec. 4). The start vector
-        is v0 (device, N values) or, if None, numpy.random.default_rng(seed).standard_normal(N)."""
+    def apply_forward(self, x, out=None, stream=None):
+        """y = F x = G G^T x (the forward product of the factorization)."""
+        _need((x, "x", self.N), *([(out, "out", self.N)] if out is not None else []))
+        torch = _torch()
+        y = out if out is not None else torch.empty_like(x)
+        _check(self._lib.rhif_apply_forward(self.handle, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def _start(self, v0, seed):
         torch = _torch()
         if v0 is None:
             import numpy as np
             v0 = torch.tensor(np.random.default_rng(seed).standard_normal(self.N), dtype=torch.float64,
                               device="cuda")
         _need((v0, "v0", self.N))
+        return v0
+
+    def estimate_ea(self, v0=None, seed: int = 0, maxit: int = 50, rtol: float = 1e-2, stream=None):
+        """(e_a, iterations): ||A - F||_2 / ||A||_2 by power iteration (Sec. 4); start vector as
+        for estimate_es."""
+        v0 = self._start(v0, seed)
+        ea = ctypes.c_double()
+        it = ctypes.c_int32()
+        _check(self._lib.rhif_estimate_ea(self.handle, _ptr(v0), maxit, rtol, ctypes.byref(ea), ctypes.byref(it),
+                                          _stream(stream)))
+        return ea.value, it.value
+
+    def estimate_es(self, v0=None, seed: int = 0, maxit: int = 50, rtol: float = 1e-2, stream=None):
+        """(e_s, iterations): ||I - G^-1 A G^-T||_2 by power iteration (Sec. 4). The start vector
+        is v0 (device, N values) or, if None, numpy.random.default_rng(seed).standard_normal(N)."""
+        v0 = self._start(v0, seed)
         es = ctypes.c_double()
         it = ctypes.c_int32()
         _check(self._lib.rhif_estimate_es(self.handle, _ptr(v0), maxit, rtol, ctypes.byref(es), ctypes.byref(it),

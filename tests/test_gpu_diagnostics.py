@@ -1,5 +1,6 @@
-"""The halves of the factor apply (z = G^-1 r, z = G^-T r) and the solve-error estimate
-e_s = ||I - G^-1 A G^-T|| (Sec. 4) through the C ABI, against the oracle's."""
+"""The halves of the factor apply (z = G^-1 r, z = G^-T r), the forward product F x = G G^T x,
+and the error estimates e_a = ||A - F|| / ||A|| and e_s = ||I - G^-1 A G^-T|| (Sec. 4) through
+the C ABI, against the oracle's."""
 import numpy as np
 import pytest
 
@@ -57,3 +58,57 @@ def test_block_jacobi_improves_es_at_scale():
     assert es_p * 10 < es_h
     Fp.close()
     Fh.close()
+
+
+@pytest.mark.parametrize("case", ["2d_constant", "2d_contrast", "3d"])
+def test_forward_against_oracle(case):
+    """F x = G G^T x on the GPU against the oracle's (replaying the GPU's choices) to 100 u;
+    the apply undoes it to within the conditioning of F."""
+    if case == "2d_constant":
+        P, A = problem("constant", 2, 64, 8, 1e-3)
+    elif case == "2d_contrast":
+        P, A = problem("two_valued", 2, 48, 4, 1e-3, seed=2, lo=1e-2, hi=1e2)
+    else:
+        P, A = problem("two_valued", 3, 12, 4, 1e-3, seed=3, lo=1e-1, hi=1e1)
+    F = gpu_factor(P)
+    rep = O.factor(A, P.d, P.s, P.leaf, P.eps, P.precond, replay=gpu_choices(F, F.stats()["levels"]))
+    x = np.random.default_rng(5).standard_normal(P.N)
+    xd = to_dev(x)
+    y = _host(F.apply_forward(xd))
+    ref = O.apply_forward(rep, x)
+    e = rel(y, ref)
+    back = rel(_host(F.apply(to_dev(y))), x)
+    print(case, "F x", e, rel_max(y, ref), "F^-1 F x - x", back, flush=True)
+    assert e <= 100 * U
+    assert back <= 1e-8
+    # in place (x and y the same buffer)
+    F.apply_forward(xd, out=xd)
+    assert np.array_equal(_host(xd), y)
+    F.close()
+
+
+def test_forward_is_a_at_tight_tolerance():
+    """With eps 1e-12 nothing of size is dropped, so F x agrees with A x to about eps
+    (Prop. 1.1: F = A when no skeletonization error is made)."""
+    P, A = problem("two_valued", 2, 48, 4, 1e-12, seed=4, lo=1e-2, hi=1e2)
+    F = gpu_factor(P)
+    x = np.random.default_rng(6).standard_normal(P.N)
+    y = _host(F.apply_forward(to_dev(x)))
+    e = rel(y, A @ x)
+    print("||F x - A x|| / ||A x||", e, flush=True)
+    assert e <= 1e-9
+    F.close()
+
+
+@pytest.mark.parametrize("precond", [1, 0])
+def test_ea_against_oracle(precond):
+    """e_a by power iteration on the GPU and in the oracle, from the same start vector, agree
+    to the estimators' 1e-2 precision (within 5 %)."""
+    P, A = problem("two_valued", 2, 48, 4, 1e-3, seed=2, precond=precond, lo=1e-2, hi=1e2)
+    F = gpu_factor(P)
+    ea_g, it = F.estimate_ea(seed=0)
+    rep = O.factor(A, P.d, P.s, P.leaf, P.eps, precond, replay=gpu_choices(F, F.stats()["levels"]))
+    ea_o = O.estimate_ea(A, rep, seed=0)
+    print("precond", precond, "e_a GPU", ea_g, "iterations", it, "oracle", ea_o, flush=True)
+    assert abs(ea_g - ea_o) <= 0.05 * ea_o
+    F.close()
