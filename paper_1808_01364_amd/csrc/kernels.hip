@@ -498,6 +498,192 @@ __device__ __forceinline__ int wg_cpqr_rows(MR* __restrict__ M, int ldr, int r, 
 }
 
 // ---------------------------------------------------------------------------------------
+// The same column-pivoted Householder QR as wg_cpqr_rows (pivot rule, ties, stopping test,
+// reflector, R left in M) for n <= 64, with the matrix in registers: thread t owns column
+// t % cw over row chunk t / cw (the layout above) and holds its cs <= RPT entries, so that a
+// step reads no matrix entry from memory. Row j, the row a step works on, is kept apart: at
+// the end of step j - 1 the chunk holding row j moves it to LDS (rowj) and shifts its registers
+// down by one, so the registers hold exactly the rows below j (and zeros) and the row loops
+// run over all of them with no bounds. Then
+//   w_c = v0 rowj[c] + sum over the registers of piv_i x_i(c),   x_i(c) -= beta w_c piv_i,
+// piv being the pivot column's entry of the same row (read from the lane that holds it: a lane
+// read when cw = 64, one chunk per wave; a wave shuffle otherwise), and row j of R follows from
+// rowj. Column sums are reduced over the wave's chunks by butterflies and over the four waves
+// through LDS in a fixed order, so every thread holds the same sums and takes the same pivot.
+// part: 9 * 64 values of MR (per-wave dot and norm sums, rowj).
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int l) {
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b), l));
+        const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), l));
+        return __builtin_bit_cast(T, (static_cast<unsigned long long>(hi) << 32) | lo);
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+    }
+}
+
+// v of the lane given by the DPP pattern CTRL (within a row of 16 lanes)
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_value(T v) {
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xF, 0xF, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
+        return __builtin_bit_cast(T, (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+                                         static_cast<unsigned>(lo));
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF,
+                                                                 false));
+    }
+}
+
+template <int RPT, typename MR, bool UNI>
+__device__ __forceinline__ int wg_cpqr_regs(MR* __restrict__ M, int ldr, int r, int n, double eps, int* pos,
+                                            int* perm, double* part_) {
+    MR* part = reinterpret_cast<MR*>(part_);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int cw = 64;
+    if constexpr (!UNI) {
+        cw = 1;
+        while (cw < n && cw < 64) cw <<= 1;
+    }
+    const int nrc = kWG / cw;
+    const int cl = UNI ? lane : tid % cw;
+    const int rc = UNI ? wave : tid / cw;
+    const int cs = (r + nrc - 1) / nrc;
+    const int i0 = rc * cs, i1 = min(r, i0 + cs);
+    const bool own = cl < n;
+    const int base = UNI ? 0 : (lane & ~(cw - 1));   // first lane of this thread's chunk in the wave
+    MR* pw = part;                                   // [wave][64] dot sums
+    MR* pq = part + 4 * 64;                          // [wave][64] squared-norm sums
+    MR* rowj = part + 8 * 64;                        // row j of every column
+    auto wave_col_sum = [&](MR v) {
+        if constexpr (!UNI)
+            for (int off = 32; off >= cw; off >>= 1) v += __shfl_xor(v, off, 64);
+        return v;
+    };
+    auto piv = [&](MR xu, int src) -> MR {
+        if constexpr (UNI) return lane_value(xu, src);
+        else return __shfl(xu, base + src, 64);
+    };
+    MR x[RPT];
+    // row `row` to rowj: its chunk's registers hold it first and shift down by one
+    auto take = [&](int row) {
+        if (rc == row / cs) {
+            if (own) rowj[cl] = x[0];
+#pragma unroll
+            for (int u = 0; u + 1 < RPT; ++u) x[u] = x[u + 1];
+            x[RPT - 1] = MR(0);
+        }
+    };
+    MR s0 = 0, s1 = 0;
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int i = i0 + u;
+        x[u] = (own && i < i1) ? M[static_cast<size_t>(i) * ldr + cl] : MR(0);
+        if (u & 1) s1 += x[u] * x[u];
+        else s0 += x[u] * x[u];
+    }
+    {
+        const MR sq = wave_col_sum(s0 + s1);
+        if (lane < cw) pq[wave * 64 + cl] = sq;
+    }
+    if (r > 0) take(0);
+    for (int c = tid; c < n; c += kWG) {
+        pos[c] = c;
+        perm[c] = c;
+    }
+    int mypos = cl;
+    __syncthreads();
+    const int kmax = min(r, n);
+    MR r11 = 0;
+    int k = 0;
+    for (int j = 0; j < kmax; ++j) {
+        // (a) pivot: the largest squared norm among columns at positions >= j, ties to the
+        //     lowest position; the same in every lane of every wave
+        const MR nrm2 = (pq[cl] + pq[64 + cl]) + (pq[128 + cl] + pq[192 + cl]);
+        const bool cand = own && mypos >= j;
+        MR best = cand ? nrm2 : MR(-1);
+        int bpos = cand ? mypos : 0x7fffffff, bc = cl;
+        auto keep_max = [&](MR ob, int op, int oc) {
+            const bool tk = ob > best || (ob == best && op < bpos);
+            best = tk ? ob : best;
+            bpos = tk ? op : bpos;
+            bc = tk ? oc : bc;
+        };
+        // butterfly over the cw lanes of a chunk: lane ^ 1, lane ^ 2 (quad permutes), the
+        // mirrored lane in the half row and in the row (DPP), then lane ^ 16, lane ^ 32
+        if (cw > 1) keep_max(dpp_value<0xB1>(best), dpp_value<0xB1>(bpos), dpp_value<0xB1>(bc));
+        if (cw > 2) keep_max(dpp_value<0x4E>(best), dpp_value<0x4E>(bpos), dpp_value<0x4E>(bc));
+        if (cw > 4) keep_max(dpp_value<0x141>(best), dpp_value<0x141>(bpos), dpp_value<0x141>(bc));
+        if (cw > 8) keep_max(dpp_value<0x140>(best), dpp_value<0x140>(bpos), dpp_value<0x140>(bc));
+        if (cw > 16) keep_max(__shfl_xor(best, 16, 64), __shfl_xor(bpos, 16, 64), __shfl_xor(bc, 16, 64));
+        if (cw > 32) keep_max(__shfl_xor(best, 32, 64), __shfl_xor(bpos, 32, 64), __shfl_xor(bc, 32, 64));
+        const int pc = __builtin_amdgcn_readfirstlane(bc);
+        const int q = __builtin_amdgcn_readfirstlane(bpos);
+        const MR nrm = sqrt(lane_value(best, 0));
+        if (j == 0) r11 = nrm;
+        if (!(nrm > static_cast<MR>(eps) * r11)) break;
+        if (tid == 0) {
+            const int qq = pos[pc], cj = perm[j];
+            perm[j] = pc;
+            perm[qq] = cj;
+            pos[cj] = qq;
+            pos[pc] = j;
+        }
+        // (b) reflector of column pc over rows j..: v = (x0 - alpha, x1, ...), beta = 2 / v^T v
+        const MR xj = rowj[cl];
+        const MR x0 = lane_value(rowj[pc], 0);
+        const MR alpha = -copysign(nrm, x0);
+        const MR v0 = x0 - alpha;
+        const MR beta = MR(1) / (nrm * (nrm + fabs(x0)));
+        const bool act = own && cl != pc && mypos >= j;
+        // (c) w_c = v^T M[j:, c]: rows > j from the registers, row j from rowj
+        MR wa = 0, wb = 0;
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+            if (u & 1) wb += piv(x[u], pc) * x[u];
+            else wa += piv(x[u], pc) * x[u];
+        }
+        {
+            const MR ws = wave_col_sum(wa + wb);
+            if (lane < cw) pw[wave * 64 + cl] = ws;
+        }
+        __syncthreads();
+        // (d) M[j:, c] -= beta w_c v (columns not chosen yet), and the new squared norms over
+        //     rows j+1..; the pivot is read back from perm so that no copy of its entries stays
+        //     live across the barrier
+        const int pcu = __builtin_amdgcn_readfirstlane(perm[j]);
+        const MR f = beta * (((pw[cl] + pw[64 + cl]) + (pw[128 + cl] + pw[192 + cl])) + v0 * xj);
+        const MR fa = act ? f : MR(0);
+        MR n0 = 0, n1 = 0;
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+            x[u] -= fa * piv(x[u], pcu);
+            if (u & 1) n1 += x[u] * x[u];
+            else n0 += x[u] * x[u];
+        }
+        {
+            const MR sq = wave_col_sum(n0 + n1);
+            if (lane < cw) pq[wave * 64 + cl] = sq;
+            // row j of R: final after this step
+            if (tid < n) M[static_cast<size_t>(j) * ldr + cl] = act ? xj - f * v0 : (cl == pc ? alpha : xj);
+        }
+        // row j + 1 to rowj (its reads of this step came before the first barrier)
+        if (j + 1 < r) take(j + 1);
+        if (cl == pc) mypos = j;
+        else if (mypos == j) mypos = q;
+        __syncthreads();
+        k = j + 1;
+    }
+    __syncthreads();
+    return k;
+}
+
+// ---------------------------------------------------------------------------------------
 // Adjoint of the solve with respect to the log-coefficients theta = log a (one thread per
 // grid cell). A depends on a_c through the cell's share of the stencil (eq. (1.1) with the
 // edge rule of the assembly below): every grid edge (x, x + e_k) of cell c carries
@@ -1745,8 +1931,41 @@ __device__ __forceinline__ void skel_eliminate(const SkelDesc& g, int k, const i
     }
 }
 
+// The ID of one group: from registers (wg_cpqr_regs) when n <= 64 and a thread's rows fit the
+// largest register form compiled in (RMAX per thread; 32 when a wave holds several chunks),
+// else wg_cpqr_rows. The register form used is the smallest that holds the rows.
+template <int RMAX, int UR, typename MR>
+__device__ __forceinline__ int cpqr_any(MR* M, int ldr, int r, int n, double eps, int* pos, int* perm,
+                                        double* part) {
+    int cw = 1;
+    while (cw < n && cw < 64) cw <<= 1;
+    const int cs = (r + kWG / cw - 1) / (kWG / cw);
+    if (n > 64 || cs > (cw < 64 ? (RMAX < 32 ? RMAX : 32) : RMAX))
+        return wg_cpqr_rows<UR, MR>(M, ldr, r, n, eps, pos, perm, part);
+    if (cw < 64) {
+        if (cs <= 8) return wg_cpqr_regs<8, MR, false>(M, ldr, r, n, eps, pos, perm, part);
+        if constexpr (RMAX >= 32)
+            if (cs > 16) return wg_cpqr_regs<32, MR, false>(M, ldr, r, n, eps, pos, perm, part);
+        return wg_cpqr_regs<16, MR, false>(M, ldr, r, n, eps, pos, perm, part);
+    }
+    if constexpr (RMAX >= 32) {
+        if (cs > 16) {
+            if constexpr (RMAX >= 64) {
+                if (cs > 32) {
+                    if constexpr (RMAX > 64)
+                        if (cs > 64) return wg_cpqr_regs<RMAX, MR, true>(M, ldr, r, n, eps, pos, perm, part);
+                    return wg_cpqr_regs<64, MR, true>(M, ldr, r, n, eps, pos, perm, part);
+                }
+            }
+            return wg_cpqr_regs<32, MR, true>(M, ldr, r, n, eps, pos, perm, part);
+        }
+    }
+    return wg_cpqr_regs<16, MR, true>(M, ldr, r, n, eps, pos, perm, part);
+}
+
 // MR: arithmetic of the ID (M, its QR and T); double, or float in the mixed-precision form.
-template <bool SM, bool SG, typename MR>
+// RMAX: the most rows of M per thread for which the ID runs from registers (cpqr_any).
+template <bool SM, bool SG, typename MR, int RMAX>
 __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t* __restrict__ cgptr,
                                                 const int32_t* __restrict__ cgl, const int32_t* __restrict__ cgoff,
                                                 const CellRef* __restrict__ cells, double* __restrict__ F,
@@ -1763,7 +1982,7 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
     int* perm = pos + nmax;
     int* rwl = reinterpret_cast<int*>(smem + ipd);
     double* part = smem + ipd + rmax;
-    double* after = part + 2 * kWG * nbm;
+    double* after = part + 2 * kWG * nbm + kCpqrRegExtra;
     MR* __restrict__ M = SM ? reinterpret_cast<MR*>(after) : reinterpret_cast<MR*>(Mpool + g.moff);
     // M occupies rmax (nmax | 1) values of MR, rounded up to whole doubles
     const size_t m_doubles = (static_cast<size_t>(rmax) * (nmax | 1) * sizeof(MR) + sizeof(double) - 1) / sizeof(double);
@@ -1801,7 +2020,7 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
     }
     __syncthreads();
     // 2. ID: rank k, pivot order, and T = R11^-1 R12 solved in place over R12
-    const int k = wg_cpqr_rows<SM ? 8 : 16, MR>(M, ldr, r, n, eps, pos, perm, part);
+    const int k = cpqr_any<RMAX, SM ? 8 : 16, MR>(M, ldr, r, n, eps, pos, perm, part);
     const int nr = n - k;
     // column-oriented back substitution, every (row, column) update of a step in parallel:
     // t_i = x_i / R_ii, then x_e -= R_ei t_i for e < i
@@ -1835,8 +2054,10 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
 // STAGED: 3 = M and G in LDS, 1 = M in LDS, 0 = both in the global pools; 4 = the layout of 3
 // compiled for kSkelWavesMany waves per SIMD (fewer registers), for launches with many more
 // groups than compute units, where more resident groups per CU hide the latency of each.
-// One kernel per form, so that each keeps the register budget of its own code.
-template <int STAGED, typename MR>
+// One kernel per form, so that each keeps the register budget of its own code. RMAX (16, 32 or
+// 96; 16 for form 4): the largest register form of the ID compiled in, chosen per level from
+// its groups' sizes, since the registers of the largest form bound the groups resident per CU.
+template <int STAGED, typename MR, int RMAX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STAGED == 4 ? kSkelWavesMany : 1))) void k_skeletonize(const SkelDesc* __restrict__ sd, const int32_t* __restrict__ cgptr,
                                                      const int32_t* __restrict__ cgl, const int32_t* __restrict__ cgoff,
                                                      const CellRef* __restrict__ cells, double* __restrict__ F,
@@ -1847,23 +2068,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STAGED == 4
                                                      unsigned long long* err) {
     extern __shared__ double smem[];
     const SkelDesc g = sd[blockIdx.x];
-    skeletonize_one<STAGED != 0, STAGED >= 3, MR>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout,
+    skeletonize_one<STAGED != 0, STAGED >= 3, MR, RMAX>(g, cgptr, cgl, cgoff, cells, F, Mpool, Tpool, Gpool, skli, eps, kout,
                                               pout, panel_cap, nmax, rmax, level, err, smem);
 }
 
-#define RHIF_SKEL_INST(S, MR)                                                                                      \
-    template __global__ void k_skeletonize<S, MR>(const SkelDesc*, const int32_t*, const int32_t*, const int32_t*, \
-                                                  const CellRef*, double*, double*, double*, double*, double*,     \
-                                                  double, int32_t*, int32_t*, int, int, int, int,                 \
-                                                  unsigned long long*);
-RHIF_SKEL_INST(0, double)
-RHIF_SKEL_INST(1, double)
-RHIF_SKEL_INST(3, double)
-RHIF_SKEL_INST(4, double)
-RHIF_SKEL_INST(0, float)
-RHIF_SKEL_INST(1, float)
-RHIF_SKEL_INST(3, float)
-RHIF_SKEL_INST(4, float)
+#define RHIF_SKEL_INST(S, MR, RM)                                                                                  \
+    template __global__ void k_skeletonize<S, MR, RM>(const SkelDesc*, const int32_t*, const int32_t*,             \
+                                                      const int32_t*, const CellRef*, double*, double*, double*,   \
+                                                      double*, double*, double, int32_t*, int32_t*, int, int, int, \
+                                                      int, unsigned long long*);
+#define RHIF_SKEL_INST3(S, MR) RHIF_SKEL_INST(S, MR, 16) RHIF_SKEL_INST(S, MR, 32) RHIF_SKEL_INST(S, MR, 96)
+RHIF_SKEL_INST3(0, double)
+RHIF_SKEL_INST3(1, double)
+RHIF_SKEL_INST3(3, double)
+RHIF_SKEL_INST(4, double, 16)
+RHIF_SKEL_INST3(0, float)
+RHIF_SKEL_INST3(1, float)
+RHIF_SKEL_INST3(3, float)
+RHIF_SKEL_INST(4, float, 16)
+#undef RHIF_SKEL_INST3
 #undef RHIF_SKEL_INST
 
 // ---------------------------------------------------------------------------------------

@@ -37,7 +37,11 @@ __global__ void k_precond_scale(const CellScaleDesc* cd, const CellGroup* cg, co
                                 double* F, int pstride);
 // waves per SIMD of the skeletonization form for launches with many groups per CU
 constexpr int kSkelWavesMany = 4;
-template <int STAGED, typename MR>
+// LDS of k_skeletonize beyond the partials of wg_cpqr_rows that the register ID needs
+constexpr int kCpqrRegExtra = 64;
+// rows of M per thread of the register forms of the ID compiled into k_skeletonize
+constexpr int kSkelRegForms[3] = {16, 32, 96};
+template <int STAGED, typename MR, int RMAX>
 __global__ void k_skeletonize(const SkelDesc* sd, const int32_t* cgptr, const int32_t* cgl, const int32_t* cgoff,
                               const CellRef* cells, double* F,
                               double* Mpool, double* Tpool, double* Gpool, double* skli, double eps, int32_t* kout,

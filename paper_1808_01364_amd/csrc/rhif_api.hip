@@ -608,6 +608,38 @@ size_t potrf_lds(int cap, int reserved) {
     return static_cast<size_t>(reserved + rhif::kPotrfSmemFixed + cap * 17) * sizeof(double);
 }
 
+using SkelKernel = decltype(&rhif::k_skeletonize<0, double, 16>);
+
+// the k_skeletonize instance of a storage form, register form (rows per thread) and precision
+template <typename MR>
+SkelKernel skel_kernel_of(int staged, int rm) {
+    using namespace rhif;
+    if (staged == 4) return k_skeletonize<4, MR, 16>;
+    if (rm <= 16)
+        return staged == 3 ? k_skeletonize<3, MR, 16> : staged == 1 ? k_skeletonize<1, MR, 16> : k_skeletonize<0, MR, 16>;
+    if (rm <= 32)
+        return staged == 3 ? k_skeletonize<3, MR, 32> : staged == 1 ? k_skeletonize<1, MR, 32> : k_skeletonize<0, MR, 32>;
+    return staged == 3 ? k_skeletonize<3, MR, 96> : staged == 1 ? k_skeletonize<1, MR, 96> : k_skeletonize<0, MR, 96>;
+}
+
+SkelKernel skel_kernel(int staged, int rm, bool f32) {
+    return f32 ? skel_kernel_of<float>(staged, rm) : skel_kernel_of<double>(staged, rm);
+}
+
+// rows of M per thread that the register ID needs for the level's groups (the largest over
+// groups with n <= 64; the same chunking as the kernel's)
+int skel_rows_per_thread(const std::vector<rhif::SkelDesc>& groups) {
+    int cs_max = 0;
+    for (const auto& sk : groups) {
+        if (sk.n > 64) continue;
+        int cw = 1;
+        while (cw < sk.n && cw < 64) cw <<= 1;
+        const int nrc = 256 / cw;
+        cs_max = std::max(cs_max, (sk.r + nrc - 1) / nrc);
+    }
+    return cs_max;
+}
+
 void set_kernel_attributes() {
     static std::once_flag once;
     std::call_once(once, [] {
@@ -616,15 +648,14 @@ void set_kernel_attributes() {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         for (const void* k : {reinterpret_cast<const void*>(&rhif::k_big_finish<double>),
                               reinterpret_cast<const void*>(&rhif::k_big_finish<float>),
-                              reinterpret_cast<const void*>(&rhif::k_skeletonize<0, double>),
-                              reinterpret_cast<const void*>(&rhif::k_skeletonize<1, double>),
-                              reinterpret_cast<const void*>(&rhif::k_skeletonize<3, double>),
-                              reinterpret_cast<const void*>(&rhif::k_skeletonize<4, double>),
-                              reinterpret_cast<const void*>(&rhif::k_skeletonize<0, float>),
-                              reinterpret_cast<const void*>(&rhif::k_skeletonize<1, float>),
-                              reinterpret_cast<const void*>(&rhif::k_skeletonize<3, float>),
-                              reinterpret_cast<const void*>(&rhif::k_skeletonize<4, float>)})
+                              reinterpret_cast<const void*>(&rhif::k_skeletonize<4, double, 16>),
+                              reinterpret_cast<const void*>(&rhif::k_skeletonize<4, float, 16>)})
             (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        for (int staged : {0, 1, 3})
+            for (int rm : rhif::kSkelRegForms)
+                for (bool f32 : {false, true})
+                    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(skel_kernel(staged, rm, f32)),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_apply_group_up),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_apply_group_dn),
@@ -1053,7 +1084,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             int rmax = 1;
             for (const auto& sk : P.skel_desc) rmax = std::max(rmax, sk.r);
             // must match the LDS layout of k_skeletonize
-            const int base = (2 * n + 1) / 2 + 1 + rmax + 2 * 256 * std::max(1, (n + 63) / 64);
+            const int base = (2 * n + 1) / 2 + 1 + rmax + 2 * 256 * std::max(1, (n + 63) / 64) + rhif::kCpqrRegExtra;
             // M in doubles of LDS (FP32 values take half)
             const int msz = f32 ? (rmax * (n | 1) + 1) / 2 : rmax * (n | 1);
             const int full = kPotrfSmemFixed + 17 * n;        // potrf scratch with the whole panel
@@ -1134,14 +1165,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                                           f->kout, f->pout, fcap, n, lvl, f->err));
             } else
             KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
-                   hipLaunchKernelGGL(f32 ? (staged == 4   ? k_skeletonize<4, float>
-                                             : staged == 3 ? k_skeletonize<3, float>
-                                             : staged == 1 ? k_skeletonize<1, float>
-                                                           : k_skeletonize<0, float>)
-                                          : (staged == 4   ? k_skeletonize<4, double>
-                                             : staged == 3 ? k_skeletonize<3, double>
-                                             : staged == 1 ? k_skeletonize<1, double>
-                                                           : k_skeletonize<0, double>),
+                   hipLaunchKernelGGL(skel_kernel(staged, skel_rows_per_thread(P.skel_desc), f32),
                                       dim3(nsk), dim3(256), lds, s, LD.skd, LD.cgptr, LD.cgl, LD.cgoff, LD.cref, LD.front,
                                       f->mp, LD.tp, LD.gp, LD.skli, f->o.eps, f->kout, f->pout, cap, n, rmax, lvl,
                                       f->err));
