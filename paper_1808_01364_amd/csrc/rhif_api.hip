@@ -72,6 +72,10 @@ struct HostCache {
     size_t down_bytes = 0;
     rhif::PlanScratch scr;
     std::vector<rhif::LevelPlan*> plans;
+    // plans[0] depends on the grid and the leaf size alone (every unknown is active at the
+    // leaf level): it is kept for the next factorization of the same geometry
+    bool plan0_ok = false;
+    int plan0_key[3] = {0, 0, 0};
 
     char* get_up(size_t b, int& slot) {
         slot = next;
@@ -809,9 +813,15 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         auto t0 = now();
         // the largest per-unknown table is built by the device: at level 0 the cells' frontal
         // unknowns (closed form; the host fills the groups' lists while the first kernels
-        // run), above it the extend-add sources
-        build_cells(g, lvl, leaf, root, n_active, prevP, scr, kApplyCap, P, true);
-        validate_cells(P, prevP, d);
+        // run), above it the extend-add sources. The level-0 plan of the last factorization
+        // of the same grid and leaf size is reused as it is.
+        const bool reuse_plan = lvl == 0 && hc.plan0_ok && hc.plan0_key[0] == d && hc.plan0_key[1] == g.s &&
+                                hc.plan0_key[2] == leaf;
+        if (lvl == 0 && !reuse_plan) hc.plan0_ok = false;
+        if (!reuse_plan) {
+            build_cells(g, lvl, leaf, root, n_active, prevP, scr, kApplyCap, P, true);
+            validate_cells(P, prevP, d);
+        }
         if (P.max_nf > 16 * kPotrfMaxTiles) fail(RHIF_ENOMEM, "a frontal matrix is too large for this version");
         f->stats.n_active[lvl] = n_active;
         f->stats.n_cells[lvl] = P.ncells;
@@ -987,8 +997,16 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
 
         // ---- plan and upload the separator half (overlaps the elimination) ----
         t0 = now();
-        build_separators(g, scr, kApplyCap, P);
-        validate_separators(P);
+        if (!reuse_plan) {
+            build_separators(g, scr, kApplyCap, P);
+            validate_separators(P);
+        }
+        if (lvl == 0) {
+            hc.plan0_ok = true;
+            hc.plan0_key[0] = d;
+            hc.plan0_key[1] = g.s;
+            hc.plan0_key[2] = leaf;
+        }
         f->stats.flops[lvl] += P.flops;
         {
             Packer pk;
