@@ -51,7 +51,9 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
 }
 
 // Cholesky factorization and inversion of a 16 x 16 SPD block held by one wave in registers:
-// lane i < 16 holds row i in a[0..i]. On return a[c] = L[i][c] (c <= i) and li[r] =
+// lane i < 16 holds row i in a[0..i]. On return a[c] = L[i][c] (c <= i; the entries above
+// the diagonal are left undefined: the rank-1 updates run unmasked, since the rows above a
+// pivot only change entries above their diagonal, which are never read) and li[r] =
 // (L^-1)[r][lane] for lane < 16. A pivot <= 0 or NaN reports `code` and continues with 1.
 __device__ __forceinline__ void wave_chol_inv16(double (&a)[16], double (&li)[16], int lane,
                                                 unsigned long long* err, unsigned long long code) {
@@ -66,12 +68,9 @@ __device__ __forceinline__ void wave_chol_inv16(double (&a)[16], double (&li)[16
         const double lcc = sqrt(dcc);
         rinv[c] = 1.0 / lcc;
         const double lic = a[c] * rinv[c];
-        a[c] = (lane == c) ? lcc : (lane > c ? lic : a[c]);
+        a[c] = (lane == c) ? lcc : lic;
 #pragma unroll
-        for (int q = c + 1; q < 16; ++q) {
-            const double lqc = readlane_d(a[c], q);
-            if (lane >= q) a[q] -= a[c] * lqc;
-        }
+        for (int q = c + 1; q < 16; ++q) a[q] -= a[c] * readlane_d(a[c], q);
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
