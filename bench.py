@@ -150,16 +150,16 @@ def extras(rhif, torch, P, csr, f):
     seq = [batch.solve_one(it) for it in items64]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ns, order = batch.autotune(items32)
+    ns, order, group = batch.autotune(items32)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    bat = batch.solve_many(items32, ns, order)
+    bat = batch.solve_many(items32, ns, order, group=group)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     out["batch"] = {"problems": len(probs), "dofs": dofs,
                     "fp64_one_by_one_dofs_per_s": dofs / (t1 - t0),
                     "fp32_mixed_autotuned_batch_dofs_per_s": dofs / (t3 - t2),
-                    "speedup": (t1 - t0) / (t3 - t2), "autotuned": {"streams": ns, "order": order},
+                    "speedup": (t1 - t0) / (t3 - t2), "autotuned": {"streams": ns, "order": order, "problems_per_factor_call": group},
                     "max_iters": {"fp64": max(r[1] for r in seq), "fp32_batch": max(r[1] for r in bat)},
                     "worst_relres_fp32_batch": max(r[2] for r in bat)}
     del items64, items32, seq, bat

@@ -175,6 +175,28 @@ rhif_status rhif_factor(const rhif_grid *g, const rhif_opts *o, const int32_t *r
                         const int32_t *col, const double *val, hipStream_t s,
                         rhif_factor_t *out);
 
+/* Factor `count` independent problems with the same options in one call (the batched form;
+ * the cells and groups of different problems are as independent as those of one problem,
+ * Sec. 2.1, and their IDs are simultaneous like those of one level, Sec. 2.2). The problems
+ * advance level by level together: every elimination, block-Jacobi and skeletonization
+ * kernel of a level is ONE launch over the blocks of all problems (only the frontal
+ * assembly is launched per problem), and one read-back per level brings the ranks of every
+ * problem to the host. Each problem is factored exactly as rhif_factor factors it alone
+ * (same choices, same arithmetic order: the results are bitwise those of rhif_factor).
+ *  grids   [host] count grids, all with the same dim (the sides may differ)
+ *  o       [host] options shared by all problems; flags must not ask for kernel or phase
+ *          times when count > 1 (EINVAL)
+ *  row_ptr, col, val [host] arrays of count device pointers: problem i's CSR as for
+ *          rhif_factor (copied; the caller may free them after the call returns)
+ *  out     [host] count handles, used and destroyed like those of rhif_factor and from any
+ *          thread; the device memory of the handles of one call is one pool, returned to the
+ *          library when the last of them is destroyed. On any error every out[i] is NULL.
+ * Synchronizes the stream once per level. Errors: as rhif_factor (an ENOTSPD message numbers
+ * blocks over the whole batch). */
+rhif_status rhif_factor_batch(int32_t count, const rhif_grid *grids, const rhif_opts *o,
+                              const int32_t *const *row_ptr, const int32_t *const *col,
+                              const double *const *val, hipStream_t s, rhif_factor_t *out);
+
 /* z = F^-1 r for nrhs right-hand sides stored one after another (column-major N x nrhs):
  * the up-sweep R_l^T = K_l^T C_l^T E_l^T for l = 0..L-1, the root solve, and the
  * down-sweep R_l = E_l C_l K_l for l = L-1..0 (eq. (3.2)).

@@ -1,15 +1,19 @@
 """Many independent problems solved concurrently on one GPU (the batched form of the solver).
 
-Each worker thread owns a HIP stream and takes problems from a shared queue: assembly,
-factorization, PCG and release of the factor, all stream-ordered on its own stream. A
-factorization waits for its ranks once per level; while one problem's host plans its next
-level, the kernels of the others keep the GPU busy, and the small upper levels of several
-problems run side by side. Results do not depend on the interleaving (every kernel's
-arithmetic order is fixed), so a batch reproduces the one-by-one solutions bit for bit.
+Worker threads, each with its own HIP stream, take work from a shared queue. A unit of work
+is a group of problems factored in one call (rhif_factor_batch: the group advances level by
+level together, every elimination, block-Jacobi and skeletonization kernel of a level is one
+launch over the blocks of all the group's problems, and one read-back per level brings all
+their ranks), followed by each problem's PCG solve and the release of the factors, all
+stream-ordered on the worker's stream. Groups of one problem are plain rhif_factor calls.
+While one worker's host plans its group's next level, the kernels of the others keep the GPU
+busy. Results do not depend on the interleaving (every kernel's arithmetic order is fixed),
+so a batch reproduces the one-by-one solutions; grouping changes at most the storage form a
+kernel takes for a level (the factors agree with the lone ones to rounding).
 
-The batch shape (how many streams, and whether the queue takes the largest problems first)
-is picked by a small autotuner that times the candidates on a sample of the batch and
-remembers the choice for batches of the same size mix.
+The batch shape (group size, number of streams, and whether the queue takes the largest
+problems first) is picked by a small autotuner that times the candidates on a sample of the
+batch and remembers the choice for batches of the same size mix.
 """
 from __future__ import annotations
 
@@ -45,6 +49,24 @@ def solve_one(item: BatchItem, rtol: float = 1e-12, maxit: int = 500, stream=Non
     return u, it, rr
 
 
+def solve_group(items, rtol: float = 1e-12, maxit: int = 500, stream=None):
+    """[(u, iterations, relative residual)] of problems with the same dim, leaf, eps and
+    precision, factored in one rhif_factor_batch call on `stream` (the current stream if None);
+    the factors are released before returning."""
+    it0 = items[0]
+    csrs = [rhif.assemble_fd(it.dim, it.n, it.a_cells, it.b, stream=stream) for it in items]
+    Fs = rhif.factor_batch([(it.dim, it.n, c) for it, c in zip(items, csrs)], it0.leaf, it0.eps, 1,
+                           it0.precision, stream=stream)
+    out = []
+    try:
+        for it, F in zip(items, Fs):
+            out.append(F.pcg(it.f, rtol, maxit, stream=stream))
+    finally:
+        for F in Fs:
+            F.close()
+    return out
+
+
 def _order(items, order: str):
     idx = list(range(len(items)))
     if order == "largest_first":
@@ -52,10 +74,24 @@ def _order(items, order: str):
     return idx
 
 
-def _run(items, nstreams: int, order: str, rtol: float, maxit: int):
+def _groups(items, order: str, group: int):
+    """The queue: consecutive problems (in the given order) with the same dim, leaf, eps and
+    precision, in groups of at most `group`."""
+    out = []
+    for i in _order(items, order):
+        it = items[i]
+        key = (it.dim, it.leaf, it.eps, it.precision)
+        if out and len(out[-1][1]) < group and out[-1][0] == key:
+            out[-1][1].append(i)
+        else:
+            out.append((key, [i]))
+    return [g for _, g in out]
+
+
+def _run(items, nstreams: int, order: str, rtol: float, maxit: int, group: int = 1):
     import torch
     out = [None] * len(items)
-    queue = _order(items, order)
+    queue = _groups(items, order, max(1, group))
     nxt = [0]
     lock = threading.Lock()
 
@@ -68,8 +104,12 @@ def _run(items, nstreams: int, order: str, rtol: float, maxit: int):
                     nxt[0] += 1
                 if q >= len(queue):
                     break
-                i = queue[q]
-                out[i] = solve_one(items[i], rtol, maxit)
+                idx = queue[q]
+                if len(idx) == 1:
+                    out[idx[0]] = solve_one(items[idx[0]], rtol, maxit)
+                else:
+                    for i, r in zip(idx, solve_group([items[i] for i in idx], rtol, maxit)):
+                        out[i] = r
         st.synchronize()
 
     nw = max(1, min(nstreams, len(items)))
@@ -79,10 +119,11 @@ def _run(items, nstreams: int, order: str, rtol: float, maxit: int):
     return out
 
 
-# batch signature -> (nstreams, order) chosen by autotune
+# batch signature -> (nstreams, order, group) chosen by autotune
 _TUNED = {}
 STREAM_CANDIDATES = (1, 2, 4, 8)
 ORDER_CANDIDATES = ("given", "largest_first")
+GROUP_CANDIDATES = (4, 8, 16)
 
 
 def _signature(items):
@@ -94,10 +135,11 @@ def _signature(items):
     return tuple(sorted((k, (v + 3) // 4) for k, v in mix.items()))
 
 
-def autotune(items, sample: int = 12, rtol: float = 1e-12, maxit: int = 500, verbose: bool = False):
-    """Pick (nstreams, order) for this batch: each candidate solves the same sample of the batch
-    (every len/sample-th problem), after one warm-up pass; the highest DOFs/s wins. The
-    choice is remembered for batches with the same size mix."""
+def autotune(items, sample: int = 16, rtol: float = 1e-12, maxit: int = 500, verbose: bool = False):
+    """Pick (nstreams, order, group) for this batch. Every candidate solves the same sample of the
+    batch (every len/sample-th problem) after one warm-up pass, and the highest DOFs/s wins: first
+    (nstreams, order) with one problem per factorization call, then (group, nstreams) with
+    that order. The choice is remembered for batches with the same size mix."""
     import torch
     key = _signature(items)
     if key in _TUNED:
@@ -105,29 +147,44 @@ def autotune(items, sample: int = 12, rtol: float = 1e-12, maxit: int = 500, ver
     step = max(1, len(items) // max(1, sample))
     samp = items[::step][:sample]
     dofs = sum(it.n ** it.dim for it in samp)
-    _run(samp, 4, "given", rtol, maxit)      # warm-up: kernel loading, device memory cache
-    best, best_rate = (4, "given"), -1.0
+    _run(samp, 4, "given", rtol, maxit)              # warm-up: kernel loading, device memory cache
+    _run(samp, 2, "given", rtol, maxit, group=max(GROUP_CANDIDATES))
+
+    def rate(ns, order, group):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _run(samp, ns, order, rtol, maxit, group)
+        torch.cuda.synchronize()
+        r = dofs / (time.perf_counter() - t0)
+        if verbose:
+            print(f"autotune: {ns} streams, {order}, groups of {group}: {r / 1e6:.1f} M DOFs/s", flush=True)
+        return r
+
+    best, best_rate = (4, "given", 1), -1.0
     for ns in STREAM_CANDIDATES:
         for order in ORDER_CANDIDATES:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _run(samp, ns, order, rtol, maxit)
-            torch.cuda.synchronize()
-            rate = dofs / (time.perf_counter() - t0)
-            if verbose:
-                print(f"autotune: {ns} streams, {order}: {rate / 1e6:.1f} M DOFs/s", flush=True)
-            if rate > best_rate:
-                best, best_rate = (ns, order), rate
+            r = rate(ns, order, 1)
+            if r > best_rate:
+                best, best_rate = (ns, order, 1), r
+    order = best[1]
+    for group in GROUP_CANDIDATES:
+        for ns in (2, 4, 8):
+            r = rate(ns, order, group)
+            if r > best_rate:
+                best, best_rate = (ns, order, group), r
     _TUNED[key] = best
     return best
 
 
-def solve_many(items, nstreams: int = None, order: str = None, rtol: float = 1e-12, maxit: int = 500):
+def solve_many(items, nstreams: int = None, order: str = None, rtol: float = 1e-12, maxit: int = 500,
+               group: int = None):
     """Solve every item; returns [(u, iterations, relative residual)] in the items' order.
     nstreams worker threads, one default-priority HIP stream each; order "given" or
-    "largest_first". Either left None is taken from autotune()."""
-    if nstreams is None or order is None:
-        ns, od = autotune(items, rtol=rtol, maxit=maxit)
+    "largest_first"; group: problems factored per rhif_factor_batch call. Any left None is
+    taken from autotune()."""
+    if nstreams is None or order is None or group is None:
+        ns, od, gr = autotune(items, rtol=rtol, maxit=maxit)
         nstreams = ns if nstreams is None else nstreams
         order = od if order is None else order
-    return _run(items, nstreams, order, rtol, maxit)
+        group = gr if group is None else group
+    return _run(items, nstreams, order, rtol, maxit, group)

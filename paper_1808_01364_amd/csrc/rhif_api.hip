@@ -3,16 +3,22 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
-#include <array>
 #include <cstring>
+#include <exception>
+#include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/rhif.h"
@@ -54,14 +60,49 @@ constexpr int64_t kBigSkelElems = 1 << 18;    // M (rows x columns) from which t
                                               // many workgroups per group
 constexpr int kBigCheck = 16;                 // steps between the host's checks for active groups
 
+// Planner state of one problem of a factorization call: scratch, level plans and the
+// host tables of the skeleton apply. Slot p of a call reuses slot p's allocations; the
+// level-0 plan depends on the grid and the leaf size alone (every unknown is active at the
+// leaf level) and is kept for the next factorization of the same geometry in the slot.
+struct PlanSet {
+    rhif::PlanScratch scr;
+    std::vector<rhif::LevelPlan*> plans;
+    bool plan0_ok = false;
+    int plan0_key[3] = {0, 0, 0};
+    std::vector<rhif::ApplyDesc> sk_ad;
+    std::vector<int32_t> sk_dofs;
+    std::vector<rhif::GroupApplyDesc> gad;
+    std::vector<int32_t> skel_of;
+    rhif::LevelPlan& plan(int lvl) {
+        while (static_cast<int>(plans.size()) <= lvl) plans.push_back(new rhif::LevelPlan());
+        return *plans[lvl];
+    }
+};
+
+// The descriptor tables of one level concatenated over the problems of a factorization
+// call, every offset moved to the problem's share of the level-wide arrays.
+struct MergedTables {
+    std::vector<rhif::CellRef> cref;
+    std::vector<rhif::FrontDesc> pot[2];   // cell eliminations below the root, at the root
+    std::vector<rhif::SepDesc> sep;
+    std::vector<rhif::CellGroup> cg;
+    std::vector<rhif::CellScaleDesc> cs;
+    std::vector<rhif::SkelDesc> skd;
+    std::vector<int32_t> cgptr, cgl, cgoff;
+};
+
 // Per-thread host state reused across factorizations: pinned staging buffers for the
 // uploads (a ring, each slot fenced by the event of its last copy), a pinned buffer for
-// the small read-backs, and the planner's scratch and level plans (so that repeated
+// the small read-backs, the planner states and the merged tables (so that repeated
 // factorizations do not pay for fresh allocations and page faults). Kept for the life of
 // the process.
 struct HostCache {
-    std::vector<rhif::GroupApplyDesc> gad;
-    std::vector<int32_t> skel_of;
+    std::vector<PlanSet*> sets;
+    MergedTables mt;
+    PlanSet& set(int p) {
+        while (static_cast<int>(sets.size()) <= p) sets.push_back(new PlanSet());
+        return *sets[p];
+    }
     static constexpr int kSlots = 3;
     char* up[kSlots] = {};
     size_t up_bytes[kSlots] = {};
@@ -70,12 +111,6 @@ struct HostCache {
     int next = 0;
     char* down = nullptr;
     size_t down_bytes = 0;
-    rhif::PlanScratch scr;
-    std::vector<rhif::LevelPlan*> plans;
-    // plans[0] depends on the grid and the leaf size alone (every unknown is active at the
-    // leaf level): it is kept for the next factorization of the same geometry
-    bool plan0_ok = false;
-    int plan0_key[3] = {0, 0, 0};
 
     char* get_up(size_t b, int& slot) {
         slot = next;
@@ -129,15 +164,87 @@ struct HostCache {
         }
         return down;
     }
-    rhif::LevelPlan& plan(int lvl) {
-        while (static_cast<int>(plans.size()) <= lvl) plans.push_back(new rhif::LevelPlan());
-        return *plans[lvl];
-    }
 };
 HostCache& host_cache() {
     thread_local HostCache* c = new HostCache();
     return *c;
 }
+
+// Host threads for the per-problem planning of a factorization call with several problems
+// (the planner's work on different problems is independent). The threads live for the
+// life of the process and wait between calls; the caller's thread takes part.
+class HostPool {
+public:
+    static HostPool& get() {
+        static HostPool* p = new HostPool();
+        return *p;
+    }
+    // fn(i) for every i in [0, n); returns when all calls have returned, rethrowing the
+    // first exception any of them threw. One call at a time (others wait).
+    void run(int n, const std::function<void(int)>& fn) {
+        if (n <= 1 || nthreads_ == 0) {
+            for (int i = 0; i < n; ++i) fn(i);
+            return;
+        }
+        std::lock_guard<std::mutex> one(run_mu_);
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            fn_ = &fn;
+            n_ = n;
+            next_.store(0);
+            pending_ = nthreads_;
+            err_ = nullptr;
+            ++gen_;
+        }
+        cv_.notify_all();
+        work();
+        std::unique_lock<std::mutex> lk(mu_);
+        done_cv_.wait(lk, [&] { return pending_ == 0; });
+        fn_ = nullptr;
+        if (err_) std::rethrow_exception(err_);
+    }
+
+private:
+    HostPool() {
+        const unsigned hw = std::thread::hardware_concurrency();
+        nthreads_ = static_cast<int>(std::min(15u, hw > 1 ? hw - 1 : 0u));
+        for (int t = 0; t < nthreads_; ++t) std::thread([this] { loop(); }).detach();
+    }
+    void work() {
+        for (;;) {
+            const int i = next_.fetch_add(1);
+            if (i >= n_) break;
+            try {
+                (*fn_)(i);
+            } catch (...) {
+                std::lock_guard<std::mutex> lk(mu_);
+                if (!err_) err_ = std::current_exception();
+            }
+        }
+    }
+    void loop() {
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return gen_ != seen; });
+                seen = gen_;
+            }
+            work();
+            std::lock_guard<std::mutex> lk(mu_);
+            if (--pending_ == 0) done_cv_.notify_one();
+        }
+    }
+    int nthreads_ = 0;
+    std::mutex run_mu_, mu_;
+    std::condition_variable cv_, done_cv_;
+    const std::function<void(int)>* fn_ = nullptr;
+    int n_ = 0;
+    std::atomic<int> next_{0};
+    int pending_ = 0;
+    uint64_t gen_ = 0;
+    std::exception_ptr err_;
+};
 
 // Packs host arrays into one upload; every sub-array is 256-byte aligned.
 struct Packer {
@@ -170,7 +277,6 @@ struct LevelDev {
     // device views into the uploaded tables
     int32_t* cdofs = nullptr;
     rhif::CellRef* cref = nullptr;
-    rhif::FrontDesc* potrf = nullptr;
     rhif::Tile* tiles = nullptr;
     int32_t* src = nullptr;
     int32_t* cg2 = nullptr;       // per frontal unknown: its group and position at the level below
@@ -178,13 +284,6 @@ struct LevelDev {
     int32_t* gslot_cnt = nullptr; // per group: the cells containing it and its frontal offsets there
     int32_t* gslot_cell = nullptr;
     int32_t* gslot_off = nullptr;
-    rhif::SepDesc* sep = nullptr;
-    rhif::CellGroup* cg = nullptr;
-    rhif::CellScaleDesc* cs = nullptr;
-    rhif::SkelDesc* skd = nullptr;
-    int32_t* cgptr = nullptr;   // boundary groups of every cell: list, entries, frontal offsets
-    int32_t* cgl = nullptr;
-    int32_t* cgoff = nullptr;
     rhif::ApplyDesc* cell_ad = nullptr;
     rhif::ApplyDesc* sep_ad = nullptr;
     rhif::GatherDesc* gat = nullptr;
@@ -329,6 +428,43 @@ private:
 constexpr int kGroupStageMax = 8192;   // doubles of T and G blocks a group apply stages in LDS
 constexpr int kKbufHead = 4;   // ints before the ID outputs: the 64-bit error word, padded
 
+// Device memory of the handles made by one factorization call (one handle, or every handle
+// of a batch): bump-allocated from chunks of the per-device cache, and given back to the
+// cache when the last of those handles is destroyed (each has waited for its own work).
+struct Arena {
+    struct Chunk {
+        void* p;
+        size_t bytes;
+    };
+    static constexpr size_t kChunkBytes = size_t(64) << 20;
+    int device = 0;
+    std::mutex mu;
+    std::vector<Chunk> chunks;
+    char* cur = nullptr;
+    size_t left = 0;
+
+    void* dalloc(size_t bytes) {
+        std::lock_guard<std::mutex> lk(mu);
+        const size_t b = (std::max<size_t>(bytes, 256) + 255) / 256 * 256;
+        if (b > left) {
+            size_t got = 0;
+            void* p = ChunkCache::of_device(device).take(std::max(b, kChunkBytes), got);
+            if (!p) fail(RHIF_ENOMEM, "device allocation failed");
+            chunks.push_back({p, got});
+            cur = static_cast<char*>(p);
+            left = got;
+        }
+        void* ptr = cur;
+        cur += b;
+        left -= b;
+        return ptr;
+    }
+    ~Arena() {
+        ChunkCache& cc = ChunkCache::of_device(device);
+        for (const Chunk& c : chunks) cc.give(c.p, c.bytes);
+    }
+};
+
 struct rhif_factor_s {
     rhif::GridInfo g;
     rhif_opts o{};
@@ -339,17 +475,10 @@ struct rhif_factor_s {
     int32_t* ci = nullptr;
     double* val = nullptr;
     std::vector<LevelDev> lev;
-    unsigned long long* err = nullptr;
-    double* mp = nullptr;     // ID scratch (largest level)
-    int64_t mp_elems = 0;
     double* ybuf = nullptr;
     int64_t y_elems = 0;
     double* ws = nullptr;
     int64_t ws_elems = 0;
-    int32_t* kbuf = nullptr;  // error word (kKbufHead ints), then the level's ID outputs
-    int32_t* kout = nullptr;  // per-level ID outputs (inside kbuf)
-    int32_t* pout = nullptr;
-    int64_t kp_elems = 0;
     // PCG workspace
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *part = nullptr, *sc = nullptr;
     double* hsc = nullptr;                 // pinned host scalars of the PCG (read back by the graphs)
@@ -363,11 +492,7 @@ struct rhif_factor_s {
     bool graphs_off = false;
 
     rhif_stats_t stats{};
-    struct Chunk {
-        void* p;
-        size_t bytes;
-    };
-    std::vector<Chunk> chunks;   // device memory of the handle (from ChunkCache)
+    std::shared_ptr<Arena> arena;   // device memory (shared with the other handles of a batch)
     // the last work of the handle on every stream it was used on (its memory may be reused
     // once these have completed)
     std::vector<std::pair<hipStream_t, hipEvent_t>> done_ev;
@@ -381,8 +506,6 @@ struct rhif_factor_s {
         }
         HIPCHK(hipEventRecord(e, st));
     }
-    char* chunk_cur = nullptr;
-    size_t chunk_left = 0;
     int device = 0;
     // per-launch device timing (RHIF_FLAG_KERNEL_TIMES)
     bool ktimes = false;
@@ -432,24 +555,9 @@ struct rhif_factor_s {
         pend.clear();
     }
 
-    static constexpr size_t kChunkBytes = size_t(64) << 20;
-    void* dalloc(size_t bytes) {
-        const size_t b = (std::max<size_t>(bytes, 256) + 255) / 256 * 256;
-        if (b > chunk_left) {
-            size_t got = 0;
-            void* p = ChunkCache::of_device(device).take(std::max(b, kChunkBytes), got);
-            if (!p) fail(RHIF_ENOMEM, "device allocation failed");
-            chunks.push_back({p, got});
-            chunk_cur = static_cast<char*>(p);
-            chunk_left = got;
-        }
-        void* ptr = chunk_cur;
-        chunk_cur += b;
-        chunk_left -= b;
-        return ptr;
-    }
+    void* dalloc(size_t bytes) { return arena->dalloc(bytes); }
     void release() {
-        // the chunks go back to the cache only once no work of this handle can still use them
+        // the memory goes back to the cache only once no work of this handle can still use it
         for (auto& p : done_ev) {
             (void)hipEventSynchronize(p.second);
             (void)hipEventDestroy(p.second);
@@ -480,11 +588,7 @@ struct rhif_factor_s {
         pend.clear();
         for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
         evpool.clear();
-        ChunkCache& cc = ChunkCache::of_device(device);
-        for (const Chunk& c : chunks) cc.give(c.p, c.bytes);
-        chunks.clear();
-        chunk_cur = nullptr;
-        chunk_left = 0;
+        arena.reset();
     }
 };
 
@@ -536,34 +640,36 @@ std::string step_name(int st) {
     }
 }
 
-// Turns the device error word (~0: no error) into an error return.
-void raise_err(rhif_factor_s* f, unsigned long long h) {
+// Turns the device error word (~0: no error) into an error return. batch: the call
+// factors several problems (their blocks are numbered over all of them).
+void raise_err(unsigned long long h, bool batch) {
     if (h != ~0ull) {
         const int ilevel = static_cast<int>(h >> 40);
         const int step = static_cast<int>((h >> 32) & 0xff);
         const int block = static_cast<int>(h & 0xffffffffu);
-        char buf[256];
+        const char* in = batch ? " (one of the batch's problems; blocks numbered over the batch)" : "";
+        char buf[320];
         if (step == 6) {
             std::snprintf(buf, sizeof(buf), "internal error: extend-add sources of cell %d at level %d disagree "
-                          "with the plan", block, ilevel);
+                          "with the plan%s", block, ilevel, in);
             fail(RHIF_EDEVICE, buf);
         }
         if (step == 7) {
             std::snprintf(buf, sizeof(buf), "internal error: skeleton row table of group %d at level %d disagrees "
-                          "with the plan", block, ilevel);
+                          "with the plan%s", block, ilevel, in);
             fail(RHIF_EDEVICE, buf);
         }
-        std::snprintf(buf, sizeof(buf), "not SPD: Cholesky pivot <= 0 or not finite at level %d, step %s, block %d",
-                      step == 3 ? f->Lskel : ilevel, step_name(step).c_str(), block);
+        std::snprintf(buf, sizeof(buf), "not SPD: Cholesky pivot <= 0 or not finite at level %d, step %s, block %d%s",
+                      ilevel, step_name(step).c_str(), block, in);
         fail(RHIF_ENOTSPD, buf);
     }
 }
 
-void check_err(rhif_factor_s* f, hipStream_t s) {
+void check_err(const unsigned long long* err, bool batch, hipStream_t s) {
     unsigned long long h = 0;
-    HIPCHK(hipMemcpyAsync(&h, f->err, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&h, err, sizeof(h), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    raise_err(f, h);
+    raise_err(h, batch);
 }
 
 template <class T>
@@ -684,241 +790,376 @@ void set_kernel_attributes() {
     });
 }
 
-void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, const double* val, hipStream_t s) {
+// Caller's CSR of one problem of a factorization call.
+struct CsrIn {
+    const int32_t* rp;
+    const int32_t* ci;
+    const double* val;
+};
+
+// One problem of a factorization call while the level loop runs.
+struct Prob {
+    rhif_factor_s* f = nullptr;
+    PlanSet* ps = nullptr;
+    int64_t n_active = 0;      // unknowns active at the current level
+    bool reuse0 = false;       // the level-0 plan of the slot's last factorization is reused
+    int pending_skel = -1;     // level whose skeleton apply tables are still to be uploaded
+    double sk_fl = 0.0;        // their skeletonization flops
+    // the problem's share of the level-wide arrays (element or entry offsets)
+    int64_t o_front = 0, o_ext = 0, o_lg = 0, o_li = 0, o_t = 0, o_g = 0, o_skli = 0, o_m = 0;
+    int32_t o_cell = 0, o_cs = 0, o_cg = 0, o_k = 0, o_p = 0;
+};
+
+// The level loop of the factorization (Sec. 3.1 / 3.2) for one or several independent
+// problems with the same options (cells and groups of different problems are as
+// independent as those of one problem: Sec. 2.1, and the simultaneous skeletonization of
+// Sec. 2.2). The problems advance level by level together. Their plans are made on the host
+// pool; every kernel of a level that works from descriptor tables (cell elimination, block
+// Jacobi, skeletonization) runs as one launch over the blocks of all problems, whose tables
+// are concatenated with every offset moved to the problem's share of level-wide arrays. Only
+// the frontal assembly, which reads each problem's own matrix and plan, is launched per
+// problem. One read-back per level brings every problem's ranks to the host. With one
+// problem the shares are the whole arrays and the launches are those of a lone factorization.
+void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream_t s) {
     using namespace rhif;
-    const GridInfo& g = f->g;
-    const int d = g.d;
+    const int B = static_cast<int>(fs.size());
+    const bool batch = B > 1;
+    rhif_factor_s* f0 = fs[0];
+    const rhif_opts& o = f0->o;
+    const int d = f0->g.d;
     const int W = 1 << d;
-    const int leaf = f->o.leaf;
+    const int leaf = o.leaf;
     // precision 1: the interpolative decompositions in FP32; precision 2: also the Schur
     // products of the cell eliminations (level 0 and the upper levels' final
     // S = A_BB - W^T W) on the FP32 matrix cores. Cholesky factors, block Jacobi and every
     // stored factor value stay FP64.
-    const bool f32 = f->o.precision >= 1;
-    const bool f32schur = f->o.precision == 2;
-    f->nnz = fd_nnz(d, g.s);
-    // the error word leads the block of the ID outputs, so that one copy reads back both
-    f->kbuf = static_cast<int32_t*>(f->dalloc(kKbufHead * sizeof(int32_t)));
-    f->err = reinterpret_cast<unsigned long long*>(f->kbuf);
-    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, f->err, ~0ull);
-    // the handle keeps its own copy of A
-    f->rp = static_cast<int32_t*>(f->dalloc((g.N + 1) * sizeof(int32_t)));
-    f->ci = static_cast<int32_t*>(f->dalloc(f->nnz * sizeof(int32_t)));
-    f->val = static_cast<double*>(f->dalloc(f->nnz * sizeof(double)));
-    HIPCHK(hipMemcpyAsync(f->rp, row_ptr, (g.N + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(f->ci, col, f->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(f->val, val, f->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
-
+    const bool f32 = o.precision >= 1;
+    const bool f32schur = o.precision == 2;
     HostCache& hc = host_cache();
-    PlanScratch& scr = hc.scr;
-    scr.reserve(g.N);
-    int64_t n_active = g.N;   // unknowns active at the current level
-    f->lev.resize(f->L + 1);
-    const bool timing = (f->o.flags & RHIF_FLAG_PHASE_TIMES) != 0;
+    MergedTables& mt = hc.mt;
+    HostPool& pool = HostPool::get();
+
+    // the error word leads the block of the ID outputs, so that one copy reads back both
+    int32_t* kbuf = static_cast<int32_t*>(f0->dalloc(kKbufHead * sizeof(int32_t)));
+    unsigned long long* err = reinterpret_cast<unsigned long long*>(kbuf);
+    int64_t kp_elems = 0;
+    double* mp = nullptr;   // ID scratch (the largest level)
+    int64_t mp_elems = 0;
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, err, ~0ull);
+
+    std::vector<Prob> pr(B);
+    int Lmax = 0;
+    for (int p = 0; p < B; ++p) {
+        rhif_factor_s* f = fs[p];
+        Prob& q = pr[p];
+        q.f = f;
+        q.ps = &hc.set(p);
+        q.n_active = f->g.N;
+        Lmax = std::max(Lmax, f->L);
+        f->lev.resize(f->L + 1);
+        // every handle keeps its own copy of A
+        f->nnz = fd_nnz(d, f->g.s);
+        f->rp = static_cast<int32_t*>(f->dalloc((f->g.N + 1) * sizeof(int32_t)));
+        f->ci = static_cast<int32_t*>(f->dalloc(f->nnz * sizeof(int32_t)));
+        f->val = static_cast<double*>(f->dalloc(f->nnz * sizeof(double)));
+        HIPCHK(hipMemcpyAsync(f->rp, in[p].rp, (f->g.N + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(f->ci, in[p].ci, f->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(f->val, in[p].val, f->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    pool.run(B, [&](int p) { pr[p].ps->scr.reserve(fs[p]->g.N); });
+
+    const bool timing = (o.flags & RHIF_FLAG_PHASE_TIMES) != 0;
     auto now = [] { return std::chrono::steady_clock::now(); };
     auto phase = [&](int idx, std::chrono::steady_clock::time_point t0) {
         if (!timing) return;
         HIPCHK(hipStreamSynchronize(s));
-        f->stats.t_phase_ms[idx] += std::chrono::duration<double, std::milli>(now() - t0).count();
+        const double ms = std::chrono::duration<double, std::milli>(now() - t0).count();
+        for (rhif_factor_s* f : fs) f->stats.t_phase_ms[idx] += ms;
     };
 
-    // The skeleton apply tables of level lv (ranks and pivots known): descriptors, the fused
-    // per-group apply table and their upload. Nothing of the next level depends on them, so
-    // they are built while the next level's first kernels run.
-    int pending_skel = -1;
-    auto finish_skel_tables = [&](int lv) {
+    // The skeleton apply tables of a problem's level lv (ranks and pivots known): descriptors
+    // and the fused per-group apply table, on the host. Nothing of the next level depends on
+    // them, so they are built while the next level's first kernels run.
+    auto skel_tables_host = [&](Prob& q) {
+        const int lv = q.pending_skel;
+        rhif_factor_s* f = q.f;
+        PlanSet& ps = *q.ps;
         LevelDev& LD = f->lev[lv];
-        const LevelPlan& P = hc.plan(lv);
+        const LevelPlan& P = ps.plan(lv);
         const int nsk = static_cast<int>(LD.k.size());
-        std::vector<ApplyDesc> sk_ad;
-        std::vector<int32_t> sk_dofs;
         double fl = 0.0, sby = 0.0;
-        skel_apply_tables(P, LD.k.data(), LD.perm.data(), kApplyCap, sk_ad, sk_dofs, f->ws_elems, fl, sby);
-        validate_skel_apply(P, sk_ad, sk_dofs, g.N);
+        skel_apply_tables(P, LD.k.data(), LD.perm.data(), kApplyCap, ps.sk_ad, ps.sk_dofs, f->ws_elems, fl, sby);
+        validate_skel_apply(P, ps.sk_ad, ps.sk_dofs, f->g.N);
         LD.b_skel = sby;
         f->stats.flops[lv] += fl;
-        if (f->ktimes && nsk > 0) {
-            for (auto it = f->pend.rbegin(); it != f->pend.rend(); ++it)
+        q.sk_fl = fl;
+        // per separator group: gather, block Jacobi and skeleton elimination in one launch
+        std::vector<GroupApplyDesc>& gad = ps.gad;
+        gad.assign(P.sep_desc.size(), GroupApplyDesc{});
+        LD.mn_grp = 0;
+        LD.tk_cap = 0;
+        std::vector<int32_t>& skel_of = ps.skel_of;
+        skel_of.assign(P.gptr.size(), -1);
+        for (int e = 0; e < nsk; ++e) skel_of[P.skels[e]] = e;
+        for (size_t e = 0; e < P.sep_desc.size(); ++e) {
+            const SepDesc& sd = P.sep_desc[e];
+            const GatherDesc& gt = P.gather[e];
+            GroupApplyDesc& x = gad[e];
+            x.n = sd.n;
+            x.dofs = sd.dofs;
+            x.nslot = gt.nslot;
+            for (int sl = 0; sl < gt.nslot; ++sl) x.yoff[sl] = gt.yoff[sl];
+            x.precond = LD.precond ? 1 : 0;
+            x.loff = sd.loff;
+            x.li = sd.lioff;
+            const int se = skel_of[P.seps[e]];
+            if (se >= 0) {
+                const SkelDesc& sk = P.skel_desc[se];
+                const int kk = LD.k[sk.gid];
+                if (kk < sk.n) {
+                    x.nr = sk.n - kk;
+                    x.k = kk;
+                    x.poff = sk.poff;
+                    x.goff = sk.goff;
+                    x.toff = sk.toff;
+                    x.skli = sk.lioff;
+                }
+            }
+            LD.mn_grp = std::max(LD.mn_grp, sd.n);
+            LD.tk_cap = std::max(LD.tk_cap, x.k * x.nr);
+        }
+        LD.n_grp = static_cast<int>(gad.size());
+        // T and G's off-diagonal block of a group go through LDS when the largest fit
+        if (2 * LD.tk_cap > kGroupStageMax) LD.tk_cap = 0;
+        LD.n_skel_ad = static_cast<int>(ps.sk_ad.size());
+        LD.lds_skel = apply_lds(ps.sk_ad);
+        apply_max(ps.sk_ad, LD.mi_skel, LD.mb_skel);
+    };
+    // ... and their upload, one copy for all problems with tables pending
+    auto skel_tables_upload = [&](const std::vector<int>& which) {
+        if (which.empty()) return;
+        Packer pk;
+        std::vector<std::array<size_t, 4>> off(which.size());
+        double fl = 0.0;
+        for (size_t i = 0; i < which.size(); ++i) {
+            Prob& q = pr[which[i]];
+            PlanSet& ps = *q.ps;
+            off[i] = {pk.add(ps.sk_ad), pk.add(ps.sk_dofs), pk.add(ps.gad), pk.add(q.f->lev[q.pending_skel].perm)};
+            fl += q.sk_fl;
+        }
+        char* T = upload_side(f0, pk, s);
+        for (size_t i = 0; i < which.size(); ++i) {
+            Prob& q = pr[which[i]];
+            LevelDev& LD = q.f->lev[q.pending_skel];
+            if (T) {
+                LD.skel_ad = view<ApplyDesc>(T, off[i][0]);
+                LD.skeldofs = view<int32_t>(T, off[i][1]);
+                LD.grp_ad = view<GroupApplyDesc>(T, off[i][2]);
+                LD.permd = view<int32_t>(T, off[i][3]);
+            }
+            q.pending_skel = -1;
+        }
+        // the level's skeletonization launch gets its algorithmic flops now that they are known
+        if (f0->ktimes) {
+            for (auto it = f0->pend.rbegin(); it != f0->pend.rend(); ++it)
                 if (it->cls == RHIF_K_SKELETONIZE) {
                     it->fl = fl;
                     break;
                 }
         }
-        // per separator group: gather, block Jacobi and skeleton elimination in one launch
-        std::vector<GroupApplyDesc>& gad = hc.gad;
-        gad.assign(P.sep_desc.size(), GroupApplyDesc{});
-        LD.mn_grp = 0;
-        LD.tk_cap = 0;
-        {
-            std::vector<int32_t>& skel_of = hc.skel_of;
-            skel_of.assign(P.gptr.size(), -1);
-            for (int e = 0; e < nsk; ++e) skel_of[P.skels[e]] = e;
-            for (size_t e = 0; e < P.sep_desc.size(); ++e) {
-                const SepDesc& sd = P.sep_desc[e];
-                const GatherDesc& gt = P.gather[e];
-                GroupApplyDesc& x = gad[e];
-                x.n = sd.n;
-                x.dofs = sd.dofs;
-                x.nslot = gt.nslot;
-                for (int sl = 0; sl < gt.nslot; ++sl) x.yoff[sl] = gt.yoff[sl];
-                x.precond = LD.precond ? 1 : 0;
-                x.loff = sd.loff;
-                x.li = sd.lioff;
-                const int se = skel_of[P.seps[e]];
-                if (se >= 0) {
-                    const SkelDesc& sk = P.skel_desc[se];
-                    const int kk = LD.k[sk.gid];
-                    if (kk < sk.n) {
-                        x.nr = sk.n - kk;
-                        x.k = kk;
-                        x.poff = sk.poff;
-                        x.goff = sk.goff;
-                        x.toff = sk.toff;
-                        x.skli = sk.lioff;
-                    }
-                }
-                LD.mn_grp = std::max(LD.mn_grp, sd.n);
-                LD.tk_cap = std::max(LD.tk_cap, x.k * x.nr);
-            }
-        }
-        {
-            Packer pk;
-            const size_t o_ad = pk.add(sk_ad), o_dofs = pk.add(sk_dofs), o_gad = pk.add(gad), o_perm = pk.add(LD.perm);
-            char* T = upload_side(f, pk, s);
-            if (T) {
-                LD.skel_ad = view<ApplyDesc>(T, o_ad);
-                LD.skeldofs = view<int32_t>(T, o_dofs);
-                LD.grp_ad = view<GroupApplyDesc>(T, o_gad);
-                LD.permd = view<int32_t>(T, o_perm);
-            }
-        }
-        LD.n_grp = static_cast<int>(gad.size());
-        // T and G's off-diagonal block of a group go through LDS when the largest fit
-        if (2 * LD.tk_cap > kGroupStageMax) LD.tk_cap = 0;
-        LD.n_skel_ad = static_cast<int>(sk_ad.size());
-        LD.lds_skel = apply_lds(sk_ad);
-        apply_max(sk_ad, LD.mi_skel, LD.mb_skel);
     };
 
-    for (int lvl = 0; lvl <= f->L; ++lvl) {
-        const bool root = (lvl == f->L);
-        LevelDev& LD = f->lev[lvl];
-        LD.root = root;
-        LD.precond = f->o.precond != 0;
-        LevelPlan& P = hc.plan(lvl);
-        const LevelPlan* prevP = lvl > 0 ? &hc.plan(lvl - 1) : nullptr;
-        const LevelDev* prev = lvl > 0 ? &f->lev[lvl - 1] : nullptr;
+    std::vector<int> act, nonroot, pend;
+    for (int lvl = 0; lvl <= Lmax; ++lvl) {
+        act.clear();
+        for (int p = 0; p < B; ++p)
+            if (lvl <= fs[p]->L) act.push_back(p);
+        const int na = static_cast<int>(act.size());
 
-        // ---- plan and upload the cell half ----
+        // ---- plan the cell half of every problem ----
         auto t0 = now();
         // the largest per-unknown table is built by the device: at level 0 the cells' frontal
         // unknowns (closed form; the host fills the groups' lists while the first kernels
-        // run), above it the extend-add sources. The level-0 plan of the last factorization
-        // of the same grid and leaf size is reused as it is.
-        const bool reuse_plan = lvl == 0 && hc.plan0_ok && hc.plan0_key[0] == d && hc.plan0_key[1] == g.s &&
-                                hc.plan0_key[2] == leaf;
-        if (lvl == 0 && !reuse_plan) hc.plan0_ok = false;
-        if (!reuse_plan) {
-            build_cells(g, lvl, leaf, root, n_active, prevP, scr, kApplyCap, P, true);
-            validate_cells(P, prevP, d);
+        // run), above it the extend-add sources
+        pool.run(na, [&](int i) {
+            Prob& q = pr[act[i]];
+            rhif_factor_s* f = q.f;
+            PlanSet& ps = *q.ps;
+            LevelPlan& P = ps.plan(lvl);
+            const LevelPlan* prevP = lvl > 0 ? &ps.plan(lvl - 1) : nullptr;
+            q.reuse0 = lvl == 0 && ps.plan0_ok && ps.plan0_key[0] == d && ps.plan0_key[1] == f->g.s &&
+                       ps.plan0_key[2] == leaf;
+            if (lvl == 0 && !q.reuse0) ps.plan0_ok = false;
+            if (!q.reuse0) {
+                build_cells(f->g, lvl, leaf, lvl == f->L, q.n_active, prevP, ps.scr, kApplyCap, P, true);
+                validate_cells(P, prevP, d);
+            }
+            if (P.max_nf > 16 * kPotrfMaxTiles) fail(RHIF_ENOMEM, "a frontal matrix is too large for this version");
+        });
+
+        // ---- the problems' shares of the level-wide arrays; merged cell tables ----
+        int64_t n_front = 0, n_ext = 0;
+        int32_t n_cell = 0;
+        mt.cref.clear();
+        mt.pot[0].clear();
+        mt.pot[1].clear();
+        double alg_elim[2] = {0.0, 0.0};
+        for (int p : act) {
+            Prob& q = pr[p];
+            rhif_factor_s* f = q.f;
+            const LevelPlan& P = q.ps->plan(lvl);
+            LevelDev& LD = f->lev[lvl];
+            const int kind = lvl == f->L ? 1 : 0;
+            LD.root = kind == 1;
+            LD.precond = o.precond != 0;
+            f->stats.n_active[lvl] = q.n_active;
+            f->stats.n_cells[lvl] = P.ncells;
+            f->stats.max_front[lvl] = P.max_nf;
+            q.o_front = n_front;
+            q.o_ext = n_ext;
+            q.o_cell = n_cell;
+            for (CellRef c : P.cell_ref) {
+                c.off += q.o_front;
+                mt.cref.push_back(c);
+            }
+            for (FrontDesc fd : P.cell_potrf) {
+                fd.off += q.o_front;
+                if (fd.ext >= 0) fd.ext += static_cast<int32_t>(q.o_ext);
+                mt.pot[kind].push_back(fd);
+            }
+            alg_elim[kind] += P.alg_elim_flops;
+            n_front += P.front_elems;
+            n_ext += P.ext_elems;
+            n_cell += P.ncells;
         }
-        if (P.max_nf > 16 * kPotrfMaxTiles) fail(RHIF_ENOMEM, "a frontal matrix is too large for this version");
-        f->stats.n_active[lvl] = n_active;
-        f->stats.n_cells[lvl] = P.ncells;
-        f->stats.max_front[lvl] = P.max_nf;
+        if (n_ext >= (int64_t(1) << 31)) fail(RHIF_ENOMEM, "too many cells in one level of the call");
+        double* front = static_cast<double*>(f0->dalloc(std::max<int64_t>(n_front, 1) * sizeof(double)));
+        int32_t* ext = static_cast<int32_t*>(f0->dalloc(std::max<int64_t>(n_ext, 1) * sizeof(int32_t)));
+        // ---- upload: every problem's cell tables and the merged ones, one copy ----
+        const rhif::CellRef* cref_all = nullptr;
+        const rhif::FrontDesc* pot_dev[2] = {nullptr, nullptr};
         {
             Packer pk;
-            const size_t o_cdofs = pk.add(P.c_dofs), o_cref = pk.add(P.cell_ref), o_potrf = pk.add(P.cell_potrf),
-                         o_tiles = pk.add(P.tiles), o_src = pk.add(P.src), o_cad = pk.add(P.cell_apply),
-                         o_g2 = pk.add(P.c_g2), o_t2 = pk.add(P.c_t2);
-            char* T = upload(f, pk, s);
-            LD.cg2 = view<int32_t>(T, o_g2);
-            LD.ct2 = view<int32_t>(T, o_t2);
-            LD.cdofs = P.dofs_on_device
-                           ? static_cast<int32_t*>(f->dalloc(std::max<int64_t>(P.c_dptr[P.ncells], 1) * sizeof(int32_t)))
-                           : view<int32_t>(T, o_cdofs);
-            LD.cref = view<CellRef>(T, o_cref);
-            LD.potrf = view<FrontDesc>(T, o_potrf);
-            LD.tiles = view<Tile>(T, o_tiles);
-            LD.src = P.src_on_device ? static_cast<int32_t*>(f->dalloc(
-                                           std::max<int64_t>(P.c_dptr[P.ncells], 1) * 2 * W * sizeof(int32_t)))
-                                     : view<int32_t>(T, o_src);
-            LD.cell_ad = view<ApplyDesc>(T, o_cad);
+            std::vector<std::array<size_t, 7>> off(na);
+            for (int i = 0; i < na; ++i) {
+                const LevelPlan& P = pr[act[i]].ps->plan(lvl);
+                off[i] = {pk.add(P.c_dofs), pk.add(P.cell_ref), pk.add(P.tiles), pk.add(P.src),
+                          pk.add(P.cell_apply), pk.add(P.c_g2), pk.add(P.c_t2)};
+            }
+            const size_t o_cref = pk.add(mt.cref), o_pot0 = pk.add(mt.pot[0]), o_pot1 = pk.add(mt.pot[1]);
+            char* T = upload(f0, pk, s);
+            cref_all = view<CellRef>(T, o_cref);
+            pot_dev[0] = view<FrontDesc>(T, o_pot0);
+            pot_dev[1] = view<FrontDesc>(T, o_pot1);
+            for (int i = 0; i < na; ++i) {
+                Prob& q = pr[act[i]];
+                rhif_factor_s* f = q.f;
+                const LevelPlan& P = q.ps->plan(lvl);
+                LevelDev& LD = f->lev[lvl];
+                LD.cg2 = view<int32_t>(T, off[i][5]);
+                LD.ct2 = view<int32_t>(T, off[i][6]);
+                LD.cdofs = P.dofs_on_device ? static_cast<int32_t*>(f0->dalloc(
+                                                  std::max<int64_t>(P.c_dptr[P.ncells], 1) * sizeof(int32_t)))
+                                            : view<int32_t>(T, off[i][0]);
+                LD.cref = view<CellRef>(T, off[i][1]);
+                LD.tiles = view<Tile>(T, off[i][2]);
+                LD.src = P.src_on_device ? static_cast<int32_t*>(f0->dalloc(
+                                               std::max<int64_t>(P.c_dptr[P.ncells], 1) * 2 * W * sizeof(int32_t)))
+                                         : view<int32_t>(T, off[i][3]);
+                LD.cell_ad = view<ApplyDesc>(T, off[i][4]);
+                LD.n_cell_ad = static_cast<int>(P.cell_apply.size());
+                LD.lds_cell = apply_lds(P.cell_apply);
+                apply_max(P.cell_apply, LD.mi_cell, LD.mb_cell);
+                LD.b_cell = P.alg_apply_cell_bytes;
+                LD.front = front + q.o_front;
+                LD.ext = ext + q.o_ext;
+                LD.bytes = P.front_elems * 8 + P.ext_elems * 4;
+                f->y_elems = std::max(f->y_elems, P.y_elems);
+                f->ws_elems = std::max(f->ws_elems, P.ws_elems);
+            }
         }
-        LD.n_cell_ad = static_cast<int>(P.cell_apply.size());
-        LD.lds_cell = apply_lds(P.cell_apply);
-        apply_max(P.cell_apply, LD.mi_cell, LD.mb_cell);
-        LD.b_cell = P.alg_apply_cell_bytes;
-        LD.front = static_cast<double*>(f->dalloc(P.front_elems * sizeof(double)));
-        LD.ext = static_cast<int32_t*>(f->dalloc(std::max<int64_t>(P.ext_elems, 1) * sizeof(int32_t)));
-        LD.bytes = P.front_elems * 8 + P.ext_elems * 4;
-        f->y_elems = std::max(f->y_elems, P.y_elems);
-        f->ws_elems = std::max(f->ws_elems, P.ws_elems);
         phase(5, t0);
 
-        // ---- frontal assembly ----
+        // ---- frontal assembly, per problem ----
         t0 = now();
-        if (P.dofs_on_device && P.ncells > 0)
-            KTIMED(f, s, RHIF_K_FRONT_CSR, 0.0, 4.0 * P.c_dptr[P.ncells],
-                   hipLaunchKernelGGL(k_leaf_dofs, dim3(P.ncells), dim3(256), 0, s, LD.cref, d, g.s, P.w, P.nc1,
-                                      LD.cdofs));
-        if (!P.tiles.empty()) {
+        for (int p : act) {
+            rhif_factor_s* f = pr[p].f;
+            const GridInfo& g = f->g;
+            const LevelPlan& P = pr[p].ps->plan(lvl);
+            const LevelPlan* prevP = lvl > 0 ? &pr[p].ps->plan(lvl - 1) : nullptr;
+            LevelDev& LD = f->lev[lvl];
+            const LevelDev* prev = lvl > 0 ? &f->lev[lvl - 1] : nullptr;
+            if (P.dofs_on_device && P.ncells > 0)
+                KTIMED(f0, s, RHIF_K_FRONT_CSR, 0.0, 4.0 * P.c_dptr[P.ncells],
+                       hipLaunchKernelGGL(k_leaf_dofs, dim3(P.ncells), dim3(256), 0, s, LD.cref, d, g.s, P.w, P.nc1,
+                                          LD.cdofs));
+            if (P.tiles.empty()) continue;
             if (lvl == 0) {
                 const double by = P.alg_front_bytes + 12.0 * f->nnz + 4.0 * (g.N + 1);
-                KTIMED(f, s, RHIF_K_FRONT_CSR, 0.0, by,
+                KTIMED(f0, s, RHIF_K_FRONT_CSR, 0.0, by,
                        hipLaunchKernelGGL(k_front_csr, dim3(P.tiles.size()), dim3(256), 0, s, LD.tiles, LD.cref,
                                           LD.cdofs, d, g.s, P.w, P.nc1, f->rp, f->ci, f->val, LD.front));
             } else {
                 if (P.src_on_device)
-                    KTIMED(f, s, RHIF_K_FRONT_EXTEND, 0.0, 4.0 * (2.0 + 2.0 * W) * P.c_dptr[P.ncells],
+                    KTIMED(f0, s, RHIF_K_FRONT_EXTEND, 0.0, 4.0 * (2.0 + 2.0 * W) * P.c_dptr[P.ncells],
                            hipLaunchKernelGGL(k_extend_src, dim3(P.ncells), dim3(256), 0, s, LD.cref, LD.cg2, LD.ct2,
                                               static_cast<int>(prevP->gptr.size()) - 1, prev->gslot_cnt,
                                               prev->gslot_cell, prev->gslot_off, prev->cref, prevP->ncells, d,
-                                              prevP->nc1, P.nc1, W, lvl, LD.src, f->err));
+                                              prevP->nc1, P.nc1, W, lvl, LD.src, err));
                 double rd = 0.0;
                 for (int c = 0; c < prevP->ncells; ++c)
                     rd += 8.0 * static_cast<double>(prevP->c_nB[c]) * prevP->c_nB[c];
-                KTIMED(f, s, RHIF_K_FRONT_EXTEND, 0.0, P.alg_front_bytes + rd,
+                KTIMED(f0, s, RHIF_K_FRONT_EXTEND, 0.0, P.alg_front_bytes + rd,
                        hipLaunchKernelGGL(k_front_extend, dim3(P.tiles.size()), dim3(256), 0, s, LD.tiles, LD.cref,
                                           LD.src, W, prev->cref, prev->front, LD.front));
             }
         }
         phase(0, t0);
 
-        // ---- cell elimination (E_l; at the root: B_L = chol(A_L)) ----
-        t0 = now();
-        if (!P.cell_potrf.empty()) {
+        // ---- cell elimination (E_l; at a problem's root: B_L = chol(A_L)), one launch
+        //      sequence for the cells below the root and one for the roots ----
+        double* linv = nullptr;
+        if (!mt.pot[0].empty() || !mt.pot[1].empty()) {
+            linv = static_cast<double*>(f0->dalloc(std::max<int64_t>(n_ext, 1) * 256 * sizeof(double)));
+            for (int p : act) pr[p].f->lev[lvl].linv = linv + 256 * pr[p].o_ext;
+        }
+        for (int kind = 0; kind < 2; ++kind) {
+            const std::vector<FrontDesc>& pot = mt.pot[kind];
+            if (pot.empty()) continue;
+            t0 = now();
+            const bool root = kind == 1;
+            const FrontDesc* potd = pot_dev[kind];
             int nmax = 0, pmax = 0, mmax = 0;
-            for (const auto& fd : P.cell_potrf) {
+            for (const auto& fd : pot) {
                 nmax = std::max(nmax, fd.n - std::min(fd.n, 1));
                 pmax = std::max(pmax, fd.p);
                 mmax = std::max(mmax, fd.n - fd.p);
             }
             const int cls = root ? RHIF_K_ROOT : (lvl == 0 ? RHIF_K_ELIM_LEAF : RHIF_K_ELIM_UPPER);
-            const unsigned ncell = static_cast<unsigned>(P.cell_potrf.size());
-            LD.linv = static_cast<double*>(f->dalloc(std::max<int64_t>(P.ext_elems, 1) * 256 * sizeof(double)));
-            double* linv = LD.linv;
+            const unsigned ncell = static_cast<unsigned>(pot.size());
+            const int w = leaf << lvl;
             // the frontal tiles of such cells skip what the banded elimination never reads
-            if (leaf_interior_banded(d, lvl, root, P.w)) {
+            if (leaf_interior_banded(d, lvl, root, w)) {
                 // leaf interiors: block-bidiagonal Cholesky factors
-                LD.leaf_banded = true;
+                for (int p : act)
+                    if ((lvl == pr[p].f->L) == root) pr[p].f->lev[lvl].leaf_banded = true;
                 const int nt = (mmax + 15) / 16;
                 const int tpw = (nt + 3) / 4;
                 const size_t lds0 =
                     static_cast<size_t>((10 + 4 * std::max(tpw, 1) + 2 * (2 + nt)) * 16 * 17) * sizeof(double);
-                KTIMED(f, s, cls, P.alg_elim_flops, 0.0,
-                       hipLaunchKernelGGL(f32schur ? k_leaf_elim<true> : k_leaf_elim<false>, dim3(ncell), dim3(256), lds0, s, LD.potrf, LD.front, linv,
-                                          std::max(tpw, 1), lvl, f->err, LD.ext));
+                KTIMED(f0, s, cls, alg_elim[kind], 0.0,
+                       hipLaunchKernelGGL(f32schur ? k_leaf_elim<true> : k_leaf_elim<false>, dim3(ncell), dim3(256),
+                                          lds0, s, potd, front, linv, std::max(tpw, 1), lvl, err, ext));
             } else if (pmax > kCholLdsPmax) {
                 // large interiors (3D upper levels, roots): panel by panel, each panel's
                 // Cholesky, row solves and trailing update as three launches over all cells
                 const int nq = (pmax + kElimPanel - 1) / kElimPanel;
                 std::vector<rhif::FrontDesc> pd;
                 std::vector<int32_t> pd_off(nq + 1, 0), pd_mrow(nq, 0);
-                std::vector<int32_t> ext_all(std::max<int64_t>(P.ext_elems, 1), 0);
+                std::vector<int32_t> ext_all(std::max<int64_t>(n_ext, 1), 0);
                 for (int q = 0; q < nq; ++q) {
                     const int j0 = q * kElimPanel;
-                    for (const auto& fd : P.cell_potrf) {
+                    for (const auto& fd : pot) {
                         if (fd.p <= j0) continue;
                         rhif::FrontDesc e = fd;
                         e.off = fd.off + j0 + static_cast<int64_t>(j0) * fd.ld;
@@ -931,13 +1172,20 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                     pd_off[q + 1] = static_cast<int32_t>(pd.size());
                 }
                 // the apply's row extents of L: every panel column block runs to the interior's end
-                for (const auto& fd : P.cell_potrf)
+                for (const auto& fd : pot)
                     for (int t = 0; t < (fd.p + 15) / 16; ++t) ext_all[fd.ext + t] = fd.p;
                 Packer pk;
-                const size_t o_pd = pk.add(pd), o_ext = pk.add(ext_all);
-                char* T = upload(f, pk, s);
-                HIPCHK(hipMemcpyAsync(LD.ext, T + o_ext, ext_all.size() * sizeof(int32_t), hipMemcpyDeviceToDevice,
-                                      s));
+                const size_t o_pd = pk.add(pd), o_ea = pk.add(ext_all);
+                char* T = upload(f0, pk, s);
+                // only the shares of this sequence's problems (the other sequence's kernels
+                // write their own)
+                for (int p : act) {
+                    const Prob& q = pr[p];
+                    const int64_t ne = q.ps->plan(lvl).ext_elems;
+                    if ((lvl == q.f->L) != root || ne == 0) continue;
+                    HIPCHK(hipMemcpyAsync(ext + q.o_ext, T + o_ea + q.o_ext * sizeof(int32_t),
+                                          ne * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+                }
                 const rhif::FrontDesc* pdd = view<rhif::FrontDesc>(T, o_pd);
                 const size_t lds1 =
                     static_cast<size_t>(rhif::kPotrfSmemFixed + (kElimPanel | 1) * kElimPanel) * sizeof(double);
@@ -945,152 +1193,267 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                 for (int q = 0; q < nq; ++q) {
                     const unsigned nc = static_cast<unsigned>(pd_off[q + 1] - pd_off[q]);
                     const rhif::FrontDesc* dq = pdd + pd_off[q];
-                    KTIMED(f, s, cls, q == 0 ? P.alg_elim_flops : 0.0, 0.0,
-                           hipLaunchKernelGGL(k_chol_lead, dim3(nc), dim3(256), lds1, s, dq, LD.front, linv,
-                                              kElimPanel, lvl, root ? 3 : 0, f->err, nullptr));
+                    KTIMED(f0, s, cls, q == 0 ? alg_elim[kind] : 0.0, 0.0,
+                           hipLaunchKernelGGL(k_chol_lead, dim3(nc), dim3(256), lds1, s, dq, front, linv, kElimPanel,
+                                              lvl, root ? 3 : 0, err, nullptr));
                     const int mr = pd_mrow[q];
                     if (mr > 0) {
-                        KTIMED(f, s, cls, 0.0, 0.0,
+                        KTIMED(f0, s, cls, 0.0, 0.0,
                                hipLaunchKernelGGL(k_trsm_rows, dim3(nc, (mr + 63) / 64), dim3(256),
-                                                  static_cast<size_t>(4 * pstride) * sizeof(double), s, dq, LD.front,
+                                                  static_cast<size_t>(4 * pstride) * sizeof(double), s, dq, front,
                                                   linv, pstride));
                         const int nb = (mr + 31) / 32;
-                        KTIMED(f, s, cls, 0.0, 0.0,
+                        KTIMED(f0, s, cls, 0.0, 0.0,
                                hipLaunchKernelGGL(k_syrk_schur<false>, dim3(nc, nb * (nb + 1) / 2), dim3(256), 0, s,
-                                                  dq, LD.front));
+                                                  dq, front));
                     }
                 }
             } else if (!root && lvl > 0) {
-                // few cells: Cholesky, row solves and Schur update as three wide launches
+                // small interiors: Cholesky, row solves and Schur update as three wide launches
                 const size_t lds1 = static_cast<size_t>(rhif::kPotrfSmemFixed + (pmax | 1) * pmax) * sizeof(double);
-                KTIMED(f, s, cls, P.alg_elim_flops, 0.0,
-                       hipLaunchKernelGGL(k_chol_lead, dim3(ncell), dim3(256), lds1, s, LD.potrf, LD.front, linv,
-                                          kCholLdsPmax, lvl, 0, f->err, LD.ext));
+                KTIMED(f0, s, cls, alg_elim[kind], 0.0,
+                       hipLaunchKernelGGL(k_chol_lead, dim3(ncell), dim3(256), lds1, s, potd, front, linv,
+                                          kCholLdsPmax, lvl, 0, err, ext));
                 if (mmax > 0) {
                     const int pstride = 17 * ((pmax + 15) / 16) * 16;
-                    KTIMED(f, s, cls, 0.0, 0.0,
+                    KTIMED(f0, s, cls, 0.0, 0.0,
                            hipLaunchKernelGGL(k_trsm_rows, dim3(ncell, (mmax + 63) / 64), dim3(256),
-                                              static_cast<size_t>(4 * pstride) * sizeof(double), s, LD.potrf, LD.front,
-                                              linv, pstride));
+                                              static_cast<size_t>(4 * pstride) * sizeof(double), s, potd, front, linv,
+                                              pstride));
                     const int nb = (mmax + 31) / 32;
-                    KTIMED(f, s, cls, 0.0, 0.0,
+                    KTIMED(f0, s, cls, 0.0, 0.0,
                            hipLaunchKernelGGL(f32schur ? k_syrk_schur<true> : k_syrk_schur<false>,
-                                              dim3(ncell, nb * (nb + 1) / 2), dim3(256), 0, s, LD.potrf, LD.front));
+                                              dim3(ncell, nb * (nb + 1) / 2), dim3(256), 0, s, potd, front));
                 }
             } else {
                 const int cap = panel_cap_for(nmax, 0);
-                KTIMED(f, s, cls, P.alg_elim_flops, 0.0,
-                       hipLaunchKernelGGL(k_potrf_batch, dim3(ncell), dim3(256), potrf_lds(cap, 0), s, LD.potrf,
-                                          LD.front, cap, lvl, root ? 3 : 0, f->err, LD.ext, linv));
+                KTIMED(f0, s, cls, alg_elim[kind], 0.0,
+                       hipLaunchKernelGGL(k_potrf_batch, dim3(ncell), dim3(256), potrf_lds(cap, 0), s, potd, front,
+                                          cap, lvl, root ? 3 : 0, err, ext, linv));
             }
-        }
-        phase(root ? 6 : 1, t0);
-        if (P.lists_pending) fill_leaf_lists(g, scr, P);
-        if (pending_skel >= 0) {
-            finish_skel_tables(pending_skel);
-            pending_skel = -1;
-        }
-        if (root) {
-            f->stats.flops[lvl] += P.flops;
-            break;
+            phase(root ? 6 : 1, t0);
         }
 
-        // ---- plan and upload the separator half (overlaps the elimination) ----
+        // ---- host, overlapping the elimination: the leaf groups' lists, the skeleton apply
+        //      tables of the level below, and the separator half of this level's plans ----
         t0 = now();
-        if (!reuse_plan) {
-            build_separators(g, scr, kApplyCap, P);
-            validate_separators(P);
+        nonroot.clear();
+        pend.clear();
+        for (int p : act) {
+            if (lvl < pr[p].f->L) nonroot.push_back(p);
+            if (pr[p].pending_skel >= 0) pend.push_back(p);
         }
-        if (lvl == 0) {
-            hc.plan0_ok = true;
-            hc.plan0_key[0] = d;
-            hc.plan0_key[1] = g.s;
-            hc.plan0_key[2] = leaf;
+        pool.run(na, [&](int i) {
+            Prob& q = pr[act[i]];
+            rhif_factor_s* f = q.f;
+            PlanSet& ps = *q.ps;
+            LevelPlan& P = ps.plan(lvl);
+            if (P.lists_pending) fill_leaf_lists(f->g, ps.scr, P);
+            if (q.pending_skel >= 0) skel_tables_host(q);
+            if (lvl == f->L) return;
+            if (!q.reuse0) {
+                build_separators(f->g, ps.scr, kApplyCap, P);
+                validate_separators(P);
+            }
+            if (lvl == 0) {
+                ps.plan0_ok = true;
+                ps.plan0_key[0] = d;
+                ps.plan0_key[1] = f->g.s;
+                ps.plan0_key[2] = leaf;
+            }
+        });
+        skel_tables_upload(pend);
+        for (int p : act)
+            if (lvl == pr[p].f->L) pr[p].f->stats.flops[lvl] += pr[p].ps->plan(lvl).flops;
+        if (nonroot.empty()) continue;
+
+        // ---- the separator half: shares, merged tables, one upload ----
+        int64_t n_lg = 0, n_t = 0, n_g = 0, n_li = 0, n_skli = 0, n_m = 0;
+        int32_t n_cs = 0, n_cg = 0, n_k = 0, n_p = 0;
+        int max_sep_n = 0, max_cell_groups = 0, max_skel_n = 0;
+        double alg_pchol = 0.0, alg_pscale = 0.0;
+        mt.sep.clear();
+        mt.cg.clear();
+        mt.cs.clear();
+        mt.skd.clear();
+        mt.cgl.clear();
+        mt.cgoff.clear();
+        mt.cgptr.clear();
+        for (int p : act) {
+            Prob& q = pr[p];
+            const LevelPlan& P = q.ps->plan(lvl);
+            const int32_t o_cgl = static_cast<int32_t>(mt.cgl.size());
+            if (lvl == q.f->L) {
+                // a root among the merged cells: no boundary groups
+                for (int c = 0; c < P.ncells; ++c) mt.cgptr.push_back(o_cgl);
+                continue;
+            }
+            q.f->stats.flops[lvl] += P.flops;
+            q.o_lg = n_lg;
+            q.o_t = n_t;
+            q.o_g = n_g;
+            q.o_li = n_li;
+            q.o_skli = n_skli;
+            q.o_m = n_m;
+            q.o_cs = n_cs;
+            q.o_cg = n_cg;
+            q.o_k = n_k;
+            q.o_p = n_p;
+            for (SepDesc sd : P.sep_desc) {
+                for (int sl = 0; sl < sd.nslot; ++sl) sd.slot_cell[sl] += q.o_cell;
+                sd.loff += q.o_lg;
+                sd.lioff += static_cast<int32_t>(q.o_li);
+                mt.sep.push_back(sd);
+            }
+            for (CellGroup cg : P.cell_groups) {
+                cg.loff += q.o_lg;
+                cg.lioff += static_cast<int32_t>(q.o_li);
+                cg.cell += q.o_cs;
+                mt.cg.push_back(cg);
+            }
+            for (CellScaleDesc cs : P.cell_scale) {
+                cs.off += q.o_front;
+                cs.g_begin += q.o_cg;
+                mt.cs.push_back(cs);
+            }
+            for (SkelDesc sk : P.skel_desc) {
+                for (int sl = 0; sl < sk.nslot; ++sl) sk.cell[sl] += q.o_cell;
+                sk.moff += q.o_m;
+                sk.toff += q.o_t;
+                sk.goff += q.o_g;
+                sk.gid += q.o_k;
+                sk.poff += q.o_p;
+                sk.lioff += static_cast<int32_t>(q.o_skli);
+                mt.skd.push_back(sk);
+            }
+            for (int c = 0; c < P.ncells; ++c) mt.cgptr.push_back(P.c_gptr[c] + o_cgl);
+            mt.cgl.insert(mt.cgl.end(), P.c_g.begin(), P.c_g.end());
+            mt.cgoff.insert(mt.cgoff.end(), P.c_goff.begin(), P.c_goff.end());
+            n_lg += P.lg_elems;
+            n_t += P.t_elems;
+            n_g += P.g_elems;
+            n_li += P.li_elems;
+            n_skli += P.skli_elems;
+            n_m += P.m_elems;
+            n_cs += static_cast<int32_t>(P.cell_scale.size());
+            n_cg += static_cast<int32_t>(P.cell_groups.size());
+            n_k += static_cast<int32_t>(P.skel_desc.size());
+            n_p += P.skel_ntotal;
+            max_sep_n = std::max(max_sep_n, P.max_sep_n);
+            max_cell_groups = std::max(max_cell_groups, P.max_cell_groups);
+            max_skel_n = std::max(max_skel_n, P.max_skel_n);
+            alg_pchol += P.alg_prec_chol_flops;
+            alg_pscale += P.alg_prec_scale_flops;
         }
-        f->stats.flops[lvl] += P.flops;
+        mt.cgptr.push_back(static_cast<int32_t>(mt.cgl.size()));
+        if (n_li >= (int64_t(1) << 31) || n_skli >= (int64_t(1) << 31))
+            fail(RHIF_ENOMEM, "too many groups in one level of the call");
+        const rhif::SepDesc* sep_all = nullptr;
+        const rhif::CellGroup* cg_all = nullptr;
+        const rhif::CellScaleDesc* cs_all = nullptr;
+        const rhif::SkelDesc* skd_all = nullptr;
+        const int32_t *cgptr_all = nullptr, *cgl_all = nullptr, *cgoff_all = nullptr;
         {
             Packer pk;
-            const size_t o_sep = pk.add(P.sep_desc), o_cg = pk.add(P.cell_groups), o_cs = pk.add(P.cell_scale),
-                         o_skd = pk.add(P.skel_desc), o_cgp = pk.add(P.c_gptr), o_cgl = pk.add(P.c_g),
-                         o_cgo = pk.add(P.c_goff), o_sad = pk.add(P.sep_apply),
-                         o_gat = pk.add(P.gather), o_sdofs = pk.add(P.sep_dofs),
-                         o_gsc = pk.add(P.gslot_cnt), o_gsl = pk.add(P.gslot_cell), o_gso = pk.add(P.gslot_off);
-            char* T = upload_side(f, pk, s);
-            LD.gslot_cnt = view<int32_t>(T, o_gsc);
-            LD.gslot_cell = view<int32_t>(T, o_gsl);
-            LD.gslot_off = view<int32_t>(T, o_gso);
-            LD.sep = view<SepDesc>(T, o_sep);
-            LD.cg = view<CellGroup>(T, o_cg);
-            LD.cs = view<CellScaleDesc>(T, o_cs);
-            LD.skd = view<SkelDesc>(T, o_skd);
-            LD.cgptr = view<int32_t>(T, o_cgp);
-            LD.cgl = view<int32_t>(T, o_cgl);
-            LD.cgoff = view<int32_t>(T, o_cgo);
-            LD.sep_ad = view<ApplyDesc>(T, o_sad);
-            LD.gat = view<GatherDesc>(T, o_gat);
-            LD.sepdofs = view<int32_t>(T, o_sdofs);
+            const int nn = static_cast<int>(nonroot.size());
+            std::vector<std::array<size_t, 6>> off(nn);
+            for (int i = 0; i < nn; ++i) {
+                const LevelPlan& P = pr[nonroot[i]].ps->plan(lvl);
+                off[i] = {pk.add(P.sep_apply), pk.add(P.gather), pk.add(P.sep_dofs),
+                          pk.add(P.gslot_cnt), pk.add(P.gslot_cell), pk.add(P.gslot_off)};
+            }
+            const size_t o_sep = pk.add(mt.sep), o_cg = pk.add(mt.cg), o_cs = pk.add(mt.cs), o_skd = pk.add(mt.skd),
+                         o_cgp = pk.add(mt.cgptr), o_cgl = pk.add(mt.cgl), o_cgo = pk.add(mt.cgoff);
+            char* T = upload_side(f0, pk, s);
+            sep_all = view<SepDesc>(T, o_sep);
+            cg_all = view<CellGroup>(T, o_cg);
+            cs_all = view<CellScaleDesc>(T, o_cs);
+            skd_all = view<SkelDesc>(T, o_skd);
+            cgptr_all = view<int32_t>(T, o_cgp);
+            cgl_all = view<int32_t>(T, o_cgl);
+            cgoff_all = view<int32_t>(T, o_cgo);
+            for (int i = 0; i < nn; ++i) {
+                rhif_factor_s* f = pr[nonroot[i]].f;
+                const LevelPlan& P = pr[nonroot[i]].ps->plan(lvl);
+                LevelDev& LD = f->lev[lvl];
+                LD.sep_ad = view<ApplyDesc>(T, off[i][0]);
+                LD.gat = view<GatherDesc>(T, off[i][1]);
+                LD.sepdofs = view<int32_t>(T, off[i][2]);
+                LD.gslot_cnt = view<int32_t>(T, off[i][3]);
+                LD.gslot_cell = view<int32_t>(T, off[i][4]);
+                LD.gslot_off = view<int32_t>(T, off[i][5]);
+                LD.n_sep_ad = static_cast<int>(P.sep_apply.size());
+                int mb = 0;
+                apply_max(P.sep_apply, LD.mi_sep, mb);
+                LD.n_gather = static_cast<int>(P.gather.size());
+                LD.lds_sep = apply_lds(P.sep_apply);
+                LD.b_sep = P.alg_apply_sep_bytes;
+                LD.b_gather = P.alg_gather_bytes;
+                f->ws_elems = std::max(f->ws_elems, P.ws_elems);
+            }
         }
-        LD.n_sep_ad = static_cast<int>(P.sep_apply.size());
-        {
-            int mb = 0;
-            apply_max(P.sep_apply, LD.mi_sep, mb);
+        double* lg = static_cast<double*>(f0->dalloc(std::max<int64_t>(n_lg, 1) * sizeof(double)));
+        double* tp = static_cast<double*>(f0->dalloc(std::max<int64_t>(n_t, 1) * sizeof(double)));
+        double* gp = static_cast<double*>(f0->dalloc(std::max<int64_t>(n_g, 1) * sizeof(double)));
+        for (int p : nonroot) {
+            const Prob& q = pr[p];
+            const LevelPlan& P = q.ps->plan(lvl);
+            LevelDev& LD = q.f->lev[lvl];
+            LD.lg = lg + q.o_lg;
+            LD.tp = tp + q.o_t;
+            LD.gp = gp + q.o_g;
+            LD.bytes += (P.lg_elems + P.t_elems + P.g_elems) * 8;
         }
-        LD.n_gather = static_cast<int>(P.gather.size());
-        LD.lds_sep = apply_lds(P.sep_apply);
-        LD.b_sep = P.alg_apply_sep_bytes;
-        LD.b_gather = P.alg_gather_bytes;
-        f->ws_elems = std::max(f->ws_elems, P.ws_elems);
-        LD.lg = static_cast<double*>(f->dalloc(P.lg_elems * sizeof(double)));
-        LD.tp = static_cast<double*>(f->dalloc(P.t_elems * sizeof(double)));
-        LD.gp = static_cast<double*>(f->dalloc(P.g_elems * sizeof(double)));
-        LD.bytes += (P.lg_elems + P.t_elems + P.g_elems) * 8;
-        if (P.m_elems > f->mp_elems) {
-            f->mp = static_cast<double*>(f->dalloc(P.m_elems * sizeof(double)));
-            f->mp_elems = P.m_elems;
+        if (n_m > mp_elems) {
+            mp = static_cast<double*>(f0->dalloc(n_m * sizeof(double)));
+            mp_elems = n_m;
         }
-        const int nsk = static_cast<int>(P.skel_desc.size());
-        const int64_t kp = static_cast<int64_t>(nsk) + P.skel_ntotal + 1;
-        if (kp > f->kp_elems) {
+        const int nsk = static_cast<int>(mt.skd.size());
+        const int64_t kp = static_cast<int64_t>(n_k) + n_p + 1;
+        if (kp > kp_elems) {
             // a larger block: the error word so far moves along (stream-ordered after every
             // kernel that may have set it)
-            int32_t* nb = static_cast<int32_t*>(f->dalloc((kKbufHead + kp) * sizeof(int32_t)));
-            HIPCHK(hipMemcpyAsync(nb, f->kbuf, sizeof(unsigned long long), hipMemcpyDeviceToDevice, s));
-            f->kbuf = nb;
-            f->err = reinterpret_cast<unsigned long long*>(nb);
-            f->kp_elems = kp;
+            int32_t* nb = static_cast<int32_t*>(f0->dalloc((kKbufHead + kp) * sizeof(int32_t)));
+            HIPCHK(hipMemcpyAsync(nb, kbuf, sizeof(unsigned long long), hipMemcpyDeviceToDevice, s));
+            kbuf = nb;
+            err = reinterpret_cast<unsigned long long*>(nb);
+            kp_elems = kp;
         }
         // ranks, then the pivot orders, right after the error word
-        f->kout = f->kbuf + kKbufHead;
-        f->pout = f->kout + nsk;
+        int32_t* kout = kbuf + kKbufHead;
+        int32_t* pout = kout + n_k;
         phase(5, t0);
 
         // ---- block Jacobi (C_l) ----
         t0 = now();
-        if (LD.precond && !P.sep_desc.empty()) {
-            const int cap = panel_cap_for(P.max_sep_n, 0);
-            LD.li = static_cast<double*>(f->dalloc(P.li_elems * sizeof(double)));
-            double* li = LD.li;
+        const int nsep = static_cast<int>(mt.sep.size());
+        if (o.precond && nsep > 0) {
+            const int cap = panel_cap_for(max_sep_n, 0);
+            double* li = static_cast<double*>(f0->dalloc(std::max<int64_t>(n_li, 1) * sizeof(double)));
+            for (int p : nonroot) pr[p].f->lev[lvl].li = li + pr[p].o_li;
             // L_g is factored in LDS when the largest group fits
-            const int nm = P.max_sep_n;
-            const bool gstage = (f->o.flags & RHIF_FLAG_GLOBAL_STAGING) != 0;
+            const int nm = max_sep_n;
+            const bool gstage = (o.flags & RHIF_FLAG_GLOBAL_STAGING) != 0;
             const bool staged = !gstage && rhif::kPotrfSmemFixed + nm * nm <= kLdsMaxDoubles - kStaticLdsReserve;
             const size_t lds_pg = staged ? static_cast<size_t>(rhif::kPotrfSmemFixed + nm * nm) * sizeof(double)
                                          : potrf_lds(cap, 0);
-            KTIMED(f, s, RHIF_K_PRECOND_CHOL, P.alg_prec_chol_flops, 0.0,
-                   hipLaunchKernelGGL(k_precond_groups, dim3(P.sep_desc.size()), dim3(256), lds_pg, s, LD.sep,
-                                      LD.cref, LD.front, LD.lg, li, cap, staged ? nm : 0, lvl, f->err));
-            if (!P.cell_scale.empty()) {
+            KTIMED(f0, s, RHIF_K_PRECOND_CHOL, alg_pchol, 0.0,
+                   hipLaunchKernelGGL(k_precond_groups, dim3(nsep), dim3(256), lds_pg, s, sep_all, cref_all, front,
+                                      lg, li, cap, staged ? nm : 0, lvl, err));
+            if (!mt.cs.empty()) {
                 // per wave a strip of finished panels in LDS, or (larger groups) one 16 x 17 tile
-                int pstride = 17 * ((P.max_sep_n + 15) / 16) * 16;
+                int pstride = 17 * ((max_sep_n + 15) / 16) * 16;
                 if (gstage || 4 * pstride > kLdsMaxDoubles) pstride = 0;
                 const size_t lds_sc = static_cast<size_t>(pstride > 0 ? 4 * pstride : 4 * 16 * 17) * sizeof(double);
-                const int gc = P.max_cell_groups;
-                KTIMED(f, s, RHIF_K_PRECOND_SCALE, P.alg_prec_scale_flops, 0.0,
-                       hipLaunchKernelGGL(k_precond_scale, dim3(P.cell_scale.size(), gc * (gc + 1) / 2), dim3(256),
-                                          lds_sc, s, LD.cs, LD.cg, LD.lg, li, LD.front, pstride));
+                const int gc = max_cell_groups;
+                KTIMED(f0, s, RHIF_K_PRECOND_SCALE, alg_pscale, 0.0,
+                       hipLaunchKernelGGL(k_precond_scale, dim3(mt.cs.size(), gc * (gc + 1) / 2), dim3(256), lds_sc,
+                                          s, cs_all, cg_all, lg, li, front, pstride));
             }
         }
-        f->stats.n_groups[lvl] = LD.precond ? static_cast<int32_t>(P.sep_desc.size()) : 0;
+        for (int p : nonroot)
+            pr[p].f->stats.n_groups[lvl] =
+                o.precond ? static_cast<int32_t>(pr[p].ps->plan(lvl).sep_desc.size()) : 0;
         phase(2, t0);
 
         // ---- skeletonization (K_l) ----
@@ -1098,9 +1461,9 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
         int32_t* hk = nullptr;
         int32_t* hp = nullptr;
         if (nsk > 0) {
-            const int n = P.max_skel_n;
+            const int n = max_skel_n;
             int rmax = 1;
-            for (const auto& sk : P.skel_desc) rmax = std::max(rmax, sk.r);
+            for (const auto& sk : mt.skd) rmax = std::max(rmax, sk.r);
             // must match the LDS layout of k_skeletonize
             const int base = (2 * n + 1) / 2 + 1 + rmax + 2 * 256 * std::max(1, (n + 63) / 64) + rhif::kCpqrRegExtra;
             // M in doubles of LDS (FP32 values take half)
@@ -1108,7 +1471,7 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
             const int full = kPotrfSmemFixed + 17 * n;        // potrf scratch with the whole panel
             int staged = 0, cap = 0;
             size_t lds = 0;
-            if (f->o.flags & RHIF_FLAG_GLOBAL_STAGING) {
+            if (o.flags & RHIF_FLAG_GLOBAL_STAGING) {
                 cap = panel_cap_for(n, base);
                 lds = potrf_lds(cap, base);
             } else if (base + msz + n * n + full <= kLdsMaxDoubles) {
@@ -1116,8 +1479,11 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                 cap = n;
                 lds = static_cast<size_t>(base + msz + n * n + full) * sizeof(double);
                 // far more groups than the 256 CUs hold at two per CU: the form that keeps more
-                // of them resident per CU, when their LDS allows it
-                if (nsk > 2 * 256 && kSkelWavesMany * lds <= kLdsMaxDoubles * sizeof(double)) staged = 4;
+                // of them resident per CU, when their LDS allows it and every group's ID fits
+                // its registers (so that each group takes the same ID code in any form)
+                if (nsk > 2 * 256 && kSkelWavesMany * lds <= kLdsMaxDoubles * sizeof(double) &&
+                    skel_rows_per_thread(mt.skd) <= 16)
+                    staged = 4;
             } else if (base + msz + kPotrfSmemFixed <= kLdsMaxDoubles) {
                 staged = 1;
                 cap = std::min(n, (kLdsMaxDoubles - base - msz - kPotrfSmemFixed) / 17);
@@ -1126,40 +1492,40 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                 cap = panel_cap_for(n, base);
                 lds = potrf_lds(cap, base);
             }
-            LD.skli = static_cast<double*>(f->dalloc(P.skli_elems * sizeof(double)));
+            double* skli = static_cast<double*>(f0->dalloc(std::max<int64_t>(n_skli, 1) * sizeof(double)));
+            for (int p : nonroot) pr[p].f->lev[lvl].skli = skli + pr[p].o_skli;
             // groups whose M is too large for LDS and has many rows (the upper 3D levels): the
             // ID spread over row blocks of kBigRowsHost rows, one launch per step for all groups
-            const bool big = (f->o.flags & RHIF_FLAG_SKEL_MULTI) ||
-                             (staged == 0 && !(f->o.flags & RHIF_FLAG_GLOBAL_STAGING) &&
+            const bool big = (o.flags & RHIF_FLAG_SKEL_MULTI) ||
+                             (staged == 0 && !(o.flags & RHIF_FLAG_GLOBAL_STAGING) &&
                               static_cast<int64_t>(rmax) * n >= kBigSkelElems);
             if (big) {
                 const int nblk = (rmax + kBigRowsHost - 1) / kBigRowsHost;
-                double* nrm = static_cast<double*>(f->dalloc(static_cast<size_t>(nsk) * nblk * n * sizeof(double)));
-                double* wpart = static_cast<double*>(f->dalloc(static_cast<size_t>(nsk) * nblk * n * sizeof(double)));
-                int32_t* posb = static_cast<int32_t*>(f->dalloc(static_cast<size_t>(nsk) * n * sizeof(int32_t)));
-                BigState* bst = static_cast<BigState*>(f->dalloc(static_cast<size_t>(nsk) * sizeof(BigState)));
+                double* nrm = static_cast<double*>(f0->dalloc(static_cast<size_t>(nsk) * nblk * n * sizeof(double)));
+                double* wpart = static_cast<double*>(f0->dalloc(static_cast<size_t>(nsk) * nblk * n * sizeof(double)));
+                int32_t* posb = static_cast<int32_t*>(f0->dalloc(static_cast<size_t>(nsk) * n * sizeof(int32_t)));
+                BigState* bst = static_cast<BigState*>(f0->dalloc(static_cast<size_t>(nsk) * sizeof(BigState)));
                 int jmax = 0;
-                for (const auto& sk : P.skel_desc) jmax = std::max(jmax, std::min(sk.r, sk.n));
+                for (const auto& sk : mt.skd) jmax = std::max(jmax, std::min(sk.r, sk.n));
                 const dim3 gb2(nsk, nblk);
-                KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
                        hipLaunchKernelGGL(f32 ? k_big_gather<float> : k_big_gather<double>, gb2, dim3(256), 0, s,
-                                          LD.skd, LD.cgptr, LD.cgl, LD.cgoff, LD.cref, LD.front, f->mp, nrm, posb,
-                                          f->pout, bst, n, nblk, lvl, f->err));
+                                          skd_all, cgptr_all, cgl_all, cgoff_all, cref_all, front, mp, nrm, posb,
+                                          pout, bst, n, nblk, lvl, err));
                 BigState* hst = reinterpret_cast<BigState*>(hc.get_down(static_cast<size_t>(nsk) * sizeof(BigState) + 64));
                 // every group takes at most jmax steps (the last one only records the rank); the
                 // host checks every kBigCheck steps whether any group is still active
                 for (int j = 0; j <= jmax; ++j) {
-                    KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                    KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
                            hipLaunchKernelGGL(f32 ? k_big_pivot<float> : k_big_pivot<double>, dim3(nsk), dim3(256), 0,
-                                              s, LD.skd, f->mp, nrm, posb, f->pout, bst, f->o.eps, j, n, nblk,
-                                              f->kout));
+                                              s, skd_all, mp, nrm, posb, pout, bst, o.eps, j, n, nblk, kout));
                     if (j == jmax) break;
-                    KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
-                           hipLaunchKernelGGL(f32 ? k_big_dot<float> : k_big_dot<double>, gb2, dim3(256), 0, s, LD.skd,
-                                              f->mp, posb, bst, wpart, j, n, nblk));
-                    KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                    KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                           hipLaunchKernelGGL(f32 ? k_big_dot<float> : k_big_dot<double>, gb2, dim3(256), 0, s,
+                                              skd_all, mp, posb, bst, wpart, j, n, nblk));
+                    KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
                            hipLaunchKernelGGL(f32 ? k_big_update<float> : k_big_update<double>, gb2, dim3(256), 0, s,
-                                              LD.skd, f->mp, nrm, posb, bst, wpart, j, n, nblk));
+                                              skd_all, mp, nrm, posb, bst, wpart, j, n, nblk));
                     if ((j + 1) % kBigCheck == 0) {
                         HIPCHK(hipMemcpyAsync(hst, bst, static_cast<size_t>(nsk) * sizeof(BigState),
                                               hipMemcpyDeviceToHost, s));
@@ -1171,74 +1537,94 @@ void do_factor(rhif_factor_s* f, const int32_t* row_ptr, const int32_t* col, con
                 }
                 // a group still active after jmax steps took every column: its rank is set by
                 // the last pivot launch (j == min(r, n))
-                KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
                        hipLaunchKernelGGL(f32 ? k_big_trisolve<float> : k_big_trisolve<double>,
-                                          dim3(nsk, (n + 63) / 64), dim3(64), 0, s, LD.skd, f->mp, f->pout, bst,
-                                          LD.tp));
+                                          dim3(nsk, (n + 63) / 64), dim3(64), 0, s, skd_all, mp, pout, bst, tp));
                 const int fbase = (n + 1) / 2 + 1;
                 const int fcap = panel_cap_for(n, fbase);
-                KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
                        hipLaunchKernelGGL(f32 ? k_big_finish<float> : k_big_finish<double>, dim3(nsk), dim3(256),
-                                          potrf_lds(fcap, fbase), s, LD.skd, LD.cref, LD.front, f->mp, LD.gp, LD.skli,
-                                          f->kout, f->pout, fcap, n, lvl, f->err));
-            } else
-            KTIMED(f, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
-                   hipLaunchKernelGGL(skel_kernel(staged, skel_rows_per_thread(P.skel_desc), f32),
-                                      dim3(nsk), dim3(256), lds, s, LD.skd, LD.cgptr, LD.cgl, LD.cgoff, LD.cref, LD.front,
-                                      f->mp, LD.tp, LD.gp, LD.skli, f->o.eps, f->kout, f->pout, cap, n, rmax, lvl,
-                                      f->err));
+                                          potrf_lds(fcap, fbase), s, skd_all, cref_all, front, mp, gp, skli, kout,
+                                          pout, fcap, n, lvl, err));
+            } else {
+                KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                       hipLaunchKernelGGL(skel_kernel(staged, skel_rows_per_thread(mt.skd), f32), dim3(nsk),
+                                          dim3(256), lds, s, skd_all, cgptr_all, cgl_all, cgoff_all, cref_all, front,
+                                          mp, tp, gp, skli, o.eps, kout, pout, cap, n, rmax, lvl, err));
+            }
             // error word, ranks and pivot orders in one copy; synchronizes: the ranks are on
             // the host now
-            const size_t nb = (kKbufHead + nsk + static_cast<size_t>(P.skel_ntotal)) * sizeof(int32_t);
+            const size_t nb = (kKbufHead + static_cast<size_t>(n_k) + static_cast<size_t>(n_p)) * sizeof(int32_t);
             char* h = hc.get_down(nb + 64);
-            HIPCHK(hipMemcpyAsync(h, f->kbuf, nb, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(h, kbuf, nb, hipMemcpyDeviceToHost, s));
             hk = reinterpret_cast<int32_t*>(h) + kKbufHead;
-            hp = hk + nsk;
+            hp = hk + n_k;
             HIPCHK(hipStreamSynchronize(s));
             unsigned long long e = 0;
             std::memcpy(&e, h, sizeof(e));
-            raise_err(f, e);
+            raise_err(e, batch);
         } else {
-            check_err(f, s);
+            check_err(err, batch, s);
         }
         phase(3, t0);
 
-        // ---- the next level's active unknowns; this level's skeleton apply tables are built
-        //      after the next level's first launches (finish_skel_tables) ----
+        // ---- every problem's next active unknowns; this level's skeleton apply tables are
+        //      built after the next level's first launches ----
         t0 = now();
-        LD.k.assign(hk, hk + nsk);
-        LD.perm.assign(hp, hp + P.skel_ntotal);
-        LD.first_dof.resize(nsk);
-        LD.gsize.resize(nsk);
-        int64_t sum_rank = 0;
-        int max_rank = 0;
-        for (int e = 0; e < nsk; ++e) {
-            const int gidx = P.skels[e];
-            LD.first_dof[e] = P.gdofs[P.gptr[gidx]];
-            LD.gsize[e] = P.gptr[gidx + 1] - P.gptr[gidx];
-            sum_rank += LD.k[e];
-            max_rank = std::max(max_rank, LD.k[e]);
+        for (int p : nonroot) {
+            const Prob& q = pr[p];
+            const LevelPlan& P = q.ps->plan(lvl);
+            LevelDev& LD = q.f->lev[lvl];
+            const int ns = static_cast<int>(P.skel_desc.size());
+            if (ns > 0) {
+                LD.k.assign(hk + q.o_k, hk + q.o_k + ns);
+                LD.perm.assign(hp + q.o_p, hp + q.o_p + P.skel_ntotal);
+            } else {
+                LD.k.clear();
+                LD.perm.clear();
+            }
         }
-        f->stats.n_skel[lvl] = nsk;
-        f->stats.sum_skel_n[lvl] = P.skel_ntotal;
-        f->stats.sum_rank[lvl] = sum_rank;
-        f->stats.max_rank[lvl] = max_rank;
-        n_active = next_active_set(P, LD.k.data(), LD.perm.data(), scr);
-        pending_skel = lvl;
+        pool.run(static_cast<int>(nonroot.size()), [&](int i) {
+            Prob& q = pr[nonroot[i]];
+            rhif_factor_s* f = q.f;
+            const LevelPlan& P = q.ps->plan(lvl);
+            LevelDev& LD = f->lev[lvl];
+            const int ns = static_cast<int>(LD.k.size());
+            LD.first_dof.resize(ns);
+            LD.gsize.resize(ns);
+            int64_t sum_rank = 0;
+            int max_rank = 0;
+            for (int e = 0; e < ns; ++e) {
+                const int gidx = P.skels[e];
+                LD.first_dof[e] = P.gdofs[P.gptr[gidx]];
+                LD.gsize[e] = P.gptr[gidx + 1] - P.gptr[gidx];
+                sum_rank += LD.k[e];
+                max_rank = std::max(max_rank, LD.k[e]);
+            }
+            f->stats.n_skel[lvl] = ns;
+            f->stats.sum_skel_n[lvl] = P.skel_ntotal;
+            f->stats.sum_rank[lvl] = sum_rank;
+            f->stats.max_rank[lvl] = max_rank;
+            q.n_active = next_active_set(P, LD.k.data(), LD.perm.data(), q.ps->scr);
+            q.pending_skel = lvl;
+        });
         phase(5, t0);
     }
-    if (pending_skel >= 0) finish_skel_tables(pending_skel);
-    check_err(f, s);
-    f->stats.levels = f->L;
-    f->stats.root_size = static_cast<int32_t>(n_active);
-    f->stats.n_active[f->L] = n_active;
-    f->ybuf = static_cast<double*>(f->dalloc(std::max<int64_t>(f->y_elems, 1) * sizeof(double)));
-    if (f->ws_elems > 0) f->ws = static_cast<double*>(f->dalloc(f->ws_elems * sizeof(double)));
-    int64_t bytes = 0;
-    for (const auto& LD : f->lev) bytes += LD.bytes;
-    f->stats.factor_bytes = bytes;
+    // every problem finished its last skeleton tables at its root level
+    check_err(err, batch, s);
+    for (Prob& q : pr) {
+        rhif_factor_s* f = q.f;
+        f->stats.levels = f->L;
+        f->stats.root_size = static_cast<int32_t>(q.n_active);
+        f->stats.n_active[f->L] = q.n_active;
+        f->ybuf = static_cast<double*>(f->dalloc(std::max<int64_t>(f->y_elems, 1) * sizeof(double)));
+        if (f->ws_elems > 0) f->ws = static_cast<double*>(f->dalloc(f->ws_elems * sizeof(double)));
+        int64_t bytes = 0;
+        for (const auto& LD : f->lev) bytes += LD.bytes;
+        f->stats.factor_bytes = bytes;
+    }
     HIPCHK(hipStreamSynchronize(s));
-    f->resolve();
+    f0->resolve();
 }
 
 void launch_up(rhif_factor_s* f, double by, const rhif::ApplyDesc* ad, int n, size_t lds, const double* pool,
@@ -1825,11 +2211,31 @@ rhif_status rhif_assemble_fd(const rhif_grid* g, const double* a_cells, const do
 
 rhif_status rhif_factor(const rhif_grid* g, const rhif_opts* o, const int32_t* row_ptr, const int32_t* col,
                         const double* val, hipStream_t s, rhif_factor_t* out) {
-    rhif_factor_s* f = nullptr;
+    if (!out) {
+        g_last_error = "out is NULL";
+        return RHIF_EINVAL;
+    }
+    return rhif_factor_batch(1, g, o, &row_ptr, &col, &val, s, out);
+}
+
+rhif_status rhif_factor_batch(int32_t count, const rhif_grid* grids, const rhif_opts* o,
+                              const int32_t* const* row_ptr, const int32_t* const* col, const double* const* val,
+                              hipStream_t s, rhif_factor_t* out) {
+    std::vector<rhif_factor_s*> fs;
+    auto drop = [&] {
+        if (fs.empty()) return;
+        (void)hipStreamSynchronize(s);
+        for (rhif_factor_s* f : fs) {
+            f->release();
+            delete f;
+        }
+        fs.clear();
+    };
     try {
         if (!out) fail(RHIF_EINVAL, "out is NULL");
-        *out = nullptr;
-        validate_grid(g);
+        if (count < 1) fail(RHIF_EINVAL, "count must be >= 1");
+        for (int32_t i = 0; i < count; ++i) out[i] = nullptr;
+        if (!grids) fail(RHIF_EINVAL, "grids is NULL");
         if (!o) fail(RHIF_EINVAL, "opts is NULL");
         if (o->leaf < 2) fail(RHIF_EINVAL, "leaf must be >= 2");
         if (!(o->eps >= 0.0) || !(o->eps < 1.0)) fail(RHIF_EINVAL, "eps must be in [0, 1)");
@@ -1837,55 +2243,63 @@ rhif_status rhif_factor(const rhif_grid* g, const rhif_opts* o, const int32_t* r
         if (o->precision < 0 || o->precision > 2)
             fail(RHIF_EINVAL, "precision must be 0 (FP64), 1 (FP32 ID) or 2 (FP32 ID and Schur products)");
         if (o->flags & kRemovedFlags) fail(RHIF_EINVAL, "flag bit 2 (leaf sublevels) is not supported");
-        if (!row_ptr || !col || !val) fail(RHIF_EINVAL, "NULL CSR pointer");
-        set_kernel_attributes();
-        f = new rhif_factor_s();
-        HIPCHK(hipGetDevice(&f->device));
-        f->g.d = g->dim;
-        f->g.s = g->n[0];
-        f->g.N = 1;
-        for (int k = 0; k < g->dim; ++k) f->g.N *= g->n[0];
-        f->o = *o;
-        f->ktimes = (o->flags & RHIF_FLAG_KERNEL_TIMES) != 0;
-        {
-            const uint32_t m = (static_cast<uint32_t>(o->flags) >> RHIF_KERNEL_MASK_SHIFT) & 0xffffu;
-            f->kmask = m ? m : 0xffffu;
+        if (count > 1 && (o->flags & (RHIF_FLAG_KERNEL_TIMES | RHIF_FLAG_PHASE_TIMES)))
+            fail(RHIF_EINVAL, "kernel and phase times are recorded for single factorizations only");
+        if (!row_ptr || !col || !val) fail(RHIF_EINVAL, "NULL CSR pointer array");
+        std::vector<CsrIn> in(count);
+        for (int32_t i = 0; i < count; ++i) {
+            validate_grid(&grids[i]);
+            if (grids[i].dim != grids[0].dim) fail(RHIF_EINVAL, "every grid of a batch must have the same dim");
+            if (!row_ptr[i] || !col[i] || !val[i]) fail(RHIF_EINVAL, "NULL CSR pointer");
+            in[i] = {row_ptr[i], col[i], val[i]};
         }
-        f->L = rhif::num_levels(f->g.s, o->leaf);
-        f->Lskel = f->L;
-        f->stats.sublevels = 0;
-        if (f->L > RHIF_MAX_LEVELS) fail(RHIF_EINVAL, "too many levels");
+        set_kernel_attributes();
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        auto arena = std::make_shared<Arena>();
+        arena->device = dev;
+        for (int32_t i = 0; i < count; ++i) {
+            rhif_factor_s* f = new rhif_factor_s();
+            fs.push_back(f);
+            f->device = dev;
+            f->arena = arena;
+            const rhif_grid* g = &grids[i];
+            f->g.d = g->dim;
+            f->g.s = g->n[0];
+            f->g.N = 1;
+            for (int k = 0; k < g->dim; ++k) f->g.N *= g->n[0];
+            f->o = *o;
+            f->ktimes = (o->flags & RHIF_FLAG_KERNEL_TIMES) != 0;
+            {
+                const uint32_t m = (static_cast<uint32_t>(o->flags) >> RHIF_KERNEL_MASK_SHIFT) & 0xffffu;
+                f->kmask = m ? m : 0xffffu;
+            }
+            f->L = rhif::num_levels(f->g.s, o->leaf);
+            f->Lskel = f->L;
+            f->stats.sublevels = 0;
+            if (f->L > RHIF_MAX_LEVELS) fail(RHIF_EINVAL, "too many levels");
+        }
         const auto t0 = std::chrono::steady_clock::now();
-        do_factor(f, row_ptr, col, val, s);
-        f->mark(s);
-        f->stats.t_total_ms =
-            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        *out = f;
+        do_factor(fs, in.data(), s);
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        for (int32_t i = 0; i < count; ++i) {
+            fs[i]->mark(s);
+            fs[i]->stats.t_total_ms = ms;
+            out[i] = fs[i];
+        }
         g_last_error.clear();
         return RHIF_OK;
     } catch (const Failure& e) {
         g_last_error = e.msg;
-        if (f) {
-            (void)hipStreamSynchronize(s);
-            f->release();
-            delete f;
-        }
+        drop();
         return e.st;
     } catch (const std::bad_alloc&) {
         g_last_error = "host allocation failed";
-        if (f) {
-            (void)hipStreamSynchronize(s);
-            f->release();
-            delete f;
-        }
+        drop();
         return RHIF_ENOMEM;
     } catch (const std::exception& e) {
         g_last_error = std::string("internal error: ") + e.what();
-        if (f) {
-            (void)hipStreamSynchronize(s);
-            f->release();
-            delete f;
-        }
+        drop();
         return RHIF_EINVAL;
     }
 }

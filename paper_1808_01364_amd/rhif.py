@@ -31,7 +31,7 @@ KCLASS_NAMES = ["front_csr", "front_extend", "elim_leaf", "elim_upper", "root", 
                 "vector", "-", "-", "-"]
 
 # every function declared in include/rhif.h
-EXPORTED = ["rhif_fd_nnz", "rhif_assemble_fd", "rhif_factor", "rhif_apply", "rhif_pcg_solve",
+EXPORTED = ["rhif_fd_nnz", "rhif_assemble_fd", "rhif_factor", "rhif_factor_batch", "rhif_apply", "rhif_pcg_solve",
             "rhif_pcg_solve_noalloc", "rhif_apply_half", "rhif_estimate_es",
             "rhif_apply_forward", "rhif_estimate_ea", "rhif_matvec", "rhif_grad_log_a", "rhif_stats", "rhif_skeletons", "rhif_destroy",
             "rhif_last_error", "rhif_version"]
@@ -99,6 +99,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rhif_fd_nnz.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_int64)]
     lib.rhif_assemble_fd.argtypes = [ctypes.POINTER(Grid), vp, vp, vp, vp, vp, vp]
     lib.rhif_factor.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Opts), vp, vp, vp, vp, ctypes.POINTER(vp)]
+    lib.rhif_factor_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(Grid), ctypes.POINTER(Opts),
+                                      ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
+                                      ctypes.POINTER(vp)]
     lib.rhif_apply.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
     lib.rhif_pcg_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int32, c_i32p,
                                    ctypes.POINTER(ctypes.c_double), vp]
@@ -240,6 +243,14 @@ class Factor:
         _check(self._lib.rhif_factor(ctypes.byref(make_grid(dim, n)), ctypes.byref(o), _ptr(rp), _ptr(col),
                                      _ptr(val), _stream(stream), ctypes.byref(h)))
         self._h = h
+
+    @classmethod
+    def _adopt(cls, dim: int, n: int, h: ctypes.c_void_p) -> "Factor":
+        self = cls.__new__(cls)
+        self.dim, self.n, self.N = dim, n, n ** dim
+        self._lib = load_library()
+        self._h = h
+        return self
 
     @property
     def handle(self):
@@ -390,6 +401,31 @@ class Factor:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def factor_batch(problems, leaf: int, eps: float, precond: int = 1, precision: int = 0, flags: int = 0,
+                 stream=None) -> List[Factor]:
+    """Factor independent problems together (rhif_factor_batch): problems is a list of
+    (dim, n, csr) with csr = (row_ptr, col, val) device tensors as for Factor. Returns one
+    Factor per problem, each bitwise the one Factor(dim, n, csr, ...) would give."""
+    if not problems:
+        return []
+    lib = load_library()
+    count = len(problems)
+    grids = (Grid * count)()
+    rps, cols, vals = ((ctypes.c_void_p * count)() for _ in range(3))
+    for i, (dim, n, csr) in enumerate(problems):
+        rp, col, val = csr
+        nnz = fd_nnz(dim, n)
+        _need((rp, f"row_ptr[{i}]", n ** dim + 1, "int32"), (col, f"col[{i}]", nnz, "int32"),
+              (val, f"val[{i}]", nnz))
+        grids[i] = make_grid(dim, n)
+        rps[i], cols[i], vals[i] = _ptr(rp), _ptr(col), _ptr(val)
+    o = Opts()
+    o.leaf, o.eps, o.precond, o.precision, o.flags = leaf, eps, precond, precision, flags
+    hs = (ctypes.c_void_p * count)()
+    _check(lib.rhif_factor_batch(count, grids, ctypes.byref(o), rps, cols, vals, _stream(stream), hs))
+    return [Factor._adopt(dim, n, ctypes.c_void_p(hs[i])) for i, (dim, n, _) in enumerate(problems)]
 
 
 def version() -> str:

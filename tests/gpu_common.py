@@ -121,7 +121,7 @@ def assert_choices(c):
     assert c["bad"] == 0 and c["missing"] == 0 and c["extra"] == 0, c
 
 
-def parity_check(P, A, n_rhs=3, well_conditioned=False, sol_tol=1e-10, flags=0, c_kappa=100.0, seed=11):
+def parity_check(P, A, n_rhs=3, well_conditioned=False, sol_tol=1e-10, flags=0, c_kappa=100.0, seed=11, F=None):
     """GPU against the oracle on the same matrix (the parity protocol of the ID's possible
     ties, Sec. 2.2):
     * every ID takes the oracle's rank and skeleton set, or differs only where the oracle's
@@ -130,8 +130,9 @@ def parity_check(P, A, n_rhs=3, well_conditioned=False, sol_tol=1e-10, flags=0, 
       the replayed oracle's, normwise and elementwise, to 100 u on well-conditioned inputs and
       otherwise to c u kappa, kappa the largest condition number of a triangular factor the
       apply solves with (the forward error of the solves);
-    * PCG takes the oracle's number of iterations and the solutions agree to sol_tol."""
-    F = gpu_factor(P, flags=flags)
+    * PCG takes the oracle's number of iterations and the solutions agree to sol_tol.
+    F: a factor of P made elsewhere (for example by a batched call); closed at the end."""
+    F = gpu_factor(P, flags=flags) if F is None else F
     st = F.stats()
     ch = gpu_choices(F, st["levels"] - st["sublevels"])
     orc = O.factor(A, P.d, P.s, P.leaf, P.eps, P.precond)

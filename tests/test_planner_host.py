@@ -29,6 +29,29 @@ def test_library_exports_every_declared_symbol():
     assert "gfx950" in rhif.version()
 
 
+def test_factor_batch_rejects_bad_calls_before_device_work():
+    """rhif_factor_batch checks its arguments before touching the device (the CSR pointers
+    here are never dereferenced): no problem, timing flags with several problems, grids of
+    different dimension; every out[i] is NULL afterwards."""
+    import ctypes
+    lib = rhif.load_library()
+    o = rhif.Opts()
+    o.leaf, o.eps, o.precond, o.precision, o.flags = 8, 1e-3, 1, 0, 0
+    grids = (rhif.Grid * 2)(rhif.make_grid(2, 16), rhif.make_grid(2, 24))
+    fake = (ctypes.c_void_p * 2)(16, 16)
+    out = (ctypes.c_void_p * 2)(1, 1)
+    assert lib.rhif_factor_batch(0, grids, ctypes.byref(o), fake, fake, fake, None, out) == rhif.RHIF_EINVAL
+    assert "count" in lib.rhif_last_error().decode()
+    o.flags = rhif.FLAG_KERNEL_TIMES
+    assert lib.rhif_factor_batch(2, grids, ctypes.byref(o), fake, fake, fake, None, out) == rhif.RHIF_EINVAL
+    assert "single" in lib.rhif_last_error().decode() and not out[0] and not out[1]
+    o.flags = 0
+    grids[1] = rhif.make_grid(3, 8)
+    out[0] = out[1] = 1
+    assert lib.rhif_factor_batch(2, grids, ctypes.byref(o), fake, fake, fake, None, out) == rhif.RHIF_EINVAL
+    assert "same dim" in lib.rhif_last_error().decode() and not out[0] and not out[1]
+
+
 def test_fd_nnz_host():
     assert rhif.fd_nnz(2, 64) == 64 * 64 + 2 * 2 * 64 * 63
     assert rhif.fd_nnz(3, 5) == 125 + 2 * 3 * 25 * 4
