@@ -214,6 +214,32 @@ rhif_status rhif_apply(rhif_factor_t f, const double *r, double *z, int32_t nrhs
 rhif_status rhif_pcg_solve(rhif_factor_t f, const double *rhs, double *u, double rtol,
                            int32_t maxit, int32_t *iters, double *relres, hipStream_t s);
 
+/* z_i = F_i^-1 r_i for every problem i of one rhif_factor_batch call (eq. (3.2)), all at
+ * once: each level's up- and down-sweep kernels run as one launch over the blocks of all
+ * problems. Every block is computed as in its own problem's rhif_apply (the results are
+ * bitwise those of rhif_apply).
+ *  f     [host] the count (>= 2) handles of ONE rhif_factor_batch call, all of them, in the
+ *        call's order (EINVAL otherwise, or once one of them has been destroyed)
+ *  r, z  [host] arrays of count device pointers to N_i doubles each (inputs not modified)
+ * The first joint call on a batch builds its merged tables (one upload). Calls on one batch
+ * are serialized. Stream-ordered, never synchronizes. Errors: EINVAL, EDEVICE. */
+rhif_status rhif_apply_batch(int32_t count, const rhif_factor_t *f, const double *const *r,
+                             double *const *z, hipStream_t s);
+
+/* rhif_pcg_solve for every problem i of one rhif_factor_batch call at once: the CG vector
+ * kernels and the applies each run as one launch over all problems, every problem with its
+ * own scalars; a problem stops updating once its own residual test passes, and each takes the
+ * iterations of its own rhif_pcg_solve (the same arithmetic: bitwise the same solution). One
+ * read-back of every problem's residual norm per iteration.
+ *  f              as for rhif_apply_batch
+ *  rhs, u         [host] arrays of count device pointers (N_i doubles each; u is output)
+ *  iters, relres  [host] arrays of count entries (output), as for rhif_pcg_solve
+ * Errors: EINVAL, EDEVICE, ENOCONV (some problem missed rtol within maxit; every u_i, iters_i
+ * and relres_i is still set). */
+rhif_status rhif_pcg_solve_batch(int32_t count, const rhif_factor_t *f, const double *const *rhs,
+                                 double *const *u, double rtol, int32_t maxit, int32_t *iters,
+                                 double *relres, hipStream_t s);
+
 /* One half of the factor apply: F^-1 = G^-T G^-1 with F = G G^T (eq. (3.3)).
  *  which = 0: z = G^-1 r (the up-sweep R_0^T .. R_{L-1}^T of eq. (3.2), then the forward
  *             solve with the root factor B_L, A_L = B_L B_L^T);

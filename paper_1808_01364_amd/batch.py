@@ -4,12 +4,13 @@ Worker threads, each with its own HIP stream, take work from a shared queue. A u
 is a group of problems factored in one call (rhif_factor_batch: the group advances level by
 level together, every elimination, block-Jacobi and skeletonization kernel of a level is one
 launch over the blocks of all the group's problems, and one read-back per level brings all
-their ranks), followed by each problem's PCG solve and the release of the factors, all
-stream-ordered on the worker's stream. Groups of one problem are plain rhif_factor calls.
+their ranks), then solved in one joint PCG (rhif_pcg_solve_batch: every apply and vector
+kernel one launch over all of them, one residual read-back per iteration), then released,
+all stream-ordered on the worker's stream. Groups of one problem are plain rhif_factor calls.
 While one worker's host plans its group's next level, the kernels of the others keep the GPU
 busy. Results do not depend on the interleaving (every kernel's arithmetic order is fixed),
 so a batch reproduces the one-by-one solutions; grouping changes at most the storage form a
-kernel takes for a level (the factors agree with the lone ones to rounding).
+kernel takes for a level, which leaves its arithmetic as it is.
 
 The batch shape (group size, number of streams, and whether the queue takes the largest
 problems first) is picked by a small autotuner that times the candidates on a sample of the
@@ -51,20 +52,20 @@ def solve_one(item: BatchItem, rtol: float = 1e-12, maxit: int = 500, stream=Non
 
 def solve_group(items, rtol: float = 1e-12, maxit: int = 500, stream=None):
     """[(u, iterations, relative residual)] of problems with the same dim, leaf, eps and
-    precision, factored in one rhif_factor_batch call on `stream` (the current stream if None);
-    the factors are released before returning."""
+    precision, factored in one rhif_factor_batch call and solved in one joint PCG
+    (rhif_pcg_solve_batch) on `stream` (the current stream if None); the factors are released
+    before returning."""
     it0 = items[0]
     csrs = [rhif.assemble_fd(it.dim, it.n, it.a_cells, it.b, stream=stream) for it in items]
     Fs = rhif.factor_batch([(it.dim, it.n, c) for it, c in zip(items, csrs)], it0.leaf, it0.eps, 1,
                            it0.precision, stream=stream)
-    out = []
     try:
-        for it, F in zip(items, Fs):
-            out.append(F.pcg(it.f, rtol, maxit, stream=stream))
+        if len(Fs) == 1:
+            return [Fs[0].pcg(items[0].f, rtol, maxit, stream=stream)]
+        return rhif.pcg_batch(Fs, [it.f for it in items], rtol, maxit, stream=stream)
     finally:
         for F in Fs:
             F.close()
-    return out
 
 
 def _order(items, order: str):
@@ -88,6 +89,28 @@ def _groups(items, order: str, group: int):
     return [g for _, g in out]
 
 
+# Worker threads and their streams live for the life of the process: the library keeps
+# per-thread host state (pinned staging buffers, planner scratch, the level-0 plan of the last
+# geometry) that a fresh thread would have to build again.
+_POOL = None
+_TLS = threading.local()
+
+
+def _executor():
+    global _POOL
+    if _POOL is None:
+        _POOL = cf.ThreadPoolExecutor(max_workers=max(STREAM_CANDIDATES))
+    return _POOL
+
+
+def _thread_stream():
+    import torch
+    st = getattr(_TLS, "stream", None)
+    if st is None:
+        st = _TLS.stream = torch.cuda.Stream()
+    return st
+
+
 def _run(items, nstreams: int, order: str, rtol: float, maxit: int, group: int = 1):
     import torch
     out = [None] * len(items)
@@ -96,7 +119,7 @@ def _run(items, nstreams: int, order: str, rtol: float, maxit: int, group: int =
     lock = threading.Lock()
 
     def worker():
-        st = torch.cuda.Stream()
+        st = _thread_stream()
         with torch.cuda.stream(st):
             while True:
                 with lock:
@@ -112,10 +135,9 @@ def _run(items, nstreams: int, order: str, rtol: float, maxit: int, group: int =
                         out[i] = r
         st.synchronize()
 
-    nw = max(1, min(nstreams, len(items)))
-    with cf.ThreadPoolExecutor(max_workers=nw) as ex:
-        for fut in [ex.submit(worker) for _ in range(nw)]:
-            fut.result()
+    nw = max(1, min(nstreams, len(queue), max(STREAM_CANDIDATES)))
+    for fut in [_executor().submit(worker) for _ in range(nw)]:
+        fut.result()
     return out
 
 

@@ -118,6 +118,7 @@ struct ApplyDesc {
     int32_t dofs;        // offset of nI interior then nB boundary unknowns (global indices)
     int32_t ext;         // >= 0: per-panel nonzero row ends of L (see FrontDesc::ext)
     int32_t li;          // offset of the inverses of L's 16 x 16 diagonal blocks (256 each)
+    int64_t zoff;        // offset of the block's problem in the vector (several problems at once)
 };
 
 // Gather of the up-sweep boundary contributions of the cells for one separator group.
@@ -127,6 +128,7 @@ struct GatherDesc {
     int32_t nslot;
     int32_t pad;
     int64_t yoff[kMaxSlots];  // scratch position of the group's first unknown in each cell
+    int64_t zoff;             // offset of the group's problem in the vector
 };
 
 // The separator-group part of one level of the factor apply, one workgroup per group: the
@@ -147,6 +149,20 @@ struct GroupApplyDesc {
     int64_t toff;       // T (k x nr, ld k) in the T pool
     int32_t skli;       // inverses of L~'s 16 x 16 diagonal blocks
     int32_t pad;
+    int64_t zoff;       // offset of the group's problem in the vector
+};
+
+// One problem of a PCG solve over several problems at once: its matrix, its place in the
+// concatenated vectors, and its blocks in the grids of the vector kernels (the grid a lone
+// solve of the problem uses, so that every sum is formed in the same order).
+struct BatchSeg {
+    const int32_t* rp;
+    const int32_t* ci;
+    const double* val;
+    int64_t zoff;        // first unknown of the problem in the vectors
+    int64_t n;           // its unknowns
+    int32_t b0;          // its first block
+    int32_t nb;          // its number of blocks
 };
 
 }  // namespace rhif

@@ -773,6 +773,27 @@ __device__ __forceinline__ double edge_coef(const double* a, int d, int s, int k
     return acc / static_cast<double>(combos);
 }
 
+// Row pointer of the 5-/7-point matrix in closed form: row i holds 1 + sum_k [x_k > 1] + [x_k < s]
+// entries, so the rows before i hold i (1 + 2d) entries less, per axis k, one for every row
+// j < i on the first plane x_k = 1 and one for every row on the last plane x_k = s; with
+// stride t = s^k such rows come in runs of t every s t rows.
+__global__ __launch_bounds__(256) void k_fd_rowptr(int d, int s, int32_t* __restrict__ row_ptr) {
+    int64_t N = 1;
+    for (int k = 0; k < d; ++k) N *= s;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i <= N;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        int64_t v = i * (1 + 2 * d), t = 1;
+        for (int k = 0; k < d; ++k) {
+            const int64_t q = i / (t * s), r = i % (t * s);
+            const int64_t first = q * t + (r < t ? r : t);
+            const int64_t last = q * t + (r > (s - 1) * t ? r - (s - 1) * t : 0);
+            v -= first + last;
+            t *= s;
+        }
+        row_ptr[i] = static_cast<int32_t>(v);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_assemble_fd(int d, int s, double inv_h2, const double* __restrict__ a,
                                                      const double* __restrict__ b, const int32_t* __restrict__ row_ptr,
                                                      int32_t* __restrict__ col, double* __restrict__ val) {
@@ -2399,6 +2420,7 @@ __global__ __launch_bounds__(256) void k_fwd_gt(const ApplyDesc* __restrict__ ad
                                                 const double* __restrict__ Tp, const int32_t* __restrict__ dofs,
                                                 const int32_t* __restrict__ ext, double* __restrict__ z) {
     const ApplyDesc d = ad[blockIdx.x];
+    z += d.zoff;   // the block's problem within the vector
     const int nI = d.nI, nB = d.nB, ld = d.ld, tid = threadIdx.x;
     const double* A = pool + d.off;
     const int32_t* di = dofs + d.dofs;
@@ -2436,6 +2458,7 @@ __global__ __launch_bounds__(256) void k_fwd_g(const ApplyDesc* __restrict__ ad,
                                                const int32_t* __restrict__ ext, double* __restrict__ z,
                                                double* __restrict__ ybuf) {
     const ApplyDesc d = ad[blockIdx.x];
+    z += d.zoff;   // the block's problem within the vector
     const int nI = d.nI, nB = d.nB, ld = d.ld, tid = threadIdx.x;
     const double* A = pool + d.off;
     const int32_t* di = dofs + d.dofs;
@@ -2473,6 +2496,7 @@ __global__ __launch_bounds__(256) void k_fwd_g(const ApplyDesc* __restrict__ ad,
 __global__ __launch_bounds__(256) void k_fwd_gather(const GatherDesc* __restrict__ gd, const int32_t* __restrict__ dofs,
                                                     const double* __restrict__ ybuf, double* __restrict__ z) {
     const GatherDesc g = gd[blockIdx.x];
+    z += g.zoff;   // the block's problem within the vector
     for (int t = threadIdx.x; t < g.n; t += kWG) {
         const int i = dofs[g.dofs + t];
         double v = z[i];
@@ -2561,6 +2585,7 @@ __global__ __launch_bounds__(256) void k_apply_up(const ApplyDesc* __restrict__ 
                                                   double* __restrict__ ws, const int32_t* __restrict__ extp) {
     extern __shared__ double smem[];
     const ApplyDesc d = ad[blockIdx.x];
+    z += d.zoff;   // the block's problem within the vector
     double* Dg = smem;
     int* ext = (extp != nullptr && d.ext >= 0 && (d.nI + 15) / 16 <= 2 * kApplyExtDoubles)
                    ? reinterpret_cast<int*>(smem + kApplyDiagDoubles)
@@ -2620,6 +2645,7 @@ __global__ __launch_bounds__(256) void k_apply_down(const ApplyDesc* __restrict_
                                                     const int32_t* __restrict__ extp) {
     extern __shared__ double smem[];
     const ApplyDesc d = ad[blockIdx.x];
+    z += d.zoff;   // the block's problem within the vector
     double* Dg = smem;
     int* ext = (extp != nullptr && d.ext >= 0 && (d.nI + 15) / 16 <= 2 * kApplyExtDoubles)
                    ? reinterpret_cast<int*>(smem + kApplyDiagDoubles)
@@ -2794,6 +2820,7 @@ __global__ __launch_bounds__(256) void k_apply_band(const ApplyDesc* __restrict_
     extern __shared__ double smem[];
     constexpr int TS = 16 * 17;
     const ApplyDesc d = ad[blockIdx.x];
+    z += d.zoff;   // the block's problem within the vector
     const int nI = d.nI, nb = (nI + 15) / 16, ld = d.ld;
     const double* A = pool + d.off;
     const double* li = lip + d.li;
@@ -2863,6 +2890,7 @@ __global__ __launch_bounds__(256) void k_apply_trsv_up(const ApplyDesc* __restri
                                                        const int32_t* __restrict__ extp) {
     extern __shared__ double smem[];
     const ApplyDesc d = ad[blockIdx.x];
+    z += d.zoff;   // the block's problem within the vector
     const int nI = d.nI, nB = d.nB;
     const int nt = (nI + 15) / 16;
     const int tid = threadIdx.x;
@@ -2899,6 +2927,7 @@ __global__ __launch_bounds__(256) void k_apply_trsv_dn(const ApplyDesc* __restri
                                                        const int32_t* __restrict__ extp) {
     extern __shared__ double smem[];
     const ApplyDesc d = ad[blockIdx.x];
+    z += d.zoff;   // the block's problem within the vector
     const int nI = d.nI, nB = d.nB;
     const int nt = (nI + 15) / 16;
     const int tid = threadIdx.x;
@@ -2967,6 +2996,7 @@ __global__ __launch_bounds__(256) void k_apply_group_up(const GroupApplyDesc* __
                                                         const int32_t* __restrict__ perm, int tkcap) {
     extern __shared__ double smem[];
     const GroupApplyDesc g = gd[blockIdx.x];
+    z += g.zoff;   // the block's problem within the vector
     const int n = g.n, tid = threadIdx.x;
     const int np = 16 * ((n + 15) / 16);
     double* zl = smem;
@@ -3025,6 +3055,7 @@ __global__ __launch_bounds__(256) void k_apply_group_dn(const GroupApplyDesc* __
                                                         const int32_t* __restrict__ perm, int tkcap) {
     extern __shared__ double smem[];
     const GroupApplyDesc g = gd[blockIdx.x];
+    z += g.zoff;   // the block's problem within the vector
     const int n = g.n, tid = threadIdx.x;
     const int np = 16 * ((n + 15) / 16);
     double* zl = smem;
@@ -3076,6 +3107,7 @@ __global__ __launch_bounds__(256) void k_apply_gemv_up(const ApplyDesc* __restri
                                                        double* __restrict__ ybuf) {
     extern __shared__ double smem[];
     const ApplyDesc d = ad[blockIdx.x];
+    z += d.zoff;   // the block's problem within the vector
     const int nI = d.nI, nB = d.nB, ld = d.ld;
     const int b0 = 64 * static_cast<int>(blockIdx.y);
     if (b0 >= nB) return;
@@ -3124,6 +3156,7 @@ __global__ __launch_bounds__(256) void k_apply_gemv_dn(const ApplyDesc* __restri
                                                        const int32_t* __restrict__ dofs, double* __restrict__ z) {
     extern __shared__ double smem[];
     const ApplyDesc d = ad[blockIdx.x];
+    z += d.zoff;   // the block's problem within the vector
     const int nI = d.nI, nB = d.nB, ld = d.ld;
     const int i0 = 64 * static_cast<int>(blockIdx.y);
     if (i0 >= nI || nB == 0) return;
@@ -3166,6 +3199,7 @@ __global__ __launch_bounds__(256) void k_apply_gemv_dn(const ApplyDesc* __restri
 __global__ __launch_bounds__(256) void k_sep_gather(const GatherDesc* __restrict__ gd, const int32_t* __restrict__ dofs,
                                                     const double* __restrict__ ybuf, double* __restrict__ z) {
     const GatherDesc g = gd[blockIdx.x];
+    z += g.zoff;   // the block's problem within the vector
     for (int t = threadIdx.x; t < g.n; t += kWG) {
         const int i = dofs[g.dofs + t];
         double v = z[i];
@@ -3285,6 +3319,109 @@ __global__ __launch_bounds__(256) void k_axpby(int64_t N, double a, const double
 __global__ __launch_bounds__(256) void k_fill(int64_t N, double v, double* __restrict__ y) {
     for (int64_t i = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; i < N; i += static_cast<int64_t>(gridDim.x) * kWG)
         y[i] = v;
+}
+
+// ---------------------------------------------------------------------------------------
+// The same vector kernels for a PCG over several problems at once: block b works for problem
+// blk[b] exactly as block b - b0 of that problem's lone grid would (same rows, same partial
+// sums), every problem with its own scalars (16 slots each). An inactive problem (converged)
+// gets alpha = beta = 0, which leaves its solution and residual as they are.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_bspmv_dot(const BatchSeg* __restrict__ seg, const int32_t* __restrict__ blk,
+                                                   const double* __restrict__ p, double* __restrict__ q,
+                                                   double* __restrict__ part) {
+    __shared__ double red[kWaves];
+    const BatchSeg g = seg[blk[blockIdx.x]];
+    const double* pp = p + g.zoff;
+    double* qq = q + g.zoff;
+    double acc = 0.0;
+    for (int64_t i = (blockIdx.x - g.b0) * static_cast<int64_t>(kWG) + threadIdx.x; i < g.n;
+         i += static_cast<int64_t>(g.nb) * kWG) {
+        double s = 0.0;
+        for (int e = g.rp[i]; e < g.rp[i + 1]; ++e) s += g.val[e] * pp[g.ci[e]];
+        qq[i] = s;
+        acc += s * pp[i];
+    }
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_bdot(const BatchSeg* __restrict__ seg, const int32_t* __restrict__ blk,
+                                              const double* __restrict__ x, const double* __restrict__ y,
+                                              double* __restrict__ part) {
+    __shared__ double red[kWaves];
+    const BatchSeg g = seg[blk[blockIdx.x]];
+    const double* xx = x + g.zoff;
+    const double* yy = y + g.zoff;
+    double acc = 0.0;
+    for (int64_t i = (blockIdx.x - g.b0) * static_cast<int64_t>(kWG) + threadIdx.x; i < g.n;
+         i += static_cast<int64_t>(g.nb) * kWG)
+        acc += xx[i] * yy[i];
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// One workgroup per problem: its partial sums in the order of k_finalize, the modes of
+// k_finalize on its 16 scalar slots.
+__global__ __launch_bounds__(256) void k_bfinalize(const BatchSeg* __restrict__ seg, const double* __restrict__ part,
+                                                   int mode, double* __restrict__ sc, const int32_t* __restrict__ active) {
+    __shared__ double red[kWaves];
+    const BatchSeg g = seg[blockIdx.x];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < g.nb; b += blockDim.x) acc += part[g.b0 + b];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x != 0) return;
+    double* c = sc + 16 * blockIdx.x;
+    const bool on = active[blockIdx.x] != 0;
+    switch (mode) {
+        case 0: c[6] = s; break;
+        case 1: c[1] = s; c[2] = on ? c[0] / s : 0.0; break;
+        case 2: c[3] = s; break;
+        case 3: c[0] = s; break;
+        case 4: c[4] = s; c[5] = on ? s / c[0] : 0.0; c[0] = s; break;
+        case 5: c[7] = s; break;
+        case 6: c[4] = s; c[5] = on ? (s - c[7]) / c[0] : 0.0; c[0] = s; break;
+        default: break;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_baxpy2(const BatchSeg* __restrict__ seg, const int32_t* __restrict__ blk,
+                                                const double* __restrict__ sc, const double* __restrict__ p,
+                                                const double* __restrict__ q, double* __restrict__ u,
+                                                double* __restrict__ r, double* __restrict__ part,
+                                                const double* __restrict__ zold, double* __restrict__ part2) {
+    __shared__ double red[kWaves];
+    const int pb = blk[blockIdx.x];
+    const BatchSeg g = seg[pb];
+    const double alpha = sc[16 * pb + 2];
+    const int64_t o = g.zoff;
+    double acc = 0.0, acc2 = 0.0;
+    for (int64_t i = (blockIdx.x - g.b0) * static_cast<int64_t>(kWG) + threadIdx.x; i < g.n;
+         i += static_cast<int64_t>(g.nb) * kWG) {
+        u[o + i] += alpha * p[o + i];
+        const double ri = r[o + i] - alpha * q[o + i];
+        r[o + i] = ri;
+        acc += ri * ri;
+        if (zold != nullptr) acc2 += ri * zold[o + i];
+    }
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+    if (zold != nullptr) {
+        const double t2 = block_sum(acc2, red);
+        if (threadIdx.x == 0) part2[blockIdx.x] = t2;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bupdate_p(const BatchSeg* __restrict__ seg, const int32_t* __restrict__ blk,
+                                                   const double* __restrict__ sc, const double* __restrict__ z,
+                                                   double* __restrict__ p) {
+    const int pb = blk[blockIdx.x];
+    const BatchSeg g = seg[pb];
+    const double beta = sc[16 * pb + 5];
+    const int64_t o = g.zoff;
+    for (int64_t i = (blockIdx.x - g.b0) * static_cast<int64_t>(kWG) + threadIdx.x; i < g.n;
+         i += static_cast<int64_t>(g.nb) * kWG)
+        p[o + i] = z[o + i] + beta * p[o + i];
 }
 
 __global__ void k_set_u64(unsigned long long* p, unsigned long long v) {

@@ -8,6 +8,7 @@
 
 namespace rhif {
 
+__global__ void k_fd_rowptr(int d, int s, int32_t* row_ptr);
 __global__ void k_assemble_fd(int d, int s, double inv_h2, const double* a, const double* b,
                               const int32_t* row_ptr, int32_t* col, double* val);
 __global__ void k_grad_log_a(int d, int s, double inv_h2, const double* a, const double* u, const double* lam,
@@ -104,6 +105,12 @@ __global__ void k_update_p(int64_t N, const double* sc, const double* z, double*
 __global__ void k_copy(int64_t N, const double* x, double* y);
 __global__ void k_fill(int64_t N, double v, double* y);
 __global__ void k_axpby(int64_t N, double a, const double* x, double b, double* y);
+__global__ void k_bspmv_dot(const BatchSeg* seg, const int32_t* blk, const double* p, double* q, double* part);
+__global__ void k_bdot(const BatchSeg* seg, const int32_t* blk, const double* x, const double* y, double* part);
+__global__ void k_bfinalize(const BatchSeg* seg, const double* part, int mode, double* sc, const int32_t* active);
+__global__ void k_baxpy2(const BatchSeg* seg, const int32_t* blk, const double* sc, const double* p, const double* q,
+                         double* u, double* r, double* part, const double* zold, double* part2);
+__global__ void k_bupdate_p(const BatchSeg* seg, const int32_t* blk, const double* sc, const double* z, double* p);
 __global__ void k_set_u64(unsigned long long* p, unsigned long long v);
 
 constexpr int kMaxSkelSegs = 64;     // row segments of one skeletonized group (2 x 26 in 3D)

@@ -61,9 +61,9 @@ constexpr int64_t kBigSkelElems = 1 << 18;    // M (rows x columns) from which t
 constexpr int kBigCheck = 16;                 // steps between the host's checks for active groups
 
 // Planner state of one problem of a factorization call: scratch, level plans and the
-// host tables of the skeleton apply. Slot p of a call reuses slot p's allocations; the
-// level-0 plan depends on the grid and the leaf size alone (every unknown is active at the
-// leaf level) and is kept for the next factorization of the same geometry in the slot.
+// host tables of the skeleton apply. The sets are kept for reuse (PlanPool); the level-0 plan
+// depends on the grid and the leaf size alone (every unknown is active at the leaf level) and
+// is reused by the next factorization of the same geometry that takes the set.
 struct PlanSet {
     rhif::PlanScratch scr;
     std::vector<rhif::LevelPlan*> plans;
@@ -77,6 +77,57 @@ struct PlanSet {
         while (static_cast<int>(plans.size()) <= lvl) plans.push_back(new rhif::LevelPlan());
         return *plans[lvl];
     }
+};
+
+// The planner states not in use, shared by all host threads: a factorization takes one per
+// problem, preferring one whose level-0 plan is of the problem's geometry, and gives them
+// back when it ends.
+class PlanPool {
+public:
+    static PlanPool& get() {
+        static PlanPool* p = new PlanPool();
+        return *p;
+    }
+    // keys[i] = (dim, side, leaf) of problem i
+    std::vector<PlanSet*> take(const std::vector<std::array<int, 3>>& keys) {
+        std::lock_guard<std::mutex> lk(mu_);
+        std::vector<PlanSet*> out(keys.size(), nullptr);
+        for (size_t i = 0; i < keys.size(); ++i)
+            for (size_t j = 0; j < free_.size(); ++j) {
+                PlanSet* ps = free_[j];
+                if (ps->plan0_ok && ps->plan0_key[0] == keys[i][0] && ps->plan0_key[1] == keys[i][1] &&
+                    ps->plan0_key[2] == keys[i][2]) {
+                    out[i] = ps;
+                    free_.erase(free_.begin() + j);
+                    break;
+                }
+            }
+        for (auto& ps : out) {
+            if (ps) continue;
+            if (!free_.empty()) {
+                ps = free_.back();
+                free_.pop_back();
+            } else {
+                ps = new PlanSet();
+            }
+        }
+        return out;
+    }
+    void give(const std::vector<PlanSet*>& sets) {
+        std::lock_guard<std::mutex> lk(mu_);
+        for (PlanSet* ps : sets)
+            if (ps) free_.push_back(ps);
+    }
+
+private:
+    std::mutex mu_;
+    std::vector<PlanSet*> free_;
+};
+
+// The planner states of one factorization call, given back however the call ends.
+struct PlanLease {
+    std::vector<PlanSet*> sets;
+    ~PlanLease() { PlanPool::get().give(sets); }
 };
 
 // The descriptor tables of one level concatenated over the problems of a factorization
@@ -93,16 +144,10 @@ struct MergedTables {
 
 // Per-thread host state reused across factorizations: pinned staging buffers for the
 // uploads (a ring, each slot fenced by the event of its last copy), a pinned buffer for
-// the small read-backs, the planner states and the merged tables (so that repeated
-// factorizations do not pay for fresh allocations and page faults). Kept for the life of
-// the process.
+// the small read-backs and the merged tables (so that repeated factorizations do not pay
+// for fresh allocations and page faults). Kept for the life of the process.
 struct HostCache {
-    std::vector<PlanSet*> sets;
     MergedTables mt;
-    PlanSet& set(int p) {
-        while (static_cast<int>(sets.size()) <= p) sets.push_back(new PlanSet());
-        return *sets[p];
-    }
     static constexpr int kSlots = 3;
     char* up[kSlots] = {};
     size_t up_bytes[kSlots] = {};
@@ -294,6 +339,7 @@ struct LevelDev {
     int32_t* permd = nullptr;                 // group-local pivot orders of the level's IDs
     int n_grp = 0, mn_grp = 0;
     int tk_cap = 0;               // largest k (n - k) of the level's skeletonized groups, if staged
+    int tk_raw = 0;               // the same, staged or not
     int n_cell_ad = 0, n_sep_ad = 0, n_gather = 0, n_skel_ad = 0;
     size_t lds_cell = 0, lds_sep = 0, lds_skel = 0;
     // largest n_I / n_B of each block family (split apply when n_I is small enough)
@@ -303,6 +349,14 @@ struct LevelDev {
     int64_t bytes = 0;   // device bytes of the factor held for this level
     // ID choices (host)
     std::vector<int32_t> k, perm, first_dof, gsize;
+    // a factorization call with several problems: this problem's share of the level-wide
+    // arrays (element offsets) and host copies of its apply tables, from which the solves
+    // over all the call's problems build their merged tables
+    int64_t o_front = 0, o_ext = 0, o_lg = 0, o_li = 0, o_t = 0, o_g = 0, o_skli = 0;
+    int64_t o_cdofs = 0, o_sepdofs = 0, o_skeldofs = 0, o_perm = 0;
+    std::vector<rhif::ApplyDesc> h_cell_ad, h_sep_ad, h_skel_ad;
+    std::vector<rhif::GatherDesc> h_gat;
+    std::vector<rhif::GroupApplyDesc> h_gad;
 };
 
 void apply_max(const std::vector<rhif::ApplyDesc>& v, int& mi, int& mb) {
@@ -465,6 +519,66 @@ struct Arena {
     }
 };
 
+// Level-wide arrays of one level of a factorization call with several problems (each
+// problem's share lies inside them at the offsets its LevelDev records).
+struct BatchLevelBase {
+    double *front = nullptr, *linv = nullptr, *lg = nullptr, *li = nullptr, *tp = nullptr, *gp = nullptr,
+           *skli = nullptr;
+    int32_t *ext = nullptr, *cdofs = nullptr, *sepdofs = nullptr, *skeldofs = nullptr, *perm = nullptr;
+};
+
+// A merged launch set of apply blocks of several problems, all taking the same kernels.
+struct MFam {
+    const rhif::ApplyDesc* ad = nullptr;
+    int n = 0, mi = 0, mb = 0;
+    size_t lds = 0;
+    bool split = false, band = false;
+    const double* pool = nullptr;
+    const double* lip = nullptr;
+    const double* tp = nullptr;
+    const int32_t* dofs = nullptr;
+    const int32_t* ext = nullptr;
+};
+
+// One level of the merged apply: cell blocks below the root and at the root, and the group
+// blocks (fused per-group kernels, or gather, block Jacobi and skeleton blocks), each family
+// split by the kernels its problems take alone ([0] fused, [1] split solve and product).
+struct MLevel {
+    MFam cells[2], roots[2], seps[2], skels[2];
+    const rhif::GroupApplyDesc* grp = nullptr;
+    int n_grp = 0, mn_grp = 0, tk = 0;
+    const rhif::GatherDesc* gat = nullptr;
+    int n_gat = 0;
+    const BatchLevelBase* b = nullptr;
+};
+
+// The applies and PCG solves over all problems of a factorization call with several problems:
+// one launch per kernel and level over the blocks of all problems, vectors concatenated.
+struct BatchSolve {
+    std::mutex mu;                          // one solve at a time
+    std::vector<rhif_factor_s*> fs;         // the call's handles (an entry is cleared when destroyed)
+    std::vector<BatchLevelBase> base;       // per level
+    std::vector<int64_t> zoff;              // each problem's first unknown in the vectors
+    int64_t ntot = 0;
+    double* ybuf = nullptr;                 // the problems' apply scratch (their shares)
+    double* ws = nullptr;
+    // built at the first solve
+    bool ready = false;
+    bool precond = true;
+    std::vector<MLevel> lev;
+    rhif::BatchSeg* seg = nullptr;
+    int32_t* blk = nullptr;
+    int nblk = 0;
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *u = nullptr, *part = nullptr, *sc = nullptr;
+    int32_t* active = nullptr;
+    double* hsc = nullptr;                  // pinned host copies of the scalars
+    int32_t* hact = nullptr;                // pinned host copy of the active flags
+    ~BatchSolve() {
+        if (hsc) (void)hipHostFree(hsc);
+        if (hact) (void)hipHostFree(hact);
+    }
+};
+
 struct rhif_factor_s {
     rhif::GridInfo g;
     rhif_opts o{};
@@ -493,6 +607,9 @@ struct rhif_factor_s {
 
     rhif_stats_t stats{};
     std::shared_ptr<Arena> arena;   // device memory (shared with the other handles of a batch)
+    std::shared_ptr<BatchSolve> bsolve;   // a call with several problems: their joint solves
+    int bidx = -1;                        // this problem's place in that call
+    int64_t o_ybuf = 0, o_ws = 0;         // its share of the call-wide apply scratch
     // the last work of the handle on every stream it was used on (its memory may be reused
     // once these have completed)
     std::vector<std::pair<hipStream_t, hipEvent_t>> done_ev;
@@ -588,6 +705,11 @@ struct rhif_factor_s {
         pend.clear();
         for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
         evpool.clear();
+        if (bsolve) {
+            std::lock_guard<std::mutex> lk(bsolve->mu);
+            bsolve->fs[bidx] = nullptr;
+        }
+        bsolve.reset();
         arena.reset();
     }
 };
@@ -676,14 +798,16 @@ template <class T>
 T* view(char* base, size_t off) { return reinterpret_cast<T*>(base + off); }
 
 // Copies the packed tables to a new device buffer, asynchronously on the stream.
-char* upload(rhif_factor_s* f, Packer& pk, hipStream_t s) {
-    if (pk.total == 0) return nullptr;
+// extra: bytes of device memory after the tables that the device fills itself.
+char* upload(rhif_factor_s* f, Packer& pk, hipStream_t s, size_t extra = 0) {
+    if (pk.total == 0 && extra == 0) return nullptr;
+    char* dst = static_cast<char*>(f->dalloc(pk.total + extra));
+    if (pk.total == 0) return dst;
     HostCache& hc = host_cache();
     int slot = 0;
     char* h = hc.get_up(pk.total, slot);
     for (size_t e = 0; e < pk.parts.size(); ++e)
         if (pk.parts[e].second) std::memcpy(h + pk.offs[e], pk.parts[e].first, pk.parts[e].second);
-    char* dst = static_cast<char*>(f->dalloc(pk.total));
     HIPCHK(hipMemcpyAsync(dst, h, pk.total, hipMemcpyHostToDevice, s));
     hc.fence(slot, s);
     return dst;
@@ -848,12 +972,18 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, err, ~0ull);
 
     std::vector<Prob> pr(B);
+    PlanLease lease;
+    {
+        std::vector<std::array<int, 3>> keys(B);
+        for (int p = 0; p < B; ++p) keys[p] = {d, fs[p]->g.s, leaf};
+        lease.sets = PlanPool::get().take(keys);
+    }
     int Lmax = 0;
     for (int p = 0; p < B; ++p) {
         rhif_factor_s* f = fs[p];
         Prob& q = pr[p];
         q.f = f;
-        q.ps = &hc.set(p);
+        q.ps = lease.sets[p];
         q.n_active = f->g.N;
         Lmax = std::max(Lmax, f->L);
         f->lev.resize(f->L + 1);
@@ -867,6 +997,17 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
         HIPCHK(hipMemcpyAsync(f->val, in[p].val, f->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
     pool.run(B, [&](int p) { pr[p].ps->scr.reserve(fs[p]->g.N); });
+    // several problems: what their solves over all of them need is kept as the levels go
+    std::shared_ptr<BatchSolve> bs;
+    if (batch) {
+        bs = std::make_shared<BatchSolve>();
+        bs->fs = fs;
+        bs->base.resize(Lmax + 1);
+        for (int p = 0; p < B; ++p) {
+            fs[p]->bsolve = bs;
+            fs[p]->bidx = p;
+        }
+    }
 
     const bool timing = (o.flags & RHIF_FLAG_PHASE_TIMES) != 0;
     auto now = [] { return std::chrono::steady_clock::now(); };
@@ -930,7 +1071,12 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
         }
         LD.n_grp = static_cast<int>(gad.size());
         // T and G's off-diagonal block of a group go through LDS when the largest fit
+        LD.tk_raw = LD.tk_cap;
         if (2 * LD.tk_cap > kGroupStageMax) LD.tk_cap = 0;
+        if (bs) {
+            LD.h_skel_ad = ps.sk_ad;
+            LD.h_gad = gad;
+        }
         LD.n_skel_ad = static_cast<int>(ps.sk_ad.size());
         LD.lds_skel = apply_lds(ps.sk_ad);
         apply_max(ps.sk_ad, LD.mi_skel, LD.mb_skel);
@@ -956,6 +1102,12 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                 LD.skeldofs = view<int32_t>(T, off[i][1]);
                 LD.grp_ad = view<GroupApplyDesc>(T, off[i][2]);
                 LD.permd = view<int32_t>(T, off[i][3]);
+                LD.o_skeldofs = static_cast<int64_t>(off[i][1] / sizeof(int32_t));
+                LD.o_perm = static_cast<int64_t>(off[i][3] / sizeof(int32_t));
+            }
+            if (bs) {
+                BatchLevelBase& b = bs->base[q.pending_skel];
+                b.skeldofs = b.perm = reinterpret_cast<int32_t*>(T);
             }
             q.pending_skel = -1;
         }
@@ -1047,7 +1199,23 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                           pk.add(P.cell_apply), pk.add(P.c_g2), pk.add(P.c_t2)};
             }
             const size_t o_cref = pk.add(mt.cref), o_pot0 = pk.add(mt.pot[0]), o_pot1 = pk.add(mt.pot[1]);
-            char* T = upload(f0, pk, s);
+            // the frontal unknowns the device writes go after the tables, in the same buffer
+            const size_t tail = (pk.total + 255) / 256 * 256;
+            std::vector<size_t> o_dev(na, 0);
+            size_t extra = tail - pk.total;
+            for (int i = 0; i < na; ++i) {
+                const LevelPlan& P = pr[act[i]].ps->plan(lvl);
+                if (!P.dofs_on_device) continue;
+                o_dev[i] = pk.total + extra;
+                extra += static_cast<size_t>(std::max<int64_t>(P.c_dptr[P.ncells], 1)) * sizeof(int32_t);
+            }
+            char* T = upload(f0, pk, s, extra);
+            if (bs) {
+                BatchLevelBase& b = bs->base[lvl];
+                b.front = front;
+                b.ext = ext;
+                b.cdofs = reinterpret_cast<int32_t*>(T);
+            }
             cref_all = view<CellRef>(T, o_cref);
             pot_dev[0] = view<FrontDesc>(T, o_pot0);
             pot_dev[1] = view<FrontDesc>(T, o_pot1);
@@ -1058,9 +1226,9 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                 LevelDev& LD = f->lev[lvl];
                 LD.cg2 = view<int32_t>(T, off[i][5]);
                 LD.ct2 = view<int32_t>(T, off[i][6]);
-                LD.cdofs = P.dofs_on_device ? static_cast<int32_t*>(f0->dalloc(
-                                                  std::max<int64_t>(P.c_dptr[P.ncells], 1) * sizeof(int32_t)))
-                                            : view<int32_t>(T, off[i][0]);
+                const size_t o_cd = P.dofs_on_device ? o_dev[i] : off[i][0];
+                LD.cdofs = view<int32_t>(T, o_cd);
+                LD.o_cdofs = static_cast<int64_t>(o_cd / sizeof(int32_t));
                 LD.cref = view<CellRef>(T, off[i][1]);
                 LD.tiles = view<Tile>(T, off[i][2]);
                 LD.src = P.src_on_device ? static_cast<int32_t*>(f0->dalloc(
@@ -1073,7 +1241,10 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                 LD.b_cell = P.alg_apply_cell_bytes;
                 LD.front = front + q.o_front;
                 LD.ext = ext + q.o_ext;
+                LD.o_front = q.o_front;
+                LD.o_ext = q.o_ext;
                 LD.bytes = P.front_elems * 8 + P.ext_elems * 4;
+                if (bs) LD.h_cell_ad = P.cell_apply;
                 f->y_elems = std::max(f->y_elems, P.y_elems);
                 f->ws_elems = std::max(f->ws_elems, P.ws_elems);
             }
@@ -1122,6 +1293,7 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
         if (!mt.pot[0].empty() || !mt.pot[1].empty()) {
             linv = static_cast<double*>(f0->dalloc(std::max<int64_t>(n_ext, 1) * 256 * sizeof(double)));
             for (int p : act) pr[p].f->lev[lvl].linv = linv + 256 * pr[p].o_ext;
+            if (bs) bs->base[lvl].linv = linv;
         }
         for (int kind = 0; kind < 2; ++kind) {
             const std::vector<FrontDesc>& pot = mt.pot[kind];
@@ -1365,6 +1537,7 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
             const size_t o_sep = pk.add(mt.sep), o_cg = pk.add(mt.cg), o_cs = pk.add(mt.cs), o_skd = pk.add(mt.skd),
                          o_cgp = pk.add(mt.cgptr), o_cgl = pk.add(mt.cgl), o_cgo = pk.add(mt.cgoff);
             char* T = upload_side(f0, pk, s);
+            if (bs) bs->base[lvl].sepdofs = reinterpret_cast<int32_t*>(T);
             sep_all = view<SepDesc>(T, o_sep);
             cg_all = view<CellGroup>(T, o_cg);
             cs_all = view<CellScaleDesc>(T, o_cs);
@@ -1379,6 +1552,11 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                 LD.sep_ad = view<ApplyDesc>(T, off[i][0]);
                 LD.gat = view<GatherDesc>(T, off[i][1]);
                 LD.sepdofs = view<int32_t>(T, off[i][2]);
+                LD.o_sepdofs = static_cast<int64_t>(off[i][2] / sizeof(int32_t));
+                if (bs) {
+                    LD.h_sep_ad = P.sep_apply;
+                    LD.h_gat = P.gather;
+                }
                 LD.gslot_cnt = view<int32_t>(T, off[i][3]);
                 LD.gslot_cell = view<int32_t>(T, off[i][4]);
                 LD.gslot_off = view<int32_t>(T, off[i][5]);
@@ -1402,7 +1580,18 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
             LD.lg = lg + q.o_lg;
             LD.tp = tp + q.o_t;
             LD.gp = gp + q.o_g;
+            LD.o_lg = q.o_lg;
+            LD.o_t = q.o_t;
+            LD.o_g = q.o_g;
+            LD.o_li = q.o_li;
+            LD.o_skli = q.o_skli;
             LD.bytes += (P.lg_elems + P.t_elems + P.g_elems) * 8;
+        }
+        if (bs) {
+            BatchLevelBase& b = bs->base[lvl];
+            b.lg = lg;
+            b.tp = tp;
+            b.gp = gp;
         }
         if (n_m > mp_elems) {
             mp = static_cast<double*>(f0->dalloc(n_m * sizeof(double)));
@@ -1431,6 +1620,7 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
             const int cap = panel_cap_for(max_sep_n, 0);
             double* li = static_cast<double*>(f0->dalloc(std::max<int64_t>(n_li, 1) * sizeof(double)));
             for (int p : nonroot) pr[p].f->lev[lvl].li = li + pr[p].o_li;
+            if (bs) bs->base[lvl].li = li;
             // L_g is factored in LDS when the largest group fits
             const int nm = max_sep_n;
             const bool gstage = (o.flags & RHIF_FLAG_GLOBAL_STAGING) != 0;
@@ -1494,6 +1684,7 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
             }
             double* skli = static_cast<double*>(f0->dalloc(std::max<int64_t>(n_skli, 1) * sizeof(double)));
             for (int p : nonroot) pr[p].f->lev[lvl].skli = skli + pr[p].o_skli;
+            if (bs) bs->base[lvl].skli = skli;
             // groups whose M is too large for LDS and has many rows (the upper 3D levels): the
             // ID spread over row blocks of kBigRowsHost rows, one launch per step for all groups
             const bool big = (o.flags & RHIF_FLAG_SKEL_MULTI) ||
@@ -1612,13 +1803,34 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
     }
     // every problem finished its last skeleton tables at its root level
     check_err(err, batch, s);
+    if (bs) {
+        // the problems' apply scratch in two call-wide arrays, each problem's vector at its
+        // place in the concatenated vectors of the solves over all of them
+        int64_t ny = 0, nw = 0;
+        bs->zoff.resize(B);
+        for (int p = 0; p < B; ++p) {
+            bs->zoff[p] = bs->ntot;
+            bs->ntot += fs[p]->g.N;
+            fs[p]->o_ybuf = ny;
+            fs[p]->o_ws = nw;
+            ny += std::max<int64_t>(fs[p]->y_elems, 1);
+            nw += fs[p]->ws_elems;
+        }
+        bs->ybuf = static_cast<double*>(f0->dalloc(ny * sizeof(double)));
+        bs->ws = nw > 0 ? static_cast<double*>(f0->dalloc(nw * sizeof(double))) : nullptr;
+    }
     for (Prob& q : pr) {
         rhif_factor_s* f = q.f;
         f->stats.levels = f->L;
         f->stats.root_size = static_cast<int32_t>(q.n_active);
         f->stats.n_active[f->L] = q.n_active;
-        f->ybuf = static_cast<double*>(f->dalloc(std::max<int64_t>(f->y_elems, 1) * sizeof(double)));
-        if (f->ws_elems > 0) f->ws = static_cast<double*>(f->dalloc(f->ws_elems * sizeof(double)));
+        if (bs) {
+            f->ybuf = bs->ybuf + f->o_ybuf;
+            if (f->ws_elems > 0) f->ws = bs->ws + f->o_ws;
+        } else {
+            f->ybuf = static_cast<double*>(f->dalloc(std::max<int64_t>(f->y_elems, 1) * sizeof(double)));
+            if (f->ws_elems > 0) f->ws = static_cast<double*>(f->dalloc(f->ws_elems * sizeof(double)));
+        }
         int64_t bytes = 0;
         for (const auto& LD : f->lev) bytes += LD.bytes;
         f->stats.factor_bytes = bytes;
@@ -2138,6 +2350,365 @@ void pcg_run(rhif_factor_s* f, const PcgWs& w, const double* rhs, double* u, dou
     if (!conv) fail(RHIF_ENOCONV, "PCG did not reach the tolerance within maxit iterations");
 }
 
+// ---------------------------------------------------------------------------------------
+// Solves over all problems of a factorization call with several problems. The apply of
+// eq. (3.2) runs level by level over the blocks of every problem in one launch per kernel;
+// each block carries its problem's place in the concatenated vectors, and the problems of a
+// family are split by the kernels they take alone, so that every block is computed as in its
+// own problem's apply. The PCG's vector kernels give every problem its own scalars and the
+// partial sums of its lone grid, so that each problem's iterates are those of its own solve.
+// ---------------------------------------------------------------------------------------
+
+// The merged tables, the vector segments and the workspace, at the first solve.
+void batch_prepare(BatchSolve& b, hipStream_t s) {
+    using namespace rhif;
+    if (b.ready) return;
+    rhif_factor_s* f0 = nullptr;
+    int Lmax = 0;
+    for (rhif_factor_s* f : b.fs) {
+        if (!f) fail(RHIF_EINVAL, "a handle of the factorization call has been destroyed");
+        if (!f0) f0 = f;
+        Lmax = std::max(Lmax, f->L);
+    }
+    const int B = static_cast<int>(b.fs.size());
+    const bool precond = f0->o.precond != 0;
+    b.precond = precond;
+    // merged tables, [level][family][fused / split]
+    struct Fam {
+        std::vector<ApplyDesc> ad;
+        int mi = 0, mb = 0;
+        size_t lds = 0;
+        int band = -1;
+    };
+    std::vector<std::array<std::array<Fam, 2>, 4>> fam(Lmax + 1);
+    std::vector<std::vector<GroupApplyDesc>> grp(Lmax + 1);
+    std::vector<std::vector<GatherDesc>> gat(Lmax + 1);
+    b.lev.assign(Lmax + 1, MLevel{});
+    auto add = [&](Fam& F, const std::vector<ApplyDesc>& src, int64_t o_pool, int64_t o_li, int64_t o_t,
+                   int64_t o_dofs, int64_t o_ext, int64_t o_y, int64_t o_w, int64_t zo, int mi, int mb, size_t lds,
+                   bool band) {
+        for (ApplyDesc a : src) {
+            a.off += o_pool;
+            if (a.toff >= 0) a.toff += o_t;
+            if (a.yoff >= 0) a.yoff += o_y;
+            if (a.wsoff >= 0) a.wsoff += o_w;
+            a.dofs += static_cast<int32_t>(o_dofs);
+            if (a.ext >= 0) a.ext += static_cast<int32_t>(o_ext);
+            a.li += static_cast<int32_t>(o_li);
+            a.zoff = zo;
+            F.ad.push_back(a);
+        }
+        F.mi = std::max(F.mi, mi);
+        F.mb = std::max(F.mb, mb);
+        F.lds = std::max(F.lds, lds);
+        if (F.band < 0) F.band = band ? 1 : 0;
+        else if (F.band != (band ? 1 : 0)) fail(RHIF_EINVAL, "internal error: mixed banded and full cell blocks");
+    };
+    std::vector<int> tkr(Lmax + 1, 0);
+    for (int p = 0; p < B; ++p) {
+        rhif_factor_s* f = b.fs[p];
+        const int64_t zo = b.zoff[p];
+        for (int lvl = 0; lvl <= f->L; ++lvl) {
+            const LevelDev& LD = f->lev[lvl];
+            const bool root = lvl == f->L;
+            const int sp = split_ok(LD.mi_cell, LD.mb_cell, LD.linv) ? 1 : 0;
+            add(fam[lvl][root ? 1 : 0][sp], LD.h_cell_ad, LD.o_front, 256 * LD.o_ext, 0, LD.o_cdofs, LD.o_ext,
+                f->o_ybuf, f->o_ws, zo, LD.mi_cell, LD.mb_cell, LD.lds_cell, LD.leaf_banded);
+            if (root) continue;
+            if (group_ok(LD)) {
+                for (GroupApplyDesc x : LD.h_gad) {
+                    x.dofs += static_cast<int32_t>(LD.o_sepdofs);
+                    for (int sl = 0; sl < x.nslot; ++sl) x.yoff[sl] += f->o_ybuf;
+                    x.loff += LD.o_lg;
+                    x.li += static_cast<int32_t>(LD.o_li);
+                    x.poff += static_cast<int32_t>(LD.o_perm);
+                    x.goff += LD.o_g;
+                    x.toff += LD.o_t;
+                    x.skli += static_cast<int32_t>(LD.o_skli);
+                    x.zoff = zo;
+                    grp[lvl].push_back(x);
+                }
+                MLevel& M = b.lev[lvl];
+                M.mn_grp = std::max(M.mn_grp, LD.mn_grp);
+                tkr[lvl] = std::max(tkr[lvl], LD.tk_raw);
+            } else {
+                for (GatherDesc g : LD.h_gat) {
+                    g.dofs += static_cast<int32_t>(LD.o_sepdofs);
+                    for (int sl = 0; sl < g.nslot; ++sl) g.yoff[sl] += f->o_ybuf;
+                    g.zoff = zo;
+                    gat[lvl].push_back(g);
+                }
+                if (precond)
+                    add(fam[lvl][2][split_ok(LD.mi_sep, 0, LD.li) ? 1 : 0], LD.h_sep_ad, LD.o_lg, LD.o_li, 0,
+                        LD.o_sepdofs, 0, f->o_ybuf, f->o_ws, zo, LD.mi_sep, 0, LD.lds_sep, false);
+                add(fam[lvl][3][split_ok(LD.mi_skel, LD.mb_skel, LD.skli) ? 1 : 0], LD.h_skel_ad, LD.o_g, LD.o_skli,
+                    LD.o_t, LD.o_skeldofs, 0, f->o_ybuf, f->o_ws, zo, LD.mi_skel, LD.mb_skel, LD.lds_skel, false);
+            }
+        }
+    }
+    // one upload of every merged table
+    Packer pk;
+    std::vector<std::array<std::array<size_t, 2>, 4>> off(Lmax + 1);
+    std::vector<size_t> o_grp(Lmax + 1), o_gat(Lmax + 1);
+    for (int lvl = 0; lvl <= Lmax; ++lvl) {
+        for (int k = 0; k < 4; ++k)
+            for (int sp = 0; sp < 2; ++sp) off[lvl][k][sp] = pk.add(fam[lvl][k][sp].ad);
+        o_grp[lvl] = pk.add(grp[lvl]);
+        o_gat[lvl] = pk.add(gat[lvl]);
+    }
+    // vector segments: each problem's blocks as its lone solve lays them out
+    std::vector<BatchSeg> seg(B);
+    std::vector<int32_t> blk;
+    for (int p = 0; p < B; ++p) {
+        rhif_factor_s* f = b.fs[p];
+        BatchSeg& g = seg[p];
+        g.rp = f->rp;
+        g.ci = f->ci;
+        g.val = f->val;
+        g.zoff = b.zoff[p];
+        g.n = f->g.N;
+        g.b0 = static_cast<int32_t>(blk.size());
+        g.nb = grid_for(f->g.N);
+        for (int e = 0; e < g.nb; ++e) blk.push_back(p);
+    }
+    const size_t o_seg = pk.add(seg), o_blk = pk.add(blk);
+    char* T = upload(f0, pk, s);
+    for (int lvl = 0; lvl <= Lmax; ++lvl) {
+        MLevel& M = b.lev[lvl];
+        M.b = &b.base[lvl];
+        const BatchLevelBase& bb = b.base[lvl];
+        MFam* dst[4] = {M.cells, M.roots, M.seps, M.skels};
+        for (int k = 0; k < 4; ++k)
+            for (int sp = 0; sp < 2; ++sp) {
+                const Fam& F = fam[lvl][k][sp];
+                MFam& m = dst[k][sp];
+                m.n = static_cast<int>(F.ad.size());
+                if (m.n == 0) continue;
+                m.ad = view<ApplyDesc>(T, off[lvl][k][sp]);
+                m.mi = F.mi;
+                m.mb = F.mb;
+                m.lds = F.lds;
+                m.split = sp == 1;
+                m.band = F.band == 1;
+                if (k < 2) {
+                    m.pool = bb.front;
+                    m.lip = bb.linv;
+                    m.dofs = bb.cdofs;
+                    m.ext = bb.ext;
+                } else if (k == 2) {
+                    m.pool = bb.lg;
+                    m.lip = bb.li;
+                    m.dofs = bb.sepdofs;
+                } else {
+                    m.pool = bb.gp;
+                    m.lip = bb.skli;
+                    m.tp = bb.tp;
+                    m.dofs = bb.skeldofs;
+                }
+                // a split set whose largest blocks together overflow the split kernels' LDS:
+                // never the case for the blocks this library makes; refuse rather than guess
+                if (m.split && !split_ok(m.mi, m.mb, m.lip))
+                    fail(RHIF_EINVAL, "internal error: merged split apply blocks exceed the LDS");
+            }
+        M.n_grp = static_cast<int>(grp[lvl].size());
+        if (M.n_grp > 0) M.grp = view<GroupApplyDesc>(T, o_grp[lvl]);
+        // T and G's off-diagonal blocks through LDS when the level's largest fit (as alone)
+        M.tk = 2 * tkr[lvl] > kGroupStageMax ? 0 : tkr[lvl];
+        M.n_gat = static_cast<int>(gat[lvl].size());
+        if (M.n_gat > 0) M.gat = view<GatherDesc>(T, o_gat[lvl]);
+    }
+    b.seg = view<BatchSeg>(T, o_seg);
+    b.blk = view<int32_t>(T, o_blk);
+    b.nblk = static_cast<int>(blk.size());
+    const size_t vb = static_cast<size_t>(std::max<int64_t>(b.ntot, 1)) * sizeof(double);
+    b.r = static_cast<double*>(f0->dalloc(vb));
+    b.z = static_cast<double*>(f0->dalloc(vb));
+    b.p = static_cast<double*>(f0->dalloc(vb));
+    b.q = static_cast<double*>(f0->dalloc(vb));
+    b.u = static_cast<double*>(f0->dalloc(vb));
+    b.part = static_cast<double*>(f0->dalloc(2 * static_cast<size_t>(b.nblk) * sizeof(double)));
+    b.sc = static_cast<double*>(f0->dalloc(16 * static_cast<size_t>(B) * sizeof(double)));
+    b.active = static_cast<int32_t*>(f0->dalloc(static_cast<size_t>(B) * sizeof(int32_t)));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&b.hsc), 16 * static_cast<size_t>(B) * sizeof(double),
+                         hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&b.hact), static_cast<size_t>(B) * sizeof(int32_t),
+                         hipHostMallocDefault));
+    b.ready = true;
+}
+
+void mfam_up(const MFam& m, double* z, double* ybuf, double* ws, hipStream_t s) {
+    if (m.n <= 0) return;
+    if (!m.split) {
+        hipLaunchKernelGGL(rhif::k_apply_up, dim3(m.n), dim3(256), m.lds, s, m.ad, m.pool, m.tp, m.dofs, z, ybuf, ws,
+                           m.ext);
+        return;
+    }
+    if (m.band)
+        hipLaunchKernelGGL(rhif::k_apply_band<true>, dim3(m.n), dim3(256), band_lds(m.mi), s, m.ad, m.pool, m.lip,
+                           m.dofs, z);
+    else
+        hipLaunchKernelGGL(rhif::k_apply_trsv_up, dim3(m.n), dim3(256), trsv_lds(m.mi, m.mb), s, m.ad, m.pool, m.lip,
+                           m.tp, m.dofs, z, m.ext);
+    if (m.mb > 0)
+        hipLaunchKernelGGL(rhif::k_apply_gemv_up, dim3(m.n, (m.mb + 63) / 64), dim3(256),
+                           static_cast<size_t>(m.mi + 256) * sizeof(double), s, m.ad, m.pool, m.dofs, z, ybuf);
+}
+
+void mfam_down(const MFam& m, double* z, double* ws, hipStream_t s) {
+    if (m.n <= 0) return;
+    if (!m.split) {
+        hipLaunchKernelGGL(rhif::k_apply_down, dim3(m.n), dim3(256), m.lds, s, m.ad, m.pool, m.tp, m.dofs, z, ws,
+                           m.ext);
+        return;
+    }
+    if (m.mb > 0)
+        hipLaunchKernelGGL(rhif::k_apply_gemv_dn, dim3(m.n, (m.mi + 63) / 64), dim3(256),
+                           static_cast<size_t>(64 * 65 + m.mb + 256) * sizeof(double), s, m.ad, m.pool, m.dofs, z);
+    if (m.band)
+        hipLaunchKernelGGL(rhif::k_apply_band<false>, dim3(m.n), dim3(256), band_lds(m.mi), s, m.ad, m.pool, m.lip,
+                           m.dofs, z);
+    else
+        hipLaunchKernelGGL(rhif::k_apply_trsv_dn, dim3(m.n), dim3(256), trsv_lds(m.mi, m.mb), s, m.ad, m.pool, m.lip,
+                           m.tp, m.dofs, z, m.ext);
+}
+
+// z <- F^-1 z for every problem at once (z: the concatenated vectors).
+void batch_apply(BatchSolve& b, double* z, hipStream_t s) {
+    const int Lmax = static_cast<int>(b.lev.size()) - 1;
+    const bool precond = b.precond;
+    for (int lvl = 0; lvl <= Lmax; ++lvl) {
+        const MLevel& M = b.lev[lvl];
+        const BatchLevelBase& bb = *M.b;
+        for (int sp = 0; sp < 2; ++sp) mfam_up(M.cells[sp], z, b.ybuf, b.ws, s);
+        if (M.n_grp > 0)
+            hipLaunchKernelGGL(rhif::k_apply_group_up, dim3(M.n_grp), dim3(256),
+                               static_cast<size_t>(2 * 16 * ((M.mn_grp + 15) / 16) + 2 * M.tk) * sizeof(double), s,
+                               M.grp, bb.sepdofs, b.ybuf, z, bb.lg, bb.li, bb.gp, bb.tp, bb.skli, bb.perm, M.tk);
+        if (M.n_gat > 0)
+            hipLaunchKernelGGL(rhif::k_sep_gather, dim3(M.n_gat), dim3(256), 0, s, M.gat, bb.sepdofs, b.ybuf, z);
+        if (precond)
+            for (int sp = 0; sp < 2; ++sp) mfam_up(M.seps[sp], z, nullptr, b.ws, s);
+        for (int sp = 0; sp < 2; ++sp) mfam_up(M.skels[sp], z, nullptr, b.ws, s);
+        for (int sp = 0; sp < 2; ++sp) mfam_up(M.roots[sp], z, b.ybuf, b.ws, s);
+    }
+    for (int lvl = Lmax; lvl >= 0; --lvl) {
+        const MLevel& M = b.lev[lvl];
+        const BatchLevelBase& bb = *M.b;
+        for (int sp = 0; sp < 2; ++sp) mfam_down(M.roots[sp], z, b.ws, s);
+        if (M.n_grp > 0)
+            hipLaunchKernelGGL(rhif::k_apply_group_dn, dim3(M.n_grp), dim3(256),
+                               static_cast<size_t>(2 * 16 * ((M.mn_grp + 15) / 16) + 2 * M.tk) * sizeof(double), s,
+                               M.grp, bb.sepdofs, z, bb.lg, bb.li, bb.gp, bb.tp, bb.skli, bb.perm, M.tk);
+        for (int sp = 0; sp < 2; ++sp) mfam_down(M.skels[sp], z, b.ws, s);
+        if (precond)
+            for (int sp = 0; sp < 2; ++sp) mfam_down(M.seps[sp], z, b.ws, s);
+        for (int sp = 0; sp < 2; ++sp) mfam_down(M.cells[sp], z, b.ws, s);
+    }
+    HIPCHK(hipGetLastError());
+}
+
+// The handles of one factorization call with several problems, all of them, in the call's
+// order; returns its joint solve state, locked.
+BatchSolve& batch_of(int32_t count, const rhif_factor_t* hs, std::unique_lock<std::mutex>& lk) {
+    if (count < 2 || !hs) fail(RHIF_EINVAL, "count must be >= 2 and handles not NULL");
+    for (int32_t i = 0; i < count; ++i)
+        if (!hs[i]) fail(RHIF_EINVAL, "NULL handle");
+    BatchSolve* b = hs[0]->bsolve.get();
+    if (!b) fail(RHIF_EINVAL, "the handles do not come from one rhif_factor_batch call with several problems");
+    lk = std::unique_lock<std::mutex>(b->mu);
+    if (static_cast<int32_t>(b->fs.size()) != count)
+        fail(RHIF_EINVAL, "pass every handle of the rhif_factor_batch call, in its order");
+    for (int32_t i = 0; i < count; ++i)
+        if (b->fs[i] != hs[i]) fail(RHIF_EINVAL, "pass every handle of the rhif_factor_batch call, in its order");
+    return *b;
+}
+
+// PCG over every problem at once: each problem takes the iterations of its own rhif_pcg_solve
+// (same kernels' arithmetic, same partial sums) and stops at its own convergence; the loop ends
+// when all have converged or after maxit iterations.
+void batch_pcg(BatchSolve& b, const double* const* rhs, double* const* u, double rtol, int32_t maxit,
+               int32_t* iters, double* relres, hipStream_t s) {
+    using namespace rhif;
+    const int B = static_cast<int>(b.fs.size());
+    const bool flex = b.fs[0]->o.precision >= 1;
+    const int nb = b.nblk;
+    const int64_t Nt = b.ntot;
+    const int gt = grid_for(Nt);
+    // r = f, u = 0, ||f||^2
+    for (int p = 0; p < B; ++p)
+        HIPCHK(hipMemcpyAsync(b.r + b.zoff[p], rhs[p], b.fs[p]->g.N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    std::vector<int32_t> act(B, 1);
+    for (int p = 0; p < B; ++p) b.hact[p] = 1;
+    HIPCHK(hipMemcpyAsync(b.active, b.hact, B * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_fill, dim3(gt), dim3(256), 0, s, Nt, 0.0, b.u);
+    hipLaunchKernelGGL(k_bdot, dim3(nb), dim3(256), 0, s, b.seg, b.blk, b.r, b.r, b.part);
+    hipLaunchKernelGGL(k_bfinalize, dim3(B), dim3(256), 0, s, b.seg, b.part, 0, b.sc, b.active);
+    // z = F^-1 r, rho = r.z, p = z
+    hipLaunchKernelGGL(k_copy, dim3(gt), dim3(256), 0, s, Nt, b.r, b.z);
+    batch_apply(b, b.z, s);
+    hipLaunchKernelGGL(k_bdot, dim3(nb), dim3(256), 0, s, b.seg, b.blk, b.r, b.z, b.part);
+    hipLaunchKernelGGL(k_bfinalize, dim3(B), dim3(256), 0, s, b.seg, b.part, 3, b.sc, b.active);
+    hipLaunchKernelGGL(k_copy, dim3(gt), dim3(256), 0, s, Nt, b.z, b.p);
+    HIPCHK(hipMemcpyAsync(b.hsc, b.sc, 16 * B * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<double> fnorm(B);
+    int nact = 0;
+    for (int p = 0; p < B; ++p) {
+        const double ff = b.hsc[16 * p + 6];
+        fnorm[p] = std::sqrt(ff);
+        iters[p] = 0;
+        relres[p] = 0.0;
+        if (ff == 0.0) act[p] = 0;
+        nact += act[p];
+    }
+    bool changed = nact < B;
+    int it = 0;
+    while (nact > 0 && it < maxit) {
+        if (changed) {
+            for (int p = 0; p < B; ++p) b.hact[p] = act[p];
+            HIPCHK(hipMemcpyAsync(b.active, b.hact, B * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            changed = false;
+        }
+        // q = A p; alpha; u += alpha p, r -= alpha q; |r|^2
+        hipLaunchKernelGGL(k_bspmv_dot, dim3(nb), dim3(256), 0, s, b.seg, b.blk, b.p, b.q, b.part);
+        hipLaunchKernelGGL(k_bfinalize, dim3(B), dim3(256), 0, s, b.seg, b.part, 1, b.sc, b.active);
+        hipLaunchKernelGGL(k_baxpy2, dim3(nb), dim3(256), 0, s, b.seg, b.blk, b.sc, b.p, b.q, b.u, b.r, b.part,
+                           flex ? b.z : nullptr, b.part + nb);
+        hipLaunchKernelGGL(k_bfinalize, dim3(B), dim3(256), 0, s, b.seg, b.part, 2, b.sc, b.active);
+        if (flex) hipLaunchKernelGGL(k_bfinalize, dim3(B), dim3(256), 0, s, b.seg, b.part + nb, 5, b.sc, b.active);
+        HIPCHK(hipMemcpyAsync(b.hsc, b.sc, 16 * B * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        ++it;
+        for (int p = 0; p < B; ++p) {
+            if (!act[p]) continue;
+            iters[p] = it;
+            relres[p] = std::sqrt(b.hsc[16 * p + 3]) / fnorm[p];
+            if (relres[p] <= rtol) {
+                act[p] = 0;
+                --nact;
+                changed = true;
+            }
+        }
+        if (nact == 0 || it >= maxit) break;
+        if (changed) {
+            for (int p = 0; p < B; ++p) b.hact[p] = act[p];
+            HIPCHK(hipMemcpyAsync(b.active, b.hact, B * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            changed = false;
+        }
+        // z = F^-1 r; rho = r.z; beta; p = z + beta p
+        hipLaunchKernelGGL(k_copy, dim3(gt), dim3(256), 0, s, Nt, b.r, b.z);
+        batch_apply(b, b.z, s);
+        hipLaunchKernelGGL(k_bdot, dim3(nb), dim3(256), 0, s, b.seg, b.blk, b.r, b.z, b.part);
+        hipLaunchKernelGGL(k_bfinalize, dim3(B), dim3(256), 0, s, b.seg, b.part, flex ? 6 : 4, b.sc, b.active);
+        hipLaunchKernelGGL(k_bupdate_p, dim3(nb), dim3(256), 0, s, b.seg, b.blk, b.sc, b.z, b.p);
+    }
+    for (int p = 0; p < B; ++p)
+        HIPCHK(hipMemcpyAsync(u[p], b.u + b.zoff[p], b.fs[p]->g.N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipGetLastError());
+    for (rhif_factor_s* f : b.fs) f->mark(s);
+    if (nact > 0) fail(RHIF_ENOCONV, "PCG did not reach the tolerance within maxit iterations for every problem");
+}
+
 
 }  // namespace
 
@@ -2181,26 +2752,8 @@ rhif_status rhif_assemble_fd(const rhif_grid* g, const double* a_cells, const do
     const int d = g->dim, sd = g->n[0];
     int64_t N = 1;
     for (int k = 0; k < d; ++k) N *= sd;
-    std::vector<int32_t> rp(N + 1);
-    rp[0] = 0;
-    for (int64_t i = 0; i < N; ++i) {
-        int64_t r = i;
-        int cnt = 1;
-        for (int k = 0; k < d; ++k) {
-            const int x = static_cast<int>(r % sd) + 1;
-            r /= sd;
-            cnt += (x > 1) + (x < sd);
-        }
-        rp[i + 1] = rp[i] + cnt;
-    }
-    {
-        HostCache& hc = host_cache();
-        int slot = 0;
-        char* h = hc.get_up((N + 1) * sizeof(int32_t), slot);
-        std::memcpy(h, rp.data(), (N + 1) * sizeof(int32_t));
-        HIPCHK(hipMemcpyAsync(row_ptr, h, (N + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        hc.fence(slot, s);
-    }
+    hipLaunchKernelGGL(rhif::k_fd_rowptr, dim3(static_cast<int>(std::min<int64_t>(N / 256 + 1, 65535))), dim3(256), 0,
+                       s, d, sd, row_ptr);
     const double h = 1.0 / (sd + 1);
     const double inv_h2 = 1.0 / (h * h);
     const int grid = static_cast<int>(std::min<int64_t>((N + 255) / 256, 65535));
@@ -2324,6 +2877,38 @@ rhif_status rhif_apply(rhif_factor_t f, const double* r, double* z, int32_t nrhs
         HIPCHK(hipStreamSynchronize(s));
         f->resolve_graph(0);
     }
+    API_END
+}
+
+rhif_status rhif_apply_batch(int32_t count, const rhif_factor_t* f, const double* const* r, double* const* z,
+                             hipStream_t s) {
+    API_BEGIN
+    std::unique_lock<std::mutex> lk;
+    BatchSolve& b = batch_of(count, f, lk);
+    if (!r || !z) fail(RHIF_EINVAL, "NULL vector array");
+    for (int32_t i = 0; i < count; ++i)
+        if (!r[i] || !z[i]) fail(RHIF_EINVAL, "NULL vector");
+    batch_prepare(b, s);
+    for (int32_t i = 0; i < count; ++i)
+        HIPCHK(hipMemcpyAsync(b.z + b.zoff[i], r[i], f[i]->g.N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    batch_apply(b, b.z, s);
+    for (int32_t i = 0; i < count; ++i)
+        HIPCHK(hipMemcpyAsync(z[i], b.z + b.zoff[i], f[i]->g.N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    for (int32_t i = 0; i < count; ++i) f[i]->mark(s);
+    API_END
+}
+
+rhif_status rhif_pcg_solve_batch(int32_t count, const rhif_factor_t* f, const double* const* rhs, double* const* u,
+                                 double rtol, int32_t maxit, int32_t* iters, double* relres, hipStream_t s) {
+    API_BEGIN
+    std::unique_lock<std::mutex> lk;
+    BatchSolve& b = batch_of(count, f, lk);
+    if (!rhs || !u || !iters || !relres) fail(RHIF_EINVAL, "NULL argument");
+    for (int32_t i = 0; i < count; ++i)
+        if (!rhs[i] || !u[i]) fail(RHIF_EINVAL, "NULL vector");
+    if (maxit < 0 || !(rtol >= 0.0)) fail(RHIF_EINVAL, "bad maxit or rtol");
+    batch_prepare(b, s);
+    batch_pcg(b, rhs, u, rtol, maxit, iters, relres, s);
     API_END
 }
 

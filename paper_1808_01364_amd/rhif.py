@@ -32,6 +32,7 @@ KCLASS_NAMES = ["front_csr", "front_extend", "elim_leaf", "elim_upper", "root", 
 
 # every function declared in include/rhif.h
 EXPORTED = ["rhif_fd_nnz", "rhif_assemble_fd", "rhif_factor", "rhif_factor_batch", "rhif_apply", "rhif_pcg_solve",
+            "rhif_apply_batch", "rhif_pcg_solve_batch",
             "rhif_pcg_solve_noalloc", "rhif_apply_half", "rhif_estimate_es",
             "rhif_apply_forward", "rhif_estimate_ea", "rhif_matvec", "rhif_grad_log_a", "rhif_stats", "rhif_skeletons", "rhif_destroy",
             "rhif_last_error", "rhif_version"]
@@ -103,6 +104,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                       ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
                                       ctypes.POINTER(vp)]
     lib.rhif_apply.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
+    lib.rhif_apply_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    lib.rhif_pcg_solve_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                         ctypes.c_double, ctypes.c_int32, c_i32p, ctypes.POINTER(ctypes.c_double), vp]
     lib.rhif_pcg_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int32, c_i32p,
                                    ctypes.POINTER(ctypes.c_double), vp]
     lib.rhif_pcg_solve_noalloc.argtypes = lib.rhif_pcg_solve.argtypes
@@ -426,6 +430,52 @@ def factor_batch(problems, leaf: int, eps: float, precond: int = 1, precision: i
     hs = (ctypes.c_void_p * count)()
     _check(lib.rhif_factor_batch(count, grids, ctypes.byref(o), rps, cols, vals, _stream(stream), hs))
     return [Factor._adopt(dim, n, ctypes.c_void_p(hs[i])) for i, (dim, n, _) in enumerate(problems)]
+
+
+def _batch_handles(factors):
+    hs = (ctypes.c_void_p * len(factors))()
+    for i, F in enumerate(factors):
+        hs[i] = F.handle.value
+    return hs
+
+
+def apply_batch(factors, rs, out=None, stream=None):
+    """[F_i^-1 r_i] for the factors of one factor_batch call (all of them, in order), in one
+    joint apply (rhif_apply_batch)."""
+    if len(rs) != len(factors):
+        raise ValueError("one right-hand side per factor")
+    _need(*[(r, f"r[{i}]", F.N) for i, (F, r) in enumerate(zip(factors, rs))])
+    torch = _torch()
+    zs = out if out is not None else [torch.empty_like(r) for r in rs]
+    _need(*[(z, f"out[{i}]", F.N) for i, (F, z) in enumerate(zip(factors, zs))])
+    n = len(factors)
+    rp, zp = (ctypes.c_void_p * n)(*[_ptr(r) for r in rs]), (ctypes.c_void_p * n)(*[_ptr(z) for z in zs])
+    _check(load_library().rhif_apply_batch(n, _batch_handles(factors), rp, zp, _stream(stream)))
+    return zs
+
+
+def pcg_batch(factors, fs, rtol: float = 1e-12, maxit: int = 500, out=None, stream=None,
+              raise_on_noconv: bool = True):
+    """[(u_i, iterations_i, relative residual_i)] of A_i u_i = f_i for the factors of one
+    factor_batch call (all of them, in order), solved together (rhif_pcg_solve_batch)."""
+    if len(fs) != len(factors):
+        raise ValueError("one right-hand side per factor")
+    _need(*[(f, f"f[{i}]", F.N) for i, (F, f) in enumerate(zip(factors, fs))])
+    torch = _torch()
+    us = out if out is not None else [torch.empty_like(f) for f in fs]
+    _need(*[(u, f"out[{i}]", F.N) for i, (F, u) in enumerate(zip(factors, us))])
+    n = len(factors)
+    fp, up = (ctypes.c_void_p * n)(*[_ptr(f) for f in fs]), (ctypes.c_void_p * n)(*[_ptr(u) for u in us])
+    it = (ctypes.c_int32 * n)()
+    rel = (ctypes.c_double * n)()
+    lib = load_library()
+    st = lib.rhif_pcg_solve_batch(n, _batch_handles(factors), fp, up, rtol, maxit, it, rel, _stream(stream))
+    if st == RHIF_ENOCONV:
+        if raise_on_noconv:
+            raise NoConvergence(st, lib.rhif_last_error().decode(), list(it), list(rel))
+    else:
+        _check(st)
+    return [(u, it[i], rel[i]) for i, u in enumerate(us)]
 
 
 def version() -> str:
