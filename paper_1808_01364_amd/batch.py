@@ -157,9 +157,11 @@ def _signature(items):
     return tuple(sorted((k, (v + 3) // 4) for k, v in mix.items()))
 
 
-def autotune(items, sample: int = 16, rtol: float = 1e-12, maxit: int = 500, verbose: bool = False):
+def autotune(items, sample: int = 64, rtol: float = 1e-12, maxit: int = 500, verbose: bool = False):
     """Pick (nstreams, order, group) for this batch. Every candidate solves the same sample of the
-    batch (every len/sample-th problem) after one warm-up pass, and the highest DOFs/s wins: first
+    batch (every len/sample-th problem; the whole batch up to `sample` problems, since the group
+    sizes and stream counts only show their effect on as many problems as they spread over)
+    after one warm-up pass, and the highest DOFs/s wins: first
     (nstreams, order) with one problem per factorization call, then (group, nstreams) with
     that order. The choice is remembered for batches with the same size mix."""
     import torch
