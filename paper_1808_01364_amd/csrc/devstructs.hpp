@@ -121,6 +121,12 @@ struct ApplyDesc {
     int64_t zoff;        // offset of the block's problem in the vector (several problems at once)
 };
 
+// Apply blocks whose largest interior exceeds kBigApplyMinI are applied panel by panel over
+// many workgroups per block (panels of kBigApplyPanel columns); every block of such a family
+// stages its vectors in the global workspace.
+constexpr int kBigApplyMinI = 512;
+constexpr int kBigApplyPanel = 128;
+
 // Gather of the up-sweep boundary contributions of the cells for one separator group.
 struct GatherDesc {
     int32_t n;

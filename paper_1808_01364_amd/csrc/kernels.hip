@@ -2803,6 +2803,177 @@ __device__ __forceinline__ void wg_trsv_bwd(const double* __restrict__ L, int ld
 }
 
 // ---------------------------------------------------------------------------------------
+// Factor apply of blocks with large interiors (n_I > kBigApplyMinI: the upper 3D levels and
+// large roots), spread over many workgroups per block. The block's vectors are staged in the
+// global workspace at wsoff ([z_I | z_B]); the solves go by panels of kBigApplyPanel columns of
+// L, one launch per panel over every block of the family:
+//   up   (L z_I = b; y = W^T z_I): launch j updates rows [P t, P t + P) of every block (the rows
+//        of L below panel j - 1 and the rows of W^T) with panel j - 1, solved by the previous
+//        launch, and workgroup t = j then solves its diagonal block (panel j);
+//   down (z_I -= W z_B; L^T z_I = b): launch j updates the columns of panel t < j with panel j,
+//        and workgroup t = j - 1 then solves its diagonal block.
+// The diagonal blocks go through the stored inverses of their 16 x 16 diagonal blocks (the
+// solves of the split kernels). phase: 0 gather, 1 T (skeleton blocks), 2 panel step j,
+// 3 scatter. Workgroup (b, t) of grid (blocks, ceil((max n_I + n_B) / P)).
+// ---------------------------------------------------------------------------------------
+constexpr int kBP = kBigApplyPanel;
+
+// Rows of panel column block q (16 columns) below which L is structurally zero.
+__device__ __forceinline__ int big_rows_end(const ApplyDesc& d, const int32_t* __restrict__ extp, int q) {
+    return (extp != nullptr && d.ext >= 0) ? static_cast<int>(extp[d.ext + q]) : d.nI;
+}
+
+// Solve the diagonal block of panel j in place (w: the block's staged z_I); TRANS: L^T.
+template <bool TRANS>
+__device__ __forceinline__ void big_diag_solve(const ApplyDesc& d, const double* __restrict__ A,
+                                               const double* __restrict__ li, const int32_t* __restrict__ extp,
+                                               double* w, int j, double* zl, int* ex) {
+    const int j0 = j * kBP, nb = min(kBP, d.nI - j0);
+    // the solves read whole 16-blocks: pad the last one with zeros
+    for (int e = threadIdx.x; e < 16 * ((nb + 15) / 16); e += kWG) zl[e] = e < nb ? w[j0 + e] : 0.0;
+    for (int q = threadIdx.x; q < (nb + 15) / 16; q += kWG)
+        ex[q] = min(nb, max(0, big_rows_end(d, extp, j0 / 16 + q) - j0));
+    __syncthreads();
+    const double* Ajj = A + j0 + static_cast<size_t>(j0) * d.ld;
+    if (TRANS) wg_trsv_bwd<false>(Ajj, d.ld, nb, li + d.li + 256 * (j0 / 16), zl, ex);
+    else wg_trsv_fwd<false>(Ajj, d.ld, nb, li + d.li + 256 * (j0 / 16), zl, ex);
+    for (int e = threadIdx.x; e < nb; e += kWG) w[j0 + e] = zl[e];
+}
+
+__global__ __launch_bounds__(256) void k_apply_big_up(const ApplyDesc* __restrict__ ad, int phase, int j,
+                                                      const double* __restrict__ pool, const double* __restrict__ li,
+                                                      const double* __restrict__ Tp, const int32_t* __restrict__ dofs,
+                                                      const int32_t* __restrict__ extp, double* __restrict__ z,
+                                                      double* __restrict__ ybuf, double* __restrict__ ws) {
+    __shared__ double xs[kBP], part[kWG], zl[kBP];
+    __shared__ int ex[kBP / 16];
+    const ApplyDesc d = ad[blockIdx.x];
+    z += d.zoff;   // the block's problem within the vector
+    const int nI = d.nI, nrows = d.nI + d.nB, t = blockIdx.y, tid = threadIdx.x;
+    const int r0 = t * kBP;
+    if (r0 >= nrows) return;
+    const int r1 = min(r0 + kBP, nrows);
+    double* w = ws + d.wsoff;
+    const int32_t* di = dofs + d.dofs;   // z_I's unknowns, then z_B's
+    const double* A = pool + d.off;
+    const int np = (nI + kBP - 1) / kBP;
+    if (phase == 0) {
+        const bool needB = d.toff >= 0 || d.yoff < 0;
+        for (int r = r0 + tid; r < r1; r += kWG) w[r] = (r < nI || needB) ? z[di[r]] : 0.0;
+        return;
+    }
+    if (phase == 1) {   // z_I -= T z_B
+        if (d.toff < 0 || r0 >= nI) return;
+        const double* T = Tp + d.toff;
+        for (int a = r0 + tid; a < min(r1, nI); a += kWG) {
+            double acc = 0.0;
+            for (int c = 0; c < d.nB; ++c) acc += T[c + static_cast<size_t>(a) * d.nB] * w[nI + c];
+            w[a] -= acc;
+        }
+        return;
+    }
+    if (phase == 3) {
+        for (int r = r0 + tid; r < r1; r += kWG) {
+            if (r < nI) z[di[r]] = w[r];
+            else if (d.yoff >= 0) ybuf[d.yoff + (r - nI)] = -w[r];
+            else z[di[r]] = w[r];
+        }
+        return;
+    }
+    // phase 2: the rows of chunk t below panel j - 1 (rows of L, then of W^T) -= A[rows, panel
+    // j - 1] x_{j-1}; then panel j's solve
+    const int c0 = (j - 1) * kBP, nc = min(kBP, nI - c0);
+    if (j >= 1 && j - 1 < np && r1 > c0 + nc) {
+        for (int c = tid; c < nc; c += kWG) xs[c] = w[c0 + c];
+        __syncthreads();
+        // two threads per row, each over half of the panel's columns
+        const int rr = tid & (kBP - 1), h = tid / kBP;
+        const int r = r0 + rr;
+        double acc = 0.0;
+        if (r < r1 && r >= c0 + nc) {
+            const int ca = h * (kBP / 2), cb = min(nc, ca + kBP / 2);
+            for (int c = ca; c < cb; ++c) {
+                const bool nz = r >= nI || r < big_rows_end(d, extp, (c0 + c) >> 4);
+                if (nz) acc += A[r + static_cast<size_t>(c0 + c) * d.ld] * xs[c];
+            }
+        }
+        part[tid] = acc;
+        __syncthreads();
+        if (h == 0 && r < r1 && r >= c0 + nc) w[r] -= part[tid] + part[tid + kBP];
+        __syncthreads();
+    }
+    if (t == j && j < np) big_diag_solve<false>(d, A, li, extp, w, j, zl, ex);
+}
+
+__global__ __launch_bounds__(256) void k_apply_big_dn(const ApplyDesc* __restrict__ ad, int phase, int j,
+                                                      const double* __restrict__ pool, const double* __restrict__ li,
+                                                      const double* __restrict__ Tp, const int32_t* __restrict__ dofs,
+                                                      const int32_t* __restrict__ extp, double* __restrict__ z,
+                                                      double* __restrict__ ws) {
+    __shared__ double xs[kBP], zl[kBP];
+    __shared__ int ex[kBP / 16];
+    const ApplyDesc d = ad[blockIdx.x];
+    z += d.zoff;   // the block's problem within the vector
+    const int nI = d.nI, nB = d.nB, nrows = nI + nB, t = blockIdx.y, tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int r0 = t * kBP;
+    if (r0 >= nrows) return;
+    const int r1 = min(r0 + kBP, nrows);
+    double* w = ws + d.wsoff;
+    const int32_t* di = dofs + d.dofs;
+    const double* A = pool + d.off;
+    const int np = (nI + kBP - 1) / kBP;
+    if (phase == 0) {
+        for (int r = r0 + tid; r < r1; r += kWG) w[r] = z[di[r]];
+        return;
+    }
+    if (phase == 3) {   // scatter z_I; z_B -= T z_I
+        for (int r = r0 + tid; r < min(r1, nI); r += kWG) z[di[r]] = w[r];
+        if (d.toff >= 0) {
+            const double* T = Tp + d.toff;
+            for (int c = r0 + tid; c < min(r0 + kBP, nB); c += kWG) {
+                double acc = 0.0;
+                for (int a = 0; a < nI; ++a) acc += T[c + static_cast<size_t>(a) * nB] * w[a];
+                z[di[nI + c]] = w[nI + c] - acc;
+            }
+        }
+        return;
+    }
+    if (t >= np) return;   // the remaining phases work on the columns of z_I
+    const int col0 = t * kBP, ncol = min(kBP, nI - col0);
+    if (phase == 1) {
+        // z_I -= W z_B on this chunk's columns (a wave per column, lanes over the rows of W^T);
+        // then the last panel's solve
+        for (int c = wave; c < ncol; c += kWaves) {
+            const double* Wc = A + nI + static_cast<size_t>(col0 + c) * d.ld;
+            double acc = 0.0;
+            for (int b = lane; b < nB; b += 64) acc += Wc[b] * w[nI + b];
+            acc = wave_sum(acc);
+            if (lane == 0) w[col0 + c] -= acc;
+        }
+        __syncthreads();
+        if (t == np - 1) big_diag_solve<true>(d, A, li, extp, w, t, zl, ex);
+        return;
+    }
+    // phase 2: columns of chunk t < j -= L[panel j rows, columns]^T x_j; then panel j - 1's solve
+    if (j >= np || t >= j) return;
+    const int j0 = j * kBP, nr = min(kBP, nI - j0);
+    for (int e = tid; e < nr; e += kWG) xs[e] = w[j0 + e];
+    __syncthreads();
+    for (int c = wave; c < ncol; c += kWaves) {
+        const int col = col0 + c;
+        const int rend = min(nr, big_rows_end(d, extp, col >> 4) - j0);
+        const double* Lc = A + j0 + static_cast<size_t>(col) * d.ld;
+        double acc = 0.0;
+        for (int e = lane; e < rend; e += 64) acc += Lc[e] * xs[e];
+        acc = wave_sum(acc);
+        if (lane == 0) w[col] -= acc;
+    }
+    __syncthreads();
+    if (t == j - 1) big_diag_solve<true>(d, A, li, extp, w, t, zl, ex);
+}
+
+// ---------------------------------------------------------------------------------------
 // Triangular solves of the apply for banded leaf cells, whose L (from k_leaf_elim) is block
 // bidiagonal in 16 x 16 blocks: in steps of 16 rows,
 //   up   (L z = b):   z_J = Li_J (b_J - L_J,J-1 z_J-1),            J = 0, 1, ...

@@ -78,6 +78,11 @@ __global__ void k_apply_up(const ApplyDesc* ad, const double* pool, const double
                            double* z, double* ybuf, double* ws, const int32_t* ext);
 __global__ void k_apply_down(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
                              double* z, double* ws, const int32_t* ext);
+__global__ void k_apply_big_up(const ApplyDesc* ad, int phase, int j, const double* pool, const double* li,
+                               const double* Tp, const int32_t* dofs, const int32_t* extp, double* z, double* ybuf,
+                               double* ws);
+__global__ void k_apply_big_dn(const ApplyDesc* ad, int phase, int j, const double* pool, const double* li,
+                               const double* Tp, const int32_t* dofs, const int32_t* extp, double* z, double* ws);
 __global__ void k_apply_trsv_up(const ApplyDesc* ad, const double* pool, const double* lip, const double* Tp,
                                 const int32_t* dofs, double* z, const int32_t* extp);
 __global__ void k_apply_trsv_dn(const ApplyDesc* ad, const double* pool, const double* lip, const double* Tp,

@@ -12,6 +12,20 @@ namespace {
 
 inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// A block family with an interior above kBigApplyMinI is applied panel by panel over many
+// workgroups per block, which stages every block's vectors in the global workspace: give the
+// blocks that fit LDS a workspace region too.
+void big_family_ws(std::vector<ApplyDesc>& fam, int64_t& ws) {
+    int mi = 0;
+    for (const ApplyDesc& a : fam) mi = std::max(mi, a.nI);
+    if (mi <= kBigApplyMinI) return;
+    for (ApplyDesc& a : fam)
+        if (a.wsoff < 0) {
+            a.wsoff = ws;
+            ws += align_up(a.nI + a.nB, 32);
+        }
+}
+
 // Coordinates x_k in 1..s of linear unknown i (x_1 fastest).
 inline void coords(int64_t i, int d, int s, int* x) {
     for (int k = 0; k < d; ++k) {
@@ -497,6 +511,7 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, int64_t n_a
         P.cell_apply.push_back(ad);
         yoff += nB;
     }
+    big_family_ws(P.cell_apply, ws);
     P.y_elems = std::max<int64_t>(yoff, 1);
     P.ws_elems = ws;
 }
@@ -656,6 +671,7 @@ void build_separators(const GridInfo& gi, PlanScratch& scr, int lds_apply_cap, L
     P.t_elems = std::max<int64_t>(toff, 32);
     P.g_elems = std::max<int64_t>(goff, 32);
     P.skli_elems = std::max<int64_t>(skli, 256);
+    big_family_ws(P.sep_apply, ws);
     P.ws_elems = ws;
 }
 
@@ -704,6 +720,7 @@ void skel_apply_tables(const LevelPlan& P, const int32_t* k, const int32_t* perm
         ndofs += n;
         skel_apply.push_back(ad);
     }
+    big_family_ws(skel_apply, ws_elems);
     skel_dofs.resize(ndofs);
 }
 
