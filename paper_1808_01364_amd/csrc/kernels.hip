@@ -2121,7 +2121,7 @@ RHIF_SKEL_INST(4, float, 16)
 // Then k_big_trisolve solves T = R11^-1 R12 in place (one thread per redundant column), and
 // k_big_finish performs the zeroing and the elimination of the redundant unknowns.
 // ---------------------------------------------------------------------------------------
-constexpr int kBigRows = 256;
+constexpr int kBigRows = 64;
 static_assert(kBigRows == kBigRowsHost, "row blocks of the multi-workgroup ID");
 
 template <typename MR>

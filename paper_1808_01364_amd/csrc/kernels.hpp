@@ -68,7 +68,7 @@ template <typename MR>
 __global__ void k_big_finish(const SkelDesc* sd, const CellRef* cells, double* F, const double* Mpool, double* Gpool,
                              double* skli, const int32_t* kout, const int32_t* pout, int panel_cap, int nmax,
                              int level, unsigned long long* err);
-constexpr int kBigRowsHost = 256;   // rows of M per workgroup in the kernels above
+constexpr int kBigRowsHost = 64;    // rows of M per workgroup in the kernels above
 __global__ void k_fwd_gt(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
                          const int32_t* ext, double* z);
 __global__ void k_fwd_g(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
