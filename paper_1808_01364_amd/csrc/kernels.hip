@@ -1696,10 +1696,13 @@ __global__ __launch_bounds__(256) void k_precond_groups(const SepDesc* __restric
 // after h in the cell's group order: S_gh := L_g^-1 S_gh L_h^-T (rows, then columns, by
 // blocked substitution with the stored inverses of the 16 x 16 diagonal blocks), written
 // also transposed into the (h, g) block. Workgroups with g = h set the diagonal block.
+// phase 0: both one-sided solves in one launch; 1: only X <- X L_h^-T (its 16-row strips are
+// independent); 2: only X <- L_g^-1 X (16-column strips), and the diagonal blocks. The strips of
+// a pair are spread over the workgroups of the grid's third dimension.
 __global__ __launch_bounds__(256) void k_precond_scale(const CellScaleDesc* __restrict__ cd,
                                                        const CellGroup* __restrict__ cg, const double* __restrict__ Lg,
                                                        const double* __restrict__ Li, double* __restrict__ F,
-                                                       int pstride) {
+                                                       int pstride, int phase) {
     extern __shared__ double smem[];
     const CellScaleDesc c = cd[blockIdx.x];
     const int gc = c.g_count;
@@ -1712,32 +1715,40 @@ __global__ __launch_bounds__(256) void k_precond_scale(const CellScaleDesc* __re
     const CellGroup G = cg[c.g_begin + eg], H = cg[c.g_begin + eh];
     double* Fc = F + c.off;
     const int ld = c.ld;
+    const int z = blockIdx.z, nz = gridDim.z;
     if (eg == eh) {
-        for (int e = threadIdx.x; e < G.n * G.n; e += kWG) {
+        if (phase == 1) return;
+        for (int e = z * kWG + threadIdx.x; e < G.n * G.n; e += nz * kWG) {
             const int a = e % G.n, b = e / G.n;
             Fc[(G.off + a) + static_cast<size_t>(G.off + b) * ld] = (G.owner && a == b) ? 1.0 : 0.0;
         }
         return;
     }
     const int wave = threadIdx.x >> 6;
+    const int s0 = (z * kWaves + wave) * 16, ss = nz * kWaves * 16;
     double* X = Fc + G.off + static_cast<size_t>(H.off) * ld;
     double* XT = Fc + H.off + static_cast<size_t>(G.off) * ld;
     if (pstride > 0) {
         double* Pw = smem + static_cast<size_t>(wave) * pstride;
-        for (int r0 = wave * 16; r0 < G.n; r0 += kWaves * 16)
-            wave_trsm_rlt(X, ld, G.n, r0, H.n, Lg + H.loff, H.n, Li + H.lioff, Pw);
-        __syncthreads();
-        for (int c0 = wave * 16; c0 < H.n; c0 += kWaves * 16)
-            wave_trsm_ll(X, ld, G.n, c0, H.n, Lg + G.loff, G.n, Li + G.lioff, Pw, XT, ld);
+        if (phase != 2)
+            for (int r0 = s0; r0 < G.n; r0 += ss) wave_trsm_rlt(X, ld, G.n, r0, H.n, Lg + H.loff, H.n, Li + H.lioff, Pw);
+        if (phase == 0) __syncthreads();
+        if (phase != 1)
+            for (int c0 = s0; c0 < H.n; c0 += ss)
+                wave_trsm_ll(X, ld, G.n, c0, H.n, Lg + G.loff, G.n, Li + G.lioff, Pw, XT, ld);
     } else {
         // groups too large for LDS strips: finished panels are read back from the frontal
         double* Pw = smem + wave * 16 * 17;
-        for (int r0 = wave * 16; r0 < G.n; r0 += kWaves * 16)
-            wave_trsm_rlt<false>(X, ld, G.n, r0, H.n, Lg + H.loff, H.n, Li + H.lioff, Pw);
-        __threadfence();
-        __syncthreads();
-        for (int c0 = wave * 16; c0 < H.n; c0 += kWaves * 16)
-            wave_trsm_ll<false>(X, ld, G.n, c0, H.n, Lg + G.loff, G.n, Li + G.lioff, Pw, XT, ld);
+        if (phase != 2)
+            for (int r0 = s0; r0 < G.n; r0 += ss)
+                wave_trsm_rlt<false>(X, ld, G.n, r0, H.n, Lg + H.loff, H.n, Li + H.lioff, Pw);
+        if (phase == 0) {
+            __threadfence();
+            __syncthreads();
+        }
+        if (phase != 1)
+            for (int c0 = s0; c0 < H.n; c0 += ss)
+                wave_trsm_ll<false>(X, ld, G.n, c0, H.n, Lg + G.loff, G.n, Li + G.lioff, Pw, XT, ld);
     }
 }
 
@@ -2119,7 +2130,8 @@ RHIF_SKEL_INST(4, float, 16)
 // k_big_dot forms the blocks' partials of v^T M, and k_big_update sums them (fixed order),
 // updates its rows and leaves the new norm partials. The host launches the three per step.
 // Then k_big_trisolve solves T = R11^-1 R12 in place (one thread per redundant column), and
-// k_big_finish performs the zeroing and the elimination of the redundant unknowns.
+// k_big_elim with the panel kernels of the cell elimination performs the zeroing and the
+// elimination of the redundant unknowns.
 // ---------------------------------------------------------------------------------------
 constexpr int kBigRows = 64;
 static_assert(kBigRows == kBigRowsHost, "row blocks of the multi-workgroup ID");
@@ -2363,23 +2375,83 @@ __global__ __launch_bounds__(64) void k_big_trisolve(const SkelDesc* __restrict_
     for (int i = 0; i < k; ++i) T[i + static_cast<size_t>(a) * k] = static_cast<double>(M[static_cast<size_t>(i) * ldr + pa]);
 }
 
-// Steps 3-5 for groups whose ID the kernels above took: rank and pivot order from kout / pout,
-// T in M; G in the global pool.
+// The skeleton elimination of the large groups spread over many workgroups per group (the
+// partial Cholesky of G then goes by the panel kernels of the cell elimination):
+//   phase 0: G = the group's permuted diagonal block (redundant unknowns first), 16 columns of
+//            G per workgroup;
+//   phase 1: V = A_ht - A_hh T over the lower (skeleton, redundant) block;
+//   phase 2: A~_tt = A_tt - T^T V - A_ht^T T on the lower triangle of the redundant block;
+//   phase 3: the skeleton block of the Schur complement back to the first cell's frontal, the
+//            second cell's share of the group cleared.
+// Each entry is formed with the operations and order of skel_eliminate.
 template <typename MR>
-__global__ __launch_bounds__(256) void k_big_finish(const SkelDesc* __restrict__ sd, const CellRef* __restrict__ cells,
-                                                    double* __restrict__ F, const double* __restrict__ Mpool,
-                                                    double* __restrict__ Gpool, double* __restrict__ skli,
-                                                    const int32_t* __restrict__ kout, const int32_t* __restrict__ pout,
-                                                    int panel_cap, int nmax, int level, unsigned long long* err) {
-    extern __shared__ double smem[];
+__global__ __launch_bounds__(256) void k_big_elim(const SkelDesc* __restrict__ sd, const CellRef* __restrict__ cells,
+                                                  double* __restrict__ F, const double* __restrict__ Mpool,
+                                                  double* __restrict__ Gpool, const int32_t* __restrict__ kout,
+                                                  const int32_t* __restrict__ pout, int phase) {
     const SkelDesc g = sd[blockIdx.x];
-    int* perm = reinterpret_cast<int*>(smem);
-    double* psmem = smem + (nmax + 1) / 2 + 1;
-    for (int e = threadIdx.x; e < g.n; e += kWG) perm[e] = pout[g.poff + e];
-    __syncthreads();
+    const int n = g.n, k = kout[g.gid], nr = n - k, ldr = n | 1, tid = threadIdx.x;
+    const int y0 = blockIdx.y * 16;
+    if (y0 >= n) return;
+    const int y1 = min(n, y0 + 16);
+    const int32_t* perm = pout + g.poff;
     const MR* M = reinterpret_cast<const MR*>(Mpool + g.moff);
-    skel_eliminate<false, MR>(g, kout[g.gid], perm, M, g.n | 1, cells, F, Gpool, Gpool + g.goff, psmem, skli, panel_cap,
-                              level, err, blockIdx.x);
+    double* Gw = Gpool + g.goff;
+    const CellRef c0 = cells[g.cell[0]];
+    CellRef c1 = c0;
+    if (g.nslot > 1) c1 = cells[g.cell[1]];
+    const double* f0 = F + c0.off + static_cast<size_t>(g.off[0]) * c0.ld;
+    const double* f1 = F + c1.off + static_cast<size_t>(g.off[1]) * c1.ld;
+    if (phase == 0) {
+        for (int e = tid; e < (y1 - y0) * n; e += kWG) {
+            const int x = e % n, y = y0 + e / n;
+            const int qx = x < nr ? perm[k + x] : perm[x - nr];
+            const int qy = y < nr ? perm[k + y] : perm[y - nr];
+            double v = f0[g.off[0] + qx + static_cast<size_t>(qy) * c0.ld];
+            if (g.nslot > 1) v += f1[g.off[1] + qx + static_cast<size_t>(qy) * c1.ld];
+            Gw[x + static_cast<size_t>(y) * n] = v;
+        }
+        return;
+    }
+    if (phase == 1) {   // columns a in [y0, y1) of the redundant block
+        for (int e = tid; e < k * (min(y1, nr) - y0); e += kWG) {
+            const int c = e % k, a = y0 + e / k;
+            const int pa = perm[k + a];
+            const double* Gc = Gw + (nr + c) + static_cast<size_t>(nr) * n;
+            double v = Gw[(nr + c) + static_cast<size_t>(a) * n], v1 = 0.0;
+            int q = 0;
+            for (; q + 1 < k; q += 2) {
+                v -= Gc[static_cast<size_t>(q) * n] * static_cast<double>(M[static_cast<size_t>(q) * ldr + pa]);
+                v1 -= Gc[static_cast<size_t>(q + 1) * n] * static_cast<double>(M[static_cast<size_t>(q + 1) * ldr + pa]);
+            }
+            if (q < k) v -= Gc[static_cast<size_t>(q) * n] * static_cast<double>(M[static_cast<size_t>(q) * ldr + pa]);
+            Gw[(nr + c) + static_cast<size_t>(a) * n] = v + v1;
+        }
+        return;
+    }
+    if (phase == 2) {   // columns b in [y0, y1), rows a >= b of the redundant block
+        for (int e = tid; e < nr * (min(y1, nr) - y0); e += kWG) {
+            const int a = e % nr, b = y0 + e / nr;
+            if (a < b) continue;
+            const int pa = perm[k + a], pb = perm[k + b];
+            double v = Gw[a + static_cast<size_t>(b) * n], v1 = 0.0;
+            for (int c = 0; c < k; ++c) {
+                const MR* Tc = M + static_cast<size_t>(c) * ldr;
+                v -= static_cast<double>(Tc[pa]) * Gw[(nr + c) + static_cast<size_t>(b) * n];
+                v1 -= Gw[a + static_cast<size_t>(nr + c) * n] * static_cast<double>(Tc[pb]);
+            }
+            Gw[a + static_cast<size_t>(b) * n] = v + v1;
+        }
+        return;
+    }
+    // phase 3
+    for (int e = tid; e < (y1 - y0) * n; e += kWG) {
+        const int a = e % n, b = y0 + e / n;
+        if (a < k && b < k)
+            F[c0.off + (g.off[0] + perm[a]) + static_cast<size_t>(g.off[0] + perm[b]) * c0.ld] =
+                Gw[(nr + a) + static_cast<size_t>(nr + b) * n];
+        if (g.nslot > 1) F[c1.off + (g.off[1] + a) + static_cast<size_t>(g.off[1] + b) * c1.ld] = 0.0;
+    }
 }
 
 #define RHIF_BIG_INST(MR)                                                                                          \
@@ -2394,9 +2466,8 @@ __global__ __launch_bounds__(256) void k_big_finish(const SkelDesc* __restrict__
                                               const double*, int, int, int);                                      \
     template __global__ void k_big_trisolve<MR>(const SkelDesc*, double*, const int32_t*, const BigState*,         \
                                                 double*);                                                         \
-    template __global__ void k_big_finish<MR>(const SkelDesc*, const CellRef*, double*, const double*, double*,    \
-                                              double*, const int32_t*, const int32_t*, int, int, int,             \
-                                              unsigned long long*);
+    template __global__ void k_big_elim<MR>(const SkelDesc*, const CellRef*, double*, const double*, double*,      \
+                                            const int32_t*, const int32_t*, int);
 RHIF_BIG_INST(double)
 RHIF_BIG_INST(float)
 #undef RHIF_BIG_INST

@@ -35,7 +35,7 @@ __global__ void k_syrk_schur(const FrontDesc* desc, double* pool);
 __global__ void k_precond_groups(const SepDesc* sd, const CellRef* cells, const double* F, double* Lg, double* Li,
                                  int panel_cap, int lds_n, int level, unsigned long long* err);
 __global__ void k_precond_scale(const CellScaleDesc* cd, const CellGroup* cg, const double* Lg, const double* Li,
-                                double* F, int pstride);
+                                double* F, int pstride, int phase);
 // waves per SIMD of the skeletonization form for launches with many groups per CU
 constexpr int kSkelWavesMany = 4;
 // LDS of k_skeletonize beyond the partials of wg_cpqr_rows that the register ID needs
@@ -65,9 +65,8 @@ template <typename MR>
 __global__ void k_big_trisolve(const SkelDesc* sd, double* Mpool, const int32_t* pout, const BigState* st,
                                double* Tpool);
 template <typename MR>
-__global__ void k_big_finish(const SkelDesc* sd, const CellRef* cells, double* F, const double* Mpool, double* Gpool,
-                             double* skli, const int32_t* kout, const int32_t* pout, int panel_cap, int nmax,
-                             int level, unsigned long long* err);
+__global__ void k_big_elim(const SkelDesc* sd, const CellRef* cells, double* F, const double* Mpool, double* Gpool,
+                           const int32_t* kout, const int32_t* pout, int phase);
 constexpr int kBigRowsHost = 64;    // rows of M per workgroup in the kernels above
 __global__ void k_fwd_gt(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
                          const int32_t* ext, double* z);

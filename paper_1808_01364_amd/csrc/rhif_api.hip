@@ -59,6 +59,7 @@ constexpr int32_t kRemovedFlags = 4;          // option bits that no longer exis
 constexpr int64_t kBigSkelElems = 1 << 18;    // M (rows x columns) from which the ID spreads over
                                               // many workgroups per group
 constexpr int kBigCheck = 16;                 // steps between the host's checks for active groups
+constexpr int kScaleRowsPerWG = 128;          // strips of a group pair's two-sided scaling per workgroup
 
 // Planner state of one problem of a factorization call: scratch, level plans and the
 // host tables of the skeleton apply. The sets are kept for reuse (PlanPool); the level-0 plan
@@ -882,9 +883,7 @@ void set_kernel_attributes() {
         const int bytes = kLdsMaxDoubles * static_cast<int>(sizeof(double));
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_precond_scale),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        for (const void* k : {reinterpret_cast<const void*>(&rhif::k_big_finish<double>),
-                              reinterpret_cast<const void*>(&rhif::k_big_finish<float>),
-                              reinterpret_cast<const void*>(&rhif::k_skeletonize<4, double, 16>),
+        for (const void* k : {reinterpret_cast<const void*>(&rhif::k_skeletonize<4, double, 16>),
                               reinterpret_cast<const void*>(&rhif::k_skeletonize<4, float, 16>)})
             (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         for (int staged : {0, 1, 3})
@@ -1638,9 +1637,19 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                 if (gstage || 4 * pstride > kLdsMaxDoubles) pstride = 0;
                 const size_t lds_sc = static_cast<size_t>(pstride > 0 ? 4 * pstride : 4 * 16 * 17) * sizeof(double);
                 const int gc = max_cell_groups;
-                KTIMED(f0, s, RHIF_K_PRECOND_SCALE, alg_pscale, 0.0,
-                       hipLaunchKernelGGL(k_precond_scale, dim3(mt.cs.size(), gc * (gc + 1) / 2), dim3(256), lds_sc,
-                                          s, cs_all, cg_all, lg, li, front, pstride));
+                // large groups: each pair's strips over several workgroups, the two one-sided
+                // solves as two launches
+                const int nz = (max_sep_n + kScaleRowsPerWG - 1) / kScaleRowsPerWG;
+                if (nz <= 1) {
+                    KTIMED(f0, s, RHIF_K_PRECOND_SCALE, alg_pscale, 0.0,
+                           hipLaunchKernelGGL(k_precond_scale, dim3(mt.cs.size(), gc * (gc + 1) / 2), dim3(256),
+                                              lds_sc, s, cs_all, cg_all, lg, li, front, pstride, 0));
+                } else {
+                    for (int ph = 1; ph <= 2; ++ph)
+                        KTIMED(f0, s, RHIF_K_PRECOND_SCALE, ph == 1 ? alg_pscale : 0.0, 0.0,
+                               hipLaunchKernelGGL(k_precond_scale, dim3(mt.cs.size(), gc * (gc + 1) / 2, nz),
+                                                  dim3(256), lds_sc, s, cs_all, cg_all, lg, li, front, pstride, ph));
+                }
             }
         }
         for (int p : nonroot)
@@ -1733,12 +1742,70 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                 KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
                        hipLaunchKernelGGL(f32 ? k_big_trisolve<float> : k_big_trisolve<double>,
                                           dim3(nsk, (n + 63) / 64), dim3(64), 0, s, skd_all, mp, pout, bst, tp));
-                const int fbase = (n + 1) / 2 + 1;
-                const int fcap = panel_cap_for(n, fbase);
-                KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
-                       hipLaunchKernelGGL(f32 ? k_big_finish<float> : k_big_finish<double>, dim3(nsk), dim3(256),
-                                          potrf_lds(fcap, fbase), s, skd_all, cref_all, front, mp, gp, skli, kout,
-                                          pout, fcap, n, lvl, err));
+                // the skeleton eliminations spread over many workgroups per group: G and its
+                // zeroed blocks, the partial Cholesky of G by the panel kernels of the cell
+                // elimination (the ranks come to the host for their tables), the write-back
+                const dim3 gcol(nsk, (n + 15) / 16);
+                auto elim = [&](int ph) {
+                    KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                           hipLaunchKernelGGL(f32 ? k_big_elim<float> : k_big_elim<double>, gcol, dim3(256), 0, s,
+                                              skd_all, cref_all, front, mp, gp, kout, pout, ph));
+                };
+                for (int ph = 0; ph < 3; ++ph) elim(ph);
+                int32_t* hkk = reinterpret_cast<int32_t*>(hc.get_down(static_cast<size_t>(n_k) * sizeof(int32_t) + 64));
+                HIPCHK(hipMemcpyAsync(hkk, kout, static_cast<size_t>(n_k) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                int nrmax = 0;
+                for (const auto& sk : mt.skd) nrmax = std::max(nrmax, sk.n - hkk[sk.gid]);
+                const int nq = (nrmax + kElimPanel - 1) / kElimPanel;
+                std::vector<rhif::FrontDesc> pd;
+                std::vector<int32_t> pd_off(nq + 1, 0), pd_mrow(std::max(nq, 1), 0);
+                for (int q = 0; q < nq; ++q) {
+                    const int j0 = q * kElimPanel;
+                    for (const auto& sk : mt.skd) {
+                        const int nr = sk.n - hkk[sk.gid];
+                        if (nr <= j0) continue;
+                        rhif::FrontDesc e{};
+                        e.off = sk.goff + j0 + static_cast<int64_t>(j0) * sk.n;
+                        e.ld = sk.n;
+                        e.n = sk.n - j0;
+                        e.p = std::min(kElimPanel, nr - j0);
+                        e.id = sk.gid;
+                        e.ext = sk.lioff / 256 + j0 / 16;
+                        pd.push_back(e);
+                        pd_mrow[q] = std::max(pd_mrow[q], e.n - e.p);
+                    }
+                    pd_off[q + 1] = static_cast<int32_t>(pd.size());
+                }
+                if (!pd.empty()) {
+                    Packer pk;
+                    const size_t o_pd = pk.add(pd);
+                    char* T = upload(f0, pk, s);
+                    const rhif::FrontDesc* pdd = view<rhif::FrontDesc>(T, o_pd);
+                    const size_t lds1 =
+                        static_cast<size_t>(rhif::kPotrfSmemFixed + (kElimPanel | 1) * kElimPanel) * sizeof(double);
+                    const int pstride = 17 * kElimPanel;
+                    for (int q = 0; q < nq; ++q) {
+                        const unsigned nc = static_cast<unsigned>(pd_off[q + 1] - pd_off[q]);
+                        if (nc == 0) continue;
+                        const rhif::FrontDesc* dq = pdd + pd_off[q];
+                        KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                               hipLaunchKernelGGL(k_chol_lead, dim3(nc), dim3(256), lds1, s, dq, gp, skli, kElimPanel,
+                                                  lvl, 2, err, nullptr));
+                        const int mr = pd_mrow[q];
+                        if (mr > 0) {
+                            KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                                   hipLaunchKernelGGL(k_trsm_rows, dim3(nc, (mr + 63) / 64), dim3(256),
+                                                      static_cast<size_t>(4 * pstride) * sizeof(double), s, dq, gp,
+                                                      skli, pstride));
+                            const int nb = (mr + 31) / 32;
+                            KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                                   hipLaunchKernelGGL(k_syrk_schur<false>, dim3(nc, nb * (nb + 1) / 2), dim3(256), 0,
+                                                      s, dq, gp));
+                        }
+                    }
+                }
+                elim(3);
             } else {
                 KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
                        hipLaunchKernelGGL(skel_kernel(staged, skel_rows_per_thread(mt.skd), f32), dim3(nsk),
