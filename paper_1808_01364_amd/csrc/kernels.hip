@@ -2194,16 +2194,15 @@ __global__ __launch_bounds__(256) void k_big_gather(const SkelDesc* __restrict__
 
 template <typename MR>
 __global__ __launch_bounds__(256) void k_big_pivot(const SkelDesc* __restrict__ sd, const double* __restrict__ Mpool,
-                                                   const double* __restrict__ nrm, int32_t* __restrict__ pos,
+                                                   const double* __restrict__ nsum, int32_t* __restrict__ pos,
                                                    int32_t* __restrict__ pout, BigState* __restrict__ st, double eps,
-                                                   int j, int nmax, int nblk, int32_t* __restrict__ kout) {
+                                                   int j, int nmax, int32_t* __restrict__ kout) {
     __shared__ double rb[kWaves];
     __shared__ int rp[kWaves], rc[kWaves];
     const int gi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (!st[gi].active) return;
     const SkelDesc g = sd[gi];
     const int n = g.n, r = g.r, ldr = n | 1;
-    const int nb = (r + kBigRows - 1) / kBigRows;
     if (j >= min(r, n)) {   // every column taken
         if (tid == 0) {
             st[gi].active = 0;
@@ -2218,9 +2217,7 @@ __global__ __launch_bounds__(256) void k_big_pivot(const SkelDesc* __restrict__ 
     for (int c = tid; c < n; c += kWG) {
         const int pp = pg[c];
         if (pp < j) continue;
-        MR v = 0;
-        for (int b = 0; b < nb; ++b) v += static_cast<MR>(nrm[(static_cast<size_t>(gi) * nblk + b) * nmax + c]);
-        const double vd = static_cast<double>(v);
+        const double vd = static_cast<double>(static_cast<MR>(nsum[static_cast<size_t>(gi) * nmax + c]));
         if (vd > best || (vd == best && pp < bpos)) {
             best = vd;
             bpos = pp;
@@ -2302,6 +2299,19 @@ __global__ __launch_bounds__(256) void k_big_dot(const SkelDesc* __restrict__ sd
             w0 = v0 * M[static_cast<size_t>(j) * ldr + c];
             ++i;
         }
+        for (; i + 7 < i1; i += 8) {   // the order of the two-row loop below, loads first
+            MR a[8], pv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                pv[u] = M[static_cast<size_t>(i + u) * ldr + s.pc];
+                a[u] = M[static_cast<size_t>(i + u) * ldr + c];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u += 2) {
+                w0 += pv[u] * a[u];
+                w1 += pv[u + 1] * a[u + 1];
+            }
+        }
         for (; i + 1 < i1; i += 2) {
             w0 += M[static_cast<size_t>(i) * ldr + s.pc] * M[static_cast<size_t>(i) * ldr + c];
             w1 += M[static_cast<size_t>(i + 1) * ldr + s.pc] * M[static_cast<size_t>(i + 1) * ldr + c];
@@ -2311,10 +2321,27 @@ __global__ __launch_bounds__(256) void k_big_dot(const SkelDesc* __restrict__ sd
     }
 }
 
+// The row blocks' partial sums of every column (norms after k_big_gather / k_big_update, v^T M
+// after k_big_dot), summed once per step in block order (in the ID's arithmetic), so that
+// k_big_pivot and the blocks of k_big_update read one value per column.
+template <typename MR>
+__global__ __launch_bounds__(256) void k_big_colsum(const SkelDesc* __restrict__ sd, const BigState* __restrict__ st,
+                                                    const double* __restrict__ part, double* __restrict__ sum, int nmax,
+                                                    int nblk) {
+    const int gi = blockIdx.x, c = blockIdx.y * kWG + threadIdx.x;
+    if (!st[gi].active) return;
+    const SkelDesc g = sd[gi];
+    if (c >= g.n) return;
+    const int nb = (g.r + kBigRows - 1) / kBigRows;
+    MR v = 0;
+    for (int b = 0; b < nb; ++b) v += static_cast<MR>(part[(static_cast<size_t>(gi) * nblk + b) * nmax + c]);
+    sum[static_cast<size_t>(gi) * nmax + c] = static_cast<double>(v);
+}
+
 template <typename MR>
 __global__ __launch_bounds__(256) void k_big_update(const SkelDesc* __restrict__ sd, double* __restrict__ Mpool,
                                                     double* __restrict__ nrm, const int32_t* __restrict__ pos,
-                                                    const BigState* __restrict__ st, const double* __restrict__ wpart,
+                                                    const BigState* __restrict__ st, const double* __restrict__ wsum,
                                                     int j, int nmax, int nblk) {
     const int gi = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
     const BigState s = st[gi];
@@ -2322,7 +2349,6 @@ __global__ __launch_bounds__(256) void k_big_update(const SkelDesc* __restrict__
     const SkelDesc g = sd[gi];
     const int n = g.n, r = g.r, ldr = n | 1;
     if (b * kBigRows >= r) return;
-    const int nb = (r + kBigRows - 1) / kBigRows;
     const int i0 = max(j, b * kBigRows), i1 = min(r, b * kBigRows + kBigRows);
     MR* M = reinterpret_cast<MR*>(Mpool + g.moff);
     const int32_t* pg = pos + static_cast<size_t>(gi) * nmax;
@@ -2330,14 +2356,29 @@ __global__ __launch_bounds__(256) void k_big_update(const SkelDesc* __restrict__
     const MR v0 = static_cast<MR>(s.v0), beta = static_cast<MR>(s.beta);
     for (int c = tid; c < n; c += kWG) {
         if (pg[c] <= j) continue;
-        MR w = 0;
-        for (int q = 0; q < nb; ++q) w += static_cast<MR>(wpart[(static_cast<size_t>(gi) * nblk + q) * nmax + c]);
+        const MR w = static_cast<MR>(wsum[static_cast<size_t>(gi) * nmax + c]);
         const MR f = beta * w;
         MR sq = 0;
         int i = i0;
         if (i == j && i < i1) {   // row j lies in this block
             M[static_cast<size_t>(j) * ldr + c] -= f * v0;
             ++i;
+        }
+        // eight rows' loads in flight before their updates (the pivot column is never written
+        // here); the norm sums in row order
+        for (; i + 7 < i1; i += 8) {
+            MR a[8], pv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                a[u] = M[static_cast<size_t>(i + u) * ldr + c];
+                pv[u] = M[static_cast<size_t>(i + u) * ldr + s.pc];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const MR nvv = a[u] - f * pv[u];
+                M[static_cast<size_t>(i + u) * ldr + c] = nvv;
+                sq += nvv * nvv;
+            }
         }
         for (; i < i1; ++i) {
             const MR nvv = M[static_cast<size_t>(i) * ldr + c] - f * M[static_cast<size_t>(i) * ldr + s.pc];
@@ -2459,7 +2500,8 @@ __global__ __launch_bounds__(256) void k_big_elim(const SkelDesc* __restrict__ s
                                               const CellRef*, const double*, double*, double*, int32_t*, int32_t*, \
                                               BigState*, int, int, int, unsigned long long*);                     \
     template __global__ void k_big_pivot<MR>(const SkelDesc*, const double*, const double*, int32_t*, int32_t*,    \
-                                             BigState*, double, int, int, int, int32_t*);                         \
+                                             BigState*, double, int, int, int32_t*);                              \
+    template __global__ void k_big_colsum<MR>(const SkelDesc*, const BigState*, const double*, double*, int, int); \
     template __global__ void k_big_dot<MR>(const SkelDesc*, const double*, const int32_t*, const BigState*,        \
                                            double*, int, int, int);                                               \
     template __global__ void k_big_update<MR>(const SkelDesc*, double*, double*, const int32_t*, const BigState*,  \

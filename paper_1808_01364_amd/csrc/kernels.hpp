@@ -53,14 +53,17 @@ __global__ void k_big_gather(const SkelDesc* sd, const int32_t* cgptr, const int
                              const CellRef* cells, const double* F, double* Mpool, double* nrm, int32_t* pos,
                              int32_t* pout, BigState* st, int nmax, int nblk, int level, unsigned long long* err);
 template <typename MR>
-__global__ void k_big_pivot(const SkelDesc* sd, const double* Mpool, const double* nrm, int32_t* pos, int32_t* pout,
-                            BigState* st, double eps, int j, int nmax, int nblk, int32_t* kout);
+__global__ void k_big_pivot(const SkelDesc* sd, const double* Mpool, const double* nsum, int32_t* pos, int32_t* pout,
+                            BigState* st, double eps, int j, int nmax, int32_t* kout);
+template <typename MR>
+__global__ void k_big_colsum(const SkelDesc* sd, const BigState* st, const double* part, double* sum, int nmax,
+                             int nblk);
 template <typename MR>
 __global__ void k_big_dot(const SkelDesc* sd, const double* Mpool, const int32_t* pos, const BigState* st,
                           double* wpart, int j, int nmax, int nblk);
 template <typename MR>
 __global__ void k_big_update(const SkelDesc* sd, double* Mpool, double* nrm, const int32_t* pos, const BigState* st,
-                             const double* wpart, int j, int nmax, int nblk);
+                             const double* wsum, int j, int nmax, int nblk);
 template <typename MR>
 __global__ void k_big_trisolve(const SkelDesc* sd, double* Mpool, const int32_t* pout, const BigState* st,
                                double* Tpool);

@@ -1707,27 +1707,36 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                 double* wpart = static_cast<double*>(f0->dalloc(static_cast<size_t>(nsk) * nblk * n * sizeof(double)));
                 int32_t* posb = static_cast<int32_t*>(f0->dalloc(static_cast<size_t>(nsk) * n * sizeof(int32_t)));
                 BigState* bst = static_cast<BigState*>(f0->dalloc(static_cast<size_t>(nsk) * sizeof(BigState)));
+                double* csum = static_cast<double*>(f0->dalloc(static_cast<size_t>(nsk) * n * sizeof(double)));
                 int jmax = 0;
                 for (const auto& sk : mt.skd) jmax = std::max(jmax, std::min(sk.r, sk.n));
-                const dim3 gb2(nsk, nblk);
+                const dim3 gb2(nsk, nblk), gcs(nsk, (n + 255) / 256);
+                auto colsum = [&](const double* part) {
+                    KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                           hipLaunchKernelGGL(f32 ? k_big_colsum<float> : k_big_colsum<double>, gcs, dim3(256), 0, s,
+                                              skd_all, bst, part, csum, n, nblk));
+                };
                 KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
                        hipLaunchKernelGGL(f32 ? k_big_gather<float> : k_big_gather<double>, gb2, dim3(256), 0, s,
                                           skd_all, cgptr_all, cgl_all, cgoff_all, cref_all, front, mp, nrm, posb,
                                           pout, bst, n, nblk, lvl, err));
+                colsum(nrm);
                 BigState* hst = reinterpret_cast<BigState*>(hc.get_down(static_cast<size_t>(nsk) * sizeof(BigState) + 64));
                 // every group takes at most jmax steps (the last one only records the rank); the
                 // host checks every kBigCheck steps whether any group is still active
                 for (int j = 0; j <= jmax; ++j) {
                     KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
                            hipLaunchKernelGGL(f32 ? k_big_pivot<float> : k_big_pivot<double>, dim3(nsk), dim3(256), 0,
-                                              s, skd_all, mp, nrm, posb, pout, bst, o.eps, j, n, nblk, kout));
+                                              s, skd_all, mp, csum, posb, pout, bst, o.eps, j, n, kout));
                     if (j == jmax) break;
                     KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
                            hipLaunchKernelGGL(f32 ? k_big_dot<float> : k_big_dot<double>, gb2, dim3(256), 0, s,
                                               skd_all, mp, posb, bst, wpart, j, n, nblk));
+                    colsum(wpart);
                     KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
                            hipLaunchKernelGGL(f32 ? k_big_update<float> : k_big_update<double>, gb2, dim3(256), 0, s,
-                                              skd_all, mp, nrm, posb, bst, wpart, j, n, nblk));
+                                              skd_all, mp, nrm, posb, bst, csum, j, n, nblk));
+                    colsum(nrm);
                     if ((j + 1) % kBigCheck == 0) {
                         HIPCHK(hipMemcpyAsync(hst, bst, static_cast<size_t>(nsk) * sizeof(BigState),
                                               hipMemcpyDeviceToHost, s));
