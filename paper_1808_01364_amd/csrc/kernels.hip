@@ -1689,6 +1689,33 @@ __global__ __launch_bounds__(256) void k_precond_groups(const SepDesc* __restric
     }
 }
 
+// Block-Jacobi step, part 1 for levels with large groups: A_gg gathered from the group's
+// cells into L_g, 16 columns per workgroup; the Cholesky factor then comes from the panel
+// kernels of the cell elimination.
+__global__ __launch_bounds__(256) void k_precond_gather(const SepDesc* __restrict__ sd,
+                                                        const CellRef* __restrict__ cells,
+                                                        const double* __restrict__ F, double* __restrict__ Lg) {
+    const SepDesc& gr = sd[blockIdx.x];
+    const int n = gr.n, ns = gr.nslot;
+    const int y0 = blockIdx.y * 16;
+    if (y0 >= n) return;
+    const int y1 = min(n, y0 + 16);
+    int64_t off[kMaxSlots];
+    int32_t ld[kMaxSlots];
+    for (int sl = 0; sl < ns; ++sl) {
+        const CellRef c = cells[gr.slot_cell[sl]];
+        off[sl] = c.off + gr.slot_off[sl] + static_cast<int64_t>(gr.slot_off[sl]) * c.ld;
+        ld[sl] = c.ld;
+    }
+    double* L = Lg + gr.loff;
+    for (int e = threadIdx.x; e < (y1 - y0) * n; e += kWG) {
+        const int a = e % n, b = y0 + e / n;
+        double v = 0.0;
+        for (int sl = 0; sl < ns; ++sl) v += F[off[sl] + a + static_cast<size_t>(b) * ld[sl]];
+        L[a + static_cast<size_t>(b) * n] = v;
+    }
+}
+
 // Block-Jacobi step, part 2: every cell's share S of the separator matrix becomes
 // Lambda^-1 S Lambda^-T with Lambda = blockdiag(L_g) over the cell's boundary groups; the
 // diagonal blocks become I in the group's first cell and 0 in the others, so that the

@@ -34,6 +34,7 @@ template <bool F32>
 __global__ void k_syrk_schur(const FrontDesc* desc, double* pool);
 __global__ void k_precond_groups(const SepDesc* sd, const CellRef* cells, const double* F, double* Lg, double* Li,
                                  int panel_cap, int lds_n, int level, unsigned long long* err);
+__global__ void k_precond_gather(const SepDesc* sd, const CellRef* cells, const double* F, double* Lg);
 __global__ void k_precond_scale(const CellScaleDesc* cd, const CellGroup* cg, const double* Lg, const double* Li,
                                 double* F, int pstride, int phase);
 // waves per SIMD of the skeletonization form for launches with many groups per CU

@@ -60,6 +60,7 @@ constexpr int64_t kBigSkelElems = 1 << 18;    // M (rows x columns) from which t
                                               // many workgroups per group
 constexpr int kBigCheck = 16;                 // steps between the host's checks for active groups
 constexpr int kScaleRowsPerWG = 128;          // strips of a group pair's two-sided scaling per workgroup
+constexpr int kPrecondPanelMinN = 256;        // larger groups: block-Jacobi Cholesky by the panel kernels
 
 // Planner state of one problem of a factorization call: scratch, level plans and the
 // host tables of the skeleton apply. The sets are kept for reuse (PlanPool); the level-0 plan
@@ -1628,9 +1629,63 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
             const bool staged = !gstage && rhif::kPotrfSmemFixed + nm * nm <= kLdsMaxDoubles - kStaticLdsReserve;
             const size_t lds_pg = staged ? static_cast<size_t>(rhif::kPotrfSmemFixed + nm * nm) * sizeof(double)
                                          : potrf_lds(cap, 0);
-            KTIMED(f0, s, RHIF_K_PRECOND_CHOL, alg_pchol, 0.0,
-                   hipLaunchKernelGGL(k_precond_groups, dim3(nsep), dim3(256), lds_pg, s, sep_all, cref_all, front,
-                                      lg, li, cap, staged ? nm : 0, lvl, err));
+            if (nm <= kPrecondPanelMinN) {
+                KTIMED(f0, s, RHIF_K_PRECOND_CHOL, alg_pchol, 0.0,
+                       hipLaunchKernelGGL(k_precond_groups, dim3(nsep), dim3(256), lds_pg, s, sep_all, cref_all, front,
+                                          lg, li, cap, staged ? nm : 0, lvl, err));
+            } else {
+                // large groups: A_gg gathered by many workgroups per group, L_g by the panel
+                // kernels of the cell elimination (one launch per 128-column panel for all groups)
+                KTIMED(f0, s, RHIF_K_PRECOND_CHOL, alg_pchol, 0.0,
+                       hipLaunchKernelGGL(k_precond_gather, dim3(nsep, (nm + 15) / 16), dim3(256), 0, s, sep_all,
+                                          cref_all, front, lg));
+                const int nq = (nm + kElimPanel - 1) / kElimPanel;
+                std::vector<rhif::FrontDesc> pd;
+                std::vector<int32_t> pd_off(nq + 1, 0), pd_mrow(nq, 0);
+                for (int q = 0; q < nq; ++q) {
+                    const int j0 = q * kElimPanel;
+                    for (int e = 0; e < nsep; ++e) {
+                        const SepDesc& sd = mt.sep[e];
+                        if (sd.n <= j0) continue;
+                        rhif::FrontDesc fd{};
+                        fd.off = sd.loff + j0 + static_cast<int64_t>(j0) * sd.n;
+                        fd.ld = sd.n;
+                        fd.n = sd.n - j0;
+                        fd.p = std::min(kElimPanel, sd.n - j0);
+                        fd.id = e;
+                        fd.ext = sd.lioff / 256 + j0 / 16;
+                        pd.push_back(fd);
+                        pd_mrow[q] = std::max(pd_mrow[q], fd.n - fd.p);
+                    }
+                    pd_off[q + 1] = static_cast<int32_t>(pd.size());
+                }
+                Packer pk;
+                const size_t o_pd = pk.add(pd);
+                char* T = upload(f0, pk, s);
+                const rhif::FrontDesc* pdd = view<rhif::FrontDesc>(T, o_pd);
+                const size_t lds1 =
+                    static_cast<size_t>(rhif::kPotrfSmemFixed + (kElimPanel | 1) * kElimPanel) * sizeof(double);
+                const int pstride = 17 * kElimPanel;
+                for (int q = 0; q < nq; ++q) {
+                    const unsigned nc = static_cast<unsigned>(pd_off[q + 1] - pd_off[q]);
+                    if (nc == 0) continue;
+                    const rhif::FrontDesc* dq = pdd + pd_off[q];
+                    KTIMED(f0, s, RHIF_K_PRECOND_CHOL, 0.0, 0.0,
+                           hipLaunchKernelGGL(k_chol_lead, dim3(nc), dim3(256), lds1, s, dq, lg, li, kElimPanel, lvl,
+                                              1, err, nullptr));
+                    const int mr = pd_mrow[q];
+                    if (mr > 0) {
+                        KTIMED(f0, s, RHIF_K_PRECOND_CHOL, 0.0, 0.0,
+                               hipLaunchKernelGGL(k_trsm_rows, dim3(nc, (mr + 63) / 64), dim3(256),
+                                                  static_cast<size_t>(4 * pstride) * sizeof(double), s, dq, lg, li,
+                                                  pstride));
+                        const int nb = (mr + 31) / 32;
+                        KTIMED(f0, s, RHIF_K_PRECOND_CHOL, 0.0, 0.0,
+                               hipLaunchKernelGGL(k_syrk_schur<false>, dim3(nc, nb * (nb + 1) / 2), dim3(256), 0, s,
+                                                  dq, lg));
+                    }
+                }
+            }
             if (!mt.cs.empty()) {
                 // per wave a strip of finished panels in LDS, or (larger groups) one 16 x 17 tile
                 int pstride = 17 * ((max_sep_n + 15) / 16) * 16;
