@@ -2419,28 +2419,52 @@ __global__ __launch_bounds__(256) void k_big_update(const SkelDesc* __restrict__
         M[static_cast<size_t>(j) * ldr + s.pc] = static_cast<MR>(s.alpha);
 }
 
-// T = R11^-1 R12 in place over R12, one thread per redundant column (back substitution
-// with the columns of R11 read from the pool).
+// T = R11^-1 R12 in place over R12 (and copied to the T pool): back substitution for `ncol`
+// redundant columns per workgroup, held in LDS; at each step every thread updates its rows of
+// all of them with one entry of the pivot column of R11 (the operations and order of a column
+// by column substitution).
+constexpr int kTrisolveCols = kTrisolveColsHost;   // most redundant columns per workgroup
+
 template <typename MR>
-__global__ __launch_bounds__(64) void k_big_trisolve(const SkelDesc* __restrict__ sd, double* __restrict__ Mpool,
-                                                     const int32_t* __restrict__ pout, const BigState* __restrict__ st,
-                                                     double* __restrict__ Tpool) {
-    const int gi = blockIdx.x;
+__global__ __launch_bounds__(256) void k_big_trisolve(const SkelDesc* __restrict__ sd, double* __restrict__ Mpool,
+                                                      const int32_t* __restrict__ pout, const BigState* __restrict__ st,
+                                                      double* __restrict__ Tpool, int ncol) {
+    extern __shared__ double smem[];
+    const int gi = blockIdx.x, tid = threadIdx.x;
     const SkelDesc g = sd[gi];
     const int n = g.n, ldr = n | 1, k = st[gi].k, nr = n - k;
-    const int a = blockIdx.y * 64 + threadIdx.x;
-    if (a >= nr) return;
+    const int a0 = blockIdx.y * ncol;
+    if (a0 >= nr || k == 0) return;
+    const int nc = min(ncol, nr - a0);
     MR* M = reinterpret_cast<MR*>(Mpool + g.moff);
     const int32_t* perm = pout + g.poff;
-    const int pa = perm[k + a];
-    for (int i = k - 1; i >= 0; --i) {
+    MR* x = reinterpret_cast<MR*>(smem);   // [ncol][k]
+    for (int e = tid; e < nc * k; e += kWG) {
+        const int c = e / k, i = e % k;
+        x[e] = M[static_cast<size_t>(i) * ldr + perm[k + a0 + c]];
+    }
+    __syncthreads();
+    for (int i = k - 1; i > 0; --i) {
         const int pi = perm[i];
-        const MR ti = M[static_cast<size_t>(i) * ldr + pa] / M[static_cast<size_t>(i) * ldr + pi];
-        M[static_cast<size_t>(i) * ldr + pa] = ti;
-        for (int e = 0; e < i; ++e) M[static_cast<size_t>(e) * ldr + pa] -= M[static_cast<size_t>(e) * ldr + pi] * ti;
+        const MR rii = M[static_cast<size_t>(i) * ldr + pi];
+        MR t[kTrisolveCols];   // row i is final: every thread forms the step's multipliers
+#pragma unroll
+        for (int c = 0; c < kTrisolveCols; ++c) t[c] = c < nc ? x[c * k + i] / rii : MR(0);
+        for (int e = tid; e < i; e += kWG) {
+            const MR r = M[static_cast<size_t>(e) * ldr + pi];
+#pragma unroll
+            for (int c = 0; c < kTrisolveCols; ++c)
+                if (c < nc) x[c * k + e] -= r * t[c];
+        }
+        __syncthreads();
     }
     double* T = Tpool + g.toff;
-    for (int i = 0; i < k; ++i) T[i + static_cast<size_t>(a) * k] = static_cast<double>(M[static_cast<size_t>(i) * ldr + pa]);
+    for (int e = tid; e < nc * k; e += kWG) {
+        const int c = e / k, i = e % k;
+        const MR ti = x[e] / M[static_cast<size_t>(i) * ldr + perm[i]];
+        M[static_cast<size_t>(i) * ldr + perm[k + a0 + c]] = ti;
+        T[i + static_cast<size_t>(a0 + c) * k] = static_cast<double>(ti);
+    }
 }
 
 // The skeleton elimination of the large groups spread over many workgroups per group (the
@@ -2534,7 +2558,7 @@ __global__ __launch_bounds__(256) void k_big_elim(const SkelDesc* __restrict__ s
     template __global__ void k_big_update<MR>(const SkelDesc*, double*, double*, const int32_t*, const BigState*,  \
                                               const double*, int, int, int);                                      \
     template __global__ void k_big_trisolve<MR>(const SkelDesc*, double*, const int32_t*, const BigState*,         \
-                                                double*);                                                         \
+                                                double*, int);                                                    \
     template __global__ void k_big_elim<MR>(const SkelDesc*, const CellRef*, double*, const double*, double*,      \
                                             const int32_t*, const int32_t*, int);
 RHIF_BIG_INST(double)

@@ -67,10 +67,11 @@ __global__ void k_big_update(const SkelDesc* sd, double* Mpool, double* nrm, con
                              const double* wsum, int j, int nmax, int nblk);
 template <typename MR>
 __global__ void k_big_trisolve(const SkelDesc* sd, double* Mpool, const int32_t* pout, const BigState* st,
-                               double* Tpool);
+                               double* Tpool, int ncol);
 template <typename MR>
 __global__ void k_big_elim(const SkelDesc* sd, const CellRef* cells, double* F, const double* Mpool, double* Gpool,
                            const int32_t* kout, const int32_t* pout, int phase);
+constexpr int kTrisolveColsHost = 8;   // redundant columns per workgroup of k_big_trisolve
 constexpr int kBigRowsHost = 64;    // rows of M per workgroup in the kernels above
 __global__ void k_fwd_gt(const ApplyDesc* ad, const double* pool, const double* Tp, const int32_t* dofs,
                          const int32_t* ext, double* z);

@@ -884,7 +884,9 @@ void set_kernel_attributes() {
         const int bytes = kLdsMaxDoubles * static_cast<int>(sizeof(double));
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rhif::k_precond_scale),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        for (const void* k : {reinterpret_cast<const void*>(&rhif::k_skeletonize<4, double, 16>),
+        for (const void* k : {reinterpret_cast<const void*>(&rhif::k_big_trisolve<double>),
+                              reinterpret_cast<const void*>(&rhif::k_big_trisolve<float>),
+                              reinterpret_cast<const void*>(&rhif::k_skeletonize<4, double, 16>),
                               reinterpret_cast<const void*>(&rhif::k_skeletonize<4, float, 16>)})
             (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         for (int staged : {0, 1, 3})
@@ -1803,12 +1805,30 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                 }
                 // a group still active after jmax steps took every column: its rank is set by
                 // the last pivot launch (j == min(r, n))
-                KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
-                       hipLaunchKernelGGL(f32 ? k_big_trisolve<float> : k_big_trisolve<double>,
-                                          dim3(nsk, (n + 63) / 64), dim3(64), 0, s, skd_all, mp, pout, bst, tp));
+                // the ranks to the host: they size the substitution's LDS and the tables of the
+                // skeleton eliminations
+                int32_t* hkk = reinterpret_cast<int32_t*>(hc.get_down(static_cast<size_t>(n_k) * sizeof(int32_t) + 64));
+                HIPCHK(hipMemcpyAsync(hkk, kout, static_cast<size_t>(n_k) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                int nrmax = 0, kmax = 0;
+                for (const auto& sk : mt.skd) {
+                    nrmax = std::max(nrmax, sk.n - hkk[sk.gid]);
+                    kmax = std::max(kmax, hkk[sk.gid]);
+                }
+                if (nrmax > 0 && kmax > 0) {
+                    const size_t mrb = f32 ? sizeof(float) : sizeof(double);
+                    int ncol = kTrisolveColsHost;
+                    while (ncol > 1 && ncol * kmax * mrb > kLdsMaxDoubles * sizeof(double)) --ncol;
+                    if (kmax * mrb > kLdsMaxDoubles * sizeof(double))
+                        fail(RHIF_ENOMEM, "a skeleton rank is too large for this version");
+                    KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
+                           hipLaunchKernelGGL(f32 ? k_big_trisolve<float> : k_big_trisolve<double>,
+                                              dim3(nsk, (nrmax + ncol - 1) / ncol), dim3(256), ncol * kmax * mrb, s,
+                                              skd_all, mp, pout, bst, tp, ncol));
+                }
                 // the skeleton eliminations spread over many workgroups per group: G and its
                 // zeroed blocks, the partial Cholesky of G by the panel kernels of the cell
-                // elimination (the ranks come to the host for their tables), the write-back
+                // elimination, the write-back
                 const dim3 gcol(nsk, (n + 15) / 16);
                 auto elim = [&](int ph) {
                     KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
@@ -1816,11 +1836,6 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                                               skd_all, cref_all, front, mp, gp, kout, pout, ph));
                 };
                 for (int ph = 0; ph < 3; ++ph) elim(ph);
-                int32_t* hkk = reinterpret_cast<int32_t*>(hc.get_down(static_cast<size_t>(n_k) * sizeof(int32_t) + 64));
-                HIPCHK(hipMemcpyAsync(hkk, kout, static_cast<size_t>(n_k) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
-                int nrmax = 0;
-                for (const auto& sk : mt.skd) nrmax = std::max(nrmax, sk.n - hkk[sk.gid]);
                 const int nq = (nrmax + kElimPanel - 1) / kElimPanel;
                 std::vector<rhif::FrontDesc> pd;
                 std::vector<int32_t> pd_off(nq + 1, 0), pd_mrow(std::max(nq, 1), 0);
