@@ -30,8 +30,8 @@ FP64_PEAK_TFLOPS = 78.6
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--side", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -1086,8 +1086,10 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
         apply_max(ps.sk_ad, LD.mi_skel, LD.mb_skel);
     };
     // ... and their upload, one copy for all problems with tables pending
+    std::vector<int> skel_rec(Lmax + 1, -1);   // per level: its (last) skeletonization timing record
     auto skel_tables_upload = [&](const std::vector<int>& which) {
         if (which.empty()) return;
+        const int lv = pr[which[0]].pending_skel;   // every problem waiting has the same level
         Packer pk;
         std::vector<std::array<size_t, 4>> off(which.size());
         double fl = 0.0;
@@ -1116,13 +1118,7 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
             q.pending_skel = -1;
         }
         // the level's skeletonization launch gets its algorithmic flops now that they are known
-        if (f0->ktimes) {
-            for (auto it = f0->pend.rbegin(); it != f0->pend.rend(); ++it)
-                if (it->cls == RHIF_K_SKELETONIZE) {
-                    it->fl = fl;
-                    break;
-                }
-        }
+        if (f0->ktimes && skel_rec[lv] >= 0) f0->pend[skel_rec[lv]].fl = fl;
     };
 
     std::vector<int> act, nonroot, pend;
@@ -1410,8 +1406,8 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
             phase(root ? 6 : 1, t0);
         }
 
-        // ---- host, overlapping the elimination: the leaf groups' lists, the skeleton apply
-        //      tables of the level below, and the separator half of this level's plans ----
+        // ---- host, overlapping the elimination: the leaf groups' lists and the separator
+        //      half of this level's plans ----
         t0 = now();
         nonroot.clear();
         pend.clear();
@@ -1425,7 +1421,6 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
             PlanSet& ps = *q.ps;
             LevelPlan& P = ps.plan(lvl);
             if (P.lists_pending) fill_leaf_lists(f->g, ps.scr, P);
-            if (q.pending_skel >= 0) skel_tables_host(q);
             if (lvl == f->L) return;
             if (!q.reuse0) {
                 build_separators(f->g, ps.scr, kApplyCap, P);
@@ -1438,10 +1433,18 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                 ps.plan0_key[2] = leaf;
             }
         });
-        skel_tables_upload(pend);
+        // the skeleton apply tables of the level below are needed by no kernel of this level:
+        // they are built while this level's skeletonization runs
+        auto finish_pending = [&] {
+            pool.run(static_cast<int>(pend.size()), [&](int i) { skel_tables_host(pr[pend[i]]); });
+            skel_tables_upload(pend);
+        };
         for (int p : act)
             if (lvl == pr[p].f->L) pr[p].f->stats.flops[lvl] += pr[p].ps->plan(lvl).flops;
-        if (nonroot.empty()) continue;
+        if (nonroot.empty()) {
+            finish_pending();
+            continue;
+        }
 
         // ---- the separator half: shares, merged tables, one upload ----
         int64_t n_lg = 0, n_t = 0, n_g = 0, n_li = 0, n_skli = 0, n_m = 0;
@@ -1891,6 +1894,8 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                                           dim3(256), lds, s, skd_all, cgptr_all, cgl_all, cgoff_all, cref_all, front,
                                           mp, tp, gp, skli, o.eps, kout, pout, cap, n, rmax, lvl, err));
             }
+            if (f0->ktimes) skel_rec[lvl] = static_cast<int>(f0->pend.size()) - 1;
+            finish_pending();
             // error word, ranks and pivot orders in one copy; synchronizes: the ranks are on
             // the host now
             const size_t nb = (kKbufHead + static_cast<size_t>(n_k) + static_cast<size_t>(n_p)) * sizeof(int32_t);
@@ -1903,6 +1908,7 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
             std::memcpy(&e, h, sizeof(e));
             raise_err(e, batch);
         } else {
+            finish_pending();
             check_err(err, batch, s);
         }
         phase(3, t0);
