@@ -325,7 +325,7 @@ template <int UR, typename MR>
 __device__ __forceinline__ int wg_cpqr_rows(MR* __restrict__ M, int ldr, int r, int n, double eps, int* pos,
                                             int* perm, double* part_) {
     MR* part = reinterpret_cast<MR*>(part_);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
     int cw = 1;
     while (cw < n && cw < 64) cw <<= 1;
     const int nrc = kWG / cw;
@@ -2033,7 +2033,7 @@ __device__ __forceinline__ void skeletonize_one(const SkelDesc& g, const int32_t
                                                 int nmax, int rmax, int level, unsigned long long* err,
                                                 double* smem) {
     const int n = g.n, r = g.r, ldr = n | 1;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     const int ipd = (2 * nmax + 1) / 2 + 1;
     const int nbm = max(1, (nmax + 63) / 64);
     int* pos = reinterpret_cast<int*>(smem);

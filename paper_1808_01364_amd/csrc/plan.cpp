@@ -26,14 +26,6 @@ void big_family_ws(std::vector<ApplyDesc>& fam, int64_t& ws) {
         }
 }
 
-// Coordinates x_k in 1..s of linear unknown i (x_1 fastest).
-inline void coords(int64_t i, int d, int s, int* x) {
-    for (int k = 0; k < d; ++k) {
-        x[k] = static_cast<int>(i % s) + 1;
-        i /= s;
-    }
-}
-
 }  // namespace
 
 void PlanScratch::init(int64_t N) {
