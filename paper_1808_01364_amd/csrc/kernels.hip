@@ -2999,8 +2999,8 @@ __device__ __forceinline__ void big_diag_solve(const ApplyDesc& d, const double*
         ex[q] = min(nb, max(0, big_rows_end(d, extp, j0 / 16 + q) - j0));
     __syncthreads();
     const double* Ajj = A + j0 + static_cast<size_t>(j0) * d.ld;
-    if (TRANS) wg_trsv_bwd<false>(Ajj, d.ld, nb, li + d.li + 256 * (j0 / 16), zl, ex);
-    else wg_trsv_fwd<false>(Ajj, d.ld, nb, li + d.li + 256 * (j0 / 16), zl, ex);
+    if (TRANS) wg_trsv_bwd(Ajj, d.ld, nb, li + d.li + 256 * (j0 / 16), zl, ex);
+    else wg_trsv_fwd(Ajj, d.ld, nb, li + d.li + 256 * (j0 / 16), zl, ex);
     for (int e = threadIdx.x; e < nb; e += kWG) w[j0 + e] = zl[e];
 }
 
@@ -3048,17 +3048,25 @@ __global__ __launch_bounds__(256) void k_apply_big_up(const ApplyDesc* __restric
     // j - 1] x_{j-1}; then panel j's solve
     const int c0 = (j - 1) * kBP, nc = min(kBP, nI - c0);
     if (j >= 1 && j - 1 < np && r1 > c0 + nc) {
-        for (int c = tid; c < nc; c += kWG) xs[c] = w[c0 + c];
+        // padded with zeros: the 16-column steps below read whole column blocks
+        for (int c = tid; c < kBP; c += kWG) xs[c] = c < nc ? w[c0 + c] : 0.0;
         __syncthreads();
-        // two threads per row, each over half of the panel's columns
+        // two threads per row, each over half of the panel's columns, 16 at a time (the
+        // structural zeros of L below a column block's row end are skipped)
         const int rr = tid & (kBP - 1), h = tid / kBP;
         const int r = r0 + rr;
         double acc = 0.0;
         if (r < r1 && r >= c0 + nc) {
             const int ca = h * (kBP / 2), cb = min(nc, ca + kBP / 2);
-            for (int c = ca; c < cb; ++c) {
-                const bool nz = r >= nI || r < big_rows_end(d, extp, (c0 + c) >> 4);
-                if (nz) acc += A[r + static_cast<size_t>(c0 + c) * d.ld] * xs[c];
+            for (int q0 = ca; q0 < cb; q0 += 16) {
+                if (r < nI && r >= big_rows_end(d, extp, (c0 + q0) >> 4)) continue;
+                const double* Ar = A + r + static_cast<size_t>(c0 + q0) * d.ld;
+                const int qn = min(16, cb - q0);
+                double v[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) v[u] = u < qn ? Ar[static_cast<size_t>(u) * d.ld] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u) acc += v[u] * xs[q0 + u];
             }
         }
         part[tid] = acc;
