@@ -1482,14 +1482,25 @@ __device__ __forceinline__ void wave_trsm_rlt(double* __restrict__ X, int ldx, i
             const int r = r0 + lh + 4 * q;
             acc[q] = (r < m && lr < jb) ? X[r + static_cast<size_t>(j0 + lr) * ldx] : 0.0;
         }
-        for (int k0 = 0; k0 < j0; k0 += 4) {
-            double av;
-            if constexpr (HL)
-                av = -Pw[(k0 + lh) * 17 + lr];
-            else
-                av = (r0 + lr < m) ? -X[(r0 + lr) + static_cast<size_t>(k0 + lh) * ldx] : 0.0;
-            const double bv = (lr < jb) ? L[(j0 + lr) + static_cast<size_t>(k0 + lh) * ldl] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        // 16 columns (four products) per step, their operands loaded before the products (j0 is
+        // a multiple of 16); the products accumulate in column order
+        auto ld16 = [&](int kc, double (&av)[4], double (&bv)[4]) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k0 = kc + 4 * u;
+                if constexpr (HL)
+                    av[u] = -Pw[(k0 + lh) * 17 + lr];
+                else
+                    av[u] = (r0 + lr < m) ? -X[(r0 + lr) + static_cast<size_t>(k0 + lh) * ldx] : 0.0;
+                bv[u] = (lr < jb) ? L[(j0 + lr) + static_cast<size_t>(k0 + lh) * ldl] : 0.0;
+            }
+        };
+#pragma nounroll
+        for (int kc = 0; kc < j0; kc += 16) {
+            double ca[4], cb[4];
+            ld16(kc, ca, cb);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[u], cb[u], acc, 0, 0, 0);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) Pt[lr * 17 + lh + 4 * q] = acc[q];
@@ -1527,14 +1538,24 @@ __device__ __forceinline__ void wave_trsm_ll(double* __restrict__ Y, int ldy, in
             const int r = i0 + lh + 4 * q;
             acc[q] = (r < n && lr < cb) ? Y[r + static_cast<size_t>(c0 + lr) * ldy] : 0.0;
         }
-        for (int k0 = 0; k0 < i0; k0 += 4) {
-            const double av = (i0 + lr < n) ? -L[(i0 + lr) + static_cast<size_t>(k0 + lh) * ldl] : 0.0;
-            double bv;
-            if constexpr (HL)
-                bv = Yb[(k0 + lh) * 17 + lr];
-            else
-                bv = (lr < cb) ? Y[(k0 + lh) + static_cast<size_t>(c0 + lr) * ldy] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        // as in wave_trsm_rlt: 16 rows of Y (four products) per step, operands loaded first
+        auto ld16 = [&](int kc, double (&av)[4], double (&bv)[4]) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k0 = kc + 4 * u;
+                av[u] = (i0 + lr < n) ? -L[(i0 + lr) + static_cast<size_t>(k0 + lh) * ldl] : 0.0;
+                if constexpr (HL)
+                    bv[u] = Yb[(k0 + lh) * 17 + lr];
+                else
+                    bv[u] = (lr < cb) ? Y[(k0 + lh) + static_cast<size_t>(c0 + lr) * ldy] : 0.0;
+            }
+        };
+#pragma nounroll
+        for (int kc = 0; kc < i0; kc += 16) {
+            double ca[4], cv[4];
+            ld16(kc, ca, cv);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[u], cv[u], acc, 0, 0, 0);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) Yt[(lh + 4 * q) * 17 + lr] = acc[q];
