@@ -144,6 +144,20 @@ struct MergedTables {
     std::vector<int32_t> cgptr, cgl, cgoff;
 };
 
+// Waits for an event by polling it (short waits wake the host sooner than a blocking
+// synchronization); a wait longer than kPollMs blocks.
+void poll_event(hipEvent_t ev) {
+    constexpr auto kPollMs = std::chrono::milliseconds(2);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const hipError_t e = hipEventQuery(ev);
+        if (e == hipSuccess) return;
+        if (e != hipErrorNotReady) HIPCHK(e);
+        if (std::chrono::steady_clock::now() - t0 > kPollMs) break;
+    }
+    HIPCHK(hipEventSynchronize(ev));
+}
+
 // Per-thread host state reused across factorizations: pinned staging buffers for the
 // uploads (a ring, each slot fenced by the event of its last copy), a pinned buffer for
 // the small read-backs and the merged tables (so that repeated factorizations do not pay
@@ -199,6 +213,21 @@ struct HostCache {
         ev = side_ev[dev][side_next[dev]];
         side_next[dev] = (side_next[dev] + 1) % 4;
         return side[dev];
+    }
+    // pinned word for the error read-backs
+    unsigned long long* errw = nullptr;
+    unsigned long long* err_word() {
+        if (!errw) HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&errw), 64, hipHostMallocDefault));
+        return errw;
+    }
+    // Waits for the work queued on s so far, by polling (the waits of the level loop are
+    // short: the rank read-back after a level's last kernel).
+    std::vector<hipEvent_t> wait_ev;
+    void wait(hipStream_t s, int dev) {
+        if (static_cast<int>(wait_ev.size()) <= dev) wait_ev.resize(dev + 1, nullptr);
+        if (!wait_ev[dev]) HIPCHK(hipEventCreateWithFlags(&wait_ev[dev], hipEventDisableTiming));
+        HIPCHK(hipEventRecord(wait_ev[dev], s));
+        poll_event(wait_ev[dev]);
     }
     char* get_down(size_t b) {
         if (b > down_bytes) {
@@ -791,11 +820,12 @@ void raise_err(unsigned long long h, bool batch) {
     }
 }
 
-void check_err(const unsigned long long* err, bool batch, hipStream_t s) {
-    unsigned long long h = 0;
-    HIPCHK(hipMemcpyAsync(&h, err, sizeof(h), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    raise_err(h, batch);
+void check_err(const unsigned long long* err, bool batch, hipStream_t s, int dev) {
+    HostCache& hc = host_cache();
+    unsigned long long* h = hc.err_word();
+    HIPCHK(hipMemcpyAsync(h, err, sizeof(*h), hipMemcpyDeviceToHost, s));
+    hc.wait(s, dev);
+    raise_err(*h, batch);
 }
 
 template <class T>
@@ -1800,7 +1830,7 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                     if ((j + 1) % kBigCheck == 0) {
                         HIPCHK(hipMemcpyAsync(hst, bst, static_cast<size_t>(nsk) * sizeof(BigState),
                                               hipMemcpyDeviceToHost, s));
-                        HIPCHK(hipStreamSynchronize(s));
+                        hc.wait(s, f0->device);
                         bool any = false;
                         for (int e = 0; e < nsk; ++e) any = any || hst[e].active;
                         if (!any) break;
@@ -1812,7 +1842,7 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                 // skeleton eliminations
                 int32_t* hkk = reinterpret_cast<int32_t*>(hc.get_down(static_cast<size_t>(n_k) * sizeof(int32_t) + 64));
                 HIPCHK(hipMemcpyAsync(hkk, kout, static_cast<size_t>(n_k) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
+                hc.wait(s, f0->device);
                 int nrmax = 0, kmax = 0;
                 for (const auto& sk : mt.skd) {
                     nrmax = std::max(nrmax, sk.n - hkk[sk.gid]);
@@ -1903,13 +1933,13 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
             HIPCHK(hipMemcpyAsync(h, kbuf, nb, hipMemcpyDeviceToHost, s));
             hk = reinterpret_cast<int32_t*>(h) + kKbufHead;
             hp = hk + n_k;
-            HIPCHK(hipStreamSynchronize(s));
+            hc.wait(s, f0->device);
             unsigned long long e = 0;
             std::memcpy(&e, h, sizeof(e));
             raise_err(e, batch);
         } else {
             finish_pending();
-            check_err(err, batch, s);
+            check_err(err, batch, s, f0->device);
         }
         phase(3, t0);
 
@@ -1956,7 +1986,7 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
         phase(5, t0);
     }
     // every problem finished its last skeleton tables at its root level
-    check_err(err, batch, s);
+    check_err(err, batch, s, f0->device);
     if (bs) {
         // the problems' apply scratch in two call-wide arrays, each problem's vector at its
         // place in the concatenated vectors of the solves over all of them
@@ -1989,7 +2019,7 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
         for (const auto& LD : f->lev) bytes += LD.bytes;
         f->stats.factor_bytes = bytes;
     }
-    HIPCHK(hipStreamSynchronize(s));
+    hc.wait(s, f0->device);
     f0->resolve();
 }
 
