@@ -968,22 +968,38 @@ __global__ __launch_bounds__(256) void k_front_csr(const Tile* __restrict__ tile
 // over the children of c whose closures contain both unknowns (ascending child index),
 // of the children's Schur-complement shares.
 // ---------------------------------------------------------------------------------------
+// A child cell's place among its parent's children (bit k: its coordinate's parity on axis k).
+__device__ __forceinline__ int child_rank(int c, int d, int pnc1) {
+    int rel = 0;
+    for (int k = 0; k < d; ++k) {
+        rel |= ((c % pnc1) & 1) << k;
+        c /= pnc1;
+    }
+    return rel;
+}
+
 __global__ __launch_bounds__(256) void k_front_extend(const Tile* __restrict__ tiles, const CellRef* __restrict__ cells,
-                                                      const int32_t* __restrict__ src, int W,
+                                                      const int32_t* __restrict__ src, int W, int d, int pnc1,
                                                       const CellRef* __restrict__ child, const double* __restrict__ Fc,
                                                       double* __restrict__ F) {
-    // the tile's column sources (2 W ints per column, W <= 8), staged once
-    __shared__ int32_t qs[64 * 16];
+    // per column of the tile, its position in each child's frontal by the child's place among
+    // the cell's children (-1: not in that child), staged once (W <= 8)
+    __shared__ int32_t qt[64 * 8];
     const Tile t = tiles[blockIdx.x];
     const CellRef cr = cells[t.cell];
     const int nf = cr.nf;
     const int ncol = min(64, nf - t.c0);
     const int32_t* sc = src + static_cast<size_t>(cr.dptr + t.c0) * 2 * W;
-    for (int e = threadIdx.x; e < ncol * 2 * W; e += kWG) qs[e] = sc[e];
-    // the row's sources: child, and the element offset of the row in that child's frontal
+    for (int e = threadIdx.x; e < ncol * W; e += kWG) qt[e] = -1;
+    __syncthreads();
+    for (int e = threadIdx.x; e < ncol * W; e += kWG) {
+        const int c = sc[2 * e];
+        if (c >= 0) qt[(e / W) * W + child_rank(c, d, pnc1)] = sc[2 * e + 1];
+    }
+    // the row's sources: child place, and the element offset of the row in that child's frontal
     const int p = t.r0 + (threadIdx.x & 63);
     const bool prow = p < nf;
-    int pc[8], cld[8];
+    int pr[8], cld[8];
     int64_t coff[8];
     int np = 0;
     if (prow) {
@@ -992,7 +1008,7 @@ __global__ __launch_bounds__(256) void k_front_extend(const Tile* __restrict__ t
             const int c = sp[2 * a];
             if (c < 0) break;
             const CellRef ch = child[c];
-            pc[np] = c;
+            pr[np] = child_rank(c, d, pnc1);
             coff[np] = ch.off + sp[2 * a + 1];
             cld[np] = ch.ld;
             ++np;
@@ -1000,8 +1016,8 @@ __global__ __launch_bounds__(256) void k_front_extend(const Tile* __restrict__ t
     }
     __syncthreads();
     if (!prow) return;
-    // four columns per thread and pass, every load of the pass issued before the sums; a
-    // child holds the column at most once, and the shares are added in the row's child order
+    // four columns per thread and pass, every load of the pass issued before the sums; the
+    // shares are added in the row's child order
     const int wave = threadIdx.x >> 6;
     for (int cq0 = wave; cq0 < ncol; cq0 += 16) {
         double v[4];
@@ -1010,14 +1026,11 @@ __global__ __launch_bounds__(256) void k_front_extend(const Tile* __restrict__ t
             const int cq = cq0 + 4 * u;
             v[u] = 0.0;
             if (cq >= ncol) continue;
-            const int32_t* sq = qs + cq * 2 * W;
+            const int32_t* qc = qt + cq * W;
 #pragma unroll
             for (int a = 0; a < 8; ++a) {
                 if (a >= np) break;
-                int off = -1;
-#pragma unroll
-                for (int b = 0; b < 8; ++b)
-                    if (b < W && sq[2 * b] == pc[a]) off = sq[2 * b + 1];
+                const int off = qc[pr[a]];
                 if (off >= 0) v[u] += Fc[coff[a] + static_cast<size_t>(off) * cld[a]];
             }
         }

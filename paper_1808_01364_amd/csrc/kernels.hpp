@@ -20,7 +20,7 @@ __global__ void k_extend_src(const CellRef* cells, const int32_t* g2, const int3
                              const int32_t* gslot_cnt, const int32_t* gslot_cell, const int32_t* gslot_off,
                              const CellRef* child, int nchild, int d, int pnc1, int nc1, int W, int level,
                              int32_t* src, unsigned long long* err);
-__global__ void k_front_extend(const Tile* tiles, const CellRef* cells, const int32_t* src, int W,
+__global__ void k_front_extend(const Tile* tiles, const CellRef* cells, const int32_t* src, int W, int d, int pnc1,
                                const CellRef* child, const double* Fc, double* F);
 __global__ void k_potrf_batch(const FrontDesc* desc, double* pool, int panel_cap, int level, int step,
                               unsigned long long* err, int32_t* ext, double* linv);

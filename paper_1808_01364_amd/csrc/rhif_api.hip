@@ -1312,7 +1312,7 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                     rd += 8.0 * static_cast<double>(prevP->c_nB[c]) * prevP->c_nB[c];
                 KTIMED(f0, s, RHIF_K_FRONT_EXTEND, 0.0, P.alg_front_bytes + rd,
                        hipLaunchKernelGGL(k_front_extend, dim3(P.tiles.size()), dim3(256), 0, s, LD.tiles, LD.cref,
-                                          LD.src, W, prev->cref, prev->front, LD.front));
+                                          LD.src, W, d, prevP->nc1, prev->cref, prev->front, LD.front));
             }
         }
         phase(0, t0);
