@@ -39,7 +39,36 @@ def _args():
                     help="skip the FP32-mixed leg, the uneven batch and the 2048^2 point")
     ap.add_argument("--cpu-sample-side", type=int, default=512,
                     help="side of the (corner) window of the same field timed with the CPU oracle")
+    ap.add_argument("--profile-3d", action="store_true",
+                    help="profiling aid: only factor and solve the 3D 64^3 problem --warmup + --steps "
+                         "times (FP64) and print their times; no benchmark line")
     return ap.parse_args()
+
+
+def profile_3d(args):
+    """The 3D 64^3 two-valued problem (the 3D leg of the extras), factored and solved
+    --warmup + --steps times, for kernel traces and counters."""
+    import torch
+    from paper_1808_01364_amd import rhif
+    from workloads.fields import CONFIGS
+    torch.cuda.set_device(0)
+    C = CONFIGS["cfg3"]()
+    dev = "cuda:0"
+    a = torch.tensor(C.a_cells.ravel(), dtype=torch.float64, device=dev)
+    b = torch.tensor(C.b, dtype=torch.float64, device=dev)
+    csr = rhif.assemble_fd(3, C.s, a, b)
+    f = torch.tensor(C.f, dtype=torch.float64, device=dev)
+    for k in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = rhif.Factor(3, C.s, csr, C.leaf, C.eps, 1)
+        t1 = time.perf_counter()
+        u, it, rr = F.pcg(f, 1e-12, 500)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        F.close()
+        print(f"{C.name} step {k}: factor {1e3 * (t1 - t0):.1f} ms, pcg {1e3 * (t2 - t1):.1f} ms, "
+              f"{it} iterations, relres {rr:.2e}", flush=True)
 
 
 def make_workload(side: int, eps: float):
@@ -122,11 +151,13 @@ def extras(rhif, torch, P, csr, f):
     """The FP32-mixed factor on the same workload; the uneven batch (64 problems, sides from
     {128, 192, 256, 384, 512}, a = exp(2 g), eps 1e-4): plain FP64 one by one against the
     FP32-mixed autotuned batch; and a problem too large for the on-chip caches (2048^2, the
-    same field recipe, seed 7) with the per-class roofline of its kernels."""
+    same field recipe, seed 7) with the per-class roofline of its kernels; the 512^2 system at
+    eps 1e-3; and the 3D 64^3 two-valued problem in FP64 and FP32-mixed."""
+    import dataclasses
     import numpy as np
     from paper_1808_01364_amd import batch
     from workloads import make_problem
-    from workloads.fields import batch_problem
+    from workloads.fields import CONFIGS, batch_problem
     out = {}
     f64 = timed_solve(rhif, torch, P, csr, f, 0)
     f32 = timed_solve(rhif, torch, P, csr, f, 1)
@@ -177,6 +208,31 @@ def extras(rhif, torch, P, csr, f):
     out["out_of_cache_2048"] = {"workload": Q.name, "N": Q.N, "t_factor_ms": tq[0], "t_pcg_ms": tq[1],
                                 "pcg_iters": tq[2], "dofs_per_s": Q.N / ((tq[0] + tq[1]) * 1e-3),
                                 "classes": rows}
+    del aq, cq, fq
+    # the same 512^2 system with a coarser ID tolerance (a cheaper, weaker preconditioner)
+    P3 = dataclasses.replace(P, eps=1e-3, name=P.name.replace(f"eps{P.eps:g}", "eps0.001"))
+    t3 = timed_solve(rhif, torch, P3, csr, f, 0)
+    out["eps_1e-3"] = {"workload": P3.name, "t_factor_ms": t3[0], "t_pcg_ms": t3[1], "pcg_iters": t3[2],
+                       "relres": t3[3], "dofs_per_s": P3.N / ((t3[0] + t3[1]) * 1e-3)}
+    # 3D: 64^3 two-valued coefficients (1e-3 / 1e3), b = 1e-2, leaf 4, eps 1e-3; FP64 and
+    # FP32-mixed, and the per-class rows of the FP64 factor and solve
+    C = CONFIGS["cfg3"]()
+    a3 = torch.tensor(C.a_cells.ravel(), dtype=torch.float64, device=dev)
+    b3 = torch.tensor(C.b, dtype=torch.float64, device=dev)
+    c3 = rhif.assemble_fd(3, C.s, a3, b3)
+    f3 = torch.tensor(C.f, dtype=torch.float64, device=dev)
+    d64 = timed_solve(rhif, torch, C, c3, f3, 0, reps=2)
+    d32 = timed_solve(rhif, torch, C, c3, f3, 1, reps=2)
+    F = rhif.Factor(3, C.s, c3, C.leaf, C.eps, 1, flags=rhif.FLAG_KERNEL_TIMES)
+    F.pcg(f3, 1e-12, 500)
+    rows3 = class_rows(F.stats()["kernels"])
+    F.close()
+    out["3d_64"] = {"workload": C.name, "N": C.N,
+                    "fp64": {"t_factor_ms": d64[0], "t_pcg_ms": d64[1], "pcg_iters": d64[2], "relres": d64[3],
+                             "dofs_per_s": C.N / ((d64[0] + d64[1]) * 1e-3)},
+                    "fp32_mixed": {"t_factor_ms": d32[0], "t_pcg_ms": d32[1], "pcg_iters": d32[2],
+                                   "relres": d32[3], "dofs_per_s": C.N / ((d32[0] + d32[1]) * 1e-3)},
+                    "classes_fp64": rows3}
     return out
 
 
@@ -187,6 +243,9 @@ def main():
         print("bench.py: the RHIF library runs one problem on one GPU; multi-GPU runs are not "
               "part of this build (how the path would shard is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.profile_3d:
+        profile_3d(args)
+        return
     import numpy as np
     import torch
     from paper_1808_01364_amd import rhif

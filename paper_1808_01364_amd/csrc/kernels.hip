@@ -3164,16 +3164,28 @@ __global__ __launch_bounds__(256) void k_apply_big_dn(const ApplyDesc* __restric
     // phase 2: columns of chunk t < j -= L[panel j rows, columns]^T x_j; then panel j - 1's solve
     if (j >= np || t >= j) return;
     const int j0 = j * kBP, nr = min(kBP, nI - j0);
-    for (int e = tid; e < nr; e += kWG) xs[e] = w[j0 + e];
+    // padded with zeros: every lane reads its kBP / 16 rows below
+    for (int e = tid; e < kBP; e += kWG) xs[e] = e < nr ? w[j0 + e] : 0.0;
     __syncthreads();
-    for (int c = wave; c < ncol; c += kWaves) {
-        const int col = col0 + c;
-        const int rend = min(nr, big_rows_end(d, extp, col >> 4) - j0);
-        const double* Lc = A + j0 + static_cast<size_t>(col) * d.ld;
+    // four columns per wave at a time, 16 lanes per column, each lane over kBP / 16 rows
+    // (all loads of a column issued before its products)
+    const int sub = lane >> 4, le = lane & 15;
+    for (int c0 = 4 * wave; c0 < ncol; c0 += 4 * kWaves) {
+        const int c = c0 + sub;
         double acc = 0.0;
-        for (int e = lane; e < rend; e += 64) acc += Lc[e] * xs[e];
-        acc = wave_sum(acc);
-        if (lane == 0) w[col] -= acc;
+        if (c < ncol) {
+            const int col = col0 + c;
+            const int rend = min(nr, big_rows_end(d, extp, col >> 4) - j0);
+            const double* Lc = A + j0 + static_cast<size_t>(col) * d.ld;
+            double v[kBP / 16];
+#pragma unroll
+            for (int m = 0; m < kBP / 16; ++m) v[m] = le + 16 * m < rend ? Lc[le + 16 * m] : 0.0;
+#pragma unroll
+            for (int m = 0; m < kBP / 16; ++m) acc += v[m] * xs[le + 16 * m];
+        }
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (le == 0 && c < ncol) w[col0 + c] -= acc;
     }
     __syncthreads();
     if (t == j - 1) big_diag_solve<true>(d, A, li, extp, w, t, zl, ex);
