@@ -124,7 +124,7 @@ struct ApplyDesc {
 // Apply blocks whose largest interior exceeds kBigApplyMinI are applied panel by panel over
 // many workgroups per block (panels of kBigApplyPanel columns); every block of such a family
 // stages its vectors in the global workspace.
-constexpr int kBigApplyMinI = 512;
+constexpr int kBigApplyMinI = 272;   // the largest interior of the split apply
 constexpr int kBigApplyPanel = 128;
 
 // Gather of the up-sweep boundary contributions of the cells for one separator group.
