@@ -1610,17 +1610,20 @@ __global__ __launch_bounds__(256) void k_trsm_rows(const FrontDesc* __restrict__
                   smem + static_cast<size_t>(wave) * pstride);
 }
 
-// S = A_BB - W^T W on the 32 x 32 block (bi, bj), bi >= bj (block y of the cell, row-major
-// over the lower triangle); each wave one 16 x 16 tile of the lower triangle. The old values
-// are read from the lower triangle; each lower element is written with its mirror.
+// S = A_BB - W^T W on the kSyrkBlock x kSyrkBlock block (bi, bj), bi >= bj (block y of the
+// cell, row-major over the lower triangle); each wave a 32 x 32 quarter of it, as 2 x 2 tiles of
+// 16 x 16 on the matrix cores (each operand load feeds two products); every tile accumulates
+// over k in ascending order. The old values are read from the lower triangle; each lower
+// element is written with its mirror.
 // F32: the product W^T W on the FP32 matrix cores with FP32 accumulation (operands rounded
 // to FP32; S and the subtraction stay FP64). The FP32 16 x 16 x 4 product leaves row
 // 4 (lane / 16) + q of its tile in register q; the FP64 one row lane / 16 + 4 q.
 template <bool F32>
 __global__ __launch_bounds__(256) void k_syrk_schur(const FrontDesc* __restrict__ desc, double* __restrict__ pool) {
+    static_assert(kSyrkBlock == 64, "four 32 x 32 quarters per block");
     const FrontDesc fd = desc[blockIdx.x];
     const int p = fd.p, ms = fd.n - fd.p, ld = fd.ld;
-    const int nb = (ms + 31) >> 5;
+    const int nb = (ms + kSyrkBlock - 1) / kSyrkBlock;
     const int t = blockIdx.y;
     if (t >= nb * (nb + 1) / 2) return;
     int bi = static_cast<int>((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -1629,50 +1632,71 @@ __global__ __launch_bounds__(256) void k_syrk_schur(const FrontDesc* __restrict_
     const int bj = t - bi * (bi + 1) / 2;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lh = lane >> 4;
-    const int ti = 2 * bi + (wave >> 1), tj = 2 * bj + (wave & 1);
+    // tiles ti0, ti0 + 1 (rows) by tj0, tj0 + 1 (columns)
+    const int ti0 = 4 * bi + 2 * (wave >> 1), tj0 = 4 * bj + 2 * (wave & 1);
+    if (ti0 + 1 < tj0 || ti0 * 16 >= ms) return;   // above the diagonal, or past the last row
     double* A = pool + fd.off;
     double* S = A + p + static_cast<size_t>(p) * ld;
     const double* Wt = A + p;
-    const bool act = ti * 16 < ms && tj * 16 < ms && ti >= tj;
-    const int c = tj * 16 + lr;
-    auto row_of = [&](int q) { return F32 ? ti * 16 + 4 * lh + q : ti * 16 + lh + 4 * q; };
-    v4d s0 = {0.0, 0.0, 0.0, 0.0}, acc = {0.0, 0.0, 0.0, 0.0};
-    v4f accf = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (act) {
+    auto act = [&](int a, int b) { return (ti0 + a) * 16 < ms && (tj0 + b) * 16 < ms && ti0 + a >= tj0 + b; };
+    auto row_of = [&](int a, int q) { return F32 ? (ti0 + a) * 16 + 4 * lh + q : (ti0 + a) * 16 + lh + 4 * q; };
+    v4d s0[2][2], acc[2][2];
+    v4f accf[2][2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = row_of(q);
-            if (r < ms && c < ms) s0[q] = S[max(r, c) + static_cast<size_t>(min(r, c)) * ld];
-        }
-        const int ra = ti * 16 + lr, rb = tj * 16 + lr;
-#pragma unroll 4
-        for (int k0 = 0; k0 < p; k0 += 4) {
-            const int k = k0 + lh;
-            const double av = (ra < ms && k < p) ? Wt[ra + static_cast<size_t>(k) * ld] : 0.0;
-            const double bv = (rb < ms && k < p) ? Wt[rb + static_cast<size_t>(k) * ld] : 0.0;
-            if constexpr (F32)
-                accf = __builtin_amdgcn_mfma_f32_16x16x4f32(static_cast<float>(av), static_cast<float>(bv), accf, 0,
-                                                           0, 0);
-            else
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-        }
-        if constexpr (F32) {
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = static_cast<double>(accf[q]);
-        }
-    }
-    // each lower element (r >= c) is written with its mirror by the one lane that read it
-    if (act) {
+        for (int b = 0; b < 2; ++b) {
+            s0[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+            acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+            accf[a][b] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            const int c = (tj0 + b) * 16 + lr;
+            if (act(a, b)) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = row_of(q);
-            if (r < ms && c < ms && r >= c) {
-                const double v = s0[q] - acc[q];
-                S[r + static_cast<size_t>(c) * ld] = v;
-                S[c + static_cast<size_t>(r) * ld] = v;
+                for (int q = 0; q < 4; ++q) {
+                    const int r = row_of(a, q);
+                    if (r < ms && c < ms) s0[a][b][q] = S[max(r, c) + static_cast<size_t>(min(r, c)) * ld];
+                }
             }
         }
+    const int ra0 = ti0 * 16 + lr, rb0 = tj0 * 16 + lr;
+#pragma unroll 2
+    for (int k0 = 0; k0 < p; k0 += 4) {
+        const int k = k0 + lh;
+        double av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            av[a] = (ra0 + 16 * a < ms && k < p) ? Wt[ra0 + 16 * a + static_cast<size_t>(k) * ld] : 0.0;
+            bv[a] = (rb0 + 16 * a < ms && k < p) ? Wt[rb0 + 16 * a + static_cast<size_t>(k) * ld] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                if constexpr (F32)
+                    accf[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(static_cast<float>(av[a]),
+                                                                      static_cast<float>(bv[b]), accf[a][b], 0, 0, 0);
+                else
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+            }
     }
+    // each lower element (r >= c) is written with its mirror by the one lane that read it
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            if (!act(a, b)) continue;
+            const int c = (tj0 + b) * 16 + lr;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = row_of(a, q);
+                const double pr = F32 ? static_cast<double>(accf[a][b][q]) : acc[a][b][q];
+                if (r < ms && c < ms && r >= c) {
+                    const double v = s0[a][b][q] - pr;
+                    S[r + static_cast<size_t>(c) * ld] = v;
+                    S[c + static_cast<size_t>(r) * ld] = v;
+                }
+            }
+        }
 }
 template __global__ void k_syrk_schur<false>(const FrontDesc*, double*);
 template __global__ void k_syrk_schur<true>(const FrontDesc*, double*);

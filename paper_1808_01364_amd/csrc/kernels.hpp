@@ -124,6 +124,7 @@ __global__ void k_set_u64(unsigned long long* p, unsigned long long v);
 
 constexpr int kMaxSkelSegs = 64;     // row segments of one skeletonized group (2 x 26 in 3D)
 constexpr int kMaxCellGroups = 32;   // boundary groups of one cell (26 in 3D)
+constexpr int kSyrkBlock = 64;               // Schur update: rows and columns per workgroup
 constexpr int kSplitApplyMaxI = 272;        // split apply: one row / column per thread and panel
 constexpr int kApplyDiagDoubles = 32 * 33;   // LDS diagonal block of the apply kernels
 constexpr int kApplyExtDoubles = 256;         // LDS panel extents (up to 512 ints, n_I <= 8192)

@@ -1404,7 +1404,7 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                                hipLaunchKernelGGL(k_trsm_rows, dim3(nc, (mr + 63) / 64), dim3(256),
                                                   static_cast<size_t>(4 * pstride) * sizeof(double), s, dq, front,
                                                   linv, pstride));
-                        const int nb = (mr + 31) / 32;
+                        const int nb = (mr + kSyrkBlock - 1) / kSyrkBlock;
                         KTIMED(f0, s, cls, 0.0, 0.0,
                                hipLaunchKernelGGL(k_syrk_schur<false>, dim3(nc, nb * (nb + 1) / 2), dim3(256), 0, s,
                                                   dq, front));
@@ -1422,7 +1422,7 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                            hipLaunchKernelGGL(k_trsm_rows, dim3(ncell, (mmax + 63) / 64), dim3(256),
                                               static_cast<size_t>(4 * pstride) * sizeof(double), s, potd, front, linv,
                                               pstride));
-                    const int nb = (mmax + 31) / 32;
+                    const int nb = (mmax + kSyrkBlock - 1) / kSyrkBlock;
                     KTIMED(f0, s, cls, 0.0, 0.0,
                            hipLaunchKernelGGL(f32schur ? k_syrk_schur<true> : k_syrk_schur<false>,
                                               dim3(ncell, nb * (nb + 1) / 2), dim3(256), 0, s, potd, front));
@@ -1714,7 +1714,7 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                                hipLaunchKernelGGL(k_trsm_rows, dim3(nc, (mr + 63) / 64), dim3(256),
                                                   static_cast<size_t>(4 * pstride) * sizeof(double), s, dq, lg, li,
                                                   pstride));
-                        const int nb = (mr + 31) / 32;
+                        const int nb = (mr + kSyrkBlock - 1) / kSyrkBlock;
                         KTIMED(f0, s, RHIF_K_PRECOND_CHOL, 0.0, 0.0,
                                hipLaunchKernelGGL(k_syrk_schur<false>, dim3(nc, nb * (nb + 1) / 2), dim3(256), 0, s,
                                                   dq, lg));
@@ -1910,7 +1910,7 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
                                    hipLaunchKernelGGL(k_trsm_rows, dim3(nc, (mr + 63) / 64), dim3(256),
                                                       static_cast<size_t>(4 * pstride) * sizeof(double), s, dq, gp,
                                                       skli, pstride));
-                            const int nb = (mr + 31) / 32;
+                            const int nb = (mr + kSyrkBlock - 1) / kSyrkBlock;
                             KTIMED(f0, s, RHIF_K_SKELETONIZE, 0.0, 0.0,
                                    hipLaunchKernelGGL(k_syrk_schur<false>, dim3(nc, nb * (nb + 1) / 2), dim3(256), 0,
                                                       s, dq, gp));
