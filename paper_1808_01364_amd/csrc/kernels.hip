@@ -3039,6 +3039,7 @@ __device__ __forceinline__ void wg_trsv_bwd(const double* __restrict__ L, int ld
 // 3 scatter. Workgroup (b, t) of grid (blocks, ceil((max n_I + n_B) / P)).
 // ---------------------------------------------------------------------------------------
 constexpr int kBP = kBigApplyPanel;
+static_assert(kWG == 2 * kBP, "two threads per row or column of a panel chunk");
 
 // Rows of panel column block q (16 columns) below which L is structurally zero.
 __device__ __forceinline__ int big_rows_end(const ApplyDesc& d, const int32_t* __restrict__ extp, int q) {
@@ -3084,13 +3085,16 @@ __global__ __launch_bounds__(256) void k_apply_big_up(const ApplyDesc* __restric
         for (int r = r0 + tid; r < r1; r += kWG) w[r] = (r < nI || needB) ? z[di[r]] : 0.0;
         return;
     }
-    if (phase == 1) {   // z_I -= T z_B
+    if (phase == 1) {   // z_I -= T z_B: a wave per row of T, lanes over its (contiguous) columns
         if (d.toff < 0 || r0 >= nI) return;
         const double* T = Tp + d.toff;
-        for (int a = r0 + tid; a < min(r1, nI); a += kWG) {
+        const int lane = tid & 63, wave = tid >> 6;
+        for (int a = r0 + wave; a < min(r1, nI); a += kWaves) {
+            const double* Ta = T + static_cast<size_t>(a) * d.nB;
             double acc = 0.0;
-            for (int c = 0; c < d.nB; ++c) acc += T[c + static_cast<size_t>(a) * d.nB] * w[nI + c];
-            w[a] -= acc;
+            for (int c = lane; c < d.nB; c += 64) acc += Ta[c] * w[nI + c];
+            acc = wave_sum(acc);
+            if (lane == 0) w[a] -= acc;
         }
         return;
     }
@@ -3159,13 +3163,29 @@ __global__ __launch_bounds__(256) void k_apply_big_dn(const ApplyDesc* __restric
     }
     if (phase == 3) {   // scatter z_I; z_B -= T z_I
         for (int r = r0 + tid; r < min(r1, nI); r += kWG) z[di[r]] = w[r];
-        if (d.toff >= 0) {
+        if (d.toff >= 0 && r0 < nB) {
+            // two threads per column of this chunk, each over half of z_I, eight loads in flight
+            __shared__ double half[kBP];
             const double* T = Tp + d.toff;
-            for (int c = r0 + tid; c < min(r0 + kBP, nB); c += kWG) {
-                double acc = 0.0;
-                for (int a = 0; a < nI; ++a) acc += T[c + static_cast<size_t>(a) * nB] * w[a];
-                z[di[nI + c]] = w[nI + c] - acc;
+            const int c = r0 + (tid & (kBP - 1)), h = tid / kBP;
+            const int a0 = h == 0 ? 0 : nI / 2, a1 = h == 0 ? nI / 2 : nI;
+            double acc = 0.0;
+            if (c < nB) {
+                double p8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                int a = a0;
+                for (; a + 7 < a1; a += 8) {
+                    double t8[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) t8[u] = T[c + static_cast<size_t>(a + u) * nB];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) p8[u] += t8[u] * w[a + u];
+                }
+                for (; a < a1; ++a) p8[0] += T[c + static_cast<size_t>(a) * nB] * w[a];
+                acc = ((p8[0] + p8[1]) + (p8[2] + p8[3])) + ((p8[4] + p8[5]) + (p8[6] + p8[7]));
             }
+            if (h == 1) half[tid - kBP] = acc;
+            __syncthreads();
+            if (h == 0 && c < nB) z[di[nI + c]] = w[nI + c] - (acc + half[tid]);
         }
         return;
     }
@@ -3176,8 +3196,22 @@ __global__ __launch_bounds__(256) void k_apply_big_dn(const ApplyDesc* __restric
         // then the last panel's solve
         for (int c = wave; c < ncol; c += kWaves) {
             const double* Wc = A + nI + static_cast<size_t>(col0 + c) * d.ld;
-            double acc = 0.0;
-            for (int b = lane; b < nB; b += 64) acc += Wc[b] * w[nI + b];
+            const double* zB = w + nI;
+            // eight loads of the column in flight per lane, eight partial sums
+            double p8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            int b = lane;
+            for (; b + 7 * 64 < nB; b += 8 * 64) {
+                double x[8], y[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    x[u] = Wc[b + 64 * u];
+                    y[u] = zB[b + 64 * u];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) p8[u] += x[u] * y[u];
+            }
+            for (; b < nB; b += 64) p8[0] += Wc[b] * zB[b];
+            double acc = ((p8[0] + p8[1]) + (p8[2] + p8[3])) + ((p8[4] + p8[5]) + (p8[6] + p8[7]));
             acc = wave_sum(acc);
             if (lane == 0) w[col0 + c] -= acc;
         }
