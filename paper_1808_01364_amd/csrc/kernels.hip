@@ -1659,7 +1659,6 @@ __global__ __launch_bounds__(256) void k_syrk_schur(const FrontDesc* __restrict_
             }
         }
     const int ra0 = ti0 * 16 + lr, rb0 = tj0 * 16 + lr;
-#pragma unroll 2
     for (int k0 = 0; k0 < p; k0 += 4) {
         const int k = k0 + lh;
         double av[2], bv[2];
@@ -3041,6 +3040,27 @@ __device__ __forceinline__ void wg_trsv_bwd(const double* __restrict__ L, int ld
 constexpr int kBP = kBigApplyPanel;
 static_assert(kWG == 2 * kBP, "two threads per row or column of a panel chunk");
 
+// Dot product of two contiguous vectors of length n by one wave: lane l takes the elements
+// l, l + 64, ..., eight loads of each vector in flight, into eight partial sums; the total
+// is returned to every lane.
+__device__ __forceinline__ double wave_dot(const double* __restrict__ x, const double* __restrict__ y, int n,
+                                           int lane) {
+    double p8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int b = lane;
+    for (; b + 7 * 64 < n; b += 8 * 64) {
+        double xv[8], yv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            xv[u] = x[b + 64 * u];
+            yv[u] = y[b + 64 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p8[u] += xv[u] * yv[u];
+    }
+    for (; b < n; b += 64) p8[0] += x[b] * y[b];
+    return wave_sum(((p8[0] + p8[1]) + (p8[2] + p8[3])) + ((p8[4] + p8[5]) + (p8[6] + p8[7])));
+}
+
 // Rows of panel column block q (16 columns) below which L is structurally zero.
 __device__ __forceinline__ int big_rows_end(const ApplyDesc& d, const int32_t* __restrict__ extp, int q) {
     return (extp != nullptr && d.ext >= 0) ? static_cast<int>(extp[d.ext + q]) : d.nI;
@@ -3090,10 +3110,7 @@ __global__ __launch_bounds__(256) void k_apply_big_up(const ApplyDesc* __restric
         const double* T = Tp + d.toff;
         const int lane = tid & 63, wave = tid >> 6;
         for (int a = r0 + wave; a < min(r1, nI); a += kWaves) {
-            const double* Ta = T + static_cast<size_t>(a) * d.nB;
-            double acc = 0.0;
-            for (int c = lane; c < d.nB; c += 64) acc += Ta[c] * w[nI + c];
-            acc = wave_sum(acc);
+            const double acc = wave_dot(T + static_cast<size_t>(a) * d.nB, w + nI, d.nB, lane);
             if (lane == 0) w[a] -= acc;
         }
         return;
@@ -3195,24 +3212,7 @@ __global__ __launch_bounds__(256) void k_apply_big_dn(const ApplyDesc* __restric
         // z_I -= W z_B on this chunk's columns (a wave per column, lanes over the rows of W^T);
         // then the last panel's solve
         for (int c = wave; c < ncol; c += kWaves) {
-            const double* Wc = A + nI + static_cast<size_t>(col0 + c) * d.ld;
-            const double* zB = w + nI;
-            // eight loads of the column in flight per lane, eight partial sums
-            double p8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            int b = lane;
-            for (; b + 7 * 64 < nB; b += 8 * 64) {
-                double x[8], y[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    x[u] = Wc[b + 64 * u];
-                    y[u] = zB[b + 64 * u];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) p8[u] += x[u] * y[u];
-            }
-            for (; b < nB; b += 64) p8[0] += Wc[b] * zB[b];
-            double acc = ((p8[0] + p8[1]) + (p8[2] + p8[3])) + ((p8[4] + p8[5]) + (p8[6] + p8[7]));
-            acc = wave_sum(acc);
+            const double acc = wave_dot(A + nI + static_cast<size_t>(col0 + c) * d.ld, w + nI, nB, lane);
             if (lane == 0) w[col0 + c] -= acc;
         }
         __syncthreads();
