@@ -194,12 +194,12 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, int64_t n_a
         auto key_of = [&](int32_t i) {   // unknowns are int32 indices: 32-bit divisions
             uint32_t r = static_cast<uint32_t>(i);
             int64_t K = 0;
-            for (int k = 0; k < d; ++k) {
+            for (int k = 0; k + 1 < d; ++k) {
                 const uint32_t q = r / us;
                 K += keyk[r - q * us + 1] * mulk[k];
                 r = q;
             }
-            return K;
+            return K + keyk[r + 1] * mulk[d - 1];   // the last coordinate is what is left
         };
         std::vector<int32_t>& gkey = scr.akey;
         gkey.assign(ng2, -1);
