@@ -229,6 +229,16 @@ struct HostCache {
         HIPCHK(hipEventRecord(wait_ev[dev], s));
         poll_event(wait_ev[dev]);
     }
+    // s waits for every upload queued so far on the device's upload stream
+    std::vector<hipEvent_t> join_ev;
+    void side_join(hipStream_t s, int dev) {
+        hipEvent_t unused = nullptr;
+        const hipStream_t cs = side_stream(dev, unused);
+        if (static_cast<int>(join_ev.size()) <= dev) join_ev.resize(dev + 1, nullptr);
+        if (!join_ev[dev]) HIPCHK(hipEventCreateWithFlags(&join_ev[dev], hipEventDisableTiming));
+        HIPCHK(hipEventRecord(join_ev[dev], cs));
+        HIPCHK(hipStreamWaitEvent(s, join_ev[dev], 0));
+    }
     char* get_down(size_t b) {
         if (b > down_bytes) {
             if (down) (void)hipHostFree(down);
@@ -848,9 +858,10 @@ char* upload(rhif_factor_s* f, Packer& pk, hipStream_t s, size_t extra = 0) {
 }
 
 // The same on the upload stream, so that the copy overlaps the kernels already queued on s;
-// s waits for it before anything queued after this call. (The destination is fresh memory
-// of the handle, so the copy depends on nothing queued before.)
-char* upload_side(rhif_factor_s* f, Packer& pk, hipStream_t s) {
+// s waits for it before anything queued after this call, or (join = false) the caller makes
+// s wait later with HostCache::side_join. (The destination is fresh memory of the handle, so
+// the copy depends on nothing queued before.)
+char* upload_side(rhif_factor_s* f, Packer& pk, hipStream_t s, bool join = true) {
     if (pk.total == 0) return nullptr;
     HostCache& hc = host_cache();
     hipEvent_t ev = nullptr;
@@ -862,8 +873,10 @@ char* upload_side(rhif_factor_s* f, Packer& pk, hipStream_t s) {
     char* dst = static_cast<char*>(f->dalloc(pk.total));
     HIPCHK(hipMemcpyAsync(dst, h, pk.total, hipMemcpyHostToDevice, cs));
     hc.fence(slot, cs);
-    HIPCHK(hipEventRecord(ev, cs));
-    HIPCHK(hipStreamWaitEvent(s, ev, 0));
+    if (join) {
+        HIPCHK(hipEventRecord(ev, cs));
+        HIPCHK(hipStreamWaitEvent(s, ev, 0));
+    }
     return dst;
 }
 
@@ -996,6 +1009,19 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
     HostCache& hc = host_cache();
     MergedTables& mt = hc.mt;
     HostPool& pool = HostPool::get();
+    // The skeleton apply tables are copied on the upload stream and read by no kernel of the
+    // factorization, so the factor's stream joins those copies once, at the end. If the call
+    // fails before that, the guard waits for them before the handles' memory is released.
+    struct SideGuard {
+        HostCache& hc;
+        int dev;
+        bool armed = false;
+        ~SideGuard() {
+            if (!armed) return;
+            hipEvent_t unused = nullptr;
+            (void)hipStreamSynchronize(hc.side_stream(dev, unused));
+        }
+    } side_guard{hc, f0->device};
 
     // the error word leads the block of the ID outputs, so that one copy reads back both
     int32_t* kbuf = static_cast<int32_t*>(f0->dalloc(kKbufHead * sizeof(int32_t)));
@@ -1129,7 +1155,8 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
             off[i] = {pk.add(ps.sk_ad), pk.add(ps.sk_dofs), pk.add(ps.gad), pk.add(q.f->lev[q.pending_skel].perm)};
             fl += q.sk_fl;
         }
-        char* T = upload_side(f0, pk, s);
+        char* T = upload_side(f0, pk, s, false);
+        side_guard.armed = side_guard.armed || T != nullptr;
         for (size_t i = 0; i < which.size(); ++i) {
             Prob& q = pr[which[i]];
             LevelDev& LD = q.f->lev[q.pending_skel];
@@ -2019,7 +2046,9 @@ void do_factor(const std::vector<rhif_factor_s*>& fs, const CsrIn* in, hipStream
         for (const auto& LD : f->lev) bytes += LD.bytes;
         f->stats.factor_bytes = bytes;
     }
+    if (side_guard.armed) hc.side_join(s, f0->device);
     hc.wait(s, f0->device);
+    side_guard.armed = false;
     f0->resolve();
 }
 
