@@ -988,7 +988,7 @@ __global__ __launch_bounds__(256) void k_front_extend(const Tile* __restrict__ t
     const Tile t = tiles[blockIdx.x];
     const CellRef cr = cells[t.cell];
     const int nf = cr.nf;
-    const int ncol = min(64, nf - t.c0);
+    const int ncol = t.shape ? t.shape & 0xff : min(64, nf - t.c0);   // 64 x 64, or the tile's shape
     const int32_t* sc = src + static_cast<size_t>(cr.dptr + t.c0) * 2 * W;
     for (int e = threadIdx.x; e < ncol * W; e += kWG) qt[e] = -1;
     __syncthreads();

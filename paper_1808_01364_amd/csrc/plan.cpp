@@ -11,6 +11,7 @@ namespace rhif {
 namespace {
 
 inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+constexpr int64_t kNarrowTileCells = 16;   // levels with at most this many cells: narrow tiles
 
 // A block family with an interior above kBigApplyMinI is applied panel by panel over many
 // workgroups per block, which stages every block's vectors in the global workspace: give the
@@ -393,6 +394,14 @@ void build_cells(const GridInfo& gi, int level, int leaf, bool root, int64_t n_a
             double band = 0.0;
             for (int j0 = 0; j0 < nI; j0 += 16) band += std::min(16, nI - j0) * (std::min(32, nI - j0) + 0.0);
             front_bytes += 8.0 * (band + static_cast<double>(nB) * nf);
+        } else if (prev != nullptr && ncells <= kNarrowTileCells) {
+            // few cells (the upper levels): 64 x 16 extend-add tiles, four times as many
+            // workgroups, each with a quarter of the dependent loads
+            for (int c0 = 0; c0 < nf; c0 += 16)
+                for (int r0 = 0; r0 < nf; r0 += 64)
+                    P.tiles.push_back(
+                        Tile{cc, r0, c0, tile_shape(std::min(64, nf - r0), std::min(16, nf - c0), false)});
+            front_bytes += 8.0 * static_cast<double>(nf) * nf;
         } else {
             for (int c0 = 0; c0 < nf; c0 += 64)
                 for (int r0 = 0; r0 < nf; r0 += 64) P.tiles.push_back(Tile{cc, r0, c0, 0});
